@@ -1,0 +1,206 @@
+"""Point sets for one scatterer shape (geometry only, float64).
+
+Every shape is described in its own body frame (reference point at the
+origin).  A discretisation carries the four point sets the method needs
+(Sec. 3.2-3.4 and Sec. 4.1-4.2 of the paper):
+
+* ``colloc`` -- m collocation points x_i on the boundary Gamma,
+* ``src``    -- n MFS sources y_j inside Gamma, on a curve a distance d in
+  from Gamma along the inward normal (Sec. 3.2: n = m/2 in 2D),
+* ``proxy``  -- p proxy points z_i on the proxy surface Psi enclosing Gamma,
+* ``eqpts``  -- k equivalent-source points x_hat, where incoming fields are
+  sampled and outgoing fields are represented.
+
+All arrays are point-major ``[count, dim]``.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class ShapeDiscretisation:
+    name: str
+    dim: int
+    colloc: np.ndarray
+    src: np.ndarray
+    proxy: np.ndarray
+    eqpts: np.ndarray
+    bounding_radius: float
+    proxy_radius: float
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def m(self) -> int:
+        return self.colloc.shape[0]
+
+    @property
+    def n(self) -> int:
+        return self.src.shape[0]
+
+    @property
+    def p(self) -> int:
+        return self.proxy.shape[0]
+
+    @property
+    def k(self) -> int:
+        return self.eqpts.shape[0]
+
+
+def circle_points(count: int, radius: float, offset: float = 0.0) -> np.ndarray:
+    """``count`` points equispaced in angle on a circle about the origin."""
+    t = 2.0 * np.pi * (np.arange(count, dtype=np.float64) + offset) / count
+    return np.stack([radius * np.cos(t), radius * np.sin(t)], axis=-1)
+
+
+def fibonacci_sphere(count: int, radius: float) -> np.ndarray:
+    """Fibonacci lattice on a sphere: z_i = 1-(2i+1)/k, azimuth i*pi*(3-sqrt5)."""
+    i = np.arange(count, dtype=np.float64)
+    zc = 1.0 - (2.0 * i + 1.0) / count
+    s = np.sqrt(np.maximum(0.0, 1.0 - zc * zc))
+    az = i * np.pi * (3.0 - np.sqrt(5.0))
+    return radius * np.stack([s * np.cos(az), s * np.sin(az), zc], axis=-1)
+
+
+# --------------------------------------------------------------------------
+# 2D parametrised curves: each returns (points, outward unit normals) at the
+# parameter values t.
+# --------------------------------------------------------------------------
+
+def _polar_curve(t, f, fp):
+    """Curve (f(t) cos t, f(t) sin t) with derivative f'(t)."""
+    c, s = np.cos(t), np.sin(t)
+    pts = np.stack([f * c, f * s], axis=-1)
+    tan = np.stack([fp * c - f * s, fp * s + f * c], axis=-1)
+    return pts, tan
+
+
+def _normals_from_tangent(tan):
+    # counter-clockwise curve: outward normal is the tangent rotated by -90 deg
+    nrm = np.stack([tan[:, 1], -tan[:, 0]], axis=-1)
+    return nrm / np.linalg.norm(nrm, axis=1)[:, None]
+
+
+def _curve_points(kind: str, t: np.ndarray, params: dict):
+    if kind == "disk":
+        a = params["radius"]
+        f = np.full_like(t, a)
+        fp = np.zeros_like(t)
+        pts, tan = _polar_curve(t, f, fp)
+    elif kind == "starfish":
+        r0, amp, lobes = params["r0"], params["amp"], params["lobes"]
+        f = r0 * (1.0 + amp * np.cos(lobes * t))
+        fp = -r0 * amp * lobes * np.sin(lobes * t)
+        pts, tan = _polar_curve(t, f, fp)
+    elif kind == "ellipse":
+        a, b = params["a"], params["b"]
+        pts = np.stack([a * np.cos(t), b * np.sin(t)], axis=-1)
+        tan = np.stack([-a * np.sin(t), b * np.cos(t)], axis=-1)
+    elif kind == "kite":
+        sc = params["scale"]
+        pts = sc * np.stack([np.cos(t) + 0.65 * np.cos(2 * t) - 0.65, 1.5 * np.sin(t)], axis=-1)
+        tan = sc * np.stack([-np.sin(t) - 1.3 * np.sin(2 * t), 1.5 * np.cos(t)], axis=-1)
+    else:
+        raise ValueError(f"unknown 2D shape kind {kind!r}")
+    return pts, _normals_from_tangent(tan)
+
+
+def _discretise_curve(name, kind, params, m, n, d, k, rho_eq, p, r_psi, bounding):
+    t_col = 2.0 * np.pi * np.arange(m, dtype=np.float64) / m
+    t_src = 2.0 * np.pi * np.arange(n, dtype=np.float64) / n
+    colloc, _ = _curve_points(kind, t_col, params)
+    on_curve, nrm = _curve_points(kind, t_src, params)
+    src = on_curve - d * nrm  # inward along the normal (Sec. 3.2)
+    return ShapeDiscretisation(
+        name=name,
+        dim=2,
+        colloc=colloc,
+        src=src,
+        proxy=circle_points(p, r_psi),
+        eqpts=circle_points(k, rho_eq),
+        bounding_radius=bounding,
+        proxy_radius=r_psi,
+        meta=dict(kind=kind, params=params, d=d, rho_eq=rho_eq),
+    )
+
+
+def disk2d(radius=1.0, m=128, n=64, src_radius=0.7, k=64, rho_eq=1.2, p=128, r_psi=1.5):
+    """Disk of the given radius; MFS sources on a concentric circle."""
+    return _discretise_curve("disk", "disk", dict(radius=radius), m, n, radius - src_radius,
+                             k, rho_eq, p, r_psi, radius)
+
+
+def starfish2d(m=256, n=128, d=0.06, k=128, rho_eq=0.67, p=257, r_psi=0.75,
+               r0=0.5, amp=0.3, lobes=5):
+    """Starfish r(theta) = r0 (1 + amp cos(lobes theta)); bounding radius r0(1+amp)."""
+    return _discretise_curve("starfish", "starfish", dict(r0=r0, amp=amp, lobes=lobes),
+                             m, n, d, k, rho_eq, p, r_psi, r0 * (1.0 + amp))
+
+
+def ellipse2d(a=0.65, b=0.325, m=256, n=128, d=0.06, k=128, rho_eq=0.70, p=257, r_psi=0.75):
+    return _discretise_curve("ellipse", "ellipse", dict(a=a, b=b), m, n, d, k, rho_eq, p,
+                             r_psi, max(a, b))
+
+
+def kite2d(bounding=0.65, m=512, n=256, d=0.06, k=256, rho_eq=0.70, p=513, r_psi=0.75):
+    """The classical inverse-scattering kite, rescaled to the given bounding radius."""
+    t = np.linspace(0.0, 2.0 * np.pi, 4097)
+    raw = np.stack([np.cos(t) + 0.65 * np.cos(2 * t) - 0.65, 1.5 * np.sin(t)], axis=-1)
+    scale = bounding / np.linalg.norm(raw, axis=1).max()
+    return _discretise_curve("kite", "kite", dict(scale=scale), m, n, d, k, rho_eq, p,
+                             r_psi, bounding)
+
+
+# --------------------------------------------------------------------------
+# 3D surfaces: Fibonacci point sets mapped radially onto the surface.
+# --------------------------------------------------------------------------
+
+def _radial_surface(name, radius_fn, m, n, src_scale, k, rho_eq, p, r_psi, bounding, meta):
+    u_col = fibonacci_sphere(m, 1.0)
+    u_src = fibonacci_sphere(n, 1.0)
+    colloc = u_col * radius_fn(u_col)[:, None]
+    src = u_src * (src_scale * radius_fn(u_src))[:, None]
+    return ShapeDiscretisation(
+        name=name,
+        dim=3,
+        colloc=colloc,
+        src=src,
+        proxy=fibonacci_sphere(p, r_psi),
+        eqpts=fibonacci_sphere(k, rho_eq),
+        bounding_radius=bounding,
+        proxy_radius=r_psi,
+        meta=dict(meta, src_scale=src_scale, rho_eq=rho_eq),
+    )
+
+
+def sphere3d(radius=1.0, m=900, n=400, src_radius=0.7, k=400, rho_eq=1.2, p=900, r_psi=1.5):
+    """Sphere with Fibonacci collocation, MFS sources, proxy and equivalent points."""
+    return _radial_surface("sphere", lambda u: np.full(u.shape[0], radius), m, n,
+                           src_radius / radius, k, rho_eq, p, r_psi, radius,
+                           dict(kind="sphere", radius=radius))
+
+
+def ellipsoid3d(axes=(1.0, 0.75, 0.5), m=900, n=400, src_scale=0.7, k=400, p=900):
+    ax = np.asarray(axes, dtype=np.float64)
+
+    def rad(u):
+        return 1.0 / np.sqrt(((u / ax) ** 2).sum(-1))
+
+    b = float(ax.max())
+    return _radial_surface("ellipsoid", rad, m, n, src_scale, k, 1.2 * b, p, 1.5 * b, b,
+                           dict(kind="ellipsoid", axes=tuple(axes)))
+
+
+def bumpy_sphere3d(m=900, n=400, src_scale=0.7, k=400, p=900):
+    """r = 1 + 0.1 cos(3 theta) sin(2 phi) in spherical angles."""
+
+    def rad(u):
+        th = np.arccos(np.clip(u[:, 2], -1.0, 1.0))
+        ph = np.arctan2(u[:, 1], u[:, 0])
+        return 1.0 + 0.1 * np.cos(3 * th) * np.sin(2 * ph)
+
+    return _radial_surface("bumpy_sphere", rad, m, n, src_scale, k, 1.32, p, 1.65, 1.1,
+                           dict(kind="bumpy_sphere"))
