@@ -1,0 +1,227 @@
+/* mfs.h -- C ABI of libmfs: the hot path of the multibody MFS scattering method
+ * (Cai, Bagge, Martinsson, "A stable and fast method for solving multibody scattering problems
+ * via the method of fundamental solutions") on AMD Instinct MI355X (gfx950).
+ *
+ * Conventions for every entry point
+ *   - Every call returns an mfs_status: 0 on success, a negative code on failure.  No call
+ *     throws, aborts or exits.  On failure mfs_last_error() returns a thread-local message.
+ *   - Arguments are validated before any work is enqueued; a rejected call leaves outputs
+ *     untouched.  HIP runtime failures map to MFS_ERR_HIP with the HIP error string.
+ *   - "device" pointers are HIP device memory owned by the caller; the library never frees
+ *     them.  "host" pointers are ordinary host memory, read during the call only.
+ *   - Complex numbers are interleaved (re, im): complex128 = 2 x double, complex64 = 2 x float.
+ *   - Multi-right-hand-side vectors are RHS-major, [R][N]: element (r, i) at r * N + i.
+ *   - The global unknowns are ordered body by body: body tau owns the k_tau consecutive
+ *     entries starting at the prefix sum of k over bodies 0..tau-1 (its equivalent points
+ *     x_hat in the order of its shape template).
+ *   - stream is a hipStream_t passed as void* (NULL = the default stream).  Calls marked
+ *     "asynchronous" only enqueue work on that stream; calls marked "synchronous" return
+ *     after their work has finished.
+ *   - All memory the library allocates for itself (scene tables, workspaces, Krylov bases)
+ *     is owned by the scene or freed before return.
+ */
+#ifndef MFS_H_
+#define MFS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MFS_OK = 0,
+  MFS_ERR_ARG = -1,    /* invalid argument: null pointer, bad size, bad enum, unsupported combination */
+  MFS_ERR_NOMEM = -2,  /* device allocation failed */
+  MFS_ERR_HIP = -3,    /* HIP runtime error (message in mfs_last_error) */
+  MFS_ERR_GEOM = -4,   /* geometry not admissible (points coincide, body outside its proxy surface) */
+  MFS_ERR_RANK = -5,   /* a least-squares factorisation has rank zero */
+  MFS_ERR_NOCONV = -6  /* iteration limit reached before the tolerance; outputs hold the last iterate */
+} mfs_status;
+
+typedef enum {
+  MFS_FP64 = 0,  /* all arithmetic in double precision */
+  MFS_FP32 = 1,  /* pair sums and S products in single precision */
+  MFS_MIXED = 2  /* solve only: FP32 operator inside FP64 GMRES, FP64 iterative refinement */
+} mfs_prec;
+
+/* Message for the last failure on this thread ("" if none).  Valid until the next call. */
+const char* mfs_last_error(void);
+
+/* Library version as an integer (major * 10000 + minor * 100 + patch). */
+int mfs_version(void);
+
+/* ------------------------------------------------------------------------------------------
+ * Scattering matrix of one shape (Sec. 4 of the paper, eq. scattering-matrix).
+ *
+ * Point sets are host FP64 arrays, point-major [count][dim], in the body frame:
+ *   colloc  m collocation points x_i on the boundary Gamma           (Sec. 3.1)
+ *   src     n MFS sources y_j inside Gamma                            (Sec. 3.1-3.2)
+ *   proxy   p proxy points z_i on a surface Psi enclosing Gamma       (Sec. 4.1-4.2)
+ *   eqpts   k equivalent points x_hat where incoming fields are sampled and outgoing fields
+ *           are represented.  NULL selects paper mode: x_hat is the skeleton of the
+ *           collocation points found by column-pivoted QR of B (Sec. 4.2), stopped at relative
+ *           precision eps_skel and capped at k_cap points.
+ * Matrices (all phi_kappa): A = phi(x - y) m x n, B = phi(z - x) p x m, D = phi(z - y) p x n,
+ * B_hat = phi(z - x_hat) p x k.
+ *   paper mode:  S = Z* C A^+ U with B ~= B(:, I) Z*, U = conj(Z), B C = D        (Sec. 4.2-4.5)
+ *   given x_hat: S = (B_hat^+ D) A^+ (B_hat^+ B)^T (the same steps with B_hat in place of
+ *                B(:, I); it equals the paper-mode formula when x_hat is a skeleton)
+ * Least-squares solves use Householder QR with column pivoting in FP64, truncated where the
+ * pivot's remaining column norm falls to eps_ls times the first pivot's (basic solution).
+ * ------------------------------------------------------------------------------------------ */
+typedef struct {
+  int32_t dim;          /* 2 or 3 */
+  double kappa;         /* wavenumber > 0 */
+  const double* colloc; /* host, [m][dim] */
+  int64_t m;
+  const double* src;    /* host, [n][dim], n <= m */
+  int64_t n;
+  const double* proxy;  /* host, [p][dim] */
+  int64_t p;
+  const double* eqpts;  /* host, [k][dim], or NULL for paper mode */
+  int64_t k;            /* given mode: number of equivalent points (k <= p) */
+  double eps_skel;      /* paper mode: relative CPQR stopping precision (e.g. 1e-10) */
+  double eps_ls;        /* relative truncation of the least-squares solves (e.g. 1e-13) */
+  int64_t k_cap;        /* paper mode: maximum skeleton size (<= min(p, m)) */
+} mfs_shape_desc;
+
+/* Build S for one shape.  Synchronous.
+ *   S64_dev       device, complex128, column-major k x k (S(i,j) at i + j*k); capacity k*k
+ *                 (paper mode: k_cap*k_cap).  Required.
+ *   S32_dev       device, complex64 copy of S in the same layout, or NULL.
+ *   k_out         host, receives k (paper mode: the skeleton size).  Required.
+ *   skel_idx_out  host, int64[k_cap]: paper mode receives the skeleton indices into colloc
+ *                 (the equivalent points are colloc[skel_idx]); ignored in given mode; may be NULL.
+ *   diag_out      host, double[4] or NULL: {numerical rank of A, numerical rank of B_hat (or of B
+ *                 in paper mode), |R_11|/|R_rr| of the B_hat (B) factorisation, ||S - S^T||_F/||S||_F}.
+ * Errors: MFS_ERR_ARG (sizes, dim, null), MFS_ERR_RANK (a factorisation of rank 0),
+ *         MFS_ERR_NOMEM, MFS_ERR_HIP. */
+mfs_status mfs_build_S(const mfs_shape_desc* desc, void* S64_dev, void* S32_dev, int64_t* k_out,
+                       int64_t* skel_idx_out, double* diag_out, void* stream);
+
+/* ------------------------------------------------------------------------------------------
+ * Scene: T bodies, each a translated copy of one of n_shapes shapes (bodies of one shape share
+ * one S; Sec. 5.1 Example 4).  The scene packs the global equivalent points
+ * x_hat = template[shape_of[tau]] + centres[tau] on the device in FP64 (absolute) and in FP32
+ * (relative to the middle of the bounding box of the centres), with body tables.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct mfs_scene mfs_scene;
+
+/* Create a scene.  Synchronous.
+ *   dim, kappa      2 or 3; wavenumber > 0
+ *   T               number of bodies >= 1
+ *   shape_of        host int32[T], values in [0, n_shapes)
+ *   centres         host double[T][dim]
+ *   k_of_shape      host int64[n_shapes], equivalent points per shape (1..4096)
+ *   eq_template     host array of n_shapes pointers to double[k_s][dim] (body frame)
+ *   S64_dev         host array of n_shapes device pointers to complex128 k_s x k_s column-major
+ *   S32_dev         host array of n_shapes device pointers to complex64 copies, or NULL
+ *                   (then FP32 and mixed operations return MFS_ERR_ARG)
+ * The S buffers stay owned by the caller and must outlive the scene.  Total N = sum k <= 2^31-1.
+ * Errors: MFS_ERR_ARG, MFS_ERR_NOMEM, MFS_ERR_HIP. */
+mfs_status mfs_scene_create(int32_t dim, double kappa, int64_t T, const int32_t* shape_of,
+                            const double* centres, int32_t n_shapes, const int64_t* k_of_shape,
+                            const double* const* eq_template, const void* const* S64_dev,
+                            const void* const* S32_dev, mfs_scene** out);
+
+/* Destroy a scene and free everything it allocated.  Synchronous (waits for the device). */
+mfs_status mfs_scene_destroy(mfs_scene* scene);
+
+/* N (global unknowns), T, and device bytes the scene holds now.  Host outputs may be NULL. */
+mfs_status mfs_scene_size(const mfs_scene* scene, int64_t* N_out, int64_t* T_out, size_t* bytes_out);
+
+/* Copy the packed FP64 equivalent points x_hat (absolute coordinates) to host double[N][dim].
+ * Synchronous. */
+mfs_status mfs_scene_points(const mfs_scene* scene, double* xhat_host);
+
+/* ------------------------------------------------------------------------------------------
+ * Hot path.
+ * ------------------------------------------------------------------------------------------ */
+
+/* Sound-soft plane-wave data at the equivalent points: vhat[r][i] = -exp(i kappa d_r . x_hat_i)
+ * (v = -u_inc, footnote to eq. BVP).  Asynchronous.
+ *   dirs_host  host double[R][dim], unit directions d_r
+ *   vhat_dev   device complex128 [R][N] (output) */
+mfs_status mfs_plane_wave(const mfs_scene* scene, const double* dirs_host, int32_t R, void* vhat_dev,
+                          void* stream);
+
+/* Off-body pair sum t = G_hat q, G_hat(i,j) = phi_kappa(x_hat_i - x_hat_j) for points on different
+ * bodies and 0 on the diagonal blocks (eq. Gmtx-entries, eq. mbody2).  Asynchronous.
+ *   q_dev, t_dev  device [R][N]; complex128 for MFS_FP64, complex64 for MFS_FP32; t != q. */
+mfs_status mfs_ghat_apply(const mfs_scene* scene, const void* q_dev, void* t_dev, int32_t R,
+                          mfs_prec prec, void* stream);
+
+/* Block-diagonal scattering matrices: y = beta * q + S t, y_tau = beta q_tau + S_shape(tau) t_tau
+ * (eq. mbody1).  beta = 0 gives the right-hand side b = S vhat (eq. mbody2) with t = vhat.
+ * Asynchronous.  q_dev may be NULL when beta = 0.  Types as for mfs_ghat_apply. */
+mfs_status mfs_s_apply(const mfs_scene* scene, const void* q_dev, const void* t_dev, void* y_dev,
+                       double beta, int32_t R, mfs_prec prec, void* stream);
+
+/* The operator of eq. mbody2: y = q + S G_hat q.  Asynchronous.
+ *   q_dev, y_dev  device [R][N]; complex128 (MFS_FP64) or complex64 (MFS_FP32); y != q. */
+mfs_status mfs_apply(const mfs_scene* scene, const void* q_dev, void* y_dev, int32_t R, mfs_prec prec,
+                     void* stream);
+
+/* GMRES solve of (I + S G_hat) qhat = S vhat (eq. mbody2, Sec. 2.3), x0 = 0.
+ *   MFS_FP64:  restarted GMRES(restart) with the FP64 operator.
+ *   MFS_MIXED: iterative refinement: r = b - A x with the FP64 operator, then GMRES with the FP32
+ *              operator and FP64 Krylov vectors on A d = r to relative tolerance inner_tol,
+ *              x += d; repeated until ||b - A x|| / ||b|| <= tol (FP64 residual) or max_refine.
+ * Each right-hand side has its own Krylov space; the R operator applications of one iteration
+ * share one pair-kernel launch.  The stopping test is ||b - A x||_2 / ||b||_2 <= tol per column,
+ * checked with the FP64 operator before returning.  Synchronous.
+ *   vhat_dev  device complex128 [R][N]: Dirichlet data at x_hat (b = S vhat is formed inside)
+ *   qhat_dev  device complex128 [R][N]: solution (output)
+ *   info      host, may be NULL. */
+typedef struct {
+  double tol;        /* relative residual target, e.g. 1e-8 */
+  int32_t maxit;     /* total inner iterations (operator applications) allowed */
+  int32_t restart;   /* Krylov basis size before a restart (1..4096) */
+  int32_t max_refine;/* MFS_MIXED: outer refinement steps allowed */
+  double inner_tol;  /* MFS_MIXED: relative residual reduction asked of each inner solve */
+  mfs_prec prec;     /* MFS_FP64 or MFS_MIXED */
+  int32_t verbose;   /* >0: print one line per restart/refinement to stderr */
+} mfs_solve_opts;
+
+typedef struct {
+  int32_t n_matvec32;   /* FP32 operator applications (per right-hand side) */
+  int32_t n_matvec64;   /* FP64 operator applications, including residual checks */
+  int32_t n_refine;     /* refinement steps taken (MFS_MIXED) */
+  int32_t n_restart;    /* GMRES restarts */
+  double relres_max;    /* max over columns of the final FP64 relative residual */
+  double t_total_s;     /* wall time of the call */
+} mfs_solve_info;
+
+mfs_status mfs_solve(const mfs_scene* scene, const void* vhat_dev, int32_t R, const mfs_solve_opts* opts,
+                     void* qhat_dev, mfs_solve_info* info, void* stream);
+
+/* Scattered field u(x) = sum_j phi_kappa(x - x_hat_j) qhat_j at M targets (eq. out_skel), valid for
+ * targets on or outside every body's proxy surface (Sec. 2.3, Sec. 4.1).  Asynchronous.
+ *   qhat_dev     device [R][N] complex128 (MFS_FP64) or complex64 (MFS_FP32)
+ *   targets_dev  device double[M][dim], absolute coordinates
+ *   u_dev        device [R][M], complex128 (MFS_FP64) or complex64 (MFS_FP32) */
+mfs_status mfs_eval_field(const mfs_scene* scene, const void* qhat_dev, int32_t R, const double* targets_dev,
+                          int64_t M, void* u_dev, mfs_prec prec, void* stream);
+
+/* ------------------------------------------------------------------------------------------
+ * Kernel timing (measurement support, not part of the method).
+ * While enabled, every pair-sum launch (G_hat and field evaluation) is bracketed by HIP events
+ * recorded on the stream it runs on, and the algorithmic pair count of the launch is recorded.
+ * ------------------------------------------------------------------------------------------ */
+typedef enum { MFS_KERNEL_PAIR_F32 = 0, MFS_KERNEL_PAIR_F64 = 1 } mfs_kernel_kind;
+
+/* Start (on != 0) or stop recording.  Starting clears earlier records.  Not thread-safe. */
+mfs_status mfs_timing_enable(int32_t on);
+
+/* Totals over the recorded launches of one kind: summed kernel time in milliseconds, number of
+ * launches, and algorithmic pair evaluations (off-body pairs times right-hand sides).  Waits for
+ * the recorded events.  Host outputs may be NULL. */
+mfs_status mfs_timing_read(mfs_kernel_kind kind, double* total_ms, int64_t* launches, double* pairs);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MFS_H_ */

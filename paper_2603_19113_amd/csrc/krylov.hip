@@ -1,0 +1,356 @@
+// FP64 GMRES building blocks (Saad & Schultz; the paper solves eq. mbody2 with GMRES, Sec. 2.3).
+//
+// Every right-hand side r has its own Arnoldi process; vectors are [R][N] complex128 and the
+// basis is V[(m+1)][R][N].  Orthogonalisation is classical Gram-Schmidt applied twice (CGS2):
+// one pass computes all j+1 inner products at once, which reads each basis vector once.
+// Reductions are two-stage with a fixed order (per-block partial sums, then one wave per value),
+// so results are reproducible run to run.  The Hessenberg column update, Givens rotations and
+// the residual estimate run on the device; the host only reads how many columns are still active.
+#include "mfs_internal.h"
+
+namespace mfs {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kElems = 4;   // vector elements per thread in the dot kernels
+constexpr int kGroup = 8;   // basis vectors reduced together
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// partial[r][i][blk] = sum over the block's elements of conj(V_i[r][n]) w[r][n], i = 0..j.
+__global__ __launch_bounds__(kThreads) void dots_kernel(const c128* __restrict__ V, const c128* __restrict__ w,
+                                                        int64_t N, int R, int jcount, int nblk,
+                                                        double* __restrict__ part) {
+  __shared__ double red[kThreads / 64][kGroup][2];
+  const int r = blockIdx.y;
+  const int64_t base = (int64_t)blockIdx.x * (kThreads * kElems);
+  c128 wl[kElems];
+#pragma unroll
+  for (int e = 0; e < kElems; ++e) {
+    const int64_t n = base + e * kThreads + threadIdx.x;
+    wl[e] = n < N ? w[(int64_t)r * N + n] : c128{0.0, 0.0};
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i0 = 0; i0 < jcount; i0 += kGroup) {
+    double sr[kGroup], si[kGroup];
+#pragma unroll
+    for (int g = 0; g < kGroup; ++g) {
+      sr[g] = 0.0;
+      si[g] = 0.0;
+      const int i = i0 + g;
+      if (i < jcount) {
+        const c128* Vi = V + ((int64_t)i * R + r) * N;
+#pragma unroll
+        for (int e = 0; e < kElems; ++e) {
+          const int64_t n = base + e * kThreads + threadIdx.x;
+          if (n < N) {
+            const c128 v = Vi[n];
+            sr[g] = fma(v.re, wl[e].re, fma(v.im, wl[e].im, sr[g]));   // conj(v) * w
+            si[g] = fma(v.re, wl[e].im, fma(-v.im, wl[e].re, si[g]));
+          }
+        }
+      }
+      sr[g] = wave_sum(sr[g]);
+      si[g] = wave_sum(si[g]);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int g = 0; g < kGroup; ++g) {
+        red[wave][g][0] = sr[g];
+        red[wave][g][1] = si[g];
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < kGroup * 2) {
+      const int g = threadIdx.x >> 1, c = threadIdx.x & 1;
+      const int i = i0 + g;
+      if (i < jcount) {
+        double s = 0.0;
+        for (int wv = 0; wv < kThreads / 64; ++wv) s += red[wv][g][c];
+        part[(((int64_t)r * jcount + i) * nblk + blockIdx.x) * 2 + c] = s;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// out[r][i] = sum_blk part[r][i][blk] (+ add[r][i] if add != null); one wave per (i, r).
+__global__ void dots_reduce_kernel(const double* __restrict__ part, int jcount, int nblk, int R, int ld,
+                                   c128* __restrict__ out, const c128* __restrict__ add) {
+  const int i = blockIdx.x, r = blockIdx.y, lane = threadIdx.x;
+  double sr = 0.0, si = 0.0;
+  for (int b = lane; b < nblk; b += 64) {
+    const int64_t o = (((int64_t)r * jcount + i) * nblk + b) * 2;
+    sr += part[o];
+    si += part[o + 1];
+  }
+  sr = wave_sum(sr);
+  si = wave_sum(si);
+  if (lane == 0) {
+    c128 v{sr, si};
+    if (add) {
+      v.re += add[(int64_t)r * ld + i].re;
+      v.im += add[(int64_t)r * ld + i].im;
+    }
+    out[(int64_t)r * ld + i] = v;
+  }
+}
+
+// w[r][n] -= sum_{i<jcount} h[r][i] V_i[r][n]
+__global__ __launch_bounds__(kThreads) void basis_axpy_kernel(const c128* __restrict__ V, const c128* __restrict__ h,
+                                                              int ld, int64_t N, int R, int jcount,
+                                                              c128* __restrict__ w) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (n >= N) return;
+  double ar = 0.0, ai = 0.0;
+  for (int i = 0; i < jcount; ++i) {
+    const c128 hi = h[(int64_t)r * ld + i];
+    const c128 v = V[((int64_t)i * R + r) * N + n];
+    ar = fma(hi.re, v.re, fma(-hi.im, v.im, ar));
+    ai = fma(hi.re, v.im, fma(hi.im, v.re, ai));
+  }
+  c128 x = w[(int64_t)r * N + n];
+  x.re -= ar;
+  x.im -= ai;
+  w[(int64_t)r * N + n] = x;
+}
+
+// part[r][blk] = sum |v|^2 over the block's elements
+__global__ __launch_bounds__(kThreads) void norm_partial_kernel(const c128* __restrict__ v, int64_t N, int nblk,
+                                                                double* __restrict__ part) {
+  __shared__ double red[kThreads / 64];
+  const int r = blockIdx.y;
+  const int64_t base = (int64_t)blockIdx.x * (kThreads * kElems);
+  double s = 0.0;
+#pragma unroll
+  for (int e = 0; e < kElems; ++e) {
+    const int64_t n = base + e * kThreads + threadIdx.x;
+    if (n < N) {
+      const c128 x = v[(int64_t)r * N + n];
+      s = fma(x.re, x.re, fma(x.im, x.im, s));
+    }
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int wv = 0; wv < kThreads / 64; ++wv) t += red[wv];
+    part[(int64_t)r * nblk + blockIdx.x] = t;
+  }
+}
+
+__global__ void norm_reduce_kernel(const double* __restrict__ part, int nblk, double* __restrict__ out) {
+  const int r = blockIdx.x, lane = threadIdx.x;
+  double s = 0.0;
+  for (int b = lane; b < nblk; b += 64) s += part[(int64_t)r * nblk + b];
+  s = wave_sum(s);
+  if (lane == 0) out[r] = sqrt(s);
+}
+
+// Start of a cycle: V_0 = r0 / beta, g = (beta, 0, ...).  Columns with beta == 0 stay inactive.
+__global__ void start_scale_kernel(const c128* __restrict__ r0, const double* __restrict__ beta, int64_t N, int R,
+                                   c128* __restrict__ V0) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (n >= N) return;
+  const double b = beta[r];
+  const double s = b > 0.0 ? 1.0 / b : 0.0;
+  const c128 x = r0[(int64_t)r * N + n];
+  V0[(int64_t)r * N + n] = c128{x.re * s, x.im * s};
+}
+
+__global__ void start_state_kernel(const double* __restrict__ beta, const double* __restrict__ bnorm,
+                                   int32_t* __restrict__ active, int32_t* __restrict__ jlen, c128* __restrict__ g,
+                                   double* __restrict__ res, int m, int R) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  jlen[r] = 0;
+  g[(int64_t)r * (m + 1)] = c128{beta[r], 0.0};
+  const double bn = bnorm[r];
+  res[r] = bn > 0.0 ? beta[r] / bn : 0.0;
+  active[r] = (beta[r] > 0.0 && active[r] != 0) ? 1 : 0;
+}
+
+// Column j of H from the Gram-Schmidt coefficients and ||w||, previous rotations, new rotation,
+// residual estimate.  One thread per right-hand side.
+__global__ void givens_kernel(int j, int m, int R, const c128* __restrict__ hcol, const c128* __restrict__ h2,
+                              const double* __restrict__ hnorm,
+                              c128* __restrict__ H, c128* __restrict__ cs, c128* __restrict__ sn,
+                              c128* __restrict__ g, double* __restrict__ res, const double* __restrict__ bnorm,
+                              double tol, int32_t* __restrict__ active, int32_t* __restrict__ jlen) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R || !active[r]) return;
+  c128* Hc = H + ((int64_t)r * m + j) * (m + 1);
+  for (int i = 0; i <= j; ++i) {
+    const c128 a1 = hcol[(int64_t)r * (m + 1) + i], a2 = h2[(int64_t)r * (m + 1) + i];
+    Hc[i] = c128{a1.re + a2.re, a1.im + a2.im};
+  }
+  Hc[j + 1] = c128{hnorm[r], 0.0};
+  c128* c = cs + (int64_t)r * m;
+  c128* s = sn + (int64_t)r * m;
+  for (int i = 0; i < j; ++i) {
+    const c128 a = Hc[i], b = Hc[i + 1];
+    // tmp = conj(c) a + conj(s) b ; b' = -s a + c b
+    const c128 t{c[i].re * a.re + c[i].im * a.im + s[i].re * b.re + s[i].im * b.im,
+                 c[i].re * a.im - c[i].im * a.re + s[i].re * b.im - s[i].im * b.re};
+    const c128 nb{-(s[i].re * a.re - s[i].im * a.im) + (c[i].re * b.re - c[i].im * b.im),
+                  -(s[i].re * a.im + s[i].im * a.re) + (c[i].re * b.im + c[i].im * b.re)};
+    Hc[i] = t;
+    Hc[i + 1] = nb;
+  }
+  const c128 a = Hc[j], b = Hc[j + 1];
+  const double den = hypot(hypot(a.re, a.im), hypot(b.re, b.im));
+  c128 cj{1.0, 0.0}, sj{0.0, 0.0};
+  if (den > 0.0) {
+    cj = c128{a.re / den, a.im / den};
+    sj = c128{b.re / den, b.im / den};
+  }
+  c[j] = cj;
+  s[j] = sj;
+  Hc[j] = c128{den, 0.0};
+  Hc[j + 1] = c128{0.0, 0.0};
+  c128* gr = g + (int64_t)r * (m + 1);
+  const c128 gj = gr[j];
+  gr[j + 1] = c128{-(sj.re * gj.re - sj.im * gj.im), -(sj.re * gj.im + sj.im * gj.re)};
+  gr[j] = c128{cj.re * gj.re + cj.im * gj.im, cj.re * gj.im - cj.im * gj.re};
+  const double bn = bnorm[r];
+  const double e = hypot(gr[j + 1].re, gr[j + 1].im);
+  res[r] = bn > 0.0 ? e / bn : 0.0;
+  jlen[r] = j + 1;
+  // converged, or breakdown (the Krylov space is invariant: the solution is exact in it)
+  if (res[r] <= tol || !(hnorm[r] > 1e-300)) active[r] = 0;
+}
+
+// V_{j+1} = w / ||w|| for active columns.
+__global__ void scale_next_kernel(const c128* __restrict__ w, const double* __restrict__ hnorm, int64_t N, int R,
+                                  c128* __restrict__ Vn) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (n >= N) return;
+  const double h = hnorm[r];
+  const double s = h > 1e-300 ? 1.0 / h : 0.0;
+  const c128 x = w[(int64_t)r * N + n];
+  Vn[(int64_t)r * N + n] = c128{x.re * s, x.im * s};
+}
+
+// y = H(0:len,0:len)^{-1} g(0:len), back substitution; one thread per right-hand side.
+__global__ void hess_solve_kernel(int m, int R, const c128* __restrict__ H, const c128* __restrict__ g,
+                                  const int32_t* __restrict__ jlen, c128* __restrict__ y) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const int len = jlen[r];
+  c128* yr = y + (int64_t)r * m;
+  for (int i = len - 1; i >= 0; --i) {
+    c128 acc = g[(int64_t)r * (m + 1) + i];
+    for (int c = i + 1; c < len; ++c) {
+      const c128 h = H[((int64_t)r * m + c) * (m + 1) + i];
+      acc.re -= h.re * yr[c].re - h.im * yr[c].im;
+      acc.im -= h.re * yr[c].im + h.im * yr[c].re;
+    }
+    const c128 d = H[((int64_t)r * m + i) * (m + 1) + i];
+    const double dd = d.re * d.re + d.im * d.im;
+    yr[i] = dd > 0.0 ? c128{(acc.re * d.re + acc.im * d.im) / dd, (acc.im * d.re - acc.re * d.im) / dd}
+                     : c128{0.0, 0.0};
+  }
+  for (int i = len; i < m; ++i) yr[i] = c128{0.0, 0.0};
+}
+
+// x[r][n] += sum_{i<len_r} y[r][i] V_i[r][n]
+__global__ __launch_bounds__(kThreads) void update_x_kernel(const c128* __restrict__ V, const c128* __restrict__ y,
+                                                            const int32_t* __restrict__ jlen, int m, int64_t N, int R,
+                                                            c128* __restrict__ x) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (n >= N) return;
+  const int len = jlen[r];
+  double ar = 0.0, ai = 0.0;
+  for (int i = 0; i < len; ++i) {
+    const c128 yi = y[(int64_t)r * m + i];
+    const c128 v = V[((int64_t)i * R + r) * N + n];
+    ar = fma(yi.re, v.re, fma(-yi.im, v.im, ar));
+    ai = fma(yi.re, v.im, fma(yi.im, v.re, ai));
+  }
+  c128 xx = x[(int64_t)r * N + n];
+  xx.re += ar;
+  xx.im += ai;
+  x[(int64_t)r * N + n] = xx;
+}
+
+__global__ void axpby_kernel(const c128* __restrict__ a, const c128* __restrict__ b, c128* __restrict__ out,
+                             double alpha, double beta, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const c128 u = a[i], v = b[i];
+  out[i] = c128{alpha * u.re + beta * v.re, alpha * u.im + beta * v.im};
+}
+
+inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t launch_norms(const c128* v, int64_t N, int R, double* part, int nblk, double* out_norm, hipStream_t st) {
+  hipLaunchKernelGGL(norm_partial_kernel, dim3(nblk, R), dim3(kThreads), 0, st, v, N, nblk, part);
+  hipLaunchKernelGGL(norm_reduce_kernel, dim3(R), dim3(64), 0, st, part, nblk, out_norm);
+  return hipGetLastError();
+}
+
+hipError_t launch_start_cycle(KrylovDev k, const c128* r0, hipStream_t st) {
+  hipError_t e = launch_norms(r0, k.N, k.R, k.part, k.nblk, k.beta, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(start_scale_kernel, dim3(blocks_for(k.N, 256), k.R), dim3(256), 0, st, r0, k.beta, k.N, k.R,
+                     k.V);
+  hipLaunchKernelGGL(start_state_kernel, dim3(blocks_for(k.R, 64)), dim3(64), 0, st, k.beta, k.bnorm, k.active,
+                     k.jlen, k.g, k.res, k.m, k.R);
+  return hipGetLastError();
+}
+
+// CGS2: hcol = V^H w; w -= V hcol; h2 = V^H w; w -= V h2 (H column = hcol + h2, summed in Givens).
+hipError_t launch_arnoldi_orth(KrylovDev k, int j, c128* w, hipStream_t st) {
+  const int jc = j + 1;
+  const int ld = k.m + 1;
+  for (int pass = 0; pass < 2; ++pass) {
+    c128* h = pass == 0 ? k.hcol : k.h2;
+    hipLaunchKernelGGL(dots_kernel, dim3(k.nblk, k.R), dim3(kThreads), 0, st, k.V, w, k.N, k.R, jc, k.nblk, k.part);
+    hipLaunchKernelGGL(dots_reduce_kernel, dim3(jc, k.R), dim3(64), 0, st, k.part, jc, k.nblk, k.R, ld, h,
+                       (const c128*)nullptr);
+    hipLaunchKernelGGL(basis_axpy_kernel, dim3(blocks_for(k.N, kThreads), k.R), dim3(kThreads), 0, st, k.V, h, ld,
+                       k.N, k.R, jc, w);
+  }
+  return hipGetLastError();
+}
+
+// ||w|| -> H(j+1, j); rotations; residual estimate; V_{j+1} = w / ||w||.
+hipError_t launch_arnoldi_finish(KrylovDev k, int j, c128* w, double tol, hipStream_t st) {
+  hipError_t e = launch_norms(w, k.N, k.R, k.part, k.nblk, k.hnorm, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(givens_kernel, dim3(blocks_for(k.R, 64)), dim3(64), 0, st, j, k.m, k.R, k.hcol, k.h2, k.hnorm,
+                     k.H, k.cs, k.sn, k.g, k.res, k.bnorm, tol, k.active, k.jlen);
+  hipLaunchKernelGGL(scale_next_kernel, dim3(blocks_for(k.N, 256), k.R), dim3(256), 0, st, w, k.hnorm, k.N, k.R,
+                     k.V + (int64_t)(j + 1) * k.R * k.N);
+  return hipGetLastError();
+}
+
+// y = H^{-1} g per column, then x += V y.
+hipError_t launch_gmres_update_x(KrylovDev k, c128* x, hipStream_t st) {
+  hipLaunchKernelGGL(hess_solve_kernel, dim3(blocks_for(k.R, 64)), dim3(64), 0, st, k.m, k.R, k.H, k.g, k.jlen, k.y);
+  hipLaunchKernelGGL(update_x_kernel, dim3(blocks_for(k.N, kThreads), k.R), dim3(kThreads), 0, st, k.V, k.y, k.jlen,
+                     k.m, k.N, k.R, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby(const c128* a, const c128* b, c128* out, double alpha, double beta, int64_t n,
+                        hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(axpby_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, a, b, out, alpha, beta, n);
+  return hipGetLastError();
+}
+
+int krylov_nblk(int64_t N) { return (int)((N + kThreads * kElems - 1) / (kThreads * kElems)); }
+
+}  // namespace mfs

@@ -1,0 +1,632 @@
+// C ABI of libmfs: scenes, the operator I + S G_hat (eq. mbody2), field evaluation and the
+// GMRES / GMRES-IR driver.  Kernels live in pair_kernels.hip, sapply.hip, krylov.hip, lsq.hip.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mfs_internal.h"
+
+namespace mfs {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+mfs_status fail(mfs_status code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+// Grow-only device buffer owned by a scene.
+struct Buf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+static mfs_status ensure(Buf& b, size_t bytes, size_t* total) {
+  if (b.cap >= bytes) return MFS_OK;
+  if (b.p) {
+    hipError_t e = hipFree(b.p);
+    if (e != hipSuccess) return fail(MFS_ERR_HIP, std::string("hipFree: ") + hipGetErrorString(e));
+    *total -= b.cap;
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MFS_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+  }
+  b.p = p;
+  b.cap = bytes;
+  *total += bytes;
+  return MFS_OK;
+}
+
+static void release(Buf& b, size_t* total) {
+  if (b.p) {
+    (void)hipFree(b.p);
+    *total -= b.cap;
+  }
+  b.p = nullptr;
+  b.cap = 0;
+}
+
+// ----------------------------------------------------------- kernel timing ---
+struct TimingRecord {
+  int kind;
+  double pairs;
+  hipEvent_t e0, e1;
+};
+static bool g_timing_on = false;
+static std::vector<TimingRecord> g_timing;
+
+TimedLaunch::TimedLaunch(int k, double p, hipStream_t s) : kind(k), pairs(p), st(s), ev0(nullptr), ev1(nullptr) {
+  if (!g_timing_on) return;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return;
+  }
+  ev0 = a;
+  ev1 = b;
+  (void)hipEventRecord(a, st);
+}
+
+TimedLaunch::~TimedLaunch() {
+  if (!ev0) return;
+  (void)hipEventRecord(static_cast<hipEvent_t>(ev1), st);
+  g_timing.push_back(TimingRecord{kind, pairs, static_cast<hipEvent_t>(ev0), static_cast<hipEvent_t>(ev1)});
+}
+
+static void timing_clear() {
+  for (auto& r : g_timing) {
+    (void)hipEventDestroy(r.e0);
+    (void)hipEventDestroy(r.e1);
+  }
+  g_timing.clear();
+}
+
+}  // namespace mfs
+
+using namespace mfs;
+
+struct mfs_scene {
+  SceneDev dev{};
+  int n_shapes = 0;
+  int64_t kmax = 0;
+  bool has_s32 = false;
+  std::vector<int64_t> k_of_shape;
+  size_t bytes = 0;
+  // owned tables
+  Buf x64, x32, body_of, body_ptr, shape_of, k_dev, S64_tab, S32_tab;
+  // workspaces
+  Buf partial, q32, dirs, kry, vecs;
+};
+
+namespace {
+
+#define MFS_TRY(expr)                  \
+  do {                                 \
+    mfs_status s__ = (expr);           \
+    if (s__ != MFS_OK) return s__;     \
+  } while (0)
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+mfs_status check_scene(const mfs_scene* s) {
+  if (!s) return fail(MFS_ERR_ARG, "scene is null");
+  return MFS_OK;
+}
+
+mfs_status check_prec_operator(const mfs_scene* s, mfs_prec prec) {
+  if (prec != MFS_FP64 && prec != MFS_FP32)
+    return fail(MFS_ERR_ARG, "operator precision must be MFS_FP64 or MFS_FP32");
+  if (prec == MFS_FP32 && !s->has_s32) return fail(MFS_ERR_ARG, "scene was created without FP32 copies of S");
+  return MFS_OK;
+}
+
+int tpt_for(mfs_prec prec) { return prec == MFS_FP64 ? 1 : 2; }
+
+// y = q + S G_hat q in FP64 (all operands complex128).
+mfs_status apply_f64(mfs_scene* s, const c128* q, c128* y, int R, hipStream_t st) {
+  const int nch = pair_chunks_for(s->dev.N, s->dev.N, tpt_for(MFS_FP64));
+  MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c128), &s->bytes));
+  c128* part = static_cast<c128*>(s->partial.p);
+  {
+    TimedLaunch tl(MFS_KERNEL_PAIR_F64, s->dev.offbody_pairs * R, st);
+    MFS_HIP_TRY(launch_ghat_f64(s->dev, q, R, part, nch, st));
+  }
+  MFS_HIP_TRY(launch_sapply_f64(s->dev, part, nch, q, 1.0, y, R, (int)s->kmax, st));
+  return MFS_OK;
+}
+
+// y = q + S G_hat q in FP32 (complex64 in and out).
+mfs_status apply_f32(mfs_scene* s, const c64* q, c64* y, int R, hipStream_t st) {
+  const int nch = pair_chunks_for(s->dev.N, s->dev.N, tpt_for(MFS_FP32));
+  MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c64), &s->bytes));
+  c64* part = static_cast<c64*>(s->partial.p);
+  {
+    TimedLaunch tl(MFS_KERNEL_PAIR_F32, s->dev.offbody_pairs * R, st);
+    MFS_HIP_TRY(launch_ghat_f32(s->dev, q, R, part, nch, st));
+  }
+  MFS_HIP_TRY(launch_sapply_f32(s->dev, part, nch, q, 1.0f, y, R, (int)s->kmax, st));
+  return MFS_OK;
+}
+
+// y = q + S G_hat q with q, y complex128 and the pair sum and S product in FP32: the identity
+// part stays exact in FP64, only S G_hat q carries single-precision error.
+mfs_status apply_mixed(mfs_scene* s, const c128* q, c128* y, int R, hipStream_t st) {
+  const int64_t NR = s->dev.N * R;
+  MFS_TRY(ensure(s->q32, (size_t)NR * sizeof(c64), &s->bytes));
+  const int nch = pair_chunks_for(s->dev.N, s->dev.N, tpt_for(MFS_FP32));
+  MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c64), &s->bytes));
+  c64* q32 = static_cast<c64*>(s->q32.p);
+  c64* part = static_cast<c64*>(s->partial.p);
+  MFS_HIP_TRY(launch_to_c64(q, q32, NR, st));
+  {
+    TimedLaunch tl(MFS_KERNEL_PAIR_F32, s->dev.offbody_pairs * R, st);
+    MFS_HIP_TRY(launch_ghat_f32(s->dev, q32, R, part, nch, st));
+  }
+  MFS_HIP_TRY(launch_sapply_mixed(s->dev, part, nch, q, 1.0, y, R, (int)s->kmax, st));
+  return MFS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mfs_last_error(void) { return g_last_error.c_str(); }
+
+int mfs_version(void) { return 100; }
+
+mfs_status mfs_build_S(const mfs_shape_desc* desc, void* S64_dev, void* S32_dev, int64_t* k_out,
+                       int64_t* skel_idx_out, double* diag_out, void* stream) {
+  g_last_error.clear();
+  return build_S_impl(desc, S64_dev, S32_dev, k_out, skel_idx_out, diag_out, as_stream(stream));
+}
+
+mfs_status mfs_scene_create(int32_t dim, double kappa, int64_t T, const int32_t* shape_of, const double* centres,
+                            int32_t n_shapes, const int64_t* k_of_shape, const double* const* eq_template,
+                            const void* const* S64_dev, const void* const* S32_dev, mfs_scene** out) {
+  g_last_error.clear();
+  if (!out) return fail(MFS_ERR_ARG, "out is null");
+  *out = nullptr;
+  if (dim != 2 && dim != 3) return fail(MFS_ERR_ARG, "dim must be 2 or 3");
+  if (!(kappa > 0.0) || !std::isfinite(kappa)) return fail(MFS_ERR_ARG, "kappa must be positive and finite");
+  if (T < 1) return fail(MFS_ERR_ARG, "T must be >= 1");
+  if (n_shapes < 1) return fail(MFS_ERR_ARG, "n_shapes must be >= 1");
+  if (!shape_of || !centres || !k_of_shape || !eq_template || !S64_dev)
+    return fail(MFS_ERR_ARG, "null table pointer");
+  int64_t kmax = 0;
+  for (int s = 0; s < n_shapes; ++s) {
+    if (k_of_shape[s] < 1 || k_of_shape[s] > 4096)
+      return fail(MFS_ERR_ARG, "k_of_shape[" + std::to_string(s) + "] must be in 1..4096");
+    if (!eq_template[s] || !S64_dev[s]) return fail(MFS_ERR_ARG, "null template or S for shape " + std::to_string(s));
+    if (S32_dev && !S32_dev[s]) return fail(MFS_ERR_ARG, "null S32 for shape " + std::to_string(s));
+    kmax = std::max(kmax, k_of_shape[s]);
+  }
+  std::vector<int64_t> body_ptr(T + 1, 0);
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t t = 0; t < T; ++t) {
+    const int s = shape_of[t];
+    if (s < 0 || s >= n_shapes) return fail(MFS_ERR_ARG, "shape_of[" + std::to_string(t) + "] out of range");
+    body_ptr[t + 1] = body_ptr[t] + k_of_shape[s];
+    for (int d = 0; d < dim; ++d) {
+      const double c = centres[t * dim + d];
+      if (!std::isfinite(c)) return fail(MFS_ERR_ARG, "non-finite centre");
+      lo[d] = std::min(lo[d], c);
+      hi[d] = std::max(hi[d], c);
+    }
+  }
+  const int64_t N = body_ptr[T];
+  if (N > 0x7fffffff) return fail(MFS_ERR_ARG, "N exceeds 2^31-1");
+  double same_body_pairs = 0.0;
+  for (int64_t t = 0; t < T; ++t) {
+    const double kt = (double)(body_ptr[t + 1] - body_ptr[t]);
+    same_body_pairs += kt * kt;
+  }
+  std::vector<int64_t> tmpl_ptr(n_shapes + 1, 0);
+  for (int s = 0; s < n_shapes; ++s) tmpl_ptr[s + 1] = tmpl_ptr[s] + k_of_shape[s];
+  std::vector<double> tmpl(tmpl_ptr[n_shapes] * dim);
+  for (int s = 0; s < n_shapes; ++s)
+    std::memcpy(&tmpl[tmpl_ptr[s] * dim], eq_template[s], sizeof(double) * k_of_shape[s] * dim);
+  double origin[3] = {0.0, 0.0, 0.0};
+  for (int d = 0; d < dim; ++d) origin[d] = 0.5 * (lo[d] + hi[d]);
+
+  mfs_scene* sc = new mfs_scene();
+  sc->n_shapes = n_shapes;
+  sc->kmax = kmax;
+  sc->has_s32 = S32_dev != nullptr;
+  sc->k_of_shape.assign(k_of_shape, k_of_shape + n_shapes);
+  auto cleanup = [&](mfs_status st) {
+    mfs_scene_destroy(sc);
+    return st;
+  };
+  Buf centres_d, tmpl_d, tmpl_ptr_d;
+  size_t tmp_bytes = 0;
+  mfs_status st;
+  if ((st = ensure(sc->x64, sizeof(double) * dim * N, &sc->bytes)) != MFS_OK) return cleanup(st);
+  if ((st = ensure(sc->x32, sizeof(float) * dim * N, &sc->bytes)) != MFS_OK) return cleanup(st);
+  if ((st = ensure(sc->body_of, sizeof(int32_t) * N, &sc->bytes)) != MFS_OK) return cleanup(st);
+  if ((st = ensure(sc->body_ptr, sizeof(int64_t) * (T + 1), &sc->bytes)) != MFS_OK) return cleanup(st);
+  if ((st = ensure(sc->shape_of, sizeof(int32_t) * T, &sc->bytes)) != MFS_OK) return cleanup(st);
+  if ((st = ensure(sc->k_dev, sizeof(int64_t) * n_shapes, &sc->bytes)) != MFS_OK) return cleanup(st);
+  if ((st = ensure(sc->S64_tab, sizeof(void*) * n_shapes, &sc->bytes)) != MFS_OK) return cleanup(st);
+  if ((st = ensure(sc->S32_tab, sizeof(void*) * n_shapes, &sc->bytes)) != MFS_OK) return cleanup(st);
+  if ((st = ensure(centres_d, sizeof(double) * T * dim, &tmp_bytes)) != MFS_OK) return cleanup(st);
+  if ((st = ensure(tmpl_d, sizeof(double) * tmpl.size(), &tmp_bytes)) != MFS_OK) return cleanup(st);
+  if ((st = ensure(tmpl_ptr_d, sizeof(int64_t) * tmpl_ptr.size(), &tmp_bytes)) != MFS_OK) return cleanup(st);
+
+  std::vector<const void*> s32v(n_shapes, nullptr);
+  if (S32_dev)
+    for (int s = 0; s < n_shapes; ++s) s32v[s] = S32_dev[s];
+  hipError_t e = hipSuccess;
+  auto cp = [&](void* dst, const void* src, size_t n) {
+    if (e == hipSuccess) e = hipMemcpy(dst, src, n, hipMemcpyHostToDevice);
+  };
+  cp(sc->body_ptr.p, body_ptr.data(), sizeof(int64_t) * (T + 1));
+  cp(sc->shape_of.p, shape_of, sizeof(int32_t) * T);
+  cp(sc->k_dev.p, k_of_shape, sizeof(int64_t) * n_shapes);
+  cp(sc->S64_tab.p, S64_dev, sizeof(void*) * n_shapes);
+  cp(sc->S32_tab.p, s32v.data(), sizeof(void*) * n_shapes);
+  cp(centres_d.p, centres, sizeof(double) * T * dim);
+  cp(tmpl_d.p, tmpl.data(), sizeof(double) * tmpl.size());
+  cp(tmpl_ptr_d.p, tmpl_ptr.data(), sizeof(int64_t) * tmpl_ptr.size());
+  if (e == hipSuccess)
+    e = launch_pack_scene(dim, T, static_cast<int32_t*>(sc->shape_of.p), static_cast<double*>(centres_d.p),
+                          static_cast<int64_t*>(tmpl_ptr_d.p), static_cast<double*>(tmpl_d.p),
+                          static_cast<int64_t*>(sc->body_ptr.p), origin, static_cast<double*>(sc->x64.p),
+                          static_cast<float*>(sc->x32.p), static_cast<int32_t*>(sc->body_of.p), N, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  release(centres_d, &tmp_bytes);
+  release(tmpl_d, &tmp_bytes);
+  release(tmpl_ptr_d, &tmp_bytes);
+  if (e != hipSuccess) return cleanup(fail(MFS_ERR_HIP, std::string("scene packing: ") + hipGetErrorString(e)));
+
+  SceneDev& d = sc->dev;
+  d.dim = dim;
+  d.N = N;
+  d.T = T;
+  d.kappa = kappa;
+  for (int i = 0; i < 3; ++i) {
+    d.origin[i] = origin[i];
+    d.x64[i] = i < dim ? static_cast<double*>(sc->x64.p) + (size_t)i * N : nullptr;
+    d.x32[i] = i < dim ? static_cast<float*>(sc->x32.p) + (size_t)i * N : nullptr;
+  }
+  d.body_of = static_cast<int32_t*>(sc->body_of.p);
+  d.body_ptr = static_cast<int64_t*>(sc->body_ptr.p);
+  d.shape_of = static_cast<int32_t*>(sc->shape_of.p);
+  d.k_of_shape = static_cast<int64_t*>(sc->k_dev.p);
+  d.S64 = static_cast<const void* const*>(sc->S64_tab.p);
+  d.S32 = static_cast<const void* const*>(sc->S32_tab.p);
+  d.offbody_pairs = (double)N * (double)N - same_body_pairs;
+  *out = sc;
+  return MFS_OK;
+}
+
+mfs_status mfs_scene_destroy(mfs_scene* s) {
+  if (!s) return MFS_OK;
+  (void)hipDeviceSynchronize();
+  Buf* all[] = {&s->x64, &s->x32, &s->body_of, &s->body_ptr, &s->shape_of, &s->k_dev, &s->S64_tab,
+                &s->S32_tab, &s->partial, &s->q32, &s->dirs, &s->kry, &s->vecs};
+  for (Buf* b : all) release(*b, &s->bytes);
+  delete s;
+  return MFS_OK;
+}
+
+mfs_status mfs_scene_size(const mfs_scene* s, int64_t* N_out, int64_t* T_out, size_t* bytes_out) {
+  MFS_TRY(check_scene(s));
+  if (N_out) *N_out = s->dev.N;
+  if (T_out) *T_out = s->dev.T;
+  if (bytes_out) *bytes_out = s->bytes;
+  return MFS_OK;
+}
+
+mfs_status mfs_scene_points(const mfs_scene* s, double* xhat_host) {
+  MFS_TRY(check_scene(s));
+  if (!xhat_host) return fail(MFS_ERR_ARG, "xhat_host is null");
+  const int dim = s->dev.dim;
+  const int64_t N = s->dev.N;
+  std::vector<double> soa((size_t)dim * N);
+  MFS_HIP_TRY(hipMemcpy(soa.data(), s->x64.p, sizeof(double) * soa.size(), hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < N; ++i)
+    for (int d = 0; d < dim; ++d) xhat_host[i * dim + d] = soa[(size_t)d * N + i];
+  return MFS_OK;
+}
+
+mfs_status mfs_plane_wave(const mfs_scene* sc, const double* dirs_host, int32_t R, void* vhat_dev, void* stream) {
+  MFS_TRY(check_scene(sc));
+  mfs_scene* s = const_cast<mfs_scene*>(sc);
+  if (R < 1 || !dirs_host || !vhat_dev) return fail(MFS_ERR_ARG, "plane wave: bad R or null pointer");
+  MFS_TRY(ensure(s->dirs, sizeof(double) * R * s->dev.dim, &s->bytes));
+  hipStream_t st = as_stream(stream);
+  MFS_HIP_TRY(hipMemcpyAsync(s->dirs.p, dirs_host, sizeof(double) * R * s->dev.dim, hipMemcpyHostToDevice, st));
+  MFS_HIP_TRY(hipStreamSynchronize(st));  // dirs_host may be released by the caller on return
+  MFS_HIP_TRY(launch_plane_wave(s->dev, static_cast<double*>(s->dirs.p), R, static_cast<c128*>(vhat_dev), st));
+  return MFS_OK;
+}
+
+mfs_status mfs_ghat_apply(const mfs_scene* sc, const void* q_dev, void* t_dev, int32_t R, mfs_prec prec,
+                          void* stream) {
+  MFS_TRY(check_scene(sc));
+  MFS_TRY(check_prec_operator(sc, prec == MFS_FP32 ? MFS_FP64 : prec));
+  if (R < 1 || !q_dev || !t_dev || q_dev == t_dev) return fail(MFS_ERR_ARG, "ghat: bad R or pointers");
+  mfs_scene* s = const_cast<mfs_scene*>(sc);
+  hipStream_t st = as_stream(stream);
+  const int nch = pair_chunks_for(s->dev.N, s->dev.N, tpt_for(prec));
+  if (prec == MFS_FP64) {
+    MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c128), &s->bytes));
+    c128* part = static_cast<c128*>(s->partial.p);
+    {
+      TimedLaunch tl(MFS_KERNEL_PAIR_F64, s->dev.offbody_pairs * R, st);
+      MFS_HIP_TRY(launch_ghat_f64(s->dev, static_cast<const c128*>(q_dev), R, part, nch, st));
+    }
+    MFS_HIP_TRY(launch_reduce_partials_f64(part, nch, s->dev.N, R, static_cast<c128*>(t_dev), st));
+  } else {
+    MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c64), &s->bytes));
+    c64* part = static_cast<c64*>(s->partial.p);
+    {
+      TimedLaunch tl(MFS_KERNEL_PAIR_F32, s->dev.offbody_pairs * R, st);
+      MFS_HIP_TRY(launch_ghat_f32(s->dev, static_cast<const c64*>(q_dev), R, part, nch, st));
+    }
+    MFS_HIP_TRY(launch_reduce_partials_f32(part, nch, s->dev.N, R, static_cast<c64*>(t_dev), st));
+  }
+  return MFS_OK;
+}
+
+mfs_status mfs_s_apply(const mfs_scene* sc, const void* q_dev, const void* t_dev, void* y_dev, double beta,
+                       int32_t R, mfs_prec prec, void* stream) {
+  MFS_TRY(check_scene(sc));
+  MFS_TRY(check_prec_operator(sc, prec));
+  if (R < 1 || !t_dev || !y_dev || (beta != 0.0 && !q_dev)) return fail(MFS_ERR_ARG, "s_apply: bad R or pointers");
+  if (t_dev == y_dev) return fail(MFS_ERR_ARG, "s_apply: y must not alias t");
+  mfs_scene* s = const_cast<mfs_scene*>(sc);
+  hipStream_t st = as_stream(stream);
+  if (prec == MFS_FP64) {
+    MFS_HIP_TRY(launch_sapply_f64(s->dev, static_cast<const c128*>(t_dev), 1, static_cast<const c128*>(q_dev), beta,
+                                  static_cast<c128*>(y_dev), R, (int)s->kmax, st));
+  } else {
+    MFS_HIP_TRY(launch_sapply_f32(s->dev, static_cast<const c64*>(t_dev), 1, static_cast<const c64*>(q_dev),
+                                  (float)beta, static_cast<c64*>(y_dev), R, (int)s->kmax, st));
+  }
+  return MFS_OK;
+}
+
+mfs_status mfs_apply(const mfs_scene* sc, const void* q_dev, void* y_dev, int32_t R, mfs_prec prec, void* stream) {
+  MFS_TRY(check_scene(sc));
+  MFS_TRY(check_prec_operator(sc, prec));
+  if (R < 1 || !q_dev || !y_dev || q_dev == y_dev) return fail(MFS_ERR_ARG, "apply: bad R or pointers");
+  mfs_scene* s = const_cast<mfs_scene*>(sc);
+  hipStream_t st = as_stream(stream);
+  if (prec == MFS_FP64) return apply_f64(s, static_cast<const c128*>(q_dev), static_cast<c128*>(y_dev), R, st);
+  return apply_f32(s, static_cast<const c64*>(q_dev), static_cast<c64*>(y_dev), R, st);
+}
+
+mfs_status mfs_eval_field(const mfs_scene* sc, const void* qhat_dev, int32_t R, const double* targets_dev, int64_t M,
+                          void* u_dev, mfs_prec prec, void* stream) {
+  MFS_TRY(check_scene(sc));
+  MFS_TRY(check_prec_operator(sc, prec == MFS_FP32 ? MFS_FP64 : prec));
+  if (R < 1 || M < 0 || !qhat_dev || !u_dev || (M > 0 && !targets_dev))
+    return fail(MFS_ERR_ARG, "eval_field: bad sizes or pointers");
+  if (M == 0) return MFS_OK;
+  mfs_scene* s = const_cast<mfs_scene*>(sc);
+  hipStream_t st = as_stream(stream);
+  const int nch = pair_chunks_for(s->dev.N, M, tpt_for(prec));
+  if (prec == MFS_FP64) {
+    MFS_TRY(ensure(s->partial, (size_t)nch * R * M * sizeof(c128), &s->bytes));
+    c128* part = static_cast<c128*>(s->partial.p);
+    {
+      TimedLaunch tl(MFS_KERNEL_PAIR_F64, (double)M * s->dev.N * R, st);
+      MFS_HIP_TRY(launch_eval_f64(s->dev, static_cast<const c128*>(qhat_dev), R, targets_dev, M, part, nch, st));
+    }
+    MFS_HIP_TRY(launch_reduce_partials_f64(part, nch, M, R, static_cast<c128*>(u_dev), st));
+  } else {
+    MFS_TRY(ensure(s->partial, (size_t)nch * R * M * sizeof(c64), &s->bytes));
+    c64* part = static_cast<c64*>(s->partial.p);
+    {
+      TimedLaunch tl(MFS_KERNEL_PAIR_F32, (double)M * s->dev.N * R, st);
+      MFS_HIP_TRY(launch_eval_f32(s->dev, static_cast<const c64*>(qhat_dev), R, targets_dev, M, part, nch, st));
+    }
+    MFS_HIP_TRY(launch_reduce_partials_f32(part, nch, M, R, static_cast<c64*>(u_dev), st));
+  }
+  return MFS_OK;
+}
+
+// ------------------------------------------------------------------- solve ---
+mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const mfs_solve_opts* opts,
+                     void* qhat_dev, mfs_solve_info* info, void* stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  MFS_TRY(check_scene(sc));
+  if (!opts || !vhat_dev || !qhat_dev || R < 1) return fail(MFS_ERR_ARG, "solve: null pointer or R < 1");
+  const mfs_prec prec = opts->prec;
+  if (prec != MFS_FP64 && prec != MFS_MIXED) return fail(MFS_ERR_ARG, "solve: prec must be MFS_FP64 or MFS_MIXED");
+  if (prec == MFS_MIXED && !sc->has_s32) return fail(MFS_ERR_ARG, "solve: MFS_MIXED needs FP32 copies of S");
+  if (!(opts->tol > 0.0) || opts->maxit < 1 || opts->restart < 1 || opts->restart > 4096)
+    return fail(MFS_ERR_ARG, "solve: need tol > 0, maxit >= 1, 1 <= restart <= 4096");
+  if (prec == MFS_MIXED && (opts->max_refine < 1 || !(opts->inner_tol > 0.0) || !(opts->inner_tol < 1.0)))
+    return fail(MFS_ERR_ARG, "solve: MFS_MIXED needs max_refine >= 1 and 0 < inner_tol < 1");
+  mfs_scene* s = const_cast<mfs_scene*>(sc);
+  hipStream_t st = as_stream(stream);
+  const int64_t N = s->dev.N;
+  const int64_t NR = N * R;
+  const int m = opts->restart;
+
+  // ---- Krylov state and vectors in two grow-only scene workspaces
+  KrylovDev k{};
+  k.N = N;
+  k.R = R;
+  k.m = m;
+  k.nblk = krylov_nblk(N);
+  const size_t szV = sizeof(c128) * (size_t)(m + 1) * NR;
+  const size_t szH = sizeof(c128) * (size_t)R * m * (m + 1);
+  const size_t szRm = sizeof(c128) * (size_t)R * m;
+  const size_t szRm1 = sizeof(c128) * (size_t)R * (m + 1);
+  const size_t szPart = sizeof(double) * 2 * (size_t)R * (m + 1) * k.nblk;
+  size_t off = 0;
+  auto carve = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  const size_t oV = carve(szV), oH = carve(szH), ocs = carve(szRm), osn = carve(szRm), og = carve(szRm1),
+               oh1 = carve(szRm1), oh2 = carve(szRm1), oy = carve(szRm), obeta = carve(8 * R), obn = carve(8 * R),
+               ores = carve(8 * R), ohn = carve(8 * R), oact = carve(4 * R), ojl = carve(4 * R),
+               opart = carve(szPart);
+  MFS_TRY(ensure(s->kry, off, &s->bytes));
+  char* base = static_cast<char*>(s->kry.p);
+  k.V = reinterpret_cast<c128*>(base + oV);
+  k.H = reinterpret_cast<c128*>(base + oH);
+  k.cs = reinterpret_cast<c128*>(base + ocs);
+  k.sn = reinterpret_cast<c128*>(base + osn);
+  k.g = reinterpret_cast<c128*>(base + og);
+  k.hcol = reinterpret_cast<c128*>(base + oh1);
+  k.h2 = reinterpret_cast<c128*>(base + oh2);
+  k.y = reinterpret_cast<c128*>(base + oy);
+  k.beta = reinterpret_cast<double*>(base + obeta);
+  k.bnorm = reinterpret_cast<double*>(base + obn);
+  k.res = reinterpret_cast<double*>(base + ores);
+  k.hnorm = reinterpret_cast<double*>(base + ohn);
+  k.active = reinterpret_cast<int32_t*>(base + oact);
+  k.jlen = reinterpret_cast<int32_t*>(base + ojl);
+  k.part = reinterpret_cast<double*>(base + opart);
+
+  MFS_TRY(ensure(s->vecs, 3 * sizeof(c128) * (size_t)NR + 256, &s->bytes));
+  c128* b = static_cast<c128*>(s->vecs.p);
+  c128* r = b + NR;
+  c128* w = r + NR;
+  c128* x = static_cast<c128*>(qhat_dev);
+  double* bnorm_dev = k.bnorm;
+
+  std::vector<double> bnorm(R), rnorm(R), relres(R, 1.0);
+  std::vector<int32_t> active(R);
+  int n64 = 0, n32 = 0, n_refine = 0, n_restart = 0, total_it = 0;
+
+  auto read_doubles = [&](const double* dev, std::vector<double>& host) -> mfs_status {
+    MFS_HIP_TRY(hipMemcpyAsync(host.data(), dev, sizeof(double) * R, hipMemcpyDeviceToHost, st));
+    MFS_HIP_TRY(hipStreamSynchronize(st));
+    return MFS_OK;
+  };
+  auto residual = [&]() -> mfs_status {  // r = b - A64 x, relres per column
+    MFS_TRY(apply_f64(s, x, w, R, st));
+    ++n64;
+    MFS_HIP_TRY(launch_axpby(b, w, r, 1.0, -1.0, NR, st));
+    MFS_HIP_TRY(launch_norms(r, N, R, k.part, k.nblk, k.hnorm, st));
+    MFS_TRY(read_doubles(k.hnorm, rnorm));
+    for (int c = 0; c < R; ++c) relres[c] = bnorm[c] > 0.0 ? rnorm[c] / bnorm[c] : 0.0;
+    return MFS_OK;
+  };
+  auto max_relres = [&]() {
+    double mx = 0.0;
+    for (double v : relres) mx = std::max(mx, v);
+    return mx;
+  };
+  auto set_active_from_relres = [&]() -> mfs_status {
+    for (int c = 0; c < R; ++c) active[c] = relres[c] > opts->tol ? 1 : 0;
+    MFS_HIP_TRY(hipMemcpyAsync(k.active, active.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice, st));
+    return MFS_OK;
+  };
+  // one GMRES cycle from the residual in r; x += V y.  Returns after m steps, convergence of all
+  // active columns to ktol (relative to kk.bnorm), or the iteration budget.
+  auto cycle = [&](KrylovDev kk, double ktol, bool mixed) -> mfs_status {
+    MFS_HIP_TRY(launch_start_cycle(kk, r, st));
+    for (int j = 0; j < m; ++j) {
+      c128* Vj = kk.V + (int64_t)j * NR;
+      if (mixed) {
+        MFS_TRY(apply_mixed(s, Vj, w, R, st));
+        ++n32;
+      } else {
+        MFS_TRY(apply_f64(s, Vj, w, R, st));
+        ++n64;
+      }
+      MFS_HIP_TRY(launch_arnoldi_orth(kk, j, w, st));
+      MFS_HIP_TRY(launch_arnoldi_finish(kk, j, w, ktol, st));
+      ++total_it;
+      MFS_HIP_TRY(hipMemcpyAsync(active.data(), kk.active, sizeof(int32_t) * R, hipMemcpyDeviceToHost, st));
+      MFS_HIP_TRY(hipStreamSynchronize(st));
+      int na = 0;
+      for (int c = 0; c < R; ++c) na += active[c];
+      if (na == 0 || total_it >= opts->maxit) break;
+    }
+    MFS_HIP_TRY(launch_gmres_update_x(kk, x, st));
+    return MFS_OK;
+  };
+
+  // b = S vhat (eq. mbody2), x0 = 0, r0 = b
+  MFS_HIP_TRY(launch_sapply_f64(s->dev, static_cast<const c128*>(vhat_dev), 1, nullptr, 0.0, b, R, (int)s->kmax, st));
+  MFS_HIP_TRY(launch_norms(b, N, R, k.part, k.nblk, bnorm_dev, st));
+  MFS_TRY(read_doubles(bnorm_dev, bnorm));
+  MFS_HIP_TRY(hipMemsetAsync(x, 0, sizeof(c128) * NR, st));
+  MFS_HIP_TRY(hipMemcpyAsync(r, b, sizeof(c128) * NR, hipMemcpyDeviceToDevice, st));
+  for (int c = 0; c < R; ++c) relres[c] = bnorm[c] > 0.0 ? 1.0 : 0.0;
+
+  if (prec == MFS_FP64) {
+    while (max_relres() > opts->tol && total_it < opts->maxit) {
+      MFS_TRY(set_active_from_relres());
+      MFS_TRY(cycle(k, opts->tol, false));
+      ++n_restart;
+      MFS_TRY(residual());
+      if (opts->verbose)
+        std::fprintf(stderr, "[mfs_solve fp64] cycle %d  iters %d  max relres %.3e\n", n_restart, total_it,
+                     max_relres());
+    }
+  } else {
+    while (max_relres() > opts->tol && n_refine < opts->max_refine && total_it < opts->maxit) {
+      MFS_TRY(set_active_from_relres());
+      KrylovDev kk = k;
+      kk.bnorm = kk.beta;  // inner estimate relative to the current residual
+      MFS_TRY(cycle(kk, opts->inner_tol, true));
+      ++n_refine;
+      ++n_restart;
+      MFS_TRY(residual());
+      if (opts->verbose)
+        std::fprintf(stderr, "[mfs_solve mixed] refine %d  iters %d  max relres %.3e\n", n_refine, total_it,
+                     max_relres());
+    }
+  }
+  MFS_HIP_TRY(hipStreamSynchronize(st));
+  const auto t1 = std::chrono::steady_clock::now();
+  if (info) {
+    info->n_matvec32 = n32;
+    info->n_matvec64 = n64;
+    info->n_refine = n_refine;
+    info->n_restart = n_restart;
+    info->relres_max = max_relres();
+    info->t_total_s = std::chrono::duration<double>(t1 - t0).count();
+  }
+  if (max_relres() > opts->tol)
+    return fail(MFS_ERR_NOCONV, "solve: relative residual " + std::to_string(max_relres()) + " above tol after " +
+                                    std::to_string(total_it) + " iterations");
+  return MFS_OK;
+}
+
+mfs_status mfs_timing_enable(int32_t on) {
+  timing_clear();
+  g_timing_on = on != 0;
+  return MFS_OK;
+}
+
+mfs_status mfs_timing_read(mfs_kernel_kind kind, double* total_ms, int64_t* launches, double* pairs) {
+  double ms = 0.0, pr = 0.0;
+  int64_t n = 0;
+  for (auto& r : g_timing) {
+    if (r.kind != (int)kind) continue;
+    MFS_HIP_TRY(hipEventSynchronize(r.e1));
+    float t = 0.0f;
+    MFS_HIP_TRY(hipEventElapsedTime(&t, r.e0, r.e1));
+    ms += t;
+    pr += r.pairs;
+    ++n;
+  }
+  if (total_ms) *total_ms = ms;
+  if (launches) *launches = n;
+  if (pairs) *pairs = pr;
+  return MFS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,137 @@
+// Internal declarations shared by the translation units of libmfs.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mfs.h"
+
+namespace mfs {
+
+// ------------------------------------------------------------------ errors ---
+void set_error(const std::string& msg);
+mfs_status fail(mfs_status code, const std::string& msg);
+
+#define MFS_HIP_TRY(expr)                                                                   \
+  do {                                                                                      \
+    hipError_t e__ = (expr);                                                                \
+    if (e__ != hipSuccess)                                                                  \
+      return ::mfs::fail(MFS_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e__)); \
+  } while (0)
+
+// --------------------------------------------------------------- complex ----
+template <typename T>
+struct Cplx {
+  T re, im;
+};
+using c64 = Cplx<float>;
+using c128 = Cplx<double>;
+
+// ------------------------------------------------------------- scene view ---
+// Device-side description of the packed scene, passed by value to kernels.
+struct SceneDev {
+  int32_t dim;
+  int64_t N;
+  int64_t T;
+  double kappa;
+  double origin[3];       // FP32 coordinates are relative to this point
+  const double* x64[3];   // absolute FP64 coordinates, SoA
+  const float* x32[3];    // FP32 coordinates relative to origin, SoA
+  const int32_t* body_of; // [N]
+  const int64_t* body_ptr;// [T+1]
+  const int32_t* shape_of;// [T]
+  const int64_t* k_of_shape;      // [n_shapes]
+  const void* const* S64;         // [n_shapes] device pointers (complex128, col-major)
+  const void* const* S32;         // [n_shapes] device pointers (complex64) or null
+  double offbody_pairs;           // N^2 - sum_tau k_tau^2
+};
+
+// ------------------------------------------------------- kernel launchers ---
+// Pair sums (pair_kernels.hip).  Targets are either the scene's own points (G_hat, with
+// same-body exclusion) or arbitrary FP64 targets (field evaluation, no exclusion).  Results
+// are per-source-chunk partial sums, partial[c][r][M], which the consumer adds in chunk order.
+int pair_chunks_for(int64_t n_sources, int64_t n_targets, int tpt);
+
+hipError_t launch_ghat_f32(const SceneDev& s, const c64* q, int R, c64* partial, int nchunks,
+                           hipStream_t st);
+hipError_t launch_ghat_f64(const SceneDev& s, const c128* q, int R, c128* partial, int nchunks,
+                           hipStream_t st);
+hipError_t launch_eval_f32(const SceneDev& s, const c64* q, int R, const double* targets, int64_t M,
+                           c64* partial, int nchunks, hipStream_t st);
+hipError_t launch_eval_f64(const SceneDev& s, const c128* q, int R, const double* targets, int64_t M,
+                           c128* partial, int nchunks, hipStream_t st);
+
+// Sum partial[c][r][M] over c into out[r][M] (field evaluation, plain G_hat output).
+hipError_t launch_reduce_partials_f32(const c64* partial, int nchunks, int64_t M, int R, c64* out,
+                                      hipStream_t st);
+hipError_t launch_reduce_partials_f64(const c128* partial, int nchunks, int64_t M, int R, c128* out,
+                                      hipStream_t st);
+
+// Block-diagonal S (sapply.hip): y = beta q + S t, t = sum over chunks of partial.
+// TQ is the type of q and y; the S factors and partials are in the operator precision.
+hipError_t launch_sapply_f64(const SceneDev& s, const c128* partial, int nchunks, const c128* q, double beta,
+                             c128* y, int R, int kmax, hipStream_t st);
+hipError_t launch_sapply_f32(const SceneDev& s, const c64* partial, int nchunks, const c64* q, float beta,
+                             c64* y, int R, int kmax, hipStream_t st);
+hipError_t launch_sapply_mixed(const SceneDev& s, const c64* partial, int nchunks, const c128* q, double beta,
+                               c128* y, int R, int kmax, hipStream_t st);
+
+// Elementwise helpers (sapply.hip).
+hipError_t launch_to_c64(const c128* in, c64* out, int64_t n, hipStream_t st);
+hipError_t launch_plane_wave(const SceneDev& s, const double* dirs_dev, int R, c128* vhat, hipStream_t st);
+hipError_t launch_pack_scene(int dim, int64_t T, const int32_t* shape_of, const double* centres,
+                             const int64_t* tmpl_ptr, const double* tmpl_pts, const int64_t* body_ptr,
+                             const double* origin, double* x64_soa, float* x32_soa, int32_t* body_of,
+                             int64_t N, hipStream_t st);
+
+// Krylov kernels (krylov.hip).  One Arnoldi/GMRES state per right-hand side; vectors [R][N].
+struct KrylovDev {
+  int64_t N;
+  int R;
+  int m;              // restart length
+  c128* V;            // [(m+1)][R][N]
+  c128* H;            // [R][m][m+1]: column j of rhs r at H + (r*m + j)*(m+1)
+  c128* cs;           // [R][m]
+  c128* sn;           // [R][m]
+  c128* g;            // [R][m+1]
+  c128* hcol;         // [R][m+1] first Gram-Schmidt coefficients
+  c128* h2;           // [R][m+1] second-pass coefficients
+  c128* y;            // [R][m]   least-squares coefficients
+  double* beta;       // [R] norms of the cycle's starting residuals
+  double* bnorm;      // [R] norms the relative estimate refers to
+  double* res;        // [R] |g_{j+1}| / bnorm
+  double* hnorm;      // [R] ||w|| of the current step
+  int32_t* active;    // [R] 1 while the column iterates in this cycle
+  int32_t* jlen;      // [R] Arnoldi steps taken by the column in this cycle
+  double* part;       // [R][m+1][nblk][2] partial sums
+  int nblk;
+};
+
+int krylov_nblk(int64_t N);
+hipError_t launch_norms(const c128* v, int64_t N, int R, double* part, int nblk, double* out_norm,
+                        hipStream_t st);
+hipError_t launch_start_cycle(KrylovDev k, const c128* r0, hipStream_t st);
+hipError_t launch_arnoldi_orth(KrylovDev k, int j, c128* w, hipStream_t st);
+hipError_t launch_arnoldi_finish(KrylovDev k, int j, c128* w, double tol, hipStream_t st);
+hipError_t launch_gmres_update_x(KrylovDev k, c128* x, hipStream_t st);
+hipError_t launch_axpby(const c128* a, const c128* b, c128* out, double alpha, double beta, int64_t n,
+                        hipStream_t st);
+
+// Kernel timing (mfs_api.hip): bracket a launch with events when recording is on.
+struct TimedLaunch {
+  TimedLaunch(int kind, double pairs, hipStream_t st);
+  ~TimedLaunch();
+  int kind;
+  double pairs;
+  hipStream_t st;
+  void* ev0;
+  void* ev1;
+};
+
+// Least squares for S (lsq.hip).
+mfs_status build_S_impl(const mfs_shape_desc* d, void* S64, void* S32, int64_t* k_out, int64_t* skel,
+                        double* diag, hipStream_t st);
+
+}  // namespace mfs

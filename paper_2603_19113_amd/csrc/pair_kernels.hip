@@ -1,0 +1,337 @@
+// Pair sums t_i = sum_j phi_kappa(x_i - xhat_j) q_j on gfx950 (eq. Gmtx-entries, eq. out_skel).
+//
+// Layout and mapping
+//   * One wave (64 lanes) owns 64*TPT consecutive targets; lane l holds targets base + 64*i + l.
+//     Consecutive targets belong to one body (bodies are packed contiguously), so a wave's
+//     targets span only one or two bodies.
+//   * Sources are streamed in index order.  Every lane needs the same source at the same time,
+//     so source coordinates, charges and body ids are read with wave-uniform addresses: the
+//     compiler turns them into scalar (SGPR) loads and no LDS staging is needed.
+//   * The source range is split into nchunks chunks (grid.y) to give the chip enough waves;
+//     each chunk writes its own partial sum partial[c][r][M], and the consumer adds the chunks
+//     in a fixed order, so the result is deterministic (no atomics).
+//   * Same-body exclusion (G_hat has zero diagonal blocks, eq. mbody2): a wave computes the range
+//     [body_ptr[bmin], body_ptr[bmax+1]) of sources that share a body with any of its targets;
+//     only that range is evaluated with a per-pair body-id test, the rest runs unmasked.
+//   * grid.z tiles the right-hand sides, RT per block; phi is computed once per pair and applied
+//     to the RT charges.
+#include "mfs_internal.h"
+#include "phi.h"
+
+namespace mfs {
+namespace {
+
+constexpr int kWaves = 4;  // waves per block
+constexpr int kBlock = 64 * kWaves;
+constexpr int kUnroll = 8;
+
+template <typename T, int DIM>
+struct PhiEval;
+
+template <>
+struct PhiEval<float, 2> {
+  Phi2DConstsF32 c;
+  __device__ __forceinline__ void operator()(float r2, float& pr, float& pi) const { phi2d_f32(r2, c, pr, pi); }
+};
+template <>
+struct PhiEval<float, 3> {
+  Phi3DConstsF32 c;
+  __device__ __forceinline__ void operator()(float r2, float& pr, float& pi) const { phi3d_f32(r2, c, pr, pi); }
+};
+template <>
+struct PhiEval<double, 2> {
+  double kappa;
+  __device__ __forceinline__ void operator()(double r2, double& pr, double& pi) const {
+    phi2d_f64(sqrt(r2), kappa, pr, pi);
+  }
+};
+template <>
+struct PhiEval<double, 3> {
+  double kappa;
+  __device__ __forceinline__ void operator()(double r2, double& pr, double& pi) const {
+    phi3d_f64(sqrt(r2), kappa, pr, pi);
+  }
+};
+
+__device__ __forceinline__ int wave_min_i32(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+  return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ __forceinline__ int wave_max_i32(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+template <typename T, int DIM, int TPT, int RT>
+struct Acc {
+  T tx[TPT][DIM];
+  int tb[TPT];
+  T ar[TPT][RT];
+  T ai[TPT][RT];
+};
+
+// One source j against all targets of the lane.
+template <typename T, int DIM, int TPT, int RT, bool MASK>
+__device__ __forceinline__ void accumulate_source(Acc<T, DIM, TPT, RT>& a, const PhiEval<T, DIM>& phi,
+                                                  const T* __restrict__ s0, const T* __restrict__ s1,
+                                                  const T* __restrict__ s2, const int32_t* __restrict__ sbody,
+                                                  const Cplx<T>* __restrict__ q, int64_t N, int R, int r0,
+                                                  int64_t j) {
+  const T sx = s0[j];
+  const T sy = s1[j];
+  T sz = T(0);
+  if constexpr (DIM == 3) sz = s2[j];
+  T qr[RT], qi[RT];
+#pragma unroll
+  for (int rr = 0; rr < RT; ++rr) {
+    const int r = (r0 + rr < R) ? r0 + rr : R - 1;  // clamp keeps the load in bounds
+    const Cplx<T> qq = q[(int64_t)r * N + j];
+    qr[rr] = qq.re;
+    qi[rr] = qq.im;
+  }
+  int sb = 0;
+  if constexpr (MASK) sb = sbody[j];
+#pragma unroll
+  for (int i = 0; i < TPT; ++i) {
+    const T dx = a.tx[i][0] - sx;
+    const T dy = a.tx[i][1] - sy;
+    T r2 = dx * dx + dy * dy;
+    if constexpr (DIM == 3) {
+      const T dz = a.tx[i][2] - sz;
+      r2 = r2 + dz * dz;
+    }
+    T pr, pi;
+    phi(r2, pr, pi);
+    if constexpr (MASK) {
+      const bool same = (a.tb[i] == sb);
+      pr = same ? T(0) : pr;
+      pi = same ? T(0) : pi;
+    }
+#pragma unroll
+    for (int rr = 0; rr < RT; ++rr) {
+      a.ar[i][rr] = fma(pr, qr[rr], fma(-pi, qi[rr], a.ar[i][rr]));
+      a.ai[i][rr] = fma(pr, qi[rr], fma(pi, qr[rr], a.ai[i][rr]));
+    }
+  }
+}
+
+template <typename T, int DIM, int TPT, int RT, bool MASK>
+__device__ __forceinline__ void run_range(Acc<T, DIM, TPT, RT>& a, const PhiEval<T, DIM>& phi,
+                                          const T* __restrict__ s0, const T* __restrict__ s1,
+                                          const T* __restrict__ s2, const int32_t* __restrict__ sbody,
+                                          const Cplx<T>* __restrict__ q, int64_t N, int R, int r0, int64_t lo,
+                                          int64_t hi) {
+  int64_t j = lo;
+  for (; j + kUnroll <= hi; j += kUnroll) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      accumulate_source<T, DIM, TPT, RT, MASK>(a, phi, s0, s1, s2, sbody, q, N, R, r0, j + u);
+  }
+  for (; j < hi; ++j) accumulate_source<T, DIM, TPT, RT, MASK>(a, phi, s0, s1, s2, sbody, q, N, R, r0, j);
+}
+
+// EXT: targets are external FP64 points (field evaluation, no exclusion); otherwise the targets
+// are the scene's own points and same-body pairs are excluded.
+template <typename T, int DIM, int TPT, int RT, bool EXT>
+__global__ __launch_bounds__(kBlock) void pair_sum_kernel(
+    PhiEval<T, DIM> phi, const T* __restrict__ s0, const T* __restrict__ s1, const T* __restrict__ s2,
+    const int32_t* __restrict__ sbody, const int64_t* __restrict__ body_ptr, const Cplx<T>* __restrict__ q,
+    int64_t N, int R, const double* __restrict__ targets, double ox, double oy, double oz, int64_t M,
+    int64_t chunk_len, Cplx<T>* __restrict__ partial) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t base = ((int64_t)blockIdx.x * kWaves + wave) * (64 * TPT);
+  if (base >= M) return;  // whole wave idle (uniform)
+  const int r0 = blockIdx.z * RT;
+  const int64_t c0 = (int64_t)blockIdx.y * chunk_len;
+  const int64_t c1 = min(N, c0 + chunk_len);
+
+  Acc<T, DIM, TPT, RT> a;
+  int bmin = 0x7fffffff, bmax = -1;
+#pragma unroll
+  for (int i = 0; i < TPT; ++i) {
+    const int64_t t = base + 64 * i + lane;
+    const bool ok = t < M;
+    const int64_t tc = ok ? t : M - 1;
+    if constexpr (EXT) {
+      // FP32 sources are relative to the scene origin; FP64 sources are absolute (ox = oy = oz = 0)
+      a.tx[i][0] = (T)(targets[tc * DIM + 0] - ox);
+      a.tx[i][1] = (T)(targets[tc * DIM + 1] - oy);
+      if constexpr (DIM == 3) a.tx[i][2] = (T)(targets[tc * DIM + 2] - oz);
+      a.tb[i] = -1;
+    } else {
+      a.tx[i][0] = s0[tc];
+      a.tx[i][1] = s1[tc];
+      if constexpr (DIM == 3) a.tx[i][2] = s2[tc];
+      a.tb[i] = ok ? sbody[tc] : -1;
+      if (ok) {
+        bmin = min(bmin, a.tb[i]);
+        bmax = max(bmax, a.tb[i]);
+      }
+    }
+#pragma unroll
+    for (int rr = 0; rr < RT; ++rr) a.ar[i][rr] = a.ai[i][rr] = T(0);
+  }
+
+  if constexpr (EXT) {
+    run_range<T, DIM, TPT, RT, false>(a, phi, s0, s1, s2, sbody, q, N, R, r0, c0, c1);
+  } else {
+    bmin = wave_min_i32(bmin);
+    bmax = wave_max_i32(bmax);
+    const int64_t s_lo = body_ptr[bmin];
+    const int64_t s_hi = body_ptr[bmax + 1];
+    run_range<T, DIM, TPT, RT, false>(a, phi, s0, s1, s2, sbody, q, N, R, r0, c0, min(c1, s_lo));
+    run_range<T, DIM, TPT, RT, true>(a, phi, s0, s1, s2, sbody, q, N, R, r0, max(c0, s_lo), min(c1, s_hi));
+    run_range<T, DIM, TPT, RT, false>(a, phi, s0, s1, s2, sbody, q, N, R, r0, max(c0, s_hi), c1);
+  }
+
+#pragma unroll
+  for (int i = 0; i < TPT; ++i) {
+    const int64_t t = base + 64 * i + lane;
+    if (t >= M) continue;
+#pragma unroll
+    for (int rr = 0; rr < RT; ++rr) {
+      const int r = r0 + rr;
+      if (r >= R) continue;
+      Cplx<T> v;
+      v.re = a.ar[i][rr];
+      v.im = a.ai[i][rr];
+      partial[((int64_t)blockIdx.y * R + r) * M + t] = v;
+    }
+  }
+}
+
+Phi2DConstsF32 make_phi2d_f32(double kappa) {
+  Phi2DConstsF32 c;
+  c.kappa = (float)kappa;
+  c.kappa_rev = (float)(kappa / (2.0 * M_PI));
+  c.three_over_kappa = (float)(3.0 / kappa);
+  c.amp = (float)(0.25 / std::sqrt(kappa));
+  c.kappa2_9 = (float)(kappa * kappa / 9.0);
+  c.log_half_kappa = (float)std::log(0.5 * kappa);
+  return c;
+}
+
+template <typename T, int DIM, int TPT, int RT, bool EXT>
+hipError_t launch_pair(const PhiEval<T, DIM>& phi, const T* s0, const T* s1, const T* s2, const int32_t* sbody,
+                       const int64_t* body_ptr, const Cplx<T>* q, int64_t N, int R, const double* targets,
+                       const double* origin, int64_t M, Cplx<T>* partial, int nchunks, hipStream_t st) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  int64_t chunk_len = (N + nchunks - 1) / nchunks;
+  chunk_len = (chunk_len + kUnroll - 1) / kUnroll * kUnroll;
+  const int64_t per_block = (int64_t)kBlock * TPT;
+  dim3 grid((unsigned)((M + per_block - 1) / per_block), (unsigned)nchunks, (unsigned)((R + RT - 1) / RT));
+  hipLaunchKernelGGL((pair_sum_kernel<T, DIM, TPT, RT, EXT>), grid, dim3(kBlock), 0, st, phi, s0, s1, s2,
+                     sbody, body_ptr, q, N, R, targets, origin[0], origin[1], origin[2], M, chunk_len,
+                     partial);
+  return hipGetLastError();
+}
+
+template <typename T, int DIM, int TPT, bool EXT>
+hipError_t dispatch_rt(const PhiEval<T, DIM>& phi, const T* s0, const T* s1, const T* s2, const int32_t* sbody,
+                       const int64_t* body_ptr, const Cplx<T>* q, int64_t N, int R, const double* targets,
+                       const double* origin, int64_t M, Cplx<T>* partial, int nchunks, hipStream_t st) {
+  if (R == 1)
+    return launch_pair<T, DIM, TPT, 1, EXT>(phi, s0, s1, s2, sbody, body_ptr, q, N, R, targets, origin, M,
+                                            partial, nchunks, st);
+  if (R == 2)
+    return launch_pair<T, DIM, TPT, 2, EXT>(phi, s0, s1, s2, sbody, body_ptr, q, N, R, targets, origin, M,
+                                            partial, nchunks, st);
+  return launch_pair<T, DIM, TPT, 4, EXT>(phi, s0, s1, s2, sbody, body_ptr, q, N, R, targets, origin, M,
+                                          partial, nchunks, st);
+}
+
+}  // namespace
+
+int pair_chunks_for(int64_t n_sources, int64_t n_targets, int tpt) {
+  // aim for ~16 waves per SIMD (256 CUs x 4 SIMDs) while keeping chunks >= 256 sources
+  const int64_t waves = (n_targets + 64 * tpt - 1) / (64 * tpt);
+  int64_t want = (16384 + waves - 1) / std::max<int64_t>(waves, 1);
+  want = std::min<int64_t>(want, std::max<int64_t>(1, n_sources / 256));
+  want = std::max<int64_t>(1, std::min<int64_t>(want, 64));
+  return (int)want;
+}
+
+static const double kZero3[3] = {0.0, 0.0, 0.0};
+
+hipError_t launch_ghat_f32(const SceneDev& s, const c64* q, int R, c64* partial, int nchunks, hipStream_t st) {
+  if (s.dim == 2) {
+    PhiEval<float, 2> phi{make_phi2d_f32(s.kappa)};
+    return dispatch_rt<float, 2, 2, false>(phi, s.x32[0], s.x32[1], nullptr, s.body_of, s.body_ptr, q, s.N, R,
+                                           nullptr, kZero3, s.N, partial, nchunks, st);
+  }
+  PhiEval<float, 3> phi{Phi3DConstsF32{(float)(s.kappa / (2.0 * M_PI))}};
+  return dispatch_rt<float, 3, 2, false>(phi, s.x32[0], s.x32[1], s.x32[2], s.body_of, s.body_ptr, q, s.N, R,
+                                         nullptr, kZero3, s.N, partial, nchunks, st);
+}
+
+hipError_t launch_ghat_f64(const SceneDev& s, const c128* q, int R, c128* partial, int nchunks, hipStream_t st) {
+  if (s.dim == 2) {
+    PhiEval<double, 2> phi{s.kappa};
+    return dispatch_rt<double, 2, 1, false>(phi, s.x64[0], s.x64[1], nullptr, s.body_of, s.body_ptr, q, s.N, R,
+                                            nullptr, kZero3, s.N, partial, nchunks, st);
+  }
+  PhiEval<double, 3> phi{s.kappa};
+  return dispatch_rt<double, 3, 1, false>(phi, s.x64[0], s.x64[1], s.x64[2], s.body_of, s.body_ptr, q, s.N, R,
+                                          nullptr, kZero3, s.N, partial, nchunks, st);
+}
+
+hipError_t launch_eval_f32(const SceneDev& s, const c64* q, int R, const double* targets, int64_t M, c64* partial,
+                           int nchunks, hipStream_t st) {
+  if (s.dim == 2) {
+    PhiEval<float, 2> phi{make_phi2d_f32(s.kappa)};
+    return dispatch_rt<float, 2, 2, true>(phi, s.x32[0], s.x32[1], nullptr, s.body_of, s.body_ptr, q, s.N, R,
+                                          targets, s.origin, M, partial, nchunks, st);
+  }
+  PhiEval<float, 3> phi{Phi3DConstsF32{(float)(s.kappa / (2.0 * M_PI))}};
+  return dispatch_rt<float, 3, 2, true>(phi, s.x32[0], s.x32[1], s.x32[2], s.body_of, s.body_ptr, q, s.N, R,
+                                        targets, s.origin, M, partial, nchunks, st);
+}
+
+hipError_t launch_eval_f64(const SceneDev& s, const c128* q, int R, const double* targets, int64_t M,
+                           c128* partial, int nchunks, hipStream_t st) {
+  if (s.dim == 2) {
+    PhiEval<double, 2> phi{s.kappa};
+    return dispatch_rt<double, 2, 1, true>(phi, s.x64[0], s.x64[1], nullptr, s.body_of, s.body_ptr, q, s.N, R,
+                                           targets, kZero3, M, partial, nchunks, st);
+  }
+  PhiEval<double, 3> phi{s.kappa};
+  return dispatch_rt<double, 3, 1, true>(phi, s.x64[0], s.x64[1], s.x64[2], s.body_of, s.body_ptr, q, s.N, R,
+                                         targets, kZero3, M, partial, nchunks, st);
+}
+
+// ----------------------------------------------------------- chunk reduce ---
+template <typename T>
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const Cplx<T>* __restrict__ partial, int nchunks,
+                                                              int64_t MR, Cplx<T>* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= MR) return;
+  T re = 0, im = 0;
+  for (int c = 0; c < nchunks; ++c) {
+    const Cplx<T> v = partial[(int64_t)c * MR + i];
+    re += v.re;
+    im += v.im;
+  }
+  out[i] = Cplx<T>{re, im};
+}
+
+hipError_t launch_reduce_partials_f32(const c64* partial, int nchunks, int64_t M, int R, c64* out, hipStream_t st) {
+  const int64_t MR = M * R;
+  if (MR == 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_partials_kernel<float>, dim3((unsigned)((MR + 255) / 256)), dim3(256), 0, st, partial,
+                     nchunks, MR, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials_f64(const c128* partial, int nchunks, int64_t M, int R, c128* out,
+                                      hipStream_t st) {
+  const int64_t MR = M * R;
+  if (MR == 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_partials_kernel<double>, dim3((unsigned)((MR + 255) / 256)), dim3(256), 0, st, partial,
+                     nchunks, MR, out);
+  return hipGetLastError();
+}
+
+}  // namespace mfs

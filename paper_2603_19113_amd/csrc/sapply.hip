@@ -1,0 +1,159 @@
+// Block-diagonal scattering-matrix products and elementwise helpers.
+//
+// y_tau = beta q_tau + S_shape(tau) t_tau for every body tau (eq. mbody1): one block per
+// (body, right-hand side).  The block first sums the pair kernel's per-chunk partials for the
+// body's k entries into LDS (fixed chunk order), then each thread forms rows of S t with S read
+// column by column (column-major, so a column is one coalesced read across the block) and t
+// broadcast from LDS.  Bodies of one shape share S, which stays resident in L2.
+#include "mfs_internal.h"
+
+namespace mfs {
+namespace {
+
+template <typename TQ, typename TS>
+__global__ __launch_bounds__(256) void sapply_kernel(const int64_t* __restrict__ body_ptr,
+                                                     const int32_t* __restrict__ shape_of,
+                                                     const void* const* __restrict__ S_of_shape,
+                                                     const Cplx<TS>* __restrict__ partial, int nchunks,
+                                                     const Cplx<TQ>* __restrict__ q, TQ beta,
+                                                     Cplx<TQ>* __restrict__ y, int64_t N, int R) {
+  extern __shared__ unsigned char smem_raw[];
+  Cplx<TS>* t = reinterpret_cast<Cplx<TS>*>(smem_raw);
+  const int64_t body = blockIdx.x;
+  const int r = blockIdx.y;
+  const int64_t start = body_ptr[body];
+  const int k = (int)(body_ptr[body + 1] - start);
+  const Cplx<TS>* __restrict__ S = static_cast<const Cplx<TS>*>(S_of_shape[shape_of[body]]);
+  const int64_t NR = N * R;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    const int64_t idx = (int64_t)r * N + start + j;
+    TS re = 0, im = 0;
+    for (int c = 0; c < nchunks; ++c) {
+      const Cplx<TS> v = partial[(int64_t)c * NR + idx];
+      re += v.re;
+      im += v.im;
+    }
+    t[j] = Cplx<TS>{re, im};
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    TS ar = 0, ai = 0;
+    const Cplx<TS>* col = S + i;
+    for (int j = 0; j < k; ++j) {
+      const Cplx<TS> s = col[(int64_t)j * k];
+      const Cplx<TS> tj = t[j];
+      ar = fma(s.re, tj.re, fma(-s.im, tj.im, ar));
+      ai = fma(s.re, tj.im, fma(s.im, tj.re, ai));
+    }
+    const int64_t idx = (int64_t)r * N + start + i;
+    Cplx<TQ> out;
+    if (beta != TQ(0)) {
+      const Cplx<TQ> qq = q[idx];
+      out.re = beta * qq.re + (TQ)ar;
+      out.im = beta * qq.im + (TQ)ai;
+    } else {
+      out.re = (TQ)ar;
+      out.im = (TQ)ai;
+    }
+    y[idx] = out;
+  }
+}
+
+template <typename TQ, typename TS>
+hipError_t launch_sapply(const SceneDev& s, const void* const* S_tab, const Cplx<TS>* partial, int nchunks,
+                         const Cplx<TQ>* q, TQ beta, Cplx<TQ>* y, int R, int kmax, hipStream_t st) {
+  if (s.T == 0 || R == 0) return hipSuccess;
+  int threads = ((kmax + 63) / 64) * 64;
+  threads = threads < 64 ? 64 : (threads > 256 ? 256 : threads);
+  const size_t shmem = sizeof(Cplx<TS>) * (size_t)kmax;
+  hipLaunchKernelGGL((sapply_kernel<TQ, TS>), dim3((unsigned)s.T, (unsigned)R), dim3(threads), shmem, st,
+                     s.body_ptr, s.shape_of, S_tab, partial, nchunks, q, beta, y, s.N, R);
+  return hipGetLastError();
+}
+
+__global__ void to_c64_kernel(const c128* __restrict__ in, c64* __restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = c64{(float)in[i].re, (float)in[i].im};
+}
+
+__global__ void plane_wave_kernel(int dim, double kappa, const double* __restrict__ x0, const double* __restrict__ x1,
+                                  const double* __restrict__ x2, const double* __restrict__ dirs, int64_t N, int R,
+                                  c128* __restrict__ v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (i >= N) return;
+  double ph = dirs[r * dim + 0] * x0[i] + dirs[r * dim + 1] * x1[i];
+  if (dim == 3) ph += dirs[r * dim + 2] * x2[i];
+  double s, c;
+  sincos(kappa * ph, &s, &c);
+  v[(int64_t)r * N + i] = c128{-c, -s};  // v = -u_inc = -exp(i kappa d.x)
+}
+
+__global__ void pack_scene_kernel(int dim, int64_t T, const int32_t* __restrict__ shape_of,
+                                  const double* __restrict__ centres, const int64_t* __restrict__ tmpl_ptr,
+                                  const double* __restrict__ tmpl_pts, const int64_t* __restrict__ body_ptr,
+                                  double ox, double oy, double oz, double* __restrict__ x64,
+                                  float* __restrict__ x32, int32_t* __restrict__ body_of, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  // body containing point i: largest tau with body_ptr[tau] <= i
+  int64_t lo = 0, hi = T - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (body_ptr[mid] <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  const int64_t tau = lo;
+  const int64_t l = i - body_ptr[tau];
+  const int s = shape_of[tau];
+  const double* p = tmpl_pts + (tmpl_ptr[s] + l) * dim;
+  const double o[3] = {ox, oy, oz};
+  for (int d = 0; d < dim; ++d) {
+    const double v = p[d] + centres[tau * dim + d];
+    x64[d * N + i] = v;
+    x32[d * N + i] = (float)(v - o[d]);
+  }
+  body_of[i] = (int32_t)tau;
+}
+
+}  // namespace
+
+hipError_t launch_sapply_f64(const SceneDev& s, const c128* partial, int nchunks, const c128* q, double beta,
+                             c128* y, int R, int kmax, hipStream_t st) {
+  return launch_sapply<double, double>(s, s.S64, partial, nchunks, q, beta, y, R, kmax, st);
+}
+
+hipError_t launch_sapply_f32(const SceneDev& s, const c64* partial, int nchunks, const c64* q, float beta, c64* y,
+                             int R, int kmax, hipStream_t st) {
+  return launch_sapply<float, float>(s, s.S32, partial, nchunks, q, beta, y, R, kmax, st);
+}
+
+hipError_t launch_sapply_mixed(const SceneDev& s, const c64* partial, int nchunks, const c128* q, double beta,
+                               c128* y, int R, int kmax, hipStream_t st) {
+  return launch_sapply<double, float>(s, s.S32, partial, nchunks, q, beta, y, R, kmax, st);
+}
+
+hipError_t launch_to_c64(const c128* in, c64* out, int64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(to_c64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_plane_wave(const SceneDev& s, const double* dirs_dev, int R, c128* vhat, hipStream_t st) {
+  if (s.N == 0 || R == 0) return hipSuccess;
+  hipLaunchKernelGGL(plane_wave_kernel, dim3((unsigned)((s.N + 255) / 256), (unsigned)R), dim3(256), 0, st, s.dim,
+                     s.kappa, s.x64[0], s.x64[1], s.x64[2], dirs_dev, s.N, R, vhat);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_scene(int dim, int64_t T, const int32_t* shape_of, const double* centres,
+                             const int64_t* tmpl_ptr, const double* tmpl_pts, const int64_t* body_ptr,
+                             const double* origin, double* x64_soa, float* x32_soa, int32_t* body_of, int64_t N,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(pack_scene_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, dim, T, shape_of,
+                     centres, tmpl_ptr, tmpl_pts, body_ptr, origin[0], origin[1], origin[2], x64_soa, x32_soa,
+                     body_of, N);
+  return hipGetLastError();
+}
+
+}  // namespace mfs

@@ -33,5 +33,7 @@ from .configs import (  # noqa: F401
     c2_starfish2000,
     c3_spheres1000,
     c4_mixed_multi_incidence,
+    c4_shapes,
+    CONFIGS,
     make_scene,
 )
