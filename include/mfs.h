@@ -178,9 +178,11 @@ mfs_status mfs_apply(const mfs_scene* scene, const void* q_dev, void* y_dev, int
 typedef struct {
   double tol;        /* relative residual target, e.g. 1e-8 */
   int32_t maxit;     /* total inner iterations (operator applications) allowed */
-  int32_t restart;   /* Krylov basis size before a restart (1..4096) */
+  int32_t restart;   /* Krylov basis size before a restart (1..32768); the basis takes
+                        (restart+1) * R * N * 16 bytes of device memory */
   int32_t max_refine;/* MFS_MIXED: outer refinement steps allowed */
-  double inner_tol;  /* MFS_MIXED: relative residual reduction asked of each inner solve */
+  double inner_tol;  /* MFS_MIXED: smallest relative residual reduction asked of an inner solve; the
+                        last steps ask only for the reduction the outer tolerance still needs */
   mfs_prec prec;     /* MFS_FP64 or MFS_MIXED */
   int32_t verbose;   /* >0: print one line per restart/refinement to stderr */
 } mfs_solve_opts;

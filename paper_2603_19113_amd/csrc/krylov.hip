@@ -13,7 +13,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kElems = 4;   // vector elements per thread in the dot kernels
-constexpr int kGroup = 8;   // basis vectors reduced together
+constexpr int kGroup = 16;  // basis vectors per dot-product block
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -21,12 +21,15 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// partial[r][i][blk] = sum over the block's elements of conj(V_i[r][n]) w[r][n], i = 0..j.
+// part[r][i][blk] = sum over the block's elements of conj(V_i[r][n]) w[r][n].
+// grid = (vector chunks, groups of kGroup basis vectors, right-hand sides): each block keeps its
+// chunk of w in registers and reads kGroup basis-vector chunks once.
 __global__ __launch_bounds__(kThreads) void dots_kernel(const c128* __restrict__ V, const c128* __restrict__ w,
                                                         int64_t N, int R, int jcount, int nblk,
                                                         double* __restrict__ part) {
   __shared__ double red[kThreads / 64][kGroup][2];
-  const int r = blockIdx.y;
+  const int r = blockIdx.z;
+  const int i0 = blockIdx.y * kGroup;
   const int64_t base = (int64_t)blockIdx.x * (kThreads * kElems);
   c128 wl[kElems];
 #pragma unroll
@@ -35,46 +38,46 @@ __global__ __launch_bounds__(kThreads) void dots_kernel(const c128* __restrict__
     wl[e] = n < N ? w[(int64_t)r * N + n] : c128{0.0, 0.0};
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int i0 = 0; i0 < jcount; i0 += kGroup) {
-    double sr[kGroup], si[kGroup];
+  double sr[kGroup], si[kGroup];
 #pragma unroll
-    for (int g = 0; g < kGroup; ++g) {
-      sr[g] = 0.0;
-      si[g] = 0.0;
-      const int i = i0 + g;
-      if (i < jcount) {
-        const c128* Vi = V + ((int64_t)i * R + r) * N;
+  for (int g = 0; g < kGroup; ++g) {
+    sr[g] = 0.0;
+    si[g] = 0.0;
+    const int i = i0 + g;
+    if (i < jcount) {
+      const c128* Vi = V + ((int64_t)i * R + r) * N;
 #pragma unroll
-        for (int e = 0; e < kElems; ++e) {
-          const int64_t n = base + e * kThreads + threadIdx.x;
-          if (n < N) {
-            const c128 v = Vi[n];
-            sr[g] = fma(v.re, wl[e].re, fma(v.im, wl[e].im, sr[g]));   // conj(v) * w
-            si[g] = fma(v.re, wl[e].im, fma(-v.im, wl[e].re, si[g]));
-          }
+      for (int e = 0; e < kElems; ++e) {
+        const int64_t n = base + e * kThreads + threadIdx.x;
+        if (n < N) {
+          const c128 v = Vi[n];
+          sr[g] = fma(v.re, wl[e].re, fma(v.im, wl[e].im, sr[g]));   // conj(v) * w
+          si[g] = fma(v.re, wl[e].im, fma(-v.im, wl[e].re, si[g]));
         }
       }
-      sr[g] = wave_sum(sr[g]);
-      si[g] = wave_sum(si[g]);
     }
-    if (lane == 0) {
+  }
 #pragma unroll
-      for (int g = 0; g < kGroup; ++g) {
-        red[wave][g][0] = sr[g];
-        red[wave][g][1] = si[g];
-      }
+  for (int g = 0; g < kGroup; ++g) {
+    sr[g] = wave_sum(sr[g]);
+    si[g] = wave_sum(si[g]);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int g = 0; g < kGroup; ++g) {
+      red[wave][g][0] = sr[g];
+      red[wave][g][1] = si[g];
     }
-    __syncthreads();
-    if (threadIdx.x < kGroup * 2) {
-      const int g = threadIdx.x >> 1, c = threadIdx.x & 1;
-      const int i = i0 + g;
-      if (i < jcount) {
-        double s = 0.0;
-        for (int wv = 0; wv < kThreads / 64; ++wv) s += red[wv][g][c];
-        part[(((int64_t)r * jcount + i) * nblk + blockIdx.x) * 2 + c] = s;
-      }
+  }
+  __syncthreads();
+  if (threadIdx.x < kGroup * 2) {
+    const int g = threadIdx.x >> 1, c = threadIdx.x & 1;
+    const int i = i0 + g;
+    if (i < jcount) {
+      double t = 0.0;
+      for (int wv = 0; wv < kThreads / 64; ++wv) t += red[wv][g][c];
+      part[(((int64_t)r * jcount + i) * nblk + blockIdx.x) * 2 + c] = t;
     }
-    __syncthreads();
   }
 }
 
@@ -107,10 +110,15 @@ __global__ __launch_bounds__(kThreads) void basis_axpy_kernel(const c128* __rest
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
   if (n >= N) return;
+  // h is read with wave-uniform addresses (scalar loads); eight basis loads are kept in flight
   double ar = 0.0, ai = 0.0;
+  const c128* hr = h + (int64_t)r * ld;
+  const c128* Vn = V + (int64_t)r * N + n;
+  const int64_t stride = (int64_t)R * N;
+#pragma unroll 8
   for (int i = 0; i < jcount; ++i) {
-    const c128 hi = h[(int64_t)r * ld + i];
-    const c128 v = V[((int64_t)i * R + r) * N + n];
+    const c128 hi = hr[i];
+    const c128 v = Vn[i * stride];
     ar = fma(hi.re, v.re, fma(-hi.im, v.im, ar));
     ai = fma(hi.re, v.im, fma(hi.im, v.re, ai));
   }
@@ -239,26 +247,36 @@ __global__ void scale_next_kernel(const c128* __restrict__ w, const double* __re
   Vn[(int64_t)r * N + n] = c128{x.re * s, x.im * s};
 }
 
-// y = H(0:len,0:len)^{-1} g(0:len), back substitution; one thread per right-hand side.
-__global__ void hess_solve_kernel(int m, int R, const c128* __restrict__ H, const c128* __restrict__ g,
-                                  const int32_t* __restrict__ jlen, c128* __restrict__ y) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= R) return;
+// y = H(0:len,0:len)^{-1} g(0:len), column-oriented back substitution; one block per right-hand
+// side: y_i = g_i / H_ii, then g_t -= H_ti y_i for t < i in parallel.  g is consumed.
+__global__ __launch_bounds__(1024) void hess_solve_kernel(int m, int R, const c128* __restrict__ H, c128* __restrict__ g,
+                                                          const int32_t* __restrict__ jlen, c128* __restrict__ y) {
+  __shared__ c128 yi_sh;
+  const int r = blockIdx.x;
   const int len = jlen[r];
+  c128* gr = g + (int64_t)r * (m + 1);
   c128* yr = y + (int64_t)r * m;
   for (int i = len - 1; i >= 0; --i) {
-    c128 acc = g[(int64_t)r * (m + 1) + i];
-    for (int c = i + 1; c < len; ++c) {
-      const c128 h = H[((int64_t)r * m + c) * (m + 1) + i];
-      acc.re -= h.re * yr[c].re - h.im * yr[c].im;
-      acc.im -= h.re * yr[c].im + h.im * yr[c].re;
+    const c128* Hc = H + ((int64_t)r * m + i) * (m + 1);
+    if (threadIdx.x == 0) {
+      const c128 d = Hc[i];
+      const double dd = d.re * d.re + d.im * d.im;
+      const c128 acc = gr[i];
+      const c128 v = dd > 0.0 ? c128{(acc.re * d.re + acc.im * d.im) / dd, (acc.im * d.re - acc.re * d.im) / dd}
+                              : c128{0.0, 0.0};
+      yr[i] = v;
+      yi_sh = v;
     }
-    const c128 d = H[((int64_t)r * m + i) * (m + 1) + i];
-    const double dd = d.re * d.re + d.im * d.im;
-    yr[i] = dd > 0.0 ? c128{(acc.re * d.re + acc.im * d.im) / dd, (acc.im * d.re - acc.re * d.im) / dd}
-                     : c128{0.0, 0.0};
+    __syncthreads();
+    const c128 v = yi_sh;
+    for (int t = threadIdx.x; t < i; t += blockDim.x) {
+      const c128 hh = Hc[t];
+      gr[t].re -= hh.re * v.re - hh.im * v.im;
+      gr[t].im -= hh.re * v.im + hh.im * v.re;
+    }
+    __syncthreads();
   }
-  for (int i = len; i < m; ++i) yr[i] = c128{0.0, 0.0};
+  for (int i = len + threadIdx.x; i < m; i += blockDim.x) yr[i] = c128{0.0, 0.0};
 }
 
 // x[r][n] += sum_{i<len_r} y[r][i] V_i[r][n]
@@ -270,6 +288,7 @@ __global__ __launch_bounds__(kThreads) void update_x_kernel(const c128* __restri
   if (n >= N) return;
   const int len = jlen[r];
   double ar = 0.0, ai = 0.0;
+#pragma unroll 8
   for (int i = 0; i < len; ++i) {
     const c128 yi = y[(int64_t)r * m + i];
     const c128 v = V[((int64_t)i * R + r) * N + n];
@@ -316,7 +335,8 @@ hipError_t launch_arnoldi_orth(KrylovDev k, int j, c128* w, hipStream_t st) {
   const int ld = k.m + 1;
   for (int pass = 0; pass < 2; ++pass) {
     c128* h = pass == 0 ? k.hcol : k.h2;
-    hipLaunchKernelGGL(dots_kernel, dim3(k.nblk, k.R), dim3(kThreads), 0, st, k.V, w, k.N, k.R, jc, k.nblk, k.part);
+    hipLaunchKernelGGL(dots_kernel, dim3(k.nblk, (jc + kGroup - 1) / kGroup, k.R), dim3(kThreads), 0, st, k.V, w,
+                       k.N, k.R, jc, k.nblk, k.part);
     hipLaunchKernelGGL(dots_reduce_kernel, dim3(jc, k.R), dim3(64), 0, st, k.part, jc, k.nblk, k.R, ld, h,
                        (const c128*)nullptr);
     hipLaunchKernelGGL(basis_axpy_kernel, dim3(blocks_for(k.N, kThreads), k.R), dim3(kThreads), 0, st, k.V, h, ld,
@@ -338,7 +358,7 @@ hipError_t launch_arnoldi_finish(KrylovDev k, int j, c128* w, double tol, hipStr
 
 // y = H^{-1} g per column, then x += V y.
 hipError_t launch_gmres_update_x(KrylovDev k, c128* x, hipStream_t st) {
-  hipLaunchKernelGGL(hess_solve_kernel, dim3(blocks_for(k.R, 64)), dim3(64), 0, st, k.m, k.R, k.H, k.g, k.jlen, k.y);
+  hipLaunchKernelGGL(hess_solve_kernel, dim3(k.R), dim3(1024), 0, st, k.m, k.R, k.H, k.g, k.jlen, k.y);
   hipLaunchKernelGGL(update_x_kernel, dim3(blocks_for(k.N, kThreads), k.R), dim3(kThreads), 0, st, k.V, k.y, k.jlen,
                      k.m, k.N, k.R, x);
   return hipGetLastError();

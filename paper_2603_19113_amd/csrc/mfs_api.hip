@@ -104,7 +104,7 @@ struct mfs_scene {
   std::vector<int64_t> k_of_shape;
   size_t bytes = 0;
   // owned tables
-  Buf x64, x32, body_of, body_ptr, shape_of, k_dev, S64_tab, S32_tab;
+  Buf x64, x32, l32, centres, body_of, body_ptr, shape_of, k_dev, S64_tab, S32_tab;
   // workspaces
   Buf partial, q32, dirs, kry, vecs;
 };
@@ -248,18 +248,19 @@ mfs_status mfs_scene_create(int32_t dim, double kappa, int64_t T, const int32_t*
     mfs_scene_destroy(sc);
     return st;
   };
-  Buf centres_d, tmpl_d, tmpl_ptr_d;
+  Buf tmpl_d, tmpl_ptr_d;
   size_t tmp_bytes = 0;
   mfs_status st;
   if ((st = ensure(sc->x64, sizeof(double) * dim * N, &sc->bytes)) != MFS_OK) return cleanup(st);
   if ((st = ensure(sc->x32, sizeof(float) * dim * N, &sc->bytes)) != MFS_OK) return cleanup(st);
+  if ((st = ensure(sc->l32, sizeof(float) * dim * N, &sc->bytes)) != MFS_OK) return cleanup(st);
+  if ((st = ensure(sc->centres, sizeof(double) * dim * T, &sc->bytes)) != MFS_OK) return cleanup(st);
   if ((st = ensure(sc->body_of, sizeof(int32_t) * N, &sc->bytes)) != MFS_OK) return cleanup(st);
   if ((st = ensure(sc->body_ptr, sizeof(int64_t) * (T + 1), &sc->bytes)) != MFS_OK) return cleanup(st);
   if ((st = ensure(sc->shape_of, sizeof(int32_t) * T, &sc->bytes)) != MFS_OK) return cleanup(st);
   if ((st = ensure(sc->k_dev, sizeof(int64_t) * n_shapes, &sc->bytes)) != MFS_OK) return cleanup(st);
   if ((st = ensure(sc->S64_tab, sizeof(void*) * n_shapes, &sc->bytes)) != MFS_OK) return cleanup(st);
   if ((st = ensure(sc->S32_tab, sizeof(void*) * n_shapes, &sc->bytes)) != MFS_OK) return cleanup(st);
-  if ((st = ensure(centres_d, sizeof(double) * T * dim, &tmp_bytes)) != MFS_OK) return cleanup(st);
   if ((st = ensure(tmpl_d, sizeof(double) * tmpl.size(), &tmp_bytes)) != MFS_OK) return cleanup(st);
   if ((st = ensure(tmpl_ptr_d, sizeof(int64_t) * tmpl_ptr.size(), &tmp_bytes)) != MFS_OK) return cleanup(st);
 
@@ -275,16 +276,16 @@ mfs_status mfs_scene_create(int32_t dim, double kappa, int64_t T, const int32_t*
   cp(sc->k_dev.p, k_of_shape, sizeof(int64_t) * n_shapes);
   cp(sc->S64_tab.p, S64_dev, sizeof(void*) * n_shapes);
   cp(sc->S32_tab.p, s32v.data(), sizeof(void*) * n_shapes);
-  cp(centres_d.p, centres, sizeof(double) * T * dim);
+  cp(sc->centres.p, centres, sizeof(double) * T * dim);
   cp(tmpl_d.p, tmpl.data(), sizeof(double) * tmpl.size());
   cp(tmpl_ptr_d.p, tmpl_ptr.data(), sizeof(int64_t) * tmpl_ptr.size());
   if (e == hipSuccess)
-    e = launch_pack_scene(dim, T, static_cast<int32_t*>(sc->shape_of.p), static_cast<double*>(centres_d.p),
+    e = launch_pack_scene(dim, T, static_cast<int32_t*>(sc->shape_of.p), static_cast<double*>(sc->centres.p),
                           static_cast<int64_t*>(tmpl_ptr_d.p), static_cast<double*>(tmpl_d.p),
                           static_cast<int64_t*>(sc->body_ptr.p), origin, static_cast<double*>(sc->x64.p),
-                          static_cast<float*>(sc->x32.p), static_cast<int32_t*>(sc->body_of.p), N, nullptr);
+                          static_cast<float*>(sc->x32.p), static_cast<float*>(sc->l32.p),
+                          static_cast<int32_t*>(sc->body_of.p), N, nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
-  release(centres_d, &tmp_bytes);
   release(tmpl_d, &tmp_bytes);
   release(tmpl_ptr_d, &tmp_bytes);
   if (e != hipSuccess) return cleanup(fail(MFS_ERR_HIP, std::string("scene packing: ") + hipGetErrorString(e)));
@@ -298,7 +299,9 @@ mfs_status mfs_scene_create(int32_t dim, double kappa, int64_t T, const int32_t*
     d.origin[i] = origin[i];
     d.x64[i] = i < dim ? static_cast<double*>(sc->x64.p) + (size_t)i * N : nullptr;
     d.x32[i] = i < dim ? static_cast<float*>(sc->x32.p) + (size_t)i * N : nullptr;
+    d.l32[i] = i < dim ? static_cast<float*>(sc->l32.p) + (size_t)i * N : nullptr;
   }
+  d.centres = static_cast<double*>(sc->centres.p);
   d.body_of = static_cast<int32_t*>(sc->body_of.p);
   d.body_ptr = static_cast<int64_t*>(sc->body_ptr.p);
   d.shape_of = static_cast<int32_t*>(sc->shape_of.p);
@@ -313,7 +316,7 @@ mfs_status mfs_scene_create(int32_t dim, double kappa, int64_t T, const int32_t*
 mfs_status mfs_scene_destroy(mfs_scene* s) {
   if (!s) return MFS_OK;
   (void)hipDeviceSynchronize();
-  Buf* all[] = {&s->x64, &s->x32, &s->body_of, &s->body_ptr, &s->shape_of, &s->k_dev, &s->S64_tab,
+  Buf* all[] = {&s->x64, &s->x32, &s->l32, &s->centres, &s->body_of, &s->body_ptr, &s->shape_of, &s->k_dev, &s->S64_tab,
                 &s->S32_tab, &s->partial, &s->q32, &s->dirs, &s->kry, &s->vecs};
   for (Buf* b : all) release(*b, &s->bytes);
   delete s;
@@ -447,8 +450,8 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
   const mfs_prec prec = opts->prec;
   if (prec != MFS_FP64 && prec != MFS_MIXED) return fail(MFS_ERR_ARG, "solve: prec must be MFS_FP64 or MFS_MIXED");
   if (prec == MFS_MIXED && !sc->has_s32) return fail(MFS_ERR_ARG, "solve: MFS_MIXED needs FP32 copies of S");
-  if (!(opts->tol > 0.0) || opts->maxit < 1 || opts->restart < 1 || opts->restart > 4096)
-    return fail(MFS_ERR_ARG, "solve: need tol > 0, maxit >= 1, 1 <= restart <= 4096");
+  if (!(opts->tol > 0.0) || opts->maxit < 1 || opts->restart < 1 || opts->restart > 32768)
+    return fail(MFS_ERR_ARG, "solve: need tol > 0, maxit >= 1, 1 <= restart <= 32768");
   if (prec == MFS_MIXED && (opts->max_refine < 1 || !(opts->inner_tol > 0.0) || !(opts->inner_tol < 1.0)))
     return fail(MFS_ERR_ARG, "solve: MFS_MIXED needs max_refine >= 1 and 0 < inner_tol < 1");
   mfs_scene* s = const_cast<mfs_scene*>(sc);
@@ -551,6 +554,14 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
       MFS_HIP_TRY(hipStreamSynchronize(st));
       int na = 0;
       for (int c = 0; c < R; ++c) na += active[c];
+      if (opts->verbose > 1 && (j + 1) % 250 == 0) {
+        std::vector<double> est(R);
+        MFS_TRY(read_doubles(kk.res, est));
+        double mx = 0.0;
+        for (int c = 0; c < R; ++c) mx = std::max(mx, est[c]);
+        std::fprintf(stderr, "[mfs_solve] step %d of cycle, %d total, active %d, estimate %.3e\n", j + 1, total_it,
+                     na, mx);
+      }
       if (na == 0 || total_it >= opts->maxit) break;
     }
     MFS_HIP_TRY(launch_gmres_update_x(kk, x, st));
@@ -580,7 +591,9 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
       MFS_TRY(set_active_from_relres());
       KrylovDev kk = k;
       kk.bnorm = kk.beta;  // inner estimate relative to the current residual
-      MFS_TRY(cycle(kk, opts->inner_tol, true));
+      // ask each inner solve for no more reduction than the outer tolerance still needs
+      const double itol = std::max(opts->inner_tol, 0.3 * opts->tol / std::max(max_relres(), 1e-300));
+      MFS_TRY(cycle(kk, std::min(itol, 0.5), true));
       ++n_refine;
       ++n_restart;
       MFS_TRY(residual());

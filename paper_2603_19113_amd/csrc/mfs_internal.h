@@ -39,6 +39,8 @@ struct SceneDev {
   double origin[3];       // FP32 coordinates are relative to this point
   const double* x64[3];   // absolute FP64 coordinates, SoA
   const float* x32[3];    // FP32 coordinates relative to origin, SoA
+  const float* l32[3];    // FP32 body-local offsets x_hat - c_body (the shape template), SoA
+  const double* centres;  // [T][dim] body centres, FP64
   const int32_t* body_of; // [N]
   const int64_t* body_ptr;// [T+1]
   const int32_t* shape_of;// [T]
@@ -83,8 +85,8 @@ hipError_t launch_to_c64(const c128* in, c64* out, int64_t n, hipStream_t st);
 hipError_t launch_plane_wave(const SceneDev& s, const double* dirs_dev, int R, c128* vhat, hipStream_t st);
 hipError_t launch_pack_scene(int dim, int64_t T, const int32_t* shape_of, const double* centres,
                              const int64_t* tmpl_ptr, const double* tmpl_pts, const int64_t* body_ptr,
-                             const double* origin, double* x64_soa, float* x32_soa, int32_t* body_of,
-                             int64_t N, hipStream_t st);
+                             const double* origin, double* x64_soa, float* x32_soa, float* l32_soa,
+                             int32_t* body_of, int64_t N, hipStream_t st);
 
 // Krylov kernels (krylov.hip).  One Arnoldi/GMRES state per right-hand side; vectors [R][N].
 struct KrylovDev {

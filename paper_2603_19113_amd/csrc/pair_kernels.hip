@@ -203,6 +203,242 @@ __global__ __launch_bounds__(kBlock) void pair_sum_kernel(
   }
 }
 
+// ---------------------------------------------------------------------------
+// G_hat in FP32 with the distance split at the body centres.
+//
+// For target i on body a and source j on body b, x_i - x_j = (c_a - c_b) + (l_i - l_j), with
+// body-local offsets l (|l| <= body radius) and centre difference dc.  With D = |dc| and
+// u = |dl|^2 + 2 dc.dl, the distance is r = D + delta, delta = u / (D + r).  D and the phase
+// kappa D mod 2 pi are formed in FP64 once per (target, source body); delta, and with it the
+// phase correction, is an O(1) quantity formed in FP32 to ~1e-7 relative.  The phase kappa r is
+// therefore accurate to ~1e-6 rad instead of ~kappa r 2^-24 (1e-4 rad at kappa r = 1400).
+// Per source body the FP32 partial sums are added into FP64 accumulators, which removes the
+// O(sqrt(N) eps) growth of one long FP32 sum.
+//
+// 2D kernel, three branches on z = kappa r:
+//   z >= 12: Hankel modulus and phase expansions (DLMF 10.18.17-18, series of M^2 taken to its
+//            square root), 3 terms each: H0 = M e^{i theta},
+//            M sqrt(pi z / 2) = 1 - 1/(16 z^2) + 53/(512 z^4),
+//            theta = z - pi/4 - 1/(8 z) + 25/(384 z^3) - 1073/(5120 z^5);
+//            errors <= 2e-7 (modulus) and 4e-8 rad (phase) for z >= 12;
+//   3 <= z < 12: A&S 9.4.3 with the same accurate phase;
+//   z < 3: A&S 9.4.1 / 9.4.2.
+// 3D kernel: exp(i kappa r) / (4 pi r) with the same phase split.
+// ---------------------------------------------------------------------------
+struct BodyPhaseConsts {
+  float kappa_rev;   // kappa / 2 pi
+  float r_far;       // 12 / kappa
+  float r_mid;       // 3 / kappa
+  // far branch, amplitude (1/4) sqrt(2/(pi kappa)) r^{-1/2} (m0 + m1 r^-2 + m2 r^-4)
+  float m0, m1, m2;
+  // far branch, phase correction in revolutions: r^-1 (p0 + p1 r^-2 + p2 r^-4)
+  float p0, p1, p2;
+  // A&S branches
+  Phi2DConstsF32 as;
+  double kappa_rev64;
+};
+
+template <int DIM, int TPT, int RT>
+struct BPAcc {
+  float lx[TPT][DIM];  // target body-local offsets
+  double c[TPT][DIM];  // target body centres
+  int tb[TPT];
+  double ar[TPT][RT], ai[TPT][RT];  // FP64 accumulators
+  // per source body
+  float tdc[TPT][DIM];  // 2 (c_a - c_b)
+  float D[TPT], D2[TPT], ph0[TPT];
+  float sr_[TPT][RT], si_[TPT][RT];  // FP32 partial sums over the current source body
+};
+
+template <int DIM>
+__device__ __forceinline__ void bp_phi(const BodyPhaseConsts& k, float u, float D, float D2, float ph0,
+                                       float& pr, float& pi) {
+  const float r2 = D2 + u;
+  const float rinv = __builtin_amdgcn_rsqf(r2);
+  const float r = r2 * rinv;
+  // delta = r - D = u / (D + r), accurate where r >> 1
+  const float delta = u * __builtin_amdgcn_rcpf(D + r);
+  if constexpr (DIM == 3) {
+    const float rev = __builtin_amdgcn_fractf(fmaf(delta, k.kappa_rev, ph0));
+    const float a = rinv * 0.07957747154594767f;  // 1 / (4 pi r)
+    pr = a * __builtin_amdgcn_cosf(rev);
+    pi = a * __builtin_amdgcn_sinf(rev);
+  } else {
+    if (r >= k.r_far) {
+      const float w2 = rinv * rinv;
+      const float m = fmaf(fmaf(k.m2, w2, k.m1), w2, k.m0);
+      const float th = rinv * fmaf(fmaf(k.p2, w2, k.p1), w2, k.p0);
+      const float rev = __builtin_amdgcn_fractf(fmaf(delta, k.kappa_rev, ph0) + th);
+      const float a = m * __builtin_amdgcn_sqrtf(rinv);
+      // (i/4) H0 = (i/4) M e^{i theta}: re = -A sin, im = A cos
+      pr = -a * __builtin_amdgcn_sinf(rev);
+      pi = a * __builtin_amdgcn_cosf(rev);
+    } else if (r >= k.r_mid) {
+      const float t = k.as.three_over_kappa * rinv;
+      float f0 = 0.00014476f;
+      f0 = fmaf(f0, t, -0.00072805f);
+      f0 = fmaf(f0, t, 0.00137237f);
+      f0 = fmaf(f0, t, -0.00009512f);
+      f0 = fmaf(f0, t, -0.00552740f);
+      f0 = fmaf(f0, t, -0.00000077f);
+      f0 = fmaf(f0, t, 0.79788456f);
+      float th = 0.00013558f * 0.15915494309189535f;
+      th = fmaf(th, t, -0.00029333f * 0.15915494309189535f);
+      th = fmaf(th, t, -0.00054125f * 0.15915494309189535f);
+      th = fmaf(th, t, 0.00262573f * 0.15915494309189535f);
+      th = fmaf(th, t, -0.00003954f * 0.15915494309189535f);
+      th = fmaf(th, t, -0.04166397f * 0.15915494309189535f);
+      th = th * t;  // -1/8 is already in ph0
+      const float rev = __builtin_amdgcn_fractf(fmaf(delta, k.kappa_rev, ph0) + th);
+      const float a = k.as.amp * f0 * __builtin_amdgcn_sqrtf(rinv);
+      pr = -a * __builtin_amdgcn_sinf(rev);
+      pi = a * __builtin_amdgcn_cosf(rev);
+    } else {
+      phi2d_f32(r2, k.as, pr, pi);
+    }
+  }
+}
+
+template <int DIM, int TPT, int RT, bool MASK>
+__device__ __forceinline__ void bp_source(BPAcc<DIM, TPT, RT>& a, const BodyPhaseConsts& k, int sb,
+                                          const float* __restrict__ l0, const float* __restrict__ l1,
+                                          const float* __restrict__ l2, const c64* __restrict__ q, int64_t N,
+                                          int R, int r0, int64_t j) {
+  float ls[DIM];
+  ls[0] = l0[j];
+  ls[1] = l1[j];
+  if constexpr (DIM == 3) ls[2] = l2[j];
+  float qr[RT], qi[RT];
+#pragma unroll
+  for (int rr = 0; rr < RT; ++rr) {
+    const int r = (r0 + rr < R) ? r0 + rr : R - 1;
+    const c64 qq = q[(int64_t)r * N + j];
+    qr[rr] = qq.re;
+    qi[rr] = qq.im;
+  }
+#pragma unroll
+  for (int i = 0; i < TPT; ++i) {
+    // u = |dl|^2 + 2 dc.dl = sum_d dl_d (dl_d + 2 dc_d)
+    float u = 0.0f;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const float dl = a.lx[i][d] - ls[d];
+      u = fmaf(dl, dl + a.tdc[i][d], u);
+    }
+    float pr, pi;
+    bp_phi<DIM>(k, u, a.D[i], a.D2[i], a.ph0[i], pr, pi);
+    if constexpr (MASK) {
+      const bool same = a.tb[i] == sb;
+      pr = same ? 0.0f : pr;
+      pi = same ? 0.0f : pi;
+    }
+#pragma unroll
+    for (int rr = 0; rr < RT; ++rr) {
+      a.sr_[i][rr] = fmaf(pr, qr[rr], fmaf(-pi, qi[rr], a.sr_[i][rr]));
+      a.si_[i][rr] = fmaf(pr, qi[rr], fmaf(pi, qr[rr], a.si_[i][rr]));
+    }
+  }
+}
+
+template <int DIM, int TPT, int RT>
+__global__ __launch_bounds__(kBlock) void ghat_bodyphase_kernel(
+    BodyPhaseConsts k, const float* __restrict__ l0, const float* __restrict__ l1, const float* __restrict__ l2,
+    const double* __restrict__ cen, const int32_t* __restrict__ body_of, const int64_t* __restrict__ body_ptr,
+    const c64* __restrict__ q, int64_t N, int R, int64_t chunk_len, c64* __restrict__ partial) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t base = ((int64_t)blockIdx.x * kWaves + wave) * (64 * TPT);
+  if (base >= N) return;
+  const int r0 = blockIdx.z * RT;
+  const int64_t c0 = (int64_t)blockIdx.y * chunk_len;
+  const int64_t c1 = min(N, c0 + chunk_len);
+
+  BPAcc<DIM, TPT, RT> a;
+  int bmin = 0x7fffffff, bmax = -1;
+#pragma unroll
+  for (int i = 0; i < TPT; ++i) {
+    const int64_t t = base + 64 * i + lane;
+    const bool ok = t < N;
+    const int64_t tc = ok ? t : N - 1;
+    a.lx[i][0] = l0[tc];
+    a.lx[i][1] = l1[tc];
+    if constexpr (DIM == 3) a.lx[i][2] = l2[tc];
+    const int tb = body_of[tc];
+    a.tb[i] = ok ? tb : -1;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) a.c[i][d] = cen[(int64_t)tb * DIM + d];
+    if (ok) {
+      bmin = min(bmin, tb);
+      bmax = max(bmax, tb);
+    }
+#pragma unroll
+    for (int rr = 0; rr < RT; ++rr) a.ar[i][rr] = a.ai[i][rr] = 0.0;
+  }
+  bmin = wave_min_i32(bmin);
+  bmax = wave_max_i32(bmax);
+
+  if (c0 < c1) {
+    const int sb0 = body_of[c0];
+    const int sb1 = body_of[c1 - 1];
+    for (int sb = sb0; sb <= sb1; ++sb) {
+      const int64_t j0 = max(c0, body_ptr[sb]);
+      const int64_t j1 = min(c1, body_ptr[sb + 1]);
+      double cs[DIM];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) cs[d] = cen[(int64_t)sb * DIM + d];
+#pragma unroll
+      for (int i = 0; i < TPT; ++i) {
+        double D2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          const double dc = a.c[i][d] - cs[d];
+          D2 = fma(dc, dc, D2);
+          a.tdc[i][d] = (float)(2.0 * dc);
+        }
+        const double D = sqrt(D2);
+        const double ph = D * k.kappa_rev64;
+        a.D[i] = (float)D;
+        a.D2[i] = (float)D2;
+        // phase of kappa D in revolutions, minus pi/4 (2D) folded in
+        a.ph0[i] = (float)(ph - floor(ph)) - (DIM == 2 ? 0.125f : 0.0f);
+#pragma unroll
+        for (int rr = 0; rr < RT; ++rr) a.sr_[i][rr] = a.si_[i][rr] = 0.0f;
+      }
+      const bool masked = sb >= bmin && sb <= bmax;
+      int64_t j = j0;
+      if (!masked) {
+        for (; j + kUnroll <= j1; j += kUnroll) {
+#pragma unroll
+          for (int uu = 0; uu < kUnroll; ++uu)
+            bp_source<DIM, TPT, RT, false>(a, k, sb, l0, l1, l2, q, N, R, r0, j + uu);
+        }
+        for (; j < j1; ++j) bp_source<DIM, TPT, RT, false>(a, k, sb, l0, l1, l2, q, N, R, r0, j);
+      } else {
+        for (; j < j1; ++j) bp_source<DIM, TPT, RT, true>(a, k, sb, l0, l1, l2, q, N, R, r0, j);
+      }
+#pragma unroll
+      for (int i = 0; i < TPT; ++i)
+#pragma unroll
+        for (int rr = 0; rr < RT; ++rr) {
+          a.ar[i][rr] += (double)a.sr_[i][rr];
+          a.ai[i][rr] += (double)a.si_[i][rr];
+        }
+    }
+  }
+
+#pragma unroll
+  for (int i = 0; i < TPT; ++i) {
+    const int64_t t = base + 64 * i + lane;
+    if (t >= N) continue;
+#pragma unroll
+    for (int rr = 0; rr < RT; ++rr) {
+      const int r = r0 + rr;
+      if (r >= R) continue;
+      partial[((int64_t)blockIdx.y * R + r) * N + t] = c64{(float)a.ar[i][rr], (float)a.ai[i][rr]};
+    }
+  }
+}
+
 Phi2DConstsF32 make_phi2d_f32(double kappa) {
   Phi2DConstsF32 c;
   c.kappa = (float)kappa;
@@ -256,15 +492,48 @@ int pair_chunks_for(int64_t n_sources, int64_t n_targets, int tpt) {
 
 static const double kZero3[3] = {0.0, 0.0, 0.0};
 
+static BodyPhaseConsts make_bodyphase(double kappa) {
+  BodyPhaseConsts k{};
+  const double two_pi = 2.0 * M_PI;
+  k.kappa_rev = (float)(kappa / two_pi);
+  k.kappa_rev64 = kappa / two_pi;
+  k.r_far = (float)(12.0 / kappa);
+  k.r_mid = (float)(3.0 / kappa);
+  const double amp = 0.25 * std::sqrt(2.0 / (M_PI * kappa));  // (1/4) sqrt(2/(pi kappa))
+  const double k2 = kappa * kappa;
+  k.m0 = (float)amp;
+  k.m1 = (float)(-amp / (16.0 * k2));
+  k.m2 = (float)(amp * 53.0 / (512.0 * k2 * k2));
+  k.p0 = (float)(-1.0 / (8.0 * kappa) / two_pi);
+  k.p1 = (float)(25.0 / (384.0 * k2 * kappa) / two_pi);
+  k.p2 = (float)(-1073.0 / (5120.0 * k2 * k2 * kappa) / two_pi);
+  k.as = make_phi2d_f32(kappa);
+  return k;
+}
+
+template <int DIM, int RT>
+static hipError_t launch_bodyphase(const SceneDev& s, const c64* q, int R, c64* partial, int nchunks,
+                                   hipStream_t st) {
+  constexpr int TPT = 2;
+  int64_t chunk_len = (s.N + nchunks - 1) / nchunks;
+  chunk_len = (chunk_len + kUnroll - 1) / kUnroll * kUnroll;
+  const int64_t per_block = (int64_t)kBlock * TPT;
+  dim3 grid((unsigned)((s.N + per_block - 1) / per_block), (unsigned)nchunks, (unsigned)((R + RT - 1) / RT));
+  hipLaunchKernelGGL((ghat_bodyphase_kernel<DIM, TPT, RT>), grid, dim3(kBlock), 0, st, make_bodyphase(s.kappa),
+                     s.l32[0], s.l32[1], s.l32[2], s.centres, s.body_of, s.body_ptr, q, s.N, R, chunk_len, partial);
+  return hipGetLastError();
+}
+
 hipError_t launch_ghat_f32(const SceneDev& s, const c64* q, int R, c64* partial, int nchunks, hipStream_t st) {
+  if (s.N <= 0) return hipSuccess;
   if (s.dim == 2) {
-    PhiEval<float, 2> phi{make_phi2d_f32(s.kappa)};
-    return dispatch_rt<float, 2, 2, false>(phi, s.x32[0], s.x32[1], nullptr, s.body_of, s.body_ptr, q, s.N, R,
-                                           nullptr, kZero3, s.N, partial, nchunks, st);
+    if (R == 1) return launch_bodyphase<2, 1>(s, q, R, partial, nchunks, st);
+    if (R == 2) return launch_bodyphase<2, 2>(s, q, R, partial, nchunks, st);
+    return launch_bodyphase<2, 4>(s, q, R, partial, nchunks, st);
   }
-  PhiEval<float, 3> phi{Phi3DConstsF32{(float)(s.kappa / (2.0 * M_PI))}};
-  return dispatch_rt<float, 3, 2, false>(phi, s.x32[0], s.x32[1], s.x32[2], s.body_of, s.body_ptr, q, s.N, R,
-                                         nullptr, kZero3, s.N, partial, nchunks, st);
+  if (R == 1) return launch_bodyphase<3, 1>(s, q, R, partial, nchunks, st);
+  if (R == 2) return launch_bodyphase<3, 2>(s, q, R, partial, nchunks, st);
+  return launch_bodyphase<3, 4>(s, q, R, partial, nchunks, st);
 }
 
 hipError_t launch_ghat_f64(const SceneDev& s, const c128* q, int R, c128* partial, int nchunks, hipStream_t st) {
