@@ -27,10 +27,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "Helmholtz pair-evals/s per matvec; GMRES solve time @1e-8 rel res; p50/p99"
-# Algorithmic flops per pair of the FP32 pair kernel (FMA = 2, transcendental = 1), counted on
-# the far branch of the 2D kernel: 2 sub, r^2 (mul+fma), rsq, r, t, f0 poly (6 fma), phase poly
-# (6 fma), phase fma, fract, sin, cos, sqrt, amplitude (2 mul), (re, im) (2 mul), complex MAC (4 fma).
-FLOP_PER_PAIR_F32 = {2: 50, 3: 25}
+# Flops per pair of the FP32 G_hat kernel (FMA = 2, transcendental = 1), counted on its far branch.
+# 2D: u = sum_d dl_d (dl_d + 2 dc_d) (8), r^2 (1), rsq (1), r (1), D + r (1), rcp (1), delta (1),
+# 1/r^2 (1), modulus poly (4), phase poly (5), phase sum (3), fract (1), sqrt (1), amplitude (1),
+# sin + cos (2), (re, im) (2), complex multiply-add (8) = 42.
+# 3D: u (12), r^2, rsq, r, D + r, rcp, delta (6), phase fma (2), fract (1), 1/(4 pi r) (1),
+# sin + cos (2), (re, im) (2), complex multiply-add (8) = 34.
+FLOP_PER_PAIR_F32 = {2: 42, 3: 34}
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 
 
@@ -71,17 +74,20 @@ def cpu_baseline(sc, seconds: float) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--workload", default="starfish2000",
                     choices=["starfish2000", "spheres1000", "mixed2000_R64", "disks16"])
     ap.add_argument("--bodies", type=int, default=None, help="override T (scaled scene, same density)")
-    ap.add_argument("--restart", type=int, default=400)
-    ap.add_argument("--inner-tol", type=float, default=1e-4)
+    ap.add_argument("--restart", type=int, default=16000,
+                    help="Krylov basis size; the default keeps the whole basis resident (no restart)")
+    ap.add_argument("--inner-tol", type=float, default=1e-6)
+    ap.add_argument("--matvecs", type=int, default=0,
+                    help="profiling mode: replace the solve by this many mixed operator applications")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--verbose", type=int, default=0)
+    ap.add_argument("--verbose", type=int, default=2, help="solver progress lines on stderr")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -110,8 +116,19 @@ def main() -> int:
         v = torch.empty((R, scene.N), dtype=torch.complex128, device="cuda")
         mfs.plane_wave(scene, dirs, v)
         q = torch.empty_like(v)
-        info = mfs.solve(scene, v, q, tol=args.tol, maxit=20000, restart=args.restart, max_refine=20,
-                         inner_tol=args.inner_tol, prec=mfs.MFS_MIXED, verbose=args.verbose)
+        if args.matvecs > 0:
+            # profiling mode: the operator applications of a solve without the Krylov recurrence
+            q32 = v.to(torch.complex64)
+            y32 = torch.empty_like(q32)
+            for _ in range(args.matvecs):
+                mfs.apply(scene, q32, y32, mfs.MFS_FP32)
+                q32, y32 = y32, q32
+            q.copy_(q32)
+            info = {"relres_max": float("nan"), "n_matvec32": args.matvecs, "n_matvec64": 0, "n_refine": 0,
+                    "t_total_s": 0.0, "n_reorth": 0, "status": "profile"}
+        else:
+            info = mfs.solve(scene, v, q, tol=args.tol, maxit=60000, restart=args.restart, max_refine=20,
+                             inner_tol=args.inner_tol, prec=mfs.MFS_MIXED, verbose=args.verbose)
         u = torch.empty((R, targets.shape[0]), dtype=torch.complex128, device="cuda")
         mfs.eval_field(scene, q, targets, u, mfs.MFS_FP64)
         torch.cuda.synchronize()
@@ -164,12 +181,14 @@ def main() -> int:
         "data": "synthetic (seeded geometry, no dataset)",
         "config": {"workload": sc.name, "T": sc.T, "N": sc.N, "R": R, "kappa": sc.kappa, "tol": args.tol,
                    "precision": "mixed", "restart": args.restart, "inner_tol": args.inner_tol},
-        "solve_s_p50": statistics.median(solve_times),
-        "solve_s_p99": float(np.percentile(solve_times, 99)),
+        "solve_s_p50": statistics.median(solve_times) if args.matvecs == 0 else None,
+        "solve_s_p99": float(np.percentile(solve_times, 99)) if args.matvecs == 0 else None,
         "relres_max": max(i["relres_max"] for i in infos),
         "n_matvec32": infos[-1]["n_matvec32"],
         "n_matvec64": infos[-1]["n_matvec64"],
         "n_refine": infos[-1]["n_refine"],
+        "n_reorth": infos[-1].get("n_reorth", 0),
+        "mode": "profile (operator applications only)" if args.matvecs > 0 else "full solve",
         "pair_kernel_f32": {"launches": n32, "avg_ms": avg32, "pairs_per_launch": pairs_per_launch32,
                             "pair_evals_per_s": pairs_per_launch32 / (avg32 * 1e-3) if n32 else 0.0},
         "pair_kernel_f64": {"launches": n64, "avg_ms": ms64 / max(n64, 1),

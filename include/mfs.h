@@ -164,16 +164,17 @@ mfs_status mfs_s_apply(const mfs_scene* scene, const void* q_dev, const void* t_
 mfs_status mfs_apply(const mfs_scene* scene, const void* q_dev, void* y_dev, int32_t R, mfs_prec prec,
                      void* stream);
 
-/* GMRES solve of (I + S G_hat) qhat = S vhat (eq. mbody2, Sec. 2.3), x0 = 0.
+/* GMRES solve of (I + S G_hat) qhat = S vhat (eq. mbody2, Sec. 2.3), from x0 = 0 or a given x0.
  *   MFS_FP64:  restarted GMRES(restart) with the FP64 operator.
  *   MFS_MIXED: iterative refinement: r = b - A x with the FP64 operator, then GMRES with the FP32
  *              operator and FP64 Krylov vectors on A d = r to relative tolerance inner_tol,
  *              x += d; repeated until ||b - A x|| / ||b|| <= tol (FP64 residual) or max_refine.
  * Each right-hand side has its own Krylov space; the R operator applications of one iteration
- * share one pair-kernel launch.  The stopping test is ||b - A x||_2 / ||b||_2 <= tol per column,
+ * share one pair-kernel launch.  Orthogonalisation is classical Gram-Schmidt with a second pass
+ * where the first one cancelled (||w'|| < ||w|| / sqrt 2).  The stopping test is ||b - A x||_2 / ||b||_2 <= tol per column,
  * checked with the FP64 operator before returning.  Synchronous.
  *   vhat_dev  device complex128 [R][N]: Dirichlet data at x_hat (b = S vhat is formed inside)
- *   qhat_dev  device complex128 [R][N]: solution (output)
+ *   qhat_dev  device complex128 [R][N]: solution (output; input too when use_x0 = 1)
  *   info      host, may be NULL. */
 typedef struct {
   double tol;        /* relative residual target, e.g. 1e-8 */
@@ -184,7 +185,12 @@ typedef struct {
   double inner_tol;  /* MFS_MIXED: smallest relative residual reduction asked of an inner solve; the
                         last steps ask only for the reduction the outer tolerance still needs */
   mfs_prec prec;     /* MFS_FP64 or MFS_MIXED */
-  int32_t verbose;   /* >0: print one line per restart/refinement to stderr */
+  int32_t verbose;   /* >0: one line per restart/refinement on stderr; >1: also every 250 steps */
+  double fp64_until; /* MFS_MIXED: within a cycle, apply the FP64 operator while the residual
+                        estimate is above this value and the FP32 one below it (inexact Krylov:
+                        early steps need the accurate operator); 0 = FP32 throughout */
+  int32_t use_x0;    /* 1: qhat_dev holds an initial guess (warm start, or resuming a checkpointed
+                        solve: the FP64 residual is recomputed first); 0: x0 = 0 */
 } mfs_solve_opts;
 
 typedef struct {
@@ -194,6 +200,7 @@ typedef struct {
   int32_t n_restart;    /* GMRES restarts */
   double relres_max;    /* max over columns of the final FP64 relative residual */
   double t_total_s;     /* wall time of the call */
+  int32_t n_reorth;     /* Arnoldi steps that took the second Gram-Schmidt pass (max over columns) */
 } mfs_solve_info;
 
 mfs_status mfs_solve(const mfs_scene* scene, const void* vhat_dev, int32_t R, const mfs_solve_opts* opts,

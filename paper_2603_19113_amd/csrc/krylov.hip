@@ -26,9 +26,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 // chunk of w in registers and reads kGroup basis-vector chunks once.
 __global__ __launch_bounds__(kThreads) void dots_kernel(const c128* __restrict__ V, const c128* __restrict__ w,
                                                         int64_t N, int R, int jcount, int nblk,
-                                                        double* __restrict__ part) {
+                                                        double* __restrict__ part, const int32_t* __restrict__ flag) {
   __shared__ double red[kThreads / 64][kGroup][2];
   const int r = blockIdx.z;
+  if (flag && !flag[r]) return;
   const int i0 = blockIdx.y * kGroup;
   const int64_t base = (int64_t)blockIdx.x * (kThreads * kElems);
   c128 wl[kElems];
@@ -83,8 +84,13 @@ __global__ __launch_bounds__(kThreads) void dots_kernel(const c128* __restrict__
 
 // out[r][i] = sum_blk part[r][i][blk] (+ add[r][i] if add != null); one wave per (i, r).
 __global__ void dots_reduce_kernel(const double* __restrict__ part, int jcount, int nblk, int R, int ld,
-                                   c128* __restrict__ out, const c128* __restrict__ add) {
+                                   c128* __restrict__ out, const c128* __restrict__ add,
+                                   const int32_t* __restrict__ flag) {
   const int i = blockIdx.x, r = blockIdx.y, lane = threadIdx.x;
+  if (flag && !flag[r]) {
+    if (lane == 0) out[(int64_t)r * ld + i] = c128{0.0, 0.0};
+    return;
+  }
   double sr = 0.0, si = 0.0;
   for (int b = lane; b < nblk; b += 64) {
     const int64_t o = (((int64_t)r * jcount + i) * nblk + b) * 2;
@@ -106,10 +112,10 @@ __global__ void dots_reduce_kernel(const double* __restrict__ part, int jcount, 
 // w[r][n] -= sum_{i<jcount} h[r][i] V_i[r][n]
 __global__ __launch_bounds__(kThreads) void basis_axpy_kernel(const c128* __restrict__ V, const c128* __restrict__ h,
                                                               int ld, int64_t N, int R, int jcount,
-                                                              c128* __restrict__ w) {
+                                                              c128* __restrict__ w, const int32_t* __restrict__ flag) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
-  if (n >= N) return;
+  if (n >= N || (flag && !flag[r])) return;
   // h is read with wave-uniform addresses (scalar loads); eight basis loads are kept in flight
   double ar = 0.0, ai = 0.0;
   const c128* hr = h + (int64_t)r * ld;
@@ -161,6 +167,27 @@ __global__ void norm_reduce_kernel(const double* __restrict__ part, int nblk, do
   if (lane == 0) out[r] = sqrt(s);
 }
 
+// Second Gram-Schmidt pass only where the first one cancelled: reorthogonalise when
+// ||w'||^2 = ||w||^2 - sum |h_i|^2 falls below ||w||^2 / 2 (the "twice is enough" test of
+// Daniel, Gragg, Kaufman and Stewart with eta = 1/sqrt(2)).  One thread per right-hand side.
+__global__ void reorth_decide_kernel(int jcount, int R, int ld, const c128* __restrict__ h,
+                                     const double* __restrict__ wn2, int32_t* __restrict__ flag,
+                                     int32_t* __restrict__ count, double eta2, double* __restrict__ ratio_log,
+                                     int m) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  double s = 0.0;
+  for (int i = 0; i < jcount; ++i) {
+    const c128 v = h[(int64_t)r * ld + i];
+    s += v.re * v.re + v.im * v.im;
+  }
+  const double w2 = wn2[r] * wn2[r];
+  const int f = (w2 - s) < eta2 * w2 ? 1 : 0;
+  flag[r] = f;
+  count[r] += f;
+  if (ratio_log) ratio_log[(int64_t)r * 2 * m + jcount - 1] = w2 > 0.0 ? sqrt(fmax(w2 - s, 0.0) / w2) : 0.0;
+}
+
 // Start of a cycle: V_0 = r0 / beta, g = (beta, 0, ...).  Columns with beta == 0 stay inactive.
 __global__ void start_scale_kernel(const c128* __restrict__ r0, const double* __restrict__ beta, int64_t N, int R,
                                    c128* __restrict__ V0) {
@@ -186,8 +213,10 @@ __global__ void start_state_kernel(const double* __restrict__ beta, const double
 }
 
 // Column j of H from the Gram-Schmidt coefficients and ||w||, previous rotations, new rotation,
-// residual estimate.  One thread per right-hand side.
-__global__ void givens_kernel(int j, int m, int R, const c128* __restrict__ hcol, const c128* __restrict__ h2,
+// residual estimate.  The Arnoldi vectors come from w = K v_j for the operator shift I + K, so the
+// shift is added to the diagonal entry.  One thread per right-hand side.
+__global__ void givens_kernel(int j, int m, int R, double shift, const c128* __restrict__ hcol,
+                              const c128* __restrict__ h2,
                               const double* __restrict__ hnorm,
                               c128* __restrict__ H, c128* __restrict__ cs, c128* __restrict__ sn,
                               c128* __restrict__ g, double* __restrict__ res, const double* __restrict__ bnorm,
@@ -199,6 +228,7 @@ __global__ void givens_kernel(int j, int m, int R, const c128* __restrict__ hcol
     const c128 a1 = hcol[(int64_t)r * (m + 1) + i], a2 = h2[(int64_t)r * (m + 1) + i];
     Hc[i] = c128{a1.re + a2.re, a1.im + a2.im};
   }
+  Hc[j].re += shift;  // H(shift I + K) = H(K) + shift I
   Hc[j + 1] = c128{hnorm[r], 0.0};
   c128* c = cs + (int64_t)r * m;
   c128* s = sn + (int64_t)r * m;
@@ -329,18 +359,25 @@ hipError_t launch_start_cycle(KrylovDev k, const c128* r0, hipStream_t st) {
   return hipGetLastError();
 }
 
-// CGS2: hcol = V^H w; w -= V hcol; h2 = V^H w; w -= V h2 (H column = hcol + h2, summed in Givens).
+// Gram-Schmidt: hcol = V^H w; w -= V hcol; then, where the first pass cancelled, h2 = V^H w;
+// w -= V h2 (the H column is hcol + h2, summed in the Givens kernel).
 hipError_t launch_arnoldi_orth(KrylovDev k, int j, c128* w, hipStream_t st) {
   const int jc = j + 1;
   const int ld = k.m + 1;
+  hipError_t e = launch_norms(w, k.N, k.R, k.part, k.nblk, k.wn, st);
+  if (e != hipSuccess) return e;
   for (int pass = 0; pass < 2; ++pass) {
     c128* h = pass == 0 ? k.hcol : k.h2;
+    const int32_t* flag = pass == 0 ? nullptr : k.reorth;
+    if (pass == 1)
+      hipLaunchKernelGGL(reorth_decide_kernel, dim3(blocks_for(k.R, 64)), dim3(64), 0, st, jc, k.R, ld, k.hcol, k.wn,
+                         k.reorth, k.n_reorth, k.reorth_eta * k.reorth_eta, k.ratio_log, k.m);
     hipLaunchKernelGGL(dots_kernel, dim3(k.nblk, (jc + kGroup - 1) / kGroup, k.R), dim3(kThreads), 0, st, k.V, w,
-                       k.N, k.R, jc, k.nblk, k.part);
+                       k.N, k.R, jc, k.nblk, k.part, flag);
     hipLaunchKernelGGL(dots_reduce_kernel, dim3(jc, k.R), dim3(64), 0, st, k.part, jc, k.nblk, k.R, ld, h,
-                       (const c128*)nullptr);
+                       (const c128*)nullptr, flag);
     hipLaunchKernelGGL(basis_axpy_kernel, dim3(blocks_for(k.N, kThreads), k.R), dim3(kThreads), 0, st, k.V, h, ld,
-                       k.N, k.R, jc, w);
+                       k.N, k.R, jc, w, flag);
   }
   return hipGetLastError();
 }
@@ -349,7 +386,7 @@ hipError_t launch_arnoldi_orth(KrylovDev k, int j, c128* w, hipStream_t st) {
 hipError_t launch_arnoldi_finish(KrylovDev k, int j, c128* w, double tol, hipStream_t st) {
   hipError_t e = launch_norms(w, k.N, k.R, k.part, k.nblk, k.hnorm, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(givens_kernel, dim3(blocks_for(k.R, 64)), dim3(64), 0, st, j, k.m, k.R, k.hcol, k.h2, k.hnorm,
+  hipLaunchKernelGGL(givens_kernel, dim3(blocks_for(k.R, 64)), dim3(64), 0, st, j, k.m, k.R, 1.0, k.hcol, k.h2, k.hnorm,
                      k.H, k.cs, k.sn, k.g, k.res, k.bnorm, tol, k.active, k.jlen);
   hipLaunchKernelGGL(scale_next_kernel, dim3(blocks_for(k.N, 256), k.R), dim3(256), 0, st, w, k.hnorm, k.N, k.R,
                      k.V + (int64_t)(j + 1) * k.R * k.N);

@@ -40,6 +40,7 @@ struct SceneDev {
   const double* x64[3];   // absolute FP64 coordinates, SoA
   const float* x32[3];    // FP32 coordinates relative to origin, SoA
   const float* l32[3];    // FP32 body-local offsets x_hat - c_body (the shape template), SoA
+  const float* lsq32;     // [N] |l|^2 of the FP32 offsets
   const double* centres;  // [T][dim] body centres, FP64
   const int32_t* body_of; // [N]
   const int64_t* body_ptr;// [T+1]
@@ -86,7 +87,7 @@ hipError_t launch_plane_wave(const SceneDev& s, const double* dirs_dev, int R, c
 hipError_t launch_pack_scene(int dim, int64_t T, const int32_t* shape_of, const double* centres,
                              const int64_t* tmpl_ptr, const double* tmpl_pts, const int64_t* body_ptr,
                              const double* origin, double* x64_soa, float* x32_soa, float* l32_soa,
-                             int32_t* body_of, int64_t N, hipStream_t st);
+                             float* lsq, int32_t* body_of, int64_t N, hipStream_t st);
 
 // Krylov kernels (krylov.hip).  One Arnoldi/GMRES state per right-hand side; vectors [R][N].
 struct KrylovDev {
@@ -107,6 +108,11 @@ struct KrylovDev {
   double* hnorm;      // [R] ||w|| of the current step
   int32_t* active;    // [R] 1 while the column iterates in this cycle
   int32_t* jlen;      // [R] Arnoldi steps taken by the column in this cycle
+  double* wn;         // [R] ||w|| before orthogonalisation
+  int32_t* reorth;    // [R] 1 if the current step takes the second Gram-Schmidt pass
+  int32_t* n_reorth;  // [R] number of second passes taken (diagnostics)
+  double reorth_eta;  // second pass when ||w'|| < eta ||w||
+  double* ratio_log;  // optional [R][2m] log of ||w'|| / ||w|| per step (diagnostics), or null
   double* part;       // [R][m+1][nblk][2] partial sums
   int nblk;
 };

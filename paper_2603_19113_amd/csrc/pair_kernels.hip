@@ -208,7 +208,9 @@ __global__ __launch_bounds__(kBlock) void pair_sum_kernel(
 //
 // For target i on body a and source j on body b, x_i - x_j = (c_a - c_b) + (l_i - l_j), with
 // body-local offsets l (|l| <= body radius) and centre difference dc.  With D = |dc| and
-// u = |dl|^2 + 2 dc.dl, the distance is r = D + delta, delta = u / (D + r).  D and the phase
+// u = |dl|^2 + 2 dc.dl, the distance is r = D + delta, delta = u / (D + r).  u is evaluated as
+// A + |l_j|^2 + P . l_j with A = |l_i|^2 + 2 dc.l_i and P = -2 (l_i + dc) formed once per
+// (target, source body) and |l_j|^2 stored per point.  D and the phase
 // kappa D mod 2 pi are formed in FP64 once per (target, source body); delta, and with it the
 // phase correction, is an O(1) quantity formed in FP32 to ~1e-7 relative.  The phase kappa r is
 // therefore accurate to ~1e-6 rad instead of ~kappa r 2^-24 (1e-4 rad at kappa r = 1400).
@@ -244,8 +246,8 @@ struct BPAcc {
   double c[TPT][DIM];  // target body centres
   int tb[TPT];
   double ar[TPT][RT], ai[TPT][RT];  // FP64 accumulators
-  // per source body
-  float tdc[TPT][DIM];  // 2 (c_a - c_b)
+  // per source body: u = A + |l_s|^2 + P . l_s with A = |l_t|^2 + 2 dc . l_t, P = -2 (l_t + dc)
+  float A[TPT], P[TPT][DIM];
   float D[TPT], D2[TPT], ph0[TPT];
   float sr_[TPT][RT], si_[TPT][RT];  // FP32 partial sums over the current source body
 };
@@ -302,12 +304,13 @@ __device__ __forceinline__ void bp_phi(const BodyPhaseConsts& k, float u, float 
 template <int DIM, int TPT, int RT, bool MASK>
 __device__ __forceinline__ void bp_source(BPAcc<DIM, TPT, RT>& a, const BodyPhaseConsts& k, int sb,
                                           const float* __restrict__ l0, const float* __restrict__ l1,
-                                          const float* __restrict__ l2, const c64* __restrict__ q, int64_t N,
-                                          int R, int r0, int64_t j) {
+                                          const float* __restrict__ l2, const float* __restrict__ lsq,
+                                          const c64* __restrict__ q, int64_t N, int R, int r0, int64_t j) {
   float ls[DIM];
   ls[0] = l0[j];
   ls[1] = l1[j];
   if constexpr (DIM == 3) ls[2] = l2[j];
+  const float bs = lsq[j];
   float qr[RT], qi[RT];
 #pragma unroll
   for (int rr = 0; rr < RT; ++rr) {
@@ -318,13 +321,10 @@ __device__ __forceinline__ void bp_source(BPAcc<DIM, TPT, RT>& a, const BodyPhas
   }
 #pragma unroll
   for (int i = 0; i < TPT; ++i) {
-    // u = |dl|^2 + 2 dc.dl = sum_d dl_d (dl_d + 2 dc_d)
-    float u = 0.0f;
+    // u = |dl|^2 + 2 dc.dl = A + |l_s|^2 + P . l_s
+    float u = a.A[i] + bs;
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      const float dl = a.lx[i][d] - ls[d];
-      u = fmaf(dl, dl + a.tdc[i][d], u);
-    }
+    for (int d = 0; d < DIM; ++d) u = fmaf(a.P[i][d], ls[d], u);
     float pr, pi;
     bp_phi<DIM>(k, u, a.D[i], a.D2[i], a.ph0[i], pr, pi);
     if constexpr (MASK) {
@@ -343,7 +343,7 @@ __device__ __forceinline__ void bp_source(BPAcc<DIM, TPT, RT>& a, const BodyPhas
 template <int DIM, int TPT, int RT>
 __global__ __launch_bounds__(kBlock) void ghat_bodyphase_kernel(
     BodyPhaseConsts k, const float* __restrict__ l0, const float* __restrict__ l1, const float* __restrict__ l2,
-    const double* __restrict__ cen, const int32_t* __restrict__ body_of, const int64_t* __restrict__ body_ptr,
+    const float* __restrict__ lsq, const double* __restrict__ cen, const int32_t* __restrict__ body_of, const int64_t* __restrict__ body_ptr,
     const c64* __restrict__ q, int64_t N, int R, int64_t chunk_len, c64* __restrict__ partial) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -389,12 +389,16 @@ __global__ __launch_bounds__(kBlock) void ghat_bodyphase_kernel(
 #pragma unroll
       for (int i = 0; i < TPT; ++i) {
         double D2 = 0.0;
+        float Ai = 0.0f;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
           const double dc = a.c[i][d] - cs[d];
           D2 = fma(dc, dc, D2);
-          a.tdc[i][d] = (float)(2.0 * dc);
+          const float dcf = (float)dc;
+          Ai = fmaf(a.lx[i][d], a.lx[i][d] + 2.0f * dcf, Ai);
+          a.P[i][d] = -2.0f * (a.lx[i][d] + dcf);
         }
+        a.A[i] = Ai;
         const double D = sqrt(D2);
         const double ph = D * k.kappa_rev64;
         a.D[i] = (float)D;
@@ -410,11 +414,11 @@ __global__ __launch_bounds__(kBlock) void ghat_bodyphase_kernel(
         for (; j + kUnroll <= j1; j += kUnroll) {
 #pragma unroll
           for (int uu = 0; uu < kUnroll; ++uu)
-            bp_source<DIM, TPT, RT, false>(a, k, sb, l0, l1, l2, q, N, R, r0, j + uu);
+            bp_source<DIM, TPT, RT, false>(a, k, sb, l0, l1, l2, lsq, q, N, R, r0, j + uu);
         }
-        for (; j < j1; ++j) bp_source<DIM, TPT, RT, false>(a, k, sb, l0, l1, l2, q, N, R, r0, j);
+        for (; j < j1; ++j) bp_source<DIM, TPT, RT, false>(a, k, sb, l0, l1, l2, lsq, q, N, R, r0, j);
       } else {
-        for (; j < j1; ++j) bp_source<DIM, TPT, RT, true>(a, k, sb, l0, l1, l2, q, N, R, r0, j);
+        for (; j < j1; ++j) bp_source<DIM, TPT, RT, true>(a, k, sb, l0, l1, l2, lsq, q, N, R, r0, j);
       }
 #pragma unroll
       for (int i = 0; i < TPT; ++i)
@@ -520,7 +524,8 @@ static hipError_t launch_bodyphase(const SceneDev& s, const c64* q, int R, c64* 
   const int64_t per_block = (int64_t)kBlock * TPT;
   dim3 grid((unsigned)((s.N + per_block - 1) / per_block), (unsigned)nchunks, (unsigned)((R + RT - 1) / RT));
   hipLaunchKernelGGL((ghat_bodyphase_kernel<DIM, TPT, RT>), grid, dim3(kBlock), 0, st, make_bodyphase(s.kappa),
-                     s.l32[0], s.l32[1], s.l32[2], s.centres, s.body_of, s.body_ptr, q, s.N, R, chunk_len, partial);
+                     s.l32[0], s.l32[1], s.l32[2], s.lsq32, s.centres, s.body_of, s.body_ptr, q, s.N, R, chunk_len,
+                     partial);
   return hipGetLastError();
 }
 

@@ -93,8 +93,8 @@ __global__ void pack_scene_kernel(int dim, int64_t T, const int32_t* __restrict_
                                   const double* __restrict__ centres, const int64_t* __restrict__ tmpl_ptr,
                                   const double* __restrict__ tmpl_pts, const int64_t* __restrict__ body_ptr,
                                   double ox, double oy, double oz, double* __restrict__ x64,
-                                  float* __restrict__ x32, float* __restrict__ l32, int32_t* __restrict__ body_of,
-                                  int64_t N) {
+                                  float* __restrict__ x32, float* __restrict__ l32, float* __restrict__ lsq,
+                                  int32_t* __restrict__ body_of, int64_t N) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   // body containing point i: largest tau with body_ptr[tau] <= i
@@ -109,12 +109,16 @@ __global__ void pack_scene_kernel(int dim, int64_t T, const int32_t* __restrict_
   const int s = shape_of[tau];
   const double* p = tmpl_pts + (tmpl_ptr[s] + l) * dim;
   const double o[3] = {ox, oy, oz};
+  float l2 = 0.0f;
   for (int d = 0; d < dim; ++d) {
     const double v = p[d] + centres[tau * dim + d];
     x64[d * N + i] = v;
     x32[d * N + i] = (float)(v - o[d]);
-    l32[d * N + i] = (float)p[d];
+    const float lf = (float)p[d];
+    l32[d * N + i] = lf;
+    l2 = fmaf(lf, lf, l2);
   }
+  lsq[i] = l2;
   body_of[i] = (int32_t)tau;
 }
 
@@ -151,10 +155,10 @@ hipError_t launch_plane_wave(const SceneDev& s, const double* dirs_dev, int R, c
 hipError_t launch_pack_scene(int dim, int64_t T, const int32_t* shape_of, const double* centres,
                              const int64_t* tmpl_ptr, const double* tmpl_pts, const int64_t* body_ptr,
                              const double* origin, double* x64_soa, float* x32_soa, float* l32_soa,
-                             int32_t* body_of, int64_t N, hipStream_t st) {
+                             float* lsq, int32_t* body_of, int64_t N, hipStream_t st) {
   hipLaunchKernelGGL(pack_scene_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, dim, T, shape_of,
                      centres, tmpl_ptr, tmpl_pts, body_ptr, origin[0], origin[1], origin[2], x64_soa, x32_soa,
-                     l32_soa, body_of, N);
+                     l32_soa, lsq, body_of, N);
   return hipGetLastError();
 }
 

@@ -43,12 +43,13 @@ class ShapeDesc(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("max_refine", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("prec", ctypes.c_int32),
-                ("verbose", ctypes.c_int32)]
+                ("verbose", ctypes.c_int32), ("fp64_until", ctypes.c_double), ("use_x0", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("n_matvec32", ctypes.c_int32), ("n_matvec64", ctypes.c_int32), ("n_refine", ctypes.c_int32),
-                ("n_restart", ctypes.c_int32), ("relres_max", ctypes.c_double), ("t_total_s", ctypes.c_double)]
+                ("n_restart", ctypes.c_int32), ("relres_max", ctypes.c_double), ("t_total_s", ctypes.c_double),
+                ("n_reorth", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -242,9 +243,10 @@ def apply(scene: Scene, q, y, prec: int = MFS_FP64, stream=None):
 
 
 def solve(scene: Scene, vhat, qhat, tol=1e-8, maxit=2000, restart=300, max_refine=10, inner_tol=1e-4,
-          prec: int = MFS_FP64, verbose: int = 0, stream=None, raise_on_noconv: bool = True) -> dict:
+          prec: int = MFS_FP64, verbose: int = 0, fp64_until: float = 0.0, use_x0: bool = False, stream=None,
+          raise_on_noconv: bool = True) -> dict:
     o = SolveOpts(tol=tol, maxit=maxit, restart=restart, max_refine=max_refine, inner_tol=inner_tol, prec=prec,
-                  verbose=verbose)
+                  verbose=verbose, fp64_until=fp64_until, use_x0=1 if use_x0 else 0)
     info = SolveInfo()
     code = _lib.mfs_solve(scene.handle, _ptr(vhat), vhat.shape[0], ctypes.byref(o), _ptr(qhat),
                           ctypes.byref(info), _stream(stream))

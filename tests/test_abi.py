@@ -1,0 +1,74 @@
+"""The C ABI library on the CPU: it loads, exports every entry point include/mfs.h declares, and
+rejects invalid arguments before touching the device (no compute calls here)."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2603_19113_amd import mfs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "mfs.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mfs_[A-Za-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(mfs.LIB_PATH):
+        pytest.fail("libmfs.so is not built: run python -m paper_2603_19113_amd.build")
+    return mfs.load()
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for required in ("mfs_build_S", "mfs_apply", "mfs_solve", "mfs_eval_field", "mfs_scene_create"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+    assert set(mfs.EXPORTS) == set(_declared_functions())
+
+
+def test_version_and_error_string(lib):
+    assert lib.mfs_version() >= 100
+    assert isinstance(lib.mfs_last_error(), bytes)
+
+
+def test_invalid_arguments_rejected_without_device(lib):
+    out = ctypes.c_void_p(0)
+    k = np.array([4], np.int64)
+    # dim 4 is rejected before any allocation
+    assert lib.mfs_scene_create(4, 1.0, 1, None, None, 1, k.ctypes.data, None, None, None, ctypes.byref(out)) == -1
+    assert b"dim" in lib.mfs_last_error()
+    # non-positive wavenumber
+    assert lib.mfs_scene_create(2, -1.0, 1, None, None, 1, k.ctypes.data, None, None, None, ctypes.byref(out)) == -1
+    # null scene for every scene entry point
+    assert lib.mfs_apply(None, None, None, 1, 0, None) == -1
+    assert lib.mfs_ghat_apply(None, None, None, 1, 0, None) == -1
+    assert lib.mfs_eval_field(None, None, 1, None, 0, None, 0, None) == -1
+    assert lib.mfs_solve(None, None, 1, None, None, None, None) == -1
+    assert lib.mfs_scene_destroy(None) == 0
+    # null descriptor for build_S
+    kk = ctypes.c_int64(0)
+    assert lib.mfs_build_S(None, None, None, ctypes.byref(kk), None, None, None) == -1
+    # descriptor with n > m
+    pts = np.zeros((4, 2))
+    d = mfs.ShapeDesc(dim=2, kappa=1.0, colloc=pts.ctypes.data, m=2, src=pts.ctypes.data, n=3,
+                      proxy=pts.ctypes.data, p=4, eqpts=pts.ctypes.data, k=2, eps_skel=1e-10, eps_ls=1e-13, k_cap=0)
+    assert lib.mfs_build_S(ctypes.byref(d), ctypes.c_void_p(1), None, ctypes.byref(kk), None, None, None) == -1
+
+
+def test_timing_interface_without_device(lib):
+    assert lib.mfs_timing_enable(1) == 0
+    ms, n, pairs = mfs.timing_read(mfs.MFS_KERNEL_PAIR_F32)
+    assert (ms, n, pairs) == (0.0, 0, 0.0)
+    assert lib.mfs_timing_enable(0) == 0

@@ -314,3 +314,23 @@ def test_invalid_arguments_are_rejected(mfs):
                   [gsc._S_hold[0][0]])
     with pytest.raises(mfs.MfsError):
         mfs.Scene(2, -1.0, np.array([0], np.int32), np.zeros((1, 2)), [sc.shapes[0].eqpts], [gsc._S_hold[0][0]])
+
+
+def test_solve_warm_start_resumes(mfs):
+    """use_x0: from the converged solution no iteration is needed; from a partial solve (iteration
+    cap) the resumed solve reaches the same answer as an uninterrupted one."""
+    torch = _torch()
+    sc = SMALL_SCENES["starfish32"]()
+    gsc, Ss = _scene_with_oracle_S(mfs, sc)
+    v = torch.empty((1, gsc.N), dtype=torch.complex128, device="cuda")
+    mfs.plane_wave(gsc, sc.directions, v)
+    q_full = torch.empty_like(v)
+    mfs.solve(gsc, v, q_full, tol=1e-10, restart=500, prec=mfs.MFS_FP64)
+    q = torch.empty_like(v)
+    part = mfs.solve(gsc, v, q, tol=1e-10, restart=500, maxit=20, prec=mfs.MFS_FP64, raise_on_noconv=False)
+    assert part["status"] == "MFS_ERR_NOCONV" and part["relres_max"] > 1e-10
+    res = mfs.solve(gsc, v, q, tol=1e-10, restart=500, prec=mfs.MFS_FP64, use_x0=True)
+    assert res["relres_max"] <= 1e-10
+    assert rel_err(q.cpu().numpy(), q_full.cpu().numpy()) < 1e-8
+    again = mfs.solve(gsc, v, q, tol=1e-10, restart=500, prec=mfs.MFS_FP64, use_x0=True)
+    assert again["n_matvec64"] == 1 and again["relres_max"] <= 1e-10  # residual check only
