@@ -312,6 +312,8 @@ mfs_status mfs_scene_create(int32_t dim, double kappa, int64_t T, const int32_t*
   d.S64 = static_cast<const void* const*>(sc->S64_tab.p);
   d.S32 = static_cast<const void* const*>(sc->S32_tab.p);
   d.offbody_pairs = (double)N * (double)N - same_body_pairs;
+  d.all_k_mult16 = true;
+  for (int s2 = 0; s2 < n_shapes; ++s2) d.all_k_mult16 = d.all_k_mult16 && (k_of_shape[s2] % 16 == 0);
   *out = sc;
   return MFS_OK;
 }

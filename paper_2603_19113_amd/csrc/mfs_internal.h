@@ -49,6 +49,7 @@ struct SceneDev {
   const void* const* S64;         // [n_shapes] device pointers (complex128, col-major)
   const void* const* S32;         // [n_shapes] device pointers (complex64) or null
   double offbody_pairs;           // N^2 - sum_tau k_tau^2
+  bool all_k_mult16;              // every shape has a multiple of 16 points (matrix-core path)
 };
 
 // ------------------------------------------------------- kernel launchers ---
@@ -56,6 +57,7 @@ struct SceneDev {
 // same-body exclusion) or arbitrary FP64 targets (field evaluation, no exclusion).  Results
 // are per-source-chunk partial sums, partial[c][r][M], which the consumer adds in chunk order.
 int pair_chunks_for(int64_t n_sources, int64_t n_targets, int tpt);
+bool ghat_uses_mfma(const SceneDev& s, int R);
 
 hipError_t launch_ghat_f32(const SceneDev& s, const c64* q, int R, c64* partial, int nchunks,
                            hipStream_t st);

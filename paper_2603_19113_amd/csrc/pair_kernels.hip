@@ -496,6 +496,153 @@ int pair_chunks_for(int64_t n_sources, int64_t n_targets, int tpt) {
 
 static const double kZero3[3] = {0.0, 0.0, 0.0};
 
+// ---------------------------------------------------------------------------
+// Many right-hand sides: T = G_hat Q, Q [R][N], on the matrix cores.
+//
+// A block of 4 waves owns 64 targets and 64 right-hand sides.  Sources are taken 16 at a time:
+//   * the block stages the charge tile Q(16 sources x 64 RHS) in LDS, transposed so that the
+//     B operand of the MFMA is read without bank conflicts;
+//   * each wave evaluates phi for its 16 targets x 16 sources with the same body-centre phase
+//     split as the single-RHS kernel, directly in the A-operand layout of
+//     v_mfma_f32_16x16x4f32 (lane l holds row l%16, k = l/16), so phi never goes through LDS;
+//   * the complex product is four real MFMAs per (k-step, 16-RHS block):
+//     Tr += Gr Qr - Gi Qi, Ti += Gr Qi + Gi Qr.
+// FP32 MFMA accumulators are added into FP64 every 16 tiles (256 sources).  Requires every body
+// to hold a multiple of 16 points, so that a 16-source tile lies in one body.
+// ---------------------------------------------------------------------------
+typedef float v4f __attribute__((ext_vector_type(4)));
+constexpr int kMfmaTargets = 64;   // per block (16 per wave)
+constexpr int kMfmaRhs = 64;       // per block (4 blocks of 16)
+constexpr int kMfmaSrc = 16;       // sources per tile
+constexpr int kMfmaFlush = 16;     // tiles between FP64 flushes
+constexpr int kMfmaMinRhs = 8;     // fewer right-hand sides use the VALU kernel
+
+template <int DIM>
+__global__ __launch_bounds__(256) void ghat_mfma_kernel(
+    BodyPhaseConsts k, const float* __restrict__ l0, const float* __restrict__ l1, const float* __restrict__ l2,
+    const float* __restrict__ lsq, const double* __restrict__ cen, const int32_t* __restrict__ body_of,
+    const c64* __restrict__ q, int64_t N, int R, int64_t chunk_len, c64* __restrict__ partial) {
+  __shared__ c64 qt[kMfmaSrc][kMfmaRhs];  // transposed charge tile
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t tbase = (int64_t)blockIdx.x * kMfmaTargets + 16 * wave;
+  const int r0 = blockIdx.z * kMfmaRhs;
+  const int64_t c0 = (int64_t)blockIdx.y * chunk_len;
+  const int64_t c1 = min(N, c0 + chunk_len);
+
+  // target of this lane in the A layout
+  const int64_t tg = tbase + (lane & 15);
+  const int64_t tgc = tg < N ? tg : N - 1;
+  float lt[DIM];
+  lt[0] = l0[tgc];
+  lt[1] = l1[tgc];
+  if constexpr (DIM == 3) lt[2] = l2[tgc];
+  const int tb = tg < N ? body_of[tgc] : -1;
+  double ct[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) ct[d] = cen[(int64_t)body_of[tgc] * DIM + d];
+
+  v4f accR[4], accI[4];
+  double sumR[4][4], sumI[4][4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    accR[b] = v4f{0.f, 0.f, 0.f, 0.f};
+    accI[b] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sumR[b][i] = sumI[b][i] = 0.0;
+  }
+  int cur_sb = -1;
+  float A = 0.f, D = 0.f, D2 = 0.f, ph0 = 0.f, P[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) P[d] = 0.f;
+
+  int tiles = 0;
+  for (int64_t j0 = c0; j0 < c1; j0 += kMfmaSrc) {
+    // stage Q(j0 .. j0+15, r0 .. r0+63), transposed
+    {
+      const int rr = threadIdx.x >> 2;        // 0..63
+      const int sg = (threadIdx.x & 3) * 4;   // 0, 4, 8, 12
+      const int r = r0 + rr;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) qt[sg + u][rr] = r < R ? q[(int64_t)r * N + j0 + sg + u] : c64{0.f, 0.f};
+    }
+    // per (target, source body) quantities, recomputed when the tile's body changes
+    const int sb = body_of[j0];
+    if (sb != cur_sb) {
+      cur_sb = sb;
+      double dd2 = 0.0;
+      float Ai = 0.f;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const double dc = ct[d] - cen[(int64_t)sb * DIM + d];
+        dd2 = fma(dc, dc, dd2);
+        const float dcf = (float)dc;
+        Ai = fmaf(lt[d], lt[d] + 2.0f * dcf, Ai);
+        P[d] = -2.0f * (lt[d] + dcf);
+      }
+      const double dd = sqrt(dd2);
+      const double ph = dd * k.kappa_rev64;
+      A = Ai;
+      D = (float)dd;
+      D2 = (float)dd2;
+      ph0 = (float)(ph - floor(ph)) - (DIM == 2 ? 0.125f : 0.0f);
+    }
+    // phi in the A layout: k-step s, source j0 + 4 s + lane / 16
+    float gr[4], gi[4];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int64_t j = j0 + 4 * st + (lane >> 4);
+      float u = A + lsq[j];
+      u = fmaf(P[0], l0[j], u);
+      u = fmaf(P[1], l1[j], u);
+      if constexpr (DIM == 3) u = fmaf(P[2], l2[j], u);
+      float pr, pi;
+      bp_phi<DIM>(k, u, D, D2, ph0, pr, pi);
+      const bool same = tb == sb;
+      gr[st] = same ? 0.f : pr;
+      gi[st] = same ? 0.f : pi;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const float ngi = -gi[st];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const c64 qq = qt[4 * st + (lane >> 4)][16 * b + (lane & 15)];
+        accR[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr[st], qq.re, accR[b], 0, 0, 0);
+        accR[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ngi, qq.im, accR[b], 0, 0, 0);
+        accI[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr[st], qq.im, accI[b], 0, 0, 0);
+        accI[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(gi[st], qq.re, accI[b], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+    if (++tiles == kMfmaFlush) {
+      tiles = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          sumR[b][i] += (double)accR[b][i];
+          sumI[b][i] += (double)accI[b][i];
+          accR[b][i] = 0.f;
+          accI[b][i] = 0.f;
+        }
+    }
+  }
+  // output layout of the 16x16 MFMA: lane l, register i -> row 4 (l / 16) + i, column l % 16
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int r = r0 + 16 * b + (lane & 15);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t t = tbase + 4 * (lane >> 4) + i;
+      if (r < R && t < N)
+        partial[((int64_t)blockIdx.y * R + r) * N + t] =
+            c64{(float)(sumR[b][i] + (double)accR[b][i]), (float)(sumI[b][i] + (double)accI[b][i])};
+    }
+  }
+}
+
 static BodyPhaseConsts make_bodyphase(double kappa) {
   BodyPhaseConsts k{};
   const double two_pi = 2.0 * M_PI;
@@ -529,8 +676,23 @@ static hipError_t launch_bodyphase(const SceneDev& s, const c64* q, int R, c64* 
   return hipGetLastError();
 }
 
+template <int DIM>
+static hipError_t launch_mfma(const SceneDev& s, const c64* q, int R, c64* partial, int nchunks, hipStream_t st) {
+  int64_t chunk_len = (s.N + nchunks - 1) / nchunks;
+  chunk_len = (chunk_len + kMfmaSrc - 1) / kMfmaSrc * kMfmaSrc;
+  dim3 grid((unsigned)((s.N + kMfmaTargets - 1) / kMfmaTargets), (unsigned)nchunks,
+            (unsigned)((R + kMfmaRhs - 1) / kMfmaRhs));
+  hipLaunchKernelGGL((ghat_mfma_kernel<DIM>), grid, dim3(256), 0, st, make_bodyphase(s.kappa), s.l32[0], s.l32[1],
+                     s.l32[2], s.lsq32, s.centres, s.body_of, q, s.N, R, chunk_len, partial);
+  return hipGetLastError();
+}
+
+bool ghat_uses_mfma(const SceneDev& s, int R) { return R >= kMfmaMinRhs && s.all_k_mult16; }
+
 hipError_t launch_ghat_f32(const SceneDev& s, const c64* q, int R, c64* partial, int nchunks, hipStream_t st) {
   if (s.N <= 0) return hipSuccess;
+  if (ghat_uses_mfma(s, R)) return s.dim == 2 ? launch_mfma<2>(s, q, R, partial, nchunks, st)
+                                              : launch_mfma<3>(s, q, R, partial, nchunks, st);
   if (s.dim == 2) {
     if (R == 1) return launch_bodyphase<2, 1>(s, q, R, partial, nchunks, st);
     if (R == 2) return launch_bodyphase<2, 2>(s, q, R, partial, nchunks, st);
