@@ -95,6 +95,77 @@ def cpu_baseline(sc, seconds: float) -> dict:
                       f"{pairs:.3e} pairs in {t_used:.1f} s)"}
 
 
+def serve(args, w, torch) -> int:
+    """Poisson request stream through the serving engine (continuous admission by HBM footprint)."""
+    from paper_2603_19113_amd.serve import Engine, GpuExecutor, footprint_bytes, latency_stats, replay, restart_for
+
+    specs = w.serving.request_stream(args.serve, rate=args.rate, seed=20260318)
+    fps = [footprint_bytes(s.scene.N, s.scene.T, s.scene.R, s.scene.dim,
+                           restart_for(s.scene.T, s.scene.kappa, s.scene.dim)) for s in specs]
+    budget = int(0.8 * torch.cuda.get_device_properties(0).total_memory)
+    ex = GpuExecutor(args.slots, tol=args.tol, keep_solution=False)
+    # warm the S library (one build per shape and wavenumber), untimed
+    for s in specs:
+        for key, sh in zip(s.shape_keys, s.scene.shapes):
+            ex.S(s.scene.dim, key, sh, s.scene.kappa, ex.streams[0])
+    torch.cuda.synchronize()
+    eng = Engine(ex, budget=budget, slots=args.slots)
+    t0 = time.perf_counter()
+    tickets = replay(eng, specs, fps)
+    wall = time.perf_counter() - t0
+    eng.close()
+    st = latency_stats(tickets)
+    fails = [t.error for t in tickets if t.error]
+    worst = max((t.result["info"]["relres_max"] for t in tickets if not t.error), default=float("nan"))
+    out = {"metric": "serving: p50/p99 latency and solves/s", "n_requests": len(specs), "rate_per_s": args.rate,
+           "slots": args.slots, "hbm_budget_bytes": budget, "wall_s": wall, **st, "relres_max": worst,
+           "errors": fails[:3], "tol": args.tol,
+           "requests": "2D (disk, ellipse, starfish, kite; kappa 5/10/20) and 3D (sphere, ellipsoid; kappa 3/5), "
+                       "4..64 bodies log-uniform, 1..16 directions"}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def compare(args, sc, mfs, torch, np) -> int:
+    """Mixed-precision batched solve vs plain FP64 GMRES, one right-hand side at a time."""
+    built = [mfs.build_S(s, sc.kappa) for s in sc.shapes]
+    scene = mfs.Scene(sc.dim, sc.kappa, sc.shape_of, sc.centres, [s.eqpts for s in sc.shapes],
+                      [b.S64 for b in built], [b.S32 for b in built])
+    R = sc.R
+    v = torch.empty((R, scene.N), dtype=torch.complex128, device="cuda")
+    mfs.plane_wave(scene, sc.directions, v)
+    q_mixed = torch.empty_like(v)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info_m = mfs.solve(scene, v, q_mixed, tol=args.tol, maxit=60000, restart=args.restart, max_refine=20,
+                       inner_tol=args.inner_tol, prec=mfs.MFS_MIXED, verbose=min(args.verbose, 1))
+    t_mixed = time.perf_counter() - t0
+    log(f"[compare] mixed, {R} RHS together: {t_mixed:.2f} s  {info_m}")
+    q64 = torch.empty_like(v)
+    t_fp64, it64, rel64 = 0.0, 0, 0.0
+    for r in range(R):
+        vr = v[r:r + 1].contiguous()
+        qr = torch.empty_like(vr)
+        t0 = time.perf_counter()
+        info = mfs.solve(scene, vr, qr, tol=args.tol, maxit=60000, restart=args.restart, prec=mfs.MFS_FP64,
+                         verbose=0)
+        t_fp64 += time.perf_counter() - t0
+        it64 += info["n_matvec64"]
+        rel64 = max(rel64, info["relres_max"])
+        q64[r].copy_(qr[0])
+        log(f"[compare] fp64 rhs {r}: {info['t_total_s']:.2f} s  {info['n_matvec64']} FP64 operator applications")
+    diff = float(torch.linalg.norm(q_mixed - q64) / torch.linalg.norm(q64))
+    out = {"workload": sc.name, "N": scene.N, "T": sc.T, "R": R, "tol": args.tol,
+           "mixed_batched": {"seconds": t_mixed, "relres_max": info_m["relres_max"],
+                             "fp32_operator_applications": info_m["n_matvec32"],
+                             "fp64_operator_applications": info_m["n_matvec64"]},
+           "fp64_single_rhs": {"seconds": t_fp64, "relres_max": rel64, "fp64_operator_applications": it64},
+           "speedup": t_fp64 / t_mixed, "solution_rel_diff": diff}
+    print(json.dumps(out), flush=True)
+    scene.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +186,14 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--verbose", type=int, default=2, help="solver progress lines on stderr")
+    ap.add_argument("--serve", type=int, default=0,
+                    help="instead of the benchmark line: replay this many Poisson-arriving requests through "
+                         "the serving engine and report p50/p99 latency and solves/s")
+    ap.add_argument("--rate", type=float, default=1.0, help="--serve: mean arrivals per second")
+    ap.add_argument("--slots", type=int, default=4, help="--serve: concurrent requests")
+    ap.add_argument("--compare", action="store_true",
+                    help="instead of the benchmark line: time the mixed-precision (batched) solve against the "
+                         "plain FP64 single-RHS form (each right-hand side solved alone) on the same scene")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -130,6 +209,8 @@ def main() -> int:
 
     mfs.load()
     torch.cuda.set_device(0)
+    if args.serve > 0:
+        return serve(args, w, torch)
     sc = w.make_scene(args.workload, T=args.bodies)
     R = sc.R
     dirs = sc.directions
@@ -169,6 +250,9 @@ def main() -> int:
         torch.cuda.synchronize()
         scene.close()
         return info
+
+    if args.compare:
+        return compare(args, sc, mfs, torch, np)
 
     for i in range(args.warmup):
         t0 = time.perf_counter()

@@ -1,10 +1,12 @@
 // C ABI of libmfs: scenes, the operator I + S G_hat (eq. mbody2), field evaluation and the
 // GMRES / GMRES-IR driver.  Kernels live in pair_kernels.hip, sapply.hip, krylov.hip, lsq.hip.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -63,7 +65,9 @@ struct TimingRecord {
   double pairs;
   hipEvent_t e0, e1;
 };
-static bool g_timing_on = false;
+// The record list is shared by every calling thread (the serving loop calls from one thread per slot).
+static std::atomic<bool> g_timing_on{false};
+static std::mutex g_timing_mu;
 static std::vector<TimingRecord> g_timing;
 
 TimedLaunch::TimedLaunch(int k, double p, hipStream_t s) : kind(k), pairs(p), st(s), ev0(nullptr), ev1(nullptr) {
@@ -82,10 +86,12 @@ TimedLaunch::TimedLaunch(int k, double p, hipStream_t s) : kind(k), pairs(p), st
 TimedLaunch::~TimedLaunch() {
   if (!ev0) return;
   (void)hipEventRecord(static_cast<hipEvent_t>(ev1), st);
+  std::lock_guard<std::mutex> lk(g_timing_mu);
   g_timing.push_back(TimingRecord{kind, pairs, static_cast<hipEvent_t>(ev0), static_cast<hipEvent_t>(ev1)});
 }
 
 static void timing_clear() {
+  std::lock_guard<std::mutex> lk(g_timing_mu);
   for (auto& r : g_timing) {
     (void)hipEventDestroy(r.e0);
     (void)hipEventDestroy(r.e1);
@@ -312,6 +318,12 @@ mfs_status mfs_scene_create(int32_t dim, double kappa, int64_t T, const int32_t*
   d.S64 = static_cast<const void* const*>(sc->S64_tab.p);
   d.S32 = static_cast<const void* const*>(sc->S32_tab.p);
   d.offbody_pairs = (double)N * (double)N - same_body_pairs;
+  d.rho_max = 0.0;
+  for (size_t i = 0; i < tmpl.size() / dim; ++i) {
+    double r2 = 0.0;
+    for (int dd = 0; dd < dim; ++dd) r2 += tmpl[i * dim + dd] * tmpl[i * dim + dd];
+    d.rho_max = std::max(d.rho_max, std::sqrt(r2));
+  }
   d.all_k_mult16 = true;
   for (int s2 = 0; s2 < n_shapes; ++s2) d.all_k_mult16 = d.all_k_mult16 && (k_of_shape[s2] % 16 == 0);
   *out = sc;
@@ -668,6 +680,7 @@ mfs_status mfs_timing_enable(int32_t on) {
 mfs_status mfs_timing_read(mfs_kernel_kind kind, double* total_ms, int64_t* launches, double* pairs) {
   double ms = 0.0, pr = 0.0;
   int64_t n = 0;
+  std::lock_guard<std::mutex> lk(g_timing_mu);
   for (auto& r : g_timing) {
     if (r.kind != (int)kind) continue;
     MFS_HIP_TRY(hipEventSynchronize(r.e1));

@@ -50,6 +50,7 @@ struct SceneDev {
   const void* const* S32;         // [n_shapes] device pointers (complex64) or null
   double offbody_pairs;           // N^2 - sum_tau k_tau^2
   bool all_k_mult16;              // every shape has a multiple of 16 points (matrix-core path)
+  double rho_max;                 // largest |x_hat - c_body| over all shapes
 };
 
 // ------------------------------------------------------- kernel launchers ---

@@ -238,6 +238,7 @@ struct BodyPhaseConsts {
   // A&S branches
   Phi2DConstsF32 as;
   double kappa_rev64;
+  float far_D;       // centre distance beyond which every pair of two bodies has z >= 12
 };
 
 template <int DIM, int TPT, int RT>
@@ -252,7 +253,7 @@ struct BPAcc {
   float sr_[TPT][RT], si_[TPT][RT];  // FP32 partial sums over the current source body
 };
 
-template <int DIM>
+template <int DIM, bool FAR_ONLY = false>
 __device__ __forceinline__ void bp_phi(const BodyPhaseConsts& k, float u, float D, float D2, float ph0,
                                        float& pr, float& pi) {
   const float r2 = D2 + u;
@@ -266,7 +267,7 @@ __device__ __forceinline__ void bp_phi(const BodyPhaseConsts& k, float u, float 
     pr = a * __builtin_amdgcn_cosf(rev);
     pi = a * __builtin_amdgcn_sinf(rev);
   } else {
-    if (r >= k.r_far) {
+    if (FAR_ONLY || r >= k.r_far) {
       const float w2 = rinv * rinv;
       const float m = fmaf(fmaf(k.m2, w2, k.m1), w2, k.m0);
       const float th = rinv * fmaf(fmaf(k.p2, w2, k.p1), w2, k.p0);
@@ -301,7 +302,7 @@ __device__ __forceinline__ void bp_phi(const BodyPhaseConsts& k, float u, float 
   }
 }
 
-template <int DIM, int TPT, int RT, bool MASK>
+template <int DIM, int TPT, int RT, bool MASK, bool FAR_ONLY = false>
 __device__ __forceinline__ void bp_source(BPAcc<DIM, TPT, RT>& a, const BodyPhaseConsts& k, int sb,
                                           const float* __restrict__ l0, const float* __restrict__ l1,
                                           const float* __restrict__ l2, const float* __restrict__ lsq,
@@ -326,7 +327,7 @@ __device__ __forceinline__ void bp_source(BPAcc<DIM, TPT, RT>& a, const BodyPhas
 #pragma unroll
     for (int d = 0; d < DIM; ++d) u = fmaf(a.P[i][d], ls[d], u);
     float pr, pi;
-    bp_phi<DIM>(k, u, a.D[i], a.D2[i], a.ph0[i], pr, pi);
+    bp_phi<DIM, FAR_ONLY>(k, u, a.D[i], a.D2[i], a.ph0[i], pr, pi);
     if constexpr (MASK) {
       const bool same = a.tb[i] == sb;
       pr = same ? 0.0f : pr;
@@ -409,8 +410,20 @@ __global__ __launch_bounds__(kBlock) void ghat_bodyphase_kernel(
         for (int rr = 0; rr < RT; ++rr) a.sr_[i][rr] = a.si_[i][rr] = 0.0f;
       }
       const bool masked = sb >= bmin && sb <= bmax;
+      // every pair of this wave and source body in the far regime (z >= 12): branch-free loop
+      bool far_lane = true;
+#pragma unroll
+      for (int i = 0; i < TPT; ++i) far_lane = far_lane && (a.tb[i] < 0 || a.D[i] >= k.far_D);
+      const bool far_all = DIM == 2 && !masked && __all(far_lane);
       int64_t j = j0;
-      if (!masked) {
+      if (far_all) {
+        for (; j + kUnroll <= j1; j += kUnroll) {
+#pragma unroll
+          for (int uu = 0; uu < kUnroll; ++uu)
+            bp_source<DIM, TPT, RT, false, true>(a, k, sb, l0, l1, l2, lsq, q, N, R, r0, j + uu);
+        }
+        for (; j < j1; ++j) bp_source<DIM, TPT, RT, false, true>(a, k, sb, l0, l1, l2, lsq, q, N, R, r0, j);
+      } else if (!masked) {
         for (; j + kUnroll <= j1; j += kUnroll) {
 #pragma unroll
           for (int uu = 0; uu < kUnroll; ++uu)
@@ -643,7 +656,7 @@ __global__ __launch_bounds__(256) void ghat_mfma_kernel(
   }
 }
 
-static BodyPhaseConsts make_bodyphase(double kappa) {
+static BodyPhaseConsts make_bodyphase(double kappa, double rho_max) {
   BodyPhaseConsts k{};
   const double two_pi = 2.0 * M_PI;
   k.kappa_rev = (float)(kappa / two_pi);
@@ -659,6 +672,8 @@ static BodyPhaseConsts make_bodyphase(double kappa) {
   k.p1 = (float)(25.0 / (384.0 * k2 * kappa) / two_pi);
   k.p2 = (float)(-1073.0 / (5120.0 * k2 * k2 * kappa) / two_pi);
   k.as = make_phi2d_f32(kappa);
+  // |x_i - x_j| >= D - 2 rho_max, so D >= 12/kappa + 2 rho_max (plus rounding slack) is far for all pairs
+  k.far_D = (float)((12.0 / kappa + 2.0 * rho_max) * (1.0 + 1e-5) + 1e-6);
   return k;
 }
 
@@ -670,7 +685,7 @@ static hipError_t launch_bodyphase(const SceneDev& s, const c64* q, int R, c64* 
   chunk_len = (chunk_len + kUnroll - 1) / kUnroll * kUnroll;
   const int64_t per_block = (int64_t)kBlock * TPT;
   dim3 grid((unsigned)((s.N + per_block - 1) / per_block), (unsigned)nchunks, (unsigned)((R + RT - 1) / RT));
-  hipLaunchKernelGGL((ghat_bodyphase_kernel<DIM, TPT, RT>), grid, dim3(kBlock), 0, st, make_bodyphase(s.kappa),
+  hipLaunchKernelGGL((ghat_bodyphase_kernel<DIM, TPT, RT>), grid, dim3(kBlock), 0, st, make_bodyphase(s.kappa, s.rho_max),
                      s.l32[0], s.l32[1], s.l32[2], s.lsq32, s.centres, s.body_of, s.body_ptr, q, s.N, R, chunk_len,
                      partial);
   return hipGetLastError();
@@ -682,7 +697,7 @@ static hipError_t launch_mfma(const SceneDev& s, const c64* q, int R, c64* parti
   chunk_len = (chunk_len + kMfmaSrc - 1) / kMfmaSrc * kMfmaSrc;
   dim3 grid((unsigned)((s.N + kMfmaTargets - 1) / kMfmaTargets), (unsigned)nchunks,
             (unsigned)((R + kMfmaRhs - 1) / kMfmaRhs));
-  hipLaunchKernelGGL((ghat_mfma_kernel<DIM>), grid, dim3(256), 0, st, make_bodyphase(s.kappa), s.l32[0], s.l32[1],
+  hipLaunchKernelGGL((ghat_mfma_kernel<DIM>), grid, dim3(256), 0, st, make_bodyphase(s.kappa, s.rho_max), s.l32[0], s.l32[1],
                      s.l32[2], s.lsq32, s.centres, s.body_of, q, s.N, R, chunk_len, partial);
   return hipGetLastError();
 }

@@ -1,0 +1,228 @@
+"""Request loop for scattering solves on one GPU: continuous admission by HBM footprint.
+
+Requests (scenes with one or more incident directions) arrive over time.  The engine keeps a FIFO
+queue and a set of slots; the head of the queue is admitted as soon as a slot is free and its
+estimated device footprint fits in the HBM budget next to the requests already running.  Each slot
+runs its request on its own HIP stream (mixed-precision GMRES-IR through the C ABI), so the work
+of admitted requests overlaps on the device, and finished requests free their footprint for the
+queue at once.  Scattering matrices are built once per (shape, wavenumber) and stay resident in a
+shared library.  Results do not depend on what else runs: every kernel is deterministic and a
+request's arithmetic never mixes with another's.
+
+The admission policy and the slot/queue machinery are plain Python and take the executor as a
+parameter, so they run on the CPU with a fake executor and a virtual clock.
+"""
+
+from __future__ import annotations
+
+import collections
+import threading
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+# ------------------------------------------------------------------ policy ---
+def footprint_bytes(N: int, T: int, R: int, dim: int, restart: int, n_targets: int = 0) -> int:
+    """Device bytes a request holds while it runs (scene tables, pair partial sums, Krylov basis and
+    Hessenberg, solver vectors, caller tensors), mirroring the library's allocations."""
+    scene = N * (8 * dim + 4 * dim + 4 * dim + 4 + 4 + 4) + T * (8 + 4 + 8 * dim)
+    partial = 16 * R * N * 16                      # at most 16 source chunks, complex128
+    q32 = R * N * 8
+    nblk = (N + 1023) // 1024
+    krylov = (restart + 1) * R * N * 16 + R * restart * (restart + 1) * 16 + 2 * R * (restart + 1) * nblk * 8 \
+        + 6 * R * (restart + 1) * 16
+    vecs = 3 * R * N * 16
+    caller = 2 * R * N * 16 + R * max(n_targets, 1) * 16
+    return int(scene + partial + q32 + krylov + vecs + caller)
+
+
+def restart_for(T: int, kappa: float, dim: int, cap: int = 4000) -> int:
+    """Krylov basis size: GMRES on these systems needs about 6 steps per body at kappa = 10 in 2D
+    (measured); keep room for that so a request rarely restarts."""
+    est = int(8 * T * max(kappa, 3.0) / 10.0) + 200
+    return max(64, min(cap, est))
+
+
+class Admission:
+    """FIFO admission by footprint: the head enters when a slot is free and it fits the budget."""
+
+    def __init__(self, budget: int, slots: int):
+        self.budget = int(budget)
+        self.slots = int(slots)
+        self.used = 0
+        self.running = 0
+        self.peak_used = 0
+
+    def fits(self, fp: int) -> bool:
+        if fp > self.budget:
+            raise ValueError(f"request needs {fp} bytes, more than the whole budget {self.budget}")
+        return self.running < self.slots and self.used + fp <= self.budget
+
+    def admit(self, fp: int):
+        self.used += fp
+        self.running += 1
+        self.peak_used = max(self.peak_used, self.used)
+
+    def release(self, fp: int):
+        self.used -= fp
+        self.running -= 1
+
+
+# ------------------------------------------------------------------ engine ---
+@dataclass
+class Ticket:
+    rid: int
+    arrival: float
+    footprint: int
+    start: float = float("nan")
+    finish: float = float("nan")
+    result: dict = field(default_factory=dict)
+    error: str | None = None
+    done: threading.Event = field(default_factory=threading.Event)
+
+    @property
+    def latency(self) -> float:
+        return self.finish - self.arrival
+
+
+class Engine:
+    """Slots x streams, one dispatcher.  executor(spec, slot) -> dict runs one request."""
+
+    def __init__(self, executor, budget: int, slots: int = 4, clock=time.monotonic):
+        self.executor = executor
+        self.policy = Admission(budget, slots)
+        self.clock = clock
+        self.queue: collections.deque = collections.deque()
+        self.lock = threading.Condition()
+        self.free_slots = list(range(slots))
+        self.closed = False
+        self.tickets: list[Ticket] = []
+        self.dispatcher = threading.Thread(target=self._dispatch, daemon=True)
+        self.dispatcher.start()
+
+    def submit(self, spec, footprint: int, arrival: float | None = None) -> Ticket:
+        t = Ticket(rid=spec.rid, arrival=self.clock() if arrival is None else arrival, footprint=footprint)
+        with self.lock:
+            if footprint > self.policy.budget:
+                raise ValueError(f"request {spec.rid} needs {footprint} bytes, over the budget")
+            self.queue.append((spec, t))
+            self.tickets.append(t)
+            self.lock.notify_all()
+        return t
+
+    def _dispatch(self):
+        while True:
+            with self.lock:
+                while not self.closed and not (self.queue and self.policy.fits(self.queue[0][1].footprint)):
+                    self.lock.wait()
+                if self.closed and not self.queue:
+                    return
+                if not self.queue:
+                    continue
+                spec, t = self.queue.popleft()
+                self.policy.admit(t.footprint)
+                slot = self.free_slots.pop()
+            threading.Thread(target=self._run, args=(spec, t, slot), daemon=True).start()
+
+    def _run(self, spec, t: Ticket, slot: int):
+        t.start = self.clock()
+        try:
+            t.result = self.executor(spec, slot)
+        except Exception as e:  # a failed request frees its slot; the error is reported on its ticket
+            t.error = f"{type(e).__name__}: {e}"
+        t.finish = self.clock()
+        with self.lock:
+            self.policy.release(t.footprint)
+            self.free_slots.append(slot)
+            self.lock.notify_all()
+        t.done.set()
+
+    def drain(self, timeout: float | None = None) -> bool:
+        deadline = None if timeout is None else time.monotonic() + timeout
+        for t in list(self.tickets):
+            left = None if deadline is None else max(0.0, deadline - time.monotonic())
+            if not t.done.wait(left):
+                return False
+        return True
+
+    def close(self):
+        with self.lock:
+            self.closed = True
+            self.lock.notify_all()
+        self.dispatcher.join(timeout=5.0)
+
+
+def latency_stats(tickets) -> dict:
+    lat = np.array([t.latency for t in tickets if t.error is None])
+    if lat.size == 0:
+        return {"n": 0}
+    first = min(t.arrival for t in tickets)
+    last = max(t.finish for t in tickets)
+    return {"n": int(lat.size), "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "mean_s": float(lat.mean()), "solves_per_s": float(lat.size / max(last - first, 1e-9)),
+            "failed": sum(1 for t in tickets if t.error is not None)}
+
+
+# ------------------------------------------------------------- GPU executor ---
+class GpuExecutor:
+    """Runs one request through the C ABI on the slot's own stream.  S per (dim, shape, kappa) is
+    built once (FP64, on the GPU) and shared by every request that uses that shape."""
+
+    def __init__(self, slots: int, tol: float = 1e-8, inner_tol: float = 3e-6, keep_solution: bool = True):
+        import torch
+
+        from . import mfs
+
+        self.mfs = mfs
+        self.torch = torch
+        mfs.load()
+        self.streams = [torch.cuda.Stream() for _ in range(slots)]  # default priority
+        self.library: dict = {}
+        self.lib_lock = threading.Lock()
+        self.tol = tol
+        self.inner_tol = inner_tol
+        self.keep_solution = keep_solution
+
+    def S(self, dim, key, shape, kappa, stream):
+        k = (dim, key, float(kappa))
+        with self.lib_lock:
+            if k not in self.library:
+                self.library[k] = self.mfs.build_S(shape, kappa, stream=stream)
+            return self.library[k]
+
+    def __call__(self, spec, slot: int) -> dict:
+        torch, mfs = self.torch, self.mfs
+        sc = spec.scene
+        st = self.streams[slot]
+        with torch.cuda.stream(st):
+            built = [self.S(sc.dim, key, sh, sc.kappa, st) for key, sh in zip(spec.shape_keys, sc.shapes)]
+            scene = mfs.Scene(sc.dim, sc.kappa, sc.shape_of, sc.centres, [s.eqpts for s in sc.shapes],
+                              [b.S64 for b in built], [b.S32 for b in built])
+            R = sc.R
+            v = torch.empty((R, scene.N), dtype=torch.complex128, device="cuda")
+            mfs.plane_wave(scene, sc.directions, v, stream=st)
+            q = torch.empty_like(v)
+            restart = restart_for(sc.T, sc.kappa, sc.dim)
+            info = mfs.solve(scene, v, q, tol=self.tol, maxit=200000, restart=restart, max_refine=30,
+                             inner_tol=self.inner_tol, prec=mfs.MFS_MIXED, stream=st)
+            st.synchronize()
+            out = {"info": info, "N": scene.N, "T": sc.T, "R": R, "dim": sc.dim, "kappa": sc.kappa,
+                   "restart": restart}
+            if self.keep_solution:
+                out["qhat"] = q.cpu().numpy()
+            scene.close()
+        return out
+
+
+def replay(engine: Engine, specs, footprints, time_scale: float = 1.0):
+    """Submit requests at their (scaled) arrival times, then wait for all of them."""
+    t0 = time.monotonic()
+    for spec, fp in zip(specs, footprints):
+        delay = t0 + spec.arrival * time_scale - time.monotonic()
+        if delay > 0:
+            time.sleep(delay)
+        engine.submit(spec, fp)
+    engine.drain()
+    return engine.tickets

@@ -26,6 +26,7 @@ from .scenes import (  # noqa: F401
     plane_wave_directions_2d,
     far_targets,
 )
+from . import serving  # noqa: F401
 from .configs import (  # noqa: F401
     BASE_SEED,
     WorkloadConfig,
