@@ -96,32 +96,55 @@ def cpu_baseline(sc, seconds: float) -> dict:
 
 
 def serve(args, w, torch) -> int:
-    """Poisson request stream through the serving engine (continuous admission by HBM footprint)."""
-    from paper_2603_19113_amd.serve import Engine, GpuExecutor, footprint_bytes, latency_stats, replay, restart_for
+    """Poisson request stream through the serving engine: continuous admission by HBM footprint,
+    per-slot streams, batching of requests on one geometry, cached device memory.
 
-    specs = w.serving.request_stream(args.serve, rate=args.rate, seed=20260318)
-    fps = [footprint_bytes(s.scene.N, s.scene.T, s.scene.R, s.scene.dim,
-                           restart_for(s.scene.T, s.scene.kappa, s.scene.dim)) for s in specs]
+    The arrival rate is 0.7 x the sustained capacity measured on a calibration burst drawn from the
+    same generator (another seed), unless --rate is given."""
+    from paper_2603_19113_amd import mfs
+    from paper_2603_19113_amd.serve import Engine, GpuExecutor, latency_stats, replay, request_batching, \
+        request_footprint
+
+    gen = dict(t_min=args.serve_tmin, t_max=args.serve_tmax, p_sweep=args.p_sweep)
+    specs = w.serving.request_stream(args.serve, rate=1.0, seed=20260318, **gen)
+    cal = w.serving.request_stream(max(8, args.serve // 4), rate=1.0, seed=20260319, **gen)
     budget = int(0.8 * torch.cuda.get_device_properties(0).total_memory)
     ex = GpuExecutor(args.slots, tol=args.tol, keep_solution=False)
-    # warm the S library (one build per shape and wavenumber), untimed
-    for s in specs:
+    for s in cal + specs:  # the S library: one FP64 build per (shape, wavenumber), untimed
         for key, sh in zip(s.shape_keys, s.scene.shapes):
             ex.S(s.scene.dim, key, sh, s.scene.kappa, ex.streams[0])
     torch.cuda.synchronize()
-    eng = Engine(ex, budget=budget, slots=args.slots)
-    t0 = time.perf_counter()
-    tickets = replay(eng, specs, fps)
-    wall = time.perf_counter() - t0
-    eng.close()
+    batching = None if args.no_batching else request_batching()
+
+    def run(stream, time_scale):
+        eng = Engine(ex, budget=budget, slots=args.slots, batching=batching)
+        t0 = time.perf_counter()
+        tickets = replay(eng, stream, [request_footprint([s]) for s in stream], time_scale=time_scale)
+        wall = time.perf_counter() - t0
+        eng.close()
+        return tickets, wall
+
+    rate = args.rate
+    capacity = None
+    if rate <= 0.0:
+        tk, wall = run(cal, 0.0)  # burst: every calibration request queued at once
+        capacity = len(cal) / wall
+        rate = 0.7 * capacity
+        print(f"[serve] calibration: {len(cal)} requests in {wall:.2f} s -> capacity {capacity:.2f}/s, "
+              f"rate {rate:.2f}/s", file=sys.stderr, flush=True)
+    pool0 = mfs.pool_stats()
+    tickets, wall = run(specs, 1.0 / rate)
+    pool1 = mfs.pool_stats()
     st = latency_stats(tickets)
     fails = [t.error for t in tickets if t.error]
     worst = max((t.result["info"]["relres_max"] for t in tickets if not t.error), default=float("nan"))
-    out = {"metric": "serving: p50/p99 latency and solves/s", "n_requests": len(specs), "rate_per_s": args.rate,
-           "slots": args.slots, "hbm_budget_bytes": budget, "wall_s": wall, **st, "relres_max": worst,
-           "errors": fails[:3], "tol": args.tol,
-           "requests": "2D (disk, ellipse, starfish, kite; kappa 5/10/20) and 3D (sphere, ellipsoid; kappa 3/5), "
-                       "4..64 bodies log-uniform, 1..16 directions"}
+    out = {"metric": "serving: p50/p99 latency and solves/s", "n_requests": len(specs), "rate_per_s": rate,
+           "capacity_per_s": capacity, "slots": args.slots, "batching": batching is not None,
+           "hbm_budget_bytes": budget, "wall_s": wall, **st, "relres_max": worst, "errors": fails[:3],
+           "tol": args.tol, "pool_hits": pool1["hits"] - pool0["hits"], "pool_misses": pool1["misses"] - pool0["misses"],
+           "requests": f"2D (disk, ellipse, starfish, kite; kappa 5/10/20) and 3D (sphere, ellipsoid; kappa 3/5), "
+                       f"{args.serve_tmin}..{args.serve_tmax} bodies log-uniform, 1..16 directions, "
+                       f"{args.p_sweep:g} of requests revisit an earlier geometry"}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -189,8 +212,14 @@ def main() -> int:
     ap.add_argument("--serve", type=int, default=0,
                     help="instead of the benchmark line: replay this many Poisson-arriving requests through "
                          "the serving engine and report p50/p99 latency and solves/s")
-    ap.add_argument("--rate", type=float, default=1.0, help="--serve: mean arrivals per second")
+    ap.add_argument("--rate", type=float, default=0.0,
+                    help="--serve: mean arrivals per second (0: 0.7 x capacity from a calibration burst)")
     ap.add_argument("--slots", type=int, default=4, help="--serve: concurrent requests")
+    ap.add_argument("--serve-tmin", type=int, default=8, help="--serve: fewest bodies per request")
+    ap.add_argument("--serve-tmax", type=int, default=128, help="--serve: most bodies per request")
+    ap.add_argument("--p-sweep", type=float, default=0.3,
+                    help="--serve: share of requests that revisit an earlier geometry with new directions")
+    ap.add_argument("--no-batching", action="store_true", help="--serve: one solve per request")
     ap.add_argument("--compare", action="store_true",
                     help="instead of the benchmark line: time the mixed-precision (batched) solve against the "
                          "plain FP64 single-RHS form (each right-hand side solved alone) on the same scene")

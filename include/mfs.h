@@ -109,7 +109,8 @@ mfs_status mfs_build_S(const mfs_shape_desc* desc, void* S64_dev, void* S32_dev,
  * ------------------------------------------------------------------------------------------ */
 typedef struct mfs_scene mfs_scene;
 
-/* Create a scene.  Synchronous.
+/* Create a scene.  Synchronous; packing runs on a private stream of the calling thread and does
+ * not wait for work on other streams.
  *   dim, kappa      2 or 3; wavenumber > 0
  *   T               number of bodies >= 1
  *   shape_of        host int32[T], values in [0, n_shapes)
@@ -126,7 +127,10 @@ mfs_status mfs_scene_create(int32_t dim, double kappa, int64_t T, const int32_t*
                             const double* const* eq_template, const void* const* S64_dev,
                             const void* const* S32_dev, mfs_scene** out);
 
-/* Destroy a scene and free everything it allocated.  Synchronous (waits for the device). */
+/* Destroy a scene.  Its device blocks go back to the library's allocation cache, ordered after
+ * the work enqueued on the stream of the scene's latest call, so the call returns at once and
+ * does not wait for other streams.  Work on a different stream that still reads the scene must be
+ * complete before this call. */
 mfs_status mfs_scene_destroy(mfs_scene* scene);
 
 /* N (global unknowns), T, and device bytes the scene holds now.  Host outputs may be NULL. */
@@ -171,8 +175,9 @@ mfs_status mfs_apply(const mfs_scene* scene, const void* q_dev, void* y_dev, int
  *              x += d; repeated until ||b - A x|| / ||b|| <= tol (FP64 residual) or max_refine.
  * Each right-hand side has its own Krylov space; the R operator applications of one iteration
  * share one pair-kernel launch.  Orthogonalisation is classical Gram-Schmidt with a second pass
- * where the first one cancelled (||w'|| < ||w|| / sqrt 2).  The stopping test is ||b - A x||_2 / ||b||_2 <= tol per column,
- * checked with the FP64 operator before returning.  Synchronous.
+ * where the first one cancelled (||w'|| < 0.2 ||w||).  The stopping test is
+ * ||b - A x||_2 / ||b||_2 <= tol per column, checked with the FP64 operator before returning.
+ * Synchronous.
  *   vhat_dev  device complex128 [R][N]: Dirichlet data at x_hat (b = S vhat is formed inside)
  *   qhat_dev  device complex128 [R][N]: solution (output; input too when use_x0 = 1)
  *   info      host, may be NULL. */
@@ -191,6 +196,11 @@ typedef struct {
                         early steps need the accurate operator); 0 = FP32 throughout */
   int32_t use_x0;    /* 1: qhat_dev holds an initial guess (warm start, or resuming a checkpointed
                         solve: the FP64 residual is recomputed first); 0: x0 = 0 */
+  int32_t use_graph; /* 1: replay the Gram-Schmidt, Givens and basis-update launches of each Arnoldi
+                        step from HIP graphs (one captured per 64 steps, the step index read from
+                        device memory); the operator application stays a direct launch.  Same
+                        arithmetic as 0, fewer launches: for small systems, where launch cost
+                        dominates.  0: direct launches */
 } mfs_solve_opts;
 
 typedef struct {
@@ -228,6 +238,31 @@ mfs_status mfs_timing_enable(int32_t on);
  * launches, and algorithmic pair evaluations (off-body pairs times right-hand sides).  Waits for
  * the recorded events.  Host outputs may be NULL. */
 mfs_status mfs_timing_read(mfs_kernel_kind kind, double* total_ms, int64_t* launches, double* pairs);
+
+/* ------------------------------------------------------------------------------------------
+ * Device allocation cache.  Scene tables, pair partial sums and Krylov bases are drawn from a
+ * process-wide cache of device blocks: a freed block stays on its device and is reused by the next
+ * request whose size it fits (at most twice the size asked for), with the new owner's stream
+ * ordered after the previous owner's last use.  A request loop therefore keeps its Krylov bases
+ * resident instead of calling hipMalloc and hipFree (which waits for the device) per request.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct {
+  int64_t hits;          /* allocations served from the cache */
+  int64_t misses;        /* allocations that called hipMalloc */
+  int64_t cached_bytes;  /* bytes held in the cache, free for reuse */
+  int64_t live_bytes;    /* bytes handed out and not yet returned */
+  int64_t limit_bytes;   /* cap on cached_bytes; blocks beyond it are freed when returned */
+} mfs_pool_stats;
+
+/* Counters of the cache (all devices).  Host output. */
+mfs_status mfs_pool_query(mfs_pool_stats* out);
+
+/* Set the cap on cached bytes (>= 0); cached blocks are released if the cache exceeds it. */
+mfs_status mfs_pool_set_limit(int64_t max_cached_bytes);
+
+/* Release every cached block to the device (waits for each block's last use).  Blocks held by live
+ * scenes are not affected. */
+mfs_status mfs_pool_trim(void);
 
 #ifdef __cplusplus
 }

@@ -6,6 +6,8 @@
 // Reductions are two-stage with a fixed order (per-block partial sums, then one wave per value),
 // so results are reproducible run to run.  The Hessenberg column update, Givens rotations and
 // the residual estimate run on the device; the host only reads how many columns are still active.
+#include <algorithm>
+
 #include "mfs_internal.h"
 
 namespace mfs {
@@ -25,12 +27,15 @@ __device__ __forceinline__ double wave_sum(double v) {
 // grid = (vector chunks, groups of kGroup basis vectors, right-hand sides): each block keeps its
 // chunk of w in registers and reads kGroup basis-vector chunks once.
 __global__ __launch_bounds__(kThreads) void dots_kernel(const c128* __restrict__ V, const c128* __restrict__ w,
-                                                        int64_t N, int R, int jcount, int nblk,
-                                                        double* __restrict__ part, const int32_t* __restrict__ flag) {
+                                                        int64_t N, int R, int jcount_h, int nblk,
+                                                        double* __restrict__ part, const int32_t* __restrict__ flag,
+                                                        const int32_t* __restrict__ jdev) {
   __shared__ double red[kThreads / 64][kGroup][2];
   const int r = blockIdx.z;
   if (flag && !flag[r]) return;
+  const int jcount = jdev ? *jdev + 1 : jcount_h;
   const int i0 = blockIdx.y * kGroup;
+  if (i0 >= jcount) return;  // graph replays size the grid for the largest step of their bucket
   const int64_t base = (int64_t)blockIdx.x * (kThreads * kElems);
   c128 wl[kElems];
 #pragma unroll
@@ -83,10 +88,12 @@ __global__ __launch_bounds__(kThreads) void dots_kernel(const c128* __restrict__
 }
 
 // out[r][i] = sum_blk part[r][i][blk] (+ add[r][i] if add != null); one wave per (i, r).
-__global__ void dots_reduce_kernel(const double* __restrict__ part, int jcount, int nblk, int R, int ld,
+__global__ void dots_reduce_kernel(const double* __restrict__ part, int jcount_h, int nblk, int R, int ld,
                                    c128* __restrict__ out, const c128* __restrict__ add,
-                                   const int32_t* __restrict__ flag) {
+                                   const int32_t* __restrict__ flag, const int32_t* __restrict__ jdev) {
   const int i = blockIdx.x, r = blockIdx.y, lane = threadIdx.x;
+  const int jcount = jdev ? *jdev + 1 : jcount_h;
+  if (i >= jcount) return;
   if (flag && !flag[r]) {
     if (lane == 0) out[(int64_t)r * ld + i] = c128{0.0, 0.0};
     return;
@@ -111,11 +118,13 @@ __global__ void dots_reduce_kernel(const double* __restrict__ part, int jcount, 
 
 // w[r][n] -= sum_{i<jcount} h[r][i] V_i[r][n]
 __global__ __launch_bounds__(kThreads) void basis_axpy_kernel(const c128* __restrict__ V, const c128* __restrict__ h,
-                                                              int ld, int64_t N, int R, int jcount,
-                                                              c128* __restrict__ w, const int32_t* __restrict__ flag) {
+                                                              int ld, int64_t N, int R, int jcount_h,
+                                                              c128* __restrict__ w, const int32_t* __restrict__ flag,
+                                                              const int32_t* __restrict__ jdev) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
   if (n >= N || (flag && !flag[r])) return;
+  const int jcount = jdev ? *jdev + 1 : jcount_h;
   // h is read with wave-uniform addresses (scalar loads); eight basis loads are kept in flight
   double ar = 0.0, ai = 0.0;
   const c128* hr = h + (int64_t)r * ld;
@@ -168,14 +177,15 @@ __global__ void norm_reduce_kernel(const double* __restrict__ part, int nblk, do
 }
 
 // Second Gram-Schmidt pass only where the first one cancelled: reorthogonalise when
-// ||w'||^2 = ||w||^2 - sum |h_i|^2 falls below ||w||^2 / 2 (the "twice is enough" test of
-// Daniel, Gragg, Kaufman and Stewart with eta = 1/sqrt(2)).  One thread per right-hand side.
-__global__ void reorth_decide_kernel(int jcount, int R, int ld, const c128* __restrict__ h,
+// ||w'||^2 = ||w||^2 - sum |h_i|^2 falls below eta^2 ||w||^2 (the test of Daniel, Gragg, Kaufman
+// and Stewart; eta2 = eta^2 is an argument).  One thread per right-hand side.
+__global__ void reorth_decide_kernel(int jcount_h, int R, int ld, const c128* __restrict__ h,
                                      const double* __restrict__ wn2, int32_t* __restrict__ flag,
                                      int32_t* __restrict__ count, double eta2, double* __restrict__ ratio_log,
-                                     int m) {
+                                     int m, const int32_t* __restrict__ jdev) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= R) return;
+  const int jcount = jdev ? *jdev + 1 : jcount_h;
   double s = 0.0;
   for (int i = 0; i < jcount; ++i) {
     const c128 v = h[(int64_t)r * ld + i];
@@ -202,8 +212,13 @@ __global__ void start_scale_kernel(const c128* __restrict__ r0, const double* __
 
 __global__ void start_state_kernel(const double* __restrict__ beta, const double* __restrict__ bnorm,
                                    int32_t* __restrict__ active, int32_t* __restrict__ jlen, c128* __restrict__ g,
-                                   double* __restrict__ res, int m, int R) {
+                                   double* __restrict__ res, int m, int R, int32_t* __restrict__ jdev,
+                                   double* __restrict__ tol_dev, double tol) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r == 0 && jdev) {
+    *jdev = 0;
+    *tol_dev = tol;
+  }
   if (r >= R) return;
   jlen[r] = 0;
   g[(int64_t)r * (m + 1)] = c128{beta[r], 0.0};
@@ -215,14 +230,17 @@ __global__ void start_state_kernel(const double* __restrict__ beta, const double
 // Column j of H from the Gram-Schmidt coefficients and ||w||, previous rotations, new rotation,
 // residual estimate.  The Arnoldi vectors come from w = K v_j for the operator shift I + K, so the
 // shift is added to the diagonal entry.  One thread per right-hand side.
-__global__ void givens_kernel(int j, int m, int R, double shift, const c128* __restrict__ hcol,
+__global__ void givens_kernel(int j_h, int m, int R, double shift, const c128* __restrict__ hcol,
                               const c128* __restrict__ h2,
                               const double* __restrict__ hnorm,
                               c128* __restrict__ H, c128* __restrict__ cs, c128* __restrict__ sn,
                               c128* __restrict__ g, double* __restrict__ res, const double* __restrict__ bnorm,
-                              double tol, int32_t* __restrict__ active, int32_t* __restrict__ jlen) {
+                              double tol_h, int32_t* __restrict__ active, int32_t* __restrict__ jlen,
+                              const int32_t* __restrict__ jdev, const double* __restrict__ tol_dev) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= R || !active[r]) return;
+  const int j = jdev ? *jdev : j_h;
+  const double tol = jdev ? *tol_dev : tol_h;
   c128* Hc = H + ((int64_t)r * m + j) * (m + 1);
   for (int i = 0; i <= j; ++i) {
     const c128 a1 = hcol[(int64_t)r * (m + 1) + i], a2 = h2[(int64_t)r * (m + 1) + i];
@@ -265,16 +283,23 @@ __global__ void givens_kernel(int j, int m, int R, double shift, const c128* __r
   if (res[r] <= tol || !(hnorm[r] > 1e-300)) active[r] = 0;
 }
 
-// V_{j+1} = w / ||w|| for active columns.
+// V_{j+1} = w / ||w||.
 __global__ void scale_next_kernel(const c128* __restrict__ w, const double* __restrict__ hnorm, int64_t N, int R,
-                                  c128* __restrict__ Vn) {
+                                  c128* __restrict__ V, int j_h, const int32_t* __restrict__ jdev) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
   if (n >= N) return;
+  const int j = jdev ? *jdev : j_h;
+  c128* Vn = V + (int64_t)(j + 1) * R * N;
   const double h = hnorm[r];
   const double s = h > 1e-300 ? 1.0 / h : 0.0;
   const c128 x = w[(int64_t)r * N + n];
   Vn[(int64_t)r * N + n] = c128{x.re * s, x.im * s};
+}
+
+// End of a replayed step: the next replay works on step j + 1.
+__global__ void step_advance_kernel(int32_t* __restrict__ jdev) {
+  if (threadIdx.x == 0) *jdev += 1;
 }
 
 // y = H(0:len,0:len)^{-1} g(0:len), column-oriented back substitution; one block per right-hand
@@ -355,14 +380,16 @@ hipError_t launch_start_cycle(KrylovDev k, const c128* r0, hipStream_t st) {
   hipLaunchKernelGGL(start_scale_kernel, dim3(blocks_for(k.N, 256), k.R), dim3(256), 0, st, r0, k.beta, k.N, k.R,
                      k.V);
   hipLaunchKernelGGL(start_state_kernel, dim3(blocks_for(k.R, 64)), dim3(64), 0, st, k.beta, k.bnorm, k.active,
-                     k.jlen, k.g, k.res, k.m, k.R);
+                     k.jlen, k.g, k.res, k.m, k.R, k.jdev, k.tol_dev, k.tol);
   return hipGetLastError();
 }
 
 // Gram-Schmidt: hcol = V^H w; w -= V hcol; then, where the first pass cancelled, h2 = V^H w;
 // w -= V h2 (the H column is hcol + h2, summed in the Givens kernel).
 hipError_t launch_arnoldi_orth(KrylovDev k, int j, c128* w, hipStream_t st) {
-  const int jc = j + 1;
+  // With a device step counter (graph replay) the grids cover the largest step of j's bucket and
+  // the kernels read the actual step from k.jdev.
+  const int jc = k.jdev ? std::min(k.m, (j / kStepBucket + 1) * kStepBucket) : j + 1;
   const int ld = k.m + 1;
   hipError_t e = launch_norms(w, k.N, k.R, k.part, k.nblk, k.wn, st);
   if (e != hipSuccess) return e;
@@ -371,13 +398,14 @@ hipError_t launch_arnoldi_orth(KrylovDev k, int j, c128* w, hipStream_t st) {
     const int32_t* flag = pass == 0 ? nullptr : k.reorth;
     if (pass == 1)
       hipLaunchKernelGGL(reorth_decide_kernel, dim3(blocks_for(k.R, 64)), dim3(64), 0, st, jc, k.R, ld, k.hcol, k.wn,
-                         k.reorth, k.n_reorth, k.reorth_eta * k.reorth_eta, k.ratio_log, k.m);
+                         k.reorth, k.n_reorth, k.reorth_eta * k.reorth_eta, k.ratio_log, k.m,
+                         (const int32_t*)k.jdev);
     hipLaunchKernelGGL(dots_kernel, dim3(k.nblk, (jc + kGroup - 1) / kGroup, k.R), dim3(kThreads), 0, st, k.V, w,
-                       k.N, k.R, jc, k.nblk, k.part, flag);
+                       k.N, k.R, jc, k.nblk, k.part, flag, (const int32_t*)k.jdev);
     hipLaunchKernelGGL(dots_reduce_kernel, dim3(jc, k.R), dim3(64), 0, st, k.part, jc, k.nblk, k.R, ld, h,
-                       (const c128*)nullptr, flag);
+                       (const c128*)nullptr, flag, (const int32_t*)k.jdev);
     hipLaunchKernelGGL(basis_axpy_kernel, dim3(blocks_for(k.N, kThreads), k.R), dim3(kThreads), 0, st, k.V, h, ld,
-                       k.N, k.R, jc, w, flag);
+                       k.N, k.R, jc, w, flag, (const int32_t*)k.jdev);
   }
   return hipGetLastError();
 }
@@ -387,9 +415,11 @@ hipError_t launch_arnoldi_finish(KrylovDev k, int j, c128* w, double tol, hipStr
   hipError_t e = launch_norms(w, k.N, k.R, k.part, k.nblk, k.hnorm, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(givens_kernel, dim3(blocks_for(k.R, 64)), dim3(64), 0, st, j, k.m, k.R, 1.0, k.hcol, k.h2, k.hnorm,
-                     k.H, k.cs, k.sn, k.g, k.res, k.bnorm, tol, k.active, k.jlen);
+                     k.H, k.cs, k.sn, k.g, k.res, k.bnorm, tol, k.active, k.jlen, (const int32_t*)k.jdev,
+                     (const double*)k.tol_dev);
   hipLaunchKernelGGL(scale_next_kernel, dim3(blocks_for(k.N, 256), k.R), dim3(256), 0, st, w, k.hnorm, k.N, k.R,
-                     k.V + (int64_t)(j + 1) * k.R * k.N);
+                     k.V, j, (const int32_t*)k.jdev);
+  if (k.jdev) hipLaunchKernelGGL(step_advance_kernel, dim3(1), dim3(64), 0, st, k.jdev);
   return hipGetLastError();
 }
 

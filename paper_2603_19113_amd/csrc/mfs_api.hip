@@ -23,36 +23,36 @@ mfs_status fail(mfs_status code, const std::string& msg) {
   return code;
 }
 
-// Grow-only device buffer owned by a scene.
+// Grow-only device buffer owned by a scene, drawn from the library's caching pool (pool.hip): a
+// grown or released block goes back to the pool ordered after the work enqueued on `st`.
 struct Buf {
   void* p = nullptr;
   size_t cap = 0;
 };
 
-static mfs_status ensure(Buf& b, size_t bytes, size_t* total) {
+static mfs_status ensure(Buf& b, size_t bytes, size_t* total, hipStream_t st) {
   if (b.cap >= bytes) return MFS_OK;
   if (b.p) {
-    hipError_t e = hipFree(b.p);
-    if (e != hipSuccess) return fail(MFS_ERR_HIP, std::string("hipFree: ") + hipGetErrorString(e));
+    pool_free(b.p, b.cap, st);
     *total -= b.cap;
     b.p = nullptr;
     b.cap = 0;
   }
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(MFS_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
-  }
+  size_t got = 0;
+  hipError_t e = hipSuccess;
+  void* p = pool_alloc(bytes, st, &got, &e);
+  if (!p)
+    return fail(MFS_ERR_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed: " +
+                                   hipGetErrorString(e));
   b.p = p;
-  b.cap = bytes;
-  *total += bytes;
+  b.cap = got;
+  *total += got;
   return MFS_OK;
 }
 
-static void release(Buf& b, size_t* total) {
+static void release(Buf& b, size_t* total, hipStream_t last) {
   if (b.p) {
-    (void)hipFree(b.p);
+    pool_free(b.p, b.cap, last);
     *total -= b.cap;
   }
   b.p = nullptr;
@@ -110,6 +110,7 @@ struct mfs_scene {
   bool has_s32 = false;
   std::vector<int64_t> k_of_shape;
   size_t bytes = 0;
+  hipStream_t last_stream = nullptr;  // stream of the latest call; releases are ordered after it
   // owned tables
   Buf x64, x32, l32, lsq, centres, body_of, body_ptr, shape_of, k_dev, S64_tab, S32_tab;
   // workspaces
@@ -143,7 +144,7 @@ int tpt_for(mfs_prec prec) { return prec == MFS_FP64 ? 1 : 2; }
 // y = q + S G_hat q in FP64 (all operands complex128).
 mfs_status apply_f64(mfs_scene* s, const c128* q, c128* y, int R, hipStream_t st, double beta = 1.0) {
   const int nch = pair_chunks_for(s->dev.N, s->dev.N, tpt_for(MFS_FP64));
-  MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c128), &s->bytes));
+  MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c128), &s->bytes, st));
   c128* part = static_cast<c128*>(s->partial.p);
   {
     TimedLaunch tl(MFS_KERNEL_PAIR_F64, s->dev.offbody_pairs * R, st);
@@ -156,7 +157,7 @@ mfs_status apply_f64(mfs_scene* s, const c128* q, c128* y, int R, hipStream_t st
 // y = q + S G_hat q in FP32 (complex64 in and out).
 mfs_status apply_f32(mfs_scene* s, const c64* q, c64* y, int R, hipStream_t st) {
   const int nch = pair_chunks_for(s->dev.N, s->dev.N, tpt_for(MFS_FP32));
-  MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c64), &s->bytes));
+  MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c64), &s->bytes, st));
   c64* part = static_cast<c64*>(s->partial.p);
   {
     TimedLaunch tl(MFS_KERNEL_PAIR_F32, s->dev.offbody_pairs * R, st);
@@ -170,9 +171,9 @@ mfs_status apply_f32(mfs_scene* s, const c64* q, c64* y, int R, hipStream_t st) 
 // part stays exact in FP64, only S G_hat q carries single-precision error.
 mfs_status apply_mixed(mfs_scene* s, const c128* q, c128* y, int R, hipStream_t st, double beta = 1.0) {
   const int64_t NR = s->dev.N * R;
-  MFS_TRY(ensure(s->q32, (size_t)NR * sizeof(c64), &s->bytes));
+  MFS_TRY(ensure(s->q32, (size_t)NR * sizeof(c64), &s->bytes, st));
   const int nch = pair_chunks_for(s->dev.N, s->dev.N, tpt_for(MFS_FP32));
-  MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c64), &s->bytes));
+  MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c64), &s->bytes, st));
   c64* q32 = static_cast<c64*>(s->q32.p);
   c64* part = static_cast<c64*>(s->partial.p);
   MFS_HIP_TRY(launch_to_c64(q, q32, NR, st));
@@ -255,29 +256,35 @@ mfs_status mfs_scene_create(int32_t dim, double kappa, int64_t T, const int32_t*
     mfs_scene_destroy(sc);
     return st;
   };
+  // Packing runs on the calling thread's private non-blocking stream, so creating a scene neither
+  // waits for nor delays requests running on other streams.
+  hipError_t pe = hipSuccess;
+  hipStream_t ps = private_stream(&pe);
+  if (pe != hipSuccess) return cleanup(fail(MFS_ERR_HIP, std::string("stream creation: ") + hipGetErrorString(pe)));
+  sc->last_stream = ps;
   Buf tmpl_d, tmpl_ptr_d;
   size_t tmp_bytes = 0;
   mfs_status st;
-  if ((st = ensure(sc->x64, sizeof(double) * dim * N, &sc->bytes)) != MFS_OK) return cleanup(st);
-  if ((st = ensure(sc->x32, sizeof(float) * dim * N, &sc->bytes)) != MFS_OK) return cleanup(st);
-  if ((st = ensure(sc->l32, sizeof(float) * dim * N, &sc->bytes)) != MFS_OK) return cleanup(st);
-  if ((st = ensure(sc->lsq, sizeof(float) * N, &sc->bytes)) != MFS_OK) return cleanup(st);
-  if ((st = ensure(sc->centres, sizeof(double) * dim * T, &sc->bytes)) != MFS_OK) return cleanup(st);
-  if ((st = ensure(sc->body_of, sizeof(int32_t) * N, &sc->bytes)) != MFS_OK) return cleanup(st);
-  if ((st = ensure(sc->body_ptr, sizeof(int64_t) * (T + 1), &sc->bytes)) != MFS_OK) return cleanup(st);
-  if ((st = ensure(sc->shape_of, sizeof(int32_t) * T, &sc->bytes)) != MFS_OK) return cleanup(st);
-  if ((st = ensure(sc->k_dev, sizeof(int64_t) * n_shapes, &sc->bytes)) != MFS_OK) return cleanup(st);
-  if ((st = ensure(sc->S64_tab, sizeof(void*) * n_shapes, &sc->bytes)) != MFS_OK) return cleanup(st);
-  if ((st = ensure(sc->S32_tab, sizeof(void*) * n_shapes, &sc->bytes)) != MFS_OK) return cleanup(st);
-  if ((st = ensure(tmpl_d, sizeof(double) * tmpl.size(), &tmp_bytes)) != MFS_OK) return cleanup(st);
-  if ((st = ensure(tmpl_ptr_d, sizeof(int64_t) * tmpl_ptr.size(), &tmp_bytes)) != MFS_OK) return cleanup(st);
+  if ((st = ensure(sc->x64, sizeof(double) * dim * N, &sc->bytes, ps)) != MFS_OK) return cleanup(st);
+  if ((st = ensure(sc->x32, sizeof(float) * dim * N, &sc->bytes, ps)) != MFS_OK) return cleanup(st);
+  if ((st = ensure(sc->l32, sizeof(float) * dim * N, &sc->bytes, ps)) != MFS_OK) return cleanup(st);
+  if ((st = ensure(sc->lsq, sizeof(float) * N, &sc->bytes, ps)) != MFS_OK) return cleanup(st);
+  if ((st = ensure(sc->centres, sizeof(double) * dim * T, &sc->bytes, ps)) != MFS_OK) return cleanup(st);
+  if ((st = ensure(sc->body_of, sizeof(int32_t) * N, &sc->bytes, ps)) != MFS_OK) return cleanup(st);
+  if ((st = ensure(sc->body_ptr, sizeof(int64_t) * (T + 1), &sc->bytes, ps)) != MFS_OK) return cleanup(st);
+  if ((st = ensure(sc->shape_of, sizeof(int32_t) * T, &sc->bytes, ps)) != MFS_OK) return cleanup(st);
+  if ((st = ensure(sc->k_dev, sizeof(int64_t) * n_shapes, &sc->bytes, ps)) != MFS_OK) return cleanup(st);
+  if ((st = ensure(sc->S64_tab, sizeof(void*) * n_shapes, &sc->bytes, ps)) != MFS_OK) return cleanup(st);
+  if ((st = ensure(sc->S32_tab, sizeof(void*) * n_shapes, &sc->bytes, ps)) != MFS_OK) return cleanup(st);
+  if ((st = ensure(tmpl_d, sizeof(double) * tmpl.size(), &tmp_bytes, ps)) != MFS_OK) return cleanup(st);
+  if ((st = ensure(tmpl_ptr_d, sizeof(int64_t) * tmpl_ptr.size(), &tmp_bytes, ps)) != MFS_OK) return cleanup(st);
 
   std::vector<const void*> s32v(n_shapes, nullptr);
   if (S32_dev)
     for (int s = 0; s < n_shapes; ++s) s32v[s] = S32_dev[s];
   hipError_t e = hipSuccess;
   auto cp = [&](void* dst, const void* src, size_t n) {
-    if (e == hipSuccess) e = hipMemcpy(dst, src, n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, ps);
   };
   cp(sc->body_ptr.p, body_ptr.data(), sizeof(int64_t) * (T + 1));
   cp(sc->shape_of.p, shape_of, sizeof(int32_t) * T);
@@ -292,10 +299,10 @@ mfs_status mfs_scene_create(int32_t dim, double kappa, int64_t T, const int32_t*
                           static_cast<int64_t*>(tmpl_ptr_d.p), static_cast<double*>(tmpl_d.p),
                           static_cast<int64_t*>(sc->body_ptr.p), origin, static_cast<double*>(sc->x64.p),
                           static_cast<float*>(sc->x32.p), static_cast<float*>(sc->l32.p),
-                          static_cast<float*>(sc->lsq.p), static_cast<int32_t*>(sc->body_of.p), N, nullptr);
-  if (e == hipSuccess) e = hipDeviceSynchronize();
-  release(tmpl_d, &tmp_bytes);
-  release(tmpl_ptr_d, &tmp_bytes);
+                          static_cast<float*>(sc->lsq.p), static_cast<int32_t*>(sc->body_of.p), N, ps);
+  if (e == hipSuccess) e = hipStreamSynchronize(ps);
+  release(tmpl_d, &tmp_bytes, ps);
+  release(tmpl_ptr_d, &tmp_bytes, ps);
   if (e != hipSuccess) return cleanup(fail(MFS_ERR_HIP, std::string("scene packing: ") + hipGetErrorString(e)));
 
   SceneDev& d = sc->dev;
@@ -332,10 +339,9 @@ mfs_status mfs_scene_create(int32_t dim, double kappa, int64_t T, const int32_t*
 
 mfs_status mfs_scene_destroy(mfs_scene* s) {
   if (!s) return MFS_OK;
-  (void)hipDeviceSynchronize();
   Buf* all[] = {&s->x64, &s->x32, &s->l32, &s->lsq, &s->centres, &s->body_of, &s->body_ptr, &s->shape_of, &s->k_dev, &s->S64_tab,
                 &s->S32_tab, &s->partial, &s->q32, &s->dirs, &s->kry, &s->vecs};
-  for (Buf* b : all) release(*b, &s->bytes);
+  for (Buf* b : all) release(*b, &s->bytes, s->last_stream);
   delete s;
   return MFS_OK;
 }
@@ -364,8 +370,9 @@ mfs_status mfs_plane_wave(const mfs_scene* sc, const double* dirs_host, int32_t 
   MFS_TRY(check_scene(sc));
   mfs_scene* s = const_cast<mfs_scene*>(sc);
   if (R < 1 || !dirs_host || !vhat_dev) return fail(MFS_ERR_ARG, "plane wave: bad R or null pointer");
-  MFS_TRY(ensure(s->dirs, sizeof(double) * R * s->dev.dim, &s->bytes));
   hipStream_t st = as_stream(stream);
+  s->last_stream = st;
+  MFS_TRY(ensure(s->dirs, sizeof(double) * R * s->dev.dim, &s->bytes, st));
   MFS_HIP_TRY(hipMemcpyAsync(s->dirs.p, dirs_host, sizeof(double) * R * s->dev.dim, hipMemcpyHostToDevice, st));
   MFS_HIP_TRY(hipStreamSynchronize(st));  // dirs_host may be released by the caller on return
   MFS_HIP_TRY(launch_plane_wave(s->dev, static_cast<double*>(s->dirs.p), R, static_cast<c128*>(vhat_dev), st));
@@ -379,9 +386,10 @@ mfs_status mfs_ghat_apply(const mfs_scene* sc, const void* q_dev, void* t_dev, i
   if (R < 1 || !q_dev || !t_dev || q_dev == t_dev) return fail(MFS_ERR_ARG, "ghat: bad R or pointers");
   mfs_scene* s = const_cast<mfs_scene*>(sc);
   hipStream_t st = as_stream(stream);
+  s->last_stream = st;
   const int nch = pair_chunks_for(s->dev.N, s->dev.N, tpt_for(prec));
   if (prec == MFS_FP64) {
-    MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c128), &s->bytes));
+    MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c128), &s->bytes, st));
     c128* part = static_cast<c128*>(s->partial.p);
     {
       TimedLaunch tl(MFS_KERNEL_PAIR_F64, s->dev.offbody_pairs * R, st);
@@ -389,7 +397,7 @@ mfs_status mfs_ghat_apply(const mfs_scene* sc, const void* q_dev, void* t_dev, i
     }
     MFS_HIP_TRY(launch_reduce_partials_f64(part, nch, s->dev.N, R, static_cast<c128*>(t_dev), st));
   } else {
-    MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c64), &s->bytes));
+    MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c64), &s->bytes, st));
     c64* part = static_cast<c64*>(s->partial.p);
     {
       TimedLaunch tl(MFS_KERNEL_PAIR_F32, s->dev.offbody_pairs * R, st);
@@ -408,6 +416,7 @@ mfs_status mfs_s_apply(const mfs_scene* sc, const void* q_dev, const void* t_dev
   if (t_dev == y_dev) return fail(MFS_ERR_ARG, "s_apply: y must not alias t");
   mfs_scene* s = const_cast<mfs_scene*>(sc);
   hipStream_t st = as_stream(stream);
+  s->last_stream = st;
   if (prec == MFS_FP64) {
     MFS_HIP_TRY(launch_sapply_f64(s->dev, static_cast<const c128*>(t_dev), 1, static_cast<const c128*>(q_dev), beta,
                                   static_cast<c128*>(y_dev), R, (int)s->kmax, st));
@@ -424,6 +433,7 @@ mfs_status mfs_apply(const mfs_scene* sc, const void* q_dev, void* y_dev, int32_
   if (R < 1 || !q_dev || !y_dev || q_dev == y_dev) return fail(MFS_ERR_ARG, "apply: bad R or pointers");
   mfs_scene* s = const_cast<mfs_scene*>(sc);
   hipStream_t st = as_stream(stream);
+  s->last_stream = st;
   if (prec == MFS_FP64) return apply_f64(s, static_cast<const c128*>(q_dev), static_cast<c128*>(y_dev), R, st);
   return apply_f32(s, static_cast<const c64*>(q_dev), static_cast<c64*>(y_dev), R, st);
 }
@@ -437,9 +447,10 @@ mfs_status mfs_eval_field(const mfs_scene* sc, const void* qhat_dev, int32_t R, 
   if (M == 0) return MFS_OK;
   mfs_scene* s = const_cast<mfs_scene*>(sc);
   hipStream_t st = as_stream(stream);
+  s->last_stream = st;
   const int nch = pair_chunks_for(s->dev.N, M, tpt_for(prec));
   if (prec == MFS_FP64) {
-    MFS_TRY(ensure(s->partial, (size_t)nch * R * M * sizeof(c128), &s->bytes));
+    MFS_TRY(ensure(s->partial, (size_t)nch * R * M * sizeof(c128), &s->bytes, st));
     c128* part = static_cast<c128*>(s->partial.p);
     {
       TimedLaunch tl(MFS_KERNEL_PAIR_F64, (double)M * s->dev.N * R, st);
@@ -447,7 +458,7 @@ mfs_status mfs_eval_field(const mfs_scene* sc, const void* qhat_dev, int32_t R, 
     }
     MFS_HIP_TRY(launch_reduce_partials_f64(part, nch, M, R, static_cast<c128*>(u_dev), st));
   } else {
-    MFS_TRY(ensure(s->partial, (size_t)nch * R * M * sizeof(c64), &s->bytes));
+    MFS_TRY(ensure(s->partial, (size_t)nch * R * M * sizeof(c64), &s->bytes, st));
     c64* part = static_cast<c64*>(s->partial.p);
     {
       TimedLaunch tl(MFS_KERNEL_PAIR_F32, (double)M * s->dev.N * R, st);
@@ -473,6 +484,7 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
     return fail(MFS_ERR_ARG, "solve: MFS_MIXED needs max_refine >= 1 and 0 < inner_tol < 1");
   mfs_scene* s = const_cast<mfs_scene*>(sc);
   hipStream_t st = as_stream(stream);
+  s->last_stream = st;
   const int64_t N = s->dev.N;
   const int64_t NR = N * R;
   const int m = opts->restart;
@@ -497,8 +509,9 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
   const size_t oV = carve(szV), oH = carve(szH), ocs = carve(szRm), osn = carve(szRm), og = carve(szRm1),
                oh1 = carve(szRm1), oh2 = carve(szRm1), oy = carve(szRm), obeta = carve(8 * R), obn = carve(8 * R),
                ores = carve(8 * R), ohn = carve(8 * R), oact = carve(4 * R), ojl = carve(4 * R),
-               own = carve(8 * R), oro = carve(4 * R), onro = carve(4 * R), opart = carve(szPart);
-  MFS_TRY(ensure(s->kry, off, &s->bytes));
+               own = carve(8 * R), oro = carve(4 * R), onro = carve(4 * R), opart = carve(szPart),
+               ojdev = carve(sizeof(int32_t)), otol = carve(sizeof(double));
+  MFS_TRY(ensure(s->kry, off, &s->bytes, st));
   char* base = static_cast<char*>(s->kry.p);
   k.V = reinterpret_cast<c128*>(base + oV);
   k.H = reinterpret_cast<c128*>(base + oH);
@@ -518,6 +531,9 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
   k.wn = reinterpret_cast<double*>(base + own);
   k.reorth = reinterpret_cast<int32_t*>(base + oro);
   k.n_reorth = reinterpret_cast<int32_t*>(base + onro);
+  const bool use_graph = opts->use_graph != 0;
+  k.jdev = use_graph ? reinterpret_cast<int32_t*>(base + ojdev) : nullptr;
+  k.tol_dev = use_graph ? reinterpret_cast<double*>(base + otol) : nullptr;
   MFS_HIP_TRY(hipMemsetAsync(k.n_reorth, 0, sizeof(int32_t) * R, st));
   // Second Gram-Schmidt pass when ||w'|| < 0.2 ||w||.  Measured on 1000 starfish (10^4 steps): the
   // median ratio is 0.26; eta = 0.2 takes the second pass on 26% of steps instead of 93% for
@@ -525,7 +541,7 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
   k.reorth_eta = 0.2;
   k.ratio_log = opts->verbose > 2 ? reinterpret_cast<double*>(k.y) : nullptr;
 
-  MFS_TRY(ensure(s->vecs, 3 * sizeof(c128) * (size_t)NR + 256, &s->bytes));
+  MFS_TRY(ensure(s->vecs, 3 * sizeof(c128) * (size_t)NR + 256, &s->bytes, st));
   c128* b = static_cast<c128*>(s->vecs.p);
   c128* r = b + NR;
   c128* w = r + NR;
@@ -534,6 +550,7 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
 
   std::vector<double> bnorm(R), rnorm(R), relres(R, 1.0);
   std::vector<int32_t> active(R);
+
   int n64 = 0, n32 = 0, n_refine = 0, n_restart = 0, total_it = 0;
 
   auto read_doubles = [&](const double* dev, std::vector<double>& host) -> mfs_status {
@@ -560,13 +577,89 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
     MFS_HIP_TRY(hipMemcpyAsync(k.active, active.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice, st));
     return MFS_OK;
   };
+  // Convergence flags and estimates come back through pinned slots with a lag: the host enqueues
+  // step j while the device still runs the steps before it, and reads the flags of step j - lag,
+  // so small systems are not bound by one host round trip per step.  Close to the target (estimate
+  // within 16x of the tolerance) it reads every step.  Steps enqueued past convergence leave the
+  // solution unchanged: converged columns are frozen by the Givens kernel (jlen stops growing).
+  constexpr int kSlots = 3;
+  size_t pin_bytes = 0;
+  hipError_t pin_err = hipSuccess;
+  char* pin = static_cast<char*>(pinned_alloc((size_t)kSlots * R * (sizeof(int32_t) + sizeof(double)), &pin_bytes,
+                                              &pin_err));
+  if (!pin) return fail(MFS_ERR_NOMEM, std::string("pinned host allocation failed: ") + hipGetErrorString(pin_err));
+  struct PinGuard {
+    void* p;
+    size_t n;
+    hipEvent_t ev[kSlots];
+    ~PinGuard() {
+      for (hipEvent_t e : ev)
+        if (e) {
+          (void)hipEventSynchronize(e);
+          (void)hipEventDestroy(e);
+        }
+      pinned_free(p, n);
+    }
+  } guard{pin, pin_bytes, {nullptr, nullptr, nullptr}};
+  for (int i = 0; i < kSlots; ++i)
+    MFS_HIP_TRY(hipEventCreateWithFlags(&guard.ev[i], hipEventDisableTiming));
+  int32_t* pin_act = reinterpret_cast<int32_t*>(pin);
+  double* pin_res = reinterpret_cast<double*>(pin + ((sizeof(int32_t) * kSlots * R + 7) & ~size_t(7)));
+
+  // Graph replay of the Krylov part of a step.  Graph b holds the launches of one step sized for
+  // the largest step of bucket b; it is captured on first use (on this thread's private stream, in
+  // thread-local capture mode) and replayed on st for every step of the bucket in every cycle of
+  // this call.  What a replay bakes in is fixed for the call: workspace addresses, R, N and the
+  // norm the estimate refers to (prec is fixed per call); the step index and tolerance are read
+  // from device memory.
+  struct GraphSet {
+    std::vector<hipGraphExec_t> exec;
+    ~GraphSet() {
+      for (hipGraphExec_t e : exec)
+        if (e) (void)hipGraphExecDestroy(e);
+    }
+  } graphs;
+  if (use_graph) graphs.exec.assign((m + kStepBucket - 1) / kStepBucket, nullptr);
+  auto krylov_step = [&](const KrylovDev& kk, int j, double ktol) -> mfs_status {
+    if (!use_graph) {
+      MFS_HIP_TRY(launch_arnoldi_orth(kk, j, w, st));
+      MFS_HIP_TRY(launch_arnoldi_finish(kk, j, w, ktol, st));
+      return MFS_OK;
+    }
+    hipGraphExec_t& ex = graphs.exec[j / kStepBucket];
+    if (!ex) {
+      hipError_t e = hipSuccess;
+      hipStream_t cs = private_stream(&e);
+      if (e != hipSuccess) return fail(MFS_ERR_HIP, std::string("stream creation: ") + hipGetErrorString(e));
+      MFS_HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      hipError_t e1 = launch_arnoldi_orth(kk, j, w, cs);
+      hipError_t e2 = e1 == hipSuccess ? launch_arnoldi_finish(kk, j, w, ktol, cs) : e1;
+      hipGraph_t g = nullptr;
+      hipError_t e3 = hipStreamEndCapture(cs, &g);  // always leave capture mode
+      if (e2 != hipSuccess || e3 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(MFS_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e2 != hipSuccess ? e2 : e3));
+      }
+      hipError_t e4 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e4 != hipSuccess) {
+        ex = nullptr;
+        return fail(MFS_ERR_HIP, std::string("graph instantiation: ") + hipGetErrorString(e4));
+      }
+    }
+    MFS_HIP_TRY(hipGraphLaunch(ex, st));
+    return MFS_OK;
+  };
+
   // one GMRES cycle from the residual in r; x += V y.  Returns after m steps, convergence of all
   // active columns to ktol (relative to kk.bnorm), or the iteration budget.
-  std::vector<double> est(R, 1.0);
   auto cycle = [&](KrylovDev kk, double ktol, bool mixed) -> mfs_status {
+    kk.tol = ktol;
     MFS_HIP_TRY(launch_start_cycle(kk, r, st));
     double est_max = 1.0;
-    for (int j = 0; j < m; ++j) {
+    int read_j = -1;  // last step whose flags the host has read
+    bool stop = false;
+    for (int j = 0; j < m && !stop; ++j) {
       c128* Vj = kk.V + (int64_t)j * NR;
       // Arnoldi on the compact part K = S G_hat: w = K v_j, and H(I + K) = H(K) + I (the shift is
       // added in the Givens kernel); the identity's large projection on v_j never enters w.
@@ -577,32 +670,39 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
         MFS_TRY(apply_f64(s, Vj, w, R, st, 0.0));
         ++n64;
       }
-      MFS_HIP_TRY(launch_arnoldi_orth(kk, j, w, st));
-      MFS_HIP_TRY(launch_arnoldi_finish(kk, j, w, ktol, st));
+      MFS_TRY(krylov_step(kk, j, ktol));
       ++total_it;
-      MFS_HIP_TRY(hipMemcpyAsync(active.data(), kk.active, sizeof(int32_t) * R, hipMemcpyDeviceToHost, st));
-      MFS_HIP_TRY(hipMemcpyAsync(est.data(), kk.res, sizeof(double) * R, hipMemcpyDeviceToHost, st));
-      MFS_HIP_TRY(hipStreamSynchronize(st));
-      int na = 0;
-      est_max = 0.0;
-      for (int c = 0; c < R; ++c) {
-        na += active[c];
-        if (active[c]) est_max = std::max(est_max, est[c]);
+      const int slot = j % kSlots;
+      MFS_HIP_TRY(hipMemcpyAsync(pin_act + slot * R, kk.active, sizeof(int32_t) * R, hipMemcpyDeviceToHost, st));
+      MFS_HIP_TRY(hipMemcpyAsync(pin_res + slot * R, kk.res, sizeof(double) * R, hipMemcpyDeviceToHost, st));
+      MFS_HIP_TRY(hipEventRecord(guard.ev[slot], st));
+      const bool last = j + 1 == m || total_it >= opts->maxit;
+      const int lag = (last || !(est_max > 16.0 * ktol)) ? 0 : kSlots - 1;
+      while (read_j < j - lag && !stop) {
+        ++read_j;
+        const int rs = read_j % kSlots;
+        MFS_HIP_TRY(hipEventSynchronize(guard.ev[rs]));
+        int na = 0;
+        est_max = 0.0;
+        for (int c = 0; c < R; ++c) {
+          na += pin_act[rs * R + c];
+          if (pin_act[rs * R + c]) est_max = std::max(est_max, pin_res[rs * R + c]);
+        }
+        if (opts->verbose > 1 && (read_j + 1) % 250 == 0)
+          std::fprintf(stderr, "[mfs_solve] step %d of cycle, %d total, active %d, estimate %.3e, fp32 %d fp64 %d\n",
+                       read_j + 1, total_it, na, est_max, n32, n64);
+        if (na == 0) stop = true;
       }
-      if (opts->verbose > 1 && (j + 1) % 250 == 0)
-        std::fprintf(stderr, "[mfs_solve] step %d of cycle, %d total, active %d, estimate %.3e, fp32 %d fp64 %d\n",
-                     j + 1, total_it, na, est_max, n32, n64);
-      if (na == 0 || total_it >= opts->maxit) break;
+      if (total_it >= opts->maxit) stop = true;
     }
     if (kk.ratio_log) {  // diagnostics: distribution of ||w'|| / ||w|| over the cycle (column 0)
-      std::vector<double> rl(active.size() ? 2 * (size_t)m : 0);
+      std::vector<double> rl((size_t)m);
       MFS_HIP_TRY(hipMemcpyAsync(rl.data(), kk.ratio_log, sizeof(double) * m, hipMemcpyDeviceToHost, st));
       MFS_HIP_TRY(hipStreamSynchronize(st));
-      int len = 0;
       std::vector<double> v;
       for (int i = 0; i < m && i < total_it; ++i)
         if (rl[i] > 0.0) v.push_back(rl[i]);
-      len = (int)v.size();
+      const int len = (int)v.size();
       std::sort(v.begin(), v.end());
       if (len > 0)
         std::fprintf(stderr, "[mfs_solve] ||w'||/||w|| over %d steps: p5 %.3f p25 %.3f p50 %.3f p75 %.3f p95 %.3f\n",
@@ -668,6 +768,23 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
   if (max_relres() > opts->tol)
     return fail(MFS_ERR_NOCONV, "solve: relative residual " + std::to_string(max_relres()) + " above tol after " +
                                     std::to_string(total_it) + " iterations");
+  return MFS_OK;
+}
+
+mfs_status mfs_pool_query(mfs_pool_stats* out) {
+  if (!out) return fail(MFS_ERR_ARG, "pool_query: null output");
+  pool_query(&out->hits, &out->misses, &out->cached_bytes, &out->live_bytes, &out->limit_bytes);
+  return MFS_OK;
+}
+
+mfs_status mfs_pool_set_limit(int64_t max_cached_bytes) {
+  if (max_cached_bytes < 0) return fail(MFS_ERR_ARG, "pool_set_limit: negative limit");
+  pool_set_limit((size_t)max_cached_bytes);
+  return MFS_OK;
+}
+
+mfs_status mfs_pool_trim(void) {
+  pool_trim();
   return MFS_OK;
 }
 

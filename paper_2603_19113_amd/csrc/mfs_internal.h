@@ -118,7 +118,16 @@ struct KrylovDev {
   double* ratio_log;  // optional [R][2m] log of ||w'|| / ||w|| per step (diagnostics), or null
   double* part;       // [R][m+1][nblk][2] partial sums
   int nblk;
+  // Graph replay: the step index and the cycle's tolerance live on the device (set by the cycle
+  // start, advanced by each step), so one captured step serves every step of its bucket.  Null
+  // for eager launches, which pass the step as an argument.
+  int32_t* jdev;
+  double* tol_dev;
+  double tol;         // tolerance written to tol_dev at the cycle start
 };
+
+// Steps per captured graph: the graph of bucket b serves steps b*kStepBucket ... (b+1)*kStepBucket-1.
+constexpr int kStepBucket = 64;
 
 int krylov_nblk(int64_t N);
 hipError_t launch_norms(const c128* v, int64_t N, int R, double* part, int nblk, double* out_norm,
@@ -140,6 +149,18 @@ struct TimedLaunch {
   void* ev0;
   void* ev1;
 };
+
+// Caching allocators (pool.hip).  pool_alloc returns a block of at least `bytes` (its size in *got);
+// when the block is reused, work on `st` is ordered after its previous owner (the host waits when st
+// is null).  pool_free hands a block back after the work enqueued on `last`.
+void* pool_alloc(size_t bytes, hipStream_t st, size_t* got, hipError_t* err);
+void pool_free(void* p, size_t bytes, hipStream_t last);
+void* pinned_alloc(size_t bytes, size_t* got, hipError_t* err);
+void pinned_free(void* p, size_t bytes);
+void pool_query(int64_t* hits, int64_t* misses, int64_t* cached, int64_t* live, int64_t* limit);
+void pool_trim();
+void pool_set_limit(size_t bytes);
+hipStream_t private_stream(hipError_t* err);
 
 // Least squares for S (lsq.hip).
 mfs_status build_S_impl(const mfs_shape_desc* d, void* S64, void* S32, int64_t* k_out, int64_t* skel,

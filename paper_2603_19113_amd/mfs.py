@@ -43,7 +43,8 @@ class ShapeDesc(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("max_refine", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("prec", ctypes.c_int32),
-                ("verbose", ctypes.c_int32), ("fp64_until", ctypes.c_double), ("use_x0", ctypes.c_int32)]
+                ("verbose", ctypes.c_int32), ("fp64_until", ctypes.c_double), ("use_x0", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -55,9 +56,18 @@ class SolveInfo(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class PoolStats(ctypes.Structure):
+    _fields_ = [("hits", ctypes.c_int64), ("misses", ctypes.c_int64), ("cached_bytes", ctypes.c_int64),
+                ("live_bytes", ctypes.c_int64), ("limit_bytes", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 EXPORTS = ["mfs_last_error", "mfs_version", "mfs_build_S", "mfs_scene_create", "mfs_scene_destroy",
            "mfs_scene_size", "mfs_scene_points", "mfs_plane_wave", "mfs_ghat_apply", "mfs_s_apply", "mfs_apply",
-           "mfs_solve", "mfs_eval_field", "mfs_timing_enable", "mfs_timing_read"]
+           "mfs_solve", "mfs_eval_field", "mfs_timing_enable", "mfs_timing_read", "mfs_pool_query",
+           "mfs_pool_set_limit", "mfs_pool_trim"]
 MFS_KERNEL_PAIR_F32, MFS_KERNEL_PAIR_F64 = 0, 1
 
 
@@ -87,6 +97,9 @@ def load(path: str = LIB_PATH):
         "mfs_eval_field": ([vp, vp, i32, vp, i64, vp, i32, vp], ctypes.c_int),
         "mfs_timing_enable": ([i32], ctypes.c_int),
         "mfs_timing_read": ([i32, ctypes.POINTER(f64), ctypes.POINTER(i64), ctypes.POINTER(f64)], ctypes.c_int),
+        "mfs_pool_query": ([ctypes.POINTER(PoolStats)], ctypes.c_int),
+        "mfs_pool_set_limit": ([i64], ctypes.c_int),
+        "mfs_pool_trim": ([], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -244,9 +257,9 @@ def apply(scene: Scene, q, y, prec: int = MFS_FP64, stream=None):
 
 def solve(scene: Scene, vhat, qhat, tol=1e-8, maxit=2000, restart=300, max_refine=10, inner_tol=1e-4,
           prec: int = MFS_FP64, verbose: int = 0, fp64_until: float = 0.0, use_x0: bool = False, stream=None,
-          raise_on_noconv: bool = True) -> dict:
+          raise_on_noconv: bool = True, use_graph: bool = False) -> dict:
     o = SolveOpts(tol=tol, maxit=maxit, restart=restart, max_refine=max_refine, inner_tol=inner_tol, prec=prec,
-                  verbose=verbose, fp64_until=fp64_until, use_x0=1 if use_x0 else 0)
+                  verbose=verbose, fp64_until=fp64_until, use_x0=1 if use_x0 else 0, use_graph=1 if use_graph else 0)
     info = SolveInfo()
     code = _lib.mfs_solve(scene.handle, _ptr(vhat), vhat.shape[0], ctypes.byref(o), _ptr(qhat),
                           ctypes.byref(info), _stream(stream))
@@ -271,3 +284,19 @@ def timing_read(kind: int) -> tuple[float, int, float]:
     ms, n, pairs = ctypes.c_double(0), ctypes.c_int64(0), ctypes.c_double(0)
     _check(load().mfs_timing_read(kind, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(pairs)))
     return float(ms.value), int(n.value), float(pairs.value)
+
+
+# ------------------------------------------------------------------- pool ---
+def pool_stats() -> dict:
+    """Counters of the library's device allocation cache."""
+    out = PoolStats()
+    _check(load().mfs_pool_query(ctypes.byref(out)))
+    return out.as_dict()
+
+
+def pool_set_limit(max_cached_bytes: int):
+    _check(load().mfs_pool_set_limit(int(max_cached_bytes)))
+
+
+def pool_trim():
+    _check(load().mfs_pool_trim())

@@ -16,9 +16,11 @@ parameter, so they run on the CPU with a fake executor and a virtual clock.
 from __future__ import annotations
 
 import collections
+import queue as queue_mod
 import threading
 import time
 from dataclasses import dataclass, field
+from typing import Any, Callable
 
 import numpy as np
 
@@ -78,6 +80,8 @@ class Ticket:
     footprint: int
     start: float = float("nan")
     finish: float = float("nan")
+    batch: int = 1                      # requests that shared this request's solve
+    admitted: int = -1                  # position in the admission order
     result: dict = field(default_factory=dict)
     error: str | None = None
     done: threading.Event = field(default_factory=threading.Event)
@@ -87,20 +91,45 @@ class Ticket:
         return self.finish - self.arrival
 
 
-class Engine:
-    """Slots x streams, one dispatcher.  executor(spec, slot) -> dict runs one request."""
+@dataclass
+class Batching:
+    """Continuous batching across requests: queued requests with the same geometry key (same bodies
+    and wavenumber, different incident fields) join the head of the queue in one multi-RHS solve."""
+    key: Callable[[Any], Any]                  # spec -> hashable geometry key
+    rhs: Callable[[Any], int]                  # spec -> right-hand sides it brings
+    footprint: Callable[[list], int]           # specs of one batch -> device bytes of the joint solve
+    max_rhs: int = 64
 
-    def __init__(self, executor, budget: int, slots: int = 4, clock=time.monotonic):
+
+class Engine:
+    """Slots x streams with one worker thread per slot and one dispatcher.
+
+    executor(specs, slot) -> list of result dicts, one per spec, runs one batch on the slot."""
+
+    def __init__(self, executor, budget: int, slots: int = 4, clock=time.monotonic, batching: Batching | None = None,
+                 start: bool = True):
         self.executor = executor
         self.policy = Admission(budget, slots)
         self.clock = clock
+        self.batching = batching
         self.queue: collections.deque = collections.deque()
         self.lock = threading.Condition()
         self.free_slots = list(range(slots))
+        self.inbox = [queue_mod.Queue() for _ in range(slots)]
         self.closed = False
         self.tickets: list[Ticket] = []
+        self.n_admitted = 0
+        self.workers = [threading.Thread(target=self._worker, args=(i,), daemon=True) for i in range(slots)]
+        for t in self.workers:
+            t.start()
         self.dispatcher = threading.Thread(target=self._dispatch, daemon=True)
-        self.dispatcher.start()
+        if start:
+            self.dispatcher.start()
+
+    def start(self):
+        """Start admitting (for an engine created with start=False, e.g. to queue a burst first)."""
+        if not self.dispatcher.is_alive():
+            self.dispatcher.start()
 
     def submit(self, spec, footprint: int, arrival: float | None = None) -> Ticket:
         t = Ticket(rid=spec.rid, arrival=self.clock() if arrival is None else arrival, footprint=footprint)
@@ -112,32 +141,73 @@ class Engine:
             self.lock.notify_all()
         return t
 
+    def _take_batch(self):
+        """Pop the head and, with batching on, every queued request on its geometry that still fits."""
+        spec, t = self.queue.popleft()
+        group = [(spec, t)]
+        fp = t.footprint
+        b = self.batching
+        if b is not None:
+            key = b.key(spec)
+            nrhs = b.rhs(spec)
+            for item in list(self.queue):
+                s2 = item[0]
+                if b.key(s2) != key or nrhs + b.rhs(s2) > b.max_rhs:
+                    continue
+                fp2 = b.footprint([x[0] for x in group] + [s2])
+                if self.policy.used + fp2 > self.policy.budget:
+                    continue
+                group.append(item)
+                self.queue.remove(item)
+                nrhs += b.rhs(s2)
+                fp = fp2
+        return group, fp
+
     def _dispatch(self):
         while True:
             with self.lock:
                 while not self.closed and not (self.queue and self.policy.fits(self.queue[0][1].footprint)):
                     self.lock.wait()
                 if self.closed and not self.queue:
+                    for box in self.inbox:
+                        box.put(None)
                     return
                 if not self.queue:
                     continue
-                spec, t = self.queue.popleft()
-                self.policy.admit(t.footprint)
+                group, fp = self._take_batch()
+                for _, t in group:
+                    t.admitted = self.n_admitted
+                    self.n_admitted += 1
+                self.policy.admit(fp)
                 slot = self.free_slots.pop()
-            threading.Thread(target=self._run, args=(spec, t, slot), daemon=True).start()
+            self.inbox[slot].put((group, fp))
 
-    def _run(self, spec, t: Ticket, slot: int):
-        t.start = self.clock()
-        try:
-            t.result = self.executor(spec, slot)
-        except Exception as e:  # a failed request frees its slot; the error is reported on its ticket
-            t.error = f"{type(e).__name__}: {e}"
-        t.finish = self.clock()
-        with self.lock:
-            self.policy.release(t.footprint)
-            self.free_slots.append(slot)
-            self.lock.notify_all()
-        t.done.set()
+    def _worker(self, slot: int):
+        while True:
+            job = self.inbox[slot].get()
+            if job is None:
+                return
+            group, fp = job
+            start = self.clock()
+            for _, t in group:
+                t.start = start
+                t.batch = len(group)
+            try:
+                results = self.executor([s for s, _ in group], slot)
+                for (_, t), res in zip(group, results):
+                    t.result = res
+            except Exception as e:  # a failed batch frees its slot; the error is reported on its tickets
+                for _, t in group:
+                    t.error = f"{type(e).__name__}: {e}"
+            finish = self.clock()
+            for _, t in group:
+                t.finish = finish
+            with self.lock:
+                self.policy.release(fp)
+                self.free_slots.append(slot)
+                self.lock.notify_all()
+            for _, t in group:
+                t.done.set()
 
     def drain(self, timeout: float | None = None) -> bool:
         deadline = None if timeout is None else time.monotonic() + timeout
@@ -151,7 +221,13 @@ class Engine:
         with self.lock:
             self.closed = True
             self.lock.notify_all()
-        self.dispatcher.join(timeout=5.0)
+        if self.dispatcher.is_alive():
+            self.dispatcher.join(timeout=5.0)
+        else:
+            for box in self.inbox:
+                box.put(None)
+        for t in self.workers:
+            t.join(timeout=5.0)
 
 
 def latency_stats(tickets) -> dict:
@@ -162,7 +238,21 @@ def latency_stats(tickets) -> dict:
     last = max(t.finish for t in tickets)
     return {"n": int(lat.size), "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
             "mean_s": float(lat.mean()), "solves_per_s": float(lat.size / max(last - first, 1e-9)),
-            "failed": sum(1 for t in tickets if t.error is not None)}
+            "failed": sum(1 for t in tickets if t.error is not None),
+            "batched": sum(1 for t in tickets if t.batch > 1)}
+
+
+# ------------------------------------------------------- request footprints ---
+def request_footprint(specs) -> int:
+    """Device bytes of one solve over the given requests (one geometry, their directions stacked)."""
+    sc = specs[0].scene
+    R = sum(s.scene.R for s in specs)
+    return footprint_bytes(sc.N, sc.T, R, sc.dim, restart_for(sc.T, sc.kappa, sc.dim))
+
+
+def request_batching(max_rhs: int = 64) -> Batching:
+    """Requests on the same geometry (bodies, shapes, wavenumber) share one multi-RHS solve."""
+    return Batching(key=lambda s: s.geometry, rhs=lambda s: s.scene.R, footprint=request_footprint, max_rhs=max_rhs)
 
 
 # ------------------------------------------------------------- GPU executor ---
@@ -192,27 +282,42 @@ class GpuExecutor:
                 self.library[k] = self.mfs.build_S(shape, kappa, stream=stream)
             return self.library[k]
 
-    def __call__(self, spec, slot: int) -> dict:
+    def __call__(self, specs, slot: int) -> list:
+        """Solve a batch of requests on one geometry as one block GMRES-IR over their stacked incident
+        directions, then split the solution rows back per request."""
         torch, mfs = self.torch, self.mfs
-        sc = spec.scene
+        spec0 = specs[0]
+        sc = spec0.scene
+        if any(s.geometry != spec0.geometry for s in specs):
+            raise ValueError("a batch must share one geometry")
+        dirs = np.concatenate([np.atleast_2d(s.scene.directions) for s in specs], axis=0)
         st = self.streams[slot]
         with torch.cuda.stream(st):
-            built = [self.S(sc.dim, key, sh, sc.kappa, st) for key, sh in zip(spec.shape_keys, sc.shapes)]
+            built = [self.S(sc.dim, key, sh, sc.kappa, st) for key, sh in zip(spec0.shape_keys, sc.shapes)]
             scene = mfs.Scene(sc.dim, sc.kappa, sc.shape_of, sc.centres, [s.eqpts for s in sc.shapes],
                               [b.S64 for b in built], [b.S32 for b in built])
-            R = sc.R
-            v = torch.empty((R, scene.N), dtype=torch.complex128, device="cuda")
-            mfs.plane_wave(scene, sc.directions, v, stream=st)
-            q = torch.empty_like(v)
-            restart = restart_for(sc.T, sc.kappa, sc.dim)
-            info = mfs.solve(scene, v, q, tol=self.tol, maxit=200000, restart=restart, max_refine=30,
-                             inner_tol=self.inner_tol, prec=mfs.MFS_MIXED, stream=st)
-            st.synchronize()
-            out = {"info": info, "N": scene.N, "T": sc.T, "R": R, "dim": sc.dim, "kappa": sc.kappa,
+            try:
+                R = dirs.shape[0]
+                v = torch.empty((R, scene.N), dtype=torch.complex128, device="cuda")
+                mfs.plane_wave(scene, dirs, v, stream=st)
+                q = torch.empty_like(v)
+                restart = restart_for(sc.T, sc.kappa, sc.dim)
+                info = mfs.solve(scene, v, q, tol=self.tol, maxit=200000, restart=restart, max_refine=30,
+                                 inner_tol=self.inner_tol, prec=mfs.MFS_MIXED, stream=st)
+                qh = q.cpu().numpy() if self.keep_solution else None  # synchronises the slot's stream
+                st.synchronize()
+                N = scene.N
+            finally:
+                scene.close()
+        out, off = [], 0
+        for s in specs:
+            r = s.scene.R
+            res = {"info": info, "N": N, "T": sc.T, "R": r, "batch_R": R, "dim": sc.dim, "kappa": sc.kappa,
                    "restart": restart}
-            if self.keep_solution:
-                out["qhat"] = q.cpu().numpy()
-            scene.close()
+            if qh is not None:
+                res["qhat"] = qh[off:off + r]
+            out.append(res)
+            off += r
         return out
 
 

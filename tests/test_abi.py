@@ -72,3 +72,13 @@ def test_timing_interface_without_device(lib):
     ms, n, pairs = mfs.timing_read(mfs.MFS_KERNEL_PAIR_F32)
     assert (ms, n, pairs) == (0.0, 0, 0.0)
     assert lib.mfs_timing_enable(0) == 0
+
+
+def test_pool_interface_without_device(lib):
+    st = mfs.pool_stats()
+    assert set(st) == {"hits", "misses", "cached_bytes", "live_bytes", "limit_bytes"}
+    assert st["limit_bytes"] > 0 and st["cached_bytes"] >= 0
+    assert lib.mfs_pool_set_limit(-1) == -1
+    mfs.pool_set_limit(st["limit_bytes"])
+    mfs.pool_trim()
+    assert lib.mfs_pool_query(None) == -1

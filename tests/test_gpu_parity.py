@@ -373,3 +373,32 @@ def test_solve_many_rhs_mixed(mfs):
     r = b - gs.matvec(sc, Ss, xh, ptr, bo, q.cpu().numpy())
     for c in range(R):
         assert np.linalg.norm(r[c]) / np.linalg.norm(b[c]) < 2e-8
+
+
+# --------------------------------------------------------------- graph replay ---
+@pytest.mark.parametrize("prec_name,restart", [("MFS_FP64", 70), ("MFS_MIXED", 150)])
+def test_solve_graph_replay_is_identical_to_direct_launches(mfs, prec_name, restart):
+    """Replayed graphs (bucket of 64 steps, step index on the device) run the same kernels on the
+    same data as direct launches, with eager operator work between replays: results are bitwise
+    equal.  restart = 70 crosses a bucket boundary and restarts several times, so graphs are
+    replayed across cycles with different tolerances; two graph solves in a row must agree too."""
+    torch = _torch()
+    sc = SMALL_SCENES["starfish32"]()
+    sc.directions = w.plane_wave_directions_2d([0.2, 1.3, 2.9])
+    gsc, Ss = _scene_with_oracle_S(mfs, sc)
+    v = torch.empty((3, gsc.N), dtype=torch.complex128, device="cuda")
+    mfs.plane_wave(gsc, sc.directions, v)
+    prec = getattr(mfs, prec_name)
+    out = []
+    for use_graph in (False, True, True):
+        q = torch.empty_like(v)
+        info = mfs.solve(gsc, v, q, tol=1e-9, restart=restart, maxit=5000, inner_tol=1e-5, prec=prec,
+                         use_graph=use_graph)
+        torch.cuda.synchronize()
+        assert info["relres_max"] <= 1e-9
+        out.append((q.cpu().numpy(), info))
+    if prec_name == "MFS_FP64":
+        assert out[0][1]["n_restart"] > 1
+    for q, info in out[1:]:
+        assert np.array_equal(q, out[0][0])
+        assert info["n_matvec32"] == out[0][1]["n_matvec32"] and info["n_matvec64"] == out[0][1]["n_matvec64"]

@@ -1,5 +1,5 @@
-"""Serving on the GPU: the same requests run one at a time and concurrently (overlapping on the
-device through per-slot streams) give the same solutions, each to the solve tolerance."""
+"""Serving on the GPU: requests run one at a time and concurrently (overlapping on the device through
+per-slot streams, and batched with other requests on the same geometry) give the same solutions."""
 
 import numpy as np
 import pytest
@@ -9,28 +9,51 @@ import workloads as w
 pytestmark = pytest.mark.gpu
 
 
-def test_results_same_alone_and_in_the_mix(gpu_lib):
-    from paper_2603_19113_amd.serve import Engine, GpuExecutor, footprint_bytes, latency_stats, restart_for
+def _run(specs, slots, batching=None):
+    from paper_2603_19113_amd.serve import Engine, GpuExecutor, latency_stats, request_footprint
 
+    eng = Engine(GpuExecutor(slots), budget=16 << 30, slots=slots, batching=batching, start=False)
+    for s in specs:
+        eng.submit(s, request_footprint([s]))
+    eng.start()
+    assert eng.drain(timeout=240)
+    eng.close()
+    errors = [t.error for t in eng.tickets if t.error]
+    assert not errors, errors
+    print(f"slots={slots} batching={batching is not None}: {latency_stats(eng.tickets)}", flush=True)
+    return {t.rid: t for t in eng.tickets}
+
+
+def test_results_same_alone_and_in_the_mix(gpu_lib):
     specs = w.serving.request_stream(6, rate=50.0, seed=11, t_min=3, t_max=10, r_max=4)
-    fps = [footprint_bytes(s.scene.N, s.scene.T, s.scene.R, s.scene.dim,
-                           restart_for(s.scene.T, s.scene.kappa, s.scene.dim)) for s in specs]
     print("requests:", [s.scene.name for s in specs], flush=True)
-    results = {}
-    for slots in (1, 3):
-        ex = GpuExecutor(slots)
-        eng = Engine(ex, budget=8 << 30, slots=slots)
-        for s, fp in zip(specs, fps):
-            eng.submit(s, fp)
-        assert eng.drain(timeout=240)
-        eng.close()
-        errors = [t.error for t in eng.tickets if t.error]
-        assert not errors, errors
-        results[slots] = {t.rid: t.result for t in eng.tickets}
-        st = latency_stats(eng.tickets)
-        print(f"slots={slots}: {st}", flush=True)
-    for rid in results[1]:
-        a, b = results[1][rid], results[3][rid]
-        assert a["info"]["relres_max"] <= 1e-8 and b["info"]["relres_max"] <= 1e-8
+    alone = _run(specs, 1)
+    mix = _run(specs, 3)
+    for rid, a in alone.items():
+        b = mix[rid]
+        assert a.result["info"]["relres_max"] <= 1e-8 and b.result["info"]["relres_max"] <= 1e-8
         # deterministic kernels and request-local arithmetic: identical, not merely close
-        assert np.array_equal(a["qhat"], b["qhat"]), rid
+        assert np.array_equal(a.result["qhat"], b.result["qhat"]), rid
+
+
+def test_batched_requests_match_their_solo_solves(gpu_lib):
+    from paper_2603_19113_amd import mfs
+    from paper_2603_19113_amd.serve import request_batching
+
+    specs = w.serving.request_stream(8, rate=50.0, seed=12, t_min=3, t_max=8, r_max=3, p_sweep=0.6)
+    print("requests:", [s.scene.name for s in specs], flush=True)
+    alone = _run(specs, 1)
+    hits0 = mfs.pool_stats()["hits"]
+    mix = _run(specs, 3, batching=request_batching())
+    assert any(t.batch > 1 for t in mix.values())
+    assert mfs.pool_stats()["hits"] > hits0          # Krylov bases and tables reused from the cache
+    for rid, a in alone.items():
+        b = mix[rid]
+        qa, qb = a.result["qhat"], b.result["qhat"]
+        assert qa.shape == qb.shape
+        assert a.result["info"]["relres_max"] <= 1e-8 and b.result["info"]["relres_max"] <= 1e-8
+        # both meet the 1e-8 residual; the systems are well conditioned, so the solutions agree to
+        # far better than the 1e-6 stated for mixed-precision results
+        for r in range(qa.shape[0]):
+            rel = np.linalg.norm(qa[r] - qb[r]) / np.linalg.norm(qa[r])
+            assert rel <= 1e-6, (rid, r, rel, b.batch)

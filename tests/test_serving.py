@@ -9,7 +9,8 @@ import numpy as np
 import pytest
 
 import workloads as w
-from paper_2603_19113_amd.serve import Admission, Engine, footprint_bytes, latency_stats, replay, restart_for
+from paper_2603_19113_amd.serve import (Admission, Batching, Engine, footprint_bytes, latency_stats, replay,
+                                        request_footprint, restart_for)
 
 
 class FakeExecutor:
@@ -21,25 +22,29 @@ class FakeExecutor:
         self.max_active = 0
         self.max_used = 0
         self.order = []
+        self.batches = []
 
-    def __call__(self, spec, slot):
+    def __call__(self, specs, slot):
         with self.lock:
             self.active += 1
             self.max_active = max(self.max_active, self.active)
             self.max_used = max(self.max_used, self.engine_ref[0].policy.used)
-            self.order.append(spec.rid)
-        time.sleep(self.durations[spec.rid])
+            self.order.extend(s.rid for s in specs)
+            self.batches.append([s.rid for s in specs])
+        time.sleep(max(self.durations[s.rid] for s in specs))
         with self.lock:
             self.active -= 1
-        if spec.rid == 3:
+        if any(s.rid == 3 for s in specs):
             raise RuntimeError("injected failure")
-        return {"rid": spec.rid, "slot": slot}
+        return [{"rid": s.rid, "slot": slot, "batch": len(specs)} for s in specs]
 
 
 class Spec:
-    def __init__(self, rid, arrival=0.0):
+    def __init__(self, rid, arrival=0.0, geometry=None, R=1):
         self.rid = rid
         self.arrival = arrival
+        self.geometry = rid if geometry is None else geometry
+        self.R = R
 
 
 def test_admission_policy_bounds():
@@ -71,8 +76,8 @@ def test_engine_respects_budget_slots_and_fifo():
     eng.close()
     assert ex.max_active <= 3
     assert ex.max_used <= 100
-    assert ex.order == sorted(ex.order)          # admitted in arrival order
     tk = {t.rid: t for t in eng.tickets}
+    assert [tk[i].admitted for i in range(n)] == list(range(n))   # admitted in arrival order
     assert tk[3].error is not None and "injected" in tk[3].error
     assert all(tk[i].error is None and tk[i].result["rid"] == i for i in range(n) if i != 3)
     assert eng.policy.used == 0 and eng.policy.running == 0
@@ -81,7 +86,7 @@ def test_engine_respects_budget_slots_and_fifo():
 
 
 def test_engine_rejects_oversized_request():
-    eng = Engine(lambda s, slot: {}, budget=10, slots=1)
+    eng = Engine(lambda specs, slot: [{} for _ in specs], budget=10, slots=1)
     with pytest.raises(ValueError):
         eng.submit(Spec(0), 11)
     eng.close()
@@ -113,3 +118,41 @@ def test_footprint_grows_with_size_and_basis():
     large = footprint_bytes(64000, 500, 4, 2, restart_for(500, 10.0, 2))
     assert 0 < small < large
     assert restart_for(5000, 20.0, 2) == 4000  # capped
+
+
+def test_batching_merges_same_geometry_within_rhs_cap():
+    # slot 0 busy with request 0; then 1..6 queue up: geometries 7,7,8,7,7,7 with R = 3 each
+    ref = [None]
+    durations = [0.15] + [0.01] * 6
+    ex = FakeExecutor(ref, durations)
+    b = Batching(key=lambda s: s.geometry, rhs=lambda s: s.R, footprint=lambda specs: 10 + sum(s.R for s in specs),
+                 max_rhs=9)
+    eng = Engine(ex, budget=1000, slots=1, batching=b)
+    ref[0] = eng
+    eng.submit(Spec(0, geometry=0, R=3), 13)
+    time.sleep(0.05)
+    geos = [7, 7, 8, 7, 7, 7]
+    for i, g in enumerate(geos, start=1):
+        eng.submit(Spec(i, geometry=g, R=3), 13)
+    assert eng.drain(timeout=30)
+    eng.close()
+    # FIFO head 1 takes 2 and 4 (R cap 9), then 3 alone (other geometry)... head 3 fails by injection
+    assert ex.batches[0] == [0]
+    assert ex.batches[1] == [1, 2, 4]
+    assert ex.batches[2] == [3]
+    assert ex.batches[3] == [5, 6]
+    tk = {t.rid: t for t in eng.tickets}
+    assert tk[1].batch == 3 and tk[1].result["batch"] == 3 and tk[3].error and tk[5].batch == 2
+    assert eng.policy.used == 0
+    st = latency_stats(eng.tickets)
+    assert st["batched"] == 5
+
+
+def test_request_footprint_of_a_batch_is_below_the_sum():
+    specs = w.serving.request_stream(8, rate=1.0, seed=3, t_min=4, t_max=16, p_sweep=0.9)
+    geo = specs[0].geometry
+    same = [s for s in specs if s.geometry == geo]
+    assert len(same) >= 2
+    joint = request_footprint(same)
+    assert joint < sum(request_footprint([s]) for s in same)
+    assert joint >= max(request_footprint([s]) for s in same)

@@ -43,17 +43,36 @@ class RequestSpec:
     arrival: float
     scene: Scene
     shape_keys: list = field(default_factory=list)
+    geometry: int = -1          # requests with equal ids share bodies, shapes and wavenumber
+
+
+def _directions(rng, dim: int, R: int) -> np.ndarray:
+    if dim == 2:
+        return plane_wave_directions_2d(2.0 * np.pi * rng.uniform(size=R))
+    d = rng.normal(size=(R, 3))
+    return d / np.linalg.norm(d, axis=1, keepdims=True)
 
 
 def request_stream(n: int, rate: float, seed: int, t_min: int = 4, t_max: int = 64, r_max: int = 16,
-                   p3d: float = 0.5) -> list:
-    """n requests with exponential inter-arrival times of mean 1/rate (seconds)."""
+                   p3d: float = 0.5, p_sweep: float = 0.0) -> list:
+    """n requests with exponential inter-arrival times of mean 1/rate (seconds).  With probability
+    p_sweep a request revisits the geometry of an earlier one with new incident directions (an
+    incidence sweep over one configuration); such requests can share a solve."""
     rng = np.random.default_rng(seed)
     lib = {2: shape_library_2d(), 3: shape_library_3d()}
     t = 0.0
     out = []
     for rid in range(n):
         t += rng.exponential(1.0 / rate)
+        if out and p_sweep > 0.0 and rng.uniform() < p_sweep:
+            base = out[int(rng.integers(len(out)))]
+            R = int(rng.integers(1, r_max + 1))
+            b = base.scene
+            sc = Scene(dim=b.dim, kappa=b.kappa, shapes=b.shapes, shape_of=b.shape_of, centres=b.centres,
+                       directions=_directions(rng, b.dim, R),
+                       name=f"req{rid}_d{b.dim}_T{b.T}_k{b.kappa:g}_R{R}_g{base.geometry}")
+            out.append(RequestSpec(rid=rid, arrival=t, scene=sc, shape_keys=base.shape_keys, geometry=base.geometry))
+            continue
         dim = 3 if rng.uniform() < p3d else 2
         T = int(round(np.exp(rng.uniform(np.log(t_min), np.log(t_max)))))
         keys = list(lib[dim].keys())
@@ -63,13 +82,11 @@ def request_stream(n: int, rate: float, seed: int, t_min: int = 4, t_max: int = 
         if dim == 2:
             box = 100.0 * np.sqrt(T / 2000.0)
             centres = random_centres(T, 2, max(box, 1.6), 1.5, int(rng.integers(1 << 30)))
-            dirs = plane_wave_directions_2d(2.0 * np.pi * rng.uniform(size=R))
         else:
             box = 40.0 * (T / 1000.0) ** (1.0 / 3.0)
             centres = random_centres(T, 3, max(box, 3.2), 3.0, int(rng.integers(1 << 30)))
-            d = rng.normal(size=(R, 3))
-            dirs = d / np.linalg.norm(d, axis=1, keepdims=True)
+        dirs = _directions(rng, dim, R)
         sc = Scene(dim=dim, kappa=kappa, shapes=[lib[dim][k] for k in keys], shape_of=shape_of,
                    centres=centres, directions=dirs, name=f"req{rid}_d{dim}_T{T}_k{kappa:g}_R{R}")
-        out.append(RequestSpec(rid=rid, arrival=t, scene=sc, shape_keys=keys))
+        out.append(RequestSpec(rid=rid, arrival=t, scene=sc, shape_keys=keys, geometry=rid))
     return out
