@@ -178,24 +178,32 @@ __global__ void norm_reduce_kernel(const double* __restrict__ part, int nblk, do
 
 // Second Gram-Schmidt pass only where the first one cancelled: reorthogonalise when
 // ||w'||^2 = ||w||^2 - sum |h_i|^2 falls below eta^2 ||w||^2 (the test of Daniel, Gragg, Kaufman
-// and Stewart; eta2 = eta^2 is an argument).  One thread per right-hand side.
-__global__ void reorth_decide_kernel(int jcount_h, int R, int ld, const c128* __restrict__ h,
-                                     const double* __restrict__ wn2, int32_t* __restrict__ flag,
-                                     int32_t* __restrict__ count, double eta2, double* __restrict__ ratio_log,
-                                     int m, const int32_t* __restrict__ jdev) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+// and Stewart; eta2 = eta^2 is an argument).  One block per right-hand side; the sum is reduced in
+// a fixed order.
+__global__ __launch_bounds__(256) void reorth_decide_kernel(int jcount_h, int R, int ld, const c128* __restrict__ h,
+                                                            const double* __restrict__ wn2,
+                                                            int32_t* __restrict__ flag, int32_t* __restrict__ count,
+                                                            double eta2, double* __restrict__ ratio_log, int m,
+                                                            const int32_t* __restrict__ jdev) {
+  __shared__ double red[4];
+  const int r = blockIdx.x;
   if (r >= R) return;
   const int jcount = jdev ? *jdev + 1 : jcount_h;
-  double s = 0.0;
-  for (int i = 0; i < jcount; ++i) {
+  double sum = 0.0;
+  for (int i = threadIdx.x; i < jcount; i += blockDim.x) {
     const c128 v = h[(int64_t)r * ld + i];
-    s += v.re * v.re + v.im * v.im;
+    sum += v.re * v.re + v.im * v.im;
   }
+  sum = wave_sum(sum);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double ssum = red[0] + red[1] + red[2] + red[3];
   const double w2 = wn2[r] * wn2[r];
-  const int f = (w2 - s) < eta2 * w2 ? 1 : 0;
+  const int f = (w2 - ssum) < eta2 * w2 ? 1 : 0;
   flag[r] = f;
   count[r] += f;
-  if (ratio_log) ratio_log[(int64_t)r * 2 * m + jcount - 1] = w2 > 0.0 ? sqrt(fmax(w2 - s, 0.0) / w2) : 0.0;
+  if (ratio_log) ratio_log[(int64_t)r * 2 * m + jcount - 1] = w2 > 0.0 ? sqrt(fmax(w2 - ssum, 0.0) / w2) : 0.0;
 }
 
 // Start of a cycle: V_0 = r0 / beta, g = (beta, 0, ...).  Columns with beta == 0 stay inactive.
@@ -229,46 +237,88 @@ __global__ void start_state_kernel(const double* __restrict__ beta, const double
 
 // Column j of H from the Gram-Schmidt coefficients and ||w||, previous rotations, new rotation,
 // residual estimate.  The Arnoldi vectors come from w = K v_j for the operator shift I + K, so the
-// shift is added to the diagonal entry.  One thread per right-hand side.
-__global__ void givens_kernel(int j_h, int m, int R, double shift, const c128* __restrict__ hcol,
-                              const c128* __restrict__ h2,
-                              const double* __restrict__ hnorm,
-                              c128* __restrict__ H, c128* __restrict__ cs, c128* __restrict__ sn,
-                              c128* __restrict__ g, double* __restrict__ res, const double* __restrict__ bnorm,
-                              double tol_h, int32_t* __restrict__ active, int32_t* __restrict__ jlen,
-                              const int32_t* __restrict__ jdev, const double* __restrict__ tol_dev) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= R || !active[r]) return;
+// shift is added to the diagonal entry.  One block per right-hand side.
+//
+// Applying rotations 0..j-1 to the new column b is a chain: with carry_0 = b_0,
+//   H(i, j) = conj(c_i) carry_i + conj(s_i) b_{i+1},   carry_{i+1} = -s_i carry_i + c_i b_{i+1},
+// a first-order linear recurrence in the carry.  Each thread composes the affine maps of one
+// contiguous segment of rotations, a scan over the segments gives every segment its incoming carry,
+// and the segments are then replayed in parallel.  |s_i| <= 1, so the composed maps stay bounded.
+constexpr int kGivensThreads = 256;
+
+__device__ __forceinline__ c128 cmul(c128 a, c128 b) { return c128{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ c128 cadd(c128 a, c128 b) { return c128{a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ c128 cconj(c128 a) { return c128{a.re, -a.im}; }
+
+__global__ __launch_bounds__(kGivensThreads) void givens_kernel(int j_h, int m, int R, double shift,
+                                                               const c128* __restrict__ hcol,
+                                                               const c128* __restrict__ h2,
+                                                               const double* __restrict__ hnorm, c128* __restrict__ H,
+                                                               c128* __restrict__ cs, c128* __restrict__ sn,
+                                                               c128* __restrict__ g, double* __restrict__ res,
+                                                               const double* __restrict__ bnorm, double tol_h,
+                                                               int32_t* __restrict__ active, int32_t* __restrict__ jlen,
+                                                               const int32_t* __restrict__ jdev,
+                                                               const double* __restrict__ tol_dev) {
+  __shared__ c128 segA[kGivensThreads], segB[kGivensThreads];
+  __shared__ c128 carry_in[kGivensThreads + 1];
+  const int r = blockIdx.x;
+  if (r >= R || !active[r]) return;  // uniform over the block
   const int j = jdev ? *jdev : j_h;
   const double tol = jdev ? *tol_dev : tol_h;
+  const int tid = threadIdx.x;
   c128* Hc = H + ((int64_t)r * m + j) * (m + 1);
-  for (int i = 0; i <= j; ++i) {
-    const c128 a1 = hcol[(int64_t)r * (m + 1) + i], a2 = h2[(int64_t)r * (m + 1) + i];
-    Hc[i] = c128{a1.re + a2.re, a1.im + a2.im};
+  const c128* hc1 = hcol + (int64_t)r * (m + 1);
+  const c128* hc2 = h2 + (int64_t)r * (m + 1);
+  const c128* c = cs + (int64_t)r * m;
+  const c128* s = sn + (int64_t)r * m;
+  // b_i = hcol_i + h2_i (+ shift on the diagonal)
+  auto bval = [&](int i) {
+    c128 v = cadd(hc1[i], hc2[i]);
+    if (i == j) v.re += shift;  // H(shift I + K) = H(K) + shift I
+    return v;
+  };
+  // segment of rotations [i0, i1) for this thread
+  const int per = (j + kGivensThreads - 1) / kGivensThreads;
+  const int i0 = min(j, tid * per), i1 = min(j, i0 + per);
+  // compose carry -> A carry + B over the segment
+  c128 A{1.0, 0.0}, B{0.0, 0.0};
+  for (int i = i0; i < i1; ++i) {
+    const c128 ms{-s[i].re, -s[i].im};
+    const c128 cb = cmul(c[i], bval(i + 1));
+    A = cmul(ms, A);
+    B = cadd(cmul(ms, B), cb);
   }
-  Hc[j].re += shift;  // H(shift I + K) = H(K) + shift I
-  Hc[j + 1] = c128{hnorm[r], 0.0};
-  c128* c = cs + (int64_t)r * m;
-  c128* s = sn + (int64_t)r * m;
-  for (int i = 0; i < j; ++i) {
-    const c128 a = Hc[i], b = Hc[i + 1];
-    // tmp = conj(c) a + conj(s) b ; b' = -s a + c b
-    const c128 t{c[i].re * a.re + c[i].im * a.im + s[i].re * b.re + s[i].im * b.im,
-                 c[i].re * a.im - c[i].im * a.re + s[i].re * b.im - s[i].im * b.re};
-    const c128 nb{-(s[i].re * a.re - s[i].im * a.im) + (c[i].re * b.re - c[i].im * b.im),
-                  -(s[i].re * a.im + s[i].im * a.re) + (c[i].re * b.im + c[i].im * b.re)};
-    Hc[i] = t;
-    Hc[i + 1] = nb;
+  segA[tid] = A;
+  segB[tid] = B;
+  __syncthreads();
+  if (tid == 0) {  // incoming carry of every segment (256 compositions, in order)
+    c128 cr = bval(0);
+    for (int t = 0; t < kGivensThreads; ++t) {
+      carry_in[t] = cr;
+      cr = cadd(cmul(segA[t], cr), segB[t]);
+    }
+    carry_in[kGivensThreads] = cr;  // carry_j
   }
-  const c128 a = Hc[j], b = Hc[j + 1];
-  const double den = hypot(hypot(a.re, a.im), hypot(b.re, b.im));
+  __syncthreads();
+  c128 cr = carry_in[tid];
+  for (int i = i0; i < i1; ++i) {
+    const c128 b = bval(i + 1);
+    Hc[i] = cadd(cmul(cconj(c[i]), cr), cmul(cconj(s[i]), b));
+    cr = cadd(cmul(c128{-s[i].re, -s[i].im}, cr), cmul(c[i], b));
+  }
+  if (tid != 0) return;
+  // new rotation on (carry_j, ||w||)
+  const c128 a = carry_in[kGivensThreads];
+  const c128 bb{hnorm[r], 0.0};
+  const double den = hypot(hypot(a.re, a.im), bb.re);
   c128 cj{1.0, 0.0}, sj{0.0, 0.0};
   if (den > 0.0) {
     cj = c128{a.re / den, a.im / den};
-    sj = c128{b.re / den, b.im / den};
+    sj = c128{bb.re / den, bb.im / den};
   }
-  c[j] = cj;
-  s[j] = sj;
+  cs[(int64_t)r * m + j] = cj;
+  sn[(int64_t)r * m + j] = sj;
   Hc[j] = c128{den, 0.0};
   Hc[j + 1] = c128{0.0, 0.0};
   c128* gr = g + (int64_t)r * (m + 1);
@@ -397,7 +447,7 @@ hipError_t launch_arnoldi_orth(KrylovDev k, int j, c128* w, hipStream_t st) {
     c128* h = pass == 0 ? k.hcol : k.h2;
     const int32_t* flag = pass == 0 ? nullptr : k.reorth;
     if (pass == 1)
-      hipLaunchKernelGGL(reorth_decide_kernel, dim3(blocks_for(k.R, 64)), dim3(64), 0, st, jc, k.R, ld, k.hcol, k.wn,
+      hipLaunchKernelGGL(reorth_decide_kernel, dim3(k.R), dim3(256), 0, st, jc, k.R, ld, k.hcol, k.wn,
                          k.reorth, k.n_reorth, k.reorth_eta * k.reorth_eta, k.ratio_log, k.m,
                          (const int32_t*)k.jdev);
     hipLaunchKernelGGL(dots_kernel, dim3(k.nblk, (jc + kGroup - 1) / kGroup, k.R), dim3(kThreads), 0, st, k.V, w,
@@ -414,7 +464,7 @@ hipError_t launch_arnoldi_orth(KrylovDev k, int j, c128* w, hipStream_t st) {
 hipError_t launch_arnoldi_finish(KrylovDev k, int j, c128* w, double tol, hipStream_t st) {
   hipError_t e = launch_norms(w, k.N, k.R, k.part, k.nblk, k.hnorm, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(givens_kernel, dim3(blocks_for(k.R, 64)), dim3(64), 0, st, j, k.m, k.R, 1.0, k.hcol, k.h2, k.hnorm,
+  hipLaunchKernelGGL(givens_kernel, dim3(k.R), dim3(kGivensThreads), 0, st, j, k.m, k.R, 1.0, k.hcol, k.h2, k.hnorm,
                      k.H, k.cs, k.sn, k.g, k.res, k.bnorm, tol, k.active, k.jlen, (const int32_t*)k.jdev,
                      (const double*)k.tol_dev);
   hipLaunchKernelGGL(scale_next_kernel, dim3(blocks_for(k.N, 256), k.R), dim3(256), 0, st, w, k.hnorm, k.N, k.R,

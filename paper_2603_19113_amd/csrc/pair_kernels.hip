@@ -499,11 +499,12 @@ hipError_t dispatch_rt(const PhiEval<T, DIM>& phi, const T* s0, const T* s1, con
 }  // namespace
 
 int pair_chunks_for(int64_t n_sources, int64_t n_targets, int tpt) {
-  // aim for ~16 waves per SIMD (256 CUs x 4 SIMDs) while keeping chunks >= 256 sources
+  // aim for ~16 waves per SIMD (256 CUs x 4 SIMDs) while keeping chunks >= 64 sources; small
+  // systems thus still spread over the chip (N = 8192: 64 chunks, 4096 waves)
   const int64_t waves = (n_targets + 64 * tpt - 1) / (64 * tpt);
   int64_t want = (16384 + waves - 1) / std::max<int64_t>(waves, 1);
-  want = std::min<int64_t>(want, std::max<int64_t>(1, n_sources / 256));
-  want = std::max<int64_t>(1, std::min<int64_t>(want, 64));
+  want = std::min<int64_t>(want, std::max<int64_t>(1, n_sources / 64));
+  want = std::max<int64_t>(1, std::min<int64_t>(want, 128));
   return (int)want;
 }
 
