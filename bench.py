@@ -34,7 +34,11 @@ METRIC = "Helmholtz pair-evals/s per matvec; GMRES solve time @1e-8 rel res; p50
 # 3D: u (12), r^2, rsq, r, D + r, rcp, delta (6), phase fma (2), fract (1), 1/(4 pi r) (1),
 # sin + cos (2), (re, im) (2), complex multiply-add (8) = 34.
 FLOP_PER_PAIR_F32 = {2: 42, 3: 34}
-PEAK_FP32_VECTOR_TFLOPS = 157.3
+# FP32 vector peak from the unit counts: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz =
+# 78.6 TFLOP/s.  The 157.3 TFLOP/s figure counts packed (two-wide) FP32 instructions, which every HIP
+# build here disables, so 78.6 is the ceiling these kernels can reach; both are reported.
+PEAK_FP32_VECTOR_TFLOPS = 78.6
+PEAK_FP32_PACKED_TFLOPS = 157.3
 
 
 def log(msg: str):
@@ -355,7 +359,9 @@ def main() -> int:
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
                      "kernel": kernel_name,
-                     "flop_per_pair": flop_pp},
+                     "flop_per_pair": flop_pp,
+                     "peak_packed_fp32": PEAK_FP32_PACKED_TFLOPS,
+                     "frac_of_packed_peak": achieved / PEAK_FP32_PACKED_TFLOPS},
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a row sample ...")
