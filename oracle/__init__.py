@@ -15,10 +15,12 @@ local_s         per-body matrices A, B, D, B_hat, truncated pseudo-inverses and
 global_system   packing of equivalent points, the off-body matrix G_hat
                 (eq. Gmtx-entries), the operator I + S G_hat (eq. mbody2),
                 right-hand side, dense and GMRES solves, field evaluation
+reconstruct     full MFS sources of each body from the solved equivalent
+                sources and the field near the bodies (Sec. 4.6)
 
 Parity status: every function is pinned by a test in ``tests/test_oracle_*``
 against a closed form, a series solution, a textbook routine or brute force,
 except where a docstring says "parity unpinned".
 """
 
-from . import fundamental, local_s, global_system  # noqa: F401
+from . import fundamental, local_s, global_system, reconstruct  # noqa: F401
