@@ -153,6 +153,71 @@ def serve(args, w, torch) -> int:
     return 0
 
 
+def near(args, sc, mfs, torch, np) -> int:
+    """Reconstruction of every body's MFS sources and field evaluation near the bodies (Sec. 4.6) on the
+    benchmark scene, timed with HIP events.  The equivalent sources are seeded random numbers: the work
+    does not depend on their values, and a full solve is not needed to time these steps."""
+    built = [mfs.build_S(s, sc.kappa) for s in sc.shapes]
+    recons = [mfs.Recon(s, sc.kappa) for s in sc.shapes]
+    scene = mfs.Scene(sc.dim, sc.kappa, sc.shape_of, sc.centres, [s.eqpts for s in sc.shapes],
+                      [b.S64 for b in built], [b.S32 for b in built])
+    R = 1
+    mt, nt = mfs.near_sizes(scene, recons)
+    v = torch.empty((R, mt), dtype=torch.complex128, device="cuda")
+    mfs.plane_wave_colloc(scene, recons, sc.directions[:R], v)
+    g = torch.Generator(device="cuda").manual_seed(20260318)
+    qhat = torch.complex(torch.randn((R, scene.N), generator=g, device="cuda", dtype=torch.float64),
+                         torch.randn((R, scene.N), generator=g, device="cuda", dtype=torch.float64))
+    qm = torch.empty((R, nt), dtype=torch.complex128, device="cuda")
+    # targets: 32 per body, on a circle (sphere: Fibonacci) between the body and its proxy surface
+    per = 32
+    tpl = []
+    for s in sc.shapes:
+        rad = 0.5 * (s.bounding_radius + s.proxy_radius)
+        tpl.append(w_points(sc.dim, per, rad))
+    tg_h = np.concatenate([tpl[int(sh)] + sc.centres[t][None, :] for t, sh in enumerate(sc.shape_of)], 0)
+    tg = torch.from_numpy(tg_h).cuda()
+    u = torch.empty((R, tg_h.shape[0]), dtype=torch.complex128, device="cuda")
+    st = torch.cuda.current_stream()
+
+    def timed(fn, reps=3):
+        fn()  # warm-up (first call builds the scene's near-field tables)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_rec = timed(lambda: mfs.reconstruct(scene, recons, v, qhat, qm))
+    t_eval = timed(lambda: mfs.eval_field_near(scene, recons, qhat, qm, tg, u))
+    # pair count of the near evaluation: per target, n of each body whose proxy surface holds it, k of the others
+    k_of = np.array([s.eqpts.shape[0] for s in sc.shapes])[sc.shape_of]
+    n_of = np.array([s.src.shape[0] for s in sc.shapes])[sc.shape_of]
+    psi = np.array([s.proxy_radius for s in sc.shapes])[sc.shape_of]
+    pairs = 0.0
+    for i0 in range(0, tg_h.shape[0], 4096):
+        blk = tg_h[i0:i0 + 4096]
+        inside = np.linalg.norm(blk[:, None, :] - sc.centres[None, :, :], axis=2) < psi[None, :]
+        pairs += float(np.sum(np.where(inside, n_of[None, :], k_of[None, :])))
+    out = {"workload": sc.name, "N": scene.N, "T": sc.T, "R": R, "mode": "reconstruction and near field",
+           "reconstruct_ms": t_rec, "near_targets": int(tg_h.shape[0]), "eval_near_ms": t_eval,
+           "eval_near_pairs": pairs, "eval_near_pair_evals_per_s_fp64": pairs / (t_eval * 1e-3),
+           "data": "seeded random equivalent sources (timing only)"}
+    for r in recons:
+        r.close()
+    scene.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def w_points(dim, count, radius):
+    import workloads as w
+
+    return w.circle_points(count, radius, 0.1) if dim == 2 else w.fibonacci_sphere(count, radius)
+
+
 def compare(args, sc, mfs, torch, np) -> int:
     """Mixed-precision batched solve vs plain FP64 GMRES, one right-hand side at a time."""
     built = [mfs.build_S(s, sc.kappa) for s in sc.shapes]
@@ -228,6 +293,9 @@ def main() -> int:
     ap.add_argument("--p-sweep", type=float, default=0.3,
                     help="--serve: share of requests that revisit an earlier geometry with new directions")
     ap.add_argument("--no-batching", action="store_true", help="--serve: one solve per request")
+    ap.add_argument("--near", action="store_true",
+                    help="instead of the benchmark line: time the reconstruction of the MFS sources and the "
+                         "near-body field evaluation (seeded equivalent sources)")
     ap.add_argument("--fp64-rhs", type=int, default=0,
                     help="--compare: time only this many single-RHS FP64 solves and scale to R (0: all)")
     ap.add_argument("--compare", action="store_true",
@@ -292,6 +360,8 @@ def main() -> int:
 
     if args.compare:
         return compare(args, sc, mfs, torch, np)
+    if args.near:
+        return near(args, sc, mfs, torch, np)
 
     for i in range(args.warmup):
         t0 = time.perf_counter()

@@ -240,6 +240,63 @@ mfs_status mfs_timing_enable(int32_t on);
 mfs_status mfs_timing_read(mfs_kernel_kind kind, double* total_ms, int64_t* launches, double* pairs);
 
 /* ------------------------------------------------------------------------------------------
+ * Full MFS sources and the field near the bodies (Sec. 4.6).
+ *
+ * The equivalent sources q_hat of body tau represent its scattered field only outside its proxy
+ * surface Psi_tau.  Its own MFS sources (the points y_j of Sec. 3) are reconstructed as
+ *     q_tau^mfs = A_tau^+ ( v_tau - U_tau (G_hat q_hat)_tau ),
+ * v_tau being the Dirichlet data at the collocation points of Gamma_tau and U_tau the map from
+ * values at the equivalent points to values at the collocation points (the one inside S).  Their
+ * field sum_j phi(x - y_j) q_j^mfs is valid everywhere outside the source curve or surface, so the
+ * scattered field can be evaluated up to and on the boundaries.  The calls below that take a
+ * scene accept at most 65535 bodies.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct mfs_recon mfs_recon;    /* per shape: pivoted QR of A, A^+ U, points, proxy radius */
+
+/* Reconstruction factors of one shape, FP64 on the device: the column-pivoted Householder QR of
+ * A = phi(x_i - y_j) (truncated at eps_ls like the solves inside mfs_build_S) and Y = A^+ U.
+ *   desc        as for mfs_build_S (given equivalent points, or paper mode with eqpts = NULL)
+ *   psi_radius  radius of the proxy surface about the body centre: a target x is inside Psi_tau
+ *               when |x - c_tau| < psi_radius
+ * Synchronous.  Errors: MFS_ERR_ARG, MFS_ERR_RANK, MFS_ERR_NOMEM, MFS_ERR_HIP. */
+mfs_status mfs_recon_create(const mfs_shape_desc* desc, double psi_radius, mfs_recon** out, void* stream);
+
+/* Free the factors.  Waits for the device (kernels on any stream may still read them). */
+mfs_status mfs_recon_destroy(mfs_recon* recon);
+
+/* Collocation points m, MFS sources n, equivalent points k, numerical rank of A.  Host outputs may
+ * be NULL. */
+mfs_status mfs_recon_size(const mfs_recon* recon, int64_t* m, int64_t* n, int64_t* k, int64_t* rank);
+
+/* Totals over the scene's bodies: collocation points (sum m_tau) and MFS sources (sum n_tau), the
+ * lengths of the per-body arrays below.  recon: host array [n_shapes] of factors, one per shape of
+ * the scene, with the scene's k and kappa.  Synchronous on the first call with a new set. */
+mfs_status mfs_near_sizes(const mfs_scene* scene, const mfs_recon* const* recon, int64_t* colloc_total,
+                          int64_t* src_total);
+
+/* v = -exp(i kappa d_r . x) at every body's collocation points, device complex128
+ * [R][colloc_total], bodies in order (footnote to eq. BVP).  Asynchronous. */
+mfs_status mfs_plane_wave_colloc(const mfs_scene* scene, const mfs_recon* const* recon, const double* dirs_host,
+                                 int32_t R, void* v_dev, void* stream);
+
+/* q^mfs of every body (Sec. 4.6), FP64.
+ *   v_colloc_dev  device complex128 [R][colloc_total]: Dirichlet data at the collocation points
+ *   qhat_dev      device complex128 [R][N]: solved equivalent sources
+ *   qmfs_dev      device complex128 [R][src_total] output, bodies in order
+ * Asynchronous. */
+mfs_status mfs_reconstruct(const mfs_scene* scene, const mfs_recon* const* recon, const void* v_colloc_dev,
+                           const void* qhat_dev, int32_t R, void* qmfs_dev, void* stream);
+
+/* Scattered field at M targets anywhere outside the MFS source curves or surfaces, FP64: body tau
+ * contributes through its MFS sources where |x - c_tau| < psi_radius and through its equivalent
+ * points elsewhere.  A target on an MFS source gives an infinite value.
+ *   targets_dev  device double [M][dim]; u_dev device complex128 [R][M]
+ * Asynchronous. */
+mfs_status mfs_eval_field_near(const mfs_scene* scene, const mfs_recon* const* recon, const void* qhat_dev,
+                               const void* qmfs_dev, int32_t R, const double* targets_dev, int64_t M, void* u_dev,
+                               void* stream);
+
+/* ------------------------------------------------------------------------------------------
  * Device allocation cache.  Scene tables, pair partial sums and Krylov bases are drawn from a
  * process-wide cache of device blocks: a freed block stays on its device and is reused by the next
  * request whose size it fits (at most twice the size asked for), with the new owner's stream

@@ -213,12 +213,14 @@ __global__ void qr_apply_kernel(QR q, int s) {
 
 // Back substitution R11 x = rhs(0:r) per right-hand side column (one block each).
 // If perm != null: X(perm[i], c) = x_i (i < r), X(perm[i], c) = 0 (r <= i < cols_out).
-// Otherwise X(i, c) = x_i for i < r.
+// Otherwise X(i, c) = x_i for i < r.  Column c sits at c * ldr in rhs and c * ldx in X, or where
+// the column map puts it.
 __global__ void backsub_kernel(const c128* __restrict__ M, int ldm, const c128* __restrict__ alpha, int r,
-                               c128* rhs, int ldr, const int* __restrict__ perm, int cols_out, c128* X, int ldx) {
+                               c128* rhs, int ldr, const int* __restrict__ perm, int cols_out, c128* X, int ldx,
+                               ColMap cm) {
   __shared__ c128 xi_sh;
   const int c = blockIdx.x;
-  c128* bcol = rhs + (int64_t)c * ldr;
+  c128* bcol = rhs + (cm.bodies ? cm.in_offset(c) : (int64_t)c * ldr);
   for (int i = r - 1; i >= 0; --i) {
     if (threadIdx.x == 0) {
       const c128 a = alpha[i];
@@ -238,11 +240,37 @@ __global__ void backsub_kernel(const c128* __restrict__ M, int ldm, const c128* 
     }
     __syncthreads();
   }
-  c128* xc = X + (int64_t)c * ldx;
+  c128* xc = X + (cm.bodies ? cm.out_offset(c) : (int64_t)c * ldx);
   if (perm) {
     for (int i = threadIdx.x; i < cols_out; i += blockDim.x) xc[perm[i]] = i < r ? bcol[i] : c128{0.0, 0.0};
   } else {
     for (int i = threadIdx.x; i < r; i += blockDim.x) xc[i] = bcol[i];
+  }
+}
+
+// Q^H applied to many right-hand sides with the stored reflectors of a factored matrix (one block
+// per column): for s < rank, col[s:] -= v_s tau_s (v_s^H col[s:]), v_s = M[s:, s].
+__global__ void qr_reflect_kernel(const c128* __restrict__ M, int rows, int ldm, const double* __restrict__ tau,
+                                  int rank, c128* rhs, int ldr, ColMap cm) {
+  __shared__ double red[kT / 64];
+  c128* col = rhs + (cm.bodies ? cm.in_offset(blockIdx.x) : (int64_t)blockIdx.x * ldr);
+  for (int s = 0; s < rank; ++s) {
+    const c128* v = M + (int64_t)s * ldm;
+    double dr = 0.0, di = 0.0;
+    for (int i = s + threadIdx.x; i < rows; i += blockDim.x) {
+      const c128 t = cconjmul(v[i], col[i]);
+      dr += t.re;
+      di += t.im;
+    }
+    dr = block_sum(dr, red);
+    di = block_sum(di, red);
+    const c128 f{tau[s] * dr, tau[s] * di};
+    for (int i = s + threadIdx.x; i < rows; i += blockDim.x) {
+      const c128 t = cmul(v[i], f);
+      col[i].re -= t.re;
+      col[i].im -= t.im;
+    }
+    __syncthreads();
   }
 }
 
@@ -335,7 +363,8 @@ mfs_status assemble(int dim, double kappa, const double* tg, int rows, const dou
 // and write the basic solution X (cols x nrhs, ld = cols).  Returns the numerical rank and
 // |R_11| / |R_rr| through rank_out / ratio_out.  If X is null only the factorisation is done.
 mfs_status qr_solve(DevMem& mem, c128* M, int rows, int cols, c128* rhs, int nrhs, double eps, int kcap, c128* X,
-                    int* rank_out, double* ratio_out, int** perm_out, c128** alpha_out, hipStream_t st) {
+                    int* rank_out, double* ratio_out, int** perm_out, c128** alpha_out, hipStream_t st,
+                    double** tau_out = nullptr) {
   QR q{};
   q.M = M;
   q.rows = rows;
@@ -372,13 +401,14 @@ mfs_status qr_solve(DevMem& mem, c128* M, int rows, int cols, c128* rhs, int nrh
   }
   if (X && nrhs > 0) {
     hipLaunchKernelGGL(backsub_kernel, dim3(nrhs), dim3(kT), 0, st, M, rows, q.alpha, rank, rhs, rows, q.perm, cols,
-                       X, cols);
+                       X, cols, ColMap{});
     LSQ_HIP(hipGetLastError());
   }
   *rank_out = rank;
   if (ratio_out) *ratio_out = ratio;
   if (perm_out) *perm_out = q.perm;
   if (alpha_out) *alpha_out = q.alpha;
+  if (tau_out) *tau_out = q.tau;
   return MFS_OK;
 }
 
@@ -478,7 +508,7 @@ mfs_status build_S_impl(const mfs_shape_desc* d, void* S64, void* S32, int64_t* 
       LSQ_HIP(hipMemcpy2DAsync(R12, sizeof(c128) * p, B + (size_t)k * p, sizeof(c128) * p, sizeof(c128) * k, m - k,
                                hipMemcpyDeviceToDevice, st));
       hipLaunchKernelGGL(backsub_kernel, dim3(m - k), dim3(kT), 0, st, B, p, alphaB, k, R12, p, (const int*)nullptr, k,
-                         T, k);
+                         T, k, ColMap{});
       LSQ_HIP(hipGetLastError());
     }
     LSQ_HIP(mem.alloc(&Z, (size_t)k * m));
@@ -535,6 +565,148 @@ mfs_status build_S_impl(const mfs_shape_desc* d, void* S64, void* S32, int64_t* 
     diag[3] = den > 0.0 ? std::sqrt(num / den) : 0.0;
   }
   return MFS_OK;
+}
+
+// Factors for the reconstruction of a body's MFS sources (Sec. 4.6): the pivoted QR of A, kept,
+// and Y = A^+ U with U the map from values at the equivalent points to values at the collocation
+// points ((B_hat^+ B)^T for given points, conj(Z) = (Z*)^T in paper mode; the same U as in S).
+mfs_status build_recon_impl(const mfs_shape_desc* d, ReconFactors* out, hipStream_t st) {
+  if (!d || !out) return fail(MFS_ERR_ARG, "recon: null descriptor or output");
+  if (d->dim != 2 && d->dim != 3) return fail(MFS_ERR_ARG, "recon: dim must be 2 or 3");
+  if (!(d->kappa > 0.0)) return fail(MFS_ERR_ARG, "recon: kappa must be > 0");
+  if (!d->colloc || !d->src || !d->proxy) return fail(MFS_ERR_ARG, "recon: null point set");
+  if (d->m < 1 || d->n < 1 || d->p < 1 || d->n > d->m) return fail(MFS_ERR_ARG, "recon: need 1 <= n <= m, p >= 1");
+  if (d->m > 16384 || d->p > 16384) return fail(MFS_ERR_ARG, "recon: m and p are limited to 16384");
+  if (!(d->eps_ls > 0.0) || !(d->eps_ls < 1.0)) return fail(MFS_ERR_ARG, "recon: need 0 < eps_ls < 1");
+  const bool paper = d->eqpts == nullptr;
+  if (!paper && (d->k < 1 || d->k > d->p || d->k > 4096))
+    return fail(MFS_ERR_ARG, "recon: given points need 1 <= k <= min(p, 4096)");
+  if (paper && (d->k_cap < 1 || d->k_cap > std::min<int64_t>(std::min(d->p, d->m), 4096) ||
+                !(d->eps_skel > 0.0) || !(d->eps_skel < 1.0)))
+    return fail(MFS_ERR_ARG, "recon: paper mode needs 1 <= k_cap <= min(p, m, 4096) and 0 < eps_skel < 1");
+  const int dim = d->dim, m = (int)d->m, n = (int)d->n, p = (int)d->p;
+  DevMem mem;
+  double *xc, *ys, *zp;
+  LSQ_HIP(mem.alloc(&xc, (size_t)m * dim));
+  LSQ_HIP(mem.alloc(&ys, (size_t)n * dim));
+  LSQ_HIP(mem.alloc(&zp, (size_t)p * dim));
+  LSQ_HIP(hipMemcpyAsync(xc, d->colloc, sizeof(double) * m * dim, hipMemcpyHostToDevice, st));
+  LSQ_HIP(hipMemcpyAsync(ys, d->src, sizeof(double) * n * dim, hipMemcpyHostToDevice, st));
+  LSQ_HIP(hipMemcpyAsync(zp, d->proxy, sizeof(double) * p * dim, hipMemcpyHostToDevice, st));
+  mfs_status stt;
+  int k = 0;
+  c128* U = nullptr;  // m x k
+  if (!paper) {
+    k = (int)d->k;
+    double* xh;
+    c128 *Bh, *B, *X;
+    LSQ_HIP(mem.alloc(&xh, (size_t)k * dim));
+    LSQ_HIP(hipMemcpyAsync(xh, d->eqpts, sizeof(double) * k * dim, hipMemcpyHostToDevice, st));
+    LSQ_HIP(mem.alloc(&Bh, (size_t)p * k));
+    LSQ_HIP(mem.alloc(&B, (size_t)p * m));
+    LSQ_HIP(mem.alloc(&X, (size_t)k * m));
+    LSQ_HIP(mem.alloc(&U, (size_t)m * k));
+    if ((stt = assemble(dim, d->kappa, zp, p, xh, k, Bh, p, st)) != MFS_OK) return stt;
+    if ((stt = assemble(dim, d->kappa, zp, p, xc, m, B, p, st)) != MFS_OK) return stt;
+    int rankB = 0;
+    if ((stt = qr_solve(mem, Bh, p, k, B, m, d->eps_ls, k, X, &rankB, nullptr, nullptr, nullptr, st)) != MFS_OK)
+      return stt;
+    if ((stt = transpose(X, k, k, m, U, m, st)) != MFS_OK) return stt;
+  } else {
+    const int kcap = (int)d->k_cap;
+    c128 *B, *T, *Z;
+    LSQ_HIP(mem.alloc(&B, (size_t)p * m));
+    if ((stt = assemble(dim, d->kappa, zp, p, xc, m, B, p, st)) != MFS_OK) return stt;
+    int* perm = nullptr;
+    c128* alphaB = nullptr;
+    int rankB = 0;
+    if ((stt = qr_solve(mem, B, p, m, nullptr, 0, d->eps_skel, kcap, nullptr, &rankB, nullptr, &perm, &alphaB, st)) !=
+        MFS_OK)
+      return stt;
+    k = rankB;
+    LSQ_HIP(mem.alloc(&T, (size_t)k * std::max(1, m - k)));
+    if (m > k) {
+      c128* R12;
+      LSQ_HIP(mem.alloc(&R12, (size_t)p * (m - k)));
+      LSQ_HIP(hipMemcpy2DAsync(R12, sizeof(c128) * p, B + (size_t)k * p, sizeof(c128) * p, sizeof(c128) * k, m - k,
+                               hipMemcpyDeviceToDevice, st));
+      hipLaunchKernelGGL(backsub_kernel, dim3(m - k), dim3(kT), 0, st, B, p, alphaB, k, R12, p, (const int*)nullptr, k,
+                         T, k, ColMap{});
+      LSQ_HIP(hipGetLastError());
+    }
+    LSQ_HIP(mem.alloc(&Z, (size_t)k * m));
+    hipLaunchKernelGGL(build_zstar_kernel, dim3((k + 127) / 128, m), dim3(128), 0, st, perm, k, m, T, k, Z);
+    LSQ_HIP(hipGetLastError());
+    LSQ_HIP(mem.alloc(&U, (size_t)m * k));
+    if ((stt = transpose(Z, k, k, m, U, m, st)) != MFS_OK) return stt;
+  }
+  // A = phi(x - y), factored in place; Y = A^+ U
+  c128 *A, *Y;
+  LSQ_HIP(mem.alloc(&A, (size_t)m * n));
+  LSQ_HIP(mem.alloc(&Y, (size_t)n * k));
+  if ((stt = assemble(dim, d->kappa, xc, m, ys, n, A, m, st)) != MFS_OK) return stt;
+  int rankA = 0;
+  int* permA = nullptr;
+  c128* alphaA = nullptr;
+  double* tauA = nullptr;
+  if ((stt = qr_solve(mem, A, m, n, U, k, d->eps_ls, n, Y, &rankA, nullptr, &permA, &alphaA, st, &tauA)) != MFS_OK)
+    return stt;
+  // keep what applying A^+ to new data needs, plus Y and the point sets, in one device block
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t oQA = 0, oAl = oQA + up(sizeof(c128) * m * n), oTau = oAl + up(sizeof(c128) * n),
+               oPerm = oTau + up(sizeof(double) * n), oY = oPerm + up(sizeof(int) * n),
+               oXc = oY + up(sizeof(c128) * n * k), oYs = oXc + up(sizeof(double) * m * dim),
+               total = oYs + up(sizeof(double) * n * dim);
+  size_t got = 0;
+  hipError_t pe = hipSuccess;
+  char* blk = static_cast<char*>(pool_alloc(total, st, &got, &pe));
+  if (!blk) return fail(MFS_ERR_NOMEM, std::string("recon: device allocation failed: ") + hipGetErrorString(pe));
+  auto d2d = [&](size_t off, const void* src, size_t bytes) {
+    return hipMemcpyAsync(blk + off, src, bytes, hipMemcpyDeviceToDevice, st);
+  };
+  hipError_t e = d2d(oQA, A, sizeof(c128) * m * n);
+  if (e == hipSuccess) e = d2d(oAl, alphaA, sizeof(c128) * n);
+  if (e == hipSuccess) e = d2d(oTau, tauA, sizeof(double) * n);
+  if (e == hipSuccess) e = d2d(oPerm, permA, sizeof(int) * n);
+  if (e == hipSuccess) e = d2d(oY, Y, sizeof(c128) * n * k);
+  if (e == hipSuccess) e = d2d(oXc, xc, sizeof(double) * m * dim);
+  if (e == hipSuccess) e = d2d(oYs, ys, sizeof(double) * n * dim);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);  // the temporaries above are freed on return
+  if (e != hipSuccess) {
+    pool_free(blk, got, st);
+    return fail(MFS_ERR_HIP, std::string("recon: ") + hipGetErrorString(e));
+  }
+  out->block = blk;
+  out->block_bytes = got;
+  out->QA = reinterpret_cast<c128*>(blk + oQA);
+  out->alpha = reinterpret_cast<c128*>(blk + oAl);
+  out->tau = reinterpret_cast<double*>(blk + oTau);
+  out->perm = reinterpret_cast<int*>(blk + oPerm);
+  out->Y = reinterpret_cast<c128*>(blk + oY);
+  out->colloc = reinterpret_cast<double*>(blk + oXc);
+  out->src = reinterpret_cast<double*>(blk + oYs);
+  out->dim = dim;
+  out->m = m;
+  out->n = n;
+  out->k = k;
+  out->rank = rankA;
+  out->kappa = d->kappa;
+  return MFS_OK;
+}
+
+hipError_t launch_qr_reflect(const c128* QA, int rows, int ld, const double* tau, int rank, c128* rhs, int ldr,
+                             int ncols, const ColMap& cm, hipStream_t st) {
+  if (ncols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(qr_reflect_kernel, dim3(ncols), dim3(kT), 0, st, QA, rows, ld, tau, rank, rhs, ldr, cm);
+  return hipGetLastError();
+}
+
+hipError_t launch_backsub(const c128* QA, int ld, const c128* alpha, int rank, c128* rhs, int ldr, const int* perm,
+                          int cols_out, c128* X, int ldx, int ncols, const ColMap& cm, hipStream_t st) {
+  if (ncols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(backsub_kernel, dim3(ncols), dim3(kT), 0, st, QA, ld, alpha, rank, rhs, ldr, perm, cols_out, X,
+                     ldx, cm);
+  return hipGetLastError();
 }
 
 }  // namespace mfs

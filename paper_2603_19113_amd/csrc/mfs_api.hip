@@ -115,6 +115,17 @@ struct mfs_scene {
   Buf x64, x32, l32, lsq, centres, body_of, body_ptr, shape_of, k_dev, S64_tab, S32_tab;
   // workspaces
   Buf partial, q32, dirs, kry, vecs;
+  // near-field tables for the last set of reconstruction factors used with this scene
+  std::vector<const mfs_recon*> near_key;
+  Buf near_tab;
+  mfs::NearTables near{};
+  std::vector<std::vector<int32_t>> bodies_of_shape;
+  std::vector<const int32_t*> bodies_dev;
+};
+
+struct mfs_recon {
+  mfs::ReconFactors f{};
+  double psi_radius = 0.0;
 };
 
 namespace {
@@ -185,6 +196,90 @@ mfs_status apply_mixed(mfs_scene* s, const c128* q, c128* y, int R, hipStream_t 
   return MFS_OK;
 }
 
+// Device tables tying the scene's bodies to the reconstruction factors of their shapes; rebuilt
+// when the factors passed in change.  Synchronous on the first call with a new set.
+mfs_status prepare_near(mfs_scene* s, const mfs_recon* const* recon, hipStream_t st) {
+  if (!recon) return fail(MFS_ERR_ARG, "reconstruction factors: null array");
+  if (s->dev.T > 65535) return fail(MFS_ERR_ARG, "near-field calls support at most 65535 bodies (one grid row each)");
+  const int ns = s->n_shapes;
+  bool same = (int)s->near_key.size() == ns;
+  for (int i = 0; i < ns; ++i) {
+    const mfs_recon* r = recon[i];
+    if (!r) return fail(MFS_ERR_ARG, "reconstruction factors: null handle for shape " + std::to_string(i));
+    if (r->f.dim != s->dev.dim || r->f.k != s->k_of_shape[i] ||
+        std::fabs(r->f.kappa - s->dev.kappa) > 1e-12 * s->dev.kappa)
+      return fail(MFS_ERR_ARG, "reconstruction factors of shape " + std::to_string(i) +
+                                   " do not match the scene (dim, k or kappa)");
+    same = same && s->near_key[i] == r;
+  }
+  if (same) return MFS_OK;
+  const int64_t T = s->dev.T;
+  std::vector<int32_t> shape_of(T);
+  MFS_HIP_TRY(hipMemcpyAsync(shape_of.data(), s->shape_of.p, sizeof(int32_t) * T, hipMemcpyDeviceToHost, st));
+  MFS_HIP_TRY(hipStreamSynchronize(st));
+  std::vector<int64_t> cptr(T + 1, 0), sptr(T + 1, 0);
+  s->bodies_of_shape.assign(ns, {});
+  for (int64_t b = 0; b < T; ++b) {
+    const int sh = shape_of[b];
+    cptr[b + 1] = cptr[b] + recon[sh]->f.m;
+    sptr[b + 1] = sptr[b] + recon[sh]->f.n;
+    s->bodies_of_shape[sh].push_back((int32_t)b);
+  }
+  std::vector<const void*> colloc(ns), src(ns), Y(ns);
+  std::vector<int32_t> mm(ns), nn(ns);
+  std::vector<double> psi2(ns);
+  NearTables t{};
+  t.mmax = t.nmax = t.kmax = 0;
+  for (int i = 0; i < ns; ++i) {
+    const ReconFactors& f = recon[i]->f;
+    colloc[i] = f.colloc;
+    src[i] = f.src;
+    Y[i] = f.Y;
+    mm[i] = f.m;
+    nn[i] = f.n;
+    psi2[i] = recon[i]->psi_radius * recon[i]->psi_radius;
+    t.mmax = std::max(t.mmax, f.m);
+    t.nmax = std::max(t.nmax, f.n);
+    t.kmax = std::max(t.kmax, f.k);
+  }
+  // one host image of all tables, copied in one go
+  std::vector<char> img;
+  auto put = [&](const void* p, size_t bytes) {
+    const size_t off = (img.size() + 255) / 256 * 256;
+    img.resize(off + bytes);
+    std::memcpy(img.data() + off, p, bytes);
+    return off;
+  };
+  const size_t oC = put(colloc.data(), sizeof(void*) * ns), oS = put(src.data(), sizeof(void*) * ns),
+               oY = put(Y.data(), sizeof(void*) * ns), oM = put(mm.data(), sizeof(int32_t) * ns),
+               oN = put(nn.data(), sizeof(int32_t) * ns), oP = put(psi2.data(), sizeof(double) * ns),
+               oCp = put(cptr.data(), sizeof(int64_t) * (T + 1)), oSp = put(sptr.data(), sizeof(int64_t) * (T + 1));
+  std::vector<size_t> oB(ns);
+  const int32_t none = -1;  // a shape with no bodies still gets a (never read) one-entry list
+  for (int i = 0; i < ns; ++i) {
+    const std::vector<int32_t>& bl = s->bodies_of_shape[i];
+    oB[i] = bl.empty() ? put(&none, sizeof(int32_t)) : put(bl.data(), sizeof(int32_t) * bl.size());
+  }
+  MFS_TRY(ensure(s->near_tab, img.size(), &s->bytes, st));
+  char* base = static_cast<char*>(s->near_tab.p);
+  MFS_HIP_TRY(hipMemcpyAsync(base, img.data(), img.size(), hipMemcpyHostToDevice, st));
+  MFS_HIP_TRY(hipStreamSynchronize(st));  // img is released on return
+  t.colloc_of_shape = reinterpret_cast<const double* const*>(base + oC);
+  t.src_of_shape = reinterpret_cast<const double* const*>(base + oS);
+  t.Y_of_shape = reinterpret_cast<const c128* const*>(base + oY);
+  t.m_of_shape = reinterpret_cast<const int32_t*>(base + oM);
+  t.n_of_shape = reinterpret_cast<const int32_t*>(base + oN);
+  t.psi2_of_shape = reinterpret_cast<const double*>(base + oP);
+  t.cptr = reinterpret_cast<const int64_t*>(base + oCp);
+  t.sptr = reinterpret_cast<const int64_t*>(base + oSp);
+  t.Mtot = cptr[T];
+  t.Ntot = sptr[T];
+  s->bodies_dev.assign(ns, nullptr);
+  for (int i = 0; i < ns; ++i) s->bodies_dev[i] = reinterpret_cast<const int32_t*>(base + oB[i]);
+  s->near = t;
+  s->near_key.assign(recon, recon + ns);
+  return MFS_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -340,7 +435,7 @@ mfs_status mfs_scene_create(int32_t dim, double kappa, int64_t T, const int32_t*
 mfs_status mfs_scene_destroy(mfs_scene* s) {
   if (!s) return MFS_OK;
   Buf* all[] = {&s->x64, &s->x32, &s->l32, &s->lsq, &s->centres, &s->body_of, &s->body_ptr, &s->shape_of, &s->k_dev, &s->S64_tab,
-                &s->S32_tab, &s->partial, &s->q32, &s->dirs, &s->kry, &s->vecs};
+                &s->S32_tab, &s->partial, &s->q32, &s->dirs, &s->kry, &s->vecs, &s->near_tab};
   for (Buf* b : all) release(*b, &s->bytes, s->last_stream);
   delete s;
   return MFS_OK;
@@ -768,6 +863,147 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
   if (max_relres() > opts->tol)
     return fail(MFS_ERR_NOCONV, "solve: relative residual " + std::to_string(max_relres()) + " above tol after " +
                                     std::to_string(total_it) + " iterations");
+  return MFS_OK;
+}
+
+// ---------------------------------------------------------- reconstruction ---
+mfs_status mfs_recon_create(const mfs_shape_desc* desc, double psi_radius, mfs_recon** out, void* stream) {
+  g_last_error.clear();
+  if (!out) return fail(MFS_ERR_ARG, "recon_create: out is null");
+  *out = nullptr;
+  if (!(psi_radius > 0.0) || !std::isfinite(psi_radius))
+    return fail(MFS_ERR_ARG, "recon_create: psi_radius must be positive and finite");
+  mfs_recon* r = new mfs_recon();
+  r->psi_radius = psi_radius;
+  const mfs_status st = build_recon_impl(desc, &r->f, as_stream(stream));
+  if (st != MFS_OK) {
+    delete r;
+    return st;
+  }
+  *out = r;
+  return MFS_OK;
+}
+
+mfs_status mfs_recon_destroy(mfs_recon* r) {
+  if (!r) return MFS_OK;
+  (void)hipDeviceSynchronize();  // kernels on any stream may still read the factors
+  pool_free(r->f.block, r->f.block_bytes, nullptr);
+  delete r;
+  return MFS_OK;
+}
+
+mfs_status mfs_recon_size(const mfs_recon* r, int64_t* m, int64_t* n, int64_t* k, int64_t* rank) {
+  if (!r) return fail(MFS_ERR_ARG, "recon_size: null handle");
+  if (m) *m = r->f.m;
+  if (n) *n = r->f.n;
+  if (k) *k = r->f.k;
+  if (rank) *rank = r->f.rank;
+  return MFS_OK;
+}
+
+mfs_status mfs_near_sizes(const mfs_scene* sc, const mfs_recon* const* recon, int64_t* colloc_total,
+                          int64_t* src_total) {
+  MFS_TRY(check_scene(sc));
+  mfs_scene* s = const_cast<mfs_scene*>(sc);
+  MFS_TRY(prepare_near(s, recon, s->last_stream));
+  if (colloc_total) *colloc_total = s->near.Mtot;
+  if (src_total) *src_total = s->near.Ntot;
+  return MFS_OK;
+}
+
+mfs_status mfs_plane_wave_colloc(const mfs_scene* sc, const mfs_recon* const* recon, const double* dirs_host,
+                                 int32_t R, void* v_dev, void* stream) {
+  MFS_TRY(check_scene(sc));
+  if (R < 1 || !dirs_host || !v_dev) return fail(MFS_ERR_ARG, "plane_wave_colloc: bad R or null pointer");
+  mfs_scene* s = const_cast<mfs_scene*>(sc);
+  hipStream_t st = as_stream(stream);
+  s->last_stream = st;
+  MFS_TRY(prepare_near(s, recon, st));
+  MFS_TRY(ensure(s->dirs, sizeof(double) * R * s->dev.dim, &s->bytes, st));
+  MFS_HIP_TRY(hipMemcpyAsync(s->dirs.p, dirs_host, sizeof(double) * R * s->dev.dim, hipMemcpyHostToDevice, st));
+  MFS_HIP_TRY(hipStreamSynchronize(st));
+  MFS_HIP_TRY(launch_plane_wave_colloc(s->dev, s->near, static_cast<double*>(s->dirs.p), R, static_cast<c128*>(v_dev),
+                                       st));
+  return MFS_OK;
+}
+
+mfs_status mfs_reconstruct(const mfs_scene* sc, const mfs_recon* const* recon, const void* v_colloc_dev,
+                           const void* qhat_dev, int32_t R, void* qmfs_dev, void* stream) {
+  MFS_TRY(check_scene(sc));
+  if (R < 1 || !v_colloc_dev || !qhat_dev || !qmfs_dev) return fail(MFS_ERR_ARG, "reconstruct: bad R or null pointer");
+  mfs_scene* s = const_cast<mfs_scene*>(sc);
+  hipStream_t st = as_stream(stream);
+  s->last_stream = st;
+  MFS_TRY(prepare_near(s, recon, st));
+  const int64_t N = s->dev.N;
+  const NearTables& t = s->near;
+  // w_hat = G_hat qhat (FP64): the field of the other bodies at each body's equivalent points
+  const int nch = pair_chunks_for(N, N, tpt_for(MFS_FP64));
+  MFS_TRY(ensure(s->partial, (size_t)nch * R * N * sizeof(c128), &s->bytes, st));
+  size_t gw = 0, gv = 0;
+  hipError_t e = hipSuccess;
+  c128* what = static_cast<c128*>(pool_alloc(sizeof(c128) * (size_t)R * N, st, &gw, &e));
+  if (!what) return fail(MFS_ERR_NOMEM, std::string("reconstruct: ") + hipGetErrorString(e));
+  c128* vs = static_cast<c128*>(pool_alloc(sizeof(c128) * (size_t)R * t.Mtot, st, &gv, &e));
+  if (!vs) {
+    pool_free(what, gw, st);
+    return fail(MFS_ERR_NOMEM, std::string("reconstruct: ") + hipGetErrorString(e));
+  }
+  struct Temps {
+    void *a, *b;
+    size_t na, nb;
+    hipStream_t st;
+    ~Temps() {
+      pool_free(a, na, st);
+      pool_free(b, nb, st);
+    }
+  } temps{what, vs, gw, gv, st};
+  {
+    TimedLaunch tl(MFS_KERNEL_PAIR_F64, s->dev.offbody_pairs * R, st);
+    MFS_HIP_TRY(launch_ghat_f64(s->dev, static_cast<const c128*>(qhat_dev), R, static_cast<c128*>(s->partial.p), nch,
+                                st));
+  }
+  MFS_HIP_TRY(launch_reduce_partials_f64(static_cast<c128*>(s->partial.p), nch, N, R, what, st));
+  // A^+ v per body: Householder reflectors then back substitution, shape by shape, in place on a copy
+  MFS_HIP_TRY(hipMemcpyAsync(vs, v_colloc_dev, sizeof(c128) * (size_t)R * t.Mtot, hipMemcpyDeviceToDevice, st));
+  for (int sh = 0; sh < s->n_shapes; ++sh) {
+    const int nb = (int)s->bodies_of_shape[sh].size();
+    if (nb == 0) continue;
+    const ReconFactors& f = recon[sh]->f;
+    ColMap cm;
+    cm.bodies = s->bodies_dev[sh];
+    cm.nb = nb;
+    cm.ptr_in = t.cptr;
+    cm.ld_in = t.Mtot;
+    cm.ptr_out = t.sptr;
+    cm.ld_out = t.Ntot;
+    const int ncols = nb * R;
+    MFS_HIP_TRY(launch_qr_reflect(f.QA, f.m, f.m, f.tau, f.rank, vs, 0, ncols, cm, st));
+    MFS_HIP_TRY(launch_backsub(f.QA, f.m, f.alpha, f.rank, vs, 0, f.perm, f.n, static_cast<c128*>(qmfs_dev), 0,
+                               ncols, cm, st));
+  }
+  // q_mfs -= (A^+ U) w_hat
+  MFS_HIP_TRY(launch_recon_combine(s->dev, t, what, R, static_cast<c128*>(qmfs_dev), st));
+  return MFS_OK;
+}
+
+mfs_status mfs_eval_field_near(const mfs_scene* sc, const mfs_recon* const* recon, const void* qhat_dev,
+                               const void* qmfs_dev, int32_t R, const double* targets_dev, int64_t M, void* u_dev,
+                               void* stream) {
+  MFS_TRY(check_scene(sc));
+  if (R < 1 || M < 0 || !qhat_dev || !qmfs_dev || !u_dev || (M > 0 && !targets_dev))
+    return fail(MFS_ERR_ARG, "eval_field_near: bad sizes or pointers");
+  if (M == 0) return MFS_OK;
+  mfs_scene* s = const_cast<mfs_scene*>(sc);
+  hipStream_t st = as_stream(stream);
+  s->last_stream = st;
+  MFS_TRY(prepare_near(s, recon, st));
+  const int nch = near_chunks_for(s->dev.T, M);
+  MFS_TRY(ensure(s->partial, (size_t)nch * R * M * sizeof(c128), &s->bytes, st));
+  c128* part = static_cast<c128*>(s->partial.p);
+  MFS_HIP_TRY(launch_eval_near(s->dev, s->near, static_cast<const c128*>(qhat_dev), static_cast<const c128*>(qmfs_dev),
+                               R, targets_dev, M, part, nch, st));
+  MFS_HIP_TRY(launch_reduce_partials_f64(part, nch, M, R, static_cast<c128*>(u_dev), st));
   return MFS_OK;
 }
 

@@ -162,6 +162,62 @@ void pool_trim();
 void pool_set_limit(size_t bytes);
 hipStream_t private_stream(hipError_t* err);
 
+// Reconstruction factors of one shape (lsq.hip): the pivoted QR of A (reflectors below the
+// diagonal, R above it with its diagonal in alpha), Y = A^+ U, and the collocation points and MFS
+// sources of the shape (body frame, [count][dim]); all in one device block from the pool.
+struct ReconFactors {
+  void* block;
+  size_t block_bytes;
+  c128* QA;      // m x n, ld m
+  c128* alpha;   // [n]
+  double* tau;   // [n]
+  int* perm;     // [n]
+  c128* Y;       // n x k, ld n
+  double* colloc;
+  double* src;
+  int dim, m, n, k, rank;
+  double kappa;
+};
+mfs_status build_recon_impl(const mfs_shape_desc* d, ReconFactors* out, hipStream_t st);
+// Columns of a batched solve that live inside [R][total] arrays: column c is body bodies[c % nb]
+// and right-hand side c / nb; its input starts at (c / nb) * ld_in + ptr_in[body] and its output
+// at (c / nb) * ld_out + ptr_out[body].  bodies == null: plain column-major strides.
+struct ColMap {
+  const int32_t* bodies = nullptr;
+  int nb = 0;
+  const int64_t* ptr_in = nullptr;
+  int64_t ld_in = 0;
+  const int64_t* ptr_out = nullptr;
+  int64_t ld_out = 0;
+  __device__ int64_t in_offset(int c) const { return (int64_t)(c / nb) * ld_in + ptr_in[bodies[c % nb]]; }
+  __device__ int64_t out_offset(int c) const { return (int64_t)(c / nb) * ld_out + ptr_out[bodies[c % nb]]; }
+};
+hipError_t launch_qr_reflect(const c128* QA, int rows, int ld, const double* tau, int rank, c128* rhs, int ldr,
+                             int ncols, const ColMap& cm, hipStream_t st);
+hipError_t launch_backsub(const c128* QA, int ld, const c128* alpha, int rank, c128* rhs, int ldr, const int* perm,
+                          int cols_out, c128* X, int ldx, int ncols, const ColMap& cm, hipStream_t st);
+
+// Near-field kernels (recon.hip).
+struct NearTables {        // device tables, per shape s and per body b
+  const double* const* colloc_of_shape;  // [n_shapes] -> [m_s][dim]
+  const double* const* src_of_shape;     // [n_shapes] -> [n_s][dim]
+  const c128* const* Y_of_shape;         // [n_shapes] -> n_s x k_s
+  const int32_t* m_of_shape;
+  const int32_t* n_of_shape;
+  const double* psi2_of_shape;           // squared proxy radius
+  const int64_t* cptr;                   // [T+1] collocation offsets
+  const int64_t* sptr;                   // [T+1] MFS source offsets
+  int64_t Mtot, Ntot;
+  int mmax, nmax, kmax;
+};
+hipError_t launch_plane_wave_colloc(const SceneDev& s, const NearTables& t, const double* dirs, int R, c128* v,
+                                    hipStream_t st);
+hipError_t launch_recon_combine(const SceneDev& s, const NearTables& t, const c128* what, int R, c128* qmfs,
+                                hipStream_t st);
+hipError_t launch_eval_near(const SceneDev& s, const NearTables& t, const c128* qhat, const c128* qmfs, int R,
+                            const double* targets, int64_t M, c128* partial, int nchunks, hipStream_t st);
+int near_chunks_for(int64_t T, int64_t M);
+
 // Least squares for S (lsq.hip).
 mfs_status build_S_impl(const mfs_shape_desc* d, void* S64, void* S32, int64_t* k_out, int64_t* skel,
                         double* diag, hipStream_t st);

@@ -67,7 +67,8 @@ class PoolStats(ctypes.Structure):
 EXPORTS = ["mfs_last_error", "mfs_version", "mfs_build_S", "mfs_scene_create", "mfs_scene_destroy",
            "mfs_scene_size", "mfs_scene_points", "mfs_plane_wave", "mfs_ghat_apply", "mfs_s_apply", "mfs_apply",
            "mfs_solve", "mfs_eval_field", "mfs_timing_enable", "mfs_timing_read", "mfs_pool_query",
-           "mfs_pool_set_limit", "mfs_pool_trim"]
+           "mfs_pool_set_limit", "mfs_pool_trim", "mfs_recon_create", "mfs_recon_destroy", "mfs_recon_size",
+           "mfs_near_sizes", "mfs_plane_wave_colloc", "mfs_reconstruct", "mfs_eval_field_near"]
 MFS_KERNEL_PAIR_F32, MFS_KERNEL_PAIR_F64 = 0, 1
 
 
@@ -100,6 +101,13 @@ def load(path: str = LIB_PATH):
         "mfs_pool_query": ([ctypes.POINTER(PoolStats)], ctypes.c_int),
         "mfs_pool_set_limit": ([i64], ctypes.c_int),
         "mfs_pool_trim": ([], ctypes.c_int),
+        "mfs_recon_create": ([ctypes.POINTER(ShapeDesc), f64, ctypes.POINTER(vp), vp], ctypes.c_int),
+        "mfs_recon_destroy": ([vp], ctypes.c_int),
+        "mfs_recon_size": ([vp] + [ctypes.POINTER(i64)] * 4, ctypes.c_int),
+        "mfs_near_sizes": ([vp, vp, ctypes.POINTER(i64), ctypes.POINTER(i64)], ctypes.c_int),
+        "mfs_plane_wave_colloc": ([vp, vp, vp, i32, vp, vp], ctypes.c_int),
+        "mfs_reconstruct": ([vp, vp, vp, vp, i32, vp, vp], ctypes.c_int),
+        "mfs_eval_field_near": ([vp, vp, vp, vp, i32, vp, i64, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -146,16 +154,11 @@ class BuiltS:
         return self.S32.T
 
 
-def build_S(shape, kappa: float, eps_ls: float = 1e-13, paper_mode: bool = False, eps_skel: float = 1e-10,
-            k_cap: int | None = None, stream=None) -> BuiltS:
-    """mfs_build_S for a workloads.ShapeDiscretisation (or any object with colloc/src/proxy/eqpts)."""
-    import torch
-
-    lib = load()
+def _shape_desc(shape, kappa, eps_ls, paper_mode, eps_skel, k_cap):
+    """ShapeDesc for a workloads.ShapeDiscretisation; returns (desc, capacity k, host arrays to keep)."""
     colloc, src, proxy = _host(shape.colloc), _host(shape.src), _host(shape.proxy)
-    dim = colloc.shape[1]
     desc = ShapeDesc()
-    desc.dim, desc.kappa = dim, float(kappa)
+    desc.dim, desc.kappa = colloc.shape[1], float(kappa)
     desc.colloc, desc.m = colloc.ctypes.data, colloc.shape[0]
     desc.src, desc.n = src.ctypes.data, src.shape[0]
     desc.proxy, desc.p = proxy.ctypes.data, proxy.shape[0]
@@ -163,12 +166,19 @@ def build_S(shape, kappa: float, eps_ls: float = 1e-13, paper_mode: bool = False
     if paper_mode:
         kc = int(k_cap if k_cap is not None else min(colloc.shape[0], proxy.shape[0]))
         desc.eqpts, desc.k, desc.k_cap = None, 0, kc
-        cap = kc
-        eq = None
-    else:
-        eq = _host(shape.eqpts)
-        desc.eqpts, desc.k, desc.k_cap = eq.ctypes.data, eq.shape[0], 0
-        cap = eq.shape[0]
+        return desc, kc, (colloc, src, proxy)
+    eq = _host(shape.eqpts)
+    desc.eqpts, desc.k, desc.k_cap = eq.ctypes.data, eq.shape[0], 0
+    return desc, eq.shape[0], (colloc, src, proxy, eq)
+
+
+def build_S(shape, kappa: float, eps_ls: float = 1e-13, paper_mode: bool = False, eps_skel: float = 1e-10,
+            k_cap: int | None = None, stream=None) -> BuiltS:
+    """mfs_build_S for a workloads.ShapeDiscretisation (or any object with colloc/src/proxy/eqpts)."""
+    import torch
+
+    lib = load()
+    desc, cap, _keep = _shape_desc(shape, kappa, eps_ls, paper_mode, eps_skel, k_cap)
     S64 = torch.empty(cap * cap, dtype=torch.complex128, device="cuda")
     S32 = torch.empty(cap * cap, dtype=torch.complex64, device="cuda")
     k_out = ctypes.c_int64(0)
@@ -284,6 +294,62 @@ def timing_read(kind: int) -> tuple[float, int, float]:
     ms, n, pairs = ctypes.c_double(0), ctypes.c_int64(0), ctypes.c_double(0)
     _check(load().mfs_timing_read(kind, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(pairs)))
     return float(ms.value), int(n.value), float(pairs.value)
+
+
+# --------------------------------------------------------- reconstruction ---
+class Recon:
+    """Owns an mfs_recon: the reconstruction factors of one shape (Sec. 4.6)."""
+
+    def __init__(self, shape, kappa: float, psi_radius: float | None = None, eps_ls: float = 1e-13,
+                 paper_mode: bool = False, eps_skel: float = 1e-10, k_cap: int | None = None, stream=None):
+        lib = load()
+        desc, _, keep = _shape_desc(shape, kappa, eps_ls, paper_mode, eps_skel, k_cap)
+        radius = float(shape.proxy_radius if psi_radius is None else psi_radius)
+        h = ctypes.c_void_p(0)
+        _check(lib.mfs_recon_create(ctypes.byref(desc), radius, ctypes.byref(h), _stream(stream)))
+        del keep
+        self.handle = h
+        m, n, k, r = (ctypes.c_int64(0) for _ in range(4))
+        _check(lib.mfs_recon_size(h, ctypes.byref(m), ctypes.byref(n), ctypes.byref(k), ctypes.byref(r)))
+        self.m, self.n, self.k, self.rank = int(m.value), int(n.value), int(k.value), int(r.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.mfs_recon_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _recon_array(recons):
+    return (ctypes.c_void_p * len(recons))(*[r.handle.value for r in recons])
+
+
+def near_sizes(scene: Scene, recons) -> tuple[int, int]:
+    """(sum of collocation points, sum of MFS sources) over the scene's bodies."""
+    a, b = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(_lib.mfs_near_sizes(scene.handle, _recon_array(recons), ctypes.byref(a), ctypes.byref(b)))
+    return int(a.value), int(b.value)
+
+
+def plane_wave_colloc(scene: Scene, recons, directions, v, stream=None):
+    d = _host(np.atleast_2d(directions))
+    _check(_lib.mfs_plane_wave_colloc(scene.handle, _recon_array(recons), d.ctypes.data, d.shape[0], _ptr(v),
+                                      _stream(stream)))
+
+
+def reconstruct(scene: Scene, recons, v_colloc, qhat, qmfs, stream=None):
+    _check(_lib.mfs_reconstruct(scene.handle, _recon_array(recons), _ptr(v_colloc), _ptr(qhat), qhat.shape[0],
+                                _ptr(qmfs), _stream(stream)))
+
+
+def eval_field_near(scene: Scene, recons, qhat, qmfs, targets, u, stream=None):
+    _check(_lib.mfs_eval_field_near(scene.handle, _recon_array(recons), _ptr(qhat), _ptr(qmfs), qhat.shape[0],
+                                    _ptr(targets), targets.shape[0], _ptr(u), _stream(stream)))
 
 
 # ------------------------------------------------------------------- pool ---

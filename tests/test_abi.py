@@ -82,3 +82,19 @@ def test_pool_interface_without_device(lib):
     mfs.pool_set_limit(st["limit_bytes"])
     mfs.pool_trim()
     assert lib.mfs_pool_query(None) == -1
+
+
+def test_reconstruction_entry_points_reject_null_arguments(lib):
+    h = ctypes.c_void_p(0)
+    assert lib.mfs_recon_create(None, 1.0, ctypes.byref(h), None) == -1
+    pts = np.zeros((4, 2))
+    d = mfs.ShapeDesc(dim=2, kappa=1.0, colloc=pts.ctypes.data, m=4, src=pts.ctypes.data, n=2,
+                      proxy=pts.ctypes.data, p=4, eqpts=pts.ctypes.data, k=2, eps_skel=1e-10, eps_ls=1e-13, k_cap=0)
+    assert lib.mfs_recon_create(ctypes.byref(d), 0.0, ctypes.byref(h), None) == -1   # psi_radius
+    assert b"psi_radius" in lib.mfs_last_error()
+    assert lib.mfs_recon_destroy(None) == 0
+    assert lib.mfs_recon_size(None, None, None, None, None) == -1
+    assert lib.mfs_near_sizes(None, None, None, None) == -1
+    assert lib.mfs_reconstruct(None, None, None, None, 1, None, None) == -1
+    assert lib.mfs_eval_field_near(None, None, None, None, 1, None, 0, None, None) == -1
+    assert lib.mfs_plane_wave_colloc(None, None, None, 1, None, None) == -1
