@@ -39,6 +39,9 @@ FLOP_PER_PAIR_F32 = {2: 42, 3: 34}
 # build here disables, so 78.6 is the ceiling these kernels can reach; both are reported.
 PEAK_FP32_VECTOR_TFLOPS = 78.6
 PEAK_FP32_PACKED_TFLOPS = 157.3
+# Many right-hand sides: G_hat tile x charge block on the FP32 matrix cores (dense FP32 MFMA peak).
+FLOP_PER_PAIR_RHS_MFMA = 8
+PEAK_FP32_MFMA_TFLOPS = 157.3
 
 
 def log(msg: str):
@@ -230,7 +233,8 @@ def compare(args, sc, mfs, torch, np) -> int:
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     info_m = mfs.solve(scene, v, q_mixed, tol=args.tol, maxit=60000, restart=args.restart, max_refine=20,
-                       inner_tol=args.inner_tol, prec=mfs.MFS_MIXED, verbose=min(args.verbose, 1))
+                       inner_tol=args.inner_tol, prec=mfs.MFS_MIXED, verbose=min(args.verbose, 1),
+                       basis32=not args.basis64)
     t_mixed = time.perf_counter() - t0
     log(f"[compare] mixed, {R} RHS together: {t_mixed:.2f} s  {info_m}")
     q64 = torch.empty_like(v)
@@ -274,6 +278,8 @@ def main() -> int:
                     help="Krylov basis size; the default keeps the whole basis resident (no restart)")
     ap.add_argument("--inner-tol", type=float, default=3e-6,
                     help="first inner solve stops here: below ~7e-6 the FP32 operator error caps the true residual")
+    ap.add_argument("--basis64", action="store_true",
+                    help="keep the Krylov basis of the mixed solve in complex128 (default: complex64)")
     ap.add_argument("--matvecs", type=int, default=0,
                     help="profiling mode: replace the solve by this many mixed operator applications")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -351,7 +357,8 @@ def main() -> int:
                     "t_total_s": 0.0, "n_reorth": 0, "status": "profile"}
         else:
             info = mfs.solve(scene, v, q, tol=args.tol, maxit=60000, restart=args.restart, max_refine=20,
-                             inner_tol=args.inner_tol, prec=mfs.MFS_MIXED, verbose=args.verbose)
+                             inner_tol=args.inner_tol, prec=mfs.MFS_MIXED, verbose=args.verbose,
+                             basis32=not args.basis64)
         u = torch.empty((R, targets.shape[0]), dtype=torch.complex128, device="cuda")
         mfs.eval_field(scene, q, targets, u, mfs.MFS_FP64)
         torch.cuda.synchronize()
@@ -387,16 +394,22 @@ def main() -> int:
     ms64, n64, p64 = mfs.timing_read(mfs.MFS_KERNEL_PAIR_F64)
     mfs.timing_enable(False)
 
-    if sc.R >= 8 and all(sh.k % 16 == 0 for sh in sc.shapes):
+    on_mfma = sc.R >= 8 and all(sh.k % 16 == 0 for sh in sc.shapes)
+    if on_mfma:
         kernel_name = "ghat_mfma_kernel<%d> (G_hat, FP32 matrix cores)" % sc.dim
     else:
         kernel_name = "ghat_bodyphase_kernel<%d,2,%d> (G_hat, FP32)" % (sc.dim, 1 if R == 1 else (2 if R == 2 else 4))
     traffic = stored_traffic(sc.name, kernel_name)
     total_pairs = p32 + p64
     value = total_pairs / wall
-    flop_pp = FLOP_PER_PAIR_F32[sc.dim]
     avg32 = ms32 / max(n32, 1)
-    pairs_per_launch32 = p32 / max(n32, 1)
+    pairs_per_launch32 = p32 / max(n32, 1)   # pair evaluations times right-hand sides
+    if on_mfma:
+        # the contraction on the matrix cores: 8 flop per (pair, right-hand side) complex multiply-add
+        flop_pp, bound, peak, peak_alt = FLOP_PER_PAIR_RHS_MFMA, "mfma", PEAK_FP32_MFMA_TFLOPS, None
+    else:
+        flop_pp, bound, peak, peak_alt = FLOP_PER_PAIR_F32[sc.dim], "alu", PEAK_FP32_VECTOR_TFLOPS, \
+            PEAK_FP32_PACKED_TFLOPS
     achieved = flop_pp * pairs_per_launch32 / (avg32 * 1e-3) / 1e12 if n32 else 0.0
     solve_times = [i["t_total_s"] for i in infos]
     out = {
@@ -413,7 +426,8 @@ def main() -> int:
         "dtype": "f32 pair sums + f64 Krylov/refinement",
         "data": "synthetic (seeded geometry, no dataset)",
         "config": {"workload": sc.name, "T": sc.T, "N": sc.N, "R": R, "kappa": sc.kappa, "tol": args.tol,
-                   "precision": "mixed", "restart": args.restart, "inner_tol": args.inner_tol},
+                   "precision": "mixed", "restart": args.restart, "inner_tol": args.inner_tol,
+                   "krylov_basis": "c128" if args.basis64 else "c64"},
         "solve_s_p50": statistics.median(solve_times) if args.matvecs == 0 else None,
         "solve_s_p99": float(np.percentile(solve_times, 99)) if args.matvecs == 0 else None,
         "relres_max": max(i["relres_max"] for i in infos),
@@ -422,16 +436,16 @@ def main() -> int:
         "n_refine": infos[-1]["n_refine"],
         "n_reorth": infos[-1].get("n_reorth", 0),
         "mode": "profile (operator applications only)" if args.matvecs > 0 else "full solve",
-        "pair_kernel_f32": {"launches": n32, "avg_ms": avg32, "pairs_per_launch": pairs_per_launch32,
+        "pair_kernel_f32": {"launches": n32, "avg_ms": avg32, "rhs": R, "pairs_per_launch": pairs_per_launch32,
                             "pair_evals_per_s": pairs_per_launch32 / (avg32 * 1e-3) if n32 else 0.0},
         "pair_kernel_f64": {"launches": n64, "avg_ms": ms64 / max(n64, 1),
                             "pair_evals_per_s": p64 / (ms64 * 1e-3) if n64 else 0.0},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": traffic,
+        "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic,
                      "kernel": kernel_name,
-                     "flop_per_pair": flop_pp,
-                     "peak_packed_fp32": PEAK_FP32_PACKED_TFLOPS,
-                     "frac_of_packed_peak": achieved / PEAK_FP32_PACKED_TFLOPS},
+                     "flop_per_pair" if not on_mfma else "flop_per_pair_rhs": flop_pp,
+                     **({"peak_packed_fp32": peak_alt, "frac_of_packed_peak": achieved / peak_alt}
+                        if peak_alt else {})},
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a row sample ...")

@@ -185,7 +185,7 @@ typedef struct {
   double tol;        /* relative residual target, e.g. 1e-8 */
   int32_t maxit;     /* total inner iterations (operator applications) allowed */
   int32_t restart;   /* Krylov basis size before a restart (1..32768); the basis takes
-                        (restart+1) * R * N * 16 bytes of device memory */
+                        (restart+1) * R * N * 16 bytes of device memory (8 with basis32) */
   int32_t max_refine;/* MFS_MIXED: outer refinement steps allowed */
   double inner_tol;  /* MFS_MIXED: smallest relative residual reduction asked of an inner solve; the
                         last steps ask only for the reduction the outer tolerance still needs */
@@ -201,6 +201,9 @@ typedef struct {
                         device memory); the operator application stays a direct launch.  Same
                         arithmetic as 0, fewer launches: for small systems, where launch cost
                         dominates.  0: direct launches */
+  int32_t basis32;   /* MFS_MIXED with fp64_until = 0: 1 stores the Krylov basis in complex64
+                        (half the memory and basis traffic; inner products, the Hessenberg matrix,
+                        rotations and the solution update stay FP64).  0: complex128 basis */
 } mfs_solve_opts;
 
 typedef struct {

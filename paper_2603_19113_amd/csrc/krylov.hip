@@ -26,11 +26,12 @@ __device__ __forceinline__ double wave_sum(double v) {
 // part[r][i][blk] = sum over the block's elements of conj(V_i[r][n]) w[r][n].
 // grid = (vector chunks, groups of kGroup basis vectors, right-hand sides): each block keeps its
 // chunk of w in registers and reads kGroup basis-vector chunks once.
-__global__ __launch_bounds__(kThreads) void dots_kernel(const c128* __restrict__ V, const c128* __restrict__ w,
+template <typename VT>
+__global__ __launch_bounds__(kThreads) void dots_kernel(const VT* __restrict__ V, const c128* __restrict__ w,
                                                         int64_t N, int R, int jcount_h, int nblk,
                                                         double* __restrict__ part, const int32_t* __restrict__ flag,
                                                         const int32_t* __restrict__ jdev) {
-  __shared__ double red[kThreads / 64][kGroup][2];
+  __shared__ double red[kThreads / 64][2 * kGroup];
   const int r = blockIdx.z;
   if (flag && !flag[r]) return;
   const int jcount = jdev ? *jdev + 1 : jcount_h;
@@ -44,45 +45,53 @@ __global__ __launch_bounds__(kThreads) void dots_kernel(const c128* __restrict__
     wl[e] = n < N ? w[(int64_t)r * N + n] : c128{0.0, 0.0};
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double sr[kGroup], si[kGroup];
+  // v[g] = real part and v[kGroup + g] = imaginary part of conj(V_{i0+g}) . w over this lane's elements
+  double v[2 * kGroup];
 #pragma unroll
   for (int g = 0; g < kGroup; ++g) {
-    sr[g] = 0.0;
-    si[g] = 0.0;
+    double ar = 0.0, ai = 0.0;
     const int i = i0 + g;
     if (i < jcount) {
-      const c128* Vi = V + ((int64_t)i * R + r) * N;
+      const VT* Vi = V + ((int64_t)i * R + r) * N;
 #pragma unroll
       for (int e = 0; e < kElems; ++e) {
         const int64_t n = base + e * kThreads + threadIdx.x;
         if (n < N) {
-          const c128 v = Vi[n];
-          sr[g] = fma(v.re, wl[e].re, fma(v.im, wl[e].im, sr[g]));   // conj(v) * w
-          si[g] = fma(v.re, wl[e].im, fma(-v.im, wl[e].re, si[g]));
+          const VT xv = Vi[n];
+          const double xr = xv.re, xi = xv.im;
+          ar = fma(xr, wl[e].re, fma(xi, wl[e].im, ar));   // conj(v) * w
+          ai = fma(xr, wl[e].im, fma(-xi, wl[e].re, ai));
         }
       }
     }
+    v[g] = ar;
+    v[kGroup + g] = ai;
   }
+  // Sum the 32 values over the wave by recursive halving: at distance d a lane keeps one half of
+  // its values and adds its partner's copy of that half, so 16 + 8 + 4 + 2 + 1 + 1 = 32 shuffles
+  // replace 6 per value.  Lanes 2t and 2t + 1 end with the total of value t.
 #pragma unroll
-  for (int g = 0; g < kGroup; ++g) {
-    sr[g] = wave_sum(sr[g]);
-    si[g] = wave_sum(si[g]);
-  }
-  if (lane == 0) {
+  for (int half = kGroup, d = 32; half >= 1; half >>= 1, d >>= 1) {
+    const bool up = (lane & d) != 0;
 #pragma unroll
-    for (int g = 0; g < kGroup; ++g) {
-      red[wave][g][0] = sr[g];
-      red[wave][g][1] = si[g];
+    for (int k = 0; k < half; ++k) {
+      const double a = v[k], b = v[k + half];
+      const double send = up ? a : b;
+      const double keep = up ? b : a;
+      v[k] = keep + __shfl_xor(send, d, 64);
     }
   }
+  v[0] += __shfl_xor(v[0], 1, 64);
+  if ((lane & 1) == 0) red[wave][lane >> 1] = v[0];
   __syncthreads();
-  if (threadIdx.x < kGroup * 2) {
-    const int g = threadIdx.x >> 1, c = threadIdx.x & 1;
+  if (threadIdx.x < 2 * kGroup) {
+    const int t = threadIdx.x;
+    const int g = t % kGroup, c = t / kGroup;
     const int i = i0 + g;
     if (i < jcount) {
-      double t = 0.0;
-      for (int wv = 0; wv < kThreads / 64; ++wv) t += red[wv][g][c];
-      part[(((int64_t)r * jcount + i) * nblk + blockIdx.x) * 2 + c] = t;
+      double sum = 0.0;
+      for (int wv = 0; wv < kThreads / 64; ++wv) sum += red[wv][t];
+      part[(((int64_t)r * jcount + i) * nblk + blockIdx.x) * 2 + c] = sum;
     }
   }
 }
@@ -117,7 +126,8 @@ __global__ void dots_reduce_kernel(const double* __restrict__ part, int jcount_h
 }
 
 // w[r][n] -= sum_{i<jcount} h[r][i] V_i[r][n]
-__global__ __launch_bounds__(kThreads) void basis_axpy_kernel(const c128* __restrict__ V, const c128* __restrict__ h,
+template <typename VT>
+__global__ __launch_bounds__(kThreads) void basis_axpy_kernel(const VT* __restrict__ V, const c128* __restrict__ h,
                                                               int ld, int64_t N, int R, int jcount_h,
                                                               c128* __restrict__ w, const int32_t* __restrict__ flag,
                                                               const int32_t* __restrict__ jdev) {
@@ -128,14 +138,15 @@ __global__ __launch_bounds__(kThreads) void basis_axpy_kernel(const c128* __rest
   // h is read with wave-uniform addresses (scalar loads); eight basis loads are kept in flight
   double ar = 0.0, ai = 0.0;
   const c128* hr = h + (int64_t)r * ld;
-  const c128* Vn = V + (int64_t)r * N + n;
+  const VT* Vn = V + (int64_t)r * N + n;
   const int64_t stride = (int64_t)R * N;
 #pragma unroll 8
   for (int i = 0; i < jcount; ++i) {
     const c128 hi = hr[i];
-    const c128 v = Vn[i * stride];
-    ar = fma(hi.re, v.re, fma(-hi.im, v.im, ar));
-    ai = fma(hi.re, v.im, fma(hi.im, v.re, ai));
+    const VT vv = Vn[i * stride];
+    const double vr = vv.re, vi = vv.im;
+    ar = fma(hi.re, vr, fma(-hi.im, vi, ar));
+    ai = fma(hi.re, vi, fma(hi.im, vr, ai));
   }
   c128 x = w[(int64_t)r * N + n];
   x.re -= ar;
@@ -207,15 +218,16 @@ __global__ __launch_bounds__(256) void reorth_decide_kernel(int jcount_h, int R,
 }
 
 // Start of a cycle: V_0 = r0 / beta, g = (beta, 0, ...).  Columns with beta == 0 stay inactive.
+template <typename VT>
 __global__ void start_scale_kernel(const c128* __restrict__ r0, const double* __restrict__ beta, int64_t N, int R,
-                                   c128* __restrict__ V0) {
+                                   VT* __restrict__ V0) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
   if (n >= N) return;
   const double b = beta[r];
   const double s = b > 0.0 ? 1.0 / b : 0.0;
   const c128 x = r0[(int64_t)r * N + n];
-  V0[(int64_t)r * N + n] = c128{x.re * s, x.im * s};
+  V0[(int64_t)r * N + n] = VT{(decltype(VT::re))(x.re * s), (decltype(VT::re))(x.im * s)};
 }
 
 __global__ void start_state_kernel(const double* __restrict__ beta, const double* __restrict__ bnorm,
@@ -334,17 +346,18 @@ __global__ __launch_bounds__(kGivensThreads) void givens_kernel(int j_h, int m, 
 }
 
 // V_{j+1} = w / ||w||.
+template <typename VT>
 __global__ void scale_next_kernel(const c128* __restrict__ w, const double* __restrict__ hnorm, int64_t N, int R,
-                                  c128* __restrict__ V, int j_h, const int32_t* __restrict__ jdev) {
+                                  VT* __restrict__ V, int j_h, const int32_t* __restrict__ jdev) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
   if (n >= N) return;
   const int j = jdev ? *jdev : j_h;
-  c128* Vn = V + (int64_t)(j + 1) * R * N;
+  VT* Vn = V + (int64_t)(j + 1) * R * N;
   const double h = hnorm[r];
   const double s = h > 1e-300 ? 1.0 / h : 0.0;
   const c128 x = w[(int64_t)r * N + n];
-  Vn[(int64_t)r * N + n] = c128{x.re * s, x.im * s};
+  Vn[(int64_t)r * N + n] = VT{(decltype(VT::re))(x.re * s), (decltype(VT::re))(x.im * s)};
 }
 
 // End of a replayed step: the next replay works on step j + 1.
@@ -385,7 +398,8 @@ __global__ __launch_bounds__(1024) void hess_solve_kernel(int m, int R, const c1
 }
 
 // x[r][n] += sum_{i<len_r} y[r][i] V_i[r][n]
-__global__ __launch_bounds__(kThreads) void update_x_kernel(const c128* __restrict__ V, const c128* __restrict__ y,
+template <typename VT>
+__global__ __launch_bounds__(kThreads) void update_x_kernel(const VT* __restrict__ V, const c128* __restrict__ y,
                                                             const int32_t* __restrict__ jlen, int m, int64_t N, int R,
                                                             c128* __restrict__ x) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -396,9 +410,10 @@ __global__ __launch_bounds__(kThreads) void update_x_kernel(const c128* __restri
 #pragma unroll 8
   for (int i = 0; i < len; ++i) {
     const c128 yi = y[(int64_t)r * m + i];
-    const c128 v = V[((int64_t)i * R + r) * N + n];
-    ar = fma(yi.re, v.re, fma(-yi.im, v.im, ar));
-    ai = fma(yi.re, v.im, fma(yi.im, v.re, ai));
+    const VT vv = V[((int64_t)i * R + r) * N + n];
+    const double vr = vv.re, vi = vv.im;
+    ar = fma(yi.re, vr, fma(-yi.im, vi, ar));
+    ai = fma(yi.re, vi, fma(yi.im, vr, ai));
   }
   c128 xx = x[(int64_t)r * N + n];
   xx.re += ar;
@@ -427,8 +442,12 @@ hipError_t launch_norms(const c128* v, int64_t N, int R, double* part, int nblk,
 hipError_t launch_start_cycle(KrylovDev k, const c128* r0, hipStream_t st) {
   hipError_t e = launch_norms(r0, k.N, k.R, k.part, k.nblk, k.beta, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(start_scale_kernel, dim3(blocks_for(k.N, 256), k.R), dim3(256), 0, st, r0, k.beta, k.N, k.R,
-                     k.V);
+  if (k.v32)
+    hipLaunchKernelGGL(start_scale_kernel<c64>, dim3(blocks_for(k.N, 256), k.R), dim3(256), 0, st, r0, k.beta, k.N,
+                       k.R, static_cast<c64*>(k.V));
+  else
+    hipLaunchKernelGGL(start_scale_kernel<c128>, dim3(blocks_for(k.N, 256), k.R), dim3(256), 0, st, r0, k.beta, k.N,
+                       k.R, static_cast<c128*>(k.V));
   hipLaunchKernelGGL(start_state_kernel, dim3(blocks_for(k.R, 64)), dim3(64), 0, st, k.beta, k.bnorm, k.active,
                      k.jlen, k.g, k.res, k.m, k.R, k.jdev, k.tol_dev, k.tol);
   return hipGetLastError();
@@ -450,12 +469,22 @@ hipError_t launch_arnoldi_orth(KrylovDev k, int j, c128* w, hipStream_t st) {
       hipLaunchKernelGGL(reorth_decide_kernel, dim3(k.R), dim3(256), 0, st, jc, k.R, ld, k.hcol, k.wn,
                          k.reorth, k.n_reorth, k.reorth_eta * k.reorth_eta, k.ratio_log, k.m,
                          (const int32_t*)k.jdev);
-    hipLaunchKernelGGL(dots_kernel, dim3(k.nblk, (jc + kGroup - 1) / kGroup, k.R), dim3(kThreads), 0, st, k.V, w,
-                       k.N, k.R, jc, k.nblk, k.part, flag, (const int32_t*)k.jdev);
+    const dim3 dgrid(k.nblk, (jc + kGroup - 1) / kGroup, k.R);
+    if (k.v32)
+      hipLaunchKernelGGL(dots_kernel<c64>, dgrid, dim3(kThreads), 0, st, static_cast<const c64*>(k.V), w, k.N, k.R,
+                         jc, k.nblk, k.part, flag, (const int32_t*)k.jdev);
+    else
+      hipLaunchKernelGGL(dots_kernel<c128>, dgrid, dim3(kThreads), 0, st, static_cast<const c128*>(k.V), w, k.N,
+                         k.R, jc, k.nblk, k.part, flag, (const int32_t*)k.jdev);
     hipLaunchKernelGGL(dots_reduce_kernel, dim3(jc, k.R), dim3(64), 0, st, k.part, jc, k.nblk, k.R, ld, h,
                        (const c128*)nullptr, flag, (const int32_t*)k.jdev);
-    hipLaunchKernelGGL(basis_axpy_kernel, dim3(blocks_for(k.N, kThreads), k.R), dim3(kThreads), 0, st, k.V, h, ld,
-                       k.N, k.R, jc, w, flag, (const int32_t*)k.jdev);
+    const dim3 agrid(blocks_for(k.N, kThreads), k.R);
+    if (k.v32)
+      hipLaunchKernelGGL(basis_axpy_kernel<c64>, agrid, dim3(kThreads), 0, st, static_cast<const c64*>(k.V), h, ld,
+                         k.N, k.R, jc, w, flag, (const int32_t*)k.jdev);
+    else
+      hipLaunchKernelGGL(basis_axpy_kernel<c128>, agrid, dim3(kThreads), 0, st, static_cast<const c128*>(k.V), h, ld,
+                         k.N, k.R, jc, w, flag, (const int32_t*)k.jdev);
   }
   return hipGetLastError();
 }
@@ -467,8 +496,12 @@ hipError_t launch_arnoldi_finish(KrylovDev k, int j, c128* w, double tol, hipStr
   hipLaunchKernelGGL(givens_kernel, dim3(k.R), dim3(kGivensThreads), 0, st, j, k.m, k.R, 1.0, k.hcol, k.h2, k.hnorm,
                      k.H, k.cs, k.sn, k.g, k.res, k.bnorm, tol, k.active, k.jlen, (const int32_t*)k.jdev,
                      (const double*)k.tol_dev);
-  hipLaunchKernelGGL(scale_next_kernel, dim3(blocks_for(k.N, 256), k.R), dim3(256), 0, st, w, k.hnorm, k.N, k.R,
-                     k.V, j, (const int32_t*)k.jdev);
+  if (k.v32)
+    hipLaunchKernelGGL(scale_next_kernel<c64>, dim3(blocks_for(k.N, 256), k.R), dim3(256), 0, st, w, k.hnorm, k.N,
+                       k.R, static_cast<c64*>(k.V), j, (const int32_t*)k.jdev);
+  else
+    hipLaunchKernelGGL(scale_next_kernel<c128>, dim3(blocks_for(k.N, 256), k.R), dim3(256), 0, st, w, k.hnorm, k.N,
+                       k.R, static_cast<c128*>(k.V), j, (const int32_t*)k.jdev);
   if (k.jdev) hipLaunchKernelGGL(step_advance_kernel, dim3(1), dim3(64), 0, st, k.jdev);
   return hipGetLastError();
 }
@@ -476,8 +509,12 @@ hipError_t launch_arnoldi_finish(KrylovDev k, int j, c128* w, double tol, hipStr
 // y = H^{-1} g per column, then x += V y.
 hipError_t launch_gmres_update_x(KrylovDev k, c128* x, hipStream_t st) {
   hipLaunchKernelGGL(hess_solve_kernel, dim3(k.R), dim3(1024), 0, st, k.m, k.R, k.H, k.g, k.jlen, k.y);
-  hipLaunchKernelGGL(update_x_kernel, dim3(blocks_for(k.N, kThreads), k.R), dim3(kThreads), 0, st, k.V, k.y, k.jlen,
-                     k.m, k.N, k.R, x);
+  if (k.v32)
+    hipLaunchKernelGGL(update_x_kernel<c64>, dim3(blocks_for(k.N, kThreads), k.R), dim3(kThreads), 0, st,
+                       static_cast<const c64*>(k.V), k.y, k.jlen, k.m, k.N, k.R, x);
+  else
+    hipLaunchKernelGGL(update_x_kernel<c128>, dim3(blocks_for(k.N, kThreads), k.R), dim3(kThreads), 0, st,
+                       static_cast<const c128*>(k.V), k.y, k.jlen, k.m, k.N, k.R, x);
   return hipGetLastError();
 }
 

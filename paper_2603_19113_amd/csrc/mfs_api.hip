@@ -280,6 +280,19 @@ mfs_status prepare_near(mfs_scene* s, const mfs_recon* const* recon, hipStream_t
   s->near_key.assign(recon, recon + ns);
   return MFS_OK;
 }
+// y = S G_hat q with q already complex64 (a single-precision Krylov basis vector) and y complex128.
+mfs_status apply_mixed_from32(mfs_scene* s, const c64* q32, c128* y, int R, hipStream_t st) {
+  const int nch = pair_chunks_for(s->dev.N, s->dev.N, tpt_for(MFS_FP32));
+  MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c64), &s->bytes, st));
+  c64* part = static_cast<c64*>(s->partial.p);
+  {
+    TimedLaunch tl(MFS_KERNEL_PAIR_F32, s->dev.offbody_pairs * R, st);
+    MFS_HIP_TRY(launch_ghat_f32(s->dev, q32, R, part, nch, st));
+  }
+  MFS_HIP_TRY(launch_sapply_mixed(s->dev, part, nch, nullptr, 0.0, y, R, (int)s->kmax, st));
+  return MFS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -590,7 +603,9 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
   k.R = R;
   k.m = m;
   k.nblk = krylov_nblk(N);
-  const size_t szV = sizeof(c128) * (size_t)(m + 1) * NR;
+  // single-precision basis: inner solves that use the FP32 operator throughout
+  const bool v32 = prec == MFS_MIXED && opts->basis32 != 0 && !(opts->fp64_until > 0.0);
+  const size_t szV = (v32 ? sizeof(c64) : sizeof(c128)) * (size_t)(m + 1) * NR;
   const size_t szH = sizeof(c128) * (size_t)R * m * (m + 1);
   const size_t szRm = sizeof(c128) * (size_t)R * m;
   const size_t szRm1 = sizeof(c128) * (size_t)R * (m + 1);
@@ -608,7 +623,8 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
                ojdev = carve(sizeof(int32_t)), otol = carve(sizeof(double));
   MFS_TRY(ensure(s->kry, off, &s->bytes, st));
   char* base = static_cast<char*>(s->kry.p);
-  k.V = reinterpret_cast<c128*>(base + oV);
+  k.V = base + oV;
+  k.v32 = v32;
   k.H = reinterpret_cast<c128*>(base + oH);
   k.cs = reinterpret_cast<c128*>(base + ocs);
   k.sn = reinterpret_cast<c128*>(base + osn);
@@ -755,13 +771,17 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
     int read_j = -1;  // last step whose flags the host has read
     bool stop = false;
     for (int j = 0; j < m && !stop; ++j) {
-      c128* Vj = kk.V + (int64_t)j * NR;
       // Arnoldi on the compact part K = S G_hat: w = K v_j, and H(I + K) = H(K) + I (the shift is
       // added in the Givens kernel); the identity's large projection on v_j never enters w.
-      if (mixed && (opts->fp64_until <= 0.0 || !(est_max > opts->fp64_until))) {
+      if (kk.v32) {
+        MFS_TRY(apply_mixed_from32(s, static_cast<const c64*>(kk.V) + (int64_t)j * NR, w, R, st));
+        ++n32;
+      } else if (mixed && (opts->fp64_until <= 0.0 || !(est_max > opts->fp64_until))) {
+        c128* Vj = static_cast<c128*>(kk.V) + (int64_t)j * NR;
         MFS_TRY(apply_mixed(s, Vj, w, R, st, 0.0));
         ++n32;
       } else {
+        c128* Vj = static_cast<c128*>(kk.V) + (int64_t)j * NR;
         MFS_TRY(apply_f64(s, Vj, w, R, st, 0.0));
         ++n64;
       }

@@ -97,7 +97,8 @@ struct KrylovDev {
   int64_t N;
   int R;
   int m;              // restart length
-  c128* V;            // [(m+1)][R][N]
+  void* V;            // [(m+1)][R][N], complex128, or complex64 when v32
+  bool v32;           // basis stored in single precision (inner solves with the FP32 operator)
   c128* H;            // [R][m][m+1]: column j of rhs r at H + (r*m + j)*(m+1)
   c128* cs;           // [R][m]
   c128* sn;           // [R][m]

@@ -570,78 +570,88 @@ __global__ __launch_bounds__(256) void ghat_mfma_kernel(
 #pragma unroll
   for (int d = 0; d < DIM; ++d) P[d] = 0.f;
 
-  int tiles = 0;
-  for (int64_t j0 = c0; j0 < c1; j0 += kMfmaSrc) {
-    // stage Q(j0 .. j0+15, r0 .. r0+63), transposed
-    {
-      const int rr = threadIdx.x >> 2;        // 0..63
-      const int sg = (threadIdx.x & 3) * 4;   // 0, 4, 8, 12
-      const int r = r0 + rr;
+  // Tiles of 16 sources are taken kMfmaFlush at a time with FP32 accumulators, which are then
+  // added into the FP64 sums; keeping the flush outside the inner loop lets the accumulators stay
+  // in the matrix-core registers across the tiles.
+  for (int64_t jb = c0; jb < c1; jb += (int64_t)kMfmaSrc * kMfmaFlush) {
+    const int64_t je = min(c1, jb + (int64_t)kMfmaSrc * kMfmaFlush);
+    for (int64_t j0 = jb; j0 < je; j0 += kMfmaSrc) {
+      // stage Q(j0 .. j0+15, r0 .. r0+63), transposed
+      {
+        const int rr = threadIdx.x >> 2;        // 0..63
+        const int sg = (threadIdx.x & 3) * 4;   // 0, 4, 8, 12
+        const int r = r0 + rr;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) qt[sg + u][rr] = r < R ? q[(int64_t)r * N + j0 + sg + u] : c64{0.f, 0.f};
-    }
-    // per (target, source body) quantities, recomputed when the tile's body changes
-    const int sb = body_of[j0];
-    if (sb != cur_sb) {
-      cur_sb = sb;
-      double dd2 = 0.0;
-      float Ai = 0.f;
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        const double dc = ct[d] - cen[(int64_t)sb * DIM + d];
-        dd2 = fma(dc, dc, dd2);
-        const float dcf = (float)dc;
-        Ai = fmaf(lt[d], lt[d] + 2.0f * dcf, Ai);
-        P[d] = -2.0f * (lt[d] + dcf);
+        for (int u = 0; u < 4; ++u) qt[sg + u][rr] = r < R ? q[(int64_t)r * N + j0 + sg + u] : c64{0.f, 0.f};
       }
-      const double dd = sqrt(dd2);
-      const double ph = dd * k.kappa_rev64;
-      A = Ai;
-      D = (float)dd;
-      D2 = (float)dd2;
-      ph0 = (float)(ph - floor(ph)) - (DIM == 2 ? 0.125f : 0.0f);
-    }
-    // phi in the A layout: k-step s, source j0 + 4 s + lane / 16
-    float gr[4], gi[4];
+      // per (target, source body) quantities, recomputed when the tile's body changes
+      const int sb = body_of[j0];
+      if (sb != cur_sb) {
+        cur_sb = sb;
+        double dd2 = 0.0;
+        float Ai = 0.f;
 #pragma unroll
-    for (int st = 0; st < 4; ++st) {
-      const int64_t j = j0 + 4 * st + (lane >> 4);
-      float u = A + lsq[j];
-      u = fmaf(P[0], l0[j], u);
-      u = fmaf(P[1], l1[j], u);
-      if constexpr (DIM == 3) u = fmaf(P[2], l2[j], u);
-      float pr, pi;
-      bp_phi<DIM>(k, u, D, D2, ph0, pr, pi);
-      const bool same = tb == sb;
-      gr[st] = same ? 0.f : pr;
-      gi[st] = same ? 0.f : pi;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int st = 0; st < 4; ++st) {
-      const float ngi = -gi[st];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const c64 qq = qt[4 * st + (lane >> 4)][16 * b + (lane & 15)];
-        accR[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr[st], qq.re, accR[b], 0, 0, 0);
-        accR[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ngi, qq.im, accR[b], 0, 0, 0);
-        accI[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr[st], qq.im, accI[b], 0, 0, 0);
-        accI[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(gi[st], qq.re, accI[b], 0, 0, 0);
-      }
-    }
-    __syncthreads();
-    if (++tiles == kMfmaFlush) {
-      tiles = 0;
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          sumR[b][i] += (double)accR[b][i];
-          sumI[b][i] += (double)accI[b][i];
-          accR[b][i] = 0.f;
-          accI[b][i] = 0.f;
+        for (int d = 0; d < DIM; ++d) {
+          const double dc = ct[d] - cen[(int64_t)sb * DIM + d];
+          dd2 = fma(dc, dc, dd2);
+          const float dcf = (float)dc;
+          Ai = fmaf(lt[d], lt[d] + 2.0f * dcf, Ai);
+          P[d] = -2.0f * (lt[d] + dcf);
         }
+        const double dd = sqrt(dd2);
+        const double ph = dd * k.kappa_rev64;
+        A = Ai;
+        D = (float)dd;
+        D2 = (float)dd2;
+        ph0 = (float)(ph - floor(ph)) - (DIM == 2 ? 0.125f : 0.0f);
+      }
+      // phi in the A layout: k-step s, source j0 + 4 s + lane / 16.  When every target of the wave is
+      // on another body and far from this one, all pairs take the asymptotic branch: no selects.
+      const bool far_all = __all(tb < 0 || (tb != sb && D >= k.far_D));
+      float gr[4], gi[4];
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int64_t j = j0 + 4 * st + (lane >> 4);
+        float u = A + lsq[j];
+        u = fmaf(P[0], l0[j], u);
+        u = fmaf(P[1], l1[j], u);
+        if constexpr (DIM == 3) u = fmaf(P[2], l2[j], u);
+        float pr, pi;
+        if (far_all) {
+          bp_phi<DIM, true>(k, u, D, D2, ph0, pr, pi);
+        } else {
+          bp_phi<DIM>(k, u, D, D2, ph0, pr, pi);
+          const bool same = tb == sb;
+          pr = same ? 0.f : pr;
+          pi = same ? 0.f : pi;
+        }
+        gr[st] = pr;
+        gi[st] = pi;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const float ngi = -gi[st];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const c64 qq = qt[4 * st + (lane >> 4)][16 * b + (lane & 15)];
+          accR[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr[st], qq.re, accR[b], 0, 0, 0);
+          accR[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ngi, qq.im, accR[b], 0, 0, 0);
+          accI[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr[st], qq.im, accI[b], 0, 0, 0);
+          accI[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(gi[st], qq.re, accI[b], 0, 0, 0);
+        }
+      }
+      __syncthreads();
     }
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        sumR[b][i] += (double)accR[b][i];
+        sumI[b][i] += (double)accI[b][i];
+        accR[b][i] = 0.f;
+        accI[b][i] = 0.f;
+      }
   }
   // output layout of the 16x16 MFMA: lane l, register i -> row 4 (l / 16) + i, column l % 16
 #pragma unroll
@@ -651,8 +661,7 @@ __global__ __launch_bounds__(256) void ghat_mfma_kernel(
     for (int i = 0; i < 4; ++i) {
       const int64_t t = tbase + 4 * (lane >> 4) + i;
       if (r < R && t < N)
-        partial[((int64_t)blockIdx.y * R + r) * N + t] =
-            c64{(float)(sumR[b][i] + (double)accR[b][i]), (float)(sumI[b][i] + (double)accI[b][i])};
+        partial[((int64_t)blockIdx.y * R + r) * N + t] = c64{(float)sumR[b][i], (float)sumI[b][i]};
     }
   }
 }

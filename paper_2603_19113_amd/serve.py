@@ -27,13 +27,14 @@ import numpy as np
 
 # ------------------------------------------------------------------ policy ---
 def footprint_bytes(N: int, T: int, R: int, dim: int, restart: int, n_targets: int = 0) -> int:
-    """Device bytes a request holds while it runs (scene tables, pair partial sums, Krylov basis and
-    Hessenberg, solver vectors, caller tensors), mirroring the library's allocations."""
+    """Device bytes a request holds while it runs (scene tables, pair partial sums, complex64 Krylov
+    basis and complex128 Hessenberg, solver vectors, caller tensors), mirroring the library's
+    allocations."""
     scene = N * (8 * dim + 4 * dim + 4 * dim + 4 + 4 + 4) + T * (8 + 4 + 8 * dim)
     partial = 16 * R * N * 16                      # at most 16 source chunks, complex128
     q32 = R * N * 8
     nblk = (N + 1023) // 1024
-    krylov = (restart + 1) * R * N * 16 + R * restart * (restart + 1) * 16 + 2 * R * (restart + 1) * nblk * 8 \
+    krylov = (restart + 1) * R * N * 8 + R * restart * (restart + 1) * 16 + 2 * R * (restart + 1) * nblk * 8 \
         + 6 * R * (restart + 1) * 16
     vecs = 3 * R * N * 16
     caller = 2 * R * N * 16 + R * max(n_targets, 1) * 16
@@ -303,7 +304,7 @@ class GpuExecutor:
                 q = torch.empty_like(v)
                 restart = restart_for(sc.T, sc.kappa, sc.dim)
                 info = mfs.solve(scene, v, q, tol=self.tol, maxit=200000, restart=restart, max_refine=30,
-                                 inner_tol=self.inner_tol, prec=mfs.MFS_MIXED, stream=st)
+                                 inner_tol=self.inner_tol, prec=mfs.MFS_MIXED, stream=st, basis32=True)
                 qh = q.cpu().numpy() if self.keep_solution else None  # synchronises the slot's stream
                 st.synchronize()
                 N = scene.N

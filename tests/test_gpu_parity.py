@@ -402,3 +402,25 @@ def test_solve_graph_replay_is_identical_to_direct_launches(mfs, prec_name, rest
     for q, info in out[1:]:
         assert np.array_equal(q, out[0][0])
         assert info["n_matvec32"] == out[0][1]["n_matvec32"] and info["n_matvec64"] == out[0][1]["n_matvec64"]
+
+
+@pytest.mark.parametrize("key,R", [("starfish32", 1), ("mixed24", 16), ("spheres6", 2)])
+def test_solve_mixed_with_single_precision_basis(mfs, key, R):
+    """basis32: Krylov vectors stored in complex64, everything else as in the mixed solve; the
+    final residual is still checked with the FP64 operator, here recomputed by the oracle."""
+    torch = _torch()
+    sc = SMALL_SCENES[key]()
+    if sc.directions.shape[0] < R:
+        sc.directions = w.plane_wave_directions_2d(np.linspace(0.1, 6.0, R)) if sc.dim == 2 else \
+            np.tile(sc.directions[:1], (R, 1))
+    gsc, Ss = _scene_with_oracle_S(mfs, sc)
+    xh, ptr, bo = gs.pack(sc)
+    v = torch.empty((R, gsc.N), dtype=torch.complex128, device="cuda")
+    mfs.plane_wave(gsc, sc.directions[:R], v)
+    q = torch.empty_like(v)
+    info = mfs.solve(gsc, v, q, tol=1e-8, restart=300, inner_tol=3e-6, prec=mfs.MFS_MIXED, basis32=True)
+    assert info["relres_max"] <= 1e-8
+    b = gs.rhs(sc, Ss, ptr, gs.plane_wave_vhat(sc, xh)[:R])
+    r = b - gs.matvec(sc, Ss, xh, ptr, bo, q.cpu().numpy())
+    for c in range(R):
+        assert np.linalg.norm(r[c]) / np.linalg.norm(b[c]) < 2e-8
