@@ -536,7 +536,7 @@ __global__ __launch_bounds__(256) void ghat_mfma_kernel(
     BodyPhaseConsts k, const float* __restrict__ l0, const float* __restrict__ l1, const float* __restrict__ l2,
     const float* __restrict__ lsq, const double* __restrict__ cen, const int32_t* __restrict__ body_of,
     const c64* __restrict__ q, int64_t N, int R, int64_t chunk_len, c64* __restrict__ partial) {
-  __shared__ c64 qt[kMfmaSrc][kMfmaRhs];  // transposed charge tile
+  __shared__ c64 qt[2][kMfmaSrc][kMfmaRhs];  // transposed charge tiles, double-buffered
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t tbase = (int64_t)blockIdx.x * kMfmaTargets + 16 * wave;
@@ -570,88 +570,139 @@ __global__ __launch_bounds__(256) void ghat_mfma_kernel(
 #pragma unroll
   for (int d = 0; d < DIM; ++d) P[d] = 0.f;
 
-  // Tiles of 16 sources are taken kMfmaFlush at a time with FP32 accumulators, which are then
-  // added into the FP64 sums; keeping the flush outside the inner loop lets the accumulators stay
-  // in the matrix-core registers across the tiles.
-  for (int64_t jb = c0; jb < c1; jb += (int64_t)kMfmaSrc * kMfmaFlush) {
-    const int64_t je = min(c1, jb + (int64_t)kMfmaSrc * kMfmaFlush);
-    for (int64_t j0 = jb; j0 < je; j0 += kMfmaSrc) {
-      // stage Q(j0 .. j0+15, r0 .. r0+63), transposed
-      {
-        const int rr = threadIdx.x >> 2;        // 0..63
-        const int sg = (threadIdx.x & 3) * 4;   // 0, 4, 8, 12
-        const int r = r0 + rr;
+  // Software pipeline over tiles of 16 sources: while the matrix cores work on tile t (charges
+  // from one LDS buffer, phi from registers), the wave loads the charges of tile t + 1, generates
+  // its phi on the VALU and stores the charges into the other buffer; one barrier per tile.
+  // Tiles are taken kMfmaFlush at a time with FP32 accumulators, then added into FP64 sums; the
+  // flush sits outside the inner loop so the accumulators stay in the matrix-core registers.
+  const int rr = threadIdx.x >> 2;        // right-hand side staged by this thread (0..63)
+  const int sg = (threadIdx.x & 3) * 4;   // its four sources in the tile: 0, 4, 8, 12
+  const int rq = r0 + rr;
+  auto load_q = [&](int64_t j0, c64* qr) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) qt[sg + u][rr] = r < R ? q[(int64_t)r * N + j0 + sg + u] : c64{0.f, 0.f};
+    for (int u = 0; u < 4; ++u) qr[u] = rq < R ? q[(int64_t)rq * N + j0 + sg + u] : c64{0.f, 0.f};
+  };
+  auto store_q = [&](int buf, const c64* qr) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) qt[buf][sg + u][rr] = qr[u];
+  };
+  // per (target, source body) quantities for the tile starting at j0; returns whether every target
+  // of the wave is on another body and far from this one (then all pairs take the asymptotic branch)
+  auto body_setup = [&](int64_t j0) {
+    const int sb = body_of[j0];
+    if (sb != cur_sb) {
+      cur_sb = sb;
+      double dd2 = 0.0;
+      float Ai = 0.f;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const double dc = ct[d] - cen[(int64_t)sb * DIM + d];
+        dd2 = fma(dc, dc, dd2);
+        const float dcf = (float)dc;
+        Ai = fmaf(lt[d], lt[d] + 2.0f * dcf, Ai);
+        P[d] = -2.0f * (lt[d] + dcf);
       }
-      // per (target, source body) quantities, recomputed when the tile's body changes
-      const int sb = body_of[j0];
-      if (sb != cur_sb) {
-        cur_sb = sb;
-        double dd2 = 0.0;
-        float Ai = 0.f;
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-          const double dc = ct[d] - cen[(int64_t)sb * DIM + d];
-          dd2 = fma(dc, dc, dd2);
-          const float dcf = (float)dc;
-          Ai = fmaf(lt[d], lt[d] + 2.0f * dcf, Ai);
-          P[d] = -2.0f * (lt[d] + dcf);
-        }
-        const double dd = sqrt(dd2);
-        const double ph = dd * k.kappa_rev64;
-        A = Ai;
-        D = (float)dd;
-        D2 = (float)dd2;
-        ph0 = (float)(ph - floor(ph)) - (DIM == 2 ? 0.125f : 0.0f);
-      }
-      // phi in the A layout: k-step s, source j0 + 4 s + lane / 16.  When every target of the wave is
-      // on another body and far from this one, all pairs take the asymptotic branch: no selects.
-      const bool far_all = __all(tb < 0 || (tb != sb && D >= k.far_D));
-      float gr[4], gi[4];
-#pragma unroll
-      for (int st = 0; st < 4; ++st) {
-        const int64_t j = j0 + 4 * st + (lane >> 4);
-        float u = A + lsq[j];
-        u = fmaf(P[0], l0[j], u);
-        u = fmaf(P[1], l1[j], u);
-        if constexpr (DIM == 3) u = fmaf(P[2], l2[j], u);
-        float pr, pi;
-        if (far_all) {
-          bp_phi<DIM, true>(k, u, D, D2, ph0, pr, pi);
-        } else {
-          bp_phi<DIM>(k, u, D, D2, ph0, pr, pi);
-          const bool same = tb == sb;
-          pr = same ? 0.f : pr;
-          pi = same ? 0.f : pi;
-        }
-        gr[st] = pr;
-        gi[st] = pi;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int st = 0; st < 4; ++st) {
-        const float ngi = -gi[st];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const c64 qq = qt[4 * st + (lane >> 4)][16 * b + (lane & 15)];
-          accR[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr[st], qq.re, accR[b], 0, 0, 0);
-          accR[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ngi, qq.im, accR[b], 0, 0, 0);
-          accI[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr[st], qq.im, accI[b], 0, 0, 0);
-          accI[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(gi[st], qq.re, accI[b], 0, 0, 0);
-        }
-      }
-      __syncthreads();
+      const double dd = sqrt(dd2);
+      const double ph = dd * k.kappa_rev64;
+      A = Ai;
+      D = (float)dd;
+      D2 = (float)dd2;
+      ph0 = (float)(ph - floor(ph)) - (DIM == 2 ? 0.125f : 0.0f);
     }
+    return (bool)__all(tb < 0 || (tb != sb && D >= k.far_D));
+  };
+  // phi in the A layout: k-step s, source j0 + 4 s + lane / 16
+  auto gen_phi = [&](int64_t j0, bool far_all, float* gr, float* gi) {
+    const int sb = cur_sb;
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        sumR[b][i] += (double)accR[b][i];
-        sumI[b][i] += (double)accI[b][i];
-        accR[b][i] = 0.f;
-        accI[b][i] = 0.f;
+    for (int st = 0; st < 4; ++st) {
+      const int64_t j = j0 + 4 * st + (lane >> 4);
+      float u = A + lsq[j];
+      u = fmaf(P[0], l0[j], u);
+      u = fmaf(P[1], l1[j], u);
+      if constexpr (DIM == 3) u = fmaf(P[2], l2[j], u);
+      float pr, pi;
+      if (far_all) {
+        bp_phi<DIM, true>(k, u, D, D2, ph0, pr, pi);
+      } else {
+        bp_phi<DIM>(k, u, D, D2, ph0, pr, pi);
+        const bool same = tb == sb;
+        pr = same ? 0.f : pr;
+        pi = same ? 0.f : pi;
       }
+      gr[st] = pr;
+      gi[st] = pi;
+    }
+  };
+  // the 64 MFMAs of one tile (4 k-steps x 4 blocks of 16 right-hand sides x 4 real products)
+  auto mfma_tile = [&](int buf, const float* gr, const float* gi) {
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const float ngi = -gi[st];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const c64 qq = qt[buf][4 * st + (lane >> 4)][16 * b + (lane & 15)];
+        accR[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr[st], qq.re, accR[b], 0, 0, 0);
+        accR[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ngi, qq.im, accR[b], 0, 0, 0);
+        accI[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr[st], qq.im, accI[b], 0, 0, 0);
+        accI[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(gi[st], qq.re, accI[b], 0, 0, 0);
+      }
+    }
+  };
+
+  if (c0 < c1) {
+    c64 qreg[4];
+    float gr[4], gi[4];
+    load_q(c0, qreg);
+    store_q(0, qreg);
+    gen_phi(c0, body_setup(c0), gr, gi);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t jb = c0; jb < c1; jb += (int64_t)kMfmaSrc * kMfmaFlush) {
+      const int64_t je = min(c1, jb + (int64_t)kMfmaSrc * kMfmaFlush);
+      for (int64_t j0 = jb; j0 < je; j0 += kMfmaSrc) {
+        const int64_t jn = j0 + kMfmaSrc;
+        const bool more = jn < c1;
+        bool far_next = false;
+        if (more) {
+          load_q(jn, qreg);  // in flight during the matrix-core work below
+          far_next = body_setup(jn);
+        }
+        float gn[4], gm[4];
+        if (more && far_next) {
+          // straight-line block: the scheduler interleaves the next tile's phi with this tile's MFMAs
+          mfma_tile(buf, gr, gi);
+          gen_phi(jn, true, gn, gm);
+#pragma unroll
+          for (int i = 0; i < 56; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+            __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // two VALU
+          }
+        } else {
+          mfma_tile(buf, gr, gi);
+          if (more) gen_phi(jn, false, gn, gm);
+        }
+        if (more) {
+          store_q(buf ^ 1, qreg);
+#pragma unroll
+          for (int st = 0; st < 4; ++st) {
+            gr[st] = gn[st];
+            gi[st] = gm[st];
+          }
+        }
+        __syncthreads();
+        buf ^= 1;
+      }
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          sumR[b][i] += (double)accR[b][i];
+          sumI[b][i] += (double)accI[b][i];
+          accR[b][i] = 0.f;
+          accI[b][i] = 0.f;
+        }
+    }
   }
   // output layout of the 16x16 MFMA: lane l, register i -> row 4 (l / 16) + i, column l % 16
 #pragma unroll

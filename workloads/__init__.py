@@ -12,6 +12,8 @@ from .shapes import (  # noqa: F401
     disk2d,
     starfish2d,
     ellipse2d,
+    teardrop2d,
+    cshape2d,
     kite2d,
     sphere3d,
     ellipsoid3d,

@@ -204,3 +204,113 @@ def bumpy_sphere3d(m=900, n=400, src_scale=0.7, k=400, p=900):
 
     return _radial_surface("bumpy_sphere", rad, m, n, src_scale, k, 1.32, p, 1.65, 1.1,
                            dict(kind="bumpy_sphere"))
+
+
+# --------------------------------------------------------------------------
+# Curves with corners: Gauss-Legendre panels, dyadically refined toward the
+# corners, MFS sources offset in proportion to each panel's length.
+# --------------------------------------------------------------------------
+
+def _teardrop_raw(t, beta):
+    """Teardrop (2 sin(t/2), -beta sin t): one corner at t = 0, counter-clockwise."""
+    pts = np.stack([2.0 * np.sin(0.5 * t), -beta * np.sin(t)], axis=-1)
+    der = np.stack([np.cos(0.5 * t), -beta * np.cos(t)], axis=-1)
+    return pts, der
+
+
+def _panel_breaks(base_panels: int, levels: int) -> np.ndarray:
+    """Panel end points in [0, 2 pi]: base_panels equal panels, the two next to the corner at
+    t = 0 = 2 pi split dyadically `levels` times toward it."""
+    h = 2.0 * np.pi / base_panels
+    inner = list(np.linspace(h, 2.0 * np.pi - h, base_panels - 1))
+    near0 = [h / 2.0 ** l for l in range(levels, 0, -1)]
+    near2pi = [2.0 * np.pi - x for x in reversed(near0)]
+    return np.array([0.0] + near0 + inner + near2pi + [2.0 * np.pi])
+
+
+def teardrop2d(bounding=0.65, beta=1.0, base_panels=16, levels=8, q=16, d_frac=0.2, k=128, rho_eq=0.70,
+               r_psi=0.75, p=None):
+    """Teardrop with a corner, scaled to the given bounding radius (centred on its bounding box).
+
+    Each panel carries q Gauss-Legendre collocation points and q/2 MFS sources (n = m/2), the
+    sources offset inward by d_frac times the panel's arclength.  Equivalent points: k on a circle
+    of radius rho_eq (the paper-mode skeleton can be taken from the collocation points instead).
+    """
+    breaks = _panel_breaks(base_panels, levels)
+    xq, _ = np.polynomial.legendre.leggauss(q)
+    xs, _ = np.polynomial.legendre.leggauss(q // 2)
+    col_t, src_t, src_d = [], [], []
+    # arclength of each panel from a fine quadrature of |gamma'|
+    xg, wg = np.polynomial.legendre.leggauss(32)
+    for a, b in zip(breaks[:-1], breaks[1:]):
+        mid, half = 0.5 * (a + b), 0.5 * (b - a)
+        _, dg = _teardrop_raw(mid + half * xg, beta)
+        length = half * float(np.sum(wg * np.linalg.norm(dg, axis=1)))
+        col_t.append(mid + half * xq)
+        src_t.append(mid + half * xs)
+        src_d.append(np.full(q // 2, d_frac * length))
+    col_t, src_t, src_d = np.concatenate(col_t), np.concatenate(src_t), np.concatenate(src_d)
+    raw_c, _ = _teardrop_raw(col_t, beta)
+    raw_s, der_s = _teardrop_raw(src_t, beta)
+    # centre and scale from a fixed dense sampling of the exact curve, so that every
+    # discretisation describes the same body
+    dense, _ = _teardrop_raw(np.linspace(0.0, 2.0 * np.pi, 200001), beta)
+    lo, hi = dense.min(0), dense.max(0)
+    centre = 0.5 * (lo + hi)
+    scale = bounding / np.linalg.norm(dense - centre, axis=1).max()
+    colloc = (raw_c - centre) * scale
+    on_curve = (raw_s - centre) * scale
+    tang = der_s / np.linalg.norm(der_s, axis=1, keepdims=True)
+    outward = np.stack([tang[:, 1], -tang[:, 0]], axis=-1)  # counter-clockwise curve
+    src = on_curve - (src_d * scale)[:, None] * outward
+    m = colloc.shape[0]
+    return ShapeDiscretisation(
+        name="teardrop", dim=2, colloc=colloc, src=src,
+        proxy=circle_points(p if p is not None else m + 1, r_psi),
+        eqpts=circle_points(k, rho_eq), bounding_radius=bounding, proxy_radius=r_psi,
+        meta=dict(kind="teardrop", beta=beta, base_panels=base_panels, levels=levels, q=q, d_frac=d_frac,
+                  corner=(np.array([0.0, 0.0]) - centre) * scale))
+
+
+def _polygon_panels(vertices, base_per_edge, levels, q, d_frac):
+    """Collocation points and MFS sources on a counter-clockwise polygon: each edge is split into
+    base_per_edge panels, the end panels refined dyadically toward both vertices; q Gauss-Legendre
+    collocation points and q/2 sources per panel, sources offset inward along the edge normal by
+    d_frac times the panel length."""
+    xq, _ = np.polynomial.legendre.leggauss(q)
+    xs, _ = np.polynomial.legendre.leggauss(q // 2)
+    col, src = [], []
+    V = np.asarray(vertices, np.float64)
+    for e in range(V.shape[0]):
+        a, b = V[e], V[(e + 1) % V.shape[0]]
+        edge = b - a
+        length = float(np.linalg.norm(edge))
+        tang = edge / length
+        inward = np.array([-tang[1], tang[0]])  # left of the direction of travel
+        h = 1.0 / base_per_edge
+        brk = [0.0] + [h / 2.0 ** l for l in range(levels, 0, -1)]
+        brk += list(np.linspace(h, 1.0 - h, base_per_edge - 1))
+        brk += [1.0 - h / 2.0 ** l for l in range(1, levels + 1)] + [1.0]
+        brk = np.array(sorted(set(brk)))
+        for s0, s1 in zip(brk[:-1], brk[1:]):
+            mid, half = 0.5 * (s0 + s1), 0.5 * (s1 - s0)
+            plen = 2.0 * half * length
+            col.append(a[None, :] + (mid + half * xq)[:, None] * edge[None, :])
+            src.append(a[None, :] + (mid + half * xs)[:, None] * edge[None, :] + d_frac * plen * inward[None, :])
+    return np.concatenate(col), np.concatenate(src)
+
+
+def cshape2d(bounding=0.65, base_per_edge=4, levels=8, q=16, d_frac=0.5, k=128, rho_eq=0.70, r_psi=0.75,
+             p=None):
+    """A C-shaped cavity (a square with a slot cut into one side): eight corners, two of them
+    re-entrant, scaled to the given bounding radius."""
+    raw = np.array([[-1.0, -1.0], [1.0, -1.0], [1.0, -0.3], [-0.3, -0.3], [-0.3, 0.3], [1.0, 0.3],
+                    [1.0, 1.0], [-1.0, 1.0]])
+    scale = bounding / np.linalg.norm(raw, axis=1).max()
+    colloc, src = _polygon_panels(raw * scale, base_per_edge, levels, q, d_frac)
+    m = colloc.shape[0]
+    return ShapeDiscretisation(
+        name="cshape", dim=2, colloc=colloc, src=src, proxy=circle_points(p if p is not None else m + 1, r_psi),
+        eqpts=circle_points(k, rho_eq), bounding_radius=bounding, proxy_radius=r_psi,
+        meta=dict(kind="cshape", base_per_edge=base_per_edge, levels=levels, q=q, d_frac=d_frac,
+                  vertices=raw * scale))
