@@ -25,7 +25,7 @@ def pack(scene):
     pts, body_of, ptr = [], [], [0]
     for tau in range(scene.T):
         s = scene.shapes[int(scene.shape_of[tau])]
-        pts.append(s.eqpts + scene.centres[tau][None, :])
+        pts.append(scene.place(tau, s.eqpts))  # x_hat = R_tau template + c_tau
         body_of.append(np.full(s.k, tau, dtype=np.int64))
         ptr.append(ptr[-1] + s.k)
     return np.concatenate(pts, 0), np.asarray(ptr, np.int64), np.concatenate(body_of)

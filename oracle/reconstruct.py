@@ -1,5 +1,7 @@
 """Full MFS sources of each body and the field near the bodies (Sec. 4.6 and the field formula of
-Sec. 2.3).  Test infrastructure only, like the rest of this package.
+Sec. 2.3).  Test infrastructure only, like the rest of this package.  Bodies may be rotated copies of
+their shape (scene.rotations): every point set of the body turns with it and S, A and U, which
+depend only on distances within the body, are the shape's.
 
 After the global solve, the equivalent sources q_hat of body tau represent its scattered field only
 outside its proxy surface Psi_tau.  Closer in, the paper reconstructs the body's own MFS sources
@@ -43,8 +45,7 @@ def collocation_offsets(scene) -> tuple[np.ndarray, np.ndarray]:
 def plane_wave_on_boundary(scene, directions=None) -> np.ndarray:
     """v = -exp(i kappa d . x) at every body's collocation points, [R, sum m] (footnote to eq. BVP)."""
     dirs = np.atleast_2d(scene.directions if directions is None else directions)
-    pts = np.concatenate([scene.shapes[int(s)].colloc + scene.centres[t][None, :]
-                          for t, s in enumerate(scene.shape_of)], 0)
+    pts = np.concatenate([scene.place(t, scene.shapes[int(s)].colloc) for t, s in enumerate(scene.shape_of)], 0)
     return -np.exp(1j * scene.kappa * (dirs @ pts.T))
 
 
@@ -83,6 +84,6 @@ def field_near(scene, xhat, qhat, q_mfs, targets) -> np.ndarray:
             u[:, ~near] += qhat[:, kptr[t]:kptr[t + 1]] @ phi_matrix(targets[~near], xhat[kptr[t]:kptr[t + 1]],
                                                                       scene.kappa).T
         if np.any(near):
-            u[:, near] += q_mfs[:, sptr[t]:sptr[t + 1]] @ phi_matrix(targets[near], sh.src + c[None, :],
+            u[:, near] += q_mfs[:, sptr[t]:sptr[t + 1]] @ phi_matrix(targets[near], scene.place(t, sh.src),
                                                                       scene.kappa).T
     return u

@@ -18,6 +18,7 @@ from .shapes import (  # noqa: F401
     sphere3d,
     ellipsoid3d,
     bumpy_sphere3d,
+    torus3d,
     fibonacci_sphere,
     circle_points,
 )
@@ -25,6 +26,7 @@ from .scenes import (  # noqa: F401
     Scene,
     grid_centres_2d,
     random_centres,
+    random_rotations,
     plane_wave_directions_2d,
     far_targets,
 )

@@ -25,6 +25,13 @@ class Scene:
     centres: np.ndarray  # float64 [T, dim]
     directions: np.ndarray  # float64 [R, dim], unit incident directions
     name: str = ""
+    rotations: np.ndarray | None = None  # float64 [T, dim, dim] body orientations, None: identity
+
+    def place(self, t: int, pts: np.ndarray) -> np.ndarray:
+        """Body-frame points of body t in world coordinates: R_t p + c_t."""
+        if self.rotations is None:
+            return pts + self.centres[t][None, :]
+        return pts @ self.rotations[t].T + self.centres[t][None, :]
 
     @property
     def T(self) -> int:
@@ -127,3 +134,21 @@ __all__ = [
     "far_targets",
     "shapes_summary",
 ]
+
+
+def random_rotations(T: int, dim: int, seed: int) -> np.ndarray:
+    """T seeded proper rotations: angles uniform in 2D, uniform on SO(3) in 3D (QR of a Gaussian
+    matrix with the sign fixed)."""
+    rng = np.random.default_rng(seed)
+    if dim == 2:
+        a = rng.uniform(0.0, 2.0 * np.pi, size=T)
+        c, s = np.cos(a), np.sin(a)
+        return np.stack([np.stack([c, -s], -1), np.stack([s, c], -1)], -2)
+    out = np.empty((T, 3, 3))
+    for t in range(T):
+        q, r = np.linalg.qr(rng.normal(size=(3, 3)))
+        q = q * np.sign(np.diag(r))[None, :]
+        if np.linalg.det(q) < 0:
+            q[:, 0] = -q[:, 0]
+        out[t] = q
+    return out

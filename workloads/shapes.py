@@ -314,3 +314,23 @@ def cshape2d(bounding=0.65, base_per_edge=4, levels=8, q=16, d_frac=0.5, k=128, 
         eqpts=circle_points(k, rho_eq), bounding_radius=bounding, proxy_radius=r_psi,
         meta=dict(kind="cshape", base_per_edge=base_per_edge, levels=levels, q=q, d_frac=d_frac,
                   vertices=raw * scale))
+
+
+def torus3d(R0=0.7, a=0.3, n_u=40, n_v=20, src_frac=0.3, k=400, rho_eq=None, p=900, r_psi=None):
+    """Torus ((R0 + a cos v) cos u, (R0 + a cos v) sin u, a sin v) on a tensor grid in (u, v)
+    (Sec. 3.4): n_u x n_v collocation points, (n_u/2) x (n_v/2) MFS sources (n = m/4) on the
+    concentric torus of tube radius src_frac * a.  Equivalent and proxy points on spheres about
+    the centre (a torus is not star-shaped, but both spheres enclose it)."""
+    def grid(nu, nv, tube):
+        u = 2.0 * np.pi * (np.arange(nu) + 0.5) / nu
+        v = 2.0 * np.pi * (np.arange(nv) + 0.5) / nv
+        U, V = np.meshgrid(u, v, indexing="ij")
+        rr = R0 + tube * np.cos(V)
+        return np.stack([rr * np.cos(U), rr * np.sin(U), tube * np.sin(V)], -1).reshape(-1, 3)
+    bounding = R0 + a
+    rho = 1.2 * bounding if rho_eq is None else rho_eq
+    rp = 1.5 * bounding if r_psi is None else r_psi
+    return ShapeDiscretisation(
+        name="torus", dim=3, colloc=grid(n_u, n_v, a), src=grid(n_u // 2, n_v // 2, src_frac * a),
+        proxy=fibonacci_sphere(p, rp), eqpts=fibonacci_sphere(k, rho), bounding_radius=bounding,
+        proxy_radius=rp, meta=dict(kind="torus", R0=R0, a=a, n_u=n_u, n_v=n_v, src_frac=src_frac))
