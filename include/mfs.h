@@ -115,6 +115,10 @@ typedef struct mfs_scene mfs_scene;
  *   T               number of bodies >= 1
  *   shape_of        host int32[T], values in [0, n_shapes)
  *   centres         host double[T][dim]
+ *   rotations       host double[T][dim][dim] (row-major), the orientation R_tau of each body, or
+ *                   NULL for none: body tau's points are R_tau p + c_tau for every point p of its
+ *                   shape.  A body's S, A and U depend only on distances, so turned copies share
+ *                   their shape's matrices (Sec. 5.1, Example 4).  Each must be a proper rotation.
  *   k_of_shape      host int64[n_shapes], equivalent points per shape (1..4096)
  *   eq_template     host array of n_shapes pointers to double[k_s][dim] (body frame)
  *   S64_dev         host array of n_shapes device pointers to complex128 k_s x k_s column-major
@@ -123,7 +127,7 @@ typedef struct mfs_scene mfs_scene;
  * The S buffers stay owned by the caller and must outlive the scene.  Total N = sum k <= 2^31-1.
  * Errors: MFS_ERR_ARG, MFS_ERR_NOMEM, MFS_ERR_HIP. */
 mfs_status mfs_scene_create(int32_t dim, double kappa, int64_t T, const int32_t* shape_of,
-                            const double* centres, int32_t n_shapes, const int64_t* k_of_shape,
+                            const double* centres, const double* rotations, int32_t n_shapes, const int64_t* k_of_shape,
                             const double* const* eq_template, const void* const* S64_dev,
                             const void* const* S32_dev, mfs_scene** out);
 

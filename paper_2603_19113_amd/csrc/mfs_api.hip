@@ -112,7 +112,7 @@ struct mfs_scene {
   size_t bytes = 0;
   hipStream_t last_stream = nullptr;  // stream of the latest call; releases are ordered after it
   // owned tables
-  Buf x64, x32, l32, lsq, centres, body_of, body_ptr, shape_of, k_dev, S64_tab, S32_tab;
+  Buf x64, x32, l32, lsq, centres, body_of, body_ptr, shape_of, k_dev, S64_tab, S32_tab, rot;
   // workspaces
   Buf partial, q32, dirs, kry, vecs;
   // near-field tables for the last set of reconstruction factors used with this scene
@@ -308,7 +308,7 @@ mfs_status mfs_build_S(const mfs_shape_desc* desc, void* S64_dev, void* S32_dev,
 }
 
 mfs_status mfs_scene_create(int32_t dim, double kappa, int64_t T, const int32_t* shape_of, const double* centres,
-                            int32_t n_shapes, const int64_t* k_of_shape, const double* const* eq_template,
+                            const double* rotations, int32_t n_shapes, const int64_t* k_of_shape, const double* const* eq_template,
                             const void* const* S64_dev, const void* const* S32_dev, mfs_scene** out) {
   g_last_error.clear();
   if (!out) return fail(MFS_ERR_ARG, "out is null");
@@ -333,6 +333,22 @@ mfs_status mfs_scene_create(int32_t dim, double kappa, int64_t T, const int32_t*
     const int s = shape_of[t];
     if (s < 0 || s >= n_shapes) return fail(MFS_ERR_ARG, "shape_of[" + std::to_string(t) + "] out of range");
     body_ptr[t + 1] = body_ptr[t] + k_of_shape[s];
+    if (rotations) {
+      // a proper orthogonal matrix: R R^T = I to rounding, det > 0
+      const double* Rt = rotations + t * dim * dim;
+      double worst = 0.0;
+      for (int a = 0; a < dim; ++a)
+        for (int b2 = 0; b2 < dim; ++b2) {
+          double dot = 0.0;
+          for (int e = 0; e < dim; ++e) dot += Rt[a * dim + e] * Rt[b2 * dim + e];
+          worst = std::max(worst, std::fabs(dot - (a == b2 ? 1.0 : 0.0)));
+        }
+      const double det = dim == 2 ? Rt[0] * Rt[3] - Rt[1] * Rt[2]
+                                  : Rt[0] * (Rt[4] * Rt[8] - Rt[5] * Rt[7]) - Rt[1] * (Rt[3] * Rt[8] - Rt[5] * Rt[6]) +
+                                        Rt[2] * (Rt[3] * Rt[7] - Rt[4] * Rt[6]);
+      if (!(worst < 1e-10) || !(det > 0.0))
+        return fail(MFS_ERR_ARG, "rotations[" + std::to_string(t) + "] is not a proper rotation");
+    }
     for (int d = 0; d < dim; ++d) {
       const double c = centres[t * dim + d];
       if (!std::isfinite(c)) return fail(MFS_ERR_ARG, "non-finite centre");
@@ -384,6 +400,8 @@ mfs_status mfs_scene_create(int32_t dim, double kappa, int64_t T, const int32_t*
   if ((st = ensure(sc->k_dev, sizeof(int64_t) * n_shapes, &sc->bytes, ps)) != MFS_OK) return cleanup(st);
   if ((st = ensure(sc->S64_tab, sizeof(void*) * n_shapes, &sc->bytes, ps)) != MFS_OK) return cleanup(st);
   if ((st = ensure(sc->S32_tab, sizeof(void*) * n_shapes, &sc->bytes, ps)) != MFS_OK) return cleanup(st);
+  if (rotations && (st = ensure(sc->rot, sizeof(double) * T * dim * dim, &sc->bytes, ps)) != MFS_OK)
+    return cleanup(st);
   if ((st = ensure(tmpl_d, sizeof(double) * tmpl.size(), &tmp_bytes, ps)) != MFS_OK) return cleanup(st);
   if ((st = ensure(tmpl_ptr_d, sizeof(int64_t) * tmpl_ptr.size(), &tmp_bytes, ps)) != MFS_OK) return cleanup(st);
 
@@ -400,11 +418,12 @@ mfs_status mfs_scene_create(int32_t dim, double kappa, int64_t T, const int32_t*
   cp(sc->S64_tab.p, S64_dev, sizeof(void*) * n_shapes);
   cp(sc->S32_tab.p, s32v.data(), sizeof(void*) * n_shapes);
   cp(sc->centres.p, centres, sizeof(double) * T * dim);
+  if (rotations) cp(sc->rot.p, rotations, sizeof(double) * T * dim * dim);
   cp(tmpl_d.p, tmpl.data(), sizeof(double) * tmpl.size());
   cp(tmpl_ptr_d.p, tmpl_ptr.data(), sizeof(int64_t) * tmpl_ptr.size());
   if (e == hipSuccess)
     e = launch_pack_scene(dim, T, static_cast<int32_t*>(sc->shape_of.p), static_cast<double*>(sc->centres.p),
-                          static_cast<int64_t*>(tmpl_ptr_d.p), static_cast<double*>(tmpl_d.p),
+                          rotations ? static_cast<double*>(sc->rot.p) : nullptr, static_cast<int64_t*>(tmpl_ptr_d.p), static_cast<double*>(tmpl_d.p),
                           static_cast<int64_t*>(sc->body_ptr.p), origin, static_cast<double*>(sc->x64.p),
                           static_cast<float*>(sc->x32.p), static_cast<float*>(sc->l32.p),
                           static_cast<float*>(sc->lsq.p), static_cast<int32_t*>(sc->body_of.p), N, ps);
@@ -425,6 +444,7 @@ mfs_status mfs_scene_create(int32_t dim, double kappa, int64_t T, const int32_t*
     d.l32[i] = i < dim ? static_cast<float*>(sc->l32.p) + (size_t)i * N : nullptr;
   }
   d.centres = static_cast<double*>(sc->centres.p);
+  d.rot = rotations ? static_cast<double*>(sc->rot.p) : nullptr;
   d.lsq32 = static_cast<float*>(sc->lsq.p);
   d.body_of = static_cast<int32_t*>(sc->body_of.p);
   d.body_ptr = static_cast<int64_t*>(sc->body_ptr.p);
@@ -448,7 +468,7 @@ mfs_status mfs_scene_create(int32_t dim, double kappa, int64_t T, const int32_t*
 mfs_status mfs_scene_destroy(mfs_scene* s) {
   if (!s) return MFS_OK;
   Buf* all[] = {&s->x64, &s->x32, &s->l32, &s->lsq, &s->centres, &s->body_of, &s->body_ptr, &s->shape_of, &s->k_dev, &s->S64_tab,
-                &s->S32_tab, &s->partial, &s->q32, &s->dirs, &s->kry, &s->vecs, &s->near_tab};
+                &s->S32_tab, &s->rot, &s->partial, &s->q32, &s->dirs, &s->kry, &s->vecs, &s->near_tab};
   for (Buf* b : all) release(*b, &s->bytes, s->last_stream);
   delete s;
   return MFS_OK;

@@ -51,6 +51,7 @@ struct SceneDev {
   double offbody_pairs;           // N^2 - sum_tau k_tau^2
   bool all_k_mult16;              // every shape has a multiple of 16 points (matrix-core path)
   double rho_max;                 // largest |x_hat - c_body| over all shapes
+  const double* rot;              // [T][dim][dim] body orientations (row-major), or null: identity
 };
 
 // ------------------------------------------------------- kernel launchers ---
@@ -88,7 +89,7 @@ hipError_t launch_sapply_mixed(const SceneDev& s, const c64* partial, int nchunk
 hipError_t launch_to_c64(const c128* in, c64* out, int64_t n, hipStream_t st);
 hipError_t launch_plane_wave(const SceneDev& s, const double* dirs_dev, int R, c128* vhat, hipStream_t st);
 hipError_t launch_pack_scene(int dim, int64_t T, const int32_t* shape_of, const double* centres,
-                             const int64_t* tmpl_ptr, const double* tmpl_pts, const int64_t* body_ptr,
+                             const double* rot, const int64_t* tmpl_ptr, const double* tmpl_pts, const int64_t* body_ptr,
                              const double* origin, double* x64_soa, float* x32_soa, float* l32_soa,
                              float* lsq, int32_t* body_of, int64_t N, hipStream_t st);
 

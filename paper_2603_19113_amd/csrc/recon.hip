@@ -17,9 +17,22 @@ namespace mfs {
 namespace {
 
 // v[r][cptr[b] + i] = -exp(i kappa d_r . (c_b + x_i)), x_i the collocation points of b's shape.
+// Body-frame point p of body b in world coordinates: c_b + R_b p (R null: identity).
+__device__ __forceinline__ double placed(const double* __restrict__ centres, const double* __restrict__ rot,
+                                         int dim, int64_t b, const double* p, int d) {
+  double v = centres[b * dim + d];
+  if (rot) {
+    const double* Rr = rot + (b * dim + d) * dim;
+    for (int e = 0; e < dim; ++e) v += Rr[e] * p[e];
+  } else {
+    v += p[d];
+  }
+  return v;
+}
+
 __global__ void plane_wave_colloc_kernel(int dim, double kappa, const double* __restrict__ centres,
-                                         const int32_t* __restrict__ shape_of, NearTables t,
-                                         const double* __restrict__ dirs, c128* __restrict__ v) {
+                                         const double* __restrict__ rot, const int32_t* __restrict__ shape_of,
+                                         NearTables t, const double* __restrict__ dirs, c128* __restrict__ v) {
   const int b = blockIdx.y, r = blockIdx.z;
   const int s = shape_of[b];
   const int m = t.m_of_shape[s];
@@ -27,7 +40,7 @@ __global__ void plane_wave_colloc_kernel(int dim, double kappa, const double* __
   if (i >= m) return;
   const double* x = t.colloc_of_shape[s] + (int64_t)i * dim;
   double ph = 0.0;
-  for (int d = 0; d < dim; ++d) ph += dirs[r * dim + d] * (centres[(int64_t)b * dim + d] + x[d]);
+  for (int d = 0; d < dim; ++d) ph += dirs[r * dim + d] * placed(centres, rot, dim, b, x, d);
   double sn, cs;
   sincos(kappa * ph, &sn, &cs);
   v[(int64_t)r * t.Mtot + t.cptr[b] + i] = c128{-cs, -sn};
@@ -71,6 +84,7 @@ template <int DIM>
 __global__ __launch_bounds__(256) void eval_near_kernel(double kappa, const double* __restrict__ x0,
                                                         const double* __restrict__ x1, const double* __restrict__ x2,
                                                         const double* __restrict__ centres,
+                                                        const double* __restrict__ rot,
                                                         const int64_t* __restrict__ body_ptr,
                                                         const int32_t* __restrict__ shape_of, NearTables t,
                                                         const c128* __restrict__ qhat, const c128* __restrict__ qmfs,
@@ -98,7 +112,7 @@ __global__ __launch_bounds__(256) void eval_near_kernel(double kappa, const doub
       for (int j = 0; j < n; ++j) {
         double d2 = 0.0;
         for (int d = 0; d < DIM; ++d) {
-          const double e = x[d] - (c[d] + y[j * DIM + d]);
+          const double e = x[d] - placed(centres, rot, DIM, b, y + j * DIM, d);
           d2 += e * e;
         }
         double pr, pi;
@@ -133,7 +147,7 @@ __global__ __launch_bounds__(256) void eval_near_kernel(double kappa, const doub
 hipError_t launch_plane_wave_colloc(const SceneDev& s, const NearTables& t, const double* dirs, int R, c128* v,
                                     hipStream_t st) {
   hipLaunchKernelGGL(plane_wave_colloc_kernel, dim3((unsigned)((t.mmax + 255) / 256), (unsigned)s.T, (unsigned)R),
-                     dim3(256), 0, st, s.dim, s.kappa, s.centres, s.shape_of, t, dirs, v);
+                     dim3(256), 0, st, s.dim, s.kappa, s.centres, s.rot, s.shape_of, t, dirs, v);
   return hipGetLastError();
 }
 
@@ -158,10 +172,10 @@ hipError_t launch_eval_near(const SceneDev& s, const NearTables& t, const c128* 
   dim3 grid((unsigned)((M + 255) / 256), (unsigned)nchunks, (unsigned)R);
   if (s.dim == 2)
     hipLaunchKernelGGL(eval_near_kernel<2>, grid, dim3(256), 0, st, s.kappa, s.x64[0], s.x64[1], s.x64[2], s.centres,
-                       s.body_ptr, s.shape_of, t, qhat, qmfs, s.N, targets, M, s.T, bchunk, partial);
+                       s.rot, s.body_ptr, s.shape_of, t, qhat, qmfs, s.N, targets, M, s.T, bchunk, partial);
   else
     hipLaunchKernelGGL(eval_near_kernel<3>, grid, dim3(256), 0, st, s.kappa, s.x64[0], s.x64[1], s.x64[2], s.centres,
-                       s.body_ptr, s.shape_of, t, qhat, qmfs, s.N, targets, M, s.T, bchunk, partial);
+                       s.rot, s.body_ptr, s.shape_of, t, qhat, qmfs, s.N, targets, M, s.T, bchunk, partial);
   return hipGetLastError();
 }
 

@@ -90,7 +90,8 @@ __global__ void plane_wave_kernel(int dim, double kappa, const double* __restric
 }
 
 __global__ void pack_scene_kernel(int dim, int64_t T, const int32_t* __restrict__ shape_of,
-                                  const double* __restrict__ centres, const int64_t* __restrict__ tmpl_ptr,
+                                  const double* __restrict__ centres, const double* __restrict__ rot,
+                                  const int64_t* __restrict__ tmpl_ptr,
                                   const double* __restrict__ tmpl_pts, const int64_t* __restrict__ body_ptr,
                                   double ox, double oy, double oz, double* __restrict__ x64,
                                   float* __restrict__ x32, float* __restrict__ l32, float* __restrict__ lsq,
@@ -107,7 +108,17 @@ __global__ void pack_scene_kernel(int dim, int64_t T, const int32_t* __restrict_
   const int64_t tau = lo;
   const int64_t l = i - body_ptr[tau];
   const int s = shape_of[tau];
-  const double* p = tmpl_pts + (tmpl_ptr[s] + l) * dim;
+  const double* p0 = tmpl_pts + (tmpl_ptr[s] + l) * dim;
+  // body-frame offset turned with the body: p = R_tau p0 (R row-major [dim][dim]; null: identity)
+  double p[3] = {0.0, 0.0, 0.0};
+  for (int d = 0; d < dim; ++d) {
+    if (rot) {
+      const double* Rr = rot + (tau * dim + d) * dim;
+      for (int e = 0; e < dim; ++e) p[d] += Rr[e] * p0[e];
+    } else {
+      p[d] = p0[d];
+    }
+  }
   const double o[3] = {ox, oy, oz};
   float l2 = 0.0f;
   for (int d = 0; d < dim; ++d) {
@@ -153,11 +164,11 @@ hipError_t launch_plane_wave(const SceneDev& s, const double* dirs_dev, int R, c
 }
 
 hipError_t launch_pack_scene(int dim, int64_t T, const int32_t* shape_of, const double* centres,
-                             const int64_t* tmpl_ptr, const double* tmpl_pts, const int64_t* body_ptr,
+                             const double* rot, const int64_t* tmpl_ptr, const double* tmpl_pts, const int64_t* body_ptr,
                              const double* origin, double* x64_soa, float* x32_soa, float* l32_soa,
                              float* lsq, int32_t* body_of, int64_t N, hipStream_t st) {
   hipLaunchKernelGGL(pack_scene_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, dim, T, shape_of,
-                     centres, tmpl_ptr, tmpl_pts, body_ptr, origin[0], origin[1], origin[2], x64_soa, x32_soa,
+                     centres, rot, tmpl_ptr, tmpl_pts, body_ptr, origin[0], origin[1], origin[2], x64_soa, x32_soa,
                      l32_soa, lsq, body_of, N);
   return hipGetLastError();
 }

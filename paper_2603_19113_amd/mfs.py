@@ -85,7 +85,7 @@ def load(path: str = LIB_PATH):
         "mfs_last_error": ([], ctypes.c_char_p),
         "mfs_version": ([], ctypes.c_int),
         "mfs_build_S": ([ctypes.POINTER(ShapeDesc), vp, vp, ctypes.POINTER(i64), vp, vp, vp], ctypes.c_int),
-        "mfs_scene_create": ([i32, f64, i64, vp, vp, i32, vp, vp, vp, vp, ctypes.POINTER(vp)], ctypes.c_int),
+        "mfs_scene_create": ([i32, f64, i64, vp, vp, vp, i32, vp, vp, vp, vp, ctypes.POINTER(vp)], ctypes.c_int),
         "mfs_scene_destroy": ([vp], ctypes.c_int),
         "mfs_scene_size": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_size_t)],
                            ctypes.c_int),
@@ -196,13 +196,14 @@ def build_S(shape, kappa: float, eps_ls: float = 1e-13, paper_mode: bool = False
 class Scene:
     """Owns an mfs_scene.  S64/S32 are lists of device tensors (column-major k x k storage)."""
 
-    def __init__(self, dim: int, kappa: float, shape_of, centres, templates, S64, S32=None):
+    def __init__(self, dim: int, kappa: float, shape_of, centres, templates, S64, S32=None, rotations=None):
         lib = load()
         self._keep = []
         self.dim = int(dim)
         self.kappa = float(kappa)
         shape_of = _host(shape_of, np.int32)
         centres = _host(centres)
+        rot = _host(rotations) if rotations is not None else None
         n_shapes = len(templates)
         tmpl = [_host(t) for t in templates]
         k_of = np.array([t.shape[0] for t in tmpl], dtype=np.int64)
@@ -211,9 +212,10 @@ class Scene:
         s32 = (ctypes.c_void_p * n_shapes)(*[s.data_ptr() for s in S32]) if S32 is not None else None
         self._keep += [shape_of, centres, tmpl, k_of, list(S64), list(S32) if S32 is not None else None]
         h = ctypes.c_void_p(0)
+        self._keep.append(rot)
         _check(lib.mfs_scene_create(self.dim, self.kappa, shape_of.shape[0], shape_of.ctypes.data,
-                                    centres.ctypes.data, n_shapes, k_of.ctypes.data, tmpl_ptrs, s64, s32,
-                                    ctypes.byref(h)))
+                                    centres.ctypes.data, rot.ctypes.data if rot is not None else None, n_shapes,
+                                    k_of.ctypes.data, tmpl_ptrs, s64, s32, ctypes.byref(h)))
         self.handle = h
         n = ctypes.c_int64(0)
         t = ctypes.c_int64(0)

@@ -17,7 +17,7 @@ def s_to_device(S: np.ndarray):
 
 def make_gpu_scene(mfs, sc, S_list_dev64, S_list_dev32):
     return mfs.Scene(sc.dim, sc.kappa, sc.shape_of, sc.centres, [s.eqpts for s in sc.shapes], S_list_dev64,
-                     S_list_dev32)
+                     S_list_dev32, rotations=getattr(sc, "rotations", None))
 
 
 def rel_err(a, b) -> float:

@@ -47,10 +47,12 @@ def test_invalid_arguments_rejected_without_device(lib):
     out = ctypes.c_void_p(0)
     k = np.array([4], np.int64)
     # dim 4 is rejected before any allocation
-    assert lib.mfs_scene_create(4, 1.0, 1, None, None, 1, k.ctypes.data, None, None, None, ctypes.byref(out)) == -1
+    assert lib.mfs_scene_create(4, 1.0, 1, None, None, None, 1, k.ctypes.data, None, None, None,
+                                ctypes.byref(out)) == -1
     assert b"dim" in lib.mfs_last_error()
     # non-positive wavenumber
-    assert lib.mfs_scene_create(2, -1.0, 1, None, None, 1, k.ctypes.data, None, None, None, ctypes.byref(out)) == -1
+    assert lib.mfs_scene_create(2, -1.0, 1, None, None, None, 1, k.ctypes.data, None, None, None,
+                                ctypes.byref(out)) == -1
     # null scene for every scene entry point
     assert lib.mfs_apply(None, None, None, 1, 0, None) == -1
     assert lib.mfs_ghat_apply(None, None, None, 1, 0, None) == -1
@@ -98,3 +100,17 @@ def test_reconstruction_entry_points_reject_null_arguments(lib):
     assert lib.mfs_reconstruct(None, None, None, None, 1, None, None) == -1
     assert lib.mfs_eval_field_near(None, None, None, None, 1, None, 0, None, None) == -1
     assert lib.mfs_plane_wave_colloc(None, None, None, 1, None, None) == -1
+
+
+def test_scene_rejects_improper_rotation_without_device(lib):
+    out = ctypes.c_void_p(0)
+    k = np.array([4], np.int64)
+    shape_of = np.zeros(1, np.int32)
+    centres = np.zeros((1, 2))
+    reflection = np.array([[[1.0, 0.0], [0.0, -1.0]]])
+    tmpl = np.zeros((4, 2))
+    tp = (ctypes.c_void_p * 1)(tmpl.ctypes.data)
+    sp = (ctypes.c_void_p * 1)(1)  # never dereferenced: validation fails first
+    assert lib.mfs_scene_create(2, 1.0, 1, shape_of.ctypes.data, centres.ctypes.data, reflection.ctypes.data, 1,
+                                k.ctypes.data, tp, sp, None, ctypes.byref(out)) == -1
+    assert b"rotation" in lib.mfs_last_error()
