@@ -239,6 +239,7 @@ struct BodyPhaseConsts {
   Phi2DConstsF32 as;
   double kappa_rev64;
   float far_D;       // centre distance beyond which every pair of two bodies has z >= 12
+  float vfar_D;      // centre distance beyond which every pair has z >= 100 (shorter expansions)
 };
 
 template <int DIM, int TPT, int RT>
@@ -253,7 +254,9 @@ struct BPAcc {
   float sr_[TPT][RT], si_[TPT][RT];  // FP32 partial sums over the current source body
 };
 
-template <int DIM, bool FAR_ONLY = false>
+// FAR: 0 = any distance (branches), 1 = every pair has z >= 12, 2 = every pair has z >= 100, where
+// the z^-4 modulus term (< 1e-9 relative) and the z^-5 phase term (< 2e-11 rad) are dropped.
+template <int DIM, int FAR = 0>
 __device__ __forceinline__ void bp_phi(const BodyPhaseConsts& k, float u, float D, float D2, float ph0,
                                        float& pr, float& pi) {
   const float r2 = D2 + u;
@@ -267,10 +270,10 @@ __device__ __forceinline__ void bp_phi(const BodyPhaseConsts& k, float u, float 
     pr = a * __builtin_amdgcn_cosf(rev);
     pi = a * __builtin_amdgcn_sinf(rev);
   } else {
-    if (FAR_ONLY || r >= k.r_far) {
+    if (FAR > 0 || r >= k.r_far) {
       const float w2 = rinv * rinv;
-      const float m = fmaf(fmaf(k.m2, w2, k.m1), w2, k.m0);
-      const float th = rinv * fmaf(fmaf(k.p2, w2, k.p1), w2, k.p0);
+      const float m = FAR == 2 ? fmaf(k.m1, w2, k.m0) : fmaf(fmaf(k.m2, w2, k.m1), w2, k.m0);
+      const float th = FAR == 2 ? rinv * fmaf(k.p1, w2, k.p0) : rinv * fmaf(fmaf(k.p2, w2, k.p1), w2, k.p0);
       const float rev = __builtin_amdgcn_fractf(fmaf(delta, k.kappa_rev, ph0) + th);
       const float a = m * __builtin_amdgcn_sqrtf(rinv);
       // (i/4) H0 = (i/4) M e^{i theta}: re = -A sin, im = A cos
@@ -302,7 +305,7 @@ __device__ __forceinline__ void bp_phi(const BodyPhaseConsts& k, float u, float 
   }
 }
 
-template <int DIM, int TPT, int RT, bool MASK, bool FAR_ONLY = false>
+template <int DIM, int TPT, int RT, bool MASK, int FAR = 0>
 __device__ __forceinline__ void bp_source(BPAcc<DIM, TPT, RT>& a, const BodyPhaseConsts& k, int sb,
                                           const float* __restrict__ l0, const float* __restrict__ l1,
                                           const float* __restrict__ l2, const float* __restrict__ lsq,
@@ -327,7 +330,7 @@ __device__ __forceinline__ void bp_source(BPAcc<DIM, TPT, RT>& a, const BodyPhas
 #pragma unroll
     for (int d = 0; d < DIM; ++d) u = fmaf(a.P[i][d], ls[d], u);
     float pr, pi;
-    bp_phi<DIM, FAR_ONLY>(k, u, a.D[i], a.D2[i], a.ph0[i], pr, pi);
+    bp_phi<DIM, FAR>(k, u, a.D[i], a.D2[i], a.ph0[i], pr, pi);
     if constexpr (MASK) {
       const bool same = a.tb[i] == sb;
       pr = same ? 0.0f : pr;
@@ -415,14 +418,25 @@ __global__ __launch_bounds__(kBlock) void ghat_bodyphase_kernel(
 #pragma unroll
       for (int i = 0; i < TPT; ++i) far_lane = far_lane && (a.tb[i] < 0 || a.D[i] >= k.far_D);
       const bool far_all = DIM == 2 && !masked && __all(far_lane);
+      bool vfar_lane = true;
+#pragma unroll
+      for (int i = 0; i < TPT; ++i) vfar_lane = vfar_lane && (a.tb[i] < 0 || a.D[i] >= k.vfar_D);
+      const bool vfar_all = far_all && __all(vfar_lane);
       int64_t j = j0;
-      if (far_all) {
+      if (vfar_all) {  // every pair at z >= 100: shorter asymptotic expansions
         for (; j + kUnroll <= j1; j += kUnroll) {
 #pragma unroll
           for (int uu = 0; uu < kUnroll; ++uu)
-            bp_source<DIM, TPT, RT, false, true>(a, k, sb, l0, l1, l2, lsq, q, N, R, r0, j + uu);
+            bp_source<DIM, TPT, RT, false, 2>(a, k, sb, l0, l1, l2, lsq, q, N, R, r0, j + uu);
         }
-        for (; j < j1; ++j) bp_source<DIM, TPT, RT, false, true>(a, k, sb, l0, l1, l2, lsq, q, N, R, r0, j);
+        for (; j < j1; ++j) bp_source<DIM, TPT, RT, false, 2>(a, k, sb, l0, l1, l2, lsq, q, N, R, r0, j);
+      } else if (far_all) {
+        for (; j + kUnroll <= j1; j += kUnroll) {
+#pragma unroll
+          for (int uu = 0; uu < kUnroll; ++uu)
+            bp_source<DIM, TPT, RT, false, 1>(a, k, sb, l0, l1, l2, lsq, q, N, R, r0, j + uu);
+        }
+        for (; j < j1; ++j) bp_source<DIM, TPT, RT, false, 1>(a, k, sb, l0, l1, l2, lsq, q, N, R, r0, j);
       } else if (!masked) {
         for (; j + kUnroll <= j1; j += kUnroll) {
 #pragma unroll
@@ -623,7 +637,7 @@ __global__ __launch_bounds__(256) void ghat_mfma_kernel(
       if constexpr (DIM == 3) u = fmaf(P[2], l2[j], u);
       float pr, pi;
       if (far_all) {
-        bp_phi<DIM, true>(k, u, D, D2, ph0, pr, pi);
+        bp_phi<DIM, 1>(k, u, D, D2, ph0, pr, pi);
       } else {
         bp_phi<DIM>(k, u, D, D2, ph0, pr, pi);
         const bool same = tb == sb;
@@ -735,6 +749,7 @@ static BodyPhaseConsts make_bodyphase(double kappa, double rho_max) {
   k.as = make_phi2d_f32(kappa);
   // |x_i - x_j| >= D - 2 rho_max, so D >= 12/kappa + 2 rho_max (plus rounding slack) is far for all pairs
   k.far_D = (float)((12.0 / kappa + 2.0 * rho_max) * (1.0 + 1e-5) + 1e-6);
+  k.vfar_D = (float)((100.0 / kappa + 2.0 * rho_max) * (1.0 + 1e-5) + 1e-6);
   return k;
 }
 
