@@ -149,7 +149,8 @@ def serve(args, w, torch) -> int:
            "capacity_per_s": capacity, "slots": args.slots, "batching": batching is not None,
            "hbm_budget_bytes": budget, "wall_s": wall, **st, "relres_max": worst, "errors": fails[:3],
            "tol": args.tol, "pool_hits": pool1["hits"] - pool0["hits"], "pool_misses": pool1["misses"] - pool0["misses"],
-           "requests": f"2D (disk, ellipse, starfish, kite; kappa 5/10/20) and 3D (sphere, ellipsoid; kappa 3/5), "
+           "requests": f"2D (disk, ellipse, starfish, kite, teardrop, C-shape; kappa 5/10/20) and 3D (sphere, "
+                       f"ellipsoid, torus; kappa 3/5), "
                        f"{args.serve_tmin}..{args.serve_tmax} bodies log-uniform, 1..16 directions, "
                        f"{args.p_sweep:g} of requests revisit an earlier geometry"}
     print(json.dumps(out), flush=True)
