@@ -116,7 +116,7 @@ struct mfs_scene {
   // workspaces
   Buf partial, q32, dirs, kry, vecs;
   // near-field tables for the last set of reconstruction factors used with this scene
-  std::vector<const mfs_recon*> near_key;
+  std::vector<uint64_t> near_key;
   Buf near_tab;
   mfs::NearTables near{};
   std::vector<std::vector<int32_t>> bodies_of_shape;
@@ -126,7 +126,10 @@ struct mfs_scene {
 struct mfs_recon {
   mfs::ReconFactors f{};
   double psi_radius = 0.0;
+  uint64_t id = 0;  // unique per handle: scenes cache tables by id, never by (reusable) address
 };
+
+static std::atomic<uint64_t> g_recon_ids{1};
 
 namespace {
 
@@ -210,7 +213,7 @@ mfs_status prepare_near(mfs_scene* s, const mfs_recon* const* recon, hipStream_t
         std::fabs(r->f.kappa - s->dev.kappa) > 1e-12 * s->dev.kappa)
       return fail(MFS_ERR_ARG, "reconstruction factors of shape " + std::to_string(i) +
                                    " do not match the scene (dim, k or kappa)");
-    same = same && s->near_key[i] == r;
+    same = same && s->near_key[i] == r->id;
   }
   if (same) return MFS_OK;
   const int64_t T = s->dev.T;
@@ -277,7 +280,8 @@ mfs_status prepare_near(mfs_scene* s, const mfs_recon* const* recon, hipStream_t
   s->bodies_dev.assign(ns, nullptr);
   for (int i = 0; i < ns; ++i) s->bodies_dev[i] = reinterpret_cast<const int32_t*>(base + oB[i]);
   s->near = t;
-  s->near_key.assign(recon, recon + ns);
+  s->near_key.resize(ns);
+  for (int i = 0; i < ns; ++i) s->near_key[i] = recon[i]->id;
   return MFS_OK;
 }
 // y = S G_hat q with q already complex64 (a single-precision Krylov basis vector) and y complex128.
@@ -915,6 +919,7 @@ mfs_status mfs_recon_create(const mfs_shape_desc* desc, double psi_radius, mfs_r
     return fail(MFS_ERR_ARG, "recon_create: psi_radius must be positive and finite");
   mfs_recon* r = new mfs_recon();
   r->psi_radius = psi_radius;
+  r->id = g_recon_ids.fetch_add(1);
   const mfs_status st = build_recon_impl(desc, &r->f, as_stream(stream));
   if (st != MFS_OK) {
     delete r;

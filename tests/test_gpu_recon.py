@@ -162,3 +162,25 @@ def test_invalid_reconstruction_arguments(gpu_lib):
     with pytest.raises(mfs.MfsError):
         mfs.near_sizes(st["gsc"], [other])
     other.close()
+
+
+def test_replaced_factors_are_picked_up(gpu_lib):
+    """A scene caches its near-field tables per set of factors; new factors (even at a reused
+    address) must replace them: the field with the second set equals a fresh scene's."""
+    mfs = gpu_lib
+    torch = _torch()
+    sc = w.c1_disks16(T=4)
+    st = _setup(mfs, sc)
+    tg = np.concatenate([_near_points(sc.centres[t], [1.1, 1.4], 11) for t in range(sc.T)])
+    first = _gpu_field(mfs, st, tg)
+    for r in st["recons"]:
+        r.close()
+    # smaller proxy radius: targets at 1.4 now use the equivalent points instead of the MFS sources
+    st["recons"] = [mfs.Recon(s, sc.kappa, psi_radius=1.3) for s in sc.shapes]
+    second = _gpu_field(mfs, st, tg)
+    fresh = _setup(mfs, sc)
+    fresh["recons"] = [mfs.Recon(s, sc.kappa, psi_radius=1.3) for s in sc.shapes]
+    ref = _gpu_field(mfs, fresh, tg)
+    assert np.array_equal(second, ref)
+    # both representations are valid at r = 1.4, so the field barely moves
+    assert np.abs(first - second).max() / np.abs(first).max() < 1e-6
