@@ -53,7 +53,8 @@ def test_build_S_on_cornered_shape_reproduces_mfs_solution(gpu_lib, name, paper)
 
 
 def _mixed_corner_scene(T=9):
-    shapes = [w.starfish2d(m=256, n=128, p=257), SHAPES["teardrop"](), SHAPES["cshape"]()]
+    # the starfish at m = 512: at the workload's m = 256 its own MFS fit leaves 1.5e-4 on its boundary
+    shapes = [w.starfish2d(m=512, n=256, p=513), SHAPES["teardrop"](), SHAPES["cshape"]()]
     rng = np.random.default_rng(31)
     centres = w.random_centres(T, 2, 7.0, 1.6, 31)
     shape_of = (np.arange(T) % 3).astype(np.int32)
@@ -89,28 +90,32 @@ def test_scene_with_cornered_bodies_solves_and_meets_boundary_condition(gpu_lib)
     mfs.plane_wave_colloc(scene, recons, sc.directions, vc)
     qm = torch.empty((1, nt), dtype=torch.complex128, device="cuda")
     mfs.reconstruct(scene, recons, vc, q, qm)
-    worst = 0.0
+    # boundary points between the collocation points, away from the corners: exact points of a finer
+    # discretisation for the curved bodies (chord midpoints would lie off a curved boundary), edge
+    # midpoints for the C-shape's straight edges
+    fine_td = w.teardrop2d(levels=8, base_panels=64, q=16, d_frac=0.5)
+    td_pts = fine_td.colloc[np.linalg.norm(fine_td.colloc - fine_td.meta["corner"][None, :], axis=1) > 0.05]
+    worst = {}
     for t in range(sc.T):
         sh = sc.shapes[int(sc.shape_of[t])]
-        mid = 0.5 * (sh.colloc[:-1] + sh.colloc[1:])
-        seg = np.linalg.norm(sh.colloc[1:] - sh.colloc[:-1], axis=1)
-        pts = mid[seg < 0.02] + sc.centres[t][None, :]
         if sh.name == "teardrop":
-            far_from_corner = np.linalg.norm(mid[seg < 0.02] - sh.meta["corner"][None, :], axis=1) > 0.05
-            pts = pts[far_from_corner]
-        if sh.name == "cshape":
-            d = np.min(np.linalg.norm(mid[seg < 0.02][:, None, :] - sh.meta["vertices"][None, :, :], axis=2), axis=1)
-            pts = pts[d > 0.05]
-        if sh.name == "starfish":
-            pts = w.starfish2d(m=2048, n=16).colloc + sc.centres[t][None, :]
+            body = td_pts
+        elif sh.name == "starfish":
+            body = w.starfish2d(m=2048, n=16).colloc
+        else:
+            mid = 0.5 * (sh.colloc[:-1] + sh.colloc[1:])
+            seg = np.linalg.norm(sh.colloc[1:] - sh.colloc[:-1], axis=1)
+            body = mid[seg < 0.02]
+            d = np.min(np.linalg.norm(body[:, None, :] - sh.meta["vertices"][None, :, :], axis=2), axis=1)
+            body = body[d > 0.05]
+        pts = body + sc.centres[t][None, :]
         tgd = torch.from_numpy(np.ascontiguousarray(pts)).cuda()
         ud = torch.empty((1, pts.shape[0]), dtype=torch.complex128, device="cuda")
         mfs.eval_field_near(scene, recons, q, qm, tgd, ud)
         total = ud.cpu().numpy()[0] + np.exp(1j * KAPPA * pts @ sc.directions[0])
-        worst = max(worst, float(np.abs(total).max()))
-    # the starfish at m = 256 leaves 1.5e-4 on its boundary (single body, plain MFS); the cornered
-    # bodies are resolved far better away from the corners
-    assert worst < 5e-4, worst
+        worst[sh.name] = max(worst.get(sh.name, 0.0), float(np.abs(total).max()))
+    # the oracle measures 1.1e-7 (starfish), 4.5e-6 (teardrop), 2.1e-5 (C-shape) on this scene
+    assert worst["starfish"] < 1e-6 and worst["teardrop"] < 3e-5 and worst["cshape"] < 1e-4, worst
     for r in recons:
         r.close()
     scene.close()
