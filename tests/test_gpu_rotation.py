@@ -19,7 +19,7 @@ def _torch():
 
 def _scene(dim):
     if dim == 2:
-        shapes = [w.kite2d(m=256, n=128, k=128, p=257), w.ellipse2d()]
+        shapes = [w.kite2d(m=512, n=256, d=0.02, k=128, p=257), w.ellipse2d()]
         centres = w.random_centres(6, 2, 6.0, 1.6, 5)
         return w.Scene(dim=2, kappa=6.0, shapes=shapes, shape_of=np.arange(6) % 2, centres=centres,
                        directions=w.plane_wave_directions_2d([0.4, 1.9]), name="rot2",

@@ -36,7 +36,7 @@ def _turned(sc, Q):
 @pytest.mark.parametrize("dim", [2, 3])
 def test_turning_the_configuration_turns_the_field(dim):
     if dim == 2:
-        shapes = [w.kite2d(m=256, n=128, k=128, p=257), w.ellipse2d()]
+        shapes = [w.kite2d(m=512, n=256, d=0.02, k=128, p=257), w.ellipse2d()]
         centres = w.random_centres(4, 2, 5.0, 1.6, 5)
         rot = w.random_rotations(4, 2, 6)
         Q = _rot2(0.7)
@@ -71,7 +71,7 @@ def test_turning_the_configuration_turns_the_field(dim):
 
 def test_rotated_body_differs_from_unrotated():
     """The pin above is not trivially satisfied: an unsymmetric body's field depends on its turn."""
-    sh = w.kite2d(m=256, n=128, k=128, p=257)
+    sh = w.kite2d(m=512, n=256, d=0.02, k=128, p=257)
     base = dict(dim=2, kappa=6.0, shapes=[sh], shape_of=np.zeros(1, np.int32), centres=np.zeros((1, 2)),
                 directions=w.plane_wave_directions_2d([0.4]), name="one")
     sc0 = w.Scene(**base)

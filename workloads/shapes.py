@@ -145,8 +145,10 @@ def ellipse2d(a=0.65, b=0.325, m=256, n=128, d=0.06, k=128, rho_eq=0.70, p=257, 
                              r_psi, max(a, b))
 
 
-def kite2d(bounding=0.65, m=512, n=256, d=0.06, k=256, rho_eq=0.70, p=513, r_psi=0.75):
-    """The classical inverse-scattering kite, rescaled to the given bounding radius."""
+def kite2d(bounding=0.65, m=512, n=256, d=0.02, k=256, rho_eq=0.70, p=513, r_psi=0.75):
+    """The classical inverse-scattering kite, rescaled to the given bounding radius.  Its wing tips
+    are sharply curved: sources much deeper than d = 0.02 fold over there and the MFS fit stalls
+    near 1e-3 (d = 0.06) or 2e-5 (d = 0.03) on the boundary, against 8e-6 at d = 0.02."""
     t = np.linspace(0.0, 2.0 * np.pi, 4097)
     raw = np.stack([np.cos(t) + 0.65 * np.cos(2 * t) - 0.65, 1.5 * np.sin(t)], axis=-1)
     scale = bounding / np.linalg.norm(raw, axis=1).max()
