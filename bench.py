@@ -48,10 +48,10 @@ def log(msg: str):
     print(msg, file=sys.stderr, flush=True)
 
 
-def stored_traffic(workload: str, kernel_name: str):
+def stored_traffic(workload: str, kernel_name: str, nchunks: int):
     """HBM bytes per launch of the FP32 G_hat kernel from the committed rocprofv3 counter summary,
-    or None if the summary is for another workload or kernel, or the kernel source has changed
-    since the counters were taken."""
+    or None if the summary is for another workload, kernel or launch shape, or the kernel source has
+    changed since the counters were taken."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "ghat_f32_starfish2000_traffic.md")
@@ -61,13 +61,15 @@ def stored_traffic(workload: str, kernel_name: str):
         return None
     fields = {}
     for line in open(path):
-        if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha256"):
+        if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha256", "nchunks"):
             k, v = line.split(":", 1)
             fields[k] = v.strip()
     csrc = os.path.join(ROOT, "paper_2603_19113_amd", "csrc")
     h = hashlib.sha256(open(os.path.join(csrc, "pair_kernels.hip"), "rb").read() +
                        open(os.path.join(csrc, "phi.h"), "rb").read()).hexdigest()
     if fields.get("kernel_source_sha256") != h or "traffic_bytes_per_launch" not in fields:
+        return None
+    if fields.get("nchunks") != str(nchunks):
         return None
     return int(fields["traffic_bytes_per_launch"])
 
@@ -286,6 +288,10 @@ def main() -> int:
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="profiling: first copy a buffer of this many MiB (calibrates rocprof byte counters)")
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the launch-shape autotuner (run before the warm-up, outside the timed steps)")
+    ap.add_argument("--launch-shape", default=None, metavar="NCHUNKS:RT",
+                    help="use this pair-sum launch shape on every scene instead of tuning (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--verbose", type=int, default=2, help="solver progress lines on stderr")
@@ -339,10 +345,21 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
 
-    def step():
+    forced = None
+    if args.launch_shape:
+        nch, rt = (int(x) for x in args.launch_shape.split(":"))
+        forced = (nch, rt)
+
+    def make_scene():
         built = [mfs.build_S(s, sc.kappa) for s in sc.shapes]
         scene = mfs.Scene(sc.dim, sc.kappa, sc.shape_of, sc.centres, [s.eqpts for s in sc.shapes],
                           [b.S64 for b in built], [b.S32 for b in built])
+        if forced:
+            mfs.tune_set(scene, R, mfs.MFS_MIXED, *forced)
+        return scene
+
+    def step():
+        scene = make_scene()
         v = torch.empty((R, scene.N), dtype=torch.complex128, device="cuda")
         mfs.plane_wave(scene, dirs, v)
         q = torch.empty_like(v)
@@ -370,6 +387,17 @@ def main() -> int:
         return compare(args, sc, mfs, torch, np)
     if args.near:
         return near(args, sc, mfs, torch, np)
+
+    # launch shape of the FP32 pair sum: tuned once on this scene (the process-wide table then serves
+    # the scenes the steps build), or the heuristic with --no-tune
+    probe = make_scene()
+    tune = None
+    if not args.no_tune and not forced:
+        t0 = time.perf_counter()
+        tune = mfs.autotune(probe, R=R, prec=mfs.MFS_MIXED, reps=2)
+        log(f"[bench] autotune ({time.perf_counter() - t0:.1f} s): {tune}")
+    shape = mfs.tune_get(probe, R, mfs.MFS_MIXED)
+    probe.close()
 
     for i in range(args.warmup):
         t0 = time.perf_counter()
@@ -399,8 +427,8 @@ def main() -> int:
     if on_mfma:
         kernel_name = "ghat_mfma_kernel<%d> (G_hat, FP32 matrix cores)" % sc.dim
     else:
-        kernel_name = "ghat_bodyphase_kernel<%d,2,%d> (G_hat, FP32)" % (sc.dim, 1 if R == 1 else (2 if R == 2 else 4))
-    traffic = stored_traffic(sc.name, kernel_name)
+        kernel_name = "ghat_bodyphase_kernel<%d,2,%d> (G_hat, FP32)" % (sc.dim, shape["rhs_per_thread"])
+    traffic = stored_traffic(sc.name, kernel_name, shape["nchunks"])
     total_pairs = p32 + p64
     value = total_pairs / wall
     avg32 = ms32 / max(n32, 1)
@@ -439,6 +467,8 @@ def main() -> int:
         "mode": "profile (operator applications only)" if args.matvecs > 0 else "full solve",
         "pair_kernel_f32": {"launches": n32, "avg_ms": avg32, "rhs": R, "pairs_per_launch": pairs_per_launch32,
                             "pair_evals_per_s": pairs_per_launch32 / (avg32 * 1e-3) if n32 else 0.0},
+        "launch_shape": {**shape, **({"tuned_ms": tune["ms"], "heuristic_ms": tune["ms_heuristic"],
+                                      "tried": tune["n_tried"]} if tune else {})},
         "pair_kernel_f64": {"launches": n64, "avg_ms": ms64 / max(n64, 1),
                             "pair_evals_per_s": p64 / (ms64 * 1e-3) if n64 else 0.0},
         "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",

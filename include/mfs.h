@@ -328,6 +328,55 @@ mfs_status mfs_pool_set_limit(int64_t max_cached_bytes);
  * scenes are not affected. */
 mfs_status mfs_pool_trim(void);
 
+/* ------------------------------------------------------------------------------------------
+ * Launch-shape autotuner.  Not part of the method: it picks how the off-body pair sum of the
+ * operator (eq. Gmtx-entries, eq. mbody2) is spread over the device, never what it computes.
+ *
+ * The pair sum splits the sources seen by every block of targets into `nchunks` slices (more
+ * slices: more blocks in flight on a small system, but more partial sums for the S product to
+ * read back), and on the VALU kernel each thread carries `rhs_per_thread` right-hand sides (1, 2
+ * or 4; the matrix-core kernel used for 8 or more right-hand sides has no such knob).  A scene
+ * uses, in this order: its own tuned shape for (precision, R); the process-wide table, keyed by
+ * (dim, kernel, R, floor(log2 N)); an occupancy heuristic.  The slices are summed in order, so a
+ * given shape gives reproducible results; another shape may change the last bits of the sums.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct {
+  int32_t nchunks;         /* chosen source slices per target block */
+  int32_t rhs_per_thread;  /* chosen right-hand sides per thread (VALU kernel), 0 otherwise */
+  double ms;               /* time of one operator application with the chosen shape */
+  double ms_heuristic;     /* the same with the heuristic shape */
+  int32_t n_tried;         /* shapes timed */
+  int32_t uses_mfma;       /* 1 when R selects the matrix-core kernel */
+} mfs_tune_result;
+
+/* Time the operator y = q + S G_hat q (mfs_apply for MFS_FP64 / MFS_FP32, the complex128-vector
+ * form with an FP32 pair sum for MFS_MIXED) on this scene with R right-hand sides for a set of
+ * launch shapes around the heuristic, `reps` applications each after one warm-up, and keep the
+ * fastest: in the scene and in the process-wide table.  Uses synthetic charges in scratch device
+ * memory; the caller's data is not touched.  Synchronous.  Pair-sum launches made while kernel
+ * timing is enabled are recorded like any other.  out may be NULL. */
+mfs_status mfs_autotune(mfs_scene* scene, int32_t R, mfs_prec prec, int32_t reps, mfs_tune_result* out,
+                        void* stream);
+
+/* The launch shape the scene will use for (R, prec): nchunks, rhs_per_thread (0 for the FP64 and
+ * matrix-core kernels) and where it comes from (2 = the scene's own, 1 = the process-wide table,
+ * 0 = the heuristic).  Host outputs may be NULL. */
+mfs_status mfs_tune_get(const mfs_scene* scene, int32_t R, mfs_prec prec, int32_t* nchunks,
+                        int32_t* rhs_per_thread, int32_t* source);
+
+/* Set the scene's own shape for (R, prec) (1 <= nchunks <= 1024; rhs_per_thread 0 = by R, or 1, 2,
+ * 4); nchunks = 0 removes it. */
+mfs_status mfs_tune_set(mfs_scene* scene, int32_t R, mfs_prec prec, int32_t nchunks, int32_t rhs_per_thread);
+
+/* The process-wide table as a text file: a header line, then one entry per line
+ * ("dim kernel R log2N nchunks rhs_per_thread").  Loading merges into the table and is all or
+ * nothing: a malformed file is rejected (MFS_ERR_ARG) and leaves the table unchanged.  Host only;
+ * no device is touched. */
+mfs_status mfs_tune_save(const char* path);
+mfs_status mfs_tune_load(const char* path);
+mfs_status mfs_tune_clear(void);
+mfs_status mfs_tune_table_size(int64_t* entries);
+
 #ifdef __cplusplus
 }
 #endif

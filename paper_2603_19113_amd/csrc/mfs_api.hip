@@ -6,8 +6,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "mfs_internal.h"
@@ -121,6 +123,8 @@ struct mfs_scene {
   mfs::NearTables near{};
   std::vector<std::vector<int32_t>> bodies_of_shape;
   std::vector<const int32_t*> bodies_dev;
+  // pair-sum launch shapes tuned on this scene, by (kernel variant, R)
+  std::map<std::pair<int, int>, LaunchShape> tuned;
 };
 
 struct mfs_recon {
@@ -155,9 +159,26 @@ mfs_status check_prec_operator(const mfs_scene* s, mfs_prec prec) {
 
 int tpt_for(mfs_prec prec) { return prec == MFS_FP64 ? 1 : 2; }
 
+int tune_variant(const mfs_scene* s, bool f64, int R) {
+  return f64 ? kTunePairF64 : ghat_uses_mfma(s->dev, R) ? kTunePairMfma : kTunePairF32;
+}
+
+// Launch shape of the pair sum over the scene's own points: the scene's tuned entry, else the
+// process-wide table, else the occupancy heuristic.
+LaunchShape shape_for(const mfs_scene* s, bool f64, int R) {
+  const int v = tune_variant(s, f64, R);
+  auto it = s->tuned.find({v, R});
+  if (it != s->tuned.end()) return it->second;
+  LaunchShape ls;
+  if (tune_lookup(s->dev.dim, v, R, s->dev.N, &ls)) return ls;
+  ls.nchunks = pair_chunks_for(s->dev.N, s->dev.N, tpt_for(f64 ? MFS_FP64 : MFS_FP32));
+  ls.rt = 0;
+  return ls;
+}
+
 // y = q + S G_hat q in FP64 (all operands complex128).
 mfs_status apply_f64(mfs_scene* s, const c128* q, c128* y, int R, hipStream_t st, double beta = 1.0) {
-  const int nch = pair_chunks_for(s->dev.N, s->dev.N, tpt_for(MFS_FP64));
+  const int nch = shape_for(s, true, R).nchunks;
   MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c128), &s->bytes, st));
   c128* part = static_cast<c128*>(s->partial.p);
   {
@@ -170,12 +191,13 @@ mfs_status apply_f64(mfs_scene* s, const c128* q, c128* y, int R, hipStream_t st
 
 // y = q + S G_hat q in FP32 (complex64 in and out).
 mfs_status apply_f32(mfs_scene* s, const c64* q, c64* y, int R, hipStream_t st) {
-  const int nch = pair_chunks_for(s->dev.N, s->dev.N, tpt_for(MFS_FP32));
+  const LaunchShape ls = shape_for(s, false, R);
+  const int nch = ls.nchunks;
   MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c64), &s->bytes, st));
   c64* part = static_cast<c64*>(s->partial.p);
   {
     TimedLaunch tl(MFS_KERNEL_PAIR_F32, s->dev.offbody_pairs * R, st);
-    MFS_HIP_TRY(launch_ghat_f32(s->dev, q, R, part, nch, st));
+    MFS_HIP_TRY(launch_ghat_f32(s->dev, q, R, part, nch, st, ls.rt));
   }
   MFS_HIP_TRY(launch_sapply_f32(s->dev, part, nch, q, 1.0f, y, R, (int)s->kmax, st));
   return MFS_OK;
@@ -186,14 +208,15 @@ mfs_status apply_f32(mfs_scene* s, const c64* q, c64* y, int R, hipStream_t st) 
 mfs_status apply_mixed(mfs_scene* s, const c128* q, c128* y, int R, hipStream_t st, double beta = 1.0) {
   const int64_t NR = s->dev.N * R;
   MFS_TRY(ensure(s->q32, (size_t)NR * sizeof(c64), &s->bytes, st));
-  const int nch = pair_chunks_for(s->dev.N, s->dev.N, tpt_for(MFS_FP32));
+  const LaunchShape ls = shape_for(s, false, R);
+  const int nch = ls.nchunks;
   MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c64), &s->bytes, st));
   c64* q32 = static_cast<c64*>(s->q32.p);
   c64* part = static_cast<c64*>(s->partial.p);
   MFS_HIP_TRY(launch_to_c64(q, q32, NR, st));
   {
     TimedLaunch tl(MFS_KERNEL_PAIR_F32, s->dev.offbody_pairs * R, st);
-    MFS_HIP_TRY(launch_ghat_f32(s->dev, q32, R, part, nch, st));
+    MFS_HIP_TRY(launch_ghat_f32(s->dev, q32, R, part, nch, st, ls.rt));
   }
   MFS_HIP_TRY(launch_sapply_mixed(s->dev, part, nch, q, beta, y, R, (int)s->kmax, st));
   return MFS_OK;
@@ -286,12 +309,13 @@ mfs_status prepare_near(mfs_scene* s, const mfs_recon* const* recon, hipStream_t
 }
 // y = S G_hat q with q already complex64 (a single-precision Krylov basis vector) and y complex128.
 mfs_status apply_mixed_from32(mfs_scene* s, const c64* q32, c128* y, int R, hipStream_t st) {
-  const int nch = pair_chunks_for(s->dev.N, s->dev.N, tpt_for(MFS_FP32));
+  const LaunchShape ls = shape_for(s, false, R);
+  const int nch = ls.nchunks;
   MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c64), &s->bytes, st));
   c64* part = static_cast<c64*>(s->partial.p);
   {
     TimedLaunch tl(MFS_KERNEL_PAIR_F32, s->dev.offbody_pairs * R, st);
-    MFS_HIP_TRY(launch_ghat_f32(s->dev, q32, R, part, nch, st));
+    MFS_HIP_TRY(launch_ghat_f32(s->dev, q32, R, part, nch, st, ls.rt));
   }
   MFS_HIP_TRY(launch_sapply_mixed(s->dev, part, nch, nullptr, 0.0, y, R, (int)s->kmax, st));
   return MFS_OK;
@@ -519,7 +543,8 @@ mfs_status mfs_ghat_apply(const mfs_scene* sc, const void* q_dev, void* t_dev, i
   mfs_scene* s = const_cast<mfs_scene*>(sc);
   hipStream_t st = as_stream(stream);
   s->last_stream = st;
-  const int nch = pair_chunks_for(s->dev.N, s->dev.N, tpt_for(prec));
+  const LaunchShape ls = shape_for(s, prec == MFS_FP64, R);
+  const int nch = ls.nchunks;
   if (prec == MFS_FP64) {
     MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c128), &s->bytes, st));
     c128* part = static_cast<c128*>(s->partial.p);
@@ -533,7 +558,7 @@ mfs_status mfs_ghat_apply(const mfs_scene* sc, const void* q_dev, void* t_dev, i
     c64* part = static_cast<c64*>(s->partial.p);
     {
       TimedLaunch tl(MFS_KERNEL_PAIR_F32, s->dev.offbody_pairs * R, st);
-      MFS_HIP_TRY(launch_ghat_f32(s->dev, static_cast<const c64*>(q_dev), R, part, nch, st));
+      MFS_HIP_TRY(launch_ghat_f32(s->dev, static_cast<const c64*>(q_dev), R, part, nch, st, ls.rt));
     }
     MFS_HIP_TRY(launch_reduce_partials_f32(part, nch, s->dev.N, R, static_cast<c64*>(t_dev), st));
   }
@@ -983,7 +1008,7 @@ mfs_status mfs_reconstruct(const mfs_scene* sc, const mfs_recon* const* recon, c
   const int64_t N = s->dev.N;
   const NearTables& t = s->near;
   // w_hat = G_hat qhat (FP64): the field of the other bodies at each body's equivalent points
-  const int nch = pair_chunks_for(N, N, tpt_for(MFS_FP64));
+  const int nch = shape_for(s, true, R).nchunks;
   MFS_TRY(ensure(s->partial, (size_t)nch * R * N * sizeof(c128), &s->bytes, st));
   size_t gw = 0, gv = 0;
   hipError_t e = hipSuccess;
@@ -1066,6 +1091,170 @@ mfs_status mfs_pool_set_limit(int64_t max_cached_bytes) {
 
 mfs_status mfs_pool_trim(void) {
   pool_trim();
+  return MFS_OK;
+}
+
+mfs_status mfs_autotune(mfs_scene* s, int32_t R, mfs_prec prec, int32_t reps, mfs_tune_result* out, void* stream) {
+  MFS_TRY(check_scene(s));
+  if (prec != MFS_FP64 && prec != MFS_FP32 && prec != MFS_MIXED)
+    return fail(MFS_ERR_ARG, "autotune: precision must be MFS_FP64, MFS_FP32 or MFS_MIXED");
+  if (prec != MFS_FP64 && !s->has_s32) return fail(MFS_ERR_ARG, "scene was created without FP32 copies of S");
+  if (R < 1 || reps < 1 || reps > 1000) return fail(MFS_ERR_ARG, "autotune: need R >= 1 and 1 <= reps <= 1000");
+  hipStream_t st = as_stream(stream);
+  s->last_stream = st;
+  mfs_tune_result res{};
+  const int64_t N = s->dev.N;
+  if (N == 0) {
+    if (out) *out = res;
+    return MFS_OK;
+  }
+  const bool f64 = prec == MFS_FP64;
+  const int v = tune_variant(s, f64, R);
+  const std::pair<int, int> key{v, R};
+  const int h = pair_chunks_for(N, N, tpt_for(f64 ? MFS_FP64 : MFS_FP32));
+  const int h_rt = v == kTunePairF32 ? ghat_default_rt(R) : 0;
+
+  // candidates: the heuristic first, then slice counts from h/4 to 4h (capped so that the partial
+  // sums stay within max(2 GiB, the heuristic's)), times 1, 2 or 4 right-hand sides per thread
+  const size_t part_elem = f64 ? sizeof(c128) : sizeof(c64);
+  const size_t cap = std::max<size_t>((size_t)2 << 30, (size_t)h * R * N * part_elem);
+  const int maxc = (int)std::min<int64_t>(kTuneMaxChunks, std::max<int64_t>(1, N / 16));
+  std::vector<int> nset;
+  for (int f : {0, -2, -1, 1, 2}) {
+    int c = f < 0 ? (h >> -f) : (h << f);
+    c = std::max(1, std::min(c, maxc));
+    if (f != 0 && (size_t)c * R * N * part_elem > cap) continue;
+    if (std::find(nset.begin(), nset.end(), c) == nset.end()) nset.push_back(c);
+  }
+  std::vector<int> rset{h_rt};
+  if (v == kTunePairF32)
+    for (int rt : {1, 2, 4})
+      if (rt != h_rt && (rt == 1 || rt / 2 < R)) rset.push_back(rt);
+  std::vector<LaunchShape> cands;
+  for (int c : nset)
+    for (int rt : rset) cands.push_back(LaunchShape{c, rt});
+
+  const size_t vec = (prec == MFS_FP32 ? sizeof(c64) : sizeof(c128)) * (size_t)R * N;
+  struct Scratch {
+    void* p[2] = {nullptr, nullptr};
+    size_t n[2] = {0, 0};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipStream_t st;
+    ~Scratch() {
+      for (int i = 0; i < 2; ++i) {
+        if (p[i]) pool_free(p[i], n[i], st);
+        if (ev[i]) (void)hipEventDestroy(ev[i]);
+      }
+    }
+  } sc;
+  sc.st = st;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < 2; ++i) {
+    sc.p[i] = pool_alloc(vec, st, &sc.n[i], &e);
+    if (!sc.p[i]) return fail(MFS_ERR_NOMEM, std::string("autotune: ") + hipGetErrorString(e));
+    MFS_HIP_TRY(hipEventCreate(&sc.ev[i]));
+  }
+  MFS_HIP_TRY(hipMemsetAsync(sc.p[0], 0x3c, vec, st));  // charges of modest size (no denormals)
+  auto run = [&]() -> mfs_status {
+    if (prec == MFS_FP64) return apply_f64(s, static_cast<const c128*>(sc.p[0]), static_cast<c128*>(sc.p[1]), R, st);
+    if (prec == MFS_FP32) return apply_f32(s, static_cast<const c64*>(sc.p[0]), static_cast<c64*>(sc.p[1]), R, st);
+    return apply_mixed(s, static_cast<const c128*>(sc.p[0]), static_cast<c128*>(sc.p[1]), R, st);
+  };
+  auto prior = s->tuned.find(key);
+  const bool had = prior != s->tuned.end();
+  const LaunchShape before = had ? prior->second : LaunchShape{};
+  auto restore = [&]() {
+    if (had) s->tuned[key] = before;
+    else s->tuned.erase(key);
+  };
+  double best = 0.0, ms_h = 0.0;
+  LaunchShape best_ls = cands.front();
+  for (size_t i = 0; i < cands.size(); ++i) {
+    s->tuned[key] = cands[i];
+    mfs_status rc = run();  // warm-up; sizes the partial sums
+    if (rc == MFS_OK && hipEventRecord(sc.ev[0], st) != hipSuccess) rc = fail(MFS_ERR_HIP, "autotune: event record");
+    for (int r = 0; rc == MFS_OK && r < reps; ++r) rc = run();
+    float ms = 0.0f;
+    if (rc == MFS_OK && (hipEventRecord(sc.ev[1], st) != hipSuccess || hipEventSynchronize(sc.ev[1]) != hipSuccess ||
+                         hipEventElapsedTime(&ms, sc.ev[0], sc.ev[1]) != hipSuccess))
+      rc = fail(MFS_ERR_HIP, "autotune: event timing failed");
+    if (rc != MFS_OK) {
+      restore();
+      return rc;
+    }
+    const double t = (double)ms / reps;
+    if (i == 0) ms_h = t;
+    if (i == 0 || t < best) {
+      best = t;
+      best_ls = cands[i];
+    }
+  }
+  s->tuned[key] = best_ls;
+  tune_store(s->dev.dim, v, R, N, best_ls);
+  // the largest candidate may have grown the partial-sum buffer well past what the winner needs
+  if (s->partial.cap > 2 * (size_t)best_ls.nchunks * R * N * part_elem) release(s->partial, &s->bytes, st);
+  res.nchunks = best_ls.nchunks;
+  res.rhs_per_thread = best_ls.rt;
+  res.ms = best;
+  res.ms_heuristic = ms_h;
+  res.n_tried = (int32_t)cands.size();
+  res.uses_mfma = v == kTunePairMfma ? 1 : 0;
+  if (out) *out = res;
+  return MFS_OK;
+}
+
+mfs_status mfs_tune_get(const mfs_scene* s, int32_t R, mfs_prec prec, int32_t* nchunks, int32_t* rhs_per_thread,
+                        int32_t* source) {
+  MFS_TRY(check_scene(s));
+  if (R < 1) return fail(MFS_ERR_ARG, "tune_get: R must be >= 1");
+  const bool f64 = prec == MFS_FP64;
+  const int v = tune_variant(s, f64, R);
+  int src = 0;
+  if (s->tuned.count({v, R})) src = 2;
+  else {
+    LaunchShape tmp;
+    if (tune_lookup(s->dev.dim, v, R, s->dev.N, &tmp)) src = 1;
+  }
+  const LaunchShape ls = shape_for(s, f64, R);
+  if (nchunks) *nchunks = ls.nchunks;
+  if (rhs_per_thread) *rhs_per_thread = v == kTunePairF32 ? (ls.rt ? ls.rt : ghat_default_rt(R)) : 0;
+  if (source) *source = src;
+  return MFS_OK;
+}
+
+mfs_status mfs_tune_set(mfs_scene* s, int32_t R, mfs_prec prec, int32_t nchunks, int32_t rhs_per_thread) {
+  MFS_TRY(check_scene(s));
+  if (R < 1) return fail(MFS_ERR_ARG, "tune_set: R must be >= 1");
+  if (nchunks < 0 || nchunks > kTuneMaxChunks)
+    return fail(MFS_ERR_ARG, "tune_set: nchunks must be in 0.." + std::to_string(kTuneMaxChunks));
+  if (rhs_per_thread != 0 && rhs_per_thread != 1 && rhs_per_thread != 2 && rhs_per_thread != 4)
+    return fail(MFS_ERR_ARG, "tune_set: rhs_per_thread must be 0, 1, 2 or 4");
+  const std::pair<int, int> key{tune_variant(s, prec == MFS_FP64, R), R};
+  if (nchunks == 0) s->tuned.erase(key);
+  else s->tuned[key] = LaunchShape{nchunks, rhs_per_thread};
+  return MFS_OK;
+}
+
+mfs_status mfs_tune_save(const char* path) {
+  if (!path) return fail(MFS_ERR_ARG, "tune_save: null path");
+  std::string err;
+  return tune_save(path, &err) ? MFS_OK : fail(MFS_ERR_ARG, err);
+}
+
+mfs_status mfs_tune_load(const char* path) {
+  if (!path) return fail(MFS_ERR_ARG, "tune_load: null path");
+  std::string err;
+  return tune_load(path, &err) ? MFS_OK : fail(MFS_ERR_ARG, err);
+}
+
+mfs_status mfs_tune_clear(void) {
+  tune_clear();
+  return MFS_OK;
+}
+
+mfs_status mfs_tune_table_size(int64_t* entries) {
+  if (!entries) return fail(MFS_ERR_ARG, "tune_table_size: null output");
+  *entries = tune_size();
   return MFS_OK;
 }
 

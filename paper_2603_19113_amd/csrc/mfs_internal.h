@@ -61,8 +61,11 @@ struct SceneDev {
 int pair_chunks_for(int64_t n_sources, int64_t n_targets, int tpt);
 bool ghat_uses_mfma(const SceneDev& s, int R);
 
+// rt: right-hand sides per thread of the VALU kernel (1, 2 or 4; anything else picks by R);
+// ignored where the matrix-core kernel runs.
+int ghat_default_rt(int R);
 hipError_t launch_ghat_f32(const SceneDev& s, const c64* q, int R, c64* partial, int nchunks,
-                           hipStream_t st);
+                           hipStream_t st, int rt = 0);
 hipError_t launch_ghat_f64(const SceneDev& s, const c128* q, int R, c128* partial, int nchunks,
                            hipStream_t st);
 hipError_t launch_eval_f32(const SceneDev& s, const c64* q, int R, const double* targets, int64_t M,
@@ -163,6 +166,22 @@ void pool_query(int64_t* hits, int64_t* misses, int64_t* cached, int64_t* live, 
 void pool_trim();
 void pool_set_limit(size_t bytes);
 hipStream_t private_stream(hipError_t* err);
+
+// Launch shapes of the pair sum (tune.hip).  nchunks: source slices per target block; rt: right-hand
+// sides per thread of the VALU kernel (0 = chosen by R).  The process-wide table is keyed by
+// (dim, kernel variant, R, floor(log2 N)) and filled by the autotuner or a loaded file.
+struct LaunchShape {
+  int nchunks = 0;
+  int rt = 0;
+};
+enum TuneVariant { kTunePairF64 = 0, kTunePairF32 = 1, kTunePairMfma = 2 };
+constexpr int kTuneMaxChunks = 1024;
+bool tune_lookup(int dim, int variant, int R, int64_t N, LaunchShape* out);
+void tune_store(int dim, int variant, int R, int64_t N, LaunchShape v);
+void tune_clear();
+int64_t tune_size();
+bool tune_save(const char* path, std::string* err);
+bool tune_load(const char* path, std::string* err);
 
 // Reconstruction factors of one shape (lsq.hip): the pivoted QR of A (reflectors below the
 // diagonal, R above it with its diagonal in alpha), Y = A^+ U, and the collocation points and MFS

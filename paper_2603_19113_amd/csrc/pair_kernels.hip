@@ -780,17 +780,21 @@ static hipError_t launch_mfma(const SceneDev& s, const c64* q, int R, c64* parti
 
 bool ghat_uses_mfma(const SceneDev& s, int R) { return R >= kMfmaMinRhs && s.all_k_mult16; }
 
-hipError_t launch_ghat_f32(const SceneDev& s, const c64* q, int R, c64* partial, int nchunks, hipStream_t st) {
+int ghat_default_rt(int R) { return R == 1 ? 1 : R == 2 ? 2 : 4; }
+
+hipError_t launch_ghat_f32(const SceneDev& s, const c64* q, int R, c64* partial, int nchunks, hipStream_t st,
+                           int rt) {
   if (s.N <= 0) return hipSuccess;
   if (ghat_uses_mfma(s, R)) return s.dim == 2 ? launch_mfma<2>(s, q, R, partial, nchunks, st)
                                               : launch_mfma<3>(s, q, R, partial, nchunks, st);
+  if (rt != 1 && rt != 2 && rt != 4) rt = ghat_default_rt(R);
   if (s.dim == 2) {
-    if (R == 1) return launch_bodyphase<2, 1>(s, q, R, partial, nchunks, st);
-    if (R == 2) return launch_bodyphase<2, 2>(s, q, R, partial, nchunks, st);
+    if (rt == 1) return launch_bodyphase<2, 1>(s, q, R, partial, nchunks, st);
+    if (rt == 2) return launch_bodyphase<2, 2>(s, q, R, partial, nchunks, st);
     return launch_bodyphase<2, 4>(s, q, R, partial, nchunks, st);
   }
-  if (R == 1) return launch_bodyphase<3, 1>(s, q, R, partial, nchunks, st);
-  if (R == 2) return launch_bodyphase<3, 2>(s, q, R, partial, nchunks, st);
+  if (rt == 1) return launch_bodyphase<3, 1>(s, q, R, partial, nchunks, st);
+  if (rt == 2) return launch_bodyphase<3, 2>(s, q, R, partial, nchunks, st);
   return launch_bodyphase<3, 4>(s, q, R, partial, nchunks, st);
 }
 

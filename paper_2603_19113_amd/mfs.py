@@ -64,11 +64,20 @@ class PoolStats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("nchunks", ctypes.c_int32), ("rhs_per_thread", ctypes.c_int32), ("ms", ctypes.c_double),
+                ("ms_heuristic", ctypes.c_double), ("n_tried", ctypes.c_int32), ("uses_mfma", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 EXPORTS = ["mfs_last_error", "mfs_version", "mfs_build_S", "mfs_scene_create", "mfs_scene_destroy",
            "mfs_scene_size", "mfs_scene_points", "mfs_plane_wave", "mfs_ghat_apply", "mfs_s_apply", "mfs_apply",
            "mfs_solve", "mfs_eval_field", "mfs_timing_enable", "mfs_timing_read", "mfs_pool_query",
            "mfs_pool_set_limit", "mfs_pool_trim", "mfs_recon_create", "mfs_recon_destroy", "mfs_recon_size",
-           "mfs_near_sizes", "mfs_plane_wave_colloc", "mfs_reconstruct", "mfs_eval_field_near"]
+           "mfs_near_sizes", "mfs_plane_wave_colloc", "mfs_reconstruct", "mfs_eval_field_near", "mfs_autotune",
+           "mfs_tune_get", "mfs_tune_set", "mfs_tune_save", "mfs_tune_load", "mfs_tune_clear", "mfs_tune_table_size"]
 MFS_KERNEL_PAIR_F32, MFS_KERNEL_PAIR_F64 = 0, 1
 
 
@@ -108,6 +117,13 @@ def load(path: str = LIB_PATH):
         "mfs_plane_wave_colloc": ([vp, vp, vp, i32, vp, vp], ctypes.c_int),
         "mfs_reconstruct": ([vp, vp, vp, vp, i32, vp, vp], ctypes.c_int),
         "mfs_eval_field_near": ([vp, vp, vp, vp, i32, vp, i64, vp, vp], ctypes.c_int),
+        "mfs_autotune": ([vp, i32, i32, i32, ctypes.POINTER(TuneResult), vp], ctypes.c_int),
+        "mfs_tune_get": ([vp, i32, i32] + [ctypes.POINTER(i32)] * 3, ctypes.c_int),
+        "mfs_tune_set": ([vp, i32, i32, i32, i32], ctypes.c_int),
+        "mfs_tune_save": ([ctypes.c_char_p], ctypes.c_int),
+        "mfs_tune_load": ([ctypes.c_char_p], ctypes.c_int),
+        "mfs_tune_clear": ([], ctypes.c_int),
+        "mfs_tune_table_size": ([ctypes.POINTER(i64)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -369,3 +385,40 @@ def pool_set_limit(max_cached_bytes: int):
 
 def pool_trim():
     _check(load().mfs_pool_trim())
+
+
+# -------------------------------------------------------------- autotuner ---
+def autotune(scene: Scene, R: int = 1, prec: int = MFS_MIXED, reps: int = 3, stream=None) -> dict:
+    """Time launch shapes of the operator on this scene and keep the fastest (synchronous)."""
+    out = TuneResult()
+    _check(_lib.mfs_autotune(scene.handle, int(R), int(prec), int(reps), ctypes.byref(out), _stream(stream)))
+    return out.as_dict()
+
+
+def tune_get(scene: Scene, R: int = 1, prec: int = MFS_MIXED) -> dict:
+    nch, rt, src = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.mfs_tune_get(scene.handle, int(R), int(prec), ctypes.byref(nch), ctypes.byref(rt), ctypes.byref(src)))
+    return {"nchunks": nch.value, "rhs_per_thread": rt.value,
+            "source": {0: "heuristic", 1: "table", 2: "scene"}[src.value]}
+
+
+def tune_set(scene: Scene, R: int, prec: int, nchunks: int, rhs_per_thread: int = 0):
+    _check(_lib.mfs_tune_set(scene.handle, int(R), int(prec), int(nchunks), int(rhs_per_thread)))
+
+
+def tune_save(path: str):
+    _check(load().mfs_tune_save(os.fsencode(path)))
+
+
+def tune_load(path: str):
+    _check(load().mfs_tune_load(os.fsencode(path)))
+
+
+def tune_clear():
+    _check(load().mfs_tune_clear())
+
+
+def tune_table_size() -> int:
+    n = ctypes.c_int64()
+    _check(load().mfs_tune_table_size(ctypes.byref(n)))
+    return n.value

@@ -114,3 +114,37 @@ def test_scene_rejects_improper_rotation_without_device(lib):
     assert lib.mfs_scene_create(2, 1.0, 1, shape_of.ctypes.data, centres.ctypes.data, reflection.ctypes.data, 1,
                                 k.ctypes.data, tp, sp, None, ctypes.byref(out)) == -1
     assert b"rotation" in lib.mfs_last_error()
+
+
+def test_launch_shape_table_round_trip_without_device(lib, tmp_path):
+    """The autotuner's process-wide table as a file: save, clear, load; malformed files are rejected
+    whole and leave the table as it was."""
+    mfs.tune_clear()
+    assert mfs.tune_table_size() == 0
+    good = tmp_path / "shapes.txt"
+    good.write_text("mfs-tune 1\n2 1 1 18 12 1\n2 2 64 18 8 0\n3 0 1 16 32 0\n")
+    mfs.tune_load(str(good))
+    assert mfs.tune_table_size() == 3
+    saved = tmp_path / "saved.txt"
+    mfs.tune_save(str(saved))
+    lines = saved.read_text().splitlines()
+    assert lines[0] == "mfs-tune 1"
+    assert sorted(lines[1:]) == sorted(good.read_text().splitlines()[1:])
+    # bad entries: nchunks out of range, bad rhs per thread, bad dim, bad variant, truncated line, no header
+    for body in ("mfs-tune 1\n2 1 1 18 2000 1\n", "mfs-tune 1\n2 1 1 18 12 3\n", "mfs-tune 1\n4 1 1 18 12 1\n",
+                 "mfs-tune 1\n2 7 1 18 12 1\n", "mfs-tune 1\n2 1 1 18 12\n", "2 1 1 18 12 1\n",
+                 "mfs-tune 1\n2 1 4 10 8 2\n2 1 0 10 8 2\n"):
+        bad = tmp_path / "bad.txt"
+        bad.write_text(body)
+        with pytest.raises(mfs.MfsError):
+            mfs.tune_load(str(bad))
+        assert mfs.tune_table_size() == 3
+    with pytest.raises(mfs.MfsError):
+        mfs.tune_load(str(tmp_path / "missing.txt"))
+    mfs.tune_clear()
+    mfs.tune_load(str(saved))
+    assert mfs.tune_table_size() == 3
+    mfs.tune_clear()
+    assert mfs.tune_table_size() == 0
+    assert lib.mfs_autotune(None, 1, 2, 1, None, None) == -1
+    assert lib.mfs_tune_set(None, 1, 2, 4, 0) == -1
