@@ -34,6 +34,10 @@ METRIC = "Helmholtz pair-evals/s per matvec; GMRES solve time @1e-8 rel res; p50
 # 3D: u (12), r^2, rsq, r, D + r, rcp, delta (6), phase fma (2), fract (1), 1/(4 pi r) (1),
 # sin + cos (2), (re, im) (2), complex multiply-add (8) = 34.
 FLOP_PER_PAIR_F32 = {2: 42, 3: 34}
+# The symmetric kernel (one right-hand side) evaluates phi once per unordered pair and makes two
+# complex multiply-adds with it: (42 - 8) + 16 = 50 flop per unordered pair in 2D, (34 - 8) + 16 = 42
+# in 3D, i.e. 25 and 21 per (ordered) pair of the operator.
+FLOP_PER_PAIR_F32_SYM = {2: 25, 3: 21}
 # FP32 vector peak from the unit counts: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz =
 # 78.6 TFLOP/s.  The 157.3 TFLOP/s figure counts packed (two-wide) FP32 instructions, which every HIP
 # build here disables, so 78.6 is the ceiling these kernels can reach; both are reported.
@@ -55,15 +59,16 @@ def stored_traffic(workload: str, kernel_name: str, nchunks: int):
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "ghat_f32_starfish2000_traffic.md")
-    if workload != "starfish2000_kappa10" or not kernel_name.startswith("ghat_bodyphase_kernel<2,2,1>"):
-        return None
-    if not os.path.exists(path):
+    if workload != "starfish2000_kappa10" or not os.path.exists(path):
         return None
     fields = {}
     for line in open(path):
-        if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha256", "nchunks"):
+        if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha256", "nchunks",
+                                                     "kernel"):
             k, v = line.split(":", 1)
             fields[k] = v.strip()
+    if not fields.get("kernel") or not kernel_name.startswith(fields["kernel"]):
+        return None
     csrc = os.path.join(ROOT, "paper_2603_19113_amd", "csrc")
     h = hashlib.sha256(open(os.path.join(csrc, "pair_kernels.hip"), "rb").read() +
                        open(os.path.join(csrc, "phi.h"), "rb").read()).hexdigest()
@@ -290,8 +295,9 @@ def main() -> int:
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-shape autotuner (run before the warm-up, outside the timed steps)")
-    ap.add_argument("--launch-shape", default=None, metavar="NCHUNKS:RT",
-                    help="use this pair-sum launch shape on every scene instead of tuning (profiling runs)")
+    ap.add_argument("--launch-shape", default=None, metavar="NCHUNKS:RT[:SYM]",
+                    help="use this pair-sum launch shape on every scene instead of tuning (profiling runs); "
+                         "SYM 1 = symmetric kernel where it applies, 0 = plain kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--verbose", type=int, default=2, help="solver progress lines on stderr")
@@ -347,8 +353,8 @@ def main() -> int:
 
     forced = None
     if args.launch_shape:
-        nch, rt = (int(x) for x in args.launch_shape.split(":"))
-        forced = (nch, rt)
+        parts = [int(x) for x in args.launch_shape.split(":")]
+        forced = (parts[0], parts[1], parts[2] if len(parts) > 2 else -1)
 
     def make_scene():
         built = [mfs.build_S(s, sc.kappa) for s in sc.shapes]
@@ -424,8 +430,11 @@ def main() -> int:
     mfs.timing_enable(False)
 
     on_mfma = sc.R >= 8 and all(sh.k % 16 == 0 for sh in sc.shapes)
+    on_sym = shape["symmetric"] == 1
     if on_mfma:
         kernel_name = "ghat_mfma_kernel<%d> (G_hat, FP32 matrix cores)" % sc.dim
+    elif on_sym:
+        kernel_name = "ghat_sym_kernel<%d> (G_hat, FP32, symmetric)" % sc.dim
     else:
         kernel_name = "ghat_bodyphase_kernel<%d,2,%d> (G_hat, FP32)" % (sc.dim, shape["rhs_per_thread"])
     traffic = stored_traffic(sc.name, kernel_name, shape["nchunks"])
@@ -437,8 +446,8 @@ def main() -> int:
         # the contraction on the matrix cores: 8 flop per (pair, right-hand side) complex multiply-add
         flop_pp, bound, peak, peak_alt = FLOP_PER_PAIR_RHS_MFMA, "mfma", PEAK_FP32_MFMA_TFLOPS, None
     else:
-        flop_pp, bound, peak, peak_alt = FLOP_PER_PAIR_F32[sc.dim], "alu", PEAK_FP32_VECTOR_TFLOPS, \
-            PEAK_FP32_PACKED_TFLOPS
+        flop_pp, bound, peak, peak_alt = (FLOP_PER_PAIR_F32_SYM if on_sym else FLOP_PER_PAIR_F32)[sc.dim], "alu", \
+            PEAK_FP32_VECTOR_TFLOPS, PEAK_FP32_PACKED_TFLOPS
     achieved = flop_pp * pairs_per_launch32 / (avg32 * 1e-3) / 1e12 if n32 else 0.0
     solve_times = [i["t_total_s"] for i in infos]
     out = {

@@ -164,16 +164,41 @@ int tune_variant(const mfs_scene* s, bool f64, int R) {
 }
 
 // Launch shape of the pair sum over the scene's own points: the scene's tuned entry, else the
-// process-wide table, else the occupancy heuristic.
-LaunchShape shape_for(const mfs_scene* s, bool f64, int R) {
+// process-wide table, else the heuristic (the symmetric kernel where it applies); resolved for this
+// scene (sym is 0 or 1 on return, and nchunks counts distance chunks when sym is 1).
+LaunchShape shape_for(const mfs_scene* s, bool f64, int R, int* source = nullptr) {
   const int v = tune_variant(s, f64, R);
+  LaunchShape e;
+  int src = 0;
   auto it = s->tuned.find({v, R});
-  if (it != s->tuned.end()) return it->second;
-  LaunchShape ls;
-  if (tune_lookup(s->dev.dim, v, R, s->dev.N, &ls)) return ls;
-  ls.nchunks = pair_chunks_for(s->dev.N, s->dev.N, tpt_for(f64 ? MFS_FP64 : MFS_FP32));
-  ls.rt = 0;
+  if (it != s->tuned.end()) {
+    e = it->second;
+    src = 2;
+  } else if (tune_lookup(s->dev.dim, v, R, s->dev.N, &e)) {
+    src = 1;
+  }
+  if (source) *source = src;
+  LaunchShape ls = e;
+  const bool sym_ok = v == kTunePairF32 && ghat_sym_possible(s->dev, R);
+  if (sym_ok && e.sym != 0) {
+    ls.sym = 1;
+    // a slice count tuned for the other kernel does not carry over
+    if (e.sym != 1 || e.nchunks <= 0) ls.nchunks = sym_plan(s->dev.N, 0).nchunks_d;
+  } else {
+    ls.sym = 0;
+    if (e.sym == 1 || e.nchunks <= 0) ls.nchunks = pair_chunks_for(s->dev.N, s->dev.N, tpt_for(f64 ? MFS_FP64 : MFS_FP32));
+  }
   return ls;
+}
+
+// Partial-sum slices the FP32 pair sum writes with this shape.
+int f32_slices(const mfs_scene* s, const LaunchShape& ls) {
+  return ls.sym == 1 ? sym_plan(s->dev.N, ls.nchunks).slices : ls.nchunks;
+}
+
+hipError_t launch_f32(const mfs_scene* s, const c64* q, int R, c64* part, const LaunchShape& ls, hipStream_t st) {
+  if (ls.sym == 1) return launch_ghat_f32_sym(s->dev, q, part, ls.nchunks, st);
+  return launch_ghat_f32(s->dev, q, R, part, ls.nchunks, st, ls.rt);
 }
 
 // y = q + S G_hat q in FP64 (all operands complex128).
@@ -192,12 +217,12 @@ mfs_status apply_f64(mfs_scene* s, const c128* q, c128* y, int R, hipStream_t st
 // y = q + S G_hat q in FP32 (complex64 in and out).
 mfs_status apply_f32(mfs_scene* s, const c64* q, c64* y, int R, hipStream_t st) {
   const LaunchShape ls = shape_for(s, false, R);
-  const int nch = ls.nchunks;
+  const int nch = f32_slices(s, ls);
   MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c64), &s->bytes, st));
   c64* part = static_cast<c64*>(s->partial.p);
   {
     TimedLaunch tl(MFS_KERNEL_PAIR_F32, s->dev.offbody_pairs * R, st);
-    MFS_HIP_TRY(launch_ghat_f32(s->dev, q, R, part, nch, st, ls.rt));
+    MFS_HIP_TRY(launch_f32(s, q, R, part, ls, st));
   }
   MFS_HIP_TRY(launch_sapply_f32(s->dev, part, nch, q, 1.0f, y, R, (int)s->kmax, st));
   return MFS_OK;
@@ -209,14 +234,14 @@ mfs_status apply_mixed(mfs_scene* s, const c128* q, c128* y, int R, hipStream_t 
   const int64_t NR = s->dev.N * R;
   MFS_TRY(ensure(s->q32, (size_t)NR * sizeof(c64), &s->bytes, st));
   const LaunchShape ls = shape_for(s, false, R);
-  const int nch = ls.nchunks;
+  const int nch = f32_slices(s, ls);
   MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c64), &s->bytes, st));
   c64* q32 = static_cast<c64*>(s->q32.p);
   c64* part = static_cast<c64*>(s->partial.p);
   MFS_HIP_TRY(launch_to_c64(q, q32, NR, st));
   {
     TimedLaunch tl(MFS_KERNEL_PAIR_F32, s->dev.offbody_pairs * R, st);
-    MFS_HIP_TRY(launch_ghat_f32(s->dev, q32, R, part, nch, st, ls.rt));
+    MFS_HIP_TRY(launch_f32(s, q32, R, part, ls, st));
   }
   MFS_HIP_TRY(launch_sapply_mixed(s->dev, part, nch, q, beta, y, R, (int)s->kmax, st));
   return MFS_OK;
@@ -310,12 +335,12 @@ mfs_status prepare_near(mfs_scene* s, const mfs_recon* const* recon, hipStream_t
 // y = S G_hat q with q already complex64 (a single-precision Krylov basis vector) and y complex128.
 mfs_status apply_mixed_from32(mfs_scene* s, const c64* q32, c128* y, int R, hipStream_t st) {
   const LaunchShape ls = shape_for(s, false, R);
-  const int nch = ls.nchunks;
+  const int nch = f32_slices(s, ls);
   MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c64), &s->bytes, st));
   c64* part = static_cast<c64*>(s->partial.p);
   {
     TimedLaunch tl(MFS_KERNEL_PAIR_F32, s->dev.offbody_pairs * R, st);
-    MFS_HIP_TRY(launch_ghat_f32(s->dev, q32, R, part, nch, st, ls.rt));
+    MFS_HIP_TRY(launch_f32(s, q32, R, part, ls, st));
   }
   MFS_HIP_TRY(launch_sapply_mixed(s->dev, part, nch, nullptr, 0.0, y, R, (int)s->kmax, st));
   return MFS_OK;
@@ -487,8 +512,11 @@ mfs_status mfs_scene_create(int32_t dim, double kappa, int64_t T, const int32_t*
     for (int dd = 0; dd < dim; ++dd) r2 += tmpl[i * dim + dd] * tmpl[i * dim + dd];
     d.rho_max = std::max(d.rho_max, std::sqrt(r2));
   }
-  d.all_k_mult16 = true;
-  for (int s2 = 0; s2 < n_shapes; ++s2) d.all_k_mult16 = d.all_k_mult16 && (k_of_shape[s2] % 16 == 0);
+  d.all_k_mult16 = d.all_k_mult64 = true;
+  for (int s2 = 0; s2 < n_shapes; ++s2) {
+    d.all_k_mult16 = d.all_k_mult16 && (k_of_shape[s2] % 16 == 0);
+    d.all_k_mult64 = d.all_k_mult64 && (k_of_shape[s2] % 64 == 0);
+  }
   *out = sc;
   return MFS_OK;
 }
@@ -544,7 +572,7 @@ mfs_status mfs_ghat_apply(const mfs_scene* sc, const void* q_dev, void* t_dev, i
   hipStream_t st = as_stream(stream);
   s->last_stream = st;
   const LaunchShape ls = shape_for(s, prec == MFS_FP64, R);
-  const int nch = ls.nchunks;
+  const int nch = prec == MFS_FP64 ? ls.nchunks : f32_slices(s, ls);
   if (prec == MFS_FP64) {
     MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c128), &s->bytes, st));
     c128* part = static_cast<c128*>(s->partial.p);
@@ -558,7 +586,7 @@ mfs_status mfs_ghat_apply(const mfs_scene* sc, const void* q_dev, void* t_dev, i
     c64* part = static_cast<c64*>(s->partial.p);
     {
       TimedLaunch tl(MFS_KERNEL_PAIR_F32, s->dev.offbody_pairs * R, st);
-      MFS_HIP_TRY(launch_ghat_f32(s->dev, static_cast<const c64*>(q_dev), R, part, nch, st, ls.rt));
+      MFS_HIP_TRY(launch_f32(s, static_cast<const c64*>(q_dev), R, part, ls, st));
     }
     MFS_HIP_TRY(launch_reduce_partials_f32(part, nch, s->dev.N, R, static_cast<c64*>(t_dev), st));
   }
@@ -1111,28 +1139,42 @@ mfs_status mfs_autotune(mfs_scene* s, int32_t R, mfs_prec prec, int32_t reps, mf
   const bool f64 = prec == MFS_FP64;
   const int v = tune_variant(s, f64, R);
   const std::pair<int, int> key{v, R};
+  const size_t part_elem = f64 ? sizeof(c128) : sizeof(c64);
+  const int maxc = (int)std::min<int64_t>(kTuneMaxChunks, std::max<int64_t>(1, N / 16));
+
+  // candidates, the untuned shape first: slice counts from h/4 to 4h around each kernel's heuristic
+  // (capped so that the partial sums stay within max(2 GiB, the heuristic's)), times 1, 2 or 4
+  // right-hand sides per thread on the VALU kernel, and the symmetric kernel where it applies
+  std::vector<LaunchShape> cands;
+  auto add = [&](LaunchShape c) {
+    for (const LaunchShape& o : cands)
+      if (o.nchunks == c.nchunks && o.rt == c.rt && o.sym == c.sym) return;
+    cands.push_back(c);
+  };
+  const bool sym_ok = v == kTunePairF32 && ghat_sym_possible(s->dev, R);
   const int h = pair_chunks_for(N, N, tpt_for(f64 ? MFS_FP64 : MFS_FP32));
   const int h_rt = v == kTunePairF32 ? ghat_default_rt(R) : 0;
-
-  // candidates: the heuristic first, then slice counts from h/4 to 4h (capped so that the partial
-  // sums stay within max(2 GiB, the heuristic's)), times 1, 2 or 4 right-hand sides per thread
-  const size_t part_elem = f64 ? sizeof(c128) : sizeof(c64);
   const size_t cap = std::max<size_t>((size_t)2 << 30, (size_t)h * R * N * part_elem);
-  const int maxc = (int)std::min<int64_t>(kTuneMaxChunks, std::max<int64_t>(1, N / 16));
-  std::vector<int> nset;
-  for (int f : {0, -2, -1, 1, 2}) {
-    int c = f < 0 ? (h >> -f) : (h << f);
-    c = std::max(1, std::min(c, maxc));
-    if (f != 0 && (size_t)c * R * N * part_elem > cap) continue;
-    if (std::find(nset.begin(), nset.end(), c) == nset.end()) nset.push_back(c);
+  auto plain = [&]() {
+    std::vector<int> rset{h_rt};
+    if (v == kTunePairF32)
+      for (int rt : {1, 2, 4})
+        if (rt != h_rt && (rt == 1 || rt / 2 < R)) rset.push_back(rt);
+    for (int f : {0, -2, -1, 1, 2}) {
+      int c = f < 0 ? (h >> -f) : (h << f);
+      c = std::max(1, std::min(c, maxc));
+      if (f != 0 && (size_t)c * R * N * part_elem > cap) continue;
+      for (int rt : rset) add(LaunchShape{c, rt, 0});
+    }
+  };
+  if (sym_ok) {
+    const SymPlan hp = sym_plan(N, 0);
+    for (int f : {0, -2, -1, 1, 2}) {
+      const int c = f < 0 ? (hp.nchunks_d >> -f) : (hp.nchunks_d << f);
+      add(LaunchShape{sym_plan(N, std::max(1, std::min(c, kTuneMaxChunks))).nchunks_d, 0, 1});
+    }
   }
-  std::vector<int> rset{h_rt};
-  if (v == kTunePairF32)
-    for (int rt : {1, 2, 4})
-      if (rt != h_rt && (rt == 1 || rt / 2 < R)) rset.push_back(rt);
-  std::vector<LaunchShape> cands;
-  for (int c : nset)
-    for (int rt : rset) cands.push_back(LaunchShape{c, rt});
+  plain();
 
   const size_t vec = (prec == MFS_FP32 ? sizeof(c64) : sizeof(c128)) * (size_t)R * N;
   struct Scratch {
@@ -1167,7 +1209,7 @@ mfs_status mfs_autotune(mfs_scene* s, int32_t R, mfs_prec prec, int32_t reps, mf
     if (had) s->tuned[key] = before;
     else s->tuned.erase(key);
   };
-  double best = 0.0, ms_h = 0.0;
+  double best = 0.0, ms_h = 0.0, ms_plain = -1.0;
   LaunchShape best_ls = cands.front();
   for (size_t i = 0; i < cands.size(); ++i) {
     s->tuned[key] = cands[i];
@@ -1184,6 +1226,7 @@ mfs_status mfs_autotune(mfs_scene* s, int32_t R, mfs_prec prec, int32_t reps, mf
     }
     const double t = (double)ms / reps;
     if (i == 0) ms_h = t;
+    if (cands[i].sym == 0 && ms_plain < 0.0) ms_plain = t;  // the plain kernel's heuristic shape
     if (i == 0 || t < best) {
       best = t;
       best_ls = cands[i];
@@ -1192,46 +1235,47 @@ mfs_status mfs_autotune(mfs_scene* s, int32_t R, mfs_prec prec, int32_t reps, mf
   s->tuned[key] = best_ls;
   tune_store(s->dev.dim, v, R, N, best_ls);
   // the largest candidate may have grown the partial-sum buffer well past what the winner needs
-  if (s->partial.cap > 2 * (size_t)best_ls.nchunks * R * N * part_elem) release(s->partial, &s->bytes, st);
+  const size_t need = (size_t)(f64 ? best_ls.nchunks : f32_slices(s, best_ls)) * R * N * part_elem;
+  if (s->partial.cap > 2 * need) release(s->partial, &s->bytes, st);
   res.nchunks = best_ls.nchunks;
   res.rhs_per_thread = best_ls.rt;
   res.ms = best;
   res.ms_heuristic = ms_h;
   res.n_tried = (int32_t)cands.size();
   res.uses_mfma = v == kTunePairMfma ? 1 : 0;
+  res.symmetric = best_ls.sym == 1 ? 1 : 0;
+  res.ms_plain = ms_plain;
   if (out) *out = res;
   return MFS_OK;
 }
 
 mfs_status mfs_tune_get(const mfs_scene* s, int32_t R, mfs_prec prec, int32_t* nchunks, int32_t* rhs_per_thread,
-                        int32_t* source) {
+                        int32_t* symmetric, int32_t* source) {
   MFS_TRY(check_scene(s));
   if (R < 1) return fail(MFS_ERR_ARG, "tune_get: R must be >= 1");
   const bool f64 = prec == MFS_FP64;
   const int v = tune_variant(s, f64, R);
   int src = 0;
-  if (s->tuned.count({v, R})) src = 2;
-  else {
-    LaunchShape tmp;
-    if (tune_lookup(s->dev.dim, v, R, s->dev.N, &tmp)) src = 1;
-  }
-  const LaunchShape ls = shape_for(s, f64, R);
+  const LaunchShape ls = shape_for(s, f64, R, &src);
   if (nchunks) *nchunks = ls.nchunks;
-  if (rhs_per_thread) *rhs_per_thread = v == kTunePairF32 ? (ls.rt ? ls.rt : ghat_default_rt(R)) : 0;
+  if (rhs_per_thread) *rhs_per_thread = v == kTunePairF32 && ls.sym != 1 ? (ls.rt ? ls.rt : ghat_default_rt(R)) : 0;
+  if (symmetric) *symmetric = ls.sym == 1 ? 1 : 0;
   if (source) *source = src;
   return MFS_OK;
 }
 
-mfs_status mfs_tune_set(mfs_scene* s, int32_t R, mfs_prec prec, int32_t nchunks, int32_t rhs_per_thread) {
+mfs_status mfs_tune_set(mfs_scene* s, int32_t R, mfs_prec prec, int32_t nchunks, int32_t rhs_per_thread,
+                        int32_t symmetric) {
   MFS_TRY(check_scene(s));
   if (R < 1) return fail(MFS_ERR_ARG, "tune_set: R must be >= 1");
   if (nchunks < 0 || nchunks > kTuneMaxChunks)
     return fail(MFS_ERR_ARG, "tune_set: nchunks must be in 0.." + std::to_string(kTuneMaxChunks));
   if (rhs_per_thread != 0 && rhs_per_thread != 1 && rhs_per_thread != 2 && rhs_per_thread != 4)
     return fail(MFS_ERR_ARG, "tune_set: rhs_per_thread must be 0, 1, 2 or 4");
+  if (symmetric < -1 || symmetric > 1) return fail(MFS_ERR_ARG, "tune_set: symmetric must be -1, 0 or 1");
   const std::pair<int, int> key{tune_variant(s, prec == MFS_FP64, R), R};
   if (nchunks == 0) s->tuned.erase(key);
-  else s->tuned[key] = LaunchShape{nchunks, rhs_per_thread};
+  else s->tuned[key] = LaunchShape{nchunks, rhs_per_thread, symmetric};
   return MFS_OK;
 }
 

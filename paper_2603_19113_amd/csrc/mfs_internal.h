@@ -50,6 +50,7 @@ struct SceneDev {
   const void* const* S32;         // [n_shapes] device pointers (complex64) or null
   double offbody_pairs;           // N^2 - sum_tau k_tau^2
   bool all_k_mult16;              // every shape has a multiple of 16 points (matrix-core path)
+  bool all_k_mult64;              // every shape has a multiple of 64 points (symmetric pair kernel)
   double rho_max;                 // largest |x_hat - c_body| over all shapes
   const double* rot;              // [T][dim][dim] body orientations (row-major), or null: identity
 };
@@ -64,6 +65,17 @@ bool ghat_uses_mfma(const SceneDev& s, int R);
 // rt: right-hand sides per thread of the VALU kernel (1, 2 or 4; anything else picks by R);
 // ignored where the matrix-core kernel runs.
 int ghat_default_rt(int R);
+// Symmetric one-right-hand-side pair kernel: groups of 256 points, G groups, distances 0..Dmax,
+// nchunks_d distance chunks of dpc each; it writes `slices` partial slices (nchunks_d target-side,
+// Dsym source-side).  nchunks_d <= 0 picks the heuristic.
+struct SymPlan {
+  int64_t G;
+  int Dmax, Dsym, dpc, nchunks_d, slices;
+  bool even;
+};
+SymPlan sym_plan(int64_t N, int nchunks_d);
+bool ghat_sym_possible(const SceneDev& s, int R);
+hipError_t launch_ghat_f32_sym(const SceneDev& s, const c64* q, c64* partial, int nchunks_d, hipStream_t st);
 hipError_t launch_ghat_f32(const SceneDev& s, const c64* q, int R, c64* partial, int nchunks,
                            hipStream_t st, int rt = 0);
 hipError_t launch_ghat_f64(const SceneDev& s, const c128* q, int R, c128* partial, int nchunks,
@@ -167,12 +179,15 @@ void pool_trim();
 void pool_set_limit(size_t bytes);
 hipStream_t private_stream(hipError_t* err);
 
-// Launch shapes of the pair sum (tune.hip).  nchunks: source slices per target block; rt: right-hand
-// sides per thread of the VALU kernel (0 = chosen by R).  The process-wide table is keyed by
+// Launch shapes of the pair sum (tune.hip).  nchunks: source slices per target block (distance
+// chunks for the symmetric kernel); rt: right-hand sides per thread of the VALU kernel (0 = chosen
+// by R); sym: the symmetric one-right-hand-side kernel where the scene allows it unless 0 (-1 = unset,
+// as the heuristic: symmetric where possible).  The process-wide table is keyed by
 // (dim, kernel variant, R, floor(log2 N)) and filled by the autotuner or a loaded file.
 struct LaunchShape {
   int nchunks = 0;
   int rt = 0;
+  int sym = -1;
 };
 enum TuneVariant { kTunePairF64 = 0, kTunePairF32 = 1, kTunePairMfma = 2 };
 constexpr int kTuneMaxChunks = 1024;

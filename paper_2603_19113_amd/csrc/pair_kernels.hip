@@ -470,6 +470,241 @@ __global__ __launch_bounds__(kBlock) void ghat_bodyphase_kernel(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Symmetric pair sum, one right-hand side: G_hat is symmetric (phi depends on |x_i - x_j| only),
+// so each unordered pair of points on different bodies needs one evaluation of phi, applied to
+// both t_i += phi q_j and t_j += phi q_i.
+//
+// Requires every body to hold a multiple of 64 points, so that every aligned tile of 64 points
+// lies on one body.  Points are cut into groups of kSymGroup = 256 (four tiles); with G groups,
+// group g meets group h = (g + d) mod G for d = 0 .. Dmax (Dmax = floor(G/2)):
+//   * 1 <= d < G/2: symmetric, each unordered pair of groups is met once, by g;
+//   * d = 0 (the group with itself) and d = G/2 for even G: one-sided, only t of group g.
+// One wave (one block) owns a group of targets, four per lane (lane l: targets 64 m + l), and a
+// range of distances (grid.y).  For each source tile of group h it stages the tile's coordinates
+// and charges in LDS twice over (entries e and e + 64) and makes 64 steps: at step s lane l takes
+// source (l + s) mod 64 from entry l + s, so the 64 lanes see 64 different sources and after 64
+// steps every (target, source) pair of the tile has been formed once.  The source-side sums
+// travel with the sources: at step s lane l holds the running sum of source (l + s) mod 64, adds
+// its products into it and hands it on with a wave rotation (DPP wave_rol:1, lane l receives lane
+// l + 1's value), so after 64 steps lane j holds source j's sum.  Everything stays in registers and
+// in program order: deterministic, no atomics.
+// Outputs, all plain stores (fixed summation order downstream):
+//   partial[c][N]                    target-side sums of distance chunk c (c < nchunks_d)
+//   partial[nchunks_d + d - 1][N]    source-side sums of distance d, written by group h - d.
+// Body-centre phase split and the Hankel branches are those of the kernel above; the body pair of
+// a (target tile, source tile) is wave-uniform, so are the far-field tests and the same-body skip.
+// ---------------------------------------------------------------------------
+constexpr int kSymTiles = 4;                 // target tiles per wave
+constexpr int kSymGroup = 64 * kSymTiles;    // points per group
+
+template <int DIM>
+struct SymLds {
+  float l[DIM][128];
+  float bs[128];
+  float qr[128], qi[128];
+};
+
+// lane l receives lane (l + 1) mod 64's value
+__device__ __forceinline__ float wave_rotate_next(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x134, 0xf, 0xf, false));
+}
+
+// All four target tiles against the staged source tile, every pair in the z >= 100 regime (the
+// common case): one pass over the 64 steps, phi of each (target, source) used twice.
+template <int DIM, bool SYM>
+__device__ __forceinline__ void sym_steps4(const SymLds<DIM>& sh, const BodyPhaseConsts& k, int lane,
+                                           const float (&A)[kSymTiles], const float (&P)[kSymTiles][DIM],
+                                           const float (&D)[kSymTiles], const float (&D2)[kSymTiles],
+                                           const float (&ph0)[kSymTiles], const float (&qtr)[kSymTiles],
+                                           const float (&qti)[kSymTiles], float (&tr)[kSymTiles],
+                                           float (&ti)[kSymTiles], float& ar, float& ai) {
+  for (int s0 = 0; s0 < 64; s0 += 8) {
+    const int e0 = lane + s0;
+#pragma unroll
+    for (int uu = 0; uu < 8; ++uu) {
+      const int e = e0 + uu;
+      float ls[DIM];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) ls[d] = sh.l[d][e];
+      const float bs = sh.bs[e];
+      const float qr = sh.qr[e], qi = sh.qi[e];
+      float sr = ar, si = ai;
+#pragma unroll
+      for (int m = 0; m < kSymTiles; ++m) {
+        float u = A[m] + bs;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) u = fmaf(P[m][d], ls[d], u);
+        float pr, pi;
+        bp_phi<DIM, 2>(k, u, D[m], D2[m], ph0[m], pr, pi);
+        tr[m] = fmaf(pr, qr, fmaf(-pi, qi, tr[m]));
+        ti[m] = fmaf(pr, qi, fmaf(pi, qr, ti[m]));
+        if constexpr (SYM) {
+          sr = fmaf(pr, qtr[m], fmaf(-pi, qti[m], sr));
+          si = fmaf(pr, qti[m], fmaf(pi, qtr[m], si));
+        }
+      }
+      if constexpr (SYM) {
+        ar = wave_rotate_next(sr);
+        ai = wave_rotate_next(si);
+      }
+    }
+  }
+}
+
+// One target tile against the staged source tile, with the Hankel branch set FAR (any regime):
+// the rare cases (near body pairs, partly filled or same-body tiles), kept lean in registers.
+// 64 rotations bring the source-side sums back to their own lanes, so passes can follow each other.
+template <int DIM, bool SYM, int FAR>
+__device__ __forceinline__ void sym_steps1(const SymLds<DIM>& sh, const BodyPhaseConsts& k, int lane, float A,
+                                           const float (&P)[DIM], float D, float D2, float ph0, float qtr,
+                                           float qti, float& tr, float& ti, float& ar, float& ai) {
+  for (int s0 = 0; s0 < 64; s0 += 8) {
+    const int e0 = lane + s0;
+#pragma unroll
+    for (int uu = 0; uu < 8; ++uu) {
+      const int e = e0 + uu;
+      float u = A + sh.bs[e];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) u = fmaf(P[d], sh.l[d][e], u);
+      float pr, pi;
+      bp_phi<DIM, FAR>(k, u, D, D2, ph0, pr, pi);
+      const float qr = sh.qr[e], qi = sh.qi[e];
+      tr = fmaf(pr, qr, fmaf(-pi, qi, tr));
+      ti = fmaf(pr, qi, fmaf(pi, qr, ti));
+      if constexpr (SYM) {
+        ar = wave_rotate_next(fmaf(pr, qtr, fmaf(-pi, qti, ar)));
+        ai = wave_rotate_next(fmaf(pr, qti, fmaf(pi, qtr, ai)));
+      }
+    }
+  }
+}
+
+template <int DIM, bool SYM>
+__device__ __forceinline__ void sym_tile(const SymLds<DIM>& sh, const BodyPhaseConsts& k, int lane,
+                                         const bool (&use)[kSymTiles], const float (&A)[kSymTiles],
+                                         const float (&P)[kSymTiles][DIM], const float (&D)[kSymTiles],
+                                         const float (&D2)[kSymTiles], const float (&ph0)[kSymTiles],
+                                         const float (&qtr)[kSymTiles], const float (&qti)[kSymTiles],
+                                         float (&tr)[kSymTiles], float (&ti)[kSymTiles], float& ar, float& ai) {
+  bool fast = true;
+#pragma unroll
+  for (int m = 0; m < kSymTiles; ++m) fast = fast && use[m] && (DIM == 3 || D[m] >= k.vfar_D);
+  if (fast) {
+    sym_steps4<DIM, SYM>(sh, k, lane, A, P, D, D2, ph0, qtr, qti, tr, ti, ar, ai);
+    return;
+  }
+#pragma unroll
+  for (int m = 0; m < kSymTiles; ++m) {
+    if (!use[m]) continue;
+    if (DIM == 3 || D[m] >= k.vfar_D)
+      sym_steps1<DIM, SYM, 2>(sh, k, lane, A[m], P[m], D[m], D2[m], ph0[m], qtr[m], qti[m], tr[m], ti[m], ar, ai);
+    else if (D[m] >= k.far_D)
+      sym_steps1<DIM, SYM, 1>(sh, k, lane, A[m], P[m], D[m], D2[m], ph0[m], qtr[m], qti[m], tr[m], ti[m], ar, ai);
+    else
+      sym_steps1<DIM, SYM, 0>(sh, k, lane, A[m], P[m], D[m], D2[m], ph0[m], qtr[m], qti[m], tr[m], ti[m], ar, ai);
+  }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(64, 4) void ghat_sym_kernel(
+    BodyPhaseConsts k, const float* __restrict__ l0, const float* __restrict__ l1, const float* __restrict__ l2,
+    const float* __restrict__ lsq, const double* __restrict__ cen, const int32_t* __restrict__ body_of,
+    const c64* __restrict__ q, int64_t N, int64_t G, int Dmax, int even_G, int dpc, int nchunks_d,
+    c64* __restrict__ partial) {
+  __shared__ SymLds<DIM> sh;
+  const int lane = threadIdx.x;
+  const int64_t g = blockIdx.x;
+  const int c = blockIdx.y;
+  const int d0 = c * dpc;
+  const int d1 = min(Dmax + 1, d0 + dpc);
+  const float* lsrc[3] = {l0, l1, l2};
+
+  // targets of this wave: tile m covers points g*256 + 64 m + (0..63), all on one body
+  bool act[kSymTiles];
+  int tb[kSymTiles];
+  float lt[kSymTiles][DIM], qtr[kSymTiles], qti[kSymTiles];
+  double ar[kSymTiles], ai[kSymTiles];
+#pragma unroll
+  for (int m = 0; m < kSymTiles; ++m) {
+    const int64_t t0 = g * kSymGroup + 64 * m;
+    act[m] = t0 < N;
+    const int64_t t = act[m] ? t0 + lane : 0;
+    tb[m] = act[m] ? __builtin_amdgcn_readfirstlane(body_of[t0]) : -1;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) lt[m][d] = lsrc[d][t];
+    const c64 qq = q[t];
+    qtr[m] = act[m] ? qq.re : 0.0f;
+    qti[m] = act[m] ? qq.im : 0.0f;
+    ar[m] = ai[m] = 0.0;
+  }
+
+  for (int d = d0; d < d1; ++d) {
+    int64_t h = g + d;
+    if (h >= G) h -= G;
+    const bool sym = d != 0 && !(even_G && d == Dmax);
+    for (int ts = 0; ts < kSymTiles; ++ts) {
+      const int64_t j0 = h * kSymGroup + 64 * ts;
+      if (j0 >= N) break;
+      const int sb = __builtin_amdgcn_readfirstlane(body_of[j0]);
+      // stage the source tile (entries e and e + 64)
+      {
+        const int64_t j = j0 + lane;
+#pragma unroll
+        for (int dd = 0; dd < DIM; ++dd) sh.l[dd][lane] = sh.l[dd][lane + 64] = lsrc[dd][j];
+        sh.bs[lane] = sh.bs[lane + 64] = lsq[j];
+        const c64 qq = q[j];
+        sh.qr[lane] = sh.qr[lane + 64] = qq.re;
+        sh.qi[lane] = sh.qi[lane + 64] = qq.im;
+      }
+      __syncthreads();
+      // per target tile: body-centre split against the source body (uniform over the wave)
+      double cs[DIM];
+#pragma unroll
+      for (int dd = 0; dd < DIM; ++dd) cs[dd] = cen[(int64_t)sb * DIM + dd];
+      bool use[kSymTiles];
+      float A[kSymTiles], P[kSymTiles][DIM], D[kSymTiles], D2[kSymTiles], ph0[kSymTiles];
+      float tr[kSymTiles], ti[kSymTiles];
+#pragma unroll
+      for (int m = 0; m < kSymTiles; ++m) {
+        use[m] = act[m] && tb[m] != sb;
+        tr[m] = ti[m] = 0.0f;
+        const int bt = use[m] ? tb[m] : sb;
+        double D2d = 0.0;
+        float Am = 0.0f;
+#pragma unroll
+        for (int dd = 0; dd < DIM; ++dd) {
+          const double dc = cen[(int64_t)bt * DIM + dd] - cs[dd];
+          D2d = fma(dc, dc, D2d);
+          const float dcf = (float)dc;
+          Am = fmaf(lt[m][dd], lt[m][dd] + 2.0f * dcf, Am);
+          P[m][dd] = -2.0f * (lt[m][dd] + dcf);
+        }
+        A[m] = Am;
+        const double Dd = sqrt(D2d);
+        const double ph = Dd * k.kappa_rev64;
+        D[m] = (float)Dd;
+        D2[m] = (float)D2d;
+        ph0[m] = (float)(ph - floor(ph)) - (DIM == 2 ? 0.125f : 0.0f);
+      }
+      float sr = 0.0f, si = 0.0f;  // lane l: source-side sum of source j0 + l (after the tile)
+      if (sym) sym_tile<DIM, true>(sh, k, lane, use, A, P, D, D2, ph0, qtr, qti, tr, ti, sr, si);
+      else sym_tile<DIM, false>(sh, k, lane, use, A, P, D, D2, ph0, qtr, qti, tr, ti, sr, si);
+#pragma unroll
+      for (int m = 0; m < kSymTiles; ++m) {
+        ar[m] += (double)tr[m];
+        ai[m] += (double)ti[m];
+      }
+      // source-side sums of this tile from the wave's targets -> slice of distance d
+      if (sym) partial[(int64_t)(nchunks_d + d - 1) * N + j0 + lane] = c64{sr, si};
+      __syncthreads();  // the tile's entries are read before the next tile is staged
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < kSymTiles; ++m)
+    if (act[m]) partial[(int64_t)c * N + g * kSymGroup + 64 * m + lane] = c64{(float)ar[m], (float)ai[m]};
+}
+
 Phi2DConstsF32 make_phi2d_f32(double kappa) {
   Phi2DConstsF32 c;
   c.kappa = (float)kappa;
@@ -782,6 +1017,43 @@ bool ghat_uses_mfma(const SceneDev& s, int R) { return R >= kMfmaMinRhs && s.all
 
 int ghat_default_rt(int R) { return R == 1 ? 1 : R == 2 ? 2 : 4; }
 
+SymPlan sym_plan(int64_t N, int nchunks_d) {
+  SymPlan p{};
+  p.G = (N + kSymGroup - 1) / kSymGroup;
+  p.Dmax = (int)(p.G / 2);
+  p.even = p.G % 2 == 0;
+  p.Dsym = p.even ? p.Dmax - 1 : p.Dmax;
+  if (p.Dsym < 0) p.Dsym = 0;
+  // heuristic: about 64k single-wave blocks (the tuner's choice on the 2000-starfish scene: 63 chunks)
+  int want = nchunks_d > 0 ? nchunks_d : (int)std::min<int64_t>(kTuneMaxChunks, (65536 + p.G - 1) / std::max<int64_t>(p.G, 1));
+  want = std::max(1, std::min(want, p.Dmax + 1));
+  p.dpc = (p.Dmax + 1 + want - 1) / want;
+  p.nchunks_d = (p.Dmax + 1 + p.dpc - 1) / p.dpc;  // no empty chunks
+  p.slices = p.nchunks_d + p.Dsym;
+  return p;
+}
+
+bool ghat_sym_possible(const SceneDev& s, int R) {
+  if (R != 1 || !s.all_k_mult64 || s.N <= 0) return false;
+  const SymPlan p = sym_plan(s.N, 0);
+  // the source-side slots grow as N^2 / 512: keep them within 8 GiB
+  return (double)(p.Dsym + 1) * (double)s.N * sizeof(c64) <= 8.0 * (1ull << 30);
+}
+
+hipError_t launch_ghat_f32_sym(const SceneDev& s, const c64* q, c64* partial, int nchunks_d, hipStream_t st) {
+  if (s.N <= 0) return hipSuccess;
+  const SymPlan p = sym_plan(s.N, nchunks_d);
+  const dim3 grid((unsigned)p.G, (unsigned)p.nchunks_d, 1);
+  const BodyPhaseConsts k = make_bodyphase(s.kappa, s.rho_max);
+  if (s.dim == 2)
+    hipLaunchKernelGGL((ghat_sym_kernel<2>), grid, dim3(64), 0, st, k, s.l32[0], s.l32[1], s.l32[2], s.lsq32,
+                       s.centres, s.body_of, q, s.N, p.G, p.Dmax, p.even ? 1 : 0, p.dpc, p.nchunks_d, partial);
+  else
+    hipLaunchKernelGGL((ghat_sym_kernel<3>), grid, dim3(64), 0, st, k, s.l32[0], s.l32[1], s.l32[2], s.lsq32,
+                       s.centres, s.body_of, q, s.N, p.G, p.Dmax, p.even ? 1 : 0, p.dpc, p.nchunks_d, partial);
+  return hipGetLastError();
+}
+
 hipError_t launch_ghat_f32(const SceneDev& s, const c64* q, int R, c64* partial, int nchunks, hipStream_t st,
                            int rt) {
   if (s.N <= 0) return hipSuccess;
@@ -839,13 +1111,13 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const Cplx<T>* __r
                                                               int64_t MR, Cplx<T>* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= MR) return;
-  T re = 0, im = 0;
+  double re = 0, im = 0;  // many slices (symmetric kernel): add them in FP64
   for (int c = 0; c < nchunks; ++c) {
     const Cplx<T> v = partial[(int64_t)c * MR + i];
-    re += v.re;
-    im += v.im;
+    re += (double)v.re;
+    im += (double)v.im;
   }
-  out[i] = Cplx<T>{re, im};
+  out[i] = Cplx<T>{(T)re, (T)im};
 }
 
 hipError_t launch_reduce_partials_f32(const c64* partial, int nchunks, int64_t M, int R, c64* out, hipStream_t st) {

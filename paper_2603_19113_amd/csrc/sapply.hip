@@ -27,13 +27,13 @@ __global__ __launch_bounds__(256) void sapply_kernel(const int64_t* __restrict__
   const int64_t NR = N * R;
   for (int j = threadIdx.x; j < k; j += blockDim.x) {
     const int64_t idx = (int64_t)r * N + start + j;
-    TS re = 0, im = 0;
+    double re = 0, im = 0;  // the symmetric pair kernel leaves hundreds of slices: add in FP64
     for (int c = 0; c < nchunks; ++c) {
       const Cplx<TS> v = partial[(int64_t)c * NR + idx];
-      re += v.re;
-      im += v.im;
+      re += (double)v.re;
+      im += (double)v.im;
     }
-    t[j] = Cplx<TS>{re, im};
+    t[j] = Cplx<TS>{(TS)re, (TS)im};
   }
   __syncthreads();
   for (int i = threadIdx.x; i < k; i += blockDim.x) {

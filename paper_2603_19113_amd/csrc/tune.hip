@@ -26,10 +26,11 @@ int log2_floor(int64_t n) {
 
 bool valid(int dim, int variant, int R, int lg, LaunchShape v) {
   return (dim == 2 || dim == 3) && variant >= kTunePairF64 && variant <= kTunePairMfma && R >= 1 && lg >= 0 &&
-         lg < 63 && v.nchunks >= 1 && v.nchunks <= kTuneMaxChunks && (v.rt == 0 || v.rt == 1 || v.rt == 2 || v.rt == 4);
+         lg < 63 && v.nchunks >= 1 && v.nchunks <= kTuneMaxChunks && (v.rt == 0 || v.rt == 1 || v.rt == 2 || v.rt == 4) &&
+         v.sym >= -1 && v.sym <= 1;
 }
 
-constexpr const char* kHeader = "mfs-tune 1";
+constexpr const char* kHeader = "mfs-tune 2";
 
 }  // namespace
 
@@ -56,7 +57,7 @@ int64_t tune_size() {
   return (int64_t)g_table.size();
 }
 
-// One line per entry: dim variant R log2N nchunks rt, after a header line.
+// One line per entry: dim variant R log2N nchunks rt sym, after a header line.
 bool tune_save(const char* path, std::string* err) {
   std::map<TuneKey, LaunchShape> copy;
   {
@@ -70,8 +71,8 @@ bool tune_save(const char* path, std::string* err) {
   }
   bool ok = std::fprintf(f, "%s\n", kHeader) > 0;
   for (const auto& [k, v] : copy)
-    ok = ok && std::fprintf(f, "%d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k),
-                            v.nchunks, v.rt) > 0;
+    ok = ok && std::fprintf(f, "%d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+                            std::get<3>(k), v.nchunks, v.rt, v.sym) > 0;
   ok = (std::fclose(f) == 0) && ok;
   if (!ok) *err = std::string("write to ") + path + " failed";
   return ok;
@@ -91,16 +92,16 @@ bool tune_load(const char* path, std::string* err) {
   bool ok = head_ok;
   if (!head_ok) *err = std::string(path) + ": not a launch-shape file (missing header)";
   while (ok) {
-    int dim, variant, R, lg, nch, rt;
-    const int got = std::fscanf(f, "%d %d %d %d %d %d", &dim, &variant, &R, &lg, &nch, &rt);
+    int dim, variant, R, lg, nch, rt, sym;
+    const int got = std::fscanf(f, "%d %d %d %d %d %d %d", &dim, &variant, &R, &lg, &nch, &rt, &sym);
     if (got == EOF) break;
     ++line;
-    if (got != 6 || !valid(dim, variant, R, lg, LaunchShape{nch, rt})) {
+    if (got != 7 || !valid(dim, variant, R, lg, LaunchShape{nch, rt, sym})) {
       *err = std::string(path) + ": bad entry on line " + std::to_string(line);
       ok = false;
       break;
     }
-    add[TuneKey{dim, variant, R, lg}] = LaunchShape{nch, rt};
+    add[TuneKey{dim, variant, R, lg}] = LaunchShape{nch, rt, sym};
   }
   std::fclose(f);
   if (!ok) return false;

@@ -66,7 +66,8 @@ class PoolStats(ctypes.Structure):
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("nchunks", ctypes.c_int32), ("rhs_per_thread", ctypes.c_int32), ("ms", ctypes.c_double),
-                ("ms_heuristic", ctypes.c_double), ("n_tried", ctypes.c_int32), ("uses_mfma", ctypes.c_int32)]
+                ("ms_heuristic", ctypes.c_double), ("n_tried", ctypes.c_int32), ("uses_mfma", ctypes.c_int32),
+                ("symmetric", ctypes.c_int32), ("ms_plain", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -118,8 +119,8 @@ def load(path: str = LIB_PATH):
         "mfs_reconstruct": ([vp, vp, vp, vp, i32, vp, vp], ctypes.c_int),
         "mfs_eval_field_near": ([vp, vp, vp, vp, i32, vp, i64, vp, vp], ctypes.c_int),
         "mfs_autotune": ([vp, i32, i32, i32, ctypes.POINTER(TuneResult), vp], ctypes.c_int),
-        "mfs_tune_get": ([vp, i32, i32] + [ctypes.POINTER(i32)] * 3, ctypes.c_int),
-        "mfs_tune_set": ([vp, i32, i32, i32, i32], ctypes.c_int),
+        "mfs_tune_get": ([vp, i32, i32] + [ctypes.POINTER(i32)] * 4, ctypes.c_int),
+        "mfs_tune_set": ([vp, i32, i32, i32, i32, i32], ctypes.c_int),
         "mfs_tune_save": ([ctypes.c_char_p], ctypes.c_int),
         "mfs_tune_load": ([ctypes.c_char_p], ctypes.c_int),
         "mfs_tune_clear": ([], ctypes.c_int),
@@ -396,14 +397,15 @@ def autotune(scene: Scene, R: int = 1, prec: int = MFS_MIXED, reps: int = 3, str
 
 
 def tune_get(scene: Scene, R: int = 1, prec: int = MFS_MIXED) -> dict:
-    nch, rt, src = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    _check(_lib.mfs_tune_get(scene.handle, int(R), int(prec), ctypes.byref(nch), ctypes.byref(rt), ctypes.byref(src)))
-    return {"nchunks": nch.value, "rhs_per_thread": rt.value,
+    nch, rt, sym, src = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.mfs_tune_get(scene.handle, int(R), int(prec), ctypes.byref(nch), ctypes.byref(rt), ctypes.byref(sym),
+                             ctypes.byref(src)))
+    return {"nchunks": nch.value, "rhs_per_thread": rt.value, "symmetric": sym.value,
             "source": {0: "heuristic", 1: "table", 2: "scene"}[src.value]}
 
 
-def tune_set(scene: Scene, R: int, prec: int, nchunks: int, rhs_per_thread: int = 0):
-    _check(_lib.mfs_tune_set(scene.handle, int(R), int(prec), int(nchunks), int(rhs_per_thread)))
+def tune_set(scene: Scene, R: int, prec: int, nchunks: int, rhs_per_thread: int = 0, symmetric: int = -1):
+    _check(_lib.mfs_tune_set(scene.handle, int(R), int(prec), int(nchunks), int(rhs_per_thread), int(symmetric)))
 
 
 def tune_save(path: str):

@@ -122,18 +122,19 @@ def test_launch_shape_table_round_trip_without_device(lib, tmp_path):
     mfs.tune_clear()
     assert mfs.tune_table_size() == 0
     good = tmp_path / "shapes.txt"
-    good.write_text("mfs-tune 1\n2 1 1 18 12 1\n2 2 64 18 8 0\n3 0 1 16 32 0\n")
+    good.write_text("mfs-tune 2\n2 1 1 18 12 1 0\n2 2 64 18 8 0 -1\n3 0 1 16 32 0 1\n")
     mfs.tune_load(str(good))
     assert mfs.tune_table_size() == 3
     saved = tmp_path / "saved.txt"
     mfs.tune_save(str(saved))
     lines = saved.read_text().splitlines()
-    assert lines[0] == "mfs-tune 1"
+    assert lines[0] == "mfs-tune 2"
     assert sorted(lines[1:]) == sorted(good.read_text().splitlines()[1:])
     # bad entries: nchunks out of range, bad rhs per thread, bad dim, bad variant, truncated line, no header
-    for body in ("mfs-tune 1\n2 1 1 18 2000 1\n", "mfs-tune 1\n2 1 1 18 12 3\n", "mfs-tune 1\n4 1 1 18 12 1\n",
-                 "mfs-tune 1\n2 7 1 18 12 1\n", "mfs-tune 1\n2 1 1 18 12\n", "2 1 1 18 12 1\n",
-                 "mfs-tune 1\n2 1 4 10 8 2\n2 1 0 10 8 2\n"):
+    for body in ("mfs-tune 2\n2 1 1 18 2000 1 0\n", "mfs-tune 2\n2 1 1 18 12 3 0\n", "mfs-tune 2\n4 1 1 18 12 1 0\n",
+                 "mfs-tune 2\n2 7 1 18 12 1 0\n", "mfs-tune 2\n2 1 1 18 12 1\n", "2 1 1 18 12 1 0\n",
+                 "mfs-tune 2\n2 1 4 10 8 2 0\n2 1 0 10 8 2 0\n", "mfs-tune 2\n2 1 1 18 12 1 2\n",
+                 "mfs-tune 1\n2 1 1 18 12 1 0\n"):
         bad = tmp_path / "bad.txt"
         bad.write_text(body)
         with pytest.raises(mfs.MfsError):
@@ -147,4 +148,4 @@ def test_launch_shape_table_round_trip_without_device(lib, tmp_path):
     mfs.tune_clear()
     assert mfs.tune_table_size() == 0
     assert lib.mfs_autotune(None, 1, 2, 1, None, None) == -1
-    assert lib.mfs_tune_set(None, 1, 2, 4, 0) == -1
+    assert lib.mfs_tune_set(None, 1, 2, 4, 0, -1) == -1

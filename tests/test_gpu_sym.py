@@ -1,0 +1,133 @@
+"""The symmetric one-right-hand-side pair kernel on the GPU against the FP64 oracle.
+
+With one right-hand side in FP32 and every body holding a multiple of 64 points, the operator
+evaluates phi once per unordered pair and adds it into both sums (G_hat is symmetric).  Its
+schedule (groups of 256 points meeting at cyclic distances, one-sided at distance 0 and G/2) has
+edge cases in the number of groups G: 1, 2 (both one-sided), odd and even G, a last group with
+fewer than four tiles, and every way of cutting the distances into chunks.  Each case is held to
+the oracle at the FP32 budget, and near body pairs exercise the Hankel branches below z = 100.
+"""
+
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle import global_system as gs, local_s
+from tests.gpu_helpers import crandn, fp32_matvec_budget, make_gpu_scene, rel_err, s_to_device
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture
+def mfs(gpu_lib):
+    gpu_lib.tune_clear()
+    yield gpu_lib
+    gpu_lib.tune_clear()
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _scene(mfs, sc):
+    Ss = [local_s.s_given_points(s, sc.kappa) for s in sc.shapes]
+    devs = [s_to_device(S) for S in Ss]
+    gsc = make_gpu_scene(mfs, sc, [d[0] for d in devs], [d[1] for d in devs])
+    gsc._S_hold = devs
+    return gsc, Ss
+
+
+def _ghat32(mfs, gsc, q):
+    torch = _torch()
+    t = torch.empty(q.shape, dtype=torch.complex64, device="cuda")
+    mfs.ghat_apply(gsc, torch.from_numpy(q.astype(np.complex64)).cuda(), t, mfs.MFS_FP32)
+    return t.cpu().numpy()
+
+
+def _disks(T):
+    """T disks of 64 equivalent points, the first T of a 4 x 4 grid of spacing 3 (kappa 5): near
+    body pairs, where the kernel takes the Hankel branches below z = 100."""
+    base = w.c1_disks16(T=16)
+    return w.Scene(dim=2, kappa=base.kappa, shapes=base.shapes, shape_of=np.zeros(T, np.int32),
+                   centres=base.centres[:T].copy(), directions=base.directions, name=f"disks{T}")
+
+
+def _starfish(T):
+    """T starfish (128 points) from the 2000-body scene, far apart (kappa 10)."""
+    return w.make_scene("starfish2000", T=T)
+
+
+def _spheres64(T):
+    sh = w.sphere3d(m=300, n=150, k=192, p=300)
+    centres = w.random_centres(T, 3, 9.0, 3.2, 4)
+    return w.Scene(dim=3, kappa=2.0, shapes=[sh], shape_of=np.zeros(T, np.int32), centres=centres,
+                   directions=np.array([[0.0, 0.0, 1.0]]), name="spheres192")
+
+
+CASES = [("disks", 1), ("disks", 3), ("disks", 4), ("disks", 5), ("disks", 8), ("disks", 9), ("disks", 13),
+         ("disks", 16), ("starfish", 2), ("starfish", 3), ("starfish", 7), ("starfish", 40),
+         ("spheres", 6)]
+
+
+@pytest.mark.parametrize("kind,T", CASES)
+def test_symmetric_kernel_matches_oracle(mfs, kind, T):
+    sc = {"disks": _disks, "starfish": _starfish, "spheres": _spheres64}[kind](T)
+    print(f"symmetric ghat {kind} T={T}", flush=True)
+    gsc, _ = _scene(mfs, sc)
+    assert mfs.tune_get(gsc, 1, mfs.MFS_FP32)["symmetric"] == 1  # the heuristic's choice here
+    xh, ptr, bo = gs.pack(sc)
+    q = crandn(np.random.default_rng(31), 1, xh.shape[0])
+    ref = gs.ghat_apply(xh, bo, sc.kappa, q)
+    budget = fp32_matvec_budget(sc)
+    sym = _ghat32(mfs, gsc, q)
+    assert rel_err(sym, ref) < budget
+    # the plain kernel on the same scene, for comparison
+    mfs.tune_set(gsc, 1, mfs.MFS_FP32, 4, 1, 0)
+    assert mfs.tune_get(gsc, 1, mfs.MFS_FP32)["symmetric"] == 0
+    plain = _ghat32(mfs, gsc, q)
+    assert rel_err(plain, ref) < budget
+    # every way of cutting the group distances into chunks gives the same operator
+    for nch in (1, 2, 3, 1024):
+        mfs.tune_set(gsc, 1, mfs.MFS_FP32, nch, 0, 1)
+        assert mfs.tune_get(gsc, 1, mfs.MFS_FP32)["symmetric"] == 1
+        assert rel_err(_ghat32(mfs, gsc, q), ref) < budget
+    gsc.close()
+
+
+def test_symmetric_kernel_is_deterministic_and_used_only_where_it_applies(mfs):
+    torch = _torch()
+    sc = _starfish(24)
+    gsc, Ss = _scene(mfs, sc)
+    mfs.tune_set(gsc, 1, mfs.MFS_FP32, 8, 0, 1)
+    assert mfs.tune_get(gsc, 1, mfs.MFS_FP32)["symmetric"] == 1
+    q = crandn(np.random.default_rng(32), 1, gsc.N)
+    a, b = _ghat32(mfs, gsc, q), _ghat32(mfs, gsc, q)
+    assert np.array_equal(a, b)
+    # two right-hand sides, FP64, or shapes whose point count is not a multiple of 64: plain kernels
+    for R, prec in ((2, mfs.MFS_FP32), (1, mfs.MFS_FP64)):
+        mfs.tune_set(gsc, R, prec, 8, 0, 1)
+        assert mfs.tune_get(gsc, R, prec)["symmetric"] == 0
+    other, _ = _scene(mfs, w.make_scene("spheres1000", T=3))
+    mfs.tune_set(other, 1, mfs.MFS_FP32, 8, 0, 1)
+    assert mfs.tune_get(other, 1, mfs.MFS_FP32)["symmetric"] == 0
+    other.close()
+    # the whole operator (S product reads the ~N/512 extra slices) against the oracle
+    xh, ptr, bo = gs.pack(sc)
+    ref = gs.matvec(sc, Ss, xh, ptr, bo, q)
+    y = torch.empty((1, gsc.N), dtype=torch.complex64, device="cuda")
+    mfs.apply(gsc, torch.from_numpy(q.astype(np.complex64)).cuda(), y, mfs.MFS_FP32)
+    assert rel_err(y.cpu().numpy(), ref) < fp32_matvec_budget(sc)
+    gsc.close()
+
+
+def test_autotune_considers_both_kernels(mfs):
+    sc = _starfish(64)
+    gsc, _ = _scene(mfs, sc)
+    res = mfs.autotune(gsc, R=1, prec=mfs.MFS_MIXED, reps=2)
+    assert res["ms_plain"] > 0 and res["n_tried"] >= 6
+    got = mfs.tune_get(gsc, 1, mfs.MFS_MIXED)
+    assert got["symmetric"] == res["symmetric"] and got["source"] == "scene"
+    print("autotune starfish64:", res, flush=True)
+    gsc.close()

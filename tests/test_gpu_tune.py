@@ -86,7 +86,8 @@ def test_mixed_tuning_and_rhs_per_thread_variants(mfs):
     outs = []
     for rt in (1, 2, 4):
         mfs.tune_set(gsc, R, mfs.MFS_FP32, 6, rt)
-        assert mfs.tune_get(gsc, R, mfs.MFS_FP32) == {"nchunks": 6, "rhs_per_thread": rt, "source": "scene"}
+        assert mfs.tune_get(gsc, R, mfs.MFS_FP32) == {"nchunks": 6, "rhs_per_thread": rt, "symmetric": 0,
+                                                      "source": "scene"}
         outs.append(_apply(mfs, gsc, q, mfs.MFS_FP32))
         assert rel_err(outs[-1], ref) < fp32_matvec_budget(sc)
     for o in outs[1:]:
