@@ -335,19 +335,19 @@ mfs_status mfs_pool_trim(void);
  * The pair sum splits the sources seen by every block of targets into `nchunks` slices (more
  * slices: more blocks in flight on a small system, but more partial sums for the S product to
  * read back), and on the VALU kernel each thread carries `rhs_per_thread` right-hand sides (1, 2
- * or 4; the matrix-core kernel used for 8 or more right-hand sides has no such knob).  With one
- * right-hand side, FP32, and every body holding a multiple of 64 points, a symmetric kernel can
+ * or 4; the matrix-core kernel used for 8 or more right-hand sides has no such knob).  With 1 to 7
+ * right-hand sides, FP32, and every body holding a multiple of 64 points, a symmetric kernel can
  * run instead: G_hat is symmetric, so it evaluates phi once per unordered pair of points and adds
  * it into both sums; there `nchunks` counts the chunks of group distances per target group, and
- * the kernel leaves about N / 512 further partial slices (at most 8 GiB of them, else the plain
- * kernel runs).  A scene uses, in this order: its own tuned shape for (precision, R); the
+ * the kernel leaves about N / 512 further partial slices per right-hand side (at most 8 GiB of
+ * them, else the plain kernel runs).  A scene uses, in this order: its own tuned shape for (precision, R); the
  * process-wide table, keyed by (dim, kernel, R, floor(log2 N)); the heuristic (the symmetric
  * kernel where it applies).  Slices are summed in a fixed order, so a given shape gives
  * reproducible results; another shape may change the last bits of the sums.
  * ------------------------------------------------------------------------------------------ */
 typedef struct {
   int32_t nchunks;         /* chosen source slices (distance chunks if symmetric) */
-  int32_t rhs_per_thread;  /* chosen right-hand sides per thread (plain VALU kernel), 0 otherwise */
+  int32_t rhs_per_thread;  /* chosen right-hand sides per thread (VALU kernels), 0 otherwise */
   double ms;               /* time of one operator application with the chosen shape */
   double ms_heuristic;     /* the same with the untuned shape */
   int32_t n_tried;         /* shapes timed */
@@ -365,8 +365,8 @@ typedef struct {
 mfs_status mfs_autotune(mfs_scene* scene, int32_t R, mfs_prec prec, int32_t reps, mfs_tune_result* out,
                         void* stream);
 
-/* The launch shape the scene will use for (R, prec): nchunks, rhs_per_thread (0 for the FP64,
- * matrix-core and symmetric kernels), symmetric (1 if the symmetric kernel runs) and where the
+/* The launch shape the scene will use for (R, prec): nchunks, rhs_per_thread (0 for the FP64 and
+ * matrix-core kernels), symmetric (1 if the symmetric kernel runs) and where the
  * shape comes from (2 = the scene's own, 1 = the process-wide table, 0 = the heuristic).  Host
  * outputs may be NULL. */
 mfs_status mfs_tune_get(const mfs_scene* scene, int32_t R, mfs_prec prec, int32_t* nchunks,

@@ -115,6 +115,8 @@ struct mfs_scene {
   hipStream_t last_stream = nullptr;  // stream of the latest call; releases are ordered after it
   // owned tables
   Buf x64, x32, l32, lsq, centres, body_of, body_ptr, shape_of, k_dev, S64_tab, S32_tab, rot;
+  // padded layout for the symmetric pair kernel (bodies whose point count is not a multiple of 64)
+  Buf pad_ptr, body_of_pad, l32p, lsqp, qpad;
   // workspaces
   Buf partial, q32, dirs, kry, vecs;
   // near-field tables for the last set of reconstruction factors used with this scene
@@ -183,7 +185,7 @@ LaunchShape shape_for(const mfs_scene* s, bool f64, int R, int* source = nullptr
   if (sym_ok && e.sym != 0) {
     ls.sym = 1;
     // a slice count tuned for the other kernel does not carry over
-    if (e.sym != 1 || e.nchunks <= 0) ls.nchunks = sym_plan(s->dev.N, 0).nchunks_d;
+    if (e.sym != 1 || e.nchunks <= 0) ls.nchunks = sym_plan(sym_view(s->dev).N, 0).nchunks_d;
   } else {
     ls.sym = 0;
     if (e.sym == 1 || e.nchunks <= 0) ls.nchunks = pair_chunks_for(s->dev.N, s->dev.N, tpt_for(f64 ? MFS_FP64 : MFS_FP32));
@@ -191,14 +193,47 @@ LaunchShape shape_for(const mfs_scene* s, bool f64, int R, int* source = nullptr
   return ls;
 }
 
-// Partial-sum slices the FP32 pair sum writes with this shape.
-int f32_slices(const mfs_scene* s, const LaunchShape& ls) {
-  return ls.sym == 1 ? sym_plan(s->dev.N, ls.nchunks).slices : ls.nchunks;
+// Rows of a partial-sum slice with this shape: the padded layout's length for the symmetric kernel
+// on bodies that are not whole tiles, else N.
+int64_t f32_rows(const mfs_scene* s, const LaunchShape& ls) {
+  return ls.sym == 1 && !s->dev.all_k_mult64 ? s->dev.Npad : s->dev.N;
 }
 
-hipError_t launch_f32(const mfs_scene* s, const c64* q, int R, c64* part, const LaunchShape& ls, hipStream_t st) {
-  if (ls.sym == 1) return launch_ghat_f32_sym(s->dev, q, part, ls.nchunks, st);
-  return launch_ghat_f32(s->dev, q, R, part, ls.nchunks, st, ls.rt);
+// Partial-sum slices the FP32 pair sum writes with this shape.
+int f32_slices(const mfs_scene* s, const LaunchShape& ls) {
+  return ls.sym == 1 ? sym_plan(f32_rows(s, ls), ls.nchunks).slices : ls.nchunks;
+}
+
+// Where the FP32 pair sum left its partial sums: `slices` slices of R rows of NP entries, body b's
+// entries from pptr[b] (pptr null: the packed layout).
+struct PartialF32 {
+  c64* part;
+  int slices;
+  const int64_t* pptr;
+  int64_t NP;
+};
+
+// The FP32 pair sum of q32 ([R][N] complex64) into the scene's partial buffer.
+mfs_status pair_f32(mfs_scene* s, const c64* q32, int R, hipStream_t st, PartialF32* out) {
+  const LaunchShape ls = shape_for(s, false, R);
+  const bool padded = ls.sym == 1 && !s->dev.all_k_mult64;
+  const int64_t rows = f32_rows(s, ls);
+  const int nch = f32_slices(s, ls);
+  MFS_TRY(ensure(s->partial, (size_t)nch * R * rows * sizeof(c64), &s->bytes, st));
+  c64* part = static_cast<c64*>(s->partial.p);
+  const c64* qs = q32;
+  if (padded) {
+    MFS_TRY(ensure(s->qpad, (size_t)R * rows * sizeof(c64), &s->bytes, st));
+    MFS_HIP_TRY(launch_gather_pad(s->dev, q32, R, static_cast<c64*>(s->qpad.p), st));
+    qs = static_cast<c64*>(s->qpad.p);
+  }
+  {
+    TimedLaunch tl(MFS_KERNEL_PAIR_F32, s->dev.offbody_pairs * R, st);
+    if (ls.sym == 1) MFS_HIP_TRY(launch_ghat_f32_sym(sym_view(s->dev), qs, R, part, ls.nchunks, ls.rt, st));
+    else MFS_HIP_TRY(launch_ghat_f32(s->dev, q32, R, part, ls.nchunks, st, ls.rt));
+  }
+  *out = PartialF32{part, nch, padded ? s->dev.pad_ptr : nullptr, padded ? rows : 0};
+  return MFS_OK;
 }
 
 // y = q + S G_hat q in FP64 (all operands complex128).
@@ -216,15 +251,9 @@ mfs_status apply_f64(mfs_scene* s, const c128* q, c128* y, int R, hipStream_t st
 
 // y = q + S G_hat q in FP32 (complex64 in and out).
 mfs_status apply_f32(mfs_scene* s, const c64* q, c64* y, int R, hipStream_t st) {
-  const LaunchShape ls = shape_for(s, false, R);
-  const int nch = f32_slices(s, ls);
-  MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c64), &s->bytes, st));
-  c64* part = static_cast<c64*>(s->partial.p);
-  {
-    TimedLaunch tl(MFS_KERNEL_PAIR_F32, s->dev.offbody_pairs * R, st);
-    MFS_HIP_TRY(launch_f32(s, q, R, part, ls, st));
-  }
-  MFS_HIP_TRY(launch_sapply_f32(s->dev, part, nch, q, 1.0f, y, R, (int)s->kmax, st));
+  PartialF32 p;
+  MFS_TRY(pair_f32(s, q, R, st, &p));
+  MFS_HIP_TRY(launch_sapply_f32(s->dev, p.part, p.slices, q, 1.0f, y, R, (int)s->kmax, st, p.pptr, p.NP));
   return MFS_OK;
 }
 
@@ -233,17 +262,11 @@ mfs_status apply_f32(mfs_scene* s, const c64* q, c64* y, int R, hipStream_t st) 
 mfs_status apply_mixed(mfs_scene* s, const c128* q, c128* y, int R, hipStream_t st, double beta = 1.0) {
   const int64_t NR = s->dev.N * R;
   MFS_TRY(ensure(s->q32, (size_t)NR * sizeof(c64), &s->bytes, st));
-  const LaunchShape ls = shape_for(s, false, R);
-  const int nch = f32_slices(s, ls);
-  MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c64), &s->bytes, st));
   c64* q32 = static_cast<c64*>(s->q32.p);
-  c64* part = static_cast<c64*>(s->partial.p);
   MFS_HIP_TRY(launch_to_c64(q, q32, NR, st));
-  {
-    TimedLaunch tl(MFS_KERNEL_PAIR_F32, s->dev.offbody_pairs * R, st);
-    MFS_HIP_TRY(launch_f32(s, q32, R, part, ls, st));
-  }
-  MFS_HIP_TRY(launch_sapply_mixed(s->dev, part, nch, q, beta, y, R, (int)s->kmax, st));
+  PartialF32 p;
+  MFS_TRY(pair_f32(s, q32, R, st, &p));
+  MFS_HIP_TRY(launch_sapply_mixed(s->dev, p.part, p.slices, q, beta, y, R, (int)s->kmax, st, p.pptr, p.NP));
   return MFS_OK;
 }
 
@@ -334,15 +357,9 @@ mfs_status prepare_near(mfs_scene* s, const mfs_recon* const* recon, hipStream_t
 }
 // y = S G_hat q with q already complex64 (a single-precision Krylov basis vector) and y complex128.
 mfs_status apply_mixed_from32(mfs_scene* s, const c64* q32, c128* y, int R, hipStream_t st) {
-  const LaunchShape ls = shape_for(s, false, R);
-  const int nch = f32_slices(s, ls);
-  MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c64), &s->bytes, st));
-  c64* part = static_cast<c64*>(s->partial.p);
-  {
-    TimedLaunch tl(MFS_KERNEL_PAIR_F32, s->dev.offbody_pairs * R, st);
-    MFS_HIP_TRY(launch_f32(s, q32, R, part, ls, st));
-  }
-  MFS_HIP_TRY(launch_sapply_mixed(s->dev, part, nch, nullptr, 0.0, y, R, (int)s->kmax, st));
+  PartialF32 p;
+  MFS_TRY(pair_f32(s, q32, R, st, &p));
+  MFS_HIP_TRY(launch_sapply_mixed(s->dev, p.part, p.slices, nullptr, 0.0, y, R, (int)s->kmax, st, p.pptr, p.NP));
   return MFS_OK;
 }
 
@@ -517,14 +534,46 @@ mfs_status mfs_scene_create(int32_t dim, double kappa, int64_t T, const int32_t*
     d.all_k_mult16 = d.all_k_mult16 && (k_of_shape[s2] % 16 == 0);
     d.all_k_mult64 = d.all_k_mult64 && (k_of_shape[s2] % 64 == 0);
   }
+  d.Npad = N;
+  d.pad_ptr = nullptr;
+  d.body_of_pad = nullptr;
+  d.lsqp = nullptr;
+  for (int i = 0; i < 3; ++i) d.l32p[i] = nullptr;
+  if (!d.all_k_mult64) {
+    // bodies padded to whole 64-point tiles, made only where the symmetric kernel would pay
+    std::vector<int64_t> pad_ptr(T + 1, 0);
+    for (int64_t t = 0; t < T; ++t) pad_ptr[t + 1] = pad_ptr[t] + (body_ptr[t + 1] - body_ptr[t] + 63) / 64 * 64;
+    const int64_t NP = pad_ptr[T];
+    if ((double)NP * (double)NP <= 1.4 * (double)N * (double)N && NP <= 0x7fffffff) {
+      std::vector<int32_t> body_of_pad(NP);
+      for (int64_t t = 0; t < T; ++t)
+        for (int64_t i = pad_ptr[t]; i < pad_ptr[t + 1]; ++i) body_of_pad[i] = (int32_t)t;
+      if ((st = ensure(sc->pad_ptr, sizeof(int64_t) * (T + 1), &sc->bytes, ps)) != MFS_OK) return cleanup(st);
+      if ((st = ensure(sc->body_of_pad, sizeof(int32_t) * NP, &sc->bytes, ps)) != MFS_OK) return cleanup(st);
+      if ((st = ensure(sc->l32p, sizeof(float) * dim * NP, &sc->bytes, ps)) != MFS_OK) return cleanup(st);
+      if ((st = ensure(sc->lsqp, sizeof(float) * NP, &sc->bytes, ps)) != MFS_OK) return cleanup(st);
+      d.Npad = NP;
+      d.pad_ptr = static_cast<int64_t*>(sc->pad_ptr.p);
+      d.body_of_pad = static_cast<int32_t*>(sc->body_of_pad.p);
+      d.lsqp = static_cast<float*>(sc->lsqp.p);
+      for (int i = 0; i < dim; ++i) d.l32p[i] = static_cast<float*>(sc->l32p.p) + (size_t)i * NP;
+      cp(sc->pad_ptr.p, pad_ptr.data(), sizeof(int64_t) * (T + 1));
+      cp(sc->body_of_pad.p, body_of_pad.data(), sizeof(int32_t) * NP);
+      if (e == hipSuccess) e = launch_pad_scene(d, static_cast<float*>(sc->l32p.p), static_cast<float*>(sc->lsqp.p), ps);
+      if (e == hipSuccess) e = hipStreamSynchronize(ps);  // the host tables are released on return
+      if (e != hipSuccess) return cleanup(fail(MFS_ERR_HIP, std::string("scene padding: ") + hipGetErrorString(e)));
+    }
+  }
   *out = sc;
   return MFS_OK;
 }
 
 mfs_status mfs_scene_destroy(mfs_scene* s) {
   if (!s) return MFS_OK;
-  Buf* all[] = {&s->x64, &s->x32, &s->l32, &s->lsq, &s->centres, &s->body_of, &s->body_ptr, &s->shape_of, &s->k_dev, &s->S64_tab,
-                &s->S32_tab, &s->rot, &s->partial, &s->q32, &s->dirs, &s->kry, &s->vecs, &s->near_tab};
+  Buf* all[] = {&s->x64,     &s->x32,     &s->l32,      &s->lsq,     &s->centres,    &s->body_of,
+                &s->body_ptr, &s->shape_of, &s->k_dev,   &s->S64_tab, &s->S32_tab,    &s->rot,
+                &s->partial,  &s->q32,      &s->dirs,    &s->kry,     &s->vecs,       &s->near_tab,
+                &s->pad_ptr,  &s->body_of_pad, &s->l32p, &s->lsqp,    &s->qpad};
   for (Buf* b : all) release(*b, &s->bytes, s->last_stream);
   delete s;
   return MFS_OK;
@@ -571,9 +620,8 @@ mfs_status mfs_ghat_apply(const mfs_scene* sc, const void* q_dev, void* t_dev, i
   mfs_scene* s = const_cast<mfs_scene*>(sc);
   hipStream_t st = as_stream(stream);
   s->last_stream = st;
-  const LaunchShape ls = shape_for(s, prec == MFS_FP64, R);
-  const int nch = prec == MFS_FP64 ? ls.nchunks : f32_slices(s, ls);
   if (prec == MFS_FP64) {
+    const int nch = shape_for(s, true, R).nchunks;
     MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c128), &s->bytes, st));
     c128* part = static_cast<c128*>(s->partial.p);
     {
@@ -582,13 +630,10 @@ mfs_status mfs_ghat_apply(const mfs_scene* sc, const void* q_dev, void* t_dev, i
     }
     MFS_HIP_TRY(launch_reduce_partials_f64(part, nch, s->dev.N, R, static_cast<c128*>(t_dev), st));
   } else {
-    MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c64), &s->bytes, st));
-    c64* part = static_cast<c64*>(s->partial.p);
-    {
-      TimedLaunch tl(MFS_KERNEL_PAIR_F32, s->dev.offbody_pairs * R, st);
-      MFS_HIP_TRY(launch_f32(s, static_cast<const c64*>(q_dev), R, part, ls, st));
-    }
-    MFS_HIP_TRY(launch_reduce_partials_f32(part, nch, s->dev.N, R, static_cast<c64*>(t_dev), st));
+    PartialF32 p;
+    MFS_TRY(pair_f32(s, static_cast<const c64*>(q_dev), R, st, &p));
+    if (p.pptr) MFS_HIP_TRY(launch_reduce_partials_padded(s->dev, p.part, p.slices, R, static_cast<c64*>(t_dev), st));
+    else MFS_HIP_TRY(launch_reduce_partials_f32(p.part, p.slices, s->dev.N, R, static_cast<c64*>(t_dev), st));
   }
   return MFS_OK;
 }
@@ -1168,10 +1213,14 @@ mfs_status mfs_autotune(mfs_scene* s, int32_t R, mfs_prec prec, int32_t reps, mf
     }
   };
   if (sym_ok) {
-    const SymPlan hp = sym_plan(N, 0);
+    const int64_t NS = sym_view(s->dev).N;
+    const SymPlan hp = sym_plan(NS, 0);
+    std::vector<int> rset{h_rt};
+    for (int rt : {1, 2, 4})
+      if (rt != h_rt && (rt == 1 || rt / 2 < R)) rset.push_back(rt);
     for (int f : {0, -2, -1, 1, 2}) {
       const int c = f < 0 ? (hp.nchunks_d >> -f) : (hp.nchunks_d << f);
-      add(LaunchShape{sym_plan(N, std::max(1, std::min(c, kTuneMaxChunks))).nchunks_d, 0, 1});
+      for (int rt : rset) add(LaunchShape{sym_plan(NS, std::max(1, std::min(c, kTuneMaxChunks))).nchunks_d, rt, 1});
     }
   }
   plain();
@@ -1235,7 +1284,8 @@ mfs_status mfs_autotune(mfs_scene* s, int32_t R, mfs_prec prec, int32_t reps, mf
   s->tuned[key] = best_ls;
   tune_store(s->dev.dim, v, R, N, best_ls);
   // the largest candidate may have grown the partial-sum buffer well past what the winner needs
-  const size_t need = (size_t)(f64 ? best_ls.nchunks : f32_slices(s, best_ls)) * R * N * part_elem;
+  const size_t need = f64 ? (size_t)best_ls.nchunks * R * N * part_elem
+                          : (size_t)f32_slices(s, best_ls) * R * f32_rows(s, best_ls) * part_elem;
   if (s->partial.cap > 2 * need) release(s->partial, &s->bytes, st);
   res.nchunks = best_ls.nchunks;
   res.rhs_per_thread = best_ls.rt;
@@ -1258,7 +1308,7 @@ mfs_status mfs_tune_get(const mfs_scene* s, int32_t R, mfs_prec prec, int32_t* n
   int src = 0;
   const LaunchShape ls = shape_for(s, f64, R, &src);
   if (nchunks) *nchunks = ls.nchunks;
-  if (rhs_per_thread) *rhs_per_thread = v == kTunePairF32 && ls.sym != 1 ? (ls.rt ? ls.rt : ghat_default_rt(R)) : 0;
+  if (rhs_per_thread) *rhs_per_thread = v == kTunePairF32 ? (ls.rt ? ls.rt : ghat_default_rt(R)) : 0;
   if (symmetric) *symmetric = ls.sym == 1 ? 1 : 0;
   if (source) *source = src;
   return MFS_OK;

@@ -51,6 +51,15 @@ struct SceneDev {
   double offbody_pairs;           // N^2 - sum_tau k_tau^2
   bool all_k_mult16;              // every shape has a multiple of 16 points (matrix-core path)
   bool all_k_mult64;              // every shape has a multiple of 64 points (symmetric pair kernel)
+  // Padded layout for the symmetric kernel when some shape's point count is not a multiple of 64:
+  // body b occupies [pad_ptr[b], pad_ptr[b+1]) with its points first and zero-charge fillers at its
+  // centre after them.  Npad = N and null tables when every count is a multiple of 64 (or no
+  // padding was made).
+  int64_t Npad;
+  const int64_t* pad_ptr;         // [T+1]
+  const int32_t* body_of_pad;     // [Npad]
+  const float* l32p[3];           // [Npad] body-local offsets, 0 for fillers
+  const float* lsqp;              // [Npad]
   double rho_max;                 // largest |x_hat - c_body| over all shapes
   const double* rot;              // [T][dim][dim] body orientations (row-major), or null: identity
 };
@@ -65,7 +74,7 @@ bool ghat_uses_mfma(const SceneDev& s, int R);
 // rt: right-hand sides per thread of the VALU kernel (1, 2 or 4; anything else picks by R);
 // ignored where the matrix-core kernel runs.
 int ghat_default_rt(int R);
-// Symmetric one-right-hand-side pair kernel: groups of 256 points, G groups, distances 0..Dmax,
+// Symmetric pair kernel (1 to 7 right-hand sides): groups of 256 points, G groups, distances 0..Dmax,
 // nchunks_d distance chunks of dpc each; it writes `slices` partial slices (nchunks_d target-side,
 // Dsym source-side).  nchunks_d <= 0 picks the heuristic.
 struct SymPlan {
@@ -75,7 +84,13 @@ struct SymPlan {
 };
 SymPlan sym_plan(int64_t N, int nchunks_d);
 bool ghat_sym_possible(const SceneDev& s, int R);
-hipError_t launch_ghat_f32_sym(const SceneDev& s, const c64* q, c64* partial, int nchunks_d, hipStream_t st);
+hipError_t launch_ghat_f32_sym(const SceneDev& s, const c64* q, int R, c64* partial, int nchunks_d, int rt,
+                               hipStream_t st);
+// The symmetric kernel's view of a scene: the scene itself, or its padded layout (N = Npad).
+SceneDev sym_view(const SceneDev& s);
+// t[r][i] = sum_c partial[c][r][pad(i)] for the padded layout.
+hipError_t launch_reduce_partials_padded(const SceneDev& s, const c64* partial, int nchunks, int R, c64* out,
+                                         hipStream_t st);
 hipError_t launch_ghat_f32(const SceneDev& s, const c64* q, int R, c64* partial, int nchunks,
                            hipStream_t st, int rt = 0);
 hipError_t launch_ghat_f64(const SceneDev& s, const c128* q, int R, c128* partial, int nchunks,
@@ -93,12 +108,18 @@ hipError_t launch_reduce_partials_f64(const c128* partial, int nchunks, int64_t 
 
 // Block-diagonal S (sapply.hip): y = beta q + S t, t = sum over chunks of partial.
 // TQ is the type of q and y; the S factors and partials are in the operator precision.
+// The S products read the pair sums at partial[c][r][pptr[body] + j] (rows of NP entries);
+// pptr = null means the packed layout (body_ptr, N).
 hipError_t launch_sapply_f64(const SceneDev& s, const c128* partial, int nchunks, const c128* q, double beta,
                              c128* y, int R, int kmax, hipStream_t st);
 hipError_t launch_sapply_f32(const SceneDev& s, const c64* partial, int nchunks, const c64* q, float beta,
-                             c64* y, int R, int kmax, hipStream_t st);
+                             c64* y, int R, int kmax, hipStream_t st, const int64_t* pptr = nullptr, int64_t NP = 0);
 hipError_t launch_sapply_mixed(const SceneDev& s, const c64* partial, int nchunks, const c128* q, double beta,
-                               c128* y, int R, int kmax, hipStream_t st);
+                               c128* y, int R, int kmax, hipStream_t st, const int64_t* pptr = nullptr,
+                               int64_t NP = 0);
+// Padded layout: fill the padded offsets (pad_scene) and gather charges into it (zero for fillers).
+hipError_t launch_pad_scene(const SceneDev& s, float* l32p, float* lsqp, hipStream_t st);
+hipError_t launch_gather_pad(const SceneDev& s, const c64* q, int R, c64* qp, hipStream_t st);
 
 // Elementwise helpers (sapply.hip).
 hipError_t launch_to_c64(const c128* in, c64* out, int64_t n, hipStream_t st);

@@ -498,11 +498,11 @@ __global__ __launch_bounds__(kBlock) void ghat_bodyphase_kernel(
 constexpr int kSymTiles = 4;                 // target tiles per wave
 constexpr int kSymGroup = 64 * kSymTiles;    // points per group
 
-template <int DIM>
+template <int DIM, int RT>
 struct SymLds {
   float l[DIM][128];
   float bs[128];
-  float qr[128], qi[128];
+  float qr[RT][128], qi[RT][128];
 };
 
 // lane l receives lane (l + 1) mod 64's value
@@ -511,14 +511,15 @@ __device__ __forceinline__ float wave_rotate_next(float x) {
 }
 
 // All four target tiles against the staged source tile, every pair in the z >= 100 regime (the
-// common case): one pass over the 64 steps, phi of each (target, source) used twice.
-template <int DIM, bool SYM>
-__device__ __forceinline__ void sym_steps4(const SymLds<DIM>& sh, const BodyPhaseConsts& k, int lane,
+// common case): one pass over the 64 steps, phi of each (target, source) used for both sums of
+// each of the RT right-hand sides.
+template <int DIM, int RT, bool SYM>
+__device__ __forceinline__ void sym_steps4(const SymLds<DIM, RT>& sh, const BodyPhaseConsts& k, int lane,
                                            const float (&A)[kSymTiles], const float (&P)[kSymTiles][DIM],
                                            const float (&D)[kSymTiles], const float (&D2)[kSymTiles],
-                                           const float (&ph0)[kSymTiles], const float (&qtr)[kSymTiles],
-                                           const float (&qti)[kSymTiles], float (&tr)[kSymTiles],
-                                           float (&ti)[kSymTiles], float& ar, float& ai) {
+                                           const float (&ph0)[kSymTiles], const float (&qtr)[kSymTiles][RT],
+                                           const float (&qti)[kSymTiles][RT], float (&tr)[kSymTiles][RT],
+                                           float (&ti)[kSymTiles][RT], float (&ar)[RT], float (&ai)[RT]) {
   for (int s0 = 0; s0 < 64; s0 += 8) {
     const int e0 = lane + s0;
 #pragma unroll
@@ -528,8 +529,14 @@ __device__ __forceinline__ void sym_steps4(const SymLds<DIM>& sh, const BodyPhas
 #pragma unroll
       for (int d = 0; d < DIM; ++d) ls[d] = sh.l[d][e];
       const float bs = sh.bs[e];
-      const float qr = sh.qr[e], qi = sh.qi[e];
-      float sr = ar, si = ai;
+      float qr[RT], qi[RT], sr[RT], si[RT];
+#pragma unroll
+      for (int rr = 0; rr < RT; ++rr) {
+        qr[rr] = sh.qr[rr][e];
+        qi[rr] = sh.qi[rr][e];
+        sr[rr] = ar[rr];
+        si[rr] = ai[rr];
+      }
 #pragma unroll
       for (int m = 0; m < kSymTiles; ++m) {
         float u = A[m] + bs;
@@ -537,16 +544,22 @@ __device__ __forceinline__ void sym_steps4(const SymLds<DIM>& sh, const BodyPhas
         for (int d = 0; d < DIM; ++d) u = fmaf(P[m][d], ls[d], u);
         float pr, pi;
         bp_phi<DIM, 2>(k, u, D[m], D2[m], ph0[m], pr, pi);
-        tr[m] = fmaf(pr, qr, fmaf(-pi, qi, tr[m]));
-        ti[m] = fmaf(pr, qi, fmaf(pi, qr, ti[m]));
-        if constexpr (SYM) {
-          sr = fmaf(pr, qtr[m], fmaf(-pi, qti[m], sr));
-          si = fmaf(pr, qti[m], fmaf(pi, qtr[m], si));
+#pragma unroll
+        for (int rr = 0; rr < RT; ++rr) {
+          tr[m][rr] = fmaf(pr, qr[rr], fmaf(-pi, qi[rr], tr[m][rr]));
+          ti[m][rr] = fmaf(pr, qi[rr], fmaf(pi, qr[rr], ti[m][rr]));
+          if constexpr (SYM) {
+            sr[rr] = fmaf(pr, qtr[m][rr], fmaf(-pi, qti[m][rr], sr[rr]));
+            si[rr] = fmaf(pr, qti[m][rr], fmaf(pi, qtr[m][rr], si[rr]));
+          }
         }
       }
       if constexpr (SYM) {
-        ar = wave_rotate_next(sr);
-        ai = wave_rotate_next(si);
+#pragma unroll
+        for (int rr = 0; rr < RT; ++rr) {
+          ar[rr] = wave_rotate_next(sr[rr]);
+          ai[rr] = wave_rotate_next(si[rr]);
+        }
       }
     }
   }
@@ -555,10 +568,11 @@ __device__ __forceinline__ void sym_steps4(const SymLds<DIM>& sh, const BodyPhas
 // One target tile against the staged source tile, with the Hankel branch set FAR (any regime):
 // the rare cases (near body pairs, partly filled or same-body tiles), kept lean in registers.
 // 64 rotations bring the source-side sums back to their own lanes, so passes can follow each other.
-template <int DIM, bool SYM, int FAR>
-__device__ __forceinline__ void sym_steps1(const SymLds<DIM>& sh, const BodyPhaseConsts& k, int lane, float A,
-                                           const float (&P)[DIM], float D, float D2, float ph0, float qtr,
-                                           float qti, float& tr, float& ti, float& ar, float& ai) {
+template <int DIM, int RT, bool SYM, int FAR>
+__device__ __forceinline__ void sym_steps1(const SymLds<DIM, RT>& sh, const BodyPhaseConsts& k, int lane, float A,
+                                           const float (&P)[DIM], float D, float D2, float ph0,
+                                           const float (&qtr)[RT], const float (&qti)[RT], float (&tr)[RT],
+                                           float (&ti)[RT], float (&ar)[RT], float (&ai)[RT]) {
   for (int s0 = 0; s0 < 64; s0 += 8) {
     const int e0 = lane + s0;
 #pragma unroll
@@ -569,62 +583,76 @@ __device__ __forceinline__ void sym_steps1(const SymLds<DIM>& sh, const BodyPhas
       for (int d = 0; d < DIM; ++d) u = fmaf(P[d], sh.l[d][e], u);
       float pr, pi;
       bp_phi<DIM, FAR>(k, u, D, D2, ph0, pr, pi);
-      const float qr = sh.qr[e], qi = sh.qi[e];
-      tr = fmaf(pr, qr, fmaf(-pi, qi, tr));
-      ti = fmaf(pr, qi, fmaf(pi, qr, ti));
-      if constexpr (SYM) {
-        ar = wave_rotate_next(fmaf(pr, qtr, fmaf(-pi, qti, ar)));
-        ai = wave_rotate_next(fmaf(pr, qti, fmaf(pi, qtr, ai)));
+#pragma unroll
+      for (int rr = 0; rr < RT; ++rr) {
+        const float qr = sh.qr[rr][e], qi = sh.qi[rr][e];
+        tr[rr] = fmaf(pr, qr, fmaf(-pi, qi, tr[rr]));
+        ti[rr] = fmaf(pr, qi, fmaf(pi, qr, ti[rr]));
+        if constexpr (SYM) {
+          ar[rr] = wave_rotate_next(fmaf(pr, qtr[rr], fmaf(-pi, qti[rr], ar[rr])));
+          ai[rr] = wave_rotate_next(fmaf(pr, qti[rr], fmaf(pi, qtr[rr], ai[rr])));
+        }
       }
     }
   }
 }
 
-template <int DIM, bool SYM>
-__device__ __forceinline__ void sym_tile(const SymLds<DIM>& sh, const BodyPhaseConsts& k, int lane,
+template <int DIM, int RT, bool SYM>
+__device__ __forceinline__ void sym_tile(const SymLds<DIM, RT>& sh, const BodyPhaseConsts& k, int lane,
                                          const bool (&use)[kSymTiles], const float (&A)[kSymTiles],
                                          const float (&P)[kSymTiles][DIM], const float (&D)[kSymTiles],
                                          const float (&D2)[kSymTiles], const float (&ph0)[kSymTiles],
-                                         const float (&qtr)[kSymTiles], const float (&qti)[kSymTiles],
-                                         float (&tr)[kSymTiles], float (&ti)[kSymTiles], float& ar, float& ai) {
+                                         const float (&qtr)[kSymTiles][RT], const float (&qti)[kSymTiles][RT],
+                                         float (&tr)[kSymTiles][RT], float (&ti)[kSymTiles][RT], float (&ar)[RT],
+                                         float (&ai)[RT]) {
   bool fast = true;
 #pragma unroll
   for (int m = 0; m < kSymTiles; ++m) fast = fast && use[m] && (DIM == 3 || D[m] >= k.vfar_D);
   if (fast) {
-    sym_steps4<DIM, SYM>(sh, k, lane, A, P, D, D2, ph0, qtr, qti, tr, ti, ar, ai);
+    sym_steps4<DIM, RT, SYM>(sh, k, lane, A, P, D, D2, ph0, qtr, qti, tr, ti, ar, ai);
     return;
   }
 #pragma unroll
   for (int m = 0; m < kSymTiles; ++m) {
     if (!use[m]) continue;
     if (DIM == 3 || D[m] >= k.vfar_D)
-      sym_steps1<DIM, SYM, 2>(sh, k, lane, A[m], P[m], D[m], D2[m], ph0[m], qtr[m], qti[m], tr[m], ti[m], ar, ai);
+      sym_steps1<DIM, RT, SYM, 2>(sh, k, lane, A[m], P[m], D[m], D2[m], ph0[m], qtr[m], qti[m], tr[m], ti[m], ar, ai);
     else if (D[m] >= k.far_D)
-      sym_steps1<DIM, SYM, 1>(sh, k, lane, A[m], P[m], D[m], D2[m], ph0[m], qtr[m], qti[m], tr[m], ti[m], ar, ai);
+      sym_steps1<DIM, RT, SYM, 1>(sh, k, lane, A[m], P[m], D[m], D2[m], ph0[m], qtr[m], qti[m], tr[m], ti[m], ar, ai);
     else
-      sym_steps1<DIM, SYM, 0>(sh, k, lane, A[m], P[m], D[m], D2[m], ph0[m], qtr[m], qti[m], tr[m], ti[m], ar, ai);
+      sym_steps1<DIM, RT, SYM, 0>(sh, k, lane, A[m], P[m], D[m], D2[m], ph0[m], qtr[m], qti[m], tr[m], ti[m], ar, ai);
   }
 }
 
-template <int DIM>
-__global__ __launch_bounds__(64, 4) void ghat_sym_kernel(
+// Occupancy target per right-hand-side grouping: the register file holds 4, 3 or 2 waves per SIMD.
+template <int RT>
+struct SymWaves {
+  static constexpr int value = RT == 1 ? 4 : (RT == 2 ? 3 : 2);
+};
+
+template <int DIM, int RT>
+__global__ __launch_bounds__(64, SymWaves<RT>::value) void ghat_sym_kernel(
     BodyPhaseConsts k, const float* __restrict__ l0, const float* __restrict__ l1, const float* __restrict__ l2,
     const float* __restrict__ lsq, const double* __restrict__ cen, const int32_t* __restrict__ body_of,
-    const c64* __restrict__ q, int64_t N, int64_t G, int Dmax, int even_G, int dpc, int nchunks_d,
+    const c64* __restrict__ q, int64_t N, int R, int64_t G, int Dmax, int even_G, int dpc, int nchunks_d,
     c64* __restrict__ partial) {
-  __shared__ SymLds<DIM> sh;
+  __shared__ SymLds<DIM, RT> sh;
   const int lane = threadIdx.x;
   const int64_t g = blockIdx.x;
   const int c = blockIdx.y;
+  const int r0 = blockIdx.z * RT;  // right-hand sides r0 .. r0 + RT - 1 (those >= R repeat R - 1, unstored)
   const int d0 = c * dpc;
   const int d1 = min(Dmax + 1, d0 + dpc);
   const float* lsrc[3] = {l0, l1, l2};
+  int rof[RT];
+#pragma unroll
+  for (int rr = 0; rr < RT; ++rr) rof[rr] = min(r0 + rr, R - 1);
 
   // targets of this wave: tile m covers points g*256 + 64 m + (0..63), all on one body
   bool act[kSymTiles];
   int tb[kSymTiles];
-  float lt[kSymTiles][DIM], qtr[kSymTiles], qti[kSymTiles];
-  double ar[kSymTiles], ai[kSymTiles];
+  float lt[kSymTiles][DIM], qtr[kSymTiles][RT], qti[kSymTiles][RT];
+  double ar[kSymTiles][RT], ai[kSymTiles][RT];
 #pragma unroll
   for (int m = 0; m < kSymTiles; ++m) {
     const int64_t t0 = g * kSymGroup + 64 * m;
@@ -633,10 +661,13 @@ __global__ __launch_bounds__(64, 4) void ghat_sym_kernel(
     tb[m] = act[m] ? __builtin_amdgcn_readfirstlane(body_of[t0]) : -1;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) lt[m][d] = lsrc[d][t];
-    const c64 qq = q[t];
-    qtr[m] = act[m] ? qq.re : 0.0f;
-    qti[m] = act[m] ? qq.im : 0.0f;
-    ar[m] = ai[m] = 0.0;
+#pragma unroll
+    for (int rr = 0; rr < RT; ++rr) {
+      const c64 qq = q[(int64_t)rof[rr] * N + t];
+      qtr[m][rr] = act[m] ? qq.re : 0.0f;
+      qti[m][rr] = act[m] ? qq.im : 0.0f;
+      ar[m][rr] = ai[m][rr] = 0.0;
+    }
   }
 
   for (int d = d0; d < d1; ++d) {
@@ -653,9 +684,12 @@ __global__ __launch_bounds__(64, 4) void ghat_sym_kernel(
 #pragma unroll
         for (int dd = 0; dd < DIM; ++dd) sh.l[dd][lane] = sh.l[dd][lane + 64] = lsrc[dd][j];
         sh.bs[lane] = sh.bs[lane + 64] = lsq[j];
-        const c64 qq = q[j];
-        sh.qr[lane] = sh.qr[lane + 64] = qq.re;
-        sh.qi[lane] = sh.qi[lane + 64] = qq.im;
+#pragma unroll
+        for (int rr = 0; rr < RT; ++rr) {
+          const c64 qq = q[(int64_t)rof[rr] * N + j];
+          sh.qr[rr][lane] = sh.qr[rr][lane + 64] = qq.re;
+          sh.qi[rr][lane] = sh.qi[rr][lane + 64] = qq.im;
+        }
       }
       __syncthreads();
       // per target tile: body-centre split against the source body (uniform over the wave)
@@ -664,11 +698,12 @@ __global__ __launch_bounds__(64, 4) void ghat_sym_kernel(
       for (int dd = 0; dd < DIM; ++dd) cs[dd] = cen[(int64_t)sb * DIM + dd];
       bool use[kSymTiles];
       float A[kSymTiles], P[kSymTiles][DIM], D[kSymTiles], D2[kSymTiles], ph0[kSymTiles];
-      float tr[kSymTiles], ti[kSymTiles];
+      float tr[kSymTiles][RT], ti[kSymTiles][RT];
 #pragma unroll
       for (int m = 0; m < kSymTiles; ++m) {
         use[m] = act[m] && tb[m] != sb;
-        tr[m] = ti[m] = 0.0f;
+#pragma unroll
+        for (int rr = 0; rr < RT; ++rr) tr[m][rr] = ti[m][rr] = 0.0f;
         const int bt = use[m] ? tb[m] : sb;
         double D2d = 0.0;
         float Am = 0.0f;
@@ -687,22 +722,35 @@ __global__ __launch_bounds__(64, 4) void ghat_sym_kernel(
         D2[m] = (float)D2d;
         ph0[m] = (float)(ph - floor(ph)) - (DIM == 2 ? 0.125f : 0.0f);
       }
-      float sr = 0.0f, si = 0.0f;  // lane l: source-side sum of source j0 + l (after the tile)
-      if (sym) sym_tile<DIM, true>(sh, k, lane, use, A, P, D, D2, ph0, qtr, qti, tr, ti, sr, si);
-      else sym_tile<DIM, false>(sh, k, lane, use, A, P, D, D2, ph0, qtr, qti, tr, ti, sr, si);
+      float sr[RT], si[RT];  // lane l: source-side sums of source j0 + l (after the tile)
 #pragma unroll
-      for (int m = 0; m < kSymTiles; ++m) {
-        ar[m] += (double)tr[m];
-        ai[m] += (double)ti[m];
-      }
+      for (int rr = 0; rr < RT; ++rr) sr[rr] = si[rr] = 0.0f;
+      if (sym) sym_tile<DIM, RT, true>(sh, k, lane, use, A, P, D, D2, ph0, qtr, qti, tr, ti, sr, si);
+      else sym_tile<DIM, RT, false>(sh, k, lane, use, A, P, D, D2, ph0, qtr, qti, tr, ti, sr, si);
+#pragma unroll
+      for (int m = 0; m < kSymTiles; ++m)
+#pragma unroll
+        for (int rr = 0; rr < RT; ++rr) {
+          ar[m][rr] += (double)tr[m][rr];
+          ai[m][rr] += (double)ti[m][rr];
+        }
       // source-side sums of this tile from the wave's targets -> slice of distance d
-      if (sym) partial[(int64_t)(nchunks_d + d - 1) * N + j0 + lane] = c64{sr, si};
+      if (sym) {
+#pragma unroll
+        for (int rr = 0; rr < RT; ++rr)
+          if (r0 + rr < R)
+            partial[((int64_t)(nchunks_d + d - 1) * R + r0 + rr) * N + j0 + lane] = c64{sr[rr], si[rr]};
+      }
       __syncthreads();  // the tile's entries are read before the next tile is staged
     }
   }
 #pragma unroll
   for (int m = 0; m < kSymTiles; ++m)
-    if (act[m]) partial[(int64_t)c * N + g * kSymGroup + 64 * m + lane] = c64{(float)ar[m], (float)ai[m]};
+#pragma unroll
+    for (int rr = 0; rr < RT; ++rr)
+      if (act[m] && r0 + rr < R)
+        partial[((int64_t)c * R + r0 + rr) * N + g * kSymGroup + 64 * m + lane] =
+            c64{(float)ar[m][rr], (float)ai[m][rr]};
 }
 
 Phi2DConstsF32 make_phi2d_f32(double kappa) {
@@ -1034,23 +1082,53 @@ SymPlan sym_plan(int64_t N, int nchunks_d) {
 }
 
 bool ghat_sym_possible(const SceneDev& s, int R) {
-  if (R != 1 || !s.all_k_mult64 || s.N <= 0) return false;
-  const SymPlan p = sym_plan(s.N, 0);
-  // the source-side slots grow as N^2 / 512: keep them within 8 GiB
-  return (double)(p.Dsym + 1) * (double)s.N * sizeof(c64) <= 8.0 * (1ull << 30);
+  if (R < 1 || R >= kMfmaMinRhs || s.N <= 0) return false;
+  int64_t NP = s.N;
+  if (!s.all_k_mult64) {
+    // padded to whole tiles: worth it while the padded pair count stays below 1.4 times the real one
+    // (the symmetric kernel does about 0.6 times the plain kernel's work per pair)
+    if (!s.pad_ptr || (double)s.Npad * (double)s.Npad > 1.4 * (double)s.N * (double)s.N) return false;
+    NP = s.Npad;
+  }
+  const SymPlan p = sym_plan(NP, 0);
+  // the source-side slices grow as N^2 / 512 per right-hand side: keep them within 8 GiB
+  return (double)(p.Dsym + 1) * (double)NP * (double)R * sizeof(c64) <= 8.0 * (1ull << 30);
 }
 
-hipError_t launch_ghat_f32_sym(const SceneDev& s, const c64* q, c64* partial, int nchunks_d, hipStream_t st) {
+SceneDev sym_view(const SceneDev& s) {
+  if (s.all_k_mult64) return s;
+  SceneDev v = s;
+  v.N = s.Npad;
+  for (int d = 0; d < 3; ++d) v.l32[d] = s.l32p[d];
+  v.lsq32 = s.lsqp;
+  v.body_of = s.body_of_pad;
+  v.body_ptr = s.pad_ptr;
+  v.all_k_mult64 = true;
+  return v;
+}
+
+template <int DIM, int RT>
+static void launch_sym(const SceneDev& s, const SymPlan& p, const c64* q, int R, c64* partial, hipStream_t st) {
+  const dim3 grid((unsigned)p.G, (unsigned)p.nchunks_d, (unsigned)((R + RT - 1) / RT));
+  hipLaunchKernelGGL((ghat_sym_kernel<DIM, RT>), grid, dim3(64), 0, st, make_bodyphase(s.kappa, s.rho_max), s.l32[0],
+                     s.l32[1], s.l32[2], s.lsq32, s.centres, s.body_of, q, s.N, R, p.G, p.Dmax, p.even ? 1 : 0, p.dpc,
+                     p.nchunks_d, partial);
+}
+
+hipError_t launch_ghat_f32_sym(const SceneDev& s, const c64* q, int R, c64* partial, int nchunks_d, int rt,
+                               hipStream_t st) {
   if (s.N <= 0) return hipSuccess;
   const SymPlan p = sym_plan(s.N, nchunks_d);
-  const dim3 grid((unsigned)p.G, (unsigned)p.nchunks_d, 1);
-  const BodyPhaseConsts k = make_bodyphase(s.kappa, s.rho_max);
-  if (s.dim == 2)
-    hipLaunchKernelGGL((ghat_sym_kernel<2>), grid, dim3(64), 0, st, k, s.l32[0], s.l32[1], s.l32[2], s.lsq32,
-                       s.centres, s.body_of, q, s.N, p.G, p.Dmax, p.even ? 1 : 0, p.dpc, p.nchunks_d, partial);
-  else
-    hipLaunchKernelGGL((ghat_sym_kernel<3>), grid, dim3(64), 0, st, k, s.l32[0], s.l32[1], s.l32[2], s.lsq32,
-                       s.centres, s.body_of, q, s.N, p.G, p.Dmax, p.even ? 1 : 0, p.dpc, p.nchunks_d, partial);
+  if (rt != 1 && rt != 2 && rt != 4) rt = ghat_default_rt(R);
+  if (s.dim == 2) {
+    if (rt == 1) launch_sym<2, 1>(s, p, q, R, partial, st);
+    else if (rt == 2) launch_sym<2, 2>(s, p, q, R, partial, st);
+    else launch_sym<2, 4>(s, p, q, R, partial, st);
+  } else {
+    if (rt == 1) launch_sym<3, 1>(s, p, q, R, partial, st);
+    else if (rt == 2) launch_sym<3, 2>(s, p, q, R, partial, st);
+    else launch_sym<3, 4>(s, p, q, R, partial, st);
+  }
   return hipGetLastError();
 }
 
@@ -1118,6 +1196,33 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const Cplx<T>* __r
     im += (double)v.im;
   }
   out[i] = Cplx<T>{(T)re, (T)im};
+}
+
+__global__ __launch_bounds__(256) void reduce_partials_padded_kernel(const c64* __restrict__ partial, int nchunks,
+                                                                      const int32_t* __restrict__ body_of,
+                                                                      const int64_t* __restrict__ body_ptr,
+                                                                      const int64_t* __restrict__ pad_ptr, int64_t N,
+                                                                      int64_t NP, int R, c64* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (i >= N) return;
+  const int b = body_of[i];
+  const int64_t ip = pad_ptr[b] + (i - body_ptr[b]);
+  double re = 0, im = 0;
+  for (int c = 0; c < nchunks; ++c) {
+    const c64 v = partial[((int64_t)c * R + r) * NP + ip];
+    re += (double)v.re;
+    im += (double)v.im;
+  }
+  out[(int64_t)r * N + i] = c64{(float)re, (float)im};
+}
+
+hipError_t launch_reduce_partials_padded(const SceneDev& s, const c64* partial, int nchunks, int R, c64* out,
+                                         hipStream_t st) {
+  if (s.N == 0 || R == 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_partials_padded_kernel, dim3((unsigned)((s.N + 255) / 256), (unsigned)R), dim3(256), 0, st,
+                     partial, nchunks, s.body_of, s.body_ptr, s.pad_ptr, s.N, s.Npad, R, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce_partials_f32(const c64* partial, int nchunks, int64_t M, int R, c64* out, hipStream_t st) {

@@ -15,6 +15,7 @@ __global__ __launch_bounds__(256) void sapply_kernel(const int64_t* __restrict__
                                                      const int32_t* __restrict__ shape_of,
                                                      const void* const* __restrict__ S_of_shape,
                                                      const Cplx<TS>* __restrict__ partial, int nchunks,
+                                                     const int64_t* __restrict__ pptr, int64_t NP,
                                                      const Cplx<TQ>* __restrict__ q, TQ beta,
                                                      Cplx<TQ>* __restrict__ y, int64_t N, int R) {
   extern __shared__ unsigned char smem_raw[];
@@ -24,12 +25,13 @@ __global__ __launch_bounds__(256) void sapply_kernel(const int64_t* __restrict__
   const int64_t start = body_ptr[body];
   const int k = (int)(body_ptr[body + 1] - start);
   const Cplx<TS>* __restrict__ S = static_cast<const Cplx<TS>*>(S_of_shape[shape_of[body]]);
-  const int64_t NR = N * R;
+  const int64_t NPR = NP * R;
+  const int64_t pstart = pptr[body];
   for (int j = threadIdx.x; j < k; j += blockDim.x) {
-    const int64_t idx = (int64_t)r * N + start + j;
+    const int64_t idx = (int64_t)r * NP + pstart + j;
     double re = 0, im = 0;  // the symmetric pair kernel leaves hundreds of slices: add in FP64
     for (int c = 0; c < nchunks; ++c) {
-      const Cplx<TS> v = partial[(int64_t)c * NR + idx];
+      const Cplx<TS> v = partial[(int64_t)c * NPR + idx];
       re += (double)v.re;
       im += (double)v.im;
     }
@@ -61,14 +63,47 @@ __global__ __launch_bounds__(256) void sapply_kernel(const int64_t* __restrict__
 
 template <typename TQ, typename TS>
 hipError_t launch_sapply(const SceneDev& s, const void* const* S_tab, const Cplx<TS>* partial, int nchunks,
-                         const Cplx<TQ>* q, TQ beta, Cplx<TQ>* y, int R, int kmax, hipStream_t st) {
+                         const Cplx<TQ>* q, TQ beta, Cplx<TQ>* y, int R, int kmax, hipStream_t st,
+                         const int64_t* pptr = nullptr, int64_t NP = 0) {
   if (s.T == 0 || R == 0) return hipSuccess;
+  if (!pptr) {
+    pptr = s.body_ptr;
+    NP = s.N;
+  }
   int threads = ((kmax + 63) / 64) * 64;
   threads = threads < 64 ? 64 : (threads > 256 ? 256 : threads);
   const size_t shmem = sizeof(Cplx<TS>) * (size_t)kmax;
   hipLaunchKernelGGL((sapply_kernel<TQ, TS>), dim3((unsigned)s.T, (unsigned)R), dim3(threads), shmem, st,
-                     s.body_ptr, s.shape_of, S_tab, partial, nchunks, q, beta, y, s.N, R);
+                     s.body_ptr, s.shape_of, S_tab, partial, nchunks, pptr, NP, q, beta, y, s.N, R);
   return hipGetLastError();
+}
+
+// Padded layout: point ip belongs to body b = body_of_pad[ip] at offset o = ip - pad_ptr[b]; it is
+// the body's point o if o < k_b, else a filler at the body centre (offset 0, charge 0).
+__global__ void pad_scene_kernel(int dim, const int64_t* __restrict__ body_ptr, const int64_t* __restrict__ pad_ptr,
+                                 const int32_t* __restrict__ body_of_pad, const float* __restrict__ l32, int64_t N,
+                                 const float* __restrict__ lsq, int64_t NP, float* __restrict__ l32p,
+                                 float* __restrict__ lsqp) {
+  const int64_t ip = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ip >= NP) return;
+  const int b = body_of_pad[ip];
+  const int64_t o = ip - pad_ptr[b];
+  const bool real = o < body_ptr[b + 1] - body_ptr[b];
+  const int64_t i = body_ptr[b] + o;
+  for (int d = 0; d < dim; ++d) l32p[d * NP + ip] = real ? l32[d * N + i] : 0.0f;
+  lsqp[ip] = real ? lsq[i] : 0.0f;
+}
+
+__global__ void gather_pad_kernel(const int64_t* __restrict__ body_ptr, const int64_t* __restrict__ pad_ptr,
+                                  const int32_t* __restrict__ body_of_pad, const c64* __restrict__ q, int64_t N,
+                                  int64_t NP, c64* __restrict__ qp) {
+  const int64_t ip = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (ip >= NP) return;
+  const int b = body_of_pad[ip];
+  const int64_t o = ip - pad_ptr[b];
+  const bool real = o < body_ptr[b + 1] - body_ptr[b];
+  qp[(int64_t)r * NP + ip] = real ? q[(int64_t)r * N + body_ptr[b] + o] : c64{0.0f, 0.0f};
 }
 
 __global__ void to_c64_kernel(const c128* __restrict__ in, c64* __restrict__ out, int64_t n) {
@@ -141,13 +176,27 @@ hipError_t launch_sapply_f64(const SceneDev& s, const c128* partial, int nchunks
 }
 
 hipError_t launch_sapply_f32(const SceneDev& s, const c64* partial, int nchunks, const c64* q, float beta, c64* y,
-                             int R, int kmax, hipStream_t st) {
-  return launch_sapply<float, float>(s, s.S32, partial, nchunks, q, beta, y, R, kmax, st);
+                             int R, int kmax, hipStream_t st, const int64_t* pptr, int64_t NP) {
+  return launch_sapply<float, float>(s, s.S32, partial, nchunks, q, beta, y, R, kmax, st, pptr, NP);
 }
 
 hipError_t launch_sapply_mixed(const SceneDev& s, const c64* partial, int nchunks, const c128* q, double beta,
-                               c128* y, int R, int kmax, hipStream_t st) {
-  return launch_sapply<double, float>(s, s.S32, partial, nchunks, q, beta, y, R, kmax, st);
+                               c128* y, int R, int kmax, hipStream_t st, const int64_t* pptr, int64_t NP) {
+  return launch_sapply<double, float>(s, s.S32, partial, nchunks, q, beta, y, R, kmax, st, pptr, NP);
+}
+
+hipError_t launch_pad_scene(const SceneDev& s, float* l32p, float* lsqp, hipStream_t st) {
+  if (s.Npad == 0) return hipSuccess;
+  hipLaunchKernelGGL(pad_scene_kernel, dim3((unsigned)((s.Npad + 255) / 256)), dim3(256), 0, st, s.dim, s.body_ptr,
+                     s.pad_ptr, s.body_of_pad, s.l32[0], s.N, s.lsq32, s.Npad, l32p, lsqp);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_pad(const SceneDev& s, const c64* q, int R, c64* qp, hipStream_t st) {
+  if (s.Npad == 0 || R == 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_pad_kernel, dim3((unsigned)((s.Npad + 255) / 256), (unsigned)R), dim3(256), 0, st,
+                     s.body_ptr, s.pad_ptr, s.body_of_pad, q, s.N, s.Npad, qp);
+  return hipGetLastError();
 }
 
 hipError_t launch_to_c64(const c128* in, c64* out, int64_t n, hipStream_t st) {

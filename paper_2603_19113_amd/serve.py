@@ -26,12 +26,33 @@ import numpy as np
 
 
 # ------------------------------------------------------------------ policy ---
+def _chunks(N: int, targets_per_thread: int) -> int:
+    """Source slices of the plain pair kernels (the library's occupancy heuristic)."""
+    waves = -(-N // (64 * targets_per_thread))
+    want = -(-16384 // max(waves, 1))
+    return max(1, min(want, max(1, N // 64), 128))
+
+
+def _sym_slices(n_pad: int) -> int:
+    """Partial slices of the symmetric kernel with its default distance chunking."""
+    G = -(-n_pad // 256)
+    dmax = G // 2
+    dsym = max(0, dmax - 1 if G % 2 == 0 else dmax)
+    want = max(1, min(min(1024, -(-65536 // max(G, 1))), dmax + 1))
+    dpc = -(-(dmax + 1) // want)
+    return -(-(dmax + 1) // dpc) + dsym
+
+
 def footprint_bytes(N: int, T: int, R: int, dim: int, restart: int, n_targets: int = 0) -> int:
     """Device bytes a request holds while it runs (scene tables, pair partial sums, complex64 Krylov
     basis and complex128 Hessenberg, solver vectors, caller tensors), mirroring the library's
     allocations."""
-    scene = N * (8 * dim + 4 * dim + 4 * dim + 4 + 4 + 4) + T * (8 + 4 + 8 * dim)
-    partial = 16 * R * N * 16                      # at most 16 source chunks, complex128
+    n_pad = N + 63 * T                             # bodies padded to whole 64-point tiles, at most
+    scene = N * (8 * dim + 4 * dim + 4 * dim + 4 + 4 + 4) + T * (8 + 4 + 8 * dim) \
+        + n_pad * (4 * dim + 8) + T * 8 + (R * n_pad * 8 if R < 8 else 0)
+    partial = max(_chunks(N, 1) * R * N * 16,      # FP64 pair sums (residuals)
+                  _chunks(N, 2) * R * N * 8,       # FP32 plain kernel
+                  _sym_slices(n_pad) * R * n_pad * 8 if R < 8 else 0)  # FP32 symmetric kernel
     q32 = R * N * 8
     nblk = (N + 1023) // 1024
     krylov = (restart + 1) * R * N * 8 + R * restart * (restart + 1) * 16 + 2 * R * (restart + 1) * nblk * 8 \

@@ -1,6 +1,6 @@
-"""The symmetric one-right-hand-side pair kernel on the GPU against the FP64 oracle.
+"""The symmetric pair kernel on the GPU against the FP64 oracle.
 
-With one right-hand side in FP32 and every body holding a multiple of 64 points, the operator
+With 1 to 7 right-hand sides in FP32 and every body holding a multiple of 64 points, the operator
 evaluates phi once per unordered pair and adds it into both sums (G_hat is symmetric).  Its
 schedule (groups of 256 points meeting at cyclic distances, one-sided at distance 0 and G/2) has
 edge cases in the number of groups G: 1, 2 (both one-sided), odd and even G, a last group with
@@ -105,11 +105,16 @@ def test_symmetric_kernel_is_deterministic_and_used_only_where_it_applies(mfs):
     q = crandn(np.random.default_rng(32), 1, gsc.N)
     a, b = _ghat32(mfs, gsc, q), _ghat32(mfs, gsc, q)
     assert np.array_equal(a, b)
-    # two right-hand sides, FP64, or shapes whose point count is not a multiple of 64: plain kernels
-    for R, prec in ((2, mfs.MFS_FP32), (1, mfs.MFS_FP64)):
+    # eight or more right-hand sides (matrix cores), FP64, or bodies that would need too much
+    # padding to whole 64-point tiles (37 points -> 64): other kernels
+    for R, prec in ((8, mfs.MFS_FP32), (1, mfs.MFS_FP64)):
         mfs.tune_set(gsc, R, prec, 8, 0, 1)
         assert mfs.tune_get(gsc, R, prec)["symmetric"] == 0
-    other, _ = _scene(mfs, w.make_scene("spheres1000", T=3))
+    sh = w.disk2d(radius=0.5, m=80, n=40, src_radius=0.35, k=37, rho_eq=0.6, p=81, r_psi=0.7)
+    odd = w.Scene(dim=2, kappa=7.0, shapes=[sh], shape_of=np.zeros(4, np.int32),
+                  centres=w.random_centres(4, 2, 6.0, 1.6, 3), directions=w.plane_wave_directions_2d([0.3]),
+                  name="disks37")
+    other, _ = _scene(mfs, odd)
     mfs.tune_set(other, 1, mfs.MFS_FP32, 8, 0, 1)
     assert mfs.tune_get(other, 1, mfs.MFS_FP32)["symmetric"] == 0
     other.close()
@@ -130,4 +135,69 @@ def test_autotune_considers_both_kernels(mfs):
     got = mfs.tune_get(gsc, 1, mfs.MFS_MIXED)
     assert got["symmetric"] == res["symmetric"] and got["source"] == "scene"
     print("autotune starfish64:", res, flush=True)
+    gsc.close()
+
+
+@pytest.mark.parametrize("kind,T,R", [("disks", 13, 2), ("disks", 9, 3), ("starfish", 40, 5), ("spheres", 6, 3),
+                                      ("starfish", 7, 7)])
+def test_symmetric_kernel_many_rhs(mfs, kind, T, R):
+    """2 to 7 right-hand sides: 1, 2 or 4 per thread, ragged last group of right-hand sides."""
+    sc = {"disks": _disks, "starfish": _starfish, "spheres": _spheres64}[kind](T)
+    print(f"symmetric ghat {kind} T={T} R={R}", flush=True)
+    gsc, _ = _scene(mfs, sc)
+    assert mfs.tune_get(gsc, R, mfs.MFS_FP32)["symmetric"] == 1
+    xh, ptr, bo = gs.pack(sc)
+    q = crandn(np.random.default_rng(33), R, xh.shape[0])
+    ref = gs.ghat_apply(xh, bo, sc.kappa, q)
+    budget = fp32_matvec_budget(sc)
+    for rt in (1, 2, 4):
+        for nch in (1, 3):
+            mfs.tune_set(gsc, R, mfs.MFS_FP32, nch, rt, 1)
+            got = mfs.tune_get(gsc, R, mfs.MFS_FP32)
+            assert got["symmetric"] == 1 and got["rhs_per_thread"] == rt
+            t = _ghat32(mfs, gsc, q)
+            for r in range(R):
+                assert rel_err(t[r], ref[r]) < budget, (rt, nch, r)
+    gsc.close()
+
+
+def _ellipses112(T):
+    """T ellipses of 112 equivalent points: padded to 128 (two tiles) for the symmetric kernel."""
+    sh = w.ellipse2d(m=224, n=112, k=112, p=225)
+    centres = w.random_centres(T, 2, 9.0, 1.6, 12)
+    return w.Scene(dim=2, kappa=8.0, shapes=[sh], shape_of=np.zeros(T, np.int32), centres=centres,
+                   directions=w.plane_wave_directions_2d([0.5, 1.5, 2.5]), name="ellipses112")
+
+
+@pytest.mark.parametrize("kind,T,R", [("spheres400", 5, 1), ("spheres400", 3, 3), ("ellipses112", 9, 1),
+                                      ("ellipses112", 11, 2)])
+def test_symmetric_kernel_on_padded_bodies(mfs, kind, T, R):
+    """Bodies whose point count is not a multiple of 64 are padded to whole tiles with zero-charge
+    points at the body centre; the pair sum, the reduction and the S product read the padded rows."""
+    torch = _torch()
+    sc = w.make_scene("spheres1000", T=T) if kind == "spheres400" else _ellipses112(T)
+    print(f"padded symmetric {kind} T={T} R={R}", flush=True)
+    gsc, Ss = _scene(mfs, sc)
+    assert mfs.tune_get(gsc, R, mfs.MFS_FP32)["symmetric"] == 1
+    xh, ptr, bo = gs.pack(sc)
+    q = crandn(np.random.default_rng(34), R, xh.shape[0])
+    budget = fp32_matvec_budget(sc)
+    ref = gs.ghat_apply(xh, bo, sc.kappa, q)
+    for nch in (1, 2):
+        mfs.tune_set(gsc, R, mfs.MFS_FP32, nch, 0, 1)
+        t = _ghat32(mfs, gsc, q)
+        for r in range(R):
+            assert rel_err(t[r], ref[r]) < budget
+    # the whole operator: the S product reads the pair sums from the padded rows
+    ref_y = gs.matvec(sc, Ss, xh, ptr, bo, q)
+    y = torch.empty((R, gsc.N), dtype=torch.complex64, device="cuda")
+    mfs.apply(gsc, torch.from_numpy(q.astype(np.complex64)).cuda(), y, mfs.MFS_FP32)
+    yy = y.cpu().numpy()
+    for r in range(R):
+        assert rel_err(yy[r], ref_y[r]) < budget
+    # and against the plain kernel on the packed layout
+    mfs.tune_set(gsc, R, mfs.MFS_FP32, 4, 0, 0)
+    assert mfs.tune_get(gsc, R, mfs.MFS_FP32)["symmetric"] == 0
+    plain = _ghat32(mfs, gsc, q)
+    assert rel_err(plain, t) < 2 * budget
     gsc.close()

@@ -85,7 +85,7 @@ def test_mixed_tuning_and_rhs_per_thread_variants(mfs):
     # does a column's work, not its arithmetic
     outs = []
     for rt in (1, 2, 4):
-        mfs.tune_set(gsc, R, mfs.MFS_FP32, 6, rt)
+        mfs.tune_set(gsc, R, mfs.MFS_FP32, 6, rt, 0)  # the plain kernel
         assert mfs.tune_get(gsc, R, mfs.MFS_FP32) == {"nchunks": 6, "rhs_per_thread": rt, "symmetric": 0,
                                                       "source": "scene"}
         outs.append(_apply(mfs, gsc, q, mfs.MFS_FP32))
