@@ -360,8 +360,10 @@ typedef struct {
  * form with an FP32 pair sum for MFS_MIXED) on this scene with R right-hand sides for a set of
  * launch shapes around the heuristic, `reps` applications each after one warm-up, and keep the
  * fastest: in the scene and in the process-wide table.  Uses synthetic charges in scratch device
- * memory; the caller's data is not touched.  Synchronous.  Pair-sum launches made while kernel
- * timing is enabled are recorded like any other.  out may be NULL. */
+ * memory; the caller's data is not touched.  Another shape replaces the untuned one only when it
+ * is at least 2% faster, so that timing noise does not move the choice between runs.
+ * Synchronous.  Pair-sum launches made while kernel timing is enabled are recorded like any
+ * other.  out may be NULL. */
 mfs_status mfs_autotune(mfs_scene* scene, int32_t R, mfs_prec prec, int32_t reps, mfs_tune_result* out,
                         void* stream);
 

@@ -1276,7 +1276,9 @@ mfs_status mfs_autotune(mfs_scene* s, int32_t R, mfs_prec prec, int32_t reps, mf
     const double t = (double)ms / reps;
     if (i == 0) ms_h = t;
     if (cands[i].sym == 0 && ms_plain < 0.0) ms_plain = t;  // the plain kernel's heuristic shape
-    if (i == 0 || t < best) {
+    // another shape replaces the untuned one only when it is clearly faster (2%), so that timing
+    // noise does not make the choice wander between runs
+    if (i == 0 || (t < best && t < 0.98 * ms_h)) {
       best = t;
       best_ls = cands[i];
     }
