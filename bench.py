@@ -37,7 +37,12 @@ FLOP_PER_PAIR_F32 = {2: 42, 3: 34}
 # The symmetric kernel (one right-hand side) evaluates phi once per unordered pair and makes two
 # complex multiply-adds with it: (42 - 8) + 16 = 50 flop per unordered pair in 2D, (34 - 8) + 16 = 42
 # in 3D, i.e. 25 and 21 per (ordered) pair of the operator.
-FLOP_PER_PAIR_F32_SYM = {2: 25, 3: 21}
+# With R right-hand sides phi is shared by all of them: (phi / R + 16) / 2 per pair and right-hand side.
+PHI_FLOP_F32 = {2: 34, 3: 26}
+
+
+def flop_per_pair_sym(dim: int, R: int) -> float:
+    return (PHI_FLOP_F32[dim] / R + 16) / 2
 # FP32 vector peak from the unit counts: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz =
 # 78.6 TFLOP/s.  The 157.3 TFLOP/s figure counts packed (two-wide) FP32 instructions, which every HIP
 # build here disables, so 78.6 is the ceiling these kernels can reach; both are reported.
@@ -293,6 +298,8 @@ def main() -> int:
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="profiling: first copy a buffer of this many MiB (calibrates rocprof byte counters)")
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--rhs", type=int, default=0,
+                    help="use only the first RHS incident directions of the workload (0: all of them)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-shape autotuner (run before the warm-up, outside the timed steps)")
     ap.add_argument("--launch-shape", default=None, metavar="NCHUNKS:RT[:SYM]",
@@ -338,6 +345,11 @@ def main() -> int:
     if args.serve > 0:
         return serve(args, w, torch)
     sc = w.make_scene(args.workload, T=args.bodies)
+    if args.rhs:
+        if not 1 <= args.rhs <= sc.R:
+            print(f"--rhs must be in 1..{sc.R} for this workload", file=sys.stderr)
+            return 2
+        sc.directions = sc.directions[:args.rhs]
     R = sc.R
     dirs = sc.directions
     targets = torch.from_numpy(w.far_targets(sc, 256)).cuda()
@@ -429,12 +441,12 @@ def main() -> int:
     ms64, n64, p64 = mfs.timing_read(mfs.MFS_KERNEL_PAIR_F64)
     mfs.timing_enable(False)
 
-    on_mfma = sc.R >= 8 and all(sh.k % 16 == 0 for sh in sc.shapes)
     on_sym = shape["symmetric"] == 1
-    if on_mfma:
-        kernel_name = "ghat_mfma_kernel<%d> (G_hat, FP32 matrix cores)" % sc.dim
-    elif on_sym:
+    on_mfma = not on_sym and sc.R >= 8 and all(sh.k % 16 == 0 for sh in sc.shapes)
+    if on_sym:
         kernel_name = "ghat_sym_kernel<%d> (G_hat, FP32, symmetric)" % sc.dim
+    elif on_mfma:
+        kernel_name = "ghat_mfma_kernel<%d> (G_hat, FP32 matrix cores)" % sc.dim
     else:
         kernel_name = "ghat_bodyphase_kernel<%d,2,%d> (G_hat, FP32)" % (sc.dim, shape["rhs_per_thread"])
     traffic = stored_traffic(sc.name, kernel_name, shape["nchunks"])
@@ -446,8 +458,9 @@ def main() -> int:
         # the contraction on the matrix cores: 8 flop per (pair, right-hand side) complex multiply-add
         flop_pp, bound, peak, peak_alt = FLOP_PER_PAIR_RHS_MFMA, "mfma", PEAK_FP32_MFMA_TFLOPS, None
     else:
-        flop_pp, bound, peak, peak_alt = (FLOP_PER_PAIR_F32_SYM if on_sym else FLOP_PER_PAIR_F32)[sc.dim], "alu", \
-            PEAK_FP32_VECTOR_TFLOPS, PEAK_FP32_PACKED_TFLOPS
+        # per pair and right-hand side: phi is shared by the R right-hand sides of a launch
+        flop_pp = flop_per_pair_sym(sc.dim, R) if on_sym else PHI_FLOP_F32[sc.dim] / R + 8
+        bound, peak, peak_alt = "alu", PEAK_FP32_VECTOR_TFLOPS, PEAK_FP32_PACKED_TFLOPS
     achieved = flop_pp * pairs_per_launch32 / (avg32 * 1e-3) / 1e12 if n32 else 0.0
     solve_times = [i["t_total_s"] for i in infos]
     out = {

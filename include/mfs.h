@@ -335,14 +335,14 @@ mfs_status mfs_pool_trim(void);
  * The pair sum splits the sources seen by every block of targets into `nchunks` slices (more
  * slices: more blocks in flight on a small system, but more partial sums for the S product to
  * read back), and on the VALU kernel each thread carries `rhs_per_thread` right-hand sides (1, 2
- * or 4; the matrix-core kernel used for 8 or more right-hand sides has no such knob).  With 1 to 7
+ * or 4; the matrix-core kernel, for 8 or more right-hand sides, has no such knob).  With 1 to 32
  * right-hand sides, FP32, and every body holding a multiple of 64 points, a symmetric kernel can
  * run instead: G_hat is symmetric, so it evaluates phi once per unordered pair of points and adds
  * it into both sums; there `nchunks` counts the chunks of group distances per target group, and
  * the kernel leaves about N / 512 further partial slices per right-hand side (at most 8 GiB of
  * them, else the plain kernel runs).  A scene uses, in this order: its own tuned shape for (precision, R); the
  * process-wide table, keyed by (dim, kernel, R, floor(log2 N)); the heuristic (the symmetric
- * kernel where it applies).  Slices are summed in a fixed order, so a given shape gives
+ * kernel where it applies and R <= 24).  Slices are summed in a fixed order, so a given shape gives
  * reproducible results; another shape may change the last bits of the sums.
  * ------------------------------------------------------------------------------------------ */
 typedef struct {
@@ -351,7 +351,7 @@ typedef struct {
   double ms;               /* time of one operator application with the chosen shape */
   double ms_heuristic;     /* the same with the untuned shape */
   int32_t n_tried;         /* shapes timed */
-  int32_t uses_mfma;       /* 1 when R selects the matrix-core kernel */
+  int32_t uses_mfma;       /* 1 when the matrix-core kernel won (R >= 8) */
   int32_t symmetric;       /* 1 when the symmetric kernel won */
   double ms_plain;         /* time with the plain kernel's heuristic shape (-1 if not timed) */
 } mfs_tune_result;

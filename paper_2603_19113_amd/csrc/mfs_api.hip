@@ -181,7 +181,9 @@ LaunchShape shape_for(const mfs_scene* s, bool f64, int R, int* source = nullptr
   }
   if (source) *source = src;
   LaunchShape ls = e;
-  const bool sym_ok = v == kTunePairF32 && ghat_sym_possible(s->dev, R);
+  // untuned: the symmetric kernel up to kSymDefaultMaxRhs right-hand sides (measured against the
+  // matrix-core kernel: 3.4x faster at 8, 1.7x at 16, 0.87x at 32); tuned or set: up to kSymMaxRhs
+  const bool sym_ok = v != kTunePairF64 && ghat_sym_possible(s->dev, R) && (e.sym == 1 || R <= kSymDefaultMaxRhs);
   if (sym_ok && e.sym != 0) {
     ls.sym = 1;
     // a slice count tuned for the other kernel does not carry over
@@ -1196,7 +1198,7 @@ mfs_status mfs_autotune(mfs_scene* s, int32_t R, mfs_prec prec, int32_t reps, mf
       if (o.nchunks == c.nchunks && o.rt == c.rt && o.sym == c.sym) return;
     cands.push_back(c);
   };
-  const bool sym_ok = v == kTunePairF32 && ghat_sym_possible(s->dev, R);
+  const bool sym_ok = v != kTunePairF64 && ghat_sym_possible(s->dev, R);
   const int h = pair_chunks_for(N, N, tpt_for(f64 ? MFS_FP64 : MFS_FP32));
   const int h_rt = v == kTunePairF32 ? ghat_default_rt(R) : 0;
   const size_t cap = std::max<size_t>((size_t)2 << 30, (size_t)h * R * N * part_elem);
@@ -1215,9 +1217,9 @@ mfs_status mfs_autotune(mfs_scene* s, int32_t R, mfs_prec prec, int32_t reps, mf
   if (sym_ok) {
     const int64_t NS = sym_view(s->dev).N;
     const SymPlan hp = sym_plan(NS, 0);
-    std::vector<int> rset{h_rt};
+    std::vector<int> rset{ghat_default_rt(R)};
     for (int rt : {1, 2, 4})
-      if (rt != h_rt && (rt == 1 || rt / 2 < R)) rset.push_back(rt);
+      if (rt != rset[0] && (rt == 1 || rt / 2 < R)) rset.push_back(rt);
     for (int f : {0, -2, -1, 1, 2}) {
       const int c = f < 0 ? (hp.nchunks_d >> -f) : (hp.nchunks_d << f);
       for (int rt : rset) add(LaunchShape{sym_plan(NS, std::max(1, std::min(c, kTuneMaxChunks))).nchunks_d, rt, 1});
@@ -1290,11 +1292,11 @@ mfs_status mfs_autotune(mfs_scene* s, int32_t R, mfs_prec prec, int32_t reps, mf
                           : (size_t)f32_slices(s, best_ls) * R * f32_rows(s, best_ls) * part_elem;
   if (s->partial.cap > 2 * need) release(s->partial, &s->bytes, st);
   res.nchunks = best_ls.nchunks;
-  res.rhs_per_thread = best_ls.rt;
+  res.rhs_per_thread = (v == kTunePairF32 || best_ls.sym == 1) ? (best_ls.rt ? best_ls.rt : ghat_default_rt(R)) : 0;
   res.ms = best;
   res.ms_heuristic = ms_h;
   res.n_tried = (int32_t)cands.size();
-  res.uses_mfma = v == kTunePairMfma ? 1 : 0;
+  res.uses_mfma = v == kTunePairMfma && best_ls.sym != 1 ? 1 : 0;
   res.symmetric = best_ls.sym == 1 ? 1 : 0;
   res.ms_plain = ms_plain;
   if (out) *out = res;
@@ -1310,7 +1312,8 @@ mfs_status mfs_tune_get(const mfs_scene* s, int32_t R, mfs_prec prec, int32_t* n
   int src = 0;
   const LaunchShape ls = shape_for(s, f64, R, &src);
   if (nchunks) *nchunks = ls.nchunks;
-  if (rhs_per_thread) *rhs_per_thread = v == kTunePairF32 ? (ls.rt ? ls.rt : ghat_default_rt(R)) : 0;
+  if (rhs_per_thread)
+    *rhs_per_thread = (v == kTunePairF32 || ls.sym == 1) ? (ls.rt ? ls.rt : ghat_default_rt(R)) : 0;
   if (symmetric) *symmetric = ls.sym == 1 ? 1 : 0;
   if (source) *source = src;
   return MFS_OK;

@@ -74,9 +74,11 @@ bool ghat_uses_mfma(const SceneDev& s, int R);
 // rt: right-hand sides per thread of the VALU kernel (1, 2 or 4; anything else picks by R);
 // ignored where the matrix-core kernel runs.
 int ghat_default_rt(int R);
-// Symmetric pair kernel (1 to 7 right-hand sides): groups of 256 points, G groups, distances 0..Dmax,
+// Symmetric pair kernel (1 to kSymMaxRhs right-hand sides): groups of 256 points, G groups, distances 0..Dmax,
 // nchunks_d distance chunks of dpc each; it writes `slices` partial slices (nchunks_d target-side,
 // Dsym source-side).  nchunks_d <= 0 picks the heuristic.
+constexpr int kSymMaxRhs = 32;         // the symmetric kernel may run up to this many right-hand sides
+constexpr int kSymDefaultMaxRhs = 24;  // and does by default up to this many
 struct SymPlan {
   int64_t G;
   int Dmax, Dsym, dpc, nchunks_d, slices;

@@ -1082,7 +1082,9 @@ SymPlan sym_plan(int64_t N, int nchunks_d) {
 }
 
 bool ghat_sym_possible(const SceneDev& s, int R) {
-  if (R < 1 || R >= kMfmaMinRhs || s.N <= 0) return false;
+  // up to 32 right-hand sides: the matrix-core kernel works on tiles of 64 of them, so below 32 most
+  // of its products are on zero padding and the symmetric VALU kernel does less work
+  if (R < 1 || R > kSymMaxRhs || s.N <= 0) return false;
   int64_t NP = s.N;
   if (!s.all_k_mult64) {
     // padded to whole tiles: worth it while the padded pair count stays below 1.4 times the real one

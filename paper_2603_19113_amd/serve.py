@@ -49,10 +49,10 @@ def footprint_bytes(N: int, T: int, R: int, dim: int, restart: int, n_targets: i
     allocations."""
     n_pad = N + 63 * T                             # bodies padded to whole 64-point tiles, at most
     scene = N * (8 * dim + 4 * dim + 4 * dim + 4 + 4 + 4) + T * (8 + 4 + 8 * dim) \
-        + n_pad * (4 * dim + 8) + T * 8 + (R * n_pad * 8 if R < 8 else 0)
+        + n_pad * (4 * dim + 8) + T * 8 + (R * n_pad * 8 if R <= 32 else 0)
     partial = max(_chunks(N, 1) * R * N * 16,      # FP64 pair sums (residuals)
                   _chunks(N, 2) * R * N * 8,       # FP32 plain kernel
-                  _sym_slices(n_pad) * R * n_pad * 8 if R < 8 else 0)  # FP32 symmetric kernel
+                  _sym_slices(n_pad) * R * n_pad * 8 if R <= 32 else 0)  # FP32 symmetric kernel
     q32 = R * N * 8
     nblk = (N + 1023) // 1024
     krylov = (restart + 1) * R * N * 8 + R * restart * (restart + 1) * 16 + 2 * R * (restart + 1) * nblk * 8 \

@@ -339,8 +339,10 @@ def test_solve_warm_start_resumes(mfs):
 @pytest.mark.parametrize("key", ["mixed24", "spheres6", "starfish32", "ragged9"])
 @pytest.mark.parametrize("R", [16, 20, 64])
 def test_ghat_many_rhs_matches_oracle(mfs, key, R):
-    """R >= 8 with every body a multiple of 16 points takes the matrix-core kernel (mixed, spheres,
-    starfish); ragged bodies stay on the VALU kernel.  R = 20 leaves a partial 64-RHS tile."""
+    """R >= 8 with every body a multiple of 16 points can take the matrix-core kernel (mixed,
+    spheres, starfish; R = 20 leaves a partial 64-RHS tile); up to 32 right-hand sides the symmetric
+    kernel is the default where it applies, so the matrix-core kernel is also forced; ragged bodies
+    stay on the plain VALU kernel."""
     torch = _torch()
     sc = SMALL_SCENES[key]()
     print(f"many-RHS G_hat {key} R={R}", flush=True)
@@ -349,13 +351,18 @@ def test_ghat_many_rhs_matches_oracle(mfs, key, R):
     rng = np.random.default_rng(31)
     q = crandn(rng, R, xh.shape[0])
     ref = gs.ghat_apply(xh, bo, sc.kappa, q)
-    t32 = torch.empty((R, gsc.N), dtype=torch.complex64, device="cuda")
-    mfs.ghat_apply(gsc, torch.from_numpy(q.astype(np.complex64)).cuda(), t32, mfs.MFS_FP32)
-    got = t32.cpu().numpy()
-    assert rel_err(got, ref) < fp32_matvec_budget(sc)
-    # every right-hand side on its own, not only in aggregate
-    for r in range(R):
-        assert rel_err(got[r], ref[r]) < fp32_matvec_budget(sc)
+    for forced in (False, True):
+        if forced:
+            if mfs.tune_get(gsc, R, mfs.MFS_FP32)["symmetric"] == 0:
+                break
+            mfs.tune_set(gsc, R, mfs.MFS_FP32, 4, 0, 0)  # the matrix-core kernel
+        t32 = torch.empty((R, gsc.N), dtype=torch.complex64, device="cuda")
+        mfs.ghat_apply(gsc, torch.from_numpy(q.astype(np.complex64)).cuda(), t32, mfs.MFS_FP32)
+        got = t32.cpu().numpy()
+        assert rel_err(got, ref) < fp32_matvec_budget(sc)
+        # every right-hand side on its own, not only in aggregate
+        for r in range(R):
+            assert rel_err(got[r], ref[r]) < fp32_matvec_budget(sc)
 
 
 def test_solve_many_rhs_mixed(mfs):

@@ -1,6 +1,6 @@
 """The symmetric pair kernel on the GPU against the FP64 oracle.
 
-With 1 to 7 right-hand sides in FP32 and every body holding a multiple of 64 points, the operator
+With 1 to 32 right-hand sides in FP32 and every body holding a multiple of 64 points, the operator
 evaluates phi once per unordered pair and adds it into both sums (G_hat is symmetric).  Its
 schedule (groups of 256 points meeting at cyclic distances, one-sided at distance 0 and G/2) has
 edge cases in the number of groups G: 1, 2 (both one-sided), odd and even G, a last group with
@@ -105,9 +105,9 @@ def test_symmetric_kernel_is_deterministic_and_used_only_where_it_applies(mfs):
     q = crandn(np.random.default_rng(32), 1, gsc.N)
     a, b = _ghat32(mfs, gsc, q), _ghat32(mfs, gsc, q)
     assert np.array_equal(a, b)
-    # eight or more right-hand sides (matrix cores), FP64, or bodies that would need too much
+    # more than 32 right-hand sides (matrix cores), FP64, or bodies that would need too much
     # padding to whole 64-point tiles (37 points -> 64): other kernels
-    for R, prec in ((8, mfs.MFS_FP32), (1, mfs.MFS_FP64)):
+    for R, prec in ((33, mfs.MFS_FP32), (1, mfs.MFS_FP64)):
         mfs.tune_set(gsc, R, prec, 8, 0, 1)
         assert mfs.tune_get(gsc, R, prec)["symmetric"] == 0
     sh = w.disk2d(radius=0.5, m=80, n=40, src_radius=0.35, k=37, rho_eq=0.6, p=81, r_psi=0.7)
@@ -139,13 +139,14 @@ def test_autotune_considers_both_kernels(mfs):
 
 
 @pytest.mark.parametrize("kind,T,R", [("disks", 13, 2), ("disks", 9, 3), ("starfish", 40, 5), ("spheres", 6, 3),
-                                      ("starfish", 7, 7)])
+                                      ("starfish", 7, 7), ("disks", 16, 13), ("starfish", 24, 32)])
 def test_symmetric_kernel_many_rhs(mfs, kind, T, R):
-    """2 to 7 right-hand sides: 1, 2 or 4 per thread, ragged last group of right-hand sides."""
+    """2 to 32 right-hand sides: 1, 2 or 4 per thread, ragged last group of right-hand sides."""
     sc = {"disks": _disks, "starfish": _starfish, "spheres": _spheres64}[kind](T)
     print(f"symmetric ghat {kind} T={T} R={R}", flush=True)
     gsc, _ = _scene(mfs, sc)
-    assert mfs.tune_get(gsc, R, mfs.MFS_FP32)["symmetric"] == 1
+    # untuned: symmetric up to 24 right-hand sides, the matrix cores above
+    assert mfs.tune_get(gsc, R, mfs.MFS_FP32)["symmetric"] == (1 if R <= 24 else 0)
     xh, ptr, bo = gs.pack(sc)
     q = crandn(np.random.default_rng(33), R, xh.shape[0])
     ref = gs.ghat_apply(xh, bo, sc.kappa, q)

@@ -106,12 +106,19 @@ def test_matrix_core_kernel_tuning(mfs):
     sc.directions = sc.directions[:16]
     gsc, Ss = _scene(mfs, sc)
     xh, ptr, bo = gs.pack(sc)
-    print("autotune mixed16 R=16 (matrix cores)", flush=True)
+    print("autotune mixed16 R=16 (matrix cores or symmetric)", flush=True)
     res = mfs.autotune(gsc, R=16, prec=mfs.MFS_FP32, reps=2)
-    assert res["uses_mfma"] == 1 and res["rhs_per_thread"] == 0
+    # 16 right-hand sides: the matrix-core kernel (tiles of 64) against the symmetric VALU kernel
+    assert res["uses_mfma"] + res["symmetric"] == 1 and res["ms_plain"] > 0
     q = crandn(np.random.default_rng(23), 16, xh.shape[0])
     ref = gs.matvec(sc, Ss, xh, ptr, bo, q)
     assert rel_err(_apply(mfs, gsc, q, mfs.MFS_FP32), ref) < fp32_matvec_budget(sc)
+    for sym in (0, 1):
+        mfs.tune_set(gsc, 16, mfs.MFS_FP32, 4, 0, sym)
+        got = mfs.tune_get(gsc, 16, mfs.MFS_FP32)
+        assert got["symmetric"] == sym and (got["rhs_per_thread"] == 0) == (sym == 0)
+        assert rel_err(_apply(mfs, gsc, q, mfs.MFS_FP32), ref) < fp32_matvec_budget(sc)
+    print("autotune mixed16:", res, flush=True)
     gsc.close()
 
 
