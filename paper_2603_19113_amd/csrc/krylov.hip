@@ -15,6 +15,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kElems = 4;   // vector elements per thread in the dot kernels
+constexpr int kElems32 = 2; // the inner products with a complex64 basis
 constexpr int kGroup = 16;  // basis vectors per dot-product block
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -26,7 +27,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // part[r][i][blk] = sum over the block's elements of conj(V_i[r][n]) w[r][n].
 // grid = (vector chunks, groups of kGroup basis vectors, right-hand sides): each block keeps its
 // chunk of w in registers and reads kGroup basis-vector chunks once.
-template <typename VT>
+template <typename VT, int ELEMS = kElems>
 __global__ __launch_bounds__(kThreads) void dots_kernel(const VT* __restrict__ V, const c128* __restrict__ w,
                                                         int64_t N, int R, int jcount_h, int nblk,
                                                         double* __restrict__ part, const int32_t* __restrict__ flag,
@@ -37,10 +38,10 @@ __global__ __launch_bounds__(kThreads) void dots_kernel(const VT* __restrict__ V
   const int jcount = jdev ? *jdev + 1 : jcount_h;
   const int i0 = blockIdx.y * kGroup;
   if (i0 >= jcount) return;  // graph replays size the grid for the largest step of their bucket
-  const int64_t base = (int64_t)blockIdx.x * (kThreads * kElems);
-  c128 wl[kElems];
+  const int64_t base = (int64_t)blockIdx.x * (kThreads * ELEMS);
+  c128 wl[ELEMS];
 #pragma unroll
-  for (int e = 0; e < kElems; ++e) {
+  for (int e = 0; e < ELEMS; ++e) {
     const int64_t n = base + e * kThreads + threadIdx.x;
     wl[e] = n < N ? w[(int64_t)r * N + n] : c128{0.0, 0.0};
   }
@@ -54,7 +55,7 @@ __global__ __launch_bounds__(kThreads) void dots_kernel(const VT* __restrict__ V
     if (i < jcount) {
       const VT* Vi = V + ((int64_t)i * R + r) * N;
 #pragma unroll
-      for (int e = 0; e < kElems; ++e) {
+      for (int e = 0; e < ELEMS; ++e) {
         const int64_t n = base + e * kThreads + threadIdx.x;
         if (n < N) {
           const VT xv = Vi[n];
@@ -469,14 +470,16 @@ hipError_t launch_arnoldi_orth(KrylovDev k, int j, c128* w, hipStream_t st) {
       hipLaunchKernelGGL(reorth_decide_kernel, dim3(k.R), dim3(256), 0, st, jc, k.R, ld, k.hcol, k.wn,
                          k.reorth, k.n_reorth, k.reorth_eta * k.reorth_eta, k.ratio_log, k.m,
                          (const int32_t*)k.jdev);
-    const dim3 dgrid(k.nblk, (jc + kGroup - 1) / kGroup, k.R);
+    // a complex64 basis: half the elements per thread and twice the blocks
+    const int nb = k.v32 ? (int)((k.N + kThreads * kElems32 - 1) / (kThreads * kElems32)) : k.nblk;
+    const dim3 dgrid(nb, (jc + kGroup - 1) / kGroup, k.R);
     if (k.v32)
-      hipLaunchKernelGGL(dots_kernel<c64>, dgrid, dim3(kThreads), 0, st, static_cast<const c64*>(k.V), w, k.N, k.R,
-                         jc, k.nblk, k.part, flag, (const int32_t*)k.jdev);
+      hipLaunchKernelGGL((dots_kernel<c64, kElems32>), dgrid, dim3(kThreads), 0, st, static_cast<const c64*>(k.V), w,
+                         k.N, k.R, jc, nb, k.part, flag, (const int32_t*)k.jdev);
     else
       hipLaunchKernelGGL(dots_kernel<c128>, dgrid, dim3(kThreads), 0, st, static_cast<const c128*>(k.V), w, k.N,
-                         k.R, jc, k.nblk, k.part, flag, (const int32_t*)k.jdev);
-    hipLaunchKernelGGL(dots_reduce_kernel, dim3(jc, k.R), dim3(64), 0, st, k.part, jc, k.nblk, k.R, ld, h,
+                         k.R, jc, nb, k.part, flag, (const int32_t*)k.jdev);
+    hipLaunchKernelGGL(dots_reduce_kernel, dim3(jc, k.R), dim3(64), 0, st, k.part, jc, nb, k.R, ld, h,
                        (const c128*)nullptr, flag, (const int32_t*)k.jdev);
     const dim3 agrid(blocks_for(k.N, kThreads), k.R);
     if (k.v32)
@@ -526,5 +529,8 @@ hipError_t launch_axpby(const c128* a, const c128* b, c128* out, double alpha, d
 }
 
 int krylov_nblk(int64_t N) { return (int)((N + kThreads * kElems - 1) / (kThreads * kElems)); }
+int krylov_part_blocks(int64_t N) {
+  return std::max(krylov_nblk(N), (int)((N + kThreads * kElems32 - 1) / (kThreads * kElems32)));
+}
 
 }  // namespace mfs

@@ -733,7 +733,7 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
   const size_t szH = sizeof(c128) * (size_t)R * m * (m + 1);
   const size_t szRm = sizeof(c128) * (size_t)R * m;
   const size_t szRm1 = sizeof(c128) * (size_t)R * (m + 1);
-  const size_t szPart = sizeof(double) * 2 * (size_t)R * (m + 1) * k.nblk;
+  const size_t szPart = sizeof(double) * 2 * (size_t)R * (m + 1) * krylov_part_blocks(N);
   size_t off = 0;
   auto carve = [&](size_t bytes) {
     const size_t o = off;

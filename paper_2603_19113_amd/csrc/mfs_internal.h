@@ -170,6 +170,7 @@ struct KrylovDev {
 constexpr int kStepBucket = 64;
 
 int krylov_nblk(int64_t N);
+int krylov_part_blocks(int64_t N);  // blocks per vector of the widest inner-product launch
 hipError_t launch_norms(const c128* v, int64_t N, int R, double* part, int nblk, double* out_norm,
                         hipStream_t st);
 hipError_t launch_start_cycle(KrylovDev k, const c128* r0, hipStream_t st);

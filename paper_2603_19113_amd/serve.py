@@ -54,7 +54,7 @@ def footprint_bytes(N: int, T: int, R: int, dim: int, restart: int, n_targets: i
                   _chunks(N, 2) * R * N * 8,       # FP32 plain kernel
                   _sym_slices(n_pad) * R * n_pad * 8 if R <= 32 else 0)  # FP32 symmetric kernel
     q32 = R * N * 8
-    nblk = (N + 1023) // 1024
+    nblk = (N + 511) // 512                       # partial inner products: widest launch
     krylov = (restart + 1) * R * N * 8 + R * restart * (restart + 1) * 16 + 2 * R * (restart + 1) * nblk * 8 \
         + 6 * R * (restart + 1) * 16
     vecs = 3 * R * N * 16
