@@ -34,15 +34,21 @@ METRIC = "Helmholtz pair-evals/s per matvec; GMRES solve time @1e-8 rel res; p50
 # 3D: u (12), r^2, rsq, r, D + r, rcp, delta (6), phase fma (2), fract (1), 1/(4 pi r) (1),
 # sin + cos (2), (re, im) (2), complex multiply-add (8) = 34.
 FLOP_PER_PAIR_F32 = {2: 42, 3: 34}
-# The symmetric kernel (one right-hand side) evaluates phi once per unordered pair and makes two
-# complex multiply-adds with it: (42 - 8) + 16 = 50 flop per unordered pair in 2D, (34 - 8) + 16 = 42
-# in 3D, i.e. 25 and 21 per (ordered) pair of the operator.
-# With R right-hand sides phi is shared by all of them: (phi / R + 16) / 2 per pair and right-hand side.
-PHI_FLOP_F32 = {2: 34, 3: 26}
+# phi alone, without the complex multiply-add (8): 34 and 26.
+PHI_FLOP_F32 = {d: f - 8 for d, f in FLOP_PER_PAIR_F32.items()}
+
+
+def flop_per_pair_plain(dim: int, R: int) -> float:
+    """Plain kernels: phi once per (ordered) pair, shared by the R right-hand sides of a launch."""
+    return PHI_FLOP_F32[dim] / R + 8
 
 
 def flop_per_pair_sym(dim: int, R: int) -> float:
+    """Symmetric kernel: phi once per unordered pair and two complex multiply-adds per right-hand
+    side, i.e. (phi / R + 16) / 2 per ordered pair and right-hand side (R = 1: 25 in 2D, 21 in 3D)."""
     return (PHI_FLOP_F32[dim] / R + 16) / 2
+
+
 # FP32 vector peak from the unit counts: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz =
 # 78.6 TFLOP/s.  The 157.3 TFLOP/s figure counts packed (two-wide) FP32 instructions, which every HIP
 # build here disables, so 78.6 is the ceiling these kernels can reach; both are reported.
@@ -459,7 +465,7 @@ def main() -> int:
         flop_pp, bound, peak, peak_alt = FLOP_PER_PAIR_RHS_MFMA, "mfma", PEAK_FP32_MFMA_TFLOPS, None
     else:
         # per pair and right-hand side: phi is shared by the R right-hand sides of a launch
-        flop_pp = flop_per_pair_sym(sc.dim, R) if on_sym else PHI_FLOP_F32[sc.dim] / R + 8
+        flop_pp = flop_per_pair_sym(sc.dim, R) if on_sym else flop_per_pair_plain(sc.dim, R)
         bound, peak, peak_alt = "alu", PEAK_FP32_VECTOR_TFLOPS, PEAK_FP32_PACKED_TFLOPS
     achieved = flop_pp * pairs_per_launch32 / (avg32 * 1e-3) / 1e12 if n32 else 0.0
     solve_times = [i["t_total_s"] for i in infos]
