@@ -30,7 +30,8 @@ __global__ __launch_bounds__(256) void sapply_kernel(const int64_t* __restrict__
   for (int j = threadIdx.x; j < k; j += blockDim.x) {
     const int64_t idx = (int64_t)r * NP + pstart + j;
     double re = 0, im = 0;  // the symmetric pair kernel leaves hundreds of slices: add in FP64
-    for (int c = 0; c < nchunks; ++c) {
+#pragma unroll 8
+    for (int c = 0; c < nchunks; ++c) {  // eight slice loads in flight per thread
       const Cplx<TS> v = partial[(int64_t)c * NPR + idx];
       re += (double)v.re;
       im += (double)v.im;
