@@ -510,10 +510,10 @@ __device__ __forceinline__ float wave_rotate_next(float x) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x134, 0xf, 0xf, false));
 }
 
-// All four target tiles against the staged source tile, every pair in the z >= 100 regime (the
-// common case): one pass over the 64 steps, phi of each (target, source) used for both sums of
-// each of the RT right-hand sides.
-template <int DIM, int RT, bool SYM>
+// All four target tiles against the staged source tile, every pair in the far regime (FAR = 2:
+// z >= 100, the common case; FAR = 1: z >= 12): one pass over the 64 steps, phi of each (target,
+// source) used for both sums of each of the RT right-hand sides.
+template <int DIM, int RT, bool SYM, int FAR>
 __device__ __forceinline__ void sym_steps4(const SymLds<DIM, RT>& sh, const BodyPhaseConsts& k, int lane,
                                            const float (&A)[kSymTiles], const float (&P)[kSymTiles][DIM],
                                            const float (&D)[kSymTiles], const float (&D2)[kSymTiles],
@@ -543,7 +543,7 @@ __device__ __forceinline__ void sym_steps4(const SymLds<DIM, RT>& sh, const Body
 #pragma unroll
         for (int d = 0; d < DIM; ++d) u = fmaf(P[m][d], ls[d], u);
         float pr, pi;
-        bp_phi<DIM, 2>(k, u, D[m], D2[m], ph0[m], pr, pi);
+        bp_phi<DIM, FAR>(k, u, D[m], D2[m], ph0[m], pr, pi);
 #pragma unroll
         for (int rr = 0; rr < RT; ++rr) {
           tr[m][rr] = fmaf(pr, qr[rr], fmaf(-pi, qi[rr], tr[m][rr]));
@@ -605,11 +605,19 @@ __device__ __forceinline__ void sym_tile(const SymLds<DIM, RT>& sh, const BodyPh
                                          const float (&qtr)[kSymTiles][RT], const float (&qti)[kSymTiles][RT],
                                          float (&tr)[kSymTiles][RT], float (&ti)[kSymTiles][RT], float (&ar)[RT],
                                          float (&ai)[RT]) {
-  bool fast = true;
+  bool all = true;
+  float dmin = 3.0e38f;
 #pragma unroll
-  for (int m = 0; m < kSymTiles; ++m) fast = fast && use[m] && (DIM == 3 || D[m] >= k.vfar_D);
-  if (fast) {
-    sym_steps4<DIM, RT, SYM>(sh, k, lane, A, P, D, D2, ph0, qtr, qti, tr, ti, ar, ai);
+  for (int m = 0; m < kSymTiles; ++m) {
+    all = all && use[m];
+    dmin = fminf(dmin, D[m]);
+  }
+  if (all && (DIM == 3 || dmin >= k.vfar_D)) {
+    sym_steps4<DIM, RT, SYM, 2>(sh, k, lane, A, P, D, D2, ph0, qtr, qti, tr, ti, ar, ai);
+    return;
+  }
+  if (DIM == 2 && all && dmin >= k.far_D) {  // closer scenes (serving at kappa 5 to 10)
+    sym_steps4<DIM, RT, SYM, 1>(sh, k, lane, A, P, D, D2, ph0, qtr, qti, tr, ti, ar, ai);
     return;
   }
 #pragma unroll
