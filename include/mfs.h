@@ -336,14 +336,16 @@ mfs_status mfs_pool_trim(void);
  * slices: more blocks in flight on a small system, but more partial sums for the S product to
  * read back), and on the VALU kernel each thread carries `rhs_per_thread` right-hand sides (1, 2
  * or 4; the matrix-core kernel, for 8 or more right-hand sides, has no such knob).  With 1 to 32
- * right-hand sides, FP32, and every body holding a multiple of 64 points, a symmetric kernel can
- * run instead: G_hat is symmetric, so it evaluates phi once per unordered pair of points and adds
- * it into both sums; there `nchunks` counts the chunks of group distances per target group, and
- * the kernel leaves about N / 512 further partial slices per right-hand side (at most 8 GiB of
- * them, else the plain kernel runs).  A scene uses, in this order: its own tuned shape for (precision, R); the
- * process-wide table, keyed by (dim, kernel, R, floor(log2 N)); the heuristic (the symmetric
- * kernel where it applies and R <= 24).  Slices are summed in a fixed order, so a given shape gives
- * reproducible results; another shape may change the last bits of the sums.
+ * right-hand sides in FP32, a symmetric kernel can run instead: G_hat is symmetric, so it
+ * evaluates phi once per unordered pair of points and adds it into both sums.  It works on tiles of
+ * 64 points of one body; bodies whose point count is not a multiple of 64 are padded with
+ * zero-charge points where that adds at most 40% to the pair count.  There `nchunks` counts the
+ * chunks of group distances per target group, and the kernel leaves about N / 512 further partial
+ * slices per right-hand side (at most 8 GiB of them, else another kernel runs).  A scene uses, in
+ * this order: its own tuned shape for (precision, R); the process-wide table, keyed by
+ * (dim, kernel, R, floor(log2 N)); the heuristic (the symmetric kernel where it applies and
+ * R <= 24).  Slices are summed in a fixed order, so a given shape gives reproducible results;
+ * another shape may change the last bits of the sums.
  * ------------------------------------------------------------------------------------------ */
 typedef struct {
   int32_t nchunks;         /* chosen source slices (distance chunks if symmetric) */
@@ -375,15 +377,15 @@ mfs_status mfs_tune_get(const mfs_scene* scene, int32_t R, mfs_prec prec, int32_
                         int32_t* rhs_per_thread, int32_t* symmetric, int32_t* source);
 
 /* Set the scene's own shape for (R, prec): 1 <= nchunks <= 1024; rhs_per_thread 0 = by R, or 1, 2,
- * 4; symmetric 1 or -1 = the symmetric kernel where it applies, 0 = the plain kernel.
- * nchunks = 0 removes the scene's entry. */
+ * 4; symmetric 1 = the symmetric kernel where it applies (up to 32 right-hand sides), -1 = as the
+ * heuristic (up to 24), 0 = never.  nchunks = 0 removes the scene's entry. */
 mfs_status mfs_tune_set(mfs_scene* scene, int32_t R, mfs_prec prec, int32_t nchunks, int32_t rhs_per_thread,
                         int32_t symmetric);
 
 /* The process-wide table as a text file: a header line, then one entry per line
- * ("dim kernel R log2N nchunks rhs_per_thread symmetric").  Loading merges into the table and is all or
- * nothing: a malformed file is rejected (MFS_ERR_ARG) and leaves the table unchanged.  Host only;
- * no device is touched. */
+ * ("dim kernel R log2N nchunks rhs_per_thread symmetric").  Loading merges into the table and is
+ * all or nothing: a malformed file is rejected (MFS_ERR_ARG) and leaves the table unchanged.  Host
+ * only; no device is touched. */
 mfs_status mfs_tune_save(const char* path);
 mfs_status mfs_tune_load(const char* path);
 mfs_status mfs_tune_clear(void);
