@@ -120,6 +120,22 @@ def test_footprint_grows_with_size_and_basis():
     assert restart_for(5000, 20.0, 2) == 4000  # capped
 
 
+def test_footprint_counts_the_symmetric_kernel_slices():
+    """Up to 32 right-hand sides the symmetric pair kernel may run; its partial slices (about N/512
+    per right-hand side, on bodies padded to 64-point tiles) must be in the estimate."""
+    from paper_2603_19113_amd.serve import _sym_slices
+
+    N, T = 32768, 256
+    n_pad = N + 63 * T
+    assert _sym_slices(256000) == 562           # the library's plan on the starfish scene
+    fp16 = footprint_bytes(N, T, 16, 2, 200)
+    assert fp16 >= _sym_slices(n_pad) * 16 * n_pad * 8
+    # beyond 32 right-hand sides the matrix-core kernel runs and needs no slices per distance
+    per_rhs_32 = footprint_bytes(N, T, 32, 2, 200) / 32
+    per_rhs_33 = footprint_bytes(N, T, 33, 2, 200) / 33
+    assert per_rhs_33 < per_rhs_32
+
+
 def test_batching_merges_same_geometry_within_rhs_cap():
     # slot 0 busy with request 0; then 1..6 queue up: geometries 7,7,8,7,7,7 with R = 3 each
     ref = [None]
