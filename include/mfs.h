@@ -179,7 +179,7 @@ mfs_status mfs_apply(const mfs_scene* scene, const void* q_dev, void* y_dev, int
  *              x += d; repeated until ||b - A x|| / ||b|| <= tol (FP64 residual) or max_refine.
  * Each right-hand side has its own Krylov space; the R operator applications of one iteration
  * share one pair-kernel launch.  Orthogonalisation is classical Gram-Schmidt with a second pass
- * where the first one cancelled (||w'|| < 0.2 ||w||).  The stopping test is
+ * where the first one cancelled (||w'|| < 0.1 ||w||).  The stopping test is
  * ||b - A x||_2 / ||b||_2 <= tol per column, checked with the FP64 operator before returning.
  * Synchronous.
  *   vhat_dev  device complex128 [R][N]: Dirichlet data at x_hat (b = S vhat is formed inside)
