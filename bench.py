@@ -253,7 +253,7 @@ def compare(args, sc, mfs, torch, np) -> int:
     t0 = time.perf_counter()
     info_m = mfs.solve(scene, v, q_mixed, tol=args.tol, maxit=60000, restart=args.restart, max_refine=20,
                        inner_tol=args.inner_tol, prec=mfs.MFS_MIXED, verbose=min(args.verbose, 1),
-                       basis32=not args.basis64)
+                       basis32=not args.basis64, deflate=not args.no_deflate)
     t_mixed = time.perf_counter() - t0
     log(f"[compare] mixed, {R} RHS together: {t_mixed:.2f} s  {info_m}")
     q64 = torch.empty_like(v)
@@ -304,6 +304,9 @@ def main() -> int:
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="profiling: first copy a buffer of this many MiB (calibrates rocprof byte counters)")
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-deflate", action="store_true",
+                    help="correction solves restart from scratch instead of deflating the first inner "
+                         "solve's Krylov space")
     ap.add_argument("--rhs", type=int, default=0,
                     help="use only the first RHS incident directions of the workload (0: all of them)")
     ap.add_argument("--no-tune", action="store_true",
@@ -400,7 +403,7 @@ def main() -> int:
         else:
             info = mfs.solve(scene, v, q, tol=args.tol, maxit=60000, restart=args.restart, max_refine=20,
                              inner_tol=args.inner_tol, prec=mfs.MFS_MIXED, verbose=args.verbose,
-                             basis32=not args.basis64)
+                             basis32=not args.basis64, deflate=not args.no_deflate)
         u = torch.empty((R, targets.shape[0]), dtype=torch.complex128, device="cuda")
         mfs.eval_field(scene, q, targets, u, mfs.MFS_FP64)
         torch.cuda.synchronize()

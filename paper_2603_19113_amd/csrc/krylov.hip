@@ -369,7 +369,8 @@ __global__ void step_advance_kernel(int32_t* __restrict__ jdev) {
 // y = H(0:len,0:len)^{-1} g(0:len), column-oriented back substitution; one block per right-hand
 // side: y_i = g_i / H_ii, then g_t -= H_ti y_i for t < i in parallel.  g is consumed.
 __global__ __launch_bounds__(1024) void hess_solve_kernel(int m, int R, const c128* __restrict__ H, c128* __restrict__ g,
-                                                          const int32_t* __restrict__ jlen, c128* __restrict__ y) {
+                                                          const int32_t* __restrict__ jlen, c128* __restrict__ y,
+                                                          int ylen) {
   __shared__ c128 yi_sh;
   const int r = blockIdx.x;
   const int len = jlen[r];
@@ -395,7 +396,80 @@ __global__ __launch_bounds__(1024) void hess_solve_kernel(int m, int R, const c1
     }
     __syncthreads();
   }
-  for (int i = len + threadIdx.x; i < m; i += blockDim.x) yr[i] = c128{0.0, 0.0};
+  for (int i = len + threadIdx.x; i < ylen; i += blockDim.x) yr[i] = c128{0.0, 0.0};
+}
+
+// Deflation in coefficient space: h[r][0..o) -= q[r] (q[r]^H h[r][0..o)), q of unit norm.  One
+// block per right-hand side; the inner product is reduced in a fixed order.
+__global__ __launch_bounds__(256) void deflate_coeffs_kernel(const c128* __restrict__ q, int o, c128* __restrict__ h,
+                                                             int ld, const int32_t* __restrict__ flag) {
+  __shared__ double red[2][4];
+  const int r = blockIdx.x;
+  if (flag && !flag[r]) return;
+  const c128* qr = q + (int64_t)r * ld;
+  c128* hr = h + (int64_t)r * ld;
+  double sr = 0.0, si = 0.0;
+  for (int i = threadIdx.x; i < o; i += blockDim.x) {  // conj(q_i) h_i
+    const c128 a = qr[i], b = hr[i];
+    sr += a.re * b.re + a.im * b.im;
+    si += a.re * b.im - a.im * b.re;
+  }
+  sr = wave_sum(sr);
+  si = wave_sum(si);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = sr;
+    red[1][threadIdx.x >> 6] = si;
+  }
+  __syncthreads();
+  const double tr = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+  const double ti = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  for (int i = threadIdx.x; i < o; i += blockDim.x) {
+    const c128 a = qr[i];
+    hr[i].re -= a.re * tr - a.im * ti;
+    hr[i].im -= a.re * ti + a.im * tr;
+  }
+}
+
+// Rotation i of a process acts on entries (i, i+1) as G_i = [[conj(c), conj(s)], [-s, c]] (the
+// Givens kernel's convention); G = G_{k-1} ... G_0 takes the Hessenberg matrix to triangular form.
+// q = G^H e_k, the unit vector orthogonal to the Hessenberg matrix's range, and e <- G e.  One
+// thread per right-hand side: a chain of k dependent rotations, run once per correction solve.
+__global__ void givens_last_column_kernel(const c128* __restrict__ cs, const c128* __restrict__ sn, int m, int R,
+                                          int kold, c128* __restrict__ q) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const c128* c = cs + (int64_t)r * m;
+  const c128* s = sn + (int64_t)r * m;
+  c128* qr = q + (int64_t)r * (m + 1);
+  for (int i = 0; i < kold; ++i) qr[i] = c128{0.0, 0.0};
+  qr[kold] = c128{1.0, 0.0};
+  for (int i = kold - 1; i >= 0; --i) {  // (x_i, x_{i+1}) <- (c x_i - conj(s) x_{i+1}, s x_i + conj(c) x_{i+1})
+    const c128 a = qr[i], b = qr[i + 1];
+    const c128 ci = c[i], si = s[i];
+    qr[i] = c128{ci.re * a.re - ci.im * a.im - (si.re * b.re + si.im * b.im),
+                 ci.re * a.im + ci.im * a.re - (si.re * b.im - si.im * b.re)};
+    qr[i + 1] = c128{si.re * a.re - si.im * a.im + (ci.re * b.re + ci.im * b.im),
+                     si.re * a.im + si.im * a.re + (ci.re * b.im - ci.im * b.re)};
+  }
+}
+
+__global__ void givens_apply_kernel(const c128* __restrict__ cs, const c128* __restrict__ sn, int m, int R, int kold,
+                                    c128* __restrict__ e) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const c128* c = cs + (int64_t)r * m;
+  const c128* s = sn + (int64_t)r * m;
+  c128* er = e + (int64_t)r * (m + 1);
+  c128 carry = er[0];
+  for (int i = 0; i < kold; ++i) {  // (x_i, x_{i+1}) <- (conj(c) x_i + conj(s) x_{i+1}, -s x_i + c x_{i+1})
+    const c128 b = er[i + 1];
+    const c128 ci = c[i], si = s[i];
+    er[i] = c128{ci.re * carry.re + ci.im * carry.im + si.re * b.re + si.im * b.im,
+                 ci.re * carry.im - ci.im * carry.re + si.re * b.im - si.im * b.re};
+    carry = c128{-(si.re * carry.re - si.im * carry.im) + ci.re * b.re - ci.im * b.im,
+                 -(si.re * carry.im + si.im * carry.re) + ci.re * b.im + ci.im * b.re};
+  }
+  er[kold] = carry;
 }
 
 // x[r][n] += sum_{i<len_r} y[r][i] V_i[r][n]
@@ -440,26 +514,33 @@ hipError_t launch_norms(const c128* v, int64_t N, int R, double* part, int nblk,
   return hipGetLastError();
 }
 
+// Basis vector `slot` of process k, and the per-column arrays shifted to the process's first index.
+template <typename VT>
+inline VT* slot_ptr(const KrylovDev& k, int slot) {
+  return static_cast<VT*>(k.V) + (int64_t)slot * k.R * k.N;
+}
+
 hipError_t launch_start_cycle(KrylovDev k, const c128* r0, hipStream_t st) {
   hipError_t e = launch_norms(r0, k.N, k.R, k.part, k.nblk, k.beta, st);
   if (e != hipSuccess) return e;
   if (k.v32)
     hipLaunchKernelGGL(start_scale_kernel<c64>, dim3(blocks_for(k.N, 256), k.R), dim3(256), 0, st, r0, k.beta, k.N,
-                       k.R, static_cast<c64*>(k.V));
+                       k.R, slot_ptr<c64>(k, k.joff));
   else
     hipLaunchKernelGGL(start_scale_kernel<c128>, dim3(blocks_for(k.N, 256), k.R), dim3(256), 0, st, r0, k.beta, k.N,
-                       k.R, static_cast<c128*>(k.V));
+                       k.R, slot_ptr<c128>(k, k.joff));
   hipLaunchKernelGGL(start_state_kernel, dim3(blocks_for(k.R, 64)), dim3(64), 0, st, k.beta, k.bnorm, k.active,
-                     k.jlen, k.g, k.res, k.m, k.R, k.jdev, k.tol_dev, k.tol);
+                     k.jlen, k.g + k.joff, k.res, k.m, k.R, k.jdev, k.tol_dev, k.tol);
   return hipGetLastError();
 }
 
 // Gram-Schmidt: hcol = V^H w; w -= V hcol; then, where the first pass cancelled, h2 = V^H w;
 // w -= V h2 (the H column is hcol + h2, summed in the Givens kernel).
 hipError_t launch_arnoldi_orth(KrylovDev k, int j, c128* w, hipStream_t st) {
+  if (k.joff != 0 && k.jdev) return hipErrorInvalidValue;  // offset processes launch eagerly
   // With a device step counter (graph replay) the grids cover the largest step of j's bucket and
   // the kernels read the actual step from k.jdev.
-  const int jc = k.jdev ? std::min(k.m, (j / kStepBucket + 1) * kStepBucket) : j + 1;
+  const int jc = k.jdev ? std::min(k.m, (j / kStepBucket + 1) * kStepBucket) : k.joff + j + 1;
   const int ld = k.m + 1;
   hipError_t e = launch_norms(w, k.N, k.R, k.part, k.nblk, k.wn, st);
   if (e != hipSuccess) return e;
@@ -481,6 +562,8 @@ hipError_t launch_arnoldi_orth(KrylovDev k, int j, c128* w, hipStream_t st) {
                          k.R, jc, nb, k.part, flag, (const int32_t*)k.jdev);
     hipLaunchKernelGGL(dots_reduce_kernel, dim3(jc, k.R), dim3(64), 0, st, k.part, jc, nb, k.R, ld, h,
                        (const c128*)nullptr, flag, (const int32_t*)k.jdev);
+    if (k.qdef)
+      hipLaunchKernelGGL(deflate_coeffs_kernel, dim3(k.R), dim3(256), 0, st, k.qdef, k.joff, h, ld, flag);
     const dim3 agrid(blocks_for(k.N, kThreads), k.R);
     if (k.v32)
       hipLaunchKernelGGL(basis_axpy_kernel<c64>, agrid, dim3(kThreads), 0, st, static_cast<const c64*>(k.V), h, ld,
@@ -496,28 +579,83 @@ hipError_t launch_arnoldi_orth(KrylovDev k, int j, c128* w, hipStream_t st) {
 hipError_t launch_arnoldi_finish(KrylovDev k, int j, c128* w, double tol, hipStream_t st) {
   hipError_t e = launch_norms(w, k.N, k.R, k.part, k.nblk, k.hnorm, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(givens_kernel, dim3(k.R), dim3(kGivensThreads), 0, st, j, k.m, k.R, 1.0, k.hcol, k.h2, k.hnorm,
-                     k.H, k.cs, k.sn, k.g, k.res, k.bnorm, tol, k.active, k.jlen, (const int32_t*)k.jdev,
-                     (const double*)k.tol_dev);
+  const int o = k.joff;
+  hipLaunchKernelGGL(givens_kernel, dim3(k.R), dim3(kGivensThreads), 0, st, j, k.m, k.R, 1.0, k.hcol + o, k.h2 + o,
+                     k.hnorm, k.H + (int64_t)o * (k.m + 1), k.cs + o, k.sn + o, k.g + o, k.res, k.bnorm, tol, k.active,
+                     k.jlen, (const int32_t*)k.jdev, (const double*)k.tol_dev);
   if (k.v32)
     hipLaunchKernelGGL(scale_next_kernel<c64>, dim3(blocks_for(k.N, 256), k.R), dim3(256), 0, st, w, k.hnorm, k.N,
-                       k.R, static_cast<c64*>(k.V), j, (const int32_t*)k.jdev);
+                       k.R, slot_ptr<c64>(k, o), j, (const int32_t*)k.jdev);
   else
     hipLaunchKernelGGL(scale_next_kernel<c128>, dim3(blocks_for(k.N, 256), k.R), dim3(256), 0, st, w, k.hnorm, k.N,
-                       k.R, static_cast<c128*>(k.V), j, (const int32_t*)k.jdev);
+                       k.R, slot_ptr<c128>(k, o), j, (const int32_t*)k.jdev);
   if (k.jdev) hipLaunchKernelGGL(step_advance_kernel, dim3(1), dim3(64), 0, st, k.jdev);
   return hipGetLastError();
 }
 
 // y = H^{-1} g per column, then x += V y.
 hipError_t launch_gmres_update_x(KrylovDev k, c128* x, hipStream_t st) {
-  hipLaunchKernelGGL(hess_solve_kernel, dim3(k.R), dim3(1024), 0, st, k.m, k.R, k.H, k.g, k.jlen, k.y);
+  const int o = k.joff;
+  hipLaunchKernelGGL(hess_solve_kernel, dim3(k.R), dim3(1024), 0, st, k.m, k.R, k.H + (int64_t)o * (k.m + 1),
+                     k.g + o, k.jlen, k.y + o, k.m - o);
+  return launch_update_from_y(k, x, st);
+}
+
+hipError_t launch_update_from_y(KrylovDev k, c128* x, hipStream_t st) {
+  const int o = k.joff;
   if (k.v32)
     hipLaunchKernelGGL(update_x_kernel<c64>, dim3(blocks_for(k.N, kThreads), k.R), dim3(kThreads), 0, st,
-                       static_cast<const c64*>(k.V), k.y, k.jlen, k.m, k.N, k.R, x);
+                       slot_ptr<c64>(k, o), k.y + o, k.jlen, k.m, k.N, k.R, x);
   else
     hipLaunchKernelGGL(update_x_kernel<c128>, dim3(blocks_for(k.N, kThreads), k.R), dim3(kThreads), 0, st,
-                       static_cast<const c128*>(k.V), k.y, k.jlen, k.m, k.N, k.R, x);
+                       slot_ptr<c128>(k, o), k.y + o, k.jlen, k.m, k.N, k.R, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_basis_dots(KrylovDev k, const c128* w, int count, c128* out, hipStream_t st) {
+  if (count < 1 || count > k.m + 1) return hipErrorInvalidValue;
+  const int ld = k.m + 1;
+  const int nb = k.v32 ? (int)((k.N + kThreads * kElems32 - 1) / (kThreads * kElems32)) : k.nblk;
+  const dim3 dgrid(nb, (count + kGroup - 1) / kGroup, k.R);
+  if (k.v32)
+    hipLaunchKernelGGL((dots_kernel<c64, kElems32>), dgrid, dim3(kThreads), 0, st, static_cast<const c64*>(k.V), w,
+                       k.N, k.R, count, nb, k.part, (const int32_t*)nullptr, (const int32_t*)nullptr);
+  else
+    hipLaunchKernelGGL(dots_kernel<c128>, dgrid, dim3(kThreads), 0, st, static_cast<const c128*>(k.V), w, k.N, k.R,
+                       count, nb, k.part, (const int32_t*)nullptr, (const int32_t*)nullptr);
+  hipLaunchKernelGGL(dots_reduce_kernel, dim3(count, k.R), dim3(64), 0, st, k.part, count, nb, k.R, ld, out,
+                     (const c128*)nullptr, (const int32_t*)nullptr, (const int32_t*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_basis_axpy(KrylovDev k, const c128* h, int count, c128* w, hipStream_t st) {
+  if (count < 1 || count > k.m + 1) return hipErrorInvalidValue;
+  const dim3 agrid(blocks_for(k.N, kThreads), k.R);
+  if (k.v32)
+    hipLaunchKernelGGL(basis_axpy_kernel<c64>, agrid, dim3(kThreads), 0, st, static_cast<const c64*>(k.V), h, k.m + 1,
+                       k.N, k.R, count, w, (const int32_t*)nullptr, (const int32_t*)nullptr);
+  else
+    hipLaunchKernelGGL(basis_axpy_kernel<c128>, agrid, dim3(kThreads), 0, st, static_cast<const c128*>(k.V), h,
+                       k.m + 1, k.N, k.R, count, w, (const int32_t*)nullptr, (const int32_t*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_givens_last_column(KrylovDev k, int kold, c128* q, hipStream_t st) {
+  if (kold < 0 || kold >= k.m) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(givens_last_column_kernel, dim3(blocks_for(k.R, 64)), dim3(64), 0, st, k.cs, k.sn, k.m, k.R,
+                     kold, q);
+  return hipGetLastError();
+}
+
+hipError_t launch_givens_apply(KrylovDev k, int kold, c128* e, hipStream_t st) {
+  if (kold < 0 || kold >= k.m) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(givens_apply_kernel, dim3(blocks_for(k.R, 64)), dim3(64), 0, st, k.cs, k.sn, k.m, k.R, kold, e);
+  return hipGetLastError();
+}
+
+hipError_t launch_deflate_coeffs(const c128* q, int o, c128* h, int R, int ld, const int32_t* flag, hipStream_t st) {
+  if (o < 1 || o > ld) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(deflate_coeffs_kernel, dim3(R), dim3(256), 0, st, q, o, h, ld, flag);
   return hipGetLastError();
 }
 

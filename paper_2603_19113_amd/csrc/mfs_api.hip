@@ -744,7 +744,8 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
                oh1 = carve(szRm1), oh2 = carve(szRm1), oy = carve(szRm), obeta = carve(8 * R), obn = carve(8 * R),
                ores = carve(8 * R), ohn = carve(8 * R), oact = carve(4 * R), ojl = carve(4 * R),
                own = carve(8 * R), oro = carve(4 * R), onro = carve(4 * R), opart = carve(szPart),
-               ojdev = carve(sizeof(int32_t)), otol = carve(sizeof(double));
+               ojdev = carve(sizeof(int32_t)), otol = carve(sizeof(double)), oq = carve(szRm1),
+               ocr = carve(szRm1), oee = carve(szRm1), ojold = carve(4 * R), orn2 = carve(8 * R);
   MFS_TRY(ensure(s->kry, off, &s->bytes, st));
   char* base = static_cast<char*>(s->kry.p);
   k.V = base + oV;
@@ -769,6 +770,11 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
   const bool use_graph = opts->use_graph != 0;
   k.jdev = use_graph ? reinterpret_cast<int32_t*>(base + ojdev) : nullptr;
   k.tol_dev = use_graph ? reinterpret_cast<double*>(base + otol) : nullptr;
+  c128* qdef = reinterpret_cast<c128*>(base + oq);      // deflation: q = G^H e_kold
+  c128* cdef = reinterpret_cast<c128*>(base + ocr);     // V_old^H r of the correction's residual
+  c128* edef = reinterpret_cast<c128*>(base + oee);     // coefficient work vector
+  int32_t* jold = reinterpret_cast<int32_t*>(base + ojold);
+  double* rn2 = reinterpret_cast<double*>(base + orn2);
   MFS_HIP_TRY(hipMemsetAsync(k.n_reorth, 0, sizeof(int32_t) * R, st));
   // Second Gram-Schmidt pass when ||w'|| < 0.1 ||w||.  Measured: on 1000 starfish the median ratio
   // is 0.26 and eta = 0.2 takes the second pass on 26% of steps (93% for eta = 1/sqrt(2)); on 2000
@@ -857,7 +863,7 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
   } graphs;
   if (use_graph) graphs.exec.assign((m + kStepBucket - 1) / kStepBucket, nullptr);
   auto krylov_step = [&](const KrylovDev& kk, int j, double ktol) -> mfs_status {
-    if (!use_graph) {
+    if (!use_graph || !kk.jdev) {
       MFS_HIP_TRY(launch_arnoldi_orth(kk, j, w, st));
       MFS_HIP_TRY(launch_arnoldi_finish(kk, j, w, ktol, st));
       return MFS_OK;
@@ -887,26 +893,27 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
     return MFS_OK;
   };
 
-  // one GMRES cycle from the residual in r; x += V y.  Returns after m steps, convergence of all
+  // one GMRES cycle from the residual in r; x += V y.  Returns after mlim steps, convergence of all
   // active columns to ktol (relative to kk.bnorm), or the iteration budget.
-  auto cycle = [&](KrylovDev kk, double ktol, bool mixed) -> mfs_status {
+  auto cycle = [&](KrylovDev kk, double ktol, bool mixed, int mlim) -> mfs_status {
     kk.tol = ktol;
     MFS_HIP_TRY(launch_start_cycle(kk, r, st));
     double est_max = 1.0;
     int read_j = -1;  // last step whose flags the host has read
     bool stop = false;
-    for (int j = 0; j < m && !stop; ++j) {
+    const int64_t slot0 = kk.joff;
+    for (int j = 0; j < mlim && !stop; ++j) {
       // Arnoldi on the compact part K = S G_hat: w = K v_j, and H(I + K) = H(K) + I (the shift is
       // added in the Givens kernel); the identity's large projection on v_j never enters w.
       if (kk.v32) {
-        MFS_TRY(apply_mixed_from32(s, static_cast<const c64*>(kk.V) + (int64_t)j * NR, w, R, st));
+        MFS_TRY(apply_mixed_from32(s, static_cast<const c64*>(kk.V) + (slot0 + j) * NR, w, R, st));
         ++n32;
       } else if (mixed && (opts->fp64_until <= 0.0 || !(est_max > opts->fp64_until))) {
-        c128* Vj = static_cast<c128*>(kk.V) + (int64_t)j * NR;
+        c128* Vj = static_cast<c128*>(kk.V) + (slot0 + j) * NR;
         MFS_TRY(apply_mixed(s, Vj, w, R, st, 0.0));
         ++n32;
       } else {
-        c128* Vj = static_cast<c128*>(kk.V) + (int64_t)j * NR;
+        c128* Vj = static_cast<c128*>(kk.V) + (slot0 + j) * NR;
         MFS_TRY(apply_f64(s, Vj, w, R, st, 0.0));
         ++n64;
       }
@@ -916,7 +923,7 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
       MFS_HIP_TRY(hipMemcpyAsync(pin_act + slot * R, kk.active, sizeof(int32_t) * R, hipMemcpyDeviceToHost, st));
       MFS_HIP_TRY(hipMemcpyAsync(pin_res + slot * R, kk.res, sizeof(double) * R, hipMemcpyDeviceToHost, st));
       MFS_HIP_TRY(hipEventRecord(guard.ev[slot], st));
-      const bool last = j + 1 == m || total_it >= opts->maxit;
+      const bool last = j + 1 == mlim || total_it >= opts->maxit;
       const int lag = (last || !(est_max > 16.0 * ktol)) ? 0 : kSlots - 1;
       while (read_j < j - lag && !stop) {
         ++read_j;
@@ -967,7 +974,7 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
   if (prec == MFS_FP64) {
     while (max_relres() > opts->tol && total_it < opts->maxit) {
       MFS_TRY(set_active_from_relres());
-      MFS_TRY(cycle(k, opts->tol, false));
+      MFS_TRY(cycle(k, opts->tol, false, m));
       ++n_restart;
       MFS_TRY(residual());
       if (opts->verbose)
@@ -975,13 +982,67 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
                      max_relres());
     }
   } else {
+    // Deflated correction solves (GCRO, de Sturler 1996; one right-hand side): the first inner
+    // solve's kold Arnoldi steps give K~ V_k = V_{k+1} Hbar with Hbar = G^H [Rk; 0].  A later
+    // correction solve keeps them: C = V_{k+1} Q (Q the first k columns of G^H) is an orthonormal
+    // basis of K~ V_k, and U = V_k Rk^{-1} satisfies K~ U = C.  The new process runs on
+    // (I - C C^H) K~ from (I - C C^H) r, its basis stored after V_{k+1}; the correction is
+    // d = W y + U C^H (r - K~ W y).  The new steps thus work only on what the first Krylov space has
+    // not resolved, instead of rebuilding it from scratch.
+    const bool deflate = opts->deflate != 0 && R == 1;
+    int kold = -1;  // steps of the kept process, -1 while none is kept
+    auto keep_space = [&]() -> mfs_status {
+      int32_t jl = 0;
+      MFS_HIP_TRY(hipMemcpyAsync(&jl, k.jlen, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      MFS_HIP_TRY(hipStreamSynchronize(st));
+      // room for at least 64 new steps after the kept vectors
+      if (jl < 1 || jl + 1 + 64 > m) return MFS_OK;
+      kold = jl;
+      MFS_HIP_TRY(hipMemcpyAsync(jold, k.jlen, sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+      MFS_HIP_TRY(launch_givens_last_column(k, kold, qdef, st));
+      return MFS_OK;
+    };
+    auto deflated_cycle = [&](double ktol) -> mfs_status {
+      const int o = kold + 1;
+      KrylovDev kd = k;
+      kd.joff = o;
+      kd.qdef = qdef;
+      kd.jdev = nullptr;
+      kd.tol_dev = nullptr;
+      kd.bnorm = rn2;  // estimate relative to the correction's own residual, before the projection
+      MFS_HIP_TRY(launch_norms(r, N, R, k.part, k.nblk, rn2, st));
+      // c = V_{k+1}^H r;  r <- r - V_{k+1} (c - q q^H c) = (I - C C^H) r
+      MFS_HIP_TRY(launch_basis_dots(k, r, o, cdef, st));
+      MFS_HIP_TRY(hipMemcpyAsync(edef, cdef, sizeof(c128) * o, hipMemcpyDeviceToDevice, st));
+      MFS_HIP_TRY(launch_deflate_coeffs(qdef, o, edef, R, m + 1, nullptr, st));
+      MFS_HIP_TRY(launch_basis_axpy(k, edef, o, r, st));
+      MFS_TRY(cycle(kd, ktol, true, m - o));  // x += W y
+      // x += U C^H (r - K~ W y) = V_k Rk^{-1} [G (c - V_{k+1}^H K~ W y)]_{0..k-1}
+      MFS_HIP_TRY(hipMemsetAsync(r, 0, sizeof(c128) * NR, st));
+      MFS_HIP_TRY(launch_update_from_y(kd, r, st));  // r = W y
+      MFS_TRY(apply_mixed(s, r, w, R, st, 0.0));     // w = K~ W y
+      ++n32;
+      MFS_HIP_TRY(launch_basis_dots(k, w, o, edef, st));
+      MFS_HIP_TRY(launch_axpby(cdef, edef, edef, 1.0, -1.0, o, st));
+      MFS_HIP_TRY(launch_givens_apply(k, kold, edef, st));
+      KrylovDev kz = k;
+      kz.g = edef;
+      kz.jlen = jold;
+      MFS_HIP_TRY(launch_gmres_update_x(kz, x, st));
+      return MFS_OK;
+    };
     while (max_relres() > opts->tol && n_refine < opts->max_refine && total_it < opts->maxit) {
       MFS_TRY(set_active_from_relres());
       KrylovDev kk = k;
       kk.bnorm = kk.beta;  // inner estimate relative to the current residual
       // ask each inner solve for no more reduction than the outer tolerance still needs
       const double itol = std::max(opts->inner_tol, 0.3 * opts->tol / std::max(max_relres(), 1e-300));
-      MFS_TRY(cycle(kk, std::min(itol, 0.5), true));
+      if (kold > 0) {
+        MFS_TRY(deflated_cycle(std::min(itol, 0.5)));
+      } else {
+        MFS_TRY(cycle(kk, std::min(itol, 0.5), true, m));
+        if (deflate) MFS_TRY(keep_space());
+      }
       ++n_refine;
       ++n_restart;
       MFS_TRY(residual());

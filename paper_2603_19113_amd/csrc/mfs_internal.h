@@ -164,6 +164,15 @@ struct KrylovDev {
   int32_t* jdev;
   double* tol_dev;
   double tol;         // tolerance written to tol_dev at the cycle start
+  // Deflated correction solves (GCRO, one right-hand side): the process starts at basis slot joff,
+  // after the joff vectors V_0..V_{joff-1} of an earlier process that are kept; its Hessenberg
+  // column, rotation, g and y entries sit at index joff + j of their arrays.  Each step's
+  // Gram-Schmidt runs over all joff + j + 1 vectors and replaces the coefficients a on the kept
+  // vectors by a - qdef (qdef^H a), which removes only the part along C = V_old Q (Q^H qdef = 0,
+  // the columns of Q spanning the range of the kept process's Hessenberg matrix).  Eager launches
+  // only (jdev null).  joff = 0 and qdef null otherwise.
+  int joff;
+  const c128* qdef;
 };
 
 // Steps per captured graph: the graph of bucket b serves steps b*kStepBucket ... (b+1)*kStepBucket-1.
@@ -177,6 +186,16 @@ hipError_t launch_start_cycle(KrylovDev k, const c128* r0, hipStream_t st);
 hipError_t launch_arnoldi_orth(KrylovDev k, int j, c128* w, hipStream_t st);
 hipError_t launch_arnoldi_finish(KrylovDev k, int j, c128* w, double tol, hipStream_t st);
 hipError_t launch_gmres_update_x(KrylovDev k, c128* x, hipStream_t st);
+// Deflation helpers (one right-hand side):
+//   out = V_{0..count-1}^H w;  w -= V_{0..count-1} h;  x += sum_{i<jlen} y_{joff+i} V_{joff+i}
+//   q = G^H e_kold and e = G e (rotations 0..kold-1 of the process that built the kept vectors)
+//   h -= q (q^H h) over the first o entries
+hipError_t launch_basis_dots(KrylovDev k, const c128* w, int count, c128* out, hipStream_t st);
+hipError_t launch_basis_axpy(KrylovDev k, const c128* h, int count, c128* w, hipStream_t st);
+hipError_t launch_update_from_y(KrylovDev k, c128* x, hipStream_t st);
+hipError_t launch_givens_last_column(KrylovDev k, int kold, c128* q, hipStream_t st);
+hipError_t launch_givens_apply(KrylovDev k, int kold, c128* e, hipStream_t st);
+hipError_t launch_deflate_coeffs(const c128* q, int o, c128* h, int R, int ld, const int32_t* flag, hipStream_t st);
 hipError_t launch_axpby(const c128* a, const c128* b, c128* out, double alpha, double beta, int64_t n,
                         hipStream_t st);
 
