@@ -208,14 +208,15 @@ typedef struct {
   int32_t basis32;   /* MFS_MIXED with fp64_until = 0: 1 stores the Krylov basis in complex64
                         (half the memory and basis traffic; inner products, the Hessenberg matrix,
                         rotations and the solution update stay FP64).  0: complex128 basis */
-  int32_t deflate;   /* MFS_MIXED with R = 1: 1 keeps the first inner solve's Krylov space (its
-                        basis, rotations and triangular factor stay in the basis workspace) and runs
-                        every later correction solve on the operator deflated by it (GCRO): the new
-                        Arnoldi vectors follow the kept ones in the same workspace, each step's
-                        Gram-Schmidt runs over both, and one more FP32 operator application per
-                        correction adds the component in the kept space.  Needs room for 64 new
-                        steps after the kept ones (restart >= kept steps + 65), else plain restarts.
-                        Ignored for R > 1 or MFS_FP64.  0: each correction solve starts afresh */
+  int32_t deflate;   /* MFS_MIXED: 1 keeps the first inner solve's Krylov space (its basis,
+                        rotations and triangular factor stay in the basis workspace; each column
+                        keeps its own) and runs every later correction solve on the operator
+                        deflated by it (GCRO): the new Arnoldi vectors follow the longest kept
+                        space in the same workspace, each step's Gram-Schmidt runs over both, and
+                        one more FP32 operator application per correction adds the component in
+                        the kept space.  Needs room for 64 new steps after the kept ones
+                        (restart >= longest kept space + 65), else plain restarts.  Ignored for
+                        MFS_FP64.  0: each correction solve starts afresh */
 } mfs_solve_opts;
 
 typedef struct {

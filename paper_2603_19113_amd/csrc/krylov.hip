@@ -399,17 +399,28 @@ __global__ __launch_bounds__(1024) void hess_solve_kernel(int m, int R, const c1
   for (int i = len + threadIdx.x; i < ylen; i += blockDim.x) yr[i] = c128{0.0, 0.0};
 }
 
-// Deflation in coefficient space: h[r][0..o) -= q[r] (q[r]^H h[r][0..o)), q of unit norm.  One
-// block per right-hand side; the inner product is reduced in a fixed order.
-__global__ __launch_bounds__(256) void deflate_coeffs_kernel(const c128* __restrict__ q, int o, c128* __restrict__ h,
-                                                             int ld, const int32_t* __restrict__ flag) {
+// Deflation in coefficient space for column r, which kept kold[r] + 1 <= o vectors:
+// h[r][0..or) -= q[r] (q[r]^H h[r][0..or)) with or = kold[r] + 1 and q of unit norm, and the
+// coefficients on the slots or..o-1 (vectors of steps after the column had converged) are zeroed.
+// A column with keep[r] == 0 gets all o coefficients zeroed.  One block per right-hand side; the
+// inner product is reduced in a fixed order.
+__global__ __launch_bounds__(256) void deflate_coeffs_kernel(const c128* __restrict__ q, int o,
+                                                             const int32_t* __restrict__ kold, c128* __restrict__ h,
+                                                             int ld, const int32_t* __restrict__ flag,
+                                                             const int32_t* __restrict__ keep) {
   __shared__ double red[2][4];
   const int r = blockIdx.x;
   if (flag && !flag[r]) return;
   const c128* qr = q + (int64_t)r * ld;
   c128* hr = h + (int64_t)r * ld;
+  if (keep && !keep[r]) {
+    for (int i = threadIdx.x; i < o; i += blockDim.x) hr[i] = c128{0.0, 0.0};
+    return;
+  }
+  const int orr = min(o, kold[r] + 1);
+  for (int i = orr + threadIdx.x; i < o; i += blockDim.x) hr[i] = c128{0.0, 0.0};
   double sr = 0.0, si = 0.0;
-  for (int i = threadIdx.x; i < o; i += blockDim.x) {  // conj(q_i) h_i
+  for (int i = threadIdx.x; i < orr; i += blockDim.x) {  // conj(q_i) h_i
     const c128 a = qr[i], b = hr[i];
     sr += a.re * b.re + a.im * b.im;
     si += a.re * b.im - a.im * b.re;
@@ -423,7 +434,7 @@ __global__ __launch_bounds__(256) void deflate_coeffs_kernel(const c128* __restr
   __syncthreads();
   const double tr = red[0][0] + red[0][1] + red[0][2] + red[0][3];
   const double ti = red[1][0] + red[1][1] + red[1][2] + red[1][3];
-  for (int i = threadIdx.x; i < o; i += blockDim.x) {
+  for (int i = threadIdx.x; i < orr; i += blockDim.x) {
     const c128 a = qr[i];
     hr[i].re -= a.re * tr - a.im * ti;
     hr[i].im -= a.re * ti + a.im * tr;
@@ -435,9 +446,10 @@ __global__ __launch_bounds__(256) void deflate_coeffs_kernel(const c128* __restr
 // q = G^H e_k, the unit vector orthogonal to the Hessenberg matrix's range, and e <- G e.  One
 // thread per right-hand side: a chain of k dependent rotations, run once per correction solve.
 __global__ void givens_last_column_kernel(const c128* __restrict__ cs, const c128* __restrict__ sn, int m, int R,
-                                          int kold, c128* __restrict__ q) {
+                                          const int32_t* __restrict__ koldv, c128* __restrict__ q) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= R) return;
+  const int kold = koldv[r];
   const c128* c = cs + (int64_t)r * m;
   const c128* s = sn + (int64_t)r * m;
   c128* qr = q + (int64_t)r * (m + 1);
@@ -453,10 +465,11 @@ __global__ void givens_last_column_kernel(const c128* __restrict__ cs, const c12
   }
 }
 
-__global__ void givens_apply_kernel(const c128* __restrict__ cs, const c128* __restrict__ sn, int m, int R, int kold,
-                                    c128* __restrict__ e) {
+__global__ void givens_apply_kernel(const c128* __restrict__ cs, const c128* __restrict__ sn, int m, int R,
+                                    const int32_t* __restrict__ koldv, c128* __restrict__ e) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= R) return;
+  const int kold = koldv[r];
   const c128* c = cs + (int64_t)r * m;
   const c128* s = sn + (int64_t)r * m;
   c128* er = e + (int64_t)r * (m + 1);
@@ -563,7 +576,8 @@ hipError_t launch_arnoldi_orth(KrylovDev k, int j, c128* w, hipStream_t st) {
     hipLaunchKernelGGL(dots_reduce_kernel, dim3(jc, k.R), dim3(64), 0, st, k.part, jc, nb, k.R, ld, h,
                        (const c128*)nullptr, flag, (const int32_t*)k.jdev);
     if (k.qdef)
-      hipLaunchKernelGGL(deflate_coeffs_kernel, dim3(k.R), dim3(256), 0, st, k.qdef, k.joff, h, ld, flag);
+      hipLaunchKernelGGL(deflate_coeffs_kernel, dim3(k.R), dim3(256), 0, st, k.qdef, k.joff,
+                         (const int32_t*)k.kold, h, ld, flag, (const int32_t*)nullptr);
     const dim3 agrid(blocks_for(k.N, kThreads), k.R);
     if (k.v32)
       hipLaunchKernelGGL(basis_axpy_kernel<c64>, agrid, dim3(kThreads), 0, st, static_cast<const c64*>(k.V), h, ld,
@@ -640,22 +654,22 @@ hipError_t launch_basis_axpy(KrylovDev k, const c128* h, int count, c128* w, hip
   return hipGetLastError();
 }
 
-hipError_t launch_givens_last_column(KrylovDev k, int kold, c128* q, hipStream_t st) {
-  if (kold < 0 || kold >= k.m) return hipErrorInvalidValue;
+hipError_t launch_givens_last_column(KrylovDev k, const int32_t* kold, c128* q, hipStream_t st) {
   hipLaunchKernelGGL(givens_last_column_kernel, dim3(blocks_for(k.R, 64)), dim3(64), 0, st, k.cs, k.sn, k.m, k.R,
                      kold, q);
   return hipGetLastError();
 }
 
-hipError_t launch_givens_apply(KrylovDev k, int kold, c128* e, hipStream_t st) {
-  if (kold < 0 || kold >= k.m) return hipErrorInvalidValue;
+hipError_t launch_givens_apply(KrylovDev k, const int32_t* kold, c128* e, hipStream_t st) {
   hipLaunchKernelGGL(givens_apply_kernel, dim3(blocks_for(k.R, 64)), dim3(64), 0, st, k.cs, k.sn, k.m, k.R, kold, e);
   return hipGetLastError();
 }
 
-hipError_t launch_deflate_coeffs(const c128* q, int o, c128* h, int R, int ld, const int32_t* flag, hipStream_t st) {
+hipError_t launch_deflate_coeffs(const c128* q, int o, const int32_t* kold, c128* h, int R, int ld,
+                                 const int32_t* keep, hipStream_t st) {
   if (o < 1 || o > ld) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(deflate_coeffs_kernel, dim3(R), dim3(256), 0, st, q, o, h, ld, flag);
+  hipLaunchKernelGGL(deflate_coeffs_kernel, dim3(R), dim3(256), 0, st, q, o, kold, h, ld, (const int32_t*)nullptr,
+                     keep);
   return hipGetLastError();
 }
 

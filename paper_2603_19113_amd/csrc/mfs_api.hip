@@ -745,7 +745,8 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
                ores = carve(8 * R), ohn = carve(8 * R), oact = carve(4 * R), ojl = carve(4 * R),
                own = carve(8 * R), oro = carve(4 * R), onro = carve(4 * R), opart = carve(szPart),
                ojdev = carve(sizeof(int32_t)), otol = carve(sizeof(double)), oq = carve(szRm1),
-               ocr = carve(szRm1), oee = carve(szRm1), ojold = carve(4 * R), orn2 = carve(8 * R);
+               ocr = carve(szRm1), oee = carve(szRm1), ojold = carve(4 * R), orn2 = carve(8 * R),
+               okeep = carve(4 * R);
   MFS_TRY(ensure(s->kry, off, &s->bytes, st));
   char* base = static_cast<char*>(s->kry.p);
   k.V = base + oV;
@@ -775,6 +776,7 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
   c128* edef = reinterpret_cast<c128*>(base + oee);     // coefficient work vector
   int32_t* jold = reinterpret_cast<int32_t*>(base + ojold);
   double* rn2 = reinterpret_cast<double*>(base + orn2);
+  int32_t* keepdev = reinterpret_cast<int32_t*>(base + okeep);  // columns a correction solve works on
   MFS_HIP_TRY(hipMemsetAsync(k.n_reorth, 0, sizeof(int32_t) * R, st));
   // Second Gram-Schmidt pass when ||w'|| < 0.1 ||w||.  Measured: on 1000 starfish the median ratio
   // is 0.26 and eta = 0.2 takes the second pass on 26% of steps (93% for eta = 1/sqrt(2)); on 2000
@@ -982,49 +984,57 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
                      max_relres());
     }
   } else {
-    // Deflated correction solves (GCRO, de Sturler 1996; one right-hand side): the first inner
-    // solve's kold Arnoldi steps give K~ V_k = V_{k+1} Hbar with Hbar = G^H [Rk; 0].  A later
-    // correction solve keeps them: C = V_{k+1} Q (Q the first k columns of G^H) is an orthonormal
-    // basis of K~ V_k, and U = V_k Rk^{-1} satisfies K~ U = C.  The new process runs on
-    // (I - C C^H) K~ from (I - C C^H) r, its basis stored after V_{k+1}; the correction is
-    // d = W y + U C^H (r - K~ W y).  The new steps thus work only on what the first Krylov space has
-    // not resolved, instead of rebuilding it from scratch.
-    const bool deflate = opts->deflate != 0 && R == 1;
-    int kold = -1;  // steps of the kept process, -1 while none is kept
+    // Deflated correction solves (GCRO, de Sturler 1996): the first inner solve's kold Arnoldi
+    // steps give K~ V_k = V_{k+1} Hbar with Hbar = G^H [Rk; 0].  A later correction solve keeps them:
+    // C = V_{k+1} Q (Q the first k columns of G^H) is an orthonormal basis of K~ V_k, and
+    // U = V_k Rk^{-1} satisfies K~ U = C.  The new process runs on (I - C C^H) K~ from
+    // (I - C C^H) r, its basis stored after the kept vectors; the correction is
+    // d = W y + U C^H (r - K~ W y).  The new steps thus work only on what the first Krylov space
+    // has not resolved, instead of rebuilding it from scratch.  Each column keeps its own k; the
+    // new processes share the first free slot after the longest.
+    const bool deflate = opts->deflate != 0;
+    int o = 0;  // first basis slot of a correction solve's process, 0 while no space is kept
     auto keep_space = [&]() -> mfs_status {
-      int32_t jl = 0;
-      MFS_HIP_TRY(hipMemcpyAsync(&jl, k.jlen, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      std::vector<int32_t> jl(R);
+      MFS_HIP_TRY(hipMemcpyAsync(jl.data(), k.jlen, sizeof(int32_t) * R, hipMemcpyDeviceToHost, st));
       MFS_HIP_TRY(hipStreamSynchronize(st));
+      int kmax = 0;
+      for (int32_t v : jl) kmax = std::max(kmax, (int)v);
       // room for at least 64 new steps after the kept vectors
-      if (jl < 1 || jl + 1 + 64 > m) return MFS_OK;
-      kold = jl;
-      MFS_HIP_TRY(hipMemcpyAsync(jold, k.jlen, sizeof(int32_t), hipMemcpyDeviceToDevice, st));
-      MFS_HIP_TRY(launch_givens_last_column(k, kold, qdef, st));
+      if (kmax < 1 || kmax + 1 + 64 > m) return MFS_OK;
+      o = kmax + 1;
+      MFS_HIP_TRY(hipMemcpyAsync(jold, k.jlen, sizeof(int32_t) * R, hipMemcpyDeviceToDevice, st));
+      MFS_HIP_TRY(launch_givens_last_column(k, jold, qdef, st));
       return MFS_OK;
     };
     auto deflated_cycle = [&](double ktol) -> mfs_status {
-      const int o = kold + 1;
+      const size_t coeff_bytes = sizeof(c128) * (size_t)R * (m + 1);
       KrylovDev kd = k;
       kd.joff = o;
       kd.qdef = qdef;
+      kd.kold = jold;
       kd.jdev = nullptr;
       kd.tol_dev = nullptr;
       kd.bnorm = rn2;  // estimate relative to the correction's own residual, before the projection
+      // columns already converged get no correction at all
+      MFS_HIP_TRY(hipMemcpyAsync(keepdev, active.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice, st));
       MFS_HIP_TRY(launch_norms(r, N, R, k.part, k.nblk, rn2, st));
-      // c = V_{k+1}^H r;  r <- r - V_{k+1} (c - q q^H c) = (I - C C^H) r
+      // c = V^H r over the kept slots;  r <- r - V (c - q q^H c) = (I - C C^H) r
       MFS_HIP_TRY(launch_basis_dots(k, r, o, cdef, st));
-      MFS_HIP_TRY(hipMemcpyAsync(edef, cdef, sizeof(c128) * o, hipMemcpyDeviceToDevice, st));
-      MFS_HIP_TRY(launch_deflate_coeffs(qdef, o, edef, R, m + 1, nullptr, st));
+      MFS_HIP_TRY(hipMemcpyAsync(edef, cdef, coeff_bytes, hipMemcpyDeviceToDevice, st));
+      MFS_HIP_TRY(launch_deflate_coeffs(qdef, o, jold, edef, R, m + 1, keepdev, st));
       MFS_HIP_TRY(launch_basis_axpy(k, edef, o, r, st));
       MFS_TRY(cycle(kd, ktol, true, m - o));  // x += W y
-      // x += U C^H (r - K~ W y) = V_k Rk^{-1} [G (c - V_{k+1}^H K~ W y)]_{0..k-1}
+      // x += U C^H (r - K~ W y) = V_k Rk^{-1} [G (c - V^H K~ W y)]_{0..k-1}
       MFS_HIP_TRY(hipMemsetAsync(r, 0, sizeof(c128) * NR, st));
       MFS_HIP_TRY(launch_update_from_y(kd, r, st));  // r = W y
       MFS_TRY(apply_mixed(s, r, w, R, st, 0.0));     // w = K~ W y
       ++n32;
       MFS_HIP_TRY(launch_basis_dots(k, w, o, edef, st));
-      MFS_HIP_TRY(launch_axpby(cdef, edef, edef, 1.0, -1.0, o, st));
-      MFS_HIP_TRY(launch_givens_apply(k, kold, edef, st));
+      MFS_HIP_TRY(launch_axpby(cdef, edef, edef, 1.0, -1.0, (int64_t)R * (m + 1), st));
+      // zero the columns left out (projecting q out changes nothing below: G q = e_k)
+      MFS_HIP_TRY(launch_deflate_coeffs(qdef, o, jold, edef, R, m + 1, keepdev, st));
+      MFS_HIP_TRY(launch_givens_apply(k, jold, edef, st));
       KrylovDev kz = k;
       kz.g = edef;
       kz.jlen = jold;
@@ -1037,7 +1047,7 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
       kk.bnorm = kk.beta;  // inner estimate relative to the current residual
       // ask each inner solve for no more reduction than the outer tolerance still needs
       const double itol = std::max(opts->inner_tol, 0.3 * opts->tol / std::max(max_relres(), 1e-300));
-      if (kold > 0) {
+      if (o > 0) {
         MFS_TRY(deflated_cycle(std::min(itol, 0.5)));
       } else {
         MFS_TRY(cycle(kk, std::min(itol, 0.5), true, m));

@@ -164,15 +164,17 @@ struct KrylovDev {
   int32_t* jdev;
   double* tol_dev;
   double tol;         // tolerance written to tol_dev at the cycle start
-  // Deflated correction solves (GCRO, one right-hand side): the process starts at basis slot joff,
-  // after the joff vectors V_0..V_{joff-1} of an earlier process that are kept; its Hessenberg
-  // column, rotation, g and y entries sit at index joff + j of their arrays.  Each step's
-  // Gram-Schmidt runs over all joff + j + 1 vectors and replaces the coefficients a on the kept
-  // vectors by a - qdef (qdef^H a), which removes only the part along C = V_old Q (Q^H qdef = 0,
-  // the columns of Q spanning the range of the kept process's Hessenberg matrix).  Eager launches
-  // only (jdev null).  joff = 0 and qdef null otherwise.
+  // Deflated correction solves (GCRO): the process starts at basis slot joff, after the vectors
+  // of an earlier process that are kept (kold[r] + 1 <= joff of them for column r; the slots
+  // between are vectors of steps after that column had converged); its Hessenberg column,
+  // rotation, g and y entries sit at index joff + j of their arrays.  Each step's Gram-Schmidt
+  // runs over all joff + j + 1 vectors and replaces the coefficients a on the kept vectors by
+  // a - qdef (qdef^H a), which removes only the part along C = V_old Q (Q^H qdef = 0, the columns
+  // of Q spanning the range of the kept process's Hessenberg matrix), and zeroes those on the
+  // slots between.  Eager launches only (jdev null).  joff = 0 and qdef null otherwise.
   int joff;
   const c128* qdef;
+  const int32_t* kold;  // [R] steps of the kept process per column
 };
 
 // Steps per captured graph: the graph of bucket b serves steps b*kStepBucket ... (b+1)*kStepBucket-1.
@@ -188,14 +190,16 @@ hipError_t launch_arnoldi_finish(KrylovDev k, int j, c128* w, double tol, hipStr
 hipError_t launch_gmres_update_x(KrylovDev k, c128* x, hipStream_t st);
 // Deflation helpers (one right-hand side):
 //   out = V_{0..count-1}^H w;  w -= V_{0..count-1} h;  x += sum_{i<jlen} y_{joff+i} V_{joff+i}
-//   q = G^H e_kold and e = G e (rotations 0..kold-1 of the process that built the kept vectors)
-//   h -= q (q^H h) over the first o entries
+//   q = G^H e_kold and e = G e (rotations 0..kold[r]-1 of the process that built the kept vectors)
+//   h -= q (q^H h) over the first kold[r] + 1 entries, zero on the rest of the first o (all o
+//   where keep[r] == 0; keep may be null)
 hipError_t launch_basis_dots(KrylovDev k, const c128* w, int count, c128* out, hipStream_t st);
 hipError_t launch_basis_axpy(KrylovDev k, const c128* h, int count, c128* w, hipStream_t st);
 hipError_t launch_update_from_y(KrylovDev k, c128* x, hipStream_t st);
-hipError_t launch_givens_last_column(KrylovDev k, int kold, c128* q, hipStream_t st);
-hipError_t launch_givens_apply(KrylovDev k, int kold, c128* e, hipStream_t st);
-hipError_t launch_deflate_coeffs(const c128* q, int o, c128* h, int R, int ld, const int32_t* flag, hipStream_t st);
+hipError_t launch_givens_last_column(KrylovDev k, const int32_t* kold, c128* q, hipStream_t st);
+hipError_t launch_givens_apply(KrylovDev k, const int32_t* kold, c128* e, hipStream_t st);
+hipError_t launch_deflate_coeffs(const c128* q, int o, const int32_t* kold, c128* h, int R, int ld,
+                                 const int32_t* keep, hipStream_t st);
 hipError_t launch_axpby(const c128* a, const c128* b, c128* out, double alpha, double beta, int64_t n,
                         hipStream_t st);
 

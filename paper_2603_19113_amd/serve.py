@@ -325,7 +325,8 @@ class GpuExecutor:
                 q = torch.empty_like(v)
                 restart = restart_for(sc.T, sc.kappa, sc.dim)
                 info = mfs.solve(scene, v, q, tol=self.tol, maxit=200000, restart=restart, max_refine=30,
-                                 inner_tol=self.inner_tol, prec=mfs.MFS_MIXED, stream=st, basis32=True)
+                                 inner_tol=self.inner_tol, prec=mfs.MFS_MIXED, stream=st, basis32=True,
+                                 deflate=True)
                 qh = q.cpu().numpy() if self.keep_solution else None  # synchronises the slot's stream
                 st.synchronize()
                 N = scene.N
