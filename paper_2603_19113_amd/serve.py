@@ -55,8 +55,10 @@ def footprint_bytes(N: int, T: int, R: int, dim: int, restart: int, n_targets: i
                   _sym_slices(n_pad) * R * n_pad * 8 if R <= 32 else 0)  # FP32 symmetric kernel
     q32 = R * N * 8
     nblk = (N + 511) // 512                       # partial inner products: widest launch
+    # basis, Hessenberg matrix, partial inner products, and nine coefficient vectors per column
+    # (rotations, g, two Gram-Schmidt passes, y, and three for deflated correction solves)
     krylov = (restart + 1) * R * N * 8 + R * restart * (restart + 1) * 16 + 2 * R * (restart + 1) * nblk * 8 \
-        + 6 * R * (restart + 1) * 16
+        + 9 * R * (restart + 1) * 16
     vecs = 3 * R * N * 16
     caller = 2 * R * N * 16 + R * max(n_targets, 1) * 16
     return int(scene + partial + q32 + krylov + vecs + caller)
