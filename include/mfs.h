@@ -177,6 +177,8 @@ mfs_status mfs_apply(const mfs_scene* scene, const void* q_dev, void* y_dev, int
  *   MFS_MIXED: iterative refinement: r = b - A x with the FP64 operator, then GMRES with the FP32
  *              operator and FP64 Krylov vectors on A d = r to relative tolerance inner_tol,
  *              x += d; repeated until ||b - A x|| / ||b|| <= tol (FP64 residual) or max_refine.
+ *              With deflate = 1 the correction solves after the first run on the operator
+ *              deflated by the first inner solve's Krylov space (GCRO) instead of afresh.
  * Each right-hand side has its own Krylov space; the R operator applications of one iteration
  * share one pair-kernel launch.  Orthogonalisation is classical Gram-Schmidt with a second pass
  * where the first one cancelled (||w'|| < 0.1 ||w||).  The stopping test is
