@@ -1051,7 +1051,7 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
         MFS_TRY(deflated_cycle(std::min(itol, 0.5)));
       } else {
         MFS_TRY(cycle(kk, std::min(itol, 0.5), true, m));
-        if (deflate) MFS_TRY(keep_space());
+        if (deflate && n_refine == 0) MFS_TRY(keep_space());  // only the first inner solve is kept
       }
       ++n_refine;
       ++n_restart;
