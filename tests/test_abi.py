@@ -149,3 +149,33 @@ def test_launch_shape_table_round_trip_without_device(lib, tmp_path):
     assert mfs.tune_table_size() == 0
     assert lib.mfs_autotune(None, 1, 2, 1, None, None) == -1
     assert lib.mfs_tune_set(None, 1, 2, 4, 0, -1) == -1
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets the C compiler gives
+    the struct of the same fields in include/mfs.h (a field added on one side only fails here)."""
+    import shutil
+    import subprocess
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    pairs = [("mfs_shape_desc", mfs.ShapeDesc), ("mfs_solve_opts", mfs.SolveOpts),
+             ("mfs_solve_info", mfs.SolveInfo), ("mfs_pool_stats", mfs.PoolStats),
+             ("mfs_tune_result", mfs.TuneResult)]
+    lines = ['#include "mfs.h"', "#include <stdio.h>", "#include <stddef.h>", "int main(void) {"]
+    for cname, cls in pairs:
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(line.split()[:2]): int(line.split()[2]) for line in out if line}
+    for cname, cls in pairs:
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
