@@ -7,7 +7,10 @@ One step = one pass of the whole path over one synthetic scene:
   solve (I + S G_hat) q = S v to 1e-8 relative residual with FP32 pair sums and S products inside
   FP64 GMRES and FP64 iterative refinement                     -> mfs_solve (MFS_MIXED)
   scattered field at far targets                               -> mfs_eval_field
-Default workload: 2000 starfish, kappa 10, 128 equivalent points each (N = 256,000).
+Default workload: 1000 unit spheres in 3D, kappa 3, 400 equivalent points each (N = 400,000,
+1.598e11 off-body pairs per operator application): the largest single-GPU scene by pair evaluations
+per matvec.  `--workload starfish2000` runs the 2000-starfish scene (one step takes minutes there:
+the system needs ~6 GMRES iterations per body).
 
 Prints one JSON line.  value = Helmholtz pair evaluations performed in the timed steps divided by
 their wall time (whole-job throughput; the geometry is generated before timing starts).
@@ -59,26 +62,36 @@ FLOP_PER_PAIR_RHS_MFMA = 8
 PEAK_FP32_MFMA_TFLOPS = 157.3
 
 
+# Host threads one GPU's share of the benchmark host may use.
+CPU_SHARE_PER_GPU = 16
+
+# Krylov basis length per workload: room for the whole solve without restarts (restarts stall these
+# systems, and a deflated correction solve needs its vectors after the kept ones).
+DEFAULT_RESTART = {"starfish2000": 16000, "spheres1000": 2000, "mixed2000_R64": 4000, "disks16": 400}
+
+
 def log(msg: str):
     print(msg, file=sys.stderr, flush=True)
 
 
-def stored_traffic(workload: str, kernel_name: str, nchunks: int):
-    """HBM bytes per launch of the FP32 G_hat kernel from the committed rocprofv3 counter summary,
-    or None if the summary is for another workload, kernel or launch shape, or the kernel source has
-    changed since the counters were taken."""
+def stored_traffic(key: str, scene_name: str, kernel_name: str, nchunks: int):
+    """HBM bytes per launch of the FP32 G_hat kernel from the committed rocprofv3 counter summary of
+    this workload (profiles/ghat_f32_<key>_traffic.md), or None if there is none, or it is for another
+    scene, kernel or launch shape, or the kernel source has changed since the counters were taken."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "ghat_f32_starfish2000_traffic.md")
-    if workload != "starfish2000_kappa10" or not os.path.exists(path):
+    path = os.path.join(ROOT, "profiles", f"ghat_f32_{key}_traffic.md")
+    if not os.path.exists(path):
         return None
     fields = {}
     for line in open(path):
         if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha256", "nchunks",
-                                                     "kernel"):
+                                                     "kernel", "scene"):
             k, v = line.split(":", 1)
             fields[k] = v.strip()
     if not fields.get("kernel") or not kernel_name.startswith(fields["kernel"]):
+        return None
+    if fields.get("scene", scene_name) != scene_name:
         return None
     csrc = os.path.join(ROOT, "paper_2603_19113_amd", "csrc")
     h = hashlib.sha256(open(os.path.join(csrc, "pair_kernels.hip"), "rb").read() +
@@ -98,10 +111,12 @@ def cpu_baseline(sc, seconds: float) -> dict:
 
     xh, ptr, bo = gs.pack(sc)
     try:
-        cores = len(os.sched_getaffinity(0))
+        host_cores = len(os.sched_getaffinity(0))
     except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
+        host_cores = os.cpu_count() or 1
+    # the oracle's thread pool takes every core of the affinity mask, up to the 16-thread CPU share
+    # that one GPU gets on the benchmark hosts (both counts are reported)
+    cores = max(1, min(host_cores, CPU_SHARE_PER_GPU))
     rng = np.random.default_rng(5)
     q = rng.standard_normal((1, sc.N)) + 1j * rng.standard_normal((1, sc.N))
     order = rng.permutation(sc.N)
@@ -115,7 +130,8 @@ def cpu_baseline(sc, seconds: float) -> dict:
         k_rows = (ptr[bo[rows] + 1] - ptr[bo[rows]]).astype(np.float64)
         pairs += float(np.sum(sc.N - k_rows))
         done += rows.size
-    return {"value": pairs / t_used, "unit": "pair-evals/s", "cores": cores, "kind": "oracle",
+    return {"value": pairs / t_used, "unit": "pair-evals/s", "cores": cores, "host_cores": host_cores,
+            "kind": "oracle",
             "sample": f"{done} of {sc.N} G_hat rows x all {sc.N} sources (FP64 scipy Hankel, "
                       f"{pairs:.3e} pairs in {t_used:.1f} s)"}
 
@@ -290,11 +306,11 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
-    ap.add_argument("--workload", default="starfish2000",
+    ap.add_argument("--workload", default="spheres1000",
                     choices=["starfish2000", "spheres1000", "mixed2000_R64", "disks16"])
     ap.add_argument("--bodies", type=int, default=None, help="override T (scaled scene, same density)")
-    ap.add_argument("--restart", type=int, default=16000,
-                    help="Krylov basis size; the default keeps the whole basis resident (no restart)")
+    ap.add_argument("--restart", type=int, default=0,
+                    help="Krylov basis size (0: the workload's default, which keeps the whole basis resident)")
     ap.add_argument("--inner-tol", type=float, default=3e-6,
                     help="first inner solve stops here: below ~7e-6 the FP32 operator error caps the true residual")
     ap.add_argument("--basis64", action="store_true",
@@ -343,6 +359,9 @@ def main() -> int:
               f"design note, not an implemented path.", file=sys.stderr)
         return 2
 
+    if args.restart <= 0:
+        args.restart = DEFAULT_RESTART[args.workload]
+
     import numpy as np
     import torch
 
@@ -377,8 +396,11 @@ def main() -> int:
         parts = [int(x) for x in args.launch_shape.split(":")]
         forced = (parts[0], parts[1], parts[2] if len(parts) > 2 else -1)
 
-    def make_scene():
-        built = [mfs.build_S(s, sc.kappa) for s in sc.shapes]
+    def build_all():
+        return [mfs.build_S(s, sc.kappa) for s in sc.shapes]
+
+    def make_scene(built=None):
+        built = built or build_all()
         scene = mfs.Scene(sc.dim, sc.kappa, sc.shape_of, sc.centres, [s.eqpts for s in sc.shapes],
                           [b.S64 for b in built], [b.S32 for b in built])
         if forced:
@@ -386,10 +408,17 @@ def main() -> int:
         return scene
 
     def step():
-        scene = make_scene()
+        """One pass of the whole path; returns the solver's info with the wall time of each phase."""
+        t0 = time.perf_counter()
+        built = build_all()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        scene = make_scene(built)
         v = torch.empty((R, scene.N), dtype=torch.complex128, device="cuda")
         mfs.plane_wave(scene, dirs, v)
         q = torch.empty_like(v)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
         if args.matvecs > 0:
             # profiling mode: the operator applications of a solve without the Krylov recurrence
             q32 = v.to(torch.complex64)
@@ -404,10 +433,14 @@ def main() -> int:
             info = mfs.solve(scene, v, q, tol=args.tol, maxit=60000, restart=args.restart, max_refine=20,
                              inner_tol=args.inner_tol, prec=mfs.MFS_MIXED, verbose=args.verbose,
                              basis32=not args.basis64, deflate=not args.no_deflate)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
         u = torch.empty((R, targets.shape[0]), dtype=torch.complex128, device="cuda")
         mfs.eval_field(scene, q, targets, u, mfs.MFS_FP64)
         torch.cuda.synchronize()
+        t4 = time.perf_counter()
         scene.close()
+        info["phase_s"] = {"build_S": t1 - t0, "scene_and_rhs": t2 - t1, "solve": t3 - t2, "field": t4 - t3}
         return info
 
     if args.compare:
@@ -442,8 +475,11 @@ def main() -> int:
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
         infos.append(info)
+        ph = info["phase_s"]
         log(f"[bench] step {i}: {times[-1]:.2f} s  relres {info['relres_max']:.2e}  "
-            f"matvec32 {info['n_matvec32']} matvec64 {info['n_matvec64']} refine {info['n_refine']}")
+            f"matvec32 {info['n_matvec32']} matvec64 {info['n_matvec64']} refine {info['n_refine']}  "
+            f"(S {ph['build_S']:.2f} s, scene {ph['scene_and_rhs']:.2f} s, solve {ph['solve']:.2f} s, "
+            f"field {ph['field']:.3f} s)")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_all
     ms32, n32, p32 = mfs.timing_read(mfs.MFS_KERNEL_PAIR_F32)
@@ -458,7 +494,7 @@ def main() -> int:
         kernel_name = "ghat_mfma_kernel<%d> (G_hat, FP32 matrix cores)" % sc.dim
     else:
         kernel_name = "ghat_bodyphase_kernel<%d,2,%d> (G_hat, FP32)" % (sc.dim, shape["rhs_per_thread"])
-    traffic = stored_traffic(sc.name, kernel_name, shape["nchunks"])
+    traffic = stored_traffic(args.workload, sc.name, kernel_name, shape["nchunks"])
     total_pairs = p32 + p64
     value = total_pairs / wall
     avg32 = ms32 / max(n32, 1)
@@ -495,6 +531,7 @@ def main() -> int:
         "n_matvec64": infos[-1]["n_matvec64"],
         "n_refine": infos[-1]["n_refine"],
         "n_reorth": infos[-1].get("n_reorth", 0),
+        "phase_s_p50": {k: statistics.median(i["phase_s"][k] for i in infos) for k in infos[0]["phase_s"]},
         "mode": "profile (operator applications only)" if args.matvecs > 0 else "full solve",
         "pair_kernel_f32": {"launches": n32, "avg_ms": avg32, "rhs": R, "pairs_per_launch": pairs_per_launch32,
                             "pair_evals_per_s": pairs_per_launch32 / (avg32 * 1e-3) if n32 else 0.0},

@@ -58,7 +58,8 @@ def ghat_apply(xhat, body_of, kappa, q, rows=None, workers: int | None = None, b
     """
     q = np.atleast_2d(np.asarray(q, dtype=np.complex128))
     rows = np.arange(xhat.shape[0]) if rows is None else np.asarray(rows)
-    workers = workers or os.cpu_count() or 1
+    # default pool: the host's cores, at most 16 (one GPU's share of a shared benchmark host)
+    workers = workers or min(os.cpu_count() or 1, 16)
     chunks = [rows[s:s + block] for s in range(0, rows.shape[0], block)]
     if workers == 1 or len(chunks) == 1:
         parts = [_ghat_rows(xhat, body_of, kappa, q, c) for c in chunks]

@@ -9,6 +9,7 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -42,16 +43,23 @@ def build(verbose: bool = True, extra: list[str] | None = None) -> str:
     """Compile every HIP source to an object, link libmfs.so, return its path."""
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
     cc = hipcc()
+    cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
-        cmd = [cc, *HIP_FLAGS, *(extra or []), "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src),
-               "-o", obj]
+        cmds.append([cc, *HIP_FLAGS, *(extra or []), "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src),
+                     "-o", obj])
+        objs.append(obj)
+
+    def compile_one(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        objs.append(obj)
+
+    # one hipcc per source, a few at a time (each takes seconds to a minute and ~1 GB of memory)
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", "0")) or min(os.cpu_count() or 1, 16)))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        list(ex.map(compile_one, cmds))
     tmp = LIB + ".tmp"
     cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

@@ -28,8 +28,24 @@ def test_flop_counts_per_pair():
 
 def test_traffic_record_lookup():
     name = "ghat_sym_kernel<2> (G_hat, FP32, symmetric)"
-    got = bench.stored_traffic("starfish2000_kappa10", name, 63)
+    got = bench.stored_traffic("starfish2000", "starfish2000_kappa10", name, 63)
     assert got is not None and got > 1e9  # the committed record matches the current kernel source
-    assert bench.stored_traffic("starfish2000_kappa10", name, 126) is None        # other launch shape
-    assert bench.stored_traffic("spheres1000_kappa3", name, 63) is None           # other workload
-    assert bench.stored_traffic("starfish2000_kappa10", "ghat_bodyphase_kernel<2,2,1> (G_hat, FP32)", 63) is None
+    assert bench.stored_traffic("starfish2000", "starfish2000_kappa10", name, 126) is None  # other launch shape
+    assert bench.stored_traffic("starfish2000", "starfish500_kappa10", name, 63) is None     # other scene
+    assert bench.stored_traffic("disks16", "disks16_kappa5", name, 63) is None              # no record
+    assert bench.stored_traffic("starfish2000", "starfish2000_kappa10",
+                                "ghat_bodyphase_kernel<2,2,1> (G_hat, FP32)", 63) is None
+
+
+def test_default_workload_is_the_largest_single_gpu_scene():
+    import workloads as w
+
+    ap_default = None
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    for line in src.splitlines():
+        if 'add_argument("--workload", default=' in line:
+            ap_default = line.split('default="')[1].split('"')[0]
+    assert ap_default == "spheres1000"
+    pairs = {k: w.make_scene(k).n_pairs() for k in ("starfish2000", "spheres1000")}
+    assert pairs["spheres1000"] > pairs["starfish2000"]
+    assert set(bench.DEFAULT_RESTART) == set(w.CONFIGS)

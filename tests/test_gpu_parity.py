@@ -1,8 +1,10 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle on the same seeded inputs.
 
-Tolerances: FP64 kernels are held to 1e-12 relative (the device Hankel function is accurate to
-~2e-15 and sums of N terms add ~sqrt(N) eps); FP32 kernels to the error model
-10 (kappa L + 10) 2^-24 of the phase kappa r in single precision (L = scene diameter); S from the
+Tolerances, per entry of every right-hand side and relative to that right-hand side's largest
+reference entry: FP64 kernels 1e-12 (the device Hankel function is accurate to ~2e-15 and sums of N
+terms add ~sqrt(N) eps); FP32 pair sums with the body-centre phase split 1e-5 (about 10x their
+measured error); FP32 field evaluation on plain single-precision distances its error model
+10 (kappa L + 10) 2^-24 (L = scene diameter); S from the
 GPU least-squares to 1e-8 relative where the factorisations are full rank (the solution of a
 full-rank least-squares problem is unique, so only rounding, amplified by cond ~ 1e4-1e6, differs).
 """
@@ -13,7 +15,8 @@ import pytest
 import workloads as w
 from oracle import global_system as gs, local_s
 from tests.analytic import disk_series
-from tests.gpu_helpers import crandn, fp32_matvec_budget, make_gpu_scene, rel_err, s_to_device
+from tests.gpu_helpers import FP32_OPERATOR_TOL, assert_entrywise, crandn, fp32_distance_budget, make_gpu_scene, \
+    rel_err, s_to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -155,11 +158,12 @@ def test_ghat_matches_oracle(mfs, key, R):
     ref = gs.ghat_apply(xh, bo, sc.kappa, q)
     t64 = torch.empty((R, gsc.N), dtype=torch.complex128, device="cuda")
     mfs.ghat_apply(gsc, torch.from_numpy(q).cuda(), t64, mfs.MFS_FP64)
-    assert rel_err(t64.cpu().numpy(), ref) < 1e-12
+    assert_entrywise(t64.cpu().numpy(), ref, 1e-12, f"G_hat FP64 {key}")
     q32 = torch.from_numpy(q.astype(np.complex64)).cuda()
     t32 = torch.empty((R, gsc.N), dtype=torch.complex64, device="cuda")
     mfs.ghat_apply(gsc, q32, t32, mfs.MFS_FP32)
-    assert rel_err(t32.cpu().numpy(), ref) < fp32_matvec_budget(sc)
+    err = assert_entrywise(t32.cpu().numpy(), ref, FP32_OPERATOR_TOL, f"G_hat FP32 {key}")
+    print(f"  fp32 entrywise error {err:.2e}", flush=True)
 
 
 def test_single_body_has_no_pairs(mfs):
@@ -183,17 +187,17 @@ def test_apply_matches_oracle_matvec(mfs, key):
     ref = gs.matvec(sc, Ss, xh, ptr, bo, q)
     y = torch.empty((2, gsc.N), dtype=torch.complex128, device="cuda")
     mfs.apply(gsc, torch.from_numpy(q).cuda(), y, mfs.MFS_FP64)
-    assert rel_err(y.cpu().numpy(), ref) < 1e-12
+    assert_entrywise(y.cpu().numpy(), ref, 1e-12, f"operator FP64 {key}")
     y32 = torch.empty((2, gsc.N), dtype=torch.complex64, device="cuda")
     mfs.apply(gsc, torch.from_numpy(q.astype(np.complex64)).cuda(), y32, mfs.MFS_FP32)
-    assert rel_err(y32.cpu().numpy(), ref) < fp32_matvec_budget(sc)
+    assert_entrywise(y32.cpu().numpy(), ref, FP32_OPERATOR_TOL, f"operator FP32 {key}")
     # the S product alone, and b = S vhat (beta = 0)
     t = crandn(rng, 2, xh.shape[0])
     yS = torch.empty((2, gsc.N), dtype=torch.complex128, device="cuda")
     mfs.s_apply(gsc, torch.from_numpy(q).cuda(), torch.from_numpy(t).cuda(), yS, 1.0, mfs.MFS_FP64)
-    assert rel_err(yS.cpu().numpy(), q + gs.apply_s(sc, Ss, ptr, t)) < 1e-13
+    assert_entrywise(yS.cpu().numpy(), q + gs.apply_s(sc, Ss, ptr, t), 1e-13, "q + S t")
     mfs.s_apply(gsc, None, torch.from_numpy(t).cuda(), yS, 0.0, mfs.MFS_FP64)
-    assert rel_err(yS.cpu().numpy(), gs.apply_s(sc, Ss, ptr, t)) < 1e-13
+    assert_entrywise(yS.cpu().numpy(), gs.apply_s(sc, Ss, ptr, t), 1e-13, "S t")
 
 
 def test_apply_is_deterministic(mfs):
@@ -217,7 +221,7 @@ def test_plane_wave_matches_oracle(mfs):
     xh, _, _ = gs.pack(sc)
     v = torch.empty((sc.R, gsc.N), dtype=torch.complex128, device="cuda")
     mfs.plane_wave(gsc, sc.directions, v)
-    assert rel_err(v.cpu().numpy(), gs.plane_wave_vhat(sc, xh)) < 1e-13
+    assert_entrywise(v.cpu().numpy(), gs.plane_wave_vhat(sc, xh), 1e-13, "plane wave")
 
 
 @pytest.mark.parametrize("key", ["disks16", "spheres6", "ragged9"])
@@ -232,11 +236,11 @@ def test_eval_field_matches_oracle(mfs, key):
     ref = gs.field(xh, sc.kappa, q, tg)
     u = torch.empty((2, tg.shape[0]), dtype=torch.complex128, device="cuda")
     mfs.eval_field(gsc, torch.from_numpy(q).cuda(), torch.from_numpy(tg).cuda(), u, mfs.MFS_FP64)
-    assert rel_err(u.cpu().numpy(), ref) < 1e-12
+    assert_entrywise(u.cpu().numpy(), ref, 1e-12, f"field FP64 {key}")
     u32 = torch.empty((2, tg.shape[0]), dtype=torch.complex64, device="cuda")
     mfs.eval_field(gsc, torch.from_numpy(q.astype(np.complex64)).cuda(), torch.from_numpy(tg).cuda(), u32,
                    mfs.MFS_FP32)
-    assert rel_err(u32.cpu().numpy(), ref) < fp32_matvec_budget(sc)
+    assert_entrywise(u32.cpu().numpy(), ref, fp32_distance_budget(sc), f"field FP32 {key}")
     # no targets: nothing to do, no error
     empty = torch.empty((0, sc.dim), dtype=torch.float64, device="cuda")
     mfs.eval_field(gsc, torch.from_numpy(q).cuda(), empty, u, mfs.MFS_FP64)
@@ -359,10 +363,8 @@ def test_ghat_many_rhs_matches_oracle(mfs, key, R):
         t32 = torch.empty((R, gsc.N), dtype=torch.complex64, device="cuda")
         mfs.ghat_apply(gsc, torch.from_numpy(q.astype(np.complex64)).cuda(), t32, mfs.MFS_FP32)
         got = t32.cpu().numpy()
-        assert rel_err(got, ref) < fp32_matvec_budget(sc)
-        # every right-hand side on its own, not only in aggregate
-        for r in range(R):
-            assert rel_err(got[r], ref[r]) < fp32_matvec_budget(sc)
+        # every entry of every right-hand side, relative to its own right-hand side's size
+        assert_entrywise(got, ref, FP32_OPERATOR_TOL, f"many-RHS G_hat {key} R={R} forced={forced}")
 
 
 def test_solve_many_rhs_mixed(mfs):
