@@ -234,6 +234,30 @@ typedef struct {
 mfs_status mfs_solve(const mfs_scene* scene, const void* vhat_dev, int32_t R, const mfs_solve_opts* opts,
                      void* qhat_dev, mfs_solve_info* info, void* stream);
 
+/* ------------------------------------------------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.
+ *
+ * mfs_apply_static computes the same operator as mfs_apply, y = q + S G_hat q, with the same
+ * kernels, but keeps every intermediate (the pair sum's partial slices, and for the symmetric
+ * kernel on bodies padded to whole tiles the padded copy of the charges) in a fixed array of
+ * MFS_STATIC_SCRATCH_BYTES that the library holds on each device it runs on until the process ends.
+ * The call allocates nothing: no hipMalloc, no hipFree, no allocating library routine, no scene
+ * workspace.  The array's device address is looked up once per device, when the first scene is
+ * created there (mfs_scene_create), so the scene passed in fixes the device.
+ *   q_dev, y_dev  device [R][N]; complex128 (MFS_FP64) or complex64 (MFS_FP32); y != q.
+ * Launch shape: the scene's, cut to what fits in the array (fewer source slices; the plain kernel
+ * when the symmetric kernel's slices do not fit), so the last bits of FP32 results may differ from
+ * mfs_apply's; the operator is the same.  Limit: one partial slice, R x N x 8 bytes (FP32) or
+ * R x N x 16 bytes (FP64), must fit in the array; larger calls return MFS_ERR_ARG and enqueue nothing.
+ * Every call on a device shares that device's array and overwrites it; no call reads what an
+ * earlier call left there (each slice is written before it is read), so nothing needs clearing.
+ * Calls that overlap on one device race on the array: serialise them (one stream, or events).
+ * Asynchronous. */
+#define MFS_STATIC_SCRATCH_BYTES (64ull << 20)
+mfs_status mfs_apply_static(const mfs_scene* scene, const void* q_dev, void* y_dev, int32_t R, mfs_prec prec,
+                            void* stream);
+
 /* Scattered field u(x) = sum_j phi_kappa(x - x_hat_j) qhat_j at M targets (eq. out_skel), valid for
  * targets on or outside every body's proxy surface (Sec. 2.3, Sec. 4.1).  Asynchronous.
  *   qhat_dev     device [R][N] complex128 (MFS_FP64) or complex64 (MFS_FP32)

@@ -107,6 +107,7 @@ using namespace mfs;
 
 struct mfs_scene {
   SceneDev dev{};
+  int device = 0;  // HIP device the scene's tables live on
   int n_shapes = 0;
   int64_t kmax = 0;
   bool has_s32 = false;
@@ -136,6 +137,31 @@ struct mfs_recon {
 };
 
 static std::atomic<uint64_t> g_recon_ids{1};
+
+// Scratch memory of mfs_apply_static: the pair sum's partial slices (and the padded copy of the
+// charges for the symmetric kernel) live in this fixed array instead of scene workspace, so that
+// call allocates nothing.  Each device holds its own copy (module globals are per device).  In host
+// code `scratch` only names the symbol: its device address comes from hipGetSymbolAddress, taken
+// once per device when the first scene is created there, and kept in g_scratch_addr.
+static __device__ __align__(256) unsigned char scratch[MFS_STATIC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_addr[kMaxDevices] = {};
+
+// Address of `scratch` on `device` (which must be current), looked up on the first call per device.
+static mfs_status scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(MFS_ERR_ARG, "device index beyond the static scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(MFS_ERR_HIP, std::string("static scratch address: ") + hipGetErrorString(e));
+    g_scratch_addr[device] = p;
+  }
+  *out = g_scratch_addr[device];
+  return MFS_OK;
+}
 
 namespace {
 
@@ -365,6 +391,64 @@ mfs_status apply_mixed_from32(mfs_scene* s, const c64* q32, c128* y, int R, hipS
   return MFS_OK;
 }
 
+// y = q + S G_hat q with every intermediate in the caller-supplied buffer `buf` of `cap` bytes (the
+// static scratch): the same kernels as apply_f64 / apply_f32, with the launch shape cut to what
+// fits.  The symmetric kernel runs when the scene's shape picks it and its slices (and the padded
+// charges) fit; otherwise the body-phase (or matrix-core) kernel with as many source slices as fit,
+// up to the scene's own count.  Every slice a consumer reads is written by the pair kernel first,
+// so nothing in `buf` needs to start at zero.  No allocation of any kind.
+mfs_status apply_in_buffer(mfs_scene* s, const void* q, void* y, int R, mfs_prec prec, void* buf, size_t cap,
+                           hipStream_t st) {
+  const int64_t N = s->dev.N;
+  if (prec == MFS_FP64) {
+    const size_t per_slice = (size_t)R * N * sizeof(c128);
+    const int fit = (int)std::min<size_t>(cap / per_slice, 1024);
+    if (fit < 1)
+      return fail(MFS_ERR_ARG, "apply_static: one FP64 partial slice needs " + std::to_string(per_slice) +
+                                   " bytes (R x N x 16), more than the static scratch's " + std::to_string(cap));
+    const int nch = std::min(shape_for(s, true, R).nchunks, fit);
+    c128* part = static_cast<c128*>(buf);
+    MFS_HIP_TRY(launch_ghat_f64(s->dev, static_cast<const c128*>(q), R, part, nch, st));
+    MFS_HIP_TRY(launch_sapply_f64(s->dev, part, nch, static_cast<const c128*>(q), 1.0, static_cast<c128*>(y), R,
+                                  (int)s->kmax, st));
+    return MFS_OK;
+  }
+  const c64* q32 = static_cast<const c64*>(q);
+  LaunchShape ls = shape_for(s, false, R);
+  if (ls.sym == 1) {
+    const bool padded = !s->dev.all_k_mult64;
+    const int64_t rows = f32_rows(s, ls);
+    const int slices = f32_slices(s, ls);
+    const size_t part_bytes = ((size_t)slices * R * rows * sizeof(c64) + 255) / 256 * 256;
+    const size_t need = part_bytes + (padded ? (size_t)R * rows * sizeof(c64) : 0);
+    if (need <= cap) {
+      c64* part = static_cast<c64*>(buf);
+      const c64* qs = q32;
+      if (padded) {
+        c64* qp = reinterpret_cast<c64*>(static_cast<char*>(buf) + part_bytes);
+        MFS_HIP_TRY(launch_gather_pad(s->dev, q32, R, qp, st));
+        qs = qp;
+      }
+      MFS_HIP_TRY(launch_ghat_f32_sym(sym_view(s->dev), qs, R, part, ls.nchunks, ls.rt, st));
+      MFS_HIP_TRY(launch_sapply_f32(s->dev, part, slices, q32, 1.0f, static_cast<c64*>(y), R, (int)s->kmax, st,
+                                    padded ? s->dev.pad_ptr : nullptr, padded ? rows : 0));
+      return MFS_OK;
+    }
+    // the symmetric kernel's slices do not fit: the plain kernel, with the plain heuristic's slices
+    ls.nchunks = pair_chunks_for(N, N, tpt_for(MFS_FP32));
+  }
+  const size_t per_slice = (size_t)R * N * sizeof(c64);
+  const int fit = (int)std::min<size_t>(cap / per_slice, 1024);
+  if (fit < 1)
+    return fail(MFS_ERR_ARG, "apply_static: one FP32 partial slice needs " + std::to_string(per_slice) +
+                                 " bytes (R x N x 8), more than the static scratch's " + std::to_string(cap));
+  const int nch = std::min(ls.nchunks, fit);
+  c64* part = static_cast<c64*>(buf);
+  MFS_HIP_TRY(launch_ghat_f32(s->dev, q32, R, part, nch, st, ls.rt));
+  MFS_HIP_TRY(launch_sapply_f32(s->dev, part, nch, q32, 1.0f, static_cast<c64*>(y), R, (int)s->kmax, st));
+  return MFS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -443,7 +527,15 @@ mfs_status mfs_scene_create(int32_t dim, double kappa, int64_t T, const int32_t*
   double origin[3] = {0.0, 0.0, 0.0};
   for (int d = 0; d < dim; ++d) origin[d] = 0.5 * (lo[d] + hi[d]);
 
+  int device = 0;
+  {
+    const hipError_t e = hipGetDevice(&device);
+    if (e != hipSuccess) return fail(MFS_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    void* scr = nullptr;
+    MFS_TRY(scratch_address(device, &scr));  // once per device: mfs_apply_static then only reads the table
+  }
   mfs_scene* sc = new mfs_scene();
+  sc->device = device;
   sc->n_shapes = n_shapes;
   sc->kmax = kmax;
   sc->has_s32 = S32_dev != nullptr;
@@ -668,6 +760,24 @@ mfs_status mfs_apply(const mfs_scene* sc, const void* q_dev, void* y_dev, int32_
   s->last_stream = st;
   if (prec == MFS_FP64) return apply_f64(s, static_cast<const c128*>(q_dev), static_cast<c128*>(y_dev), R, st);
   return apply_f32(s, static_cast<const c64*>(q_dev), static_cast<c64*>(y_dev), R, st);
+}
+
+mfs_status mfs_apply_static(const mfs_scene* sc, const void* q_dev, void* y_dev, int32_t R, mfs_prec prec,
+                            void* stream) {
+  MFS_TRY(check_scene(sc));
+  MFS_TRY(check_prec_operator(sc, prec));
+  if (R < 1 || !q_dev || !y_dev || q_dev == y_dev) return fail(MFS_ERR_ARG, "apply_static: bad R or pointers");
+  mfs_scene* s = const_cast<mfs_scene*>(sc);
+  void* buf = nullptr;
+  {
+    // the address was taken when the scene was created; this only reads the table
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    buf = (s->device >= 0 && s->device < kMaxDevices) ? g_scratch_addr[s->device] : nullptr;
+  }
+  if (!buf) return fail(MFS_ERR_ARG, "apply_static: no static scratch address for the scene's device");
+  hipStream_t st = as_stream(stream);
+  s->last_stream = st;
+  return apply_in_buffer(s, q_dev, y_dev, R, prec, buf, (size_t)MFS_STATIC_SCRATCH_BYTES, st);
 }
 
 mfs_status mfs_eval_field(const mfs_scene* sc, const void* qhat_dev, int32_t R, const double* targets_dev, int64_t M,

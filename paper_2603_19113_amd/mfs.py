@@ -75,7 +75,7 @@ class TuneResult(ctypes.Structure):
 
 EXPORTS = ["mfs_last_error", "mfs_version", "mfs_build_S", "mfs_scene_create", "mfs_scene_destroy",
            "mfs_scene_size", "mfs_scene_points", "mfs_plane_wave", "mfs_ghat_apply", "mfs_s_apply", "mfs_apply",
-           "mfs_solve", "mfs_eval_field", "mfs_timing_enable", "mfs_timing_read", "mfs_pool_query",
+           "mfs_apply_static", "mfs_solve", "mfs_eval_field", "mfs_timing_enable", "mfs_timing_read", "mfs_pool_query",
            "mfs_pool_set_limit", "mfs_pool_trim", "mfs_recon_create", "mfs_recon_destroy", "mfs_recon_size",
            "mfs_near_sizes", "mfs_plane_wave_colloc", "mfs_reconstruct", "mfs_eval_field_near", "mfs_autotune",
            "mfs_tune_get", "mfs_tune_set", "mfs_tune_save", "mfs_tune_load", "mfs_tune_clear", "mfs_tune_table_size"]
@@ -104,6 +104,7 @@ def load(path: str = LIB_PATH):
         "mfs_ghat_apply": ([vp, vp, vp, i32, i32, vp], ctypes.c_int),
         "mfs_s_apply": ([vp, vp, vp, vp, f64, i32, i32, vp], ctypes.c_int),
         "mfs_apply": ([vp, vp, vp, i32, i32, vp], ctypes.c_int),
+        "mfs_apply_static": ([vp, vp, vp, i32, i32, vp], ctypes.c_int),
         "mfs_solve": ([vp, vp, i32, ctypes.POINTER(SolveOpts), vp, ctypes.POINTER(SolveInfo), vp], ctypes.c_int),
         "mfs_eval_field": ([vp, vp, i32, vp, i64, vp, i32, vp], ctypes.c_int),
         "mfs_timing_enable": ([i32], ctypes.c_int),
@@ -282,6 +283,16 @@ def s_apply(scene: Scene, q, t, y, beta: float, prec: int = MFS_FP64, stream=Non
 
 def apply(scene: Scene, q, y, prec: int = MFS_FP64, stream=None):
     _check(_lib.mfs_apply(scene.handle, _ptr(q), _ptr(y), q.shape[0], prec, _stream(stream)))
+
+
+def apply_static(scene: Scene, q, y, prec: int = MFS_FP64, stream=None):
+    """mfs_apply_static: the operator of mfs_apply with its intermediates in the library's static
+    per-device scratch array (no allocation)."""
+    _check(_lib.mfs_apply_static(scene.handle, _ptr(q), _ptr(y), q.shape[0], prec, _stream(stream)))
+
+
+# largest intermediate mfs_apply_static accepts (bytes per device), as in mfs.h
+STATIC_SCRATCH_BYTES = 64 << 20
 
 
 def solve(scene: Scene, vhat, qhat, tol=1e-8, maxit=2000, restart=300, max_refine=10, inner_tol=1e-4,

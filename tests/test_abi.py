@@ -38,6 +38,12 @@ def test_library_exports_every_declared_symbol(lib):
     assert set(mfs.EXPORTS) == set(_declared_functions())
 
 
+def test_static_scratch_size_matches_header():
+    text = open(os.path.join(ROOT, "include", "mfs.h")).read()
+    m = re.search(r"#define MFS_STATIC_SCRATCH_BYTES \((\d+)ull << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == mfs.STATIC_SCRATCH_BYTES
+
+
 def test_version_and_error_string(lib):
     assert lib.mfs_version() >= 100
     assert isinstance(lib.mfs_last_error(), bytes)
@@ -55,6 +61,7 @@ def test_invalid_arguments_rejected_without_device(lib):
                                 ctypes.byref(out)) == -1
     # null scene for every scene entry point
     assert lib.mfs_apply(None, None, None, 1, 0, None) == -1
+    assert lib.mfs_apply_static(None, None, None, 1, 0, None) == -1
     assert lib.mfs_ghat_apply(None, None, None, 1, 0, None) == -1
     assert lib.mfs_eval_field(None, None, 1, None, 0, None, 0, None) == -1
     assert lib.mfs_solve(None, None, 1, None, None, None, None) == -1
