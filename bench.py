@@ -30,10 +30,25 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "Helmholtz pair-evals/s per matvec; GMRES solve time @1e-8 rel res; p50/p99"
-# Flops per pair of the FP32 G_hat kernel (FMA = 2, transcendental = 1), counted on its far branch.
-# 2D: u = sum_d dl_d (dl_d + 2 dc_d) (8), r^2 (1), rsq (1), r (1), D + r (1), rcp (1), delta (1),
-# 1/r^2 (1), modulus poly (4), phase poly (5), phase sum (3), fract (1), sqrt (1), amplitude (1),
-# sin + cos (2), (re, im) (2), complex multiply-add (8) = 42.
+# Algorithmic work of one off-body pair (phi and one complex multiply-add), in flop-equivalents
+# (FMA = 2, transcendental = 1), counted on the far-field branch of a plain FP32 evaluation:
+# 2D ~27 VALU operations and 4-5 transcendentals = 45, 3D ~15 VALU and 3 transcendentals = 25.
+# The roofline's `achieved` is this work per launch divided by the launch time, whatever the kernel
+# does to get there (the symmetric kernels evaluate phi once per unordered pair, so they do less).
+ALG_FLOP_PER_PAIR = {2: 45, 3: 25}
+ALG_PHI_FLOP = {d: f - 8 for d, f in ALG_FLOP_PER_PAIR.items()}  # phi alone, without the 8-flop complex MAC
+
+
+def alg_flop_per_pair(dim: int, R: int) -> float:
+    """Algorithmic work per pair and right-hand side: phi shared by the R right-hand sides, one
+    complex multiply-add each."""
+    return ALG_PHI_FLOP[dim] / R + 8
+
+
+# What the FP32 kernels themselves execute per pair (FMA = 2, transcendental = 1), counted on their
+# far branch.  2D: u = sum_d dl_d (dl_d + 2 dc_d) (8), r^2 (1), rsq (1), r (1), D + r (1), rcp (1),
+# delta (1), 1/r^2 (1), modulus poly (4), phase poly (5), phase sum (3), fract (1), sqrt (1),
+# amplitude (1), sin + cos (2), (re, im) (2), complex multiply-add (8) = 42.
 # 3D: u (12), r^2, rsq, r, D + r, rcp, delta (6), phase fma (2), fract (1), 1/(4 pi r) (1),
 # sin + cos (2), (re, im) (2), complex multiply-add (8) = 34.
 FLOP_PER_PAIR_F32 = {2: 42, 3: 34}
@@ -52,11 +67,11 @@ def flop_per_pair_sym(dim: int, R: int) -> float:
     return (PHI_FLOP_F32[dim] / R + 16) / 2
 
 
-# FP32 vector peak from the unit counts: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz =
-# 78.6 TFLOP/s.  The 157.3 TFLOP/s figure counts packed (two-wide) FP32 instructions, which every HIP
-# build here disables, so 78.6 is the ceiling these kernels can reach; both are reported.
-PEAK_FP32_VECTOR_TFLOPS = 78.6
-PEAK_FP32_PACKED_TFLOPS = 157.3
+# MI355X FP32 vector peak, 157.3 TFLOP/s (256 CUs x 4 SIMDs x 2.4 GHz x 64 flop per cycle with the
+# packed two-wide FP32 instructions).  Every HIP build here disables packed FP32, so these kernels
+# issue one-wide FP32 at most: 78.6 TFLOP/s, reported beside it.
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_FP32_UNPACKED_TFLOPS = 78.6
 # Many right-hand sides: G_hat tile x charge block on the FP32 matrix cores (dense FP32 MFMA peak).
 FLOP_PER_PAIR_RHS_MFMA = 8
 PEAK_FP32_MFMA_TFLOPS = 157.3
@@ -74,13 +89,20 @@ def log(msg: str):
     print(msg, file=sys.stderr, flush=True)
 
 
-def stored_traffic(key: str, scene_name: str, kernel_name: str, nchunks: int):
+def kernel_source_sha256() -> str:
+    """Hash of the pair-kernel sources, recorded with every traffic measurement."""
+    import hashlib
+
+    csrc = os.path.join(ROOT, "paper_2603_19113_amd", "csrc")
+    return hashlib.sha256(open(os.path.join(csrc, "pair_kernels.hip"), "rb").read() +
+                          open(os.path.join(csrc, "phi.h"), "rb").read()).hexdigest()
+
+
+def stored_traffic(key: str, scene_name: str, kernel_name: str, nchunks: int, folder: str | None = None):
     """HBM bytes per launch of the FP32 G_hat kernel from the committed rocprofv3 counter summary of
     this workload (profiles/ghat_f32_<key>_traffic.md), or None if there is none, or it is for another
     scene, kernel or launch shape, or the kernel source has changed since the counters were taken."""
-    import hashlib
-
-    path = os.path.join(ROOT, "profiles", f"ghat_f32_{key}_traffic.md")
+    path = os.path.join(folder or os.path.join(ROOT, "profiles"), f"ghat_f32_{key}_traffic.md")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -93,10 +115,7 @@ def stored_traffic(key: str, scene_name: str, kernel_name: str, nchunks: int):
         return None
     if fields.get("scene", scene_name) != scene_name:
         return None
-    csrc = os.path.join(ROOT, "paper_2603_19113_amd", "csrc")
-    h = hashlib.sha256(open(os.path.join(csrc, "pair_kernels.hip"), "rb").read() +
-                       open(os.path.join(csrc, "phi.h"), "rb").read()).hexdigest()
-    if fields.get("kernel_source_sha256") != h or "traffic_bytes_per_launch" not in fields:
+    if fields.get("kernel_source_sha256") != kernel_source_sha256() or "traffic_bytes_per_launch" not in fields:
         return None
     if fields.get("nchunks") != str(nchunks):
         return None
@@ -488,8 +507,12 @@ def main() -> int:
 
     on_sym = shape["symmetric"] == 1
     on_mfma = not on_sym and sc.R >= 8 and all(sh.k % 16 == 0 for sh in sc.shapes)
-    if on_sym:
-        kernel_name = "ghat_sym_kernel<%d> (G_hat, FP32, symmetric)" % sc.dim
+    sub_blocks = sc.dim == 3 and all(sh.k % 16 == 0 for sh in sc.shapes) and not all(sh.k % 64 == 0 for sh in sc.shapes)
+    rt = shape["rhs_per_thread"] or (1 if R == 1 else 2 if R == 2 else 4)
+    if on_sym and sub_blocks:
+        kernel_name = "ghat_sym16_kernel<%d> (G_hat, FP32, symmetric, 16-point sub-blocks)" % rt
+    elif on_sym:
+        kernel_name = "ghat_sym_kernel<%d,%d> (G_hat, FP32, symmetric)" % (sc.dim, rt)
     elif on_mfma:
         kernel_name = "ghat_mfma_kernel<%d> (G_hat, FP32 matrix cores)" % sc.dim
     else:
@@ -499,14 +522,18 @@ def main() -> int:
     value = total_pairs / wall
     avg32 = ms32 / max(n32, 1)
     pairs_per_launch32 = p32 / max(n32, 1)   # pair evaluations times right-hand sides
+    rate = pairs_per_launch32 / (avg32 * 1e-3) if n32 else 0.0  # (pair, right-hand side) per second
     if on_mfma:
         # the contraction on the matrix cores: 8 flop per (pair, right-hand side) complex multiply-add
-        flop_pp, bound, peak, peak_alt = FLOP_PER_PAIR_RHS_MFMA, "mfma", PEAK_FP32_MFMA_TFLOPS, None
+        alg_pp, kern_pp, bound, peak = FLOP_PER_PAIR_RHS_MFMA, FLOP_PER_PAIR_RHS_MFMA, "mfma", PEAK_FP32_MFMA_TFLOPS
     else:
-        # per pair and right-hand side: phi is shared by the R right-hand sides of a launch
-        flop_pp = flop_per_pair_sym(sc.dim, R) if on_sym else flop_per_pair_plain(sc.dim, R)
-        bound, peak, peak_alt = "alu", PEAK_FP32_VECTOR_TFLOPS, PEAK_FP32_PACKED_TFLOPS
-    achieved = flop_pp * pairs_per_launch32 / (avg32 * 1e-3) / 1e12 if n32 else 0.0
+        alg_pp = alg_flop_per_pair(sc.dim, R)
+        kern_pp = flop_per_pair_sym(sc.dim, R) if on_sym else flop_per_pair_plain(sc.dim, R)
+        if on_sym and sub_blocks:
+            kern_pp -= 1.0 / R  # no 1/(4 pi r) product and no fract per unordered pair: 2 flop less
+        bound, peak = "alu", PEAK_FP32_VECTOR_TFLOPS
+    achieved = alg_pp * rate / 1e12
+    kernel_tflops = kern_pp * rate / 1e12
     solve_times = [i["t_total_s"] for i in infos]
     out = {
         "metric": METRIC,
@@ -541,10 +568,12 @@ def main() -> int:
                             "pair_evals_per_s": p64 / (ms64 * 1e-3) if n64 else 0.0},
         "roofline": {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
-                     "kernel": kernel_name,
-                     "flop_per_pair" if not on_mfma else "flop_per_pair_rhs": flop_pp,
-                     **({"peak_packed_fp32": peak_alt, "frac_of_packed_peak": achieved / peak_alt}
-                        if peak_alt else {})},
+                     "kernel": kernel_name, "avg_launch_ms": avg32,
+                     ("alg_flop_per_pair" if not on_mfma else "alg_flop_per_pair_rhs"): alg_pp,
+                     "kernel_flop_per_pair": kern_pp, "kernel_tflops": kernel_tflops,
+                     **({"peak_unpacked_fp32": PEAK_FP32_UNPACKED_TFLOPS,
+                         "kernel_frac_of_unpacked_peak": kernel_tflops / PEAK_FP32_UNPACKED_TFLOPS}
+                        if not on_mfma else {})},
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a row sample ...")

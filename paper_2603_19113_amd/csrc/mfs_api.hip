@@ -224,7 +224,7 @@ LaunchShape shape_for(const mfs_scene* s, bool f64, int R, int* source = nullptr
 // Rows of a partial-sum slice with this shape: the padded layout's length for the symmetric kernel
 // on bodies that are not whole tiles, else N.
 int64_t f32_rows(const mfs_scene* s, const LaunchShape& ls) {
-  return ls.sym == 1 && !s->dev.all_k_mult64 ? s->dev.Npad : s->dev.N;
+  return ls.sym == 1 && sym_padded(s->dev) ? s->dev.Npad : s->dev.N;
 }
 
 // Partial-sum slices the FP32 pair sum writes with this shape.
@@ -244,7 +244,7 @@ struct PartialF32 {
 // The FP32 pair sum of q32 ([R][N] complex64) into the scene's partial buffer.
 mfs_status pair_f32(mfs_scene* s, const c64* q32, int R, hipStream_t st, PartialF32* out) {
   const LaunchShape ls = shape_for(s, false, R);
-  const bool padded = ls.sym == 1 && !s->dev.all_k_mult64;
+  const bool padded = ls.sym == 1 && sym_padded(s->dev);
   const int64_t rows = f32_rows(s, ls);
   const int nch = f32_slices(s, ls);
   MFS_TRY(ensure(s->partial, (size_t)nch * R * rows * sizeof(c64), &s->bytes, st));
@@ -416,7 +416,7 @@ mfs_status apply_in_buffer(mfs_scene* s, const void* q, void* y, int R, mfs_prec
   const c64* q32 = static_cast<const c64*>(q);
   LaunchShape ls = shape_for(s, false, R);
   if (ls.sym == 1) {
-    const bool padded = !s->dev.all_k_mult64;
+    const bool padded = sym_padded(s->dev);
     const int64_t rows = f32_rows(s, ls);
     const int slices = f32_slices(s, ls);
     const size_t part_bytes = ((size_t)slices * R * rows * sizeof(c64) + 255) / 256 * 256;
@@ -628,12 +628,13 @@ mfs_status mfs_scene_create(int32_t dim, double kappa, int64_t T, const int32_t*
     d.all_k_mult16 = d.all_k_mult16 && (k_of_shape[s2] % 16 == 0);
     d.all_k_mult64 = d.all_k_mult64 && (k_of_shape[s2] % 64 == 0);
   }
+  d.sym16 = dim == 3 && d.all_k_mult16 && !d.all_k_mult64;
   d.Npad = N;
   d.pad_ptr = nullptr;
   d.body_of_pad = nullptr;
   d.lsqp = nullptr;
   for (int i = 0; i < 3; ++i) d.l32p[i] = nullptr;
-  if (!d.all_k_mult64) {
+  if (sym_padded(d)) {
     // bodies padded to whole 64-point tiles, made only where the symmetric kernel would pay
     std::vector<int64_t> pad_ptr(T + 1, 0);
     for (int64_t t = 0; t < T; ++t) pad_ptr[t + 1] = pad_ptr[t] + (body_ptr[t + 1] - body_ptr[t] + 63) / 64 * 64;

@@ -51,6 +51,8 @@ struct SceneDev {
   double offbody_pairs;           // N^2 - sum_tau k_tau^2
   bool all_k_mult16;              // every shape has a multiple of 16 points (matrix-core path)
   bool all_k_mult64;              // every shape has a multiple of 64 points (symmetric pair kernel)
+  bool sym16;                     // 3D, every shape a multiple of 16 points but not all of 64: the
+                                  // symmetric kernel works on 16-point sub-blocks, no padded layout
   // Padded layout for the symmetric kernel when some shape's point count is not a multiple of 64:
   // body b occupies [pad_ptr[b], pad_ptr[b+1]) with its points first and zero-charge fillers at its
   // centre after them.  Npad = N and null tables when every count is a multiple of 64 (or no
@@ -90,6 +92,8 @@ hipError_t launch_ghat_f32_sym(const SceneDev& s, const c64* q, int R, c64* part
                                hipStream_t st);
 // The symmetric kernel's view of a scene: the scene itself, or its padded layout (N = Npad).
 SceneDev sym_view(const SceneDev& s);
+// True when the symmetric kernel runs on the padded layout (bodies padded to whole 64-point tiles).
+bool sym_padded(const SceneDev& s);
 // t[r][i] = sum_c partial[c][r][pad(i)] for the padded layout.
 hipError_t launch_reduce_partials_padded(const SceneDev& s, const c64* partial, int nchunks, int R, c64* out,
                                          hipStream_t st);

@@ -761,6 +761,345 @@ __global__ __launch_bounds__(64, SymWaves<RT>::value) void ghat_sym_kernel(
             c64{(float)ar[m][rr], (float)ai[m][rr]};
 }
 
+// ---------------------------------------------------------------------------
+// Symmetric pair sum in 3D on bodies of 16 n points, without padding to whole tiles.
+//
+// Same group schedule, outputs and body-centre split as ghat_sym_kernel, but a 64-point tile may
+// straddle bodies: it is seen as four sub-blocks of 16 points, each on one body (every body holds a
+// multiple of 16 points, so bodies start on sub-block boundaries).  The 64 steps against a staged
+// source tile run in four phases of 16.  Lane l = 16 G + i (row G) takes, in phase p, sub-block
+// b = (G + p) mod 4 of the source tile, and at step t of the phase source 16 b + ((i + t) mod 16):
+// over the four phases every lane meets every source once.  Within a phase a lane's sources all
+// lie on one body, so the per-lane body-centre constants (target body against that sub-block's
+// body) are fixed for the phase and are recomputed only at phase starts, and only when the source
+// tile straddles bodies.  The source-side running sums rotate by one lane inside each row of 16
+// per step (DPP row rotation), and at the end of a phase move one row down (lane l receives lane
+// l + 16), where the next phase's lanes for that sub-block are; after four phases every sum is back
+// in its own lane.  Sub-block entries are staged twice (e and e + 16) at a stride of 48 floats, so
+// that the two half-waves read different LDS banks.  3D only: the kernel has no Hankel branches.
+// Idle target lanes and idle source slots (past N) carry zero charge and stay finite.  The pairs are
+// summed as e^{i kappa r} / r and the sums scaled by 1/(4 pi) when stored.
+// ---------------------------------------------------------------------------
+constexpr int kSubBlock = 16;   // points per sub-block
+constexpr int kSubStride = 48;  // LDS floats per staged sub-block
+
+template <int RT>
+struct Sym16Lds {
+  float l[3][4 * kSubStride];
+  float bs[4 * kSubStride];
+  float qr[RT][4 * kSubStride], qi[RT][4 * kSubStride];
+};
+
+// lane l receives the value of lane (l & ~15) | ((l + 1) & 15): rotation by one lane inside each row
+// of 16 (DPP row_ror:15)
+__device__ __forceinline__ float row_rotate_next(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x12F, 0xf, 0xf, false));
+}
+
+// lane l receives the value of lane (l + 16) mod 64
+__device__ __forceinline__ float rows_shift_next(float x, int lane) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(((lane + 16) & 63) << 2, __float_as_int(x)));
+}
+
+// one of four wave-uniform values picked by a per-lane index
+__device__ __forceinline__ int pick4(const int (&v)[4], int b) {
+  return b == 0 ? v[0] : b == 1 ? v[1] : b == 2 ? v[2] : v[3];
+}
+
+// Body-centre split of a target (body bt, local offset lt) against source body bsrc:
+// u = A + |l_s|^2 + P . l_s with A = |l_t|^2 + 2 dc . l_t, P = -2 (l_t + dc), D = |dc| and the phase
+// of kappa D in revolutions, from the FP64 centres.
+__device__ __forceinline__ void split_consts3(const BodyPhaseConsts& k, const double* __restrict__ cen, int bt,
+                                              int bsrc, const float (&lt)[3], float& A, float (&P)[3], float& D,
+                                              float& D2, float& ph0) {
+  double D2d = 0.0;
+  float Am = 0.0f;
+#pragma unroll
+  for (int dd = 0; dd < 3; ++dd) {
+    const double dc = cen[(int64_t)bt * 3 + dd] - cen[(int64_t)bsrc * 3 + dd];
+    D2d = fma(dc, dc, D2d);
+    const float dcf = (float)dc;
+    Am = fmaf(lt[dd], lt[dd] + 2.0f * dcf, Am);
+    P[dd] = -2.0f * (lt[dd] + dcf);
+  }
+  A = Am;
+  const double Dd = sqrt(D2d);
+  const double ph = Dd * k.kappa_rev64;
+  D = (float)Dd;
+  D2 = (float)D2d;
+  ph0 = (float)(ph - floor(ph));
+}
+
+// 4 pi phi in 3D with the body-centre split: e^{i kappa r} / r (the 1/(4 pi) is applied to the sums).
+// The phase in revolutions, ph0 + kappa delta / 2 pi, stays within [-1.2, 2.2] here (ph0 in [0, 1),
+// |delta| below two body radii), well inside the [-256, 256] revolutions that v_sin / v_cos take, so
+// no v_fract is needed before them.
+__device__ __forceinline__ void phi3_4pi(const BodyPhaseConsts& k, float u, float D, float D2, float ph0, float& pr,
+                                         float& pi) {
+  const float r2 = D2 + u;
+  const float rinv = __builtin_amdgcn_rsqf(r2);
+  const float r = r2 * rinv;
+  const float delta = u * __builtin_amdgcn_rcpf(D + r);
+  const float rev = fmaf(delta, k.kappa_rev, ph0);
+  pr = rinv * __builtin_amdgcn_cosf(rev);
+  pi = rinv * __builtin_amdgcn_sinf(rev);
+}
+constexpr float kInv4Pi = 0.07957747154594767f;
+
+// The bodies a lane's constants refer to in a phase whose source sub-block lies on body sb (-1: idle
+// slots): an idle target lane takes the source body, an idle sub-block the target's body.
+__device__ __forceinline__ void phase_bodies(int tb, int sb, int& bt, int& bsrc) {
+  bt = tb >= 0 ? tb : (sb >= 0 ? sb : 0);
+  bsrc = sb >= 0 ? sb : bt;
+}
+
+// All four target tiles against the staged source tile; no pair of the meeting is on one body.
+template <int RT, bool SYM>
+__device__ __forceinline__ void sym16_steps4(const Sym16Lds<RT>& sh, const BodyPhaseConsts& k,
+                                             const double* __restrict__ cen, int lane, const int (&tb)[kSymTiles],
+                                             const int (&sbb)[4], bool pure, const float (&lt)[kSymTiles][3],
+                                             const float (&qtr)[kSymTiles][RT], const float (&qti)[kSymTiles][RT],
+                                             float (&tr)[kSymTiles][RT], float (&ti)[kSymTiles][RT], float (&sr)[RT],
+                                             float (&si)[RT]) {
+  const int row = lane >> 4, li = lane & 15;
+  float A[kSymTiles], P[kSymTiles][3], D[kSymTiles], D2[kSymTiles], ph0[kSymTiles];
+  for (int p = 0; p < 4; ++p) {
+    const int blk = (row + p) & 3;
+    if (p == 0 || !pure) {
+      const int sb = pick4(sbb, blk);
+#pragma unroll
+      for (int m = 0; m < kSymTiles; ++m) {
+        int bt, bsrc;
+        phase_bodies(tb[m], sb, bt, bsrc);
+        split_consts3(k, cen, bt, bsrc, lt[m], A[m], P[m], D[m], D2[m], ph0[m]);
+      }
+    }
+    const int e0 = blk * kSubStride + li;
+    for (int t0 = 0; t0 < kSubBlock; t0 += 8) {
+#pragma unroll
+      for (int uu = 0; uu < 8; ++uu) {
+        const int e = e0 + t0 + uu;
+        const float ls0 = sh.l[0][e], ls1 = sh.l[1][e], ls2 = sh.l[2][e];
+        const float bs = sh.bs[e];
+        float qr[RT], qi[RT];
+#pragma unroll
+        for (int rr = 0; rr < RT; ++rr) {
+          qr[rr] = sh.qr[rr][e];
+          qi[rr] = sh.qi[rr][e];
+        }
+#pragma unroll
+        for (int m = 0; m < kSymTiles; ++m) {
+          float u = A[m] + bs;
+          u = fmaf(P[m][0], ls0, u);
+          u = fmaf(P[m][1], ls1, u);
+          u = fmaf(P[m][2], ls2, u);
+          float pr, pi;
+          phi3_4pi(k, u, D[m], D2[m], ph0[m], pr, pi);
+#pragma unroll
+          for (int rr = 0; rr < RT; ++rr) {
+            tr[m][rr] = fmaf(pr, qr[rr], fmaf(-pi, qi[rr], tr[m][rr]));
+            ti[m][rr] = fmaf(pr, qi[rr], fmaf(pi, qr[rr], ti[m][rr]));
+            if constexpr (SYM) {
+              sr[rr] = fmaf(pr, qtr[m][rr], fmaf(-pi, qti[m][rr], sr[rr]));
+              si[rr] = fmaf(pr, qti[m][rr], fmaf(pi, qtr[m][rr], si[rr]));
+            }
+          }
+        }
+        if constexpr (SYM) {
+#pragma unroll
+          for (int rr = 0; rr < RT; ++rr) {
+            sr[rr] = row_rotate_next(sr[rr]);
+            si[rr] = row_rotate_next(si[rr]);
+          }
+        }
+      }
+    }
+    if constexpr (SYM) {
+#pragma unroll
+      for (int rr = 0; rr < RT; ++rr) {
+        sr[rr] = rows_shift_next(sr[rr], lane);
+        si[rr] = rows_shift_next(si[rr], lane);
+      }
+    }
+  }
+}
+
+// One target tile against the staged source tile, pairs on one body skipped (a lane's source body
+// is fixed within a phase, so the test is per lane and phase): the rare meetings near the diagonal.
+// Four phases bring the source-side sums back to their own lanes, so passes can follow each other.
+template <int RT, bool SYM>
+__device__ __forceinline__ void sym16_steps1(const Sym16Lds<RT>& sh, const BodyPhaseConsts& k,
+                                             const double* __restrict__ cen, int lane, int tbm, const int (&sbb)[4],
+                                             const float (&ltm)[3], const float (&qtr)[RT], const float (&qti)[RT],
+                                             float (&tr)[RT], float (&ti)[RT], float (&sr)[RT], float (&si)[RT]) {
+  const int row = lane >> 4, li = lane & 15;
+  for (int p = 0; p < 4; ++p) {
+    const int blk = (row + p) & 3;
+    const int sb = pick4(sbb, blk);
+    int bt, bsrc;
+    phase_bodies(tbm, sb, bt, bsrc);
+    float A, P[3], D, D2, ph0;
+    split_consts3(k, cen, bt, bsrc, ltm, A, P, D, D2, ph0);
+    const bool same = tbm >= 0 && tbm == sb;
+    const int e0 = blk * kSubStride + li;
+    for (int t0 = 0; t0 < kSubBlock; t0 += 8) {
+#pragma unroll
+      for (int uu = 0; uu < 8; ++uu) {
+        const int e = e0 + t0 + uu;
+        float u = A + sh.bs[e];
+        u = fmaf(P[0], sh.l[0][e], u);
+        u = fmaf(P[1], sh.l[1][e], u);
+        u = fmaf(P[2], sh.l[2][e], u);
+        float pr, pi;
+        phi3_4pi(k, u, D, D2, ph0, pr, pi);
+        pr = same ? 0.0f : pr;  // a select: also discards the non-finite value of a point with itself
+        pi = same ? 0.0f : pi;
+#pragma unroll
+        for (int rr = 0; rr < RT; ++rr) {
+          const float qr = sh.qr[rr][e], qi = sh.qi[rr][e];
+          tr[rr] = fmaf(pr, qr, fmaf(-pi, qi, tr[rr]));
+          ti[rr] = fmaf(pr, qi, fmaf(pi, qr, ti[rr]));
+          if constexpr (SYM) {
+            sr[rr] = row_rotate_next(fmaf(pr, qtr[rr], fmaf(-pi, qti[rr], sr[rr])));
+            si[rr] = row_rotate_next(fmaf(pr, qti[rr], fmaf(pi, qtr[rr], si[rr])));
+          }
+        }
+      }
+    }
+    if constexpr (SYM) {
+#pragma unroll
+      for (int rr = 0; rr < RT; ++rr) {
+        sr[rr] = rows_shift_next(sr[rr], lane);
+        si[rr] = rows_shift_next(si[rr], lane);
+      }
+    }
+  }
+}
+
+template <int RT>
+__global__ __launch_bounds__(64, SymWaves<RT>::value) void ghat_sym16_kernel(
+    BodyPhaseConsts k, const float* __restrict__ l0, const float* __restrict__ l1, const float* __restrict__ l2,
+    const float* __restrict__ lsq, const double* __restrict__ cen, const int32_t* __restrict__ body_of,
+    const c64* __restrict__ q, int64_t N, int R, int64_t G, int Dmax, int even_G, int dpc, int nchunks_d,
+    c64* __restrict__ partial) {
+  __shared__ Sym16Lds<RT> sh;
+  const int lane = threadIdx.x;
+  const int64_t g = blockIdx.x;
+  const int c = blockIdx.y;
+  const int r0 = blockIdx.z * RT;  // right-hand sides r0 .. r0 + RT - 1 (those >= R repeat R - 1, unstored)
+  const int d0 = c * dpc;
+  const int d1 = min(Dmax + 1, d0 + dpc);
+  const float* lsrc[3] = {l0, l1, l2};
+  int rof[RT];
+#pragma unroll
+  for (int rr = 0; rr < RT; ++rr) rof[rr] = min(r0 + rr, R - 1);
+
+  // targets: lane l of tile m is point g*256 + 64 m + l; lanes past N are idle (tb = -1, zero charge)
+  int tb[kSymTiles];
+  float lt[kSymTiles][3], qtr[kSymTiles][RT], qti[kSymTiles][RT];
+  double ar[kSymTiles][RT], ai[kSymTiles][RT];
+#pragma unroll
+  for (int m = 0; m < kSymTiles; ++m) {
+    const int64_t t = g * kSymGroup + 64 * m + lane;
+    const bool ok = t < N;
+    const int64_t tc = ok ? t : 0;
+    tb[m] = ok ? body_of[tc] : -1;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) lt[m][d] = ok ? lsrc[d][tc] : 0.0f;
+#pragma unroll
+    for (int rr = 0; rr < RT; ++rr) {
+      const c64 qq = q[(int64_t)rof[rr] * N + tc];
+      qtr[m][rr] = ok ? qq.re : 0.0f;
+      qti[m][rr] = ok ? qq.im : 0.0f;
+      ar[m][rr] = ai[m][rr] = 0.0;
+    }
+  }
+
+  for (int d = d0; d < d1; ++d) {
+    int64_t h = g + d;
+    if (h >= G) h -= G;
+    const bool sym = d != 0 && !(even_G && d == Dmax);
+    for (int ts = 0; ts < kSymTiles; ++ts) {
+      const int64_t j0 = h * kSymGroup + 64 * ts;
+      if (j0 >= N) break;
+      int sbb[4];  // body of each sub-block of the source tile, -1 past N (wave-uniform)
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        sbb[u] = j0 + kSubBlock * u < N ? __builtin_amdgcn_readfirstlane(body_of[j0 + kSubBlock * u]) : -1;
+      // stage the source tile: lane 16 u + i holds source j0 + 16 u + i at entries u*48 + i and + 16.
+      // Idle slots: zero offset and charge, |l|^2 = 1 so that no distance is zero
+      {
+        const int64_t j = j0 + lane;
+        const bool ok = j < N;
+        const int64_t jc = ok ? j : 0;
+        const int e = (lane >> 4) * kSubStride + (lane & 15);
+#pragma unroll
+        for (int dd = 0; dd < 3; ++dd) sh.l[dd][e] = sh.l[dd][e + kSubBlock] = ok ? lsrc[dd][jc] : 0.0f;
+        sh.bs[e] = sh.bs[e + kSubBlock] = ok ? lsq[jc] : 1.0f;
+#pragma unroll
+        for (int rr = 0; rr < RT; ++rr) {
+          const c64 qq = q[(int64_t)rof[rr] * N + jc];
+          sh.qr[rr][e] = sh.qr[rr][e + kSubBlock] = ok ? qq.re : 0.0f;
+          sh.qi[rr][e] = sh.qi[rr][e + kSubBlock] = ok ? qq.im : 0.0f;
+        }
+      }
+      __syncthreads();
+      // is any pair of this meeting on one body?  (then the per-tile path with the same-body test)
+      bool clash = false;
+#pragma unroll
+      for (int m = 0; m < kSymTiles; ++m)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) clash = clash || (tb[m] >= 0 && tb[m] == sbb[u]);
+      const bool any_clash = __any(clash);
+      const bool pure = sbb[0] >= 0 && sbb[1] == sbb[0] && sbb[2] == sbb[0] && sbb[3] == sbb[0];
+      float tr[kSymTiles][RT], ti[kSymTiles][RT];
+      float sr[RT], si[RT];  // lane l: source-side sums of source j0 + l (after the tile)
+#pragma unroll
+      for (int rr = 0; rr < RT; ++rr) {
+        sr[rr] = si[rr] = 0.0f;
+#pragma unroll
+        for (int m = 0; m < kSymTiles; ++m) tr[m][rr] = ti[m][rr] = 0.0f;
+      }
+      if (!any_clash) {
+        if (sym) sym16_steps4<RT, true>(sh, k, cen, lane, tb, sbb, pure, lt, qtr, qti, tr, ti, sr, si);
+        else sym16_steps4<RT, false>(sh, k, cen, lane, tb, sbb, pure, lt, qtr, qti, tr, ti, sr, si);
+      } else {
+#pragma unroll
+        for (int m = 0; m < kSymTiles; ++m) {
+          if (g * kSymGroup + 64 * m >= N) continue;  // a tile with no targets
+          if (sym) sym16_steps1<RT, true>(sh, k, cen, lane, tb[m], sbb, lt[m], qtr[m], qti[m], tr[m], ti[m], sr, si);
+          else sym16_steps1<RT, false>(sh, k, cen, lane, tb[m], sbb, lt[m], qtr[m], qti[m], tr[m], ti[m], sr, si);
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < kSymTiles; ++m)
+#pragma unroll
+        for (int rr = 0; rr < RT; ++rr) {
+          ar[m][rr] += (double)tr[m][rr];
+          ai[m][rr] += (double)ti[m][rr];
+        }
+      // source-side sums of this tile from the wave's targets -> slice of distance d
+      if (sym && j0 + lane < N) {
+#pragma unroll
+        for (int rr = 0; rr < RT; ++rr)
+          if (r0 + rr < R)
+            partial[((int64_t)(nchunks_d + d - 1) * R + r0 + rr) * N + j0 + lane] =
+                c64{sr[rr] * kInv4Pi, si[rr] * kInv4Pi};
+      }
+      __syncthreads();  // the tile's entries are read before the next tile is staged
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < kSymTiles; ++m) {
+    const int64_t t = g * kSymGroup + 64 * m + lane;
+#pragma unroll
+    for (int rr = 0; rr < RT; ++rr)
+      if (t < N && r0 + rr < R)
+        partial[((int64_t)c * R + r0 + rr) * N + t] =
+            c64{(float)(ar[m][rr] * (double)kInv4Pi), (float)(ai[m][rr] * (double)kInv4Pi)};
+  }
+}
+
 Phi2DConstsF32 make_phi2d_f32(double kappa) {
   Phi2DConstsF32 c;
   c.kappa = (float)kappa;
@@ -1094,7 +1433,7 @@ bool ghat_sym_possible(const SceneDev& s, int R) {
   // of its products are on zero padding and the symmetric VALU kernel does less work
   if (R < 1 || R > kSymMaxRhs || s.N <= 0) return false;
   int64_t NP = s.N;
-  if (!s.all_k_mult64) {
+  if (sym_padded(s)) {
     // padded to whole tiles: worth it while the padded pair count stays below 1.4 times the real one
     // (the symmetric kernel does about 0.6 times the plain kernel's work per pair)
     if (!s.pad_ptr || (double)s.Npad * (double)s.Npad > 1.4 * (double)s.N * (double)s.N) return false;
@@ -1105,8 +1444,10 @@ bool ghat_sym_possible(const SceneDev& s, int R) {
   return (double)(p.Dsym + 1) * (double)NP * (double)R * sizeof(c64) <= 8.0 * (1ull << 30);
 }
 
+bool sym_padded(const SceneDev& s) { return !s.all_k_mult64 && !s.sym16; }
+
 SceneDev sym_view(const SceneDev& s) {
-  if (s.all_k_mult64) return s;
+  if (!sym_padded(s)) return s;
   SceneDev v = s;
   v.N = s.Npad;
   for (int d = 0; d < 3; ++d) v.l32[d] = s.l32p[d];
@@ -1125,11 +1466,25 @@ static void launch_sym(const SceneDev& s, const SymPlan& p, const c64* q, int R,
                      p.nchunks_d, partial);
 }
 
+template <int RT>
+static void launch_sym16(const SceneDev& s, const SymPlan& p, const c64* q, int R, c64* partial, hipStream_t st) {
+  const dim3 grid((unsigned)p.G, (unsigned)p.nchunks_d, (unsigned)((R + RT - 1) / RT));
+  hipLaunchKernelGGL((ghat_sym16_kernel<RT>), grid, dim3(64), 0, st, make_bodyphase(s.kappa, s.rho_max), s.l32[0],
+                     s.l32[1], s.l32[2], s.lsq32, s.centres, s.body_of, q, s.N, R, p.G, p.Dmax, p.even ? 1 : 0, p.dpc,
+                     p.nchunks_d, partial);
+}
+
 hipError_t launch_ghat_f32_sym(const SceneDev& s, const c64* q, int R, c64* partial, int nchunks_d, int rt,
                                hipStream_t st) {
   if (s.N <= 0) return hipSuccess;
   const SymPlan p = sym_plan(s.N, nchunks_d);
   if (rt != 1 && rt != 2 && rt != 4) rt = ghat_default_rt(R);
+  if (s.sym16) {  // 3D, bodies of 16 n points: tiles may straddle bodies
+    if (rt == 1) launch_sym16<1>(s, p, q, R, partial, st);
+    else if (rt == 2) launch_sym16<2>(s, p, q, R, partial, st);
+    else launch_sym16<4>(s, p, q, R, partial, st);
+    return hipGetLastError();
+  }
   if (s.dim == 2) {
     if (rt == 1) launch_sym<2, 1>(s, p, q, R, partial, st);
     else if (rt == 2) launch_sym<2, 2>(s, p, q, R, partial, st);

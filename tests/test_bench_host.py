@@ -26,15 +26,29 @@ def test_flop_counts_per_pair():
     assert bench.flop_per_pair_sym(2, 4) == (34 / 4 + 16) / 2
 
 
-def test_traffic_record_lookup():
-    name = "ghat_sym_kernel<2> (G_hat, FP32, symmetric)"
-    got = bench.stored_traffic("starfish2000", "starfish2000_kappa10", name, 63)
-    assert got is not None and got > 1e9  # the committed record matches the current kernel source
-    assert bench.stored_traffic("starfish2000", "starfish2000_kappa10", name, 126) is None  # other launch shape
-    assert bench.stored_traffic("starfish2000", "starfish500_kappa10", name, 63) is None     # other scene
-    assert bench.stored_traffic("disks16", "disks16_kappa5", name, 63) is None              # no record
-    assert bench.stored_traffic("starfish2000", "starfish2000_kappa10",
-                                "ghat_bodyphase_kernel<2,2,1> (G_hat, FP32)", 63) is None
+def test_traffic_record_lookup(tmp_path):
+    """A counter record is used only for its workload's scene, kernel, launch shape and the kernel
+    source it was taken with (anything else gives traffic = null)."""
+    name = "ghat_sym16_kernel<1> (G_hat, FP32, symmetric, 16-point sub-blocks)"
+    rec = tmp_path / "ghat_f32_spheres1000_traffic.md"
+    rec.write_text("# record\nscene: spheres1000_kappa3\nkernel: ghat_sym16_kernel<1>\nnchunks: 37\n"
+                   f"traffic_bytes_per_launch: 123456789\nkernel_source_sha256: {bench.kernel_source_sha256()}\n")
+    got = bench.stored_traffic("spheres1000", "spheres1000_kappa3", name, 37, folder=str(tmp_path))
+    assert got == 123456789
+    assert bench.stored_traffic("spheres1000", "spheres1000_kappa3", name, 38, folder=str(tmp_path)) is None
+    assert bench.stored_traffic("spheres1000", "spheres500_kappa3", name, 37, folder=str(tmp_path)) is None
+    assert bench.stored_traffic("spheres1000", "spheres1000_kappa3", "ghat_sym_kernel<3,1> (G_hat)", 37,
+                                folder=str(tmp_path)) is None
+    assert bench.stored_traffic("disks16", "disks16_kappa5", name, 37, folder=str(tmp_path)) is None
+    rec.write_text(rec.read_text().replace(bench.kernel_source_sha256(), "0" * 64))  # kernel changed since
+    assert bench.stored_traffic("spheres1000", "spheres1000_kappa3", name, 37, folder=str(tmp_path)) is None
+
+
+def test_roofline_uses_the_algorithmic_work_per_pair():
+    # phi and one complex multiply-add per pair: 45 flop-equivalents in 2D, 25 in 3D
+    assert bench.alg_flop_per_pair(2, 1) == 45 and bench.alg_flop_per_pair(3, 1) == 25
+    assert bench.alg_flop_per_pair(3, 4) == 17 / 4 + 8
+    assert bench.PEAK_FP32_VECTOR_TFLOPS == 157.3
 
 
 def test_default_workload_is_the_largest_single_gpu_scene():

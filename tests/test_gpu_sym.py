@@ -173,8 +173,10 @@ def _ellipses112(T):
 @pytest.mark.parametrize("kind,T,R", [("spheres400", 5, 1), ("spheres400", 3, 3), ("ellipses112", 9, 1),
                                       ("ellipses112", 11, 2)])
 def test_symmetric_kernel_on_padded_bodies(mfs, kind, T, R):
-    """Bodies whose point count is not a multiple of 64 are padded to whole tiles with zero-charge
-    points at the body centre; the pair sum, the reduction and the S product read the padded rows."""
+    """Bodies whose point count is not a multiple of 64: in 2D (ellipses of 112) they are padded to
+    whole tiles with zero-charge points at the body centre, and the pair sum, the reduction and the S
+    product read the padded rows; in 3D (spheres of 400) the kernel works on 16-point sub-blocks of
+    the packed layout instead (no padding).  Both against the oracle and the plain kernel."""
     torch = _torch()
     sc = w.make_scene("spheres1000", T=T) if kind == "spheres400" else _ellipses112(T)
     print(f"padded symmetric {kind} T={T} R={R}", flush=True)
@@ -201,4 +203,57 @@ def test_symmetric_kernel_on_padded_bodies(mfs, kind, T, R):
     assert mfs.tune_get(gsc, R, mfs.MFS_FP32)["symmetric"] == 0
     plain = _ghat32(mfs, gsc, q)
     assert entrywise_err(plain, t) < 2 * budget
+    gsc.close()
+
+
+def _spheres_k(T, k, seed=9):
+    """T small spheres (radius 0.5) of k equivalent points in 3D, centres at least 1.7 apart, kappa 4:
+    with k = 48, 80 or 400 the 64-point tiles straddle bodies (16-point sub-blocks)."""
+    sh = w.sphere3d(radius=0.5, m=2 * k + 40, n=k, src_radius=0.35, k=k, rho_eq=0.6, p=2 * k + 40, r_psi=0.75)
+    centres = w.random_centres(T, 3, 2.2 * T ** (1.0 / 3.0) + 2.0, 1.7, seed)
+    return w.Scene(dim=3, kappa=4.0, shapes=[sh], shape_of=np.zeros(T, np.int32), centres=centres,
+                   directions=np.array([[1.0, 0.0, 0.0], [0.0, 0.6, 0.8], [0.0, 0.0, 1.0], [0.6, 0.8, 0.0],
+                                        [0.0, 1.0, 0.0]]), name=f"spheres{T}_k{k}")
+
+
+def _two_sphere_shapes(T):
+    """3D scene mixing 400- and 48-point spheres: sub-blocks of both kinds in one tile."""
+    a = w.sphere3d(radius=0.5, m=440, n=200, src_radius=0.35, k=400, rho_eq=0.6, p=440, r_psi=0.75)
+    b = w.sphere3d(radius=0.5, m=140, n=48, src_radius=0.35, k=48, rho_eq=0.6, p=140, r_psi=0.75)
+    centres = w.random_centres(T, 3, 2.2 * T ** (1.0 / 3.0) + 2.0, 1.7, 17)
+    shape_of = (np.arange(T) % 3 == 0).astype(np.int32)
+    return w.Scene(dim=3, kappa=4.0, shapes=[a, b], shape_of=shape_of, centres=centres,
+                   directions=np.array([[1.0, 0.0, 0.0], [0.0, 0.6, 0.8], [0.0, 0.0, 1.0]]), name=f"spheres2shape{T}")
+
+
+@pytest.mark.parametrize("case,T,R", [("k400", 3, 1), ("k400", 7, 2), ("k48", 9, 1), ("k48", 23, 3),
+                                      ("k80", 5, 5), ("k400", 1, 1), ("mix", 10, 1), ("mix", 13, 3),
+                                      ("k48", 40, 2)])
+def test_symmetric_kernel_on_sub_blocks_3d(mfs, case, T, R):
+    """3D bodies of 16 n points (not whole 64-point tiles): the symmetric kernel runs on 16-point
+    sub-blocks with no padded layout.  Cases: tiles straddling two bodies (400), several bodies in
+    one tile (48, 80), a last tile only partly filled (N not a multiple of 64), one body (no pairs),
+    two shapes, 1 to 5 right-hand sides with 1, 2 and 4 per thread, 1 to 3 distance chunks; against
+    the oracle entry by entry, through G_hat and through the whole operator."""
+    torch = _torch()
+    sc = _two_sphere_shapes(T) if case == "mix" else _spheres_k(T, int(case[1:]))
+    sc.directions = sc.directions[:R]
+    print(f"sub-block symmetric {case} T={T} N={sc.N} R={R}", flush=True)
+    gsc, Ss = _scene(mfs, sc)
+    assert mfs.tune_get(gsc, R, mfs.MFS_FP32)["symmetric"] == 1
+    xh, ptr, bo = gs.pack(sc)
+    q = crandn(np.random.default_rng(35), R, xh.shape[0])
+    ref = gs.ghat_apply(xh, bo, sc.kappa, q)
+    for rt in ((1, 2, 4) if R > 1 else (1,)):
+        for nch in (1, 2, 3):
+            mfs.tune_set(gsc, R, mfs.MFS_FP32, nch, rt, 1)
+            t = _ghat32(mfs, gsc, q)
+            if T == 1:
+                assert np.count_nonzero(t) == 0
+            else:
+                assert entrywise_err(t, ref) < FP32_OPERATOR_TOL, (rt, nch)
+    ref_y = gs.matvec(sc, Ss, xh, ptr, bo, q)
+    y = torch.empty((R, gsc.N), dtype=torch.complex64, device="cuda")
+    mfs.apply(gsc, torch.from_numpy(q.astype(np.complex64)).cuda(), y, mfs.MFS_FP32)
+    assert entrywise_err(y.cpu().numpy(), ref_y) < FP32_OPERATOR_TOL
     gsc.close()

@@ -68,3 +68,48 @@ def test_every_pair_once_every_slice_entry_once(tiles, nchunks_d):
 def test_slice_count_of_the_starfish_scene():
     # 256,000 points: 1000 groups, 63 distance chunks of 8, 499 source-side slices
     assert plan(256000, 0) == (1000, 500, True, 499, 8, 63, 562)
+
+
+# ----------------------------------------------------------------------------------------------
+# The 3D kernel on 16-point sub-blocks (tiles may straddle bodies).  Against one staged source tile,
+# lane l = 16 G + i takes in phase p (0..3) sub-block b = (G + p) mod 4 and at step t (0..15) the
+# source 16 b + ((i + t) mod 16), read from LDS entry 48 b + i + t (each sub-block staged twice, at
+# e and e + 16).  The running source-side sums rotate by one lane inside each row of 16 after every
+# step (lane l receives lane (l & ~15) | ((l + 1) & 15)) and move one row down after every phase
+# (lane l receives lane (l + 16) mod 64).  The model follows which source's sum each lane holds.
+def sub_block_schedule():
+    holder = list(range(64))  # holder[l]: the source whose running sum lane l holds
+    pairs = collections.Counter()
+    entries = set()
+    for p in range(4):
+        for t in range(16):
+            for lane in range(64):
+                G, i = lane >> 4, lane & 15
+                b = (G + p) & 3
+                e = 48 * b + i + t
+                src = 16 * b + ((i + t) & 15)
+                assert e - 48 * b in range(32)  # inside the sub-block's two staged copies
+                assert (e - 48 * b) % 16 == src % 16
+                assert holder[lane] == src  # the lane adds into the sum of the source it meets
+                pairs[(lane, src)] += 1
+                entries.add(e)
+            holder = [holder[(lane & ~15) | ((lane + 1) & 15)] for lane in range(64)]
+        holder = [holder[(lane + 16) & 63] for lane in range(64)]
+    return pairs, holder, entries
+
+
+def test_sub_block_schedule_meets_every_pair_once_and_returns_the_sums():
+    pairs, holder, entries = sub_block_schedule()
+    assert len(pairs) == 64 * 64 and set(pairs.values()) == {1}
+    assert holder == list(range(64))  # lane j ends with source j's sum: plain coalesced stores
+    assert max(entries) < 4 * 48
+
+
+def test_sub_block_phases_see_one_sub_block_per_row():
+    # within a phase each row of 16 lanes reads one sub-block, so a lane's source body (and its
+    # body-centre constants) is fixed for the phase; the four rows read four different sub-blocks
+    for p in range(4):
+        blocks = [((lane >> 4) + p) & 3 for lane in range(64)]
+        for G in range(4):
+            assert len(set(blocks[16 * G:16 * G + 16])) == 1
+        assert sorted(set(blocks)) == [0, 1, 2, 3]
