@@ -82,7 +82,7 @@ CPU_SHARE_PER_GPU = 16
 
 # Krylov basis length per workload: room for the whole solve without restarts (restarts stall these
 # systems, and a deflated correction solve needs its vectors after the kept ones).
-DEFAULT_RESTART = {"starfish2000": 16000, "spheres1000": 2000, "mixed2000_R64": 4000, "disks16": 400}
+DEFAULT_RESTART = {"starfish2000": 16000, "spheres1000": 2000, "mixed2000_R64": 1000, "disks16": 400}
 
 
 def log(msg: str):
@@ -286,9 +286,10 @@ def compare(args, sc, mfs, torch, np) -> int:
     q_mixed = torch.empty_like(v)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    use_block = R > 1 and not args.no_block
     info_m = mfs.solve(scene, v, q_mixed, tol=args.tol, maxit=60000, restart=args.restart, max_refine=20,
                        inner_tol=args.inner_tol, prec=mfs.MFS_MIXED, verbose=min(args.verbose, 1),
-                       basis32=not args.basis64, deflate=not args.no_deflate)
+                       basis32=not args.basis64, deflate=not args.no_deflate and not use_block, block=use_block)
     t_mixed = time.perf_counter() - t0
     log(f"[compare] mixed, {R} RHS together: {t_mixed:.2f} s  {info_m}")
     q64 = torch.empty_like(v)
@@ -310,6 +311,7 @@ def compare(args, sc, mfs, torch, np) -> int:
     t_fp64_all = t_fp64 * R / n64
     out = {"workload": sc.name, "N": scene.N, "T": sc.T, "R": R, "tol": args.tol, "restart": args.restart,
            "mixed_batched": {"seconds": t_mixed, "relres_max": info_m["relres_max"],
+                             "krylov": "block GMRES" if use_block else "GMRES per column",
                              "fp32_operator_applications": info_m["n_matvec32"],
                              "fp64_operator_applications": info_m["n_matvec64"]},
            "fp64_single_rhs": {"seconds": t_fp64_all, "timed_rhs": n64, "extrapolated": n64 < R,
@@ -339,6 +341,8 @@ def main() -> int:
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="profiling: first copy a buffer of this many MiB (calibrates rocprof byte counters)")
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-block", action="store_true",
+                    help="several right-hand sides: one Krylov space per column instead of block GMRES")
     ap.add_argument("--no-deflate", action="store_true",
                     help="correction solves restart from scratch instead of deflating the first inner "
                          "solve's Krylov space")
@@ -399,6 +403,7 @@ def main() -> int:
         sc.directions = sc.directions[:args.rhs]
     R = sc.R
     dirs = sc.directions
+    use_block = R > 1 and not args.no_block  # one block Krylov space for the R incident directions
     targets = torch.from_numpy(w.far_targets(sc, 256)).cuda()
     log(f"[bench] workload {sc.name}: T={sc.T} N={sc.N} R={R} pairs/matvec={sc.n_pairs():.4e}")
     if args.copy_mib > 0:
@@ -451,7 +456,8 @@ def main() -> int:
         else:
             info = mfs.solve(scene, v, q, tol=args.tol, maxit=60000, restart=args.restart, max_refine=20,
                              inner_tol=args.inner_tol, prec=mfs.MFS_MIXED, verbose=args.verbose,
-                             basis32=not args.basis64, deflate=not args.no_deflate)
+                             basis32=not args.basis64, deflate=not args.no_deflate and not use_block,
+                             block=use_block)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         u = torch.empty((R, targets.shape[0]), dtype=torch.complex128, device="cuda")
@@ -550,7 +556,8 @@ def main() -> int:
         "data": "synthetic (seeded geometry, no dataset)",
         "config": {"workload": sc.name, "T": sc.T, "N": sc.N, "R": R, "kappa": sc.kappa, "tol": args.tol,
                    "precision": "mixed", "restart": args.restart, "inner_tol": args.inner_tol,
-                   "krylov_basis": "c128" if args.basis64 else "c64"},
+                   "krylov_basis": "c128" if args.basis64 else "c64",
+                   "krylov": "block GMRES (one space for the R directions)" if use_block else "GMRES per column"},
         "solve_s_p50": statistics.median(solve_times) if args.matvecs == 0 else None,
         "solve_s_p99": float(np.percentile(solve_times, 99)) if args.matvecs == 0 else None,
         "relres_max": max(i["relres_max"] for i in infos),

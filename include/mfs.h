@@ -179,8 +179,8 @@ mfs_status mfs_apply(const mfs_scene* scene, const void* q_dev, void* y_dev, int
  *              x += d; repeated until ||b - A x|| / ||b|| <= tol (FP64 residual) or max_refine.
  *              With deflate = 1 the correction solves after the first run on the operator
  *              deflated by the first inner solve's Krylov space (GCRO) instead of afresh.
- * Each right-hand side has its own Krylov space; the R operator applications of one iteration
- * share one pair-kernel launch.  Orthogonalisation is classical Gram-Schmidt with a second pass
+ * Each right-hand side has its own Krylov space (unless block = 1, below); the R operator
+ * applications of one iteration share one pair-kernel launch.  Orthogonalisation is classical Gram-Schmidt with a second pass
  * where the first one cancelled (||w'|| < 0.1 ||w||).  The stopping test is
  * ||b - A x||_2 / ||b||_2 <= tol per column, checked with the FP64 operator before returning.
  * Synchronous.
@@ -219,6 +219,17 @@ typedef struct {
                         the kept space.  Needs room for 64 new steps after the kept ones
                         (restart >= longest kept space + 65), else plain restarts.  Ignored for
                         MFS_FP64.  0: each correction solve starts afresh */
+  int32_t block;     /* 1 with 2 <= R <= 64: block GMRES, one Krylov space shared by the R right-hand
+                        sides (each step applies the operator to a block of R basis vectors and
+                        extends the space by R; every column is the best combination of the whole
+                        space).  restart then counts block steps: the basis takes
+                        (restart+1) * R * N * 8 bytes with basis32 (16 otherwise) and the block
+                        Hessenberg matrix R^2 restart (restart+3) / 2 * 16 bytes.  Orthogonalisation
+                        is block classical Gram-Schmidt with two passes and shifted CholeskyQR3 of each
+                        new block, inner products and the least-squares problem in FP64.  MFS_MIXED:
+                        each cycle runs on the FP32 operator and is followed by the FP64 residual, as
+                        above; MFS_FP64: restarted block GMRES with the FP64 operator.  Not combined
+                        with fp64_until, use_graph or deflate.  0: one Krylov space per column */
 } mfs_solve_opts;
 
 typedef struct {

@@ -449,6 +449,359 @@ mfs_status apply_in_buffer(mfs_scene* s, const void* q, void* y, int R, mfs_prec
   return MFS_OK;
 }
 
+// ------------------------------------------------------------- block GMRES ---
+// Workspace of a block solve (carved from the scene's Krylov workspace): basis slots of N x R,
+// the packed block Hessenberg matrix, Householder vectors, least-squares right side and solution,
+// partial sums of the inner products, and R x R factors.
+struct BlockWork {
+  int64_t N = 0;
+  int R = 0, m = 0;
+  bool v32 = false;
+  void* V = nullptr;
+  c128 *Hp = nullptr, *refl = nullptr, *g = nullptr, *Y = nullptr, *h2 = nullptr, *part = nullptr;
+  c128 *gram = nullptr, *F = nullptr, *Finv = nullptr, *rtot = nullptr;
+  double *bnorm = nullptr, *res = nullptr, *npart = nullptr;
+  int32_t *flag = nullptr, *dep = nullptr;
+  int nblk = 0;
+  c128 *W = nullptr, *Wt = nullptr;  // N x R blocks
+  c128 *q1 = nullptr, *coef = nullptr;  // completion of dependent columns: one vector, its coefficients
+  // pinned host slots: R doubles, a flag and R ints
+  double* res_pin = nullptr;
+  int32_t *flag_pin = nullptr, *dep_pin = nullptr;
+  hipEvent_t ev = nullptr;
+  size_t vbytes() const { return v32 ? sizeof(c64) : sizeof(c128); }
+  void* slot(int j) const { return static_cast<char*>(V) + (size_t)j * R * N * vbytes(); }
+  int64_t hoff(int j) const { return (int64_t)R * R * ((int64_t)j * (j + 3) / 2); }
+  int64_t ldg() const { return (int64_t)(m + 1) * R; }
+};
+
+// Bytes of the block workspace for N, R, m block steps (basis of complex64 when v32).
+size_t block_work_bytes(int64_t N, int R, int m, bool v32, int64_t* offs) {
+  size_t off = 0;
+  int idx = 0;
+  auto carve = [&](size_t bytes) {
+    if (offs) offs[idx] = (int64_t)off;
+    ++idx;
+    off += (bytes + 255) / 256 * 256;
+  };
+  const size_t RR = (size_t)R * R;
+  carve((v32 ? sizeof(c64) : sizeof(c128)) * (size_t)(m + 1) * R * N);  // V
+  carve(sizeof(c128) * RR * ((size_t)m * (m + 3) / 2));                // Hp
+  carve(sizeof(c128) * (size_t)m * R * (R + 1));                       // refl
+  carve(sizeof(c128) * (size_t)(m + 1) * R * R);                       // g
+  carve(sizeof(c128) * (size_t)m * R * R);                             // Y
+  carve(sizeof(c128) * (size_t)(m + 1) * R * R);                       // h2
+  carve(sizeof(c128) * (size_t)std::max<int64_t>(kBdotsPartMax, (int64_t)(m + 1) * R) * R);  // part
+  for (int i = 0; i < 4; ++i) carve(sizeof(c128) * RR);                // gram, F, Finv, rtot
+  carve(sizeof(double) * R);                                           // bnorm
+  carve(sizeof(double) * R);                                           // res
+  carve(sizeof(double) * 2 * (size_t)R * krylov_part_blocks(N));       // norm partials
+  carve(sizeof(int32_t));                                              // flag
+  carve(sizeof(c128) * (size_t)R * N);                                 // W
+  carve(sizeof(c128) * (size_t)R * N);                                 // Wt
+  carve(sizeof(int32_t) * R);                                          // dep
+  carve(sizeof(c128) * (size_t)N);                                     // q1
+  carve(sizeof(c128) * (size_t)(m + 1) * R);                           // coef
+  return off;
+}
+
+BlockWork block_work_at(char* base, int64_t N, int R, int m, bool v32) {
+  int64_t o[32];
+  block_work_bytes(N, R, m, v32, o);
+  BlockWork b;
+  b.N = N;
+  b.R = R;
+  b.m = m;
+  b.v32 = v32;
+  b.V = base + o[0];
+  b.Hp = reinterpret_cast<c128*>(base + o[1]);
+  b.refl = reinterpret_cast<c128*>(base + o[2]);
+  b.g = reinterpret_cast<c128*>(base + o[3]);
+  b.Y = reinterpret_cast<c128*>(base + o[4]);
+  b.h2 = reinterpret_cast<c128*>(base + o[5]);
+  b.part = reinterpret_cast<c128*>(base + o[6]);
+  b.gram = reinterpret_cast<c128*>(base + o[7]);
+  b.F = reinterpret_cast<c128*>(base + o[8]);
+  b.Finv = reinterpret_cast<c128*>(base + o[9]);
+  b.rtot = reinterpret_cast<c128*>(base + o[10]);
+  b.bnorm = reinterpret_cast<double*>(base + o[11]);
+  b.res = reinterpret_cast<double*>(base + o[12]);
+  b.npart = reinterpret_cast<double*>(base + o[13]);
+  b.flag = reinterpret_cast<int32_t*>(base + o[14]);
+  b.W = reinterpret_cast<c128*>(base + o[15]);
+  b.Wt = reinterpret_cast<c128*>(base + o[16]);
+  b.dep = reinterpret_cast<int32_t*>(base + o[17]);
+  b.q1 = reinterpret_cast<c128*>(base + o[18]);
+  b.coef = reinterpret_cast<c128*>(base + o[19]);
+  b.nblk = krylov_nblk(N);
+  return b;
+}
+
+// q1 -= A (A^H q1) for the K columns of A (N x K, complex64 when a32): one Gram-Schmidt pass.
+mfs_status project_out(const BlockWork& bw, const void* A, bool a32, int K, hipStream_t st) {
+  if (K <= 0) return MFS_OK;
+  const int ns = bdots_splits(bw.N, K);
+  MFS_HIP_TRY(launch_bdots(A, a32, bw.N, K, bw.q1, bw.N, 1, bw.N, bw.part, ns, st));
+  MFS_HIP_TRY(launch_breduce(bw.part, ns, K, 1, bw.coef, K, false, nullptr, 0, st));
+  MFS_HIP_TRY(launch_bgemm_nk(A, a32, bw.N, bw.N, K, bw.coef, K, 1, -1.0, 1.0, bw.q1, bw.N, bw.q1, bw.N, st));
+  return MFS_OK;
+}
+
+// Orthonormal basis of the columns of W (N x R): shifted CholeskyQR3 (Fukaya et al. 2020) with the
+// columns scaled to unit norm in the first step, so that columns of very different size (right-hand
+// sides at different stages of convergence) do not square the condition number.  W = Q Rtot with
+// Rtot upper triangular (bw.rtot); Q is left in bw.W or bw.Wt, returned.  A column of W that lies
+// in the span of the columns before it gets a zero row of Rtot; its column of Q is then completed
+// with a pseudo-random vector orthogonalised (twice) against the first nprev basis columns and the
+// rest of Q, so that Q stays orthonormal and W = Q Rtot still holds.
+mfs_status block_qr(const BlockWork& bw, c128* W, c128** Q, int nprev, uint64_t seed, hipStream_t st) {
+  const int64_t N = bw.N;
+  const int R = bw.R;
+  const double u = 1.1102230246251565e-16;  // 2^-53
+  const double shift = 11.0 * ((double)N * R + (double)R * (R + 1)) * u * R;  // |W D^-1|_2^2 <= R
+  c128* cur = W;
+  c128* nxt = W == bw.W ? bw.Wt : bw.W;
+  const int ns = bdots_splits(N, R);
+  MFS_HIP_TRY(hipMemsetAsync(bw.flag, 0, sizeof(int32_t), st));
+  for (int p = 0; p < 3; ++p) {
+    MFS_HIP_TRY(launch_bdots(cur, false, N, R, cur, N, R, N, bw.part, ns, st));
+    MFS_HIP_TRY(launch_breduce(bw.part, ns, R, R, bw.gram, R, false, nullptr, 0, st));
+    // after the shifted first step the columns have unit norm: a pivot^2 of 1e-12 marks a column
+    // that only rounding separated from the span of the others
+    MFS_HIP_TRY(launch_chol(bw.gram, R, p == 0, p == 0 ? shift : 0.0, p == 0, p == 0 ? 0.0 : 1e-12, bw.F, bw.Finv,
+                            bw.rtot, bw.dep, bw.flag, st));
+    MFS_HIP_TRY(launch_bgemm_nk(cur, false, N, N, R, bw.Finv, R, R, 1.0, 0.0, nullptr, 0, nxt, N, st));
+    std::swap(cur, nxt);
+  }
+  *Q = cur;
+  MFS_HIP_TRY(hipMemcpyAsync(bw.flag_pin, bw.flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  MFS_HIP_TRY(hipMemcpyAsync(bw.dep_pin, bw.dep, sizeof(int32_t) * R, hipMemcpyDeviceToHost, st));
+  MFS_HIP_TRY(hipEventRecord(bw.ev, st));
+  MFS_HIP_TRY(hipEventSynchronize(bw.ev));
+  if (!*bw.flag_pin) return MFS_OK;
+  for (int k = 0; k < R; ++k) {
+    if (!bw.dep_pin[k]) continue;
+    MFS_HIP_TRY(launch_fill_random(bw.q1, N, seed * 64 + (uint64_t)k, st));
+    for (int pass = 0; pass < 2; ++pass) {
+      MFS_TRY(project_out(bw, bw.V, bw.v32, nprev, st));
+      MFS_TRY(project_out(bw, cur, false, R, st));  // column k of Q is zero until filled
+    }
+    MFS_HIP_TRY(launch_norms(bw.q1, N, 1, bw.npart, bw.nblk, bw.res, st));
+    MFS_HIP_TRY(hipMemcpyAsync(bw.res_pin, bw.res, sizeof(double), hipMemcpyDeviceToHost, st));
+    MFS_HIP_TRY(hipStreamSynchronize(st));
+    const double nrm = bw.res_pin[0];
+    if (!(nrm > 0.0)) return fail(MFS_ERR_HIP, "block QR: completion vector vanished");
+    MFS_HIP_TRY(launch_axpby(bw.q1, bw.q1, cur + (int64_t)k * N, 1.0 / nrm, 0.0, N, st));
+  }
+  return MFS_OK;
+}
+
+// Store the N x R block Q into basis slot j (rounded to complex64 when the basis is).
+mfs_status block_store_slot(const BlockWork& bw, int j, const c128* Q, hipStream_t st) {
+  const int64_t NR = bw.N * bw.R;
+  if (bw.v32) MFS_HIP_TRY(launch_to_c64(Q, static_cast<c64*>(bw.slot(j)), NR, st));
+  else MFS_HIP_TRY(hipMemcpyAsync(bw.slot(j), Q, sizeof(c128) * NR, hipMemcpyDeviceToDevice, st));
+  return MFS_OK;
+}
+
+// One block GMRES cycle on the residual block r (N x R): V_0 B0 = r, at most mlim block steps
+// (mlim <= bw.m), stopping when every column's residual estimate |g_{j+1,c}| falls to ktol times
+// that column's starting norm; then x += V Y.  `apply(j)` computes bw.W = S G_hat V_j (the
+// operator without its identity, which goes onto the Hessenberg diagonal).  Returns the steps taken
+// and the largest final estimate; res_pin is pinned host memory for R doubles and a flag.
+template <typename Apply>
+mfs_status block_cycle(const BlockWork& bw, const c128* r, c128* x, double ktol, int mlim, Apply apply, int verbose,
+                       int* steps_out, double* est_out, hipStream_t st) {
+  const int64_t N = bw.N;
+  const int R = bw.R;
+  const int64_t ldg = bw.ldg();
+  MFS_HIP_TRY(launch_norms(r, N, R, bw.npart, bw.nblk, bw.bnorm, st));
+  // starting block: r, with a pseudo-random vector in place of any zero column
+  MFS_HIP_TRY(hipMemcpyAsync(bw.W, r, sizeof(c128) * N * R, hipMemcpyDeviceToDevice, st));
+  MFS_HIP_TRY(launch_fill_zero_columns(bw.W, N, R, bw.bnorm, st));
+  c128* Q = nullptr;
+  MFS_TRY(block_qr(bw, bw.W, &Q, 0, 0, st));
+  MFS_TRY(block_store_slot(bw, 0, Q, st));
+  // g = [B0; 0] with B0 = Rtot, zero for the zero columns
+  MFS_HIP_TRY(hipMemsetAsync(bw.g, 0, sizeof(c128) * ldg * R, st));
+  MFS_HIP_TRY(hipMemcpy2DAsync(bw.g, sizeof(c128) * ldg, bw.rtot, sizeof(c128) * R, sizeof(c128) * R, R,
+                               hipMemcpyDeviceToDevice, st));
+  MFS_HIP_TRY(launch_mask_zero_columns(bw.g, ldg, R, R, bw.bnorm, st));
+  int J = 0;
+  double est = 1.0;
+  for (int j = 0; j < mlim; ++j) {
+    MFS_TRY(apply(j));  // bw.W = S G_hat V_j
+    const int K = (j + 1) * R;
+    c128* hcol = bw.Hp + bw.hoff(j);
+    const int64_t ldh = (int64_t)(j + 2) * R;
+    const int ns = bdots_splits(N, K);
+    // block classical Gram-Schmidt, two passes: H(0..j, j) = V^H W, W -= V H
+    MFS_HIP_TRY(launch_bdots(bw.V, bw.v32, N, K, bw.W, N, R, N, bw.part, ns, st));
+    MFS_HIP_TRY(launch_breduce(bw.part, ns, K, R, hcol, ldh, false, nullptr, 0, st));
+    MFS_HIP_TRY(launch_bgemm_nk(bw.V, bw.v32, N, N, K, hcol, ldh, R, -1.0, 1.0, bw.W, N, bw.W, N, st));
+    MFS_HIP_TRY(launch_bdots(bw.V, bw.v32, N, K, bw.W, N, R, N, bw.part, ns, st));
+    MFS_HIP_TRY(launch_breduce(bw.part, ns, K, R, hcol, ldh, true, bw.h2, ldg, st));
+    MFS_HIP_TRY(launch_bgemm_nk(bw.V, bw.v32, N, N, K, bw.h2, ldg, R, -1.0, 1.0, bw.W, N, bw.W, N, st));
+    // W = V_{j+1} H(j+1, j)
+    MFS_TRY(block_qr(bw, bw.W, &Q, K, (uint64_t)j + 1, st));
+    MFS_TRY(block_store_slot(bw, j + 1, Q, st));
+    MFS_HIP_TRY(hipMemcpy2DAsync(hcol + K, sizeof(c128) * ldh, bw.rtot, sizeof(c128) * R, sizeof(c128) * R, R,
+                                 hipMemcpyDeviceToDevice, st));
+    MFS_HIP_TRY(launch_add_identity(hcol, ldh, (int64_t)j * R, R, st));
+    // QR of the Hessenberg matrix: earlier reflectors on the new column block, then its own
+    MFS_HIP_TRY(launch_bhess_apply(bw.refl, R, 0, (int64_t)j * R, hcol, ldh, R, st));
+    MFS_HIP_TRY(launch_bhess_newqr(bw.refl, R, (int64_t)j * R, hcol, ldh, st));
+    MFS_HIP_TRY(launch_bhess_apply(bw.refl, R, (int64_t)j * R, (int64_t)(j + 1) * R, bw.g, ldg, R, st));
+    MFS_HIP_TRY(launch_bres(bw.g, ldg, (int64_t)(j + 1) * R, R, bw.bnorm, bw.res, st));
+    MFS_HIP_TRY(hipMemcpyAsync(bw.res_pin, bw.res, sizeof(double) * R, hipMemcpyDeviceToHost, st));
+    MFS_HIP_TRY(hipEventRecord(bw.ev, st));
+    MFS_HIP_TRY(hipEventSynchronize(bw.ev));
+    J = j + 1;
+    est = 0.0;
+    for (int c = 0; c < R; ++c) est = std::max(est, bw.res_pin[c]);
+    if (verbose > 1 && (J % 50 == 0))
+      std::fprintf(stderr, "[mfs_solve block] step %d of cycle, max estimate %.3e\n", J, est);
+    if (est <= ktol) break;
+  }
+  // Y = U^{-1} g (block back substitution), x += V Y
+  for (int i = J - 1; i >= 0; --i) {
+    const c128* Ui = bw.Hp + bw.hoff(i);
+    const int64_t ldu = (int64_t)(i + 2) * R;
+    MFS_HIP_TRY(launch_btrsm_diag(Ui + (int64_t)i * R, ldu, bw.g + (int64_t)i * R, ldg, bw.Y + (int64_t)i * R,
+                                  (int64_t)bw.m * R, R, st));
+    if (i > 0)
+      MFS_HIP_TRY(launch_bgemm_nk(Ui, false, ldu, (int64_t)i * R, R, bw.Y + (int64_t)i * R, (int64_t)bw.m * R, R,
+                                  -1.0, 1.0, bw.g, ldg, bw.g, ldg, st));
+  }
+  if (J > 0)
+    MFS_HIP_TRY(launch_bgemm_nk(bw.V, bw.v32, N, N, J * R, bw.Y, (int64_t)bw.m * R, R, 1.0, 1.0, x, N, x, N, st));
+  *steps_out = J;
+  *est_out = est;
+  return MFS_OK;
+}
+
+// The block solve behind mfs_solve with opts->block (2 <= R <= 64): one block Krylov space for the
+// R right-hand sides.  MFS_MIXED: each cycle runs on the FP32 operator (basis in complex64 with
+// basis32) on the current FP64 residual and asks for the reduction the outer tolerance still
+// needs (at most down to inner_tol), then the FP64 residual is formed (iterative refinement).
+// MFS_FP64: cycles of restarted block GMRES with the FP64 operator, the FP64 residual checked after
+// each.  Converged right-hand sides stay in the block (their residuals keep shrinking).
+mfs_status solve_block(mfs_scene* s, const c128* vhat, int R, const mfs_solve_opts* opts, c128* x,
+                       mfs_solve_info* info, hipStream_t st, std::chrono::steady_clock::time_point t0) {
+  if (R > 64) return fail(MFS_ERR_ARG, "solve: block GMRES takes at most 64 right-hand sides");
+  const mfs_prec prec = opts->prec;
+  const int64_t N = s->dev.N, NR = N * R;
+  const int m = opts->restart;
+  const bool v32 = prec == MFS_MIXED && opts->basis32 != 0;
+  MFS_TRY(ensure(s->kry, block_work_bytes(N, R, m, v32, nullptr), &s->bytes, st));
+  BlockWork bw = block_work_at(static_cast<char*>(s->kry.p), N, R, m, v32);
+  MFS_TRY(ensure(s->vecs, 3 * sizeof(c128) * (size_t)NR + 256, &s->bytes, st));
+  c128* b = static_cast<c128*>(s->vecs.p);
+  c128* r = b + NR;
+  c128* w = r + NR;
+  size_t pin_bytes = 0;
+  hipError_t pin_err = hipSuccess;
+  char* pin = static_cast<char*>(pinned_alloc(sizeof(double) * R + sizeof(int32_t) * (R + 2) + 64, &pin_bytes, &pin_err));
+  if (!pin) return fail(MFS_ERR_NOMEM, std::string("pinned host allocation failed: ") + hipGetErrorString(pin_err));
+  struct PinGuard {
+    void* p;
+    size_t n;
+    hipEvent_t ev;
+    ~PinGuard() {
+      if (ev) {
+        (void)hipEventSynchronize(ev);
+        (void)hipEventDestroy(ev);
+      }
+      pinned_free(p, n);
+    }
+  } guard{pin, pin_bytes, nullptr};
+  MFS_HIP_TRY(hipEventCreateWithFlags(&guard.ev, hipEventDisableTiming));
+  double* res_pin = reinterpret_cast<double*>(pin);
+  bw.res_pin = res_pin;
+  bw.flag_pin = reinterpret_cast<int32_t*>(pin + sizeof(double) * R);
+  bw.dep_pin = bw.flag_pin + 1;
+  bw.ev = guard.ev;
+
+  std::vector<double> bnorm(R), relres(R, 1.0);
+  auto read_norms = [&](const c128* v, std::vector<double>& out) -> mfs_status {
+    MFS_HIP_TRY(launch_norms(v, N, R, bw.npart, bw.nblk, bw.res, st));
+    MFS_HIP_TRY(hipMemcpyAsync(res_pin, bw.res, sizeof(double) * R, hipMemcpyDeviceToHost, st));
+    MFS_HIP_TRY(hipStreamSynchronize(st));
+    out.assign(res_pin, res_pin + R);
+    return MFS_OK;
+  };
+  int n32 = 0, n64 = 0, n_refine = 0, n_restart = 0, total = 0;
+  auto residual = [&]() -> mfs_status {  // r = b - A64 x, relres per column
+    MFS_TRY(apply_f64(s, x, w, R, st));
+    ++n64;
+    MFS_HIP_TRY(launch_axpby(b, w, r, 1.0, -1.0, NR, st));
+    std::vector<double> rn;
+    MFS_TRY(read_norms(r, rn));
+    for (int c = 0; c < R; ++c) relres[c] = bnorm[c] > 0.0 ? rn[c] / bnorm[c] : 0.0;
+    return MFS_OK;
+  };
+  auto max_relres = [&]() {
+    double mx = 0.0;
+    for (double v : relres) mx = std::max(mx, v);
+    return mx;
+  };
+  auto apply = [&](int j) -> mfs_status {  // bw.W = S G_hat V_j
+    if (prec == MFS_MIXED) {
+      if (v32) MFS_TRY(apply_mixed_from32(s, static_cast<const c64*>(bw.slot(j)), bw.W, R, st));
+      else MFS_TRY(apply_mixed(s, static_cast<const c128*>(bw.slot(j)), bw.W, R, st, 0.0));
+      ++n32;
+    } else {
+      MFS_TRY(apply_f64(s, static_cast<const c128*>(bw.slot(j)), bw.W, R, st, 0.0));
+      ++n64;
+    }
+    return MFS_OK;
+  };
+
+  // b = S vhat (eq. mbody2)
+  MFS_HIP_TRY(launch_sapply_f64(s->dev, vhat, 1, nullptr, 0.0, b, R, (int)s->kmax, st));
+  MFS_TRY(read_norms(b, bnorm));
+  if (opts->use_x0) {
+    MFS_TRY(residual());
+  } else {
+    MFS_HIP_TRY(hipMemsetAsync(x, 0, sizeof(c128) * NR, st));
+    MFS_HIP_TRY(hipMemcpyAsync(r, b, sizeof(c128) * NR, hipMemcpyDeviceToDevice, st));
+    for (int c = 0; c < R; ++c) relres[c] = bnorm[c] > 0.0 ? 1.0 : 0.0;
+  }
+  const int max_cycles = prec == MFS_MIXED ? opts->max_refine : 1 << 30;
+  while (max_relres() > opts->tol && n_refine < max_cycles && total < opts->maxit) {
+    // reduction still needed by the worst column, relative to each column's current residual
+    double ktol = opts->tol / std::max(max_relres(), 1e-300);
+    if (prec == MFS_MIXED) ktol = std::min(std::max(opts->inner_tol, 0.3 * ktol), 0.5);
+    const int mlim = std::min(m, opts->maxit - total);
+    int steps = 0;
+    double est = 0.0;
+    MFS_TRY(block_cycle(bw, r, x, ktol, mlim, apply, opts->verbose, &steps, &est, st));
+    total += steps;
+    ++n_refine;
+    ++n_restart;
+    MFS_TRY(residual());
+    if (opts->verbose)
+      std::fprintf(stderr, "[mfs_solve block %s] cycle %d  block steps %d (total %d)  estimate %.3e  max relres %.3e\n",
+                   prec == MFS_MIXED ? "mixed" : "fp64", n_refine, steps, total, est, max_relres());
+    if (steps == 0) break;
+  }
+  MFS_HIP_TRY(hipStreamSynchronize(st));
+  const auto t1 = std::chrono::steady_clock::now();
+  if (info) {
+    info->n_reorth = total;  // every block step takes both Gram-Schmidt passes
+    info->n_matvec32 = n32;
+    info->n_matvec64 = n64;
+    info->n_refine = prec == MFS_MIXED ? n_refine : 0;
+    info->n_restart = n_restart;
+    info->relres_max = max_relres();
+    info->t_total_s = std::chrono::duration<double>(t1 - t0).count();
+  }
+  if (max_relres() > opts->tol)
+    return fail(MFS_ERR_NOCONV, "block solve: relative residual " + std::to_string(max_relres()) + " above tol after " +
+                                    std::to_string(total) + " block steps");
+  return MFS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -828,6 +1181,11 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
   mfs_scene* s = const_cast<mfs_scene*>(sc);
   hipStream_t st = as_stream(stream);
   s->last_stream = st;
+  if (opts->block != 0 && R > 1) {
+    if (opts->fp64_until > 0.0 || opts->use_graph || opts->deflate)
+      return fail(MFS_ERR_ARG, "solve: block GMRES does not take fp64_until, use_graph or deflate");
+    return solve_block(s, static_cast<const c128*>(vhat_dev), R, opts, static_cast<c128*>(qhat_dev), info, st, t0);
+  }
   const int64_t N = s->dev.N;
   const int64_t NR = N * R;
   const int m = opts->restart;

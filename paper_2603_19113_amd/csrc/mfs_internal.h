@@ -207,6 +207,36 @@ hipError_t launch_deflate_coeffs(const c128* q, int o, const int32_t* kold, c128
 hipError_t launch_axpby(const c128* a, const c128* b, c128* out, double alpha, double beta, int64_t n,
                         hipStream_t st);
 
+// Block GMRES (bkrylov.hip): one Krylov space for all R <= 64 right-hand sides.  Matrices are
+// column-major complex128 unless a32 (then A is complex64); see bkrylov.hip for the layouts.
+//   bdots:     part[s][c][k] = sum over row slice s of conj(A[k][n]) B[c][n], k < K, c < R
+//   breduce:   out[k + c ldo] (= or +=) sum_s part[s][c][k]; copy gets the sum too when not null
+//   bgemm_nk:  out[c ldo + n] = beta in[c ldi + n] + alpha sum_k A[k lda + n] C[k + c ldc], n < M
+//   chol:      one shifted CholeskyQR step on an R x R Gram matrix (F, Finv, Rtot = F Rtot)
+//   bhess_*:   Householder QR of the block Hessenberg matrix (reflector rho on rows rho..rho+R)
+constexpr int64_t kBdotsPartMax = 131072;  // bound on nsplit * K of one bdots launch
+int bdots_splits(int64_t N, int K);
+hipError_t launch_bdots(const void* A, bool a32, int64_t lda, int K, const c128* B, int64_t ldb, int R, int64_t N,
+                        c128* part, int nsplit, hipStream_t st);
+hipError_t launch_breduce(const c128* part, int nsplit, int K, int R, c128* out, int64_t ldo, bool accumulate,
+                          c128* copy, int64_t ldc, hipStream_t st);
+hipError_t launch_bgemm_nk(const void* A, bool a32, int64_t lda, int64_t M, int K, const c128* C, int64_t ldc, int R,
+                           double alpha, double beta, const c128* in, int64_t ldi, c128* out, int64_t ldo,
+                           hipStream_t st);
+hipError_t launch_chol(const c128* G, int R, bool scale, double shift, bool first, double dep_tol, c128* F, c128* Finv,
+                       c128* Rtot, int32_t* dep, int32_t* flag, hipStream_t st);
+hipError_t launch_fill_random(c128* x, int64_t N, uint64_t seed, hipStream_t st);
+hipError_t launch_bhess_apply(const c128* refl, int R, int64_t rho0, int64_t rho1, c128* X, int64_t ldx, int ncols,
+                              hipStream_t st);
+hipError_t launch_bhess_newqr(c128* refl, int R, int64_t jR, c128* X, int64_t ldx, hipStream_t st);
+hipError_t launch_bres(const c128* g, int64_t ldg, int64_t row0, int R, const double* bnorm, double* res,
+                       hipStream_t st);
+hipError_t launch_btrsm_diag(const c128* U, int64_t ldu, const c128* g, int64_t ldg, c128* Y, int64_t ldy, int R,
+                             hipStream_t st);
+hipError_t launch_fill_zero_columns(c128* X, int64_t N, int R, const double* bnorm, hipStream_t st);
+hipError_t launch_mask_zero_columns(c128* M, int64_t ldm, int rows, int R, const double* bnorm, hipStream_t st);
+hipError_t launch_add_identity(c128* X, int64_t ldx, int64_t row0, int R, hipStream_t st);
+
 // Kernel timing (mfs_api.hip): bracket a launch with events when recording is on.
 struct TimedLaunch {
   TimedLaunch(int kind, double pairs, hipStream_t st);

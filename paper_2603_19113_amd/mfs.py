@@ -44,7 +44,8 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("max_refine", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("prec", ctypes.c_int32),
                 ("verbose", ctypes.c_int32), ("fp64_until", ctypes.c_double), ("use_x0", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("basis32", ctypes.c_int32), ("deflate", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("basis32", ctypes.c_int32), ("deflate", ctypes.c_int32),
+                ("block", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -298,10 +299,10 @@ STATIC_SCRATCH_BYTES = 64 << 20
 def solve(scene: Scene, vhat, qhat, tol=1e-8, maxit=2000, restart=300, max_refine=10, inner_tol=1e-4,
           prec: int = MFS_FP64, verbose: int = 0, fp64_until: float = 0.0, use_x0: bool = False, stream=None,
           raise_on_noconv: bool = True, use_graph: bool = False, basis32: bool = False,
-          deflate: bool = False) -> dict:
+          deflate: bool = False, block: bool = False) -> dict:
     o = SolveOpts(tol=tol, maxit=maxit, restart=restart, max_refine=max_refine, inner_tol=inner_tol, prec=prec,
                   verbose=verbose, fp64_until=fp64_until, use_x0=1 if use_x0 else 0, use_graph=1 if use_graph else 0,
-                  basis32=1 if basis32 else 0, deflate=1 if deflate else 0)
+                  basis32=1 if basis32 else 0, deflate=1 if deflate else 0, block=1 if block else 0)
     info = SolveInfo()
     code = _lib.mfs_solve(scene.handle, _ptr(vhat), vhat.shape[0], ctypes.byref(o), _ptr(qhat),
                           ctypes.byref(info), _stream(stream))
