@@ -454,6 +454,46 @@ __global__ __launch_bounds__(64) void bhess_apply_kernel(const c128* __restrict_
   window_store(wv, x, rho1 - 1, R, lane);
 }
 
+// Slide the window up one row: row base + R is final (stored), rows base-1 .. base+R-1 stay or load.
+__device__ __forceinline__ void window_slide_up(Window& wv, c128* __restrict__ X, int64_t base, int R, int lane) {
+  if (R == 64) {
+    if (lane == 63) X[base + 64] = c128{wv.br, wv.bi};
+  } else if (lane == R) {
+    X[base + R] = c128{wv.ar, wv.ai};
+  }
+  const int src = (lane + 63) & 63;
+  double nr = __shfl(wv.ar, src, 64), ni = __shfl(wv.ai, src, 64);
+  if (R == 64 && lane == 63) {
+    wv.br = wv.ar;  // old row base + 63 becomes position 64
+    wv.bi = wv.ai;
+  }
+  if (lane == 0) {
+    const c128 t = X[base - 1];
+    nr = t.re;
+    ni = t.im;
+  } else if (lane > R) {
+    nr = ni = 0.0;
+  }
+  wv.ar = nr;
+  wv.ai = ni;
+}
+
+// Apply reflectors rho1 - 1 down to rho0 (the product H_rho0 ... H_{rho1-1} = the unitary factor Q of
+// the Hessenberg QR, where the forward order gives Q^H) to column blockIdx.x of X.
+__global__ __launch_bounds__(64) void bhess_apply_rev_kernel(const c128* __restrict__ refl, int R, int64_t rho0,
+                                                             int64_t rho1, c128* __restrict__ X, int64_t ldx) {
+  const int lane = threadIdx.x;
+  c128* x = X + (int64_t)blockIdx.x * ldx;
+  if (rho1 <= rho0) return;
+  Window wv;
+  window_load(wv, x, rho1 - 1, R, lane);
+  for (int64_t rho = rho1 - 1; rho >= rho0; --rho) {
+    window_reflect(wv, refl + rho * (R + 1), R, lane);
+    if (rho > rho0) window_slide_up(wv, x, rho, R, lane);
+  }
+  window_store(wv, x, rho0, R, lane);
+}
+
 // QR of the new column block's bottom 2R x R part (rows jR .. (j+2)R - 1; the lower R x R block is
 // upper triangular): for column c, the reflectors jR .. jR + c - 1 already built are applied, then
 // reflector jR + c is formed from rows jR + c .. jR + c + R and stored, leaving alpha on the
@@ -585,7 +625,31 @@ __global__ void add_identity_kernel(c128* __restrict__ X, int64_t ldx, int64_t r
   if (c < R) X[row0 + c + (int64_t)c * ldx].re += 1.0;
 }
 
+// out[i + c ldo] (= or +=) in[i + c ldi] for i < rows, c < cols.
+__global__ void copy2d_kernel(const c128* __restrict__ in, int64_t ldi, int64_t rows, int cols, c128* __restrict__ out,
+                              int64_t ldo, int accumulate) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= rows || c >= cols) return;
+  const c128 v = in[i + (int64_t)c * ldi];
+  c128* o = out + i + (int64_t)c * ldo;
+  if (accumulate) {
+    o->re += v.re;
+    o->im += v.im;
+  } else {
+    *o = v;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_copy2d(const c128* in, int64_t ldi, int64_t rows, int cols, c128* out, int64_t ldo, bool accumulate,
+                         hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy2d_kernel, dim3((unsigned)((rows + 255) / 256), (unsigned)cols), dim3(256), 0, st, in, ldi, rows,
+                     cols, out, ldo, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
 
 hipError_t launch_mask_zero_columns(c128* M, int64_t ldm, int rows, int R, const double* bnorm, hipStream_t st) {
   hipLaunchKernelGGL(mask_zero_columns_kernel, dim3((unsigned)R), dim3(64), 0, st, M, ldm, rows, R, bnorm);
@@ -660,6 +724,13 @@ hipError_t launch_bhess_apply(const c128* refl, int R, int64_t rho0, int64_t rho
                               hipStream_t st) {
   if (rho1 <= rho0 || ncols <= 0) return hipSuccess;
   hipLaunchKernelGGL(bhess_apply_kernel, dim3((unsigned)ncols), dim3(64), 0, st, refl, R, rho0, rho1, X, ldx);
+  return hipGetLastError();
+}
+
+hipError_t launch_bhess_apply_rev(const c128* refl, int R, int64_t rho0, int64_t rho1, c128* X, int64_t ldx,
+                                  int ncols, hipStream_t st) {
+  if (rho1 <= rho0 || ncols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(bhess_apply_rev_kernel, dim3((unsigned)ncols), dim3(64), 0, st, refl, R, rho0, rho1, X, ldx);
   return hipGetLastError();
 }
 

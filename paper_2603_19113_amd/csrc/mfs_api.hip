@@ -604,54 +604,124 @@ mfs_status block_store_slot(const BlockWork& bw, int j, const c128* Q, hipStream
   return MFS_OK;
 }
 
-// One block GMRES cycle on the residual block r (N x R): V_0 B0 = r, at most mlim block steps
-// (mlim <= bw.m), stopping when every column's residual estimate |g_{j+1,c}| falls to ktol times
-// that column's starting norm; then x += V Y.  `apply(j)` computes bw.W = S G_hat V_j (the
-// operator without its identity, which goes onto the Hessenberg diagonal).  Returns the steps taken
-// and the largest final estimate; res_pin is pinned host memory for R doubles and a flag.
-template <typename Apply>
-mfs_status block_cycle(const BlockWork& bw, const c128* r, c128* x, double ktol, int mlim, Apply apply, int verbose,
-                       int* steps_out, double* est_out, hipStream_t st) {
+// Where one block Arnoldi process keeps its state: first basis slot, packed Hessenberg matrix and
+// Householder vectors (a later process's follow those of a kept one).
+struct BlockProcess {
+  int o = 0;
+  c128* Hp = nullptr;
+  c128* refl = nullptr;
+};
+
+// The first cycle's process, kept for the deflated correction cycles (GCRO, de Sturler 1996, the
+// block form of the single-right-hand-side path): after k block steps K~ V_k = V_{k+1} Hbar with
+// Hbar = Q [U; 0] (Q from the stored reflectors), C = V_{k+1} Q_{:, 0:kR} is an orthonormal basis of
+// K~ V_k, and C C^H = V_{k+1} (I - q q^H) V_{k+1}^H with q the last R columns of Q.
+struct KeptSpace {
+  int k = 0;  // block steps (slots 0..k)
+  const c128* Hp = nullptr;
+  const c128* refl = nullptr;
+};
+
+// Y = U^{-1} rhs for the first J column blocks of a process's triangular factor (block back
+// substitution; rhs, leading dimension ldr, is overwritten).
+mfs_status block_backsolve(const BlockWork& bw, const c128* Hp, int J, c128* rhs, int64_t ldr, hipStream_t st) {
+  const int R = bw.R;
+  for (int i = J - 1; i >= 0; --i) {
+    const c128* Ui = Hp + bw.hoff(i);
+    const int64_t ldu = (int64_t)(i + 2) * R;
+    MFS_HIP_TRY(launch_btrsm_diag(Ui + (int64_t)i * R, ldu, rhs + (int64_t)i * R, ldr, bw.Y + (int64_t)i * R,
+                                  (int64_t)bw.m * R, R, st));
+    if (i > 0)
+      MFS_HIP_TRY(launch_bgemm_nk(Ui, false, ldu, (int64_t)i * R, R, bw.Y + (int64_t)i * R, (int64_t)bw.m * R, R,
+                                  -1.0, 1.0, rhs, ldr, rhs, ldr, st));
+  }
+  return MFS_OK;
+}
+
+// a <- (I - q q^H) a for the first (k+1)R rows of the R columns of a (leading dimension lda): Q^H,
+// zero the last R rows, Q.
+mfs_status project_kept(const BlockWork& bw, const KeptSpace& kp, c128* a, int64_t lda, hipStream_t st) {
+  const int R = bw.R;
+  const int64_t kR = (int64_t)kp.k * R;
+  MFS_HIP_TRY(launch_bhess_apply(kp.refl, R, 0, kR, a, lda, R, st));
+  MFS_HIP_TRY(hipMemset2DAsync(a + kR, sizeof(c128) * lda, 0, sizeof(c128) * R, R, st));
+  MFS_HIP_TRY(launch_bhess_apply_rev(kp.refl, R, 0, kR, a, lda, R, st));
+  return MFS_OK;
+}
+
+// One block GMRES cycle on the residual block r (N x R), at most mlim block steps, stopping when
+// every column's residual estimate |g_{j+1,c}| falls to ktol times that column's starting norm;
+// x += the correction.  `apply(slot)` computes bw.W = S G_hat V_slot and `apply_vec(v)` computes
+// bw.W = S G_hat v for an N x R complex128 block (the operator without its identity, which goes onto
+// the Hessenberg diagonal).  With a kept space (kp.k > 0) the process runs on (I - C C^H) K~ from
+// (I - C C^H) r with its basis from slot pr.o, and the correction is W y + V_k U^{-1} C^H (r - K~ W y).
+template <typename Apply, typename ApplyVec>
+mfs_status block_cycle(const BlockWork& bw, const BlockProcess& pr, const KeptSpace& kp, const c128* r, c128* x,
+                       double ktol, int mlim, Apply apply, ApplyVec apply_vec, int verbose, int* steps_out,
+                       double* est_out, hipStream_t st) {
   const int64_t N = bw.N;
   const int R = bw.R;
   const int64_t ldg = bw.ldg();
+  const int o = pr.o;
+  const bool defl = kp.k > 0;
+  const int ko = defl ? kp.k + 1 : 0;  // kept basis blocks
   MFS_HIP_TRY(launch_norms(r, N, R, bw.npart, bw.nblk, bw.bnorm, st));
-  // starting block: r, with a pseudo-random vector in place of any zero column
+  // starting block: r (projected off C with a kept space), a pseudo-random vector for a zero column
   MFS_HIP_TRY(hipMemcpyAsync(bw.W, r, sizeof(c128) * N * R, hipMemcpyDeviceToDevice, st));
+  if (defl) {
+    const int K = ko * R;
+    const int ns = bdots_splits(N, K);
+    MFS_HIP_TRY(launch_bdots(bw.V, bw.v32, N, K, bw.W, N, R, N, bw.part, ns, st));
+    MFS_HIP_TRY(launch_breduce(bw.part, ns, K, R, bw.h2, ldg, false, nullptr, 0, st));
+    MFS_TRY(project_kept(bw, kp, bw.h2, ldg, st));
+    MFS_HIP_TRY(launch_bgemm_nk(bw.V, bw.v32, N, N, K, bw.h2, ldg, R, -1.0, 1.0, bw.W, N, bw.W, N, st));
+  }
   MFS_HIP_TRY(launch_fill_zero_columns(bw.W, N, R, bw.bnorm, st));
   c128* Q = nullptr;
-  MFS_TRY(block_qr(bw, bw.W, &Q, 0, 0, st));
-  MFS_TRY(block_store_slot(bw, 0, Q, st));
-  // g = [B0; 0] with B0 = Rtot, zero for the zero columns
+  MFS_TRY(block_qr(bw, bw.W, &Q, defl ? ko * R : 0, (uint64_t)o << 20, st));
+  MFS_TRY(block_store_slot(bw, o, Q, st));
+  // g = [B0; 0]: the starting block's coefficients, zero for the zero columns; the estimate is
+  // relative to |r|, not to |(I - C C^H) r|
   MFS_HIP_TRY(hipMemsetAsync(bw.g, 0, sizeof(c128) * ldg * R, st));
   MFS_HIP_TRY(hipMemcpy2DAsync(bw.g, sizeof(c128) * ldg, bw.rtot, sizeof(c128) * R, sizeof(c128) * R, R,
                                hipMemcpyDeviceToDevice, st));
   MFS_HIP_TRY(launch_mask_zero_columns(bw.g, ldg, R, R, bw.bnorm, st));
   int J = 0;
   double est = 1.0;
-  for (int j = 0; j < mlim; ++j) {
-    MFS_TRY(apply(j));  // bw.W = S G_hat V_j
-    const int K = (j + 1) * R;
-    c128* hcol = bw.Hp + bw.hoff(j);
+  for (int j = 0; j < mlim && o + j + 1 <= bw.m; ++j) {
+    MFS_TRY(apply(o + j));  // bw.W = S G_hat V_{o+j}
+    const int K = (o + j + 1) * R;  // every basis block so far (kept and this process's)
+    c128* hcol = pr.Hp + bw.hoff(j);
     const int64_t ldh = (int64_t)(j + 2) * R;
     const int ns = bdots_splits(N, K);
-    // block classical Gram-Schmidt, two passes: H(0..j, j) = V^H W, W -= V H
-    MFS_HIP_TRY(launch_bdots(bw.V, bw.v32, N, K, bw.W, N, R, N, bw.part, ns, st));
-    MFS_HIP_TRY(launch_breduce(bw.part, ns, K, R, hcol, ldh, false, nullptr, 0, st));
-    MFS_HIP_TRY(launch_bgemm_nk(bw.V, bw.v32, N, N, K, hcol, ldh, R, -1.0, 1.0, bw.W, N, bw.W, N, st));
-    MFS_HIP_TRY(launch_bdots(bw.V, bw.v32, N, K, bw.W, N, R, N, bw.part, ns, st));
-    MFS_HIP_TRY(launch_breduce(bw.part, ns, K, R, hcol, ldh, true, bw.h2, ldg, st));
-    MFS_HIP_TRY(launch_bgemm_nk(bw.V, bw.v32, N, N, K, bw.h2, ldg, R, -1.0, 1.0, bw.W, N, bw.W, N, st));
-    // W = V_{j+1} H(j+1, j)
-    MFS_TRY(block_qr(bw, bw.W, &Q, K, (uint64_t)j + 1, st));
-    MFS_TRY(block_store_slot(bw, j + 1, Q, st));
-    MFS_HIP_TRY(hipMemcpy2DAsync(hcol + K, sizeof(c128) * ldh, bw.rtot, sizeof(c128) * R, sizeof(c128) * R, R,
-                                 hipMemcpyDeviceToDevice, st));
+    // block classical Gram-Schmidt, two passes.  Without a kept space: H(0..j, j) = V^H W, W -= V H.
+    // With one, the coefficients on the kept vectors are replaced by their part along C (the rest
+    // of the kept space stays in W) and only this process's coefficients enter its Hessenberg matrix.
+    for (int pass = 0; pass < 2; ++pass) {
+      MFS_HIP_TRY(launch_bdots(bw.V, bw.v32, N, K, bw.W, N, R, N, bw.part, ns, st));
+      if (!defl) {
+        MFS_HIP_TRY(launch_breduce(bw.part, ns, K, R, hcol, ldh, pass == 1, pass == 1 ? bw.h2 : nullptr, ldg, st));
+        MFS_HIP_TRY(launch_bgemm_nk(bw.V, bw.v32, N, N, K, pass == 0 ? hcol : bw.h2, pass == 0 ? ldh : ldg, R, -1.0,
+                                    1.0, bw.W, N, bw.W, N, st));
+      } else {
+        MFS_HIP_TRY(launch_breduce(bw.part, ns, K, R, bw.h2, ldg, false, nullptr, 0, st));
+        // this process's rows go to its Hessenberg column (set, then accumulated); its basis follows
+        // the kept blocks directly (o = k + 1)
+        MFS_HIP_TRY(launch_copy2d(bw.h2 + (int64_t)o * R, ldg, (int64_t)(j + 1) * R, R, hcol, ldh, pass == 1, st));
+        MFS_TRY(project_kept(bw, kp, bw.h2, ldg, st));
+        MFS_HIP_TRY(launch_bgemm_nk(bw.V, bw.v32, N, N, K, bw.h2, ldg, R, -1.0, 1.0, bw.W, N, bw.W, N, st));
+      }
+    }
+    // W = V_{o+j+1} H(j+1, j)
+    MFS_TRY(block_qr(bw, bw.W, &Q, K, ((uint64_t)o << 20) + (uint64_t)j + 1, st));
+    MFS_TRY(block_store_slot(bw, o + j + 1, Q, st));
+    MFS_HIP_TRY(hipMemcpy2DAsync(hcol + (int64_t)(j + 1) * R, sizeof(c128) * ldh, bw.rtot, sizeof(c128) * R,
+                                 sizeof(c128) * R, R, hipMemcpyDeviceToDevice, st));
     MFS_HIP_TRY(launch_add_identity(hcol, ldh, (int64_t)j * R, R, st));
     // QR of the Hessenberg matrix: earlier reflectors on the new column block, then its own
-    MFS_HIP_TRY(launch_bhess_apply(bw.refl, R, 0, (int64_t)j * R, hcol, ldh, R, st));
-    MFS_HIP_TRY(launch_bhess_newqr(bw.refl, R, (int64_t)j * R, hcol, ldh, st));
-    MFS_HIP_TRY(launch_bhess_apply(bw.refl, R, (int64_t)j * R, (int64_t)(j + 1) * R, bw.g, ldg, R, st));
+    MFS_HIP_TRY(launch_bhess_apply(pr.refl, R, 0, (int64_t)j * R, hcol, ldh, R, st));
+    MFS_HIP_TRY(launch_bhess_newqr(pr.refl, R, (int64_t)j * R, hcol, ldh, st));
+    MFS_HIP_TRY(launch_bhess_apply(pr.refl, R, (int64_t)j * R, (int64_t)(j + 1) * R, bw.g, ldg, R, st));
     MFS_HIP_TRY(launch_bres(bw.g, ldg, (int64_t)(j + 1) * R, R, bw.bnorm, bw.res, st));
     MFS_HIP_TRY(hipMemcpyAsync(bw.res_pin, bw.res, sizeof(double) * R, hipMemcpyDeviceToHost, st));
     MFS_HIP_TRY(hipEventRecord(bw.ev, st));
@@ -663,18 +733,29 @@ mfs_status block_cycle(const BlockWork& bw, const c128* r, c128* x, double ktol,
       std::fprintf(stderr, "[mfs_solve block] step %d of cycle, max estimate %.3e\n", J, est);
     if (est <= ktol) break;
   }
-  // Y = U^{-1} g (block back substitution), x += V Y
-  for (int i = J - 1; i >= 0; --i) {
-    const c128* Ui = bw.Hp + bw.hoff(i);
-    const int64_t ldu = (int64_t)(i + 2) * R;
-    MFS_HIP_TRY(launch_btrsm_diag(Ui + (int64_t)i * R, ldu, bw.g + (int64_t)i * R, ldg, bw.Y + (int64_t)i * R,
-                                  (int64_t)bw.m * R, R, st));
-    if (i > 0)
-      MFS_HIP_TRY(launch_bgemm_nk(Ui, false, ldu, (int64_t)i * R, R, bw.Y + (int64_t)i * R, (int64_t)bw.m * R, R,
-                                  -1.0, 1.0, bw.g, ldg, bw.g, ldg, st));
+  // W y: Y = U^{-1} g (block back substitution), then x += V_{o..o+J-1} Y
+  MFS_TRY(block_backsolve(bw, pr.Hp, J, bw.g, ldg, st));
+  if (!defl) {
+    if (J > 0)
+      MFS_HIP_TRY(launch_bgemm_nk(bw.slot(o), bw.v32, N, N, J * R, bw.Y, (int64_t)bw.m * R, R, 1.0, 1.0, x, N, x, N,
+                                  st));
+  } else {
+    // d1 = W y into Wt; x += d1; u = r - K~ d1 = r - d1 - S G_hat d1; z = Q^H V_{0..k}^H u;
+    // x += V_{0..k-1} U^{-1} z_{0..kR-1}
+    MFS_HIP_TRY(launch_bgemm_nk(bw.slot(o), bw.v32, N, N, J * R, bw.Y, (int64_t)bw.m * R, R, 1.0, 0.0, nullptr, 0,
+                                bw.Wt, N, st));
+    MFS_HIP_TRY(launch_axpby(x, bw.Wt, x, 1.0, 1.0, N * R, st));
+    MFS_TRY(apply_vec(bw.Wt));  // bw.W = S G_hat d1
+    MFS_HIP_TRY(launch_axpby(r, bw.W, bw.W, 1.0, -1.0, N * R, st));
+    MFS_HIP_TRY(launch_axpby(bw.W, bw.Wt, bw.W, 1.0, -1.0, N * R, st));
+    const int K = ko * R;
+    const int ns = bdots_splits(N, K);
+    MFS_HIP_TRY(launch_bdots(bw.V, bw.v32, N, K, bw.W, N, R, N, bw.part, ns, st));
+    MFS_HIP_TRY(launch_breduce(bw.part, ns, K, R, bw.h2, ldg, false, nullptr, 0, st));
+    MFS_HIP_TRY(launch_bhess_apply(kp.refl, R, 0, (int64_t)kp.k * R, bw.h2, ldg, R, st));
+    MFS_TRY(block_backsolve(bw, kp.Hp, kp.k, bw.h2, ldg, st));
+    MFS_HIP_TRY(launch_bgemm_nk(bw.V, bw.v32, N, N, kp.k * R, bw.Y, (int64_t)bw.m * R, R, 1.0, 1.0, x, N, x, N, st));
   }
-  if (J > 0)
-    MFS_HIP_TRY(launch_bgemm_nk(bw.V, bw.v32, N, N, J * R, bw.Y, (int64_t)bw.m * R, R, 1.0, 1.0, x, N, x, N, st));
   *steps_out = J;
   *est_out = est;
   return MFS_OK;
@@ -756,6 +837,19 @@ mfs_status solve_block(mfs_scene* s, const c128* vhat, int R, const mfs_solve_op
     }
     return MFS_OK;
   };
+  auto apply_vec = [&](const c128* v) -> mfs_status {  // bw.W = S G_hat v, v an N x R complex128 block
+    if (prec == MFS_MIXED) {
+      MFS_TRY(apply_mixed(s, v, bw.W, R, st, 0.0));
+      ++n32;
+    } else {
+      MFS_TRY(apply_f64(s, v, bw.W, R, st, 0.0));
+      ++n64;
+    }
+    return MFS_OK;
+  };
+  BlockProcess first{0, bw.Hp, bw.refl};
+  KeptSpace kept{};
+  BlockProcess later = first;
 
   // b = S vhat (eq. mbody2)
   MFS_HIP_TRY(launch_sapply_f64(s->dev, vhat, 1, nullptr, 0.0, b, R, (int)s->kmax, st));
@@ -772,10 +866,17 @@ mfs_status solve_block(mfs_scene* s, const c128* vhat, int R, const mfs_solve_op
     // reduction still needed by the worst column, relative to each column's current residual
     double ktol = opts->tol / std::max(max_relres(), 1e-300);
     if (prec == MFS_MIXED) ktol = std::min(std::max(opts->inner_tol, 0.3 * ktol), 0.5);
-    const int mlim = std::min(m, opts->maxit - total);
+    const int mlim = std::min(m - (kept.k > 0 ? later.o : 0), opts->maxit - total);
     int steps = 0;
     double est = 0.0;
-    MFS_TRY(block_cycle(bw, r, x, ktol, mlim, apply, opts->verbose, &steps, &est, st));
+    const bool use_kept = kept.k > 0;
+    MFS_TRY(block_cycle(bw, use_kept ? later : first, kept, r, x, ktol, mlim, apply, apply_vec, opts->verbose, &steps,
+                        &est, st));
+    // keep the first cycle's space for the correction cycles when there is room for 8 more blocks
+    if (!use_kept && opts->deflate && prec == MFS_MIXED && n_refine == 0 && steps > 0 && steps + 1 + 8 <= m) {
+      kept = KeptSpace{steps, bw.Hp, bw.refl};
+      later = BlockProcess{steps + 1, bw.Hp + bw.hoff(steps), bw.refl + (int64_t)steps * R * (R + 1)};
+    }
     total += steps;
     ++n_refine;
     ++n_restart;
@@ -1182,8 +1283,8 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
   hipStream_t st = as_stream(stream);
   s->last_stream = st;
   if (opts->block != 0 && R > 1) {
-    if (opts->fp64_until > 0.0 || opts->use_graph || opts->deflate)
-      return fail(MFS_ERR_ARG, "solve: block GMRES does not take fp64_until, use_graph or deflate");
+    if (opts->fp64_until > 0.0 || opts->use_graph)
+      return fail(MFS_ERR_ARG, "solve: block GMRES does not take fp64_until or use_graph");
     return solve_block(s, static_cast<const c128*>(vhat_dev), R, opts, static_cast<c128*>(qhat_dev), info, st, t0);
   }
   const int64_t N = s->dev.N;

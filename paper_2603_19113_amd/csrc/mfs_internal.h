@@ -228,6 +228,8 @@ hipError_t launch_chol(const c128* G, int R, bool scale, double shift, bool firs
 hipError_t launch_fill_random(c128* x, int64_t N, uint64_t seed, hipStream_t st);
 hipError_t launch_bhess_apply(const c128* refl, int R, int64_t rho0, int64_t rho1, c128* X, int64_t ldx, int ncols,
                               hipStream_t st);
+hipError_t launch_bhess_apply_rev(const c128* refl, int R, int64_t rho0, int64_t rho1, c128* X, int64_t ldx,
+                                  int ncols, hipStream_t st);
 hipError_t launch_bhess_newqr(c128* refl, int R, int64_t jR, c128* X, int64_t ldx, hipStream_t st);
 hipError_t launch_bres(const c128* g, int64_t ldg, int64_t row0, int R, const double* bnorm, double* res,
                        hipStream_t st);
@@ -236,6 +238,8 @@ hipError_t launch_btrsm_diag(const c128* U, int64_t ldu, const c128* g, int64_t 
 hipError_t launch_fill_zero_columns(c128* X, int64_t N, int R, const double* bnorm, hipStream_t st);
 hipError_t launch_mask_zero_columns(c128* M, int64_t ldm, int rows, int R, const double* bnorm, hipStream_t st);
 hipError_t launch_add_identity(c128* X, int64_t ldx, int64_t row0, int R, hipStream_t st);
+hipError_t launch_copy2d(const c128* in, int64_t ldi, int64_t rows, int cols, c128* out, int64_t ldo, bool accumulate,
+                         hipStream_t st);
 
 // Kernel timing (mfs_api.hip): bracket a launch with events when recording is on.
 struct TimedLaunch {

@@ -3,7 +3,8 @@ against the oracle's dense LU solution of the same system (the solution of (I + 
 unique, so every column must match it to the solve's tolerance) and the oracle's own residual.
 
 Cases: the mixed-precision block solve with a complex64 basis (16 and 64 right-hand sides, the
-many-right-hand-side pair kernel on the matrix cores), the FP64 block solve with restarts, right-hand
+many-right-hand-side pair kernel on the matrix cores), with the correction cycles deflated by the
+first cycle's block space (GCRO), the FP64 block solve with restarts, right-hand
 sides that repeat (an exactly rank-deficient block: CholeskyQR marks the dependent columns and the
 basis is completed with orthogonalised random vectors), a zero right-hand side (zero solution), and
 the block solve against the per-column solve on the same scene (same solutions, far fewer steps)."""
@@ -125,5 +126,34 @@ def test_block_solve_rejects_what_it_does_not_take(gpu_lib):
         mfs.solve(gsc, v, torch.empty_like(v), prec=mfs.MFS_MIXED, block=True)  # more than 64 columns
     v2 = v[:2].contiguous()
     with pytest.raises(mfs.MfsError):
-        mfs.solve(gsc, v2, torch.empty_like(v2), prec=mfs.MFS_MIXED, block=True, deflate=True)
+        mfs.solve(gsc, v2, torch.empty_like(v2), prec=mfs.MFS_MIXED, block=True, use_graph=True)
+    gsc.close()
+
+
+@pytest.mark.parametrize("key,T,R", [("mixed2000_R64", 60, 64), ("starfish2000", 40, 8)])
+def test_block_deflated_correction_cycles(gpu_lib, key, T, R):
+    """deflate with block: the correction cycles run on (I - C C^H) K~ with C from the first cycle's
+    kept block space; same solution as the dense LU, fewer block steps in the corrections than the
+    plain restart, and the same first cycle."""
+    import torch
+
+    mfs = gpu_lib
+    sc = w.make_scene(key, T=T)
+    sc.directions = w.plane_wave_directions_2d(2.0 * np.pi * np.arange(R) / R)
+    print(f"deflated block solve: {sc.name} N={sc.N} R={R}", flush=True)
+    gsc, Ss = _scene(mfs, sc)
+    v = torch.empty((R, gsc.N), dtype=torch.complex128, device="cuda")
+    mfs.plane_wave(gsc, sc.directions, v)
+    runs = {}
+    for deflate in (False, True):
+        q = torch.empty_like(v)
+        info = mfs.solve(gsc, v, q, tol=1e-8, restart=400, maxit=20000, max_refine=10, inner_tol=3e-6,
+                         prec=mfs.MFS_MIXED, basis32=True, block=True, deflate=deflate, verbose=1)
+        print(f"  deflate={deflate}: {info}", flush=True)
+        assert info["relres_max"] <= 1e-8
+        runs[deflate] = (q.cpu().numpy(), info)
+    _check(sc, Ss, runs[True][0], 2e-8, 1e-6)
+    assert runs[True][1]["n_matvec32"] < runs[False][1]["n_matvec32"]
+    for c in range(R):
+        assert rel_err(runs[True][0][c], runs[False][0][c]) < 1e-6
     gsc.close()
