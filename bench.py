@@ -289,7 +289,7 @@ def compare(args, sc, mfs, torch, np) -> int:
     use_block = R > 1 and not args.no_block
     info_m = mfs.solve(scene, v, q_mixed, tol=args.tol, maxit=60000, restart=args.restart, max_refine=20,
                        inner_tol=args.inner_tol, prec=mfs.MFS_MIXED, verbose=min(args.verbose, 1),
-                       basis32=not args.basis64, deflate=not args.no_deflate and not use_block, block=use_block)
+                       basis32=not args.basis64, deflate=not args.no_deflate, block=use_block)
     t_mixed = time.perf_counter() - t0
     log(f"[compare] mixed, {R} RHS together: {t_mixed:.2f} s  {info_m}")
     q64 = torch.empty_like(v)
@@ -456,8 +456,7 @@ def main() -> int:
         else:
             info = mfs.solve(scene, v, q, tol=args.tol, maxit=60000, restart=args.restart, max_refine=20,
                              inner_tol=args.inner_tol, prec=mfs.MFS_MIXED, verbose=args.verbose,
-                             basis32=not args.basis64, deflate=not args.no_deflate and not use_block,
-                             block=use_block)
+                             basis32=not args.basis64, deflate=not args.no_deflate, block=use_block)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         u = torch.empty((R, targets.shape[0]), dtype=torch.complex128, device="cuda")

@@ -216,6 +216,165 @@ __global__ __launch_bounds__(256) void bgemm_nk_kernel(const TA* __restrict__ A,
   }
 }
 
+// ------------------------------------------------- FP32 matrix-core forms ---
+// The same two products on the FP32 matrix cores (twice the FP64 rate), for the Gram-Schmidt passes
+// of the mixed solve, whose basis is complex64 already: operands are rounded to FP32 when staged,
+// each 32-long slab of the reduction is accumulated in FP32 (relative error ~ sqrt(32) 2^-24 of the
+// slab's sum) and then added into FP64 accumulators, so the error does not grow with N or K.  The
+// 16x16x4 FP32 product leaves D row 4 (l / 16) + v, column l % 16 in register v of lane l.
+typedef float f4 __attribute__((ext_vector_type(4)));
+constexpr int kPadF = 68;  // LDS row length in floats (64 + 4)
+
+__device__ __forceinline__ f4 mfma32(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename TA>
+__global__ __launch_bounds__(256) void bdots32_kernel(const TA* __restrict__ A, int64_t lda, int K,
+                                                      const c128* __restrict__ B, int64_t ldb, int R, int64_t N,
+                                                      int64_t slice_len, c128* __restrict__ part) {
+  __shared__ float Are[kSlab][kPadF], Aim[kSlab][kPadF], Bre[kSlab][kPadF], Bim[kSlab][kPadF];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int k0 = blockIdx.x * kTile;
+  const int s = blockIdx.y;
+  const int64_t n0 = (int64_t)s * slice_len;
+  const int64_t n1 = min(N, n0 + slice_len);
+  d4 sumR[4], sumI[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) sumR[t] = sumI[t] = d4{0.0, 0.0, 0.0, 0.0};
+  const int col = tid >> 2, nq = (tid & 3) * 8;
+  for (int64_t nb = n0; nb < n1; nb += kSlab) {
+    {
+      const int ka = k0 + col;
+      const bool oka = ka < K, okb = col < R;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int64_t n = nb + nq + i;
+        const bool okn = n < n1;
+        c128 a = {0.0, 0.0}, b = {0.0, 0.0};
+        if (oka && okn) a = load_c(A + (int64_t)ka * lda + n);
+        if (okb && okn) b = B[(int64_t)col * ldb + n];
+        Are[nq + i][col] = (float)a.re;
+        Aim[nq + i][col] = (float)a.im;
+        Bre[nq + i][col] = (float)b.re;
+        Bim[nq + i][col] = (float)b.im;
+      }
+    }
+    __syncthreads();
+    f4 accR[4], accI[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) accR[t] = accI[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kk = 0; kk < kSlab; kk += 4) {
+      const int r = kk + (lane >> 4);
+      const float ar = Are[r][16 * w + (lane & 15)], ai = Aim[r][16 * w + (lane & 15)];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float br = Bre[r][16 * t + (lane & 15)], bi = Bim[r][16 * t + (lane & 15)];
+        accR[t] = mfma32(ar, br, accR[t]);
+        accR[t] = mfma32(ai, bi, accR[t]);
+        accI[t] = mfma32(ar, bi, accI[t]);
+        accI[t] = mfma32(-ai, br, accI[t]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        sumR[t][v] += (double)accR[t][v];
+        sumI[t][v] += (double)accI[t][v];
+      }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int c = 16 * t + (lane & 15);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int k = k0 + 16 * w + 4 * (lane >> 4) + v;
+      if (k < K && c < R) part[((int64_t)s * R + c) * K + k] = c128{sumR[t][v], sumI[t][v]};
+    }
+  }
+}
+
+template <typename TA>
+__global__ __launch_bounds__(256) void bgemm32_nk_kernel(const TA* __restrict__ A, int64_t lda, int64_t M, int K,
+                                                         const c128* __restrict__ C, int64_t ldc, int R, double alpha,
+                                                         double beta, const c128* in, int64_t ldi, c128* out,
+                                                         int64_t ldo) {
+  __shared__ float Are[kSlab][kPadF], Aim[kSlab][kPadF], Cre[kSlab][kPadF], Cim[kSlab][kPadF];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t n0 = (int64_t)blockIdx.x * kTile;
+  d4 sumR[4], sumI[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) sumR[t] = sumI[t] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int kb = 0; kb < K; kb += kSlab) {
+    {
+      const int kc = tid >> 3, nq = (tid & 7) * 8;
+      const int k = kb + kc;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int64_t n = n0 + nq + i;
+        c128 a = {0.0, 0.0};
+        if (k < K && n < M) a = load_c(A + (int64_t)k * lda + n);
+        Are[kc][nq + i] = (float)a.re;
+        Aim[kc][nq + i] = (float)a.im;
+      }
+      const int cc = tid >> 2, kq = (tid & 3) * 8;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int kk = kb + kq + i;
+        c128 v = {0.0, 0.0};
+        if (kk < K && cc < R) v = C[kk + (int64_t)cc * ldc];
+        Cre[kq + i][cc] = (float)v.re;
+        Cim[kq + i][cc] = (float)v.im;
+      }
+    }
+    __syncthreads();
+    f4 accR[4], accI[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) accR[t] = accI[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kk = 0; kk < kSlab; kk += 4) {
+      const int r = kk + (lane >> 4);
+      const float ar = Are[r][16 * w + (lane & 15)], ai = Aim[r][16 * w + (lane & 15)];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float cr = Cre[r][16 * t + (lane & 15)], ci = Cim[r][16 * t + (lane & 15)];
+        accR[t] = mfma32(ar, cr, accR[t]);
+        accR[t] = mfma32(-ai, ci, accR[t]);
+        accI[t] = mfma32(ar, ci, accI[t]);
+        accI[t] = mfma32(ai, cr, accI[t]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        sumR[t][v] += (double)accR[t][v];
+        sumI[t][v] += (double)accI[t][v];
+      }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int c = 16 * t + (lane & 15);
+    if (c >= R) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t n = n0 + 16 * w + 4 * (lane >> 4) + v;
+      if (n >= M) continue;
+      c128 o = {alpha * sumR[t][v], alpha * sumI[t][v]};
+      if (beta != 0.0) {
+        const c128 x = in[(int64_t)c * ldi + n];
+        o.re += beta * x.re;
+        o.im += beta * x.im;
+      }
+      out[(int64_t)c * ldo + n] = o;
+    }
+  }
+}
+
 // ----------------------------------------------------------------- chol ---
 // One step of shifted CholeskyQR on an R x R Gram matrix G = W^H W (column-major, Hermitian).
 // scale != 0: the columns are first scaled to unit norm (d_c = sqrt(G_cc), 1 where G_cc = 0) and
@@ -677,10 +836,19 @@ int bdots_splits(int64_t N, int K) {
 }
 
 hipError_t launch_bdots(const void* A, bool a32, int64_t lda, int K, const c128* B, int64_t ldb, int R, int64_t N,
-                        c128* part, int nsplit, hipStream_t st) {
+                        c128* part, int nsplit, hipStream_t st, bool fp32) {
   if (K <= 0 || N <= 0) return hipSuccess;
   const int64_t slice = ((N + nsplit - 1) / nsplit + kSlab - 1) / kSlab * kSlab;
   const dim3 grid((unsigned)((K + kTile - 1) / kTile), (unsigned)nsplit);
+  if (fp32) {
+    if (a32)
+      hipLaunchKernelGGL(bdots32_kernel<c64>, grid, dim3(256), 0, st, static_cast<const c64*>(A), lda, K, B, ldb, R, N,
+                         slice, part);
+    else
+      hipLaunchKernelGGL(bdots32_kernel<c128>, grid, dim3(256), 0, st, static_cast<const c128*>(A), lda, K, B, ldb, R,
+                         N, slice, part);
+    return hipGetLastError();
+  }
   if (a32)
     hipLaunchKernelGGL(bdots_kernel<c64>, grid, dim3(256), 0, st, static_cast<const c64*>(A), lda, K, B, ldb, R, N,
                        slice, part);
@@ -701,9 +869,18 @@ hipError_t launch_breduce(const c128* part, int nsplit, int K, int R, c128* out,
 
 hipError_t launch_bgemm_nk(const void* A, bool a32, int64_t lda, int64_t M, int K, const c128* C, int64_t ldc, int R,
                            double alpha, double beta, const c128* in, int64_t ldi, c128* out, int64_t ldo,
-                           hipStream_t st) {
+                           hipStream_t st, bool fp32) {
   if (M <= 0) return hipSuccess;
   const dim3 grid((unsigned)((M + kTile - 1) / kTile));
+  if (fp32) {
+    if (a32)
+      hipLaunchKernelGGL(bgemm32_nk_kernel<c64>, grid, dim3(256), 0, st, static_cast<const c64*>(A), lda, M, K, C, ldc,
+                         R, alpha, beta, in, ldi, out, ldo);
+    else
+      hipLaunchKernelGGL(bgemm32_nk_kernel<c128>, grid, dim3(256), 0, st, static_cast<const c128*>(A), lda, M, K, C,
+                         ldc, R, alpha, beta, in, ldi, out, ldo);
+    return hipGetLastError();
+  }
   if (a32)
     hipLaunchKernelGGL(bgemm_nk_kernel<c64>, grid, dim3(256), 0, st, static_cast<const c64*>(A), lda, M, K, C, ldc, R,
                        alpha, beta, in, ldi, out, ldo);

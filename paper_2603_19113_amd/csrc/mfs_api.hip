@@ -460,13 +460,16 @@ struct BlockWork {
   void* V = nullptr;
   c128 *Hp = nullptr, *refl = nullptr, *g = nullptr, *Y = nullptr, *h2 = nullptr, *part = nullptr;
   c128 *gram = nullptr, *F = nullptr, *Finv = nullptr, *rtot = nullptr;
-  double *bnorm = nullptr, *res = nullptr, *npart = nullptr;
+  double *bnorm = nullptr, *res = nullptr, *npart = nullptr, *wn = nullptr;
   int32_t *flag = nullptr, *dep = nullptr;
   int nblk = 0;
   c128 *W = nullptr, *Wt = nullptr;  // N x R blocks
   c128 *q1 = nullptr, *coef = nullptr;  // completion of dependent columns: one vector, its coefficients
-  // pinned host slots: R doubles, a flag and R ints
+  // pinned host slots: R doubles, 2R doubles, a flag and R ints
   double* res_pin = nullptr;
+  double* wn_pin = nullptr;
+  double reorth_eta = 0.5;  // second Gram-Schmidt pass when some column keeps less than this of its norm
+  int* n_second = nullptr;  // counts the steps that took it
   int32_t *flag_pin = nullptr, *dep_pin = nullptr;
   hipEvent_t ev = nullptr;
   size_t vbytes() const { return v32 ? sizeof(c64) : sizeof(c128); }
@@ -502,6 +505,7 @@ size_t block_work_bytes(int64_t N, int R, int m, bool v32, int64_t* offs) {
   carve(sizeof(int32_t) * R);                                          // dep
   carve(sizeof(c128) * (size_t)N);                                     // q1
   carve(sizeof(c128) * (size_t)(m + 1) * R);                           // coef
+  carve(sizeof(double) * 2 * R);                                       // wn: |W| before and after a pass
   return off;
 }
 
@@ -533,6 +537,7 @@ BlockWork block_work_at(char* base, int64_t N, int R, int m, bool v32) {
   b.dep = reinterpret_cast<int32_t*>(base + o[17]);
   b.q1 = reinterpret_cast<c128*>(base + o[18]);
   b.coef = reinterpret_cast<c128*>(base + o[19]);
+  b.wn = reinterpret_cast<double*>(base + o[20]);
   b.nblk = krylov_nblk(N);
   return b;
 }
@@ -665,6 +670,9 @@ mfs_status block_cycle(const BlockWork& bw, const BlockProcess& pr, const KeptSp
   const int o = pr.o;
   const bool defl = kp.k > 0;
   const int ko = defl ? kp.k + 1 : 0;  // kept basis blocks
+  // Gram-Schmidt on the FP32 matrix cores when the basis is complex64 (the mixed solve): its
+  // rounding (~3e-7 of the norms) is below the FP32 operator's own error
+  const bool gs32 = bw.v32;
   MFS_HIP_TRY(launch_norms(r, N, R, bw.npart, bw.nblk, bw.bnorm, st));
   // starting block: r (projected off C with a kept space), a pseudo-random vector for a zero column
   MFS_HIP_TRY(hipMemcpyAsync(bw.W, r, sizeof(c128) * N * R, hipMemcpyDeviceToDevice, st));
@@ -697,19 +705,31 @@ mfs_status block_cycle(const BlockWork& bw, const BlockProcess& pr, const KeptSp
     // block classical Gram-Schmidt, two passes.  Without a kept space: H(0..j, j) = V^H W, W -= V H.
     // With one, the coefficients on the kept vectors are replaced by their part along C (the rest
     // of the kept space stays in W) and only this process's coefficients enter its Hessenberg matrix.
+    MFS_HIP_TRY(launch_norms(bw.W, N, R, bw.npart, bw.nblk, bw.wn, st));
     for (int pass = 0; pass < 2; ++pass) {
-      MFS_HIP_TRY(launch_bdots(bw.V, bw.v32, N, K, bw.W, N, R, N, bw.part, ns, st));
+      if (pass == 1) {
+        // second pass only where the first cancelled: some column kept less than eta of its norm
+        MFS_HIP_TRY(launch_norms(bw.W, N, R, bw.npart, bw.nblk, bw.wn + R, st));
+        MFS_HIP_TRY(hipMemcpyAsync(bw.wn_pin, bw.wn, sizeof(double) * 2 * R, hipMemcpyDeviceToHost, st));
+        MFS_HIP_TRY(hipEventRecord(bw.ev, st));
+        MFS_HIP_TRY(hipEventSynchronize(bw.ev));
+        bool again = false;
+        for (int c = 0; c < R; ++c) again = again || !(bw.wn_pin[R + c] >= bw.reorth_eta * bw.wn_pin[c]);
+        if (!again) break;
+        if (bw.n_second) ++*bw.n_second;
+      }
+      MFS_HIP_TRY(launch_bdots(bw.V, bw.v32, N, K, bw.W, N, R, N, bw.part, ns, st, gs32));
       if (!defl) {
         MFS_HIP_TRY(launch_breduce(bw.part, ns, K, R, hcol, ldh, pass == 1, pass == 1 ? bw.h2 : nullptr, ldg, st));
         MFS_HIP_TRY(launch_bgemm_nk(bw.V, bw.v32, N, N, K, pass == 0 ? hcol : bw.h2, pass == 0 ? ldh : ldg, R, -1.0,
-                                    1.0, bw.W, N, bw.W, N, st));
+                                    1.0, bw.W, N, bw.W, N, st, gs32));
       } else {
         MFS_HIP_TRY(launch_breduce(bw.part, ns, K, R, bw.h2, ldg, false, nullptr, 0, st));
         // this process's rows go to its Hessenberg column (set, then accumulated); its basis follows
         // the kept blocks directly (o = k + 1)
         MFS_HIP_TRY(launch_copy2d(bw.h2 + (int64_t)o * R, ldg, (int64_t)(j + 1) * R, R, hcol, ldh, pass == 1, st));
         MFS_TRY(project_kept(bw, kp, bw.h2, ldg, st));
-        MFS_HIP_TRY(launch_bgemm_nk(bw.V, bw.v32, N, N, K, bw.h2, ldg, R, -1.0, 1.0, bw.W, N, bw.W, N, st));
+        MFS_HIP_TRY(launch_bgemm_nk(bw.V, bw.v32, N, N, K, bw.h2, ldg, R, -1.0, 1.0, bw.W, N, bw.W, N, st, gs32));
       }
     }
     // W = V_{o+j+1} H(j+1, j)
@@ -782,7 +802,8 @@ mfs_status solve_block(mfs_scene* s, const c128* vhat, int R, const mfs_solve_op
   c128* w = r + NR;
   size_t pin_bytes = 0;
   hipError_t pin_err = hipSuccess;
-  char* pin = static_cast<char*>(pinned_alloc(sizeof(double) * R + sizeof(int32_t) * (R + 2) + 64, &pin_bytes, &pin_err));
+  char* pin = static_cast<char*>(
+      pinned_alloc(sizeof(double) * 3 * R + sizeof(int32_t) * (R + 2) + 64, &pin_bytes, &pin_err));
   if (!pin) return fail(MFS_ERR_NOMEM, std::string("pinned host allocation failed: ") + hipGetErrorString(pin_err));
   struct PinGuard {
     void* p;
@@ -799,7 +820,8 @@ mfs_status solve_block(mfs_scene* s, const c128* vhat, int R, const mfs_solve_op
   MFS_HIP_TRY(hipEventCreateWithFlags(&guard.ev, hipEventDisableTiming));
   double* res_pin = reinterpret_cast<double*>(pin);
   bw.res_pin = res_pin;
-  bw.flag_pin = reinterpret_cast<int32_t*>(pin + sizeof(double) * R);
+  bw.wn_pin = res_pin + R;
+  bw.flag_pin = reinterpret_cast<int32_t*>(pin + sizeof(double) * 3 * R);
   bw.dep_pin = bw.flag_pin + 1;
   bw.ev = guard.ev;
 
@@ -847,6 +869,8 @@ mfs_status solve_block(mfs_scene* s, const c128* vhat, int R, const mfs_solve_op
     }
     return MFS_OK;
   };
+  int n_second = 0;
+  bw.n_second = &n_second;
   BlockProcess first{0, bw.Hp, bw.refl};
   KeptSpace kept{};
   BlockProcess later = first;
@@ -889,7 +913,7 @@ mfs_status solve_block(mfs_scene* s, const c128* vhat, int R, const mfs_solve_op
   MFS_HIP_TRY(hipStreamSynchronize(st));
   const auto t1 = std::chrono::steady_clock::now();
   if (info) {
-    info->n_reorth = total;  // every block step takes both Gram-Schmidt passes
+    info->n_reorth = n_second;  // block steps that took the second Gram-Schmidt pass
     info->n_matvec32 = n32;
     info->n_matvec64 = n64;
     info->n_refine = prec == MFS_MIXED ? n_refine : 0;

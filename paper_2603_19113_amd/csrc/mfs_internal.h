@@ -216,13 +216,15 @@ hipError_t launch_axpby(const c128* a, const c128* b, c128* out, double alpha, d
 //   bhess_*:   Householder QR of the block Hessenberg matrix (reflector rho on rows rho..rho+R)
 constexpr int64_t kBdotsPartMax = 131072;  // bound on nsplit * K of one bdots launch
 int bdots_splits(int64_t N, int K);
+// fp32: the FP32 matrix-core form (operands rounded to FP32, each 32-long slab of the reduction
+// summed in FP32 and added into FP64), for the Gram-Schmidt passes of the mixed solve
 hipError_t launch_bdots(const void* A, bool a32, int64_t lda, int K, const c128* B, int64_t ldb, int R, int64_t N,
-                        c128* part, int nsplit, hipStream_t st);
+                        c128* part, int nsplit, hipStream_t st, bool fp32 = false);
 hipError_t launch_breduce(const c128* part, int nsplit, int K, int R, c128* out, int64_t ldo, bool accumulate,
                           c128* copy, int64_t ldc, hipStream_t st);
 hipError_t launch_bgemm_nk(const void* A, bool a32, int64_t lda, int64_t M, int K, const c128* C, int64_t ldc, int R,
                            double alpha, double beta, const c128* in, int64_t ldi, c128* out, int64_t ldo,
-                           hipStream_t st);
+                           hipStream_t st, bool fp32 = false);
 hipError_t launch_chol(const c128* G, int R, bool scale, double shift, bool first, double dep_tol, c128* F, c128* Finv,
                        c128* Rtot, int32_t* dep, int32_t* flag, hipStream_t st);
 hipError_t launch_fill_random(c128* x, int64_t N, uint64_t seed, hipStream_t st);
