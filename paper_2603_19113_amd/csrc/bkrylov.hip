@@ -229,9 +229,27 @@ __device__ __forceinline__ f4 mfma32(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Staging of one slab: thread tid holds 8 consecutive entries of one column in registers (loaded
+// for the next slab while the matrix cores work on the current one) and writes them to LDS.
+struct SlabRegs {
+  double re[8], im[8];
+};
+
 template <typename TA>
+__device__ __forceinline__ void slab_load(SlabRegs& g, const TA* __restrict__ X, int64_t ldx, int col, bool okc,
+                                          int64_t n, int64_t nend) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    c128 v = {0.0, 0.0};
+    if (okc && n + i < nend) v = load_c(X + (int64_t)col * ldx + n + i);
+    g.re[i] = v.re;
+    g.im[i] = v.im;
+  }
+}
+
+template <typename TA, typename TB>
 __global__ __launch_bounds__(256) void bdots32_kernel(const TA* __restrict__ A, int64_t lda, int K,
-                                                      const c128* __restrict__ B, int64_t ldb, int R, int64_t N,
+                                                      const TB* __restrict__ B, int64_t ldb, int R, int64_t N,
                                                       int64_t slice_len, c128* __restrict__ part) {
   __shared__ float Are[kSlab][kPadF], Aim[kSlab][kPadF], Bre[kSlab][kPadF], Bim[kSlab][kPadF];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -243,24 +261,25 @@ __global__ __launch_bounds__(256) void bdots32_kernel(const TA* __restrict__ A, 
 #pragma unroll
   for (int t = 0; t < 4; ++t) sumR[t] = sumI[t] = d4{0.0, 0.0, 0.0, 0.0};
   const int col = tid >> 2, nq = (tid & 3) * 8;
+  const bool oka = k0 + col < K, okb = col < R;
+  SlabRegs ga, gb;
+  if (n0 < n1) {
+    slab_load(ga, A, lda, k0 + col, oka, n0 + nq, n1);
+    slab_load(gb, B, ldb, col, okb, n0 + nq, n1);
+  }
   for (int64_t nb = n0; nb < n1; nb += kSlab) {
-    {
-      const int ka = k0 + col;
-      const bool oka = ka < K, okb = col < R;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int64_t n = nb + nq + i;
-        const bool okn = n < n1;
-        c128 a = {0.0, 0.0}, b = {0.0, 0.0};
-        if (oka && okn) a = load_c(A + (int64_t)ka * lda + n);
-        if (okb && okn) b = B[(int64_t)col * ldb + n];
-        Are[nq + i][col] = (float)a.re;
-        Aim[nq + i][col] = (float)a.im;
-        Bre[nq + i][col] = (float)b.re;
-        Bim[nq + i][col] = (float)b.im;
-      }
+    for (int i = 0; i < 8; ++i) {
+      Are[nq + i][col] = (float)ga.re[i];
+      Aim[nq + i][col] = (float)ga.im[i];
+      Bre[nq + i][col] = (float)gb.re[i];
+      Bim[nq + i][col] = (float)gb.im[i];
     }
     __syncthreads();
+    if (nb + kSlab < n1) {  // next slab in flight during the products
+      slab_load(ga, A, lda, k0 + col, oka, nb + kSlab + nq, n1);
+      slab_load(gb, B, ldb, col, okb, nb + kSlab + nq, n1);
+    }
     f4 accR[4], accI[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) accR[t] = accI[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -297,9 +316,9 @@ __global__ __launch_bounds__(256) void bdots32_kernel(const TA* __restrict__ A, 
   }
 }
 
-template <typename TA>
+template <typename TA, typename TC>
 __global__ __launch_bounds__(256) void bgemm32_nk_kernel(const TA* __restrict__ A, int64_t lda, int64_t M, int K,
-                                                         const c128* __restrict__ C, int64_t ldc, int R, double alpha,
+                                                         const TC* __restrict__ C, int64_t ldc, int R, double alpha,
                                                          double beta, const c128* in, int64_t ldi, c128* out,
                                                          int64_t ldo) {
   __shared__ float Are[kSlab][kPadF], Aim[kSlab][kPadF], Cre[kSlab][kPadF], Cim[kSlab][kPadF];
@@ -308,29 +327,38 @@ __global__ __launch_bounds__(256) void bgemm32_nk_kernel(const TA* __restrict__ 
   d4 sumR[4], sumI[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) sumR[t] = sumI[t] = d4{0.0, 0.0, 0.0, 0.0};
+  // A slab: 32 columns k x 64 rows n, thread tid: column tid / 8, n from (tid % 8) * 8;
+  // C slab: 32 rows k x 64 columns c, thread tid: column tid / 4, k from (tid % 4) * 8
+  const int kc = tid >> 3, nq = (tid & 7) * 8;
+  const int cc = tid >> 2, kq = (tid & 3) * 8;
+  SlabRegs ga, gc;
+  auto load = [&](int kb) {
+    const int k = kb + kc;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int64_t n = n0 + nq + i;
+      c128 a = {0.0, 0.0};
+      if (k < K && n < M) a = load_c(A + (int64_t)k * lda + n);
+      ga.re[i] = a.re;
+      ga.im[i] = a.im;
+      const int kk = kb + kq + i;
+      c128 v = {0.0, 0.0};
+      if (kk < K && cc < R) v = load_c(C + kk + (int64_t)cc * ldc);
+      gc.re[i] = v.re;
+      gc.im[i] = v.im;
+    }
+  };
+  if (K > 0) load(0);
   for (int kb = 0; kb < K; kb += kSlab) {
-    {
-      const int kc = tid >> 3, nq = (tid & 7) * 8;
-      const int k = kb + kc;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int64_t n = n0 + nq + i;
-        c128 a = {0.0, 0.0};
-        if (k < K && n < M) a = load_c(A + (int64_t)k * lda + n);
-        Are[kc][nq + i] = (float)a.re;
-        Aim[kc][nq + i] = (float)a.im;
-      }
-      const int cc = tid >> 2, kq = (tid & 3) * 8;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int kk = kb + kq + i;
-        c128 v = {0.0, 0.0};
-        if (kk < K && cc < R) v = C[kk + (int64_t)cc * ldc];
-        Cre[kq + i][cc] = (float)v.re;
-        Cim[kq + i][cc] = (float)v.im;
-      }
+    for (int i = 0; i < 8; ++i) {
+      Are[kc][nq + i] = (float)ga.re[i];
+      Aim[kc][nq + i] = (float)ga.im[i];
+      Cre[kq + i][cc] = (float)gc.re[i];
+      Cim[kq + i][cc] = (float)gc.im[i];
     }
     __syncthreads();
+    if (kb + kSlab < K) load(kb + kSlab);  // next slab in flight during the products
     f4 accR[4], accI[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) accR[t] = accI[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -842,11 +870,11 @@ hipError_t launch_bdots(const void* A, bool a32, int64_t lda, int K, const c128*
   const dim3 grid((unsigned)((K + kTile - 1) / kTile), (unsigned)nsplit);
   if (fp32) {
     if (a32)
-      hipLaunchKernelGGL(bdots32_kernel<c64>, grid, dim3(256), 0, st, static_cast<const c64*>(A), lda, K, B, ldb, R, N,
-                         slice, part);
+      hipLaunchKernelGGL((bdots32_kernel<c64, c128>), grid, dim3(256), 0, st, static_cast<const c64*>(A), lda, K, B, ldb,
+                         R, N, slice, part);
     else
-      hipLaunchKernelGGL(bdots32_kernel<c128>, grid, dim3(256), 0, st, static_cast<const c128*>(A), lda, K, B, ldb, R,
-                         N, slice, part);
+      hipLaunchKernelGGL((bdots32_kernel<c128, c128>), grid, dim3(256), 0, st, static_cast<const c128*>(A), lda, K, B,
+                         ldb, R, N, slice, part);
     return hipGetLastError();
   }
   if (a32)
@@ -855,6 +883,42 @@ hipError_t launch_bdots(const void* A, bool a32, int64_t lda, int K, const c128*
   else
     hipLaunchKernelGGL(bdots_kernel<c128>, grid, dim3(256), 0, st, static_cast<const c128*>(A), lda, K, B, ldb, R,
                        N, slice, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_bdots32_b64(const c64* A, int64_t lda, int K, const c64* B, int64_t ldb, int R, int64_t N, c128* part,
+                              int nsplit, hipStream_t st) {
+  if (K <= 0 || N <= 0) return hipSuccess;
+  const int64_t slice = ((N + nsplit - 1) / nsplit + kSlab - 1) / kSlab * kSlab;
+  const dim3 grid((unsigned)((K + kTile - 1) / kTile), (unsigned)nsplit);
+  hipLaunchKernelGGL((bdots32_kernel<c64, c64>), grid, dim3(256), 0, st, A, lda, K, B, ldb, R, N, slice, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_bgemm32_c64(const c64* A, int64_t lda, int64_t M, int K, const c64* C, int64_t ldc, int R,
+                              double alpha, double beta, const c128* in, int64_t ldi, c128* out, int64_t ldo,
+                              hipStream_t st) {
+  if (M <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((M + kTile - 1) / kTile));
+  hipLaunchKernelGGL((bgemm32_nk_kernel<c64, c64>), grid, dim3(256), 0, st, A, lda, M, K, C, ldc, R, alpha, beta, in, ldi,
+                     out, ldo);
+  return hipGetLastError();
+}
+
+// out[k + c ldo] = (complex64) in[k + c ldi] for k < rows, c < cols
+__global__ void to_c64_2d_kernel(const c128* __restrict__ in, int64_t ldi, int64_t rows, int cols, c64* __restrict__ out,
+                                 int64_t ldo) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= rows || c >= cols) return;
+  const c128 v = in[i + (int64_t)c * ldi];
+  out[i + (int64_t)c * ldo] = c64{(float)v.re, (float)v.im};
+}
+
+hipError_t launch_to_c64_2d(const c128* in, int64_t ldi, int64_t rows, int cols, c64* out, int64_t ldo, hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(to_c64_2d_kernel, dim3((unsigned)((rows + 255) / 256), (unsigned)cols), dim3(256), 0, st, in, ldi,
+                     rows, cols, out, ldo);
   return hipGetLastError();
 }
 
@@ -874,11 +938,11 @@ hipError_t launch_bgemm_nk(const void* A, bool a32, int64_t lda, int64_t M, int 
   const dim3 grid((unsigned)((M + kTile - 1) / kTile));
   if (fp32) {
     if (a32)
-      hipLaunchKernelGGL(bgemm32_nk_kernel<c64>, grid, dim3(256), 0, st, static_cast<const c64*>(A), lda, M, K, C, ldc,
-                         R, alpha, beta, in, ldi, out, ldo);
+      hipLaunchKernelGGL((bgemm32_nk_kernel<c64, c128>), grid, dim3(256), 0, st, static_cast<const c64*>(A), lda, M, K,
+                         C, ldc, R, alpha, beta, in, ldi, out, ldo);
     else
-      hipLaunchKernelGGL(bgemm32_nk_kernel<c128>, grid, dim3(256), 0, st, static_cast<const c128*>(A), lda, M, K, C,
-                         ldc, R, alpha, beta, in, ldi, out, ldo);
+      hipLaunchKernelGGL((bgemm32_nk_kernel<c128, c128>), grid, dim3(256), 0, st, static_cast<const c128*>(A), lda, M,
+                         K, C, ldc, R, alpha, beta, in, ldi, out, ldo);
     return hipGetLastError();
   }
   if (a32)

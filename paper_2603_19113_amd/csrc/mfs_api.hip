@@ -465,10 +465,11 @@ struct BlockWork {
   int nblk = 0;
   c128 *W = nullptr, *Wt = nullptr;  // N x R blocks
   c128 *q1 = nullptr, *coef = nullptr;  // completion of dependent columns: one vector, its coefficients
+  c64 *W32 = nullptr, *coef32 = nullptr;  // complex64 copies of W and of the Gram-Schmidt coefficients
   // pinned host slots: R doubles, 2R doubles, a flag and R ints
   double* res_pin = nullptr;
   double* wn_pin = nullptr;
-  double reorth_eta = 0.5;  // second Gram-Schmidt pass when some column keeps less than this of its norm
+  double reorth_eta = 0.1;  // second Gram-Schmidt pass when some column keeps less than this of its norm
   int* n_second = nullptr;  // counts the steps that took it
   int32_t *flag_pin = nullptr, *dep_pin = nullptr;
   hipEvent_t ev = nullptr;
@@ -506,6 +507,8 @@ size_t block_work_bytes(int64_t N, int R, int m, bool v32, int64_t* offs) {
   carve(sizeof(c128) * (size_t)N);                                     // q1
   carve(sizeof(c128) * (size_t)(m + 1) * R);                           // coef
   carve(sizeof(double) * 2 * R);                                       // wn: |W| before and after a pass
+  carve(sizeof(c64) * (size_t)R * N);                                  // W32
+  carve(sizeof(c64) * (size_t)(m + 1) * R * R);                        // coef32
   return off;
 }
 
@@ -538,6 +541,8 @@ BlockWork block_work_at(char* base, int64_t N, int R, int m, bool v32) {
   b.q1 = reinterpret_cast<c128*>(base + o[18]);
   b.coef = reinterpret_cast<c128*>(base + o[19]);
   b.wn = reinterpret_cast<double*>(base + o[20]);
+  b.W32 = reinterpret_cast<c64*>(base + o[21]);
+  b.coef32 = reinterpret_cast<c64*>(base + o[22]);
   b.nblk = krylov_nblk(N);
   return b;
 }
@@ -706,6 +711,27 @@ mfs_status block_cycle(const BlockWork& bw, const BlockProcess& pr, const KeptSp
     // With one, the coefficients on the kept vectors are replaced by their part along C (the rest
     // of the kept space stays in W) and only this process's coefficients enter its Hessenberg matrix.
     MFS_HIP_TRY(launch_norms(bw.W, N, R, bw.npart, bw.nblk, bw.wn, st));
+    // inner products V^H W (FP32 matrix cores on complex64 copies of W when gs32)
+    auto dots = [&]() -> mfs_status {
+      if (gs32) {
+        MFS_HIP_TRY(launch_to_c64(bw.W, bw.W32, N * R, st));
+        MFS_HIP_TRY(launch_bdots32_b64(static_cast<const c64*>(bw.V), N, K, bw.W32, N, R, N, bw.part, ns, st));
+      } else {
+        MFS_HIP_TRY(launch_bdots(bw.V, bw.v32, N, K, bw.W, N, R, N, bw.part, ns, st));
+      }
+      return MFS_OK;
+    };
+    // W -= V C for the K x R coefficients C (leading dimension ldc)
+    auto update = [&](const c128* C, int64_t ldc) -> mfs_status {
+      if (gs32) {
+        MFS_HIP_TRY(launch_to_c64_2d(C, ldc, K, R, bw.coef32, K, st));
+        MFS_HIP_TRY(launch_bgemm32_c64(static_cast<const c64*>(bw.V), N, N, K, bw.coef32, K, R, -1.0, 1.0, bw.W, N,
+                                       bw.W, N, st));
+      } else {
+        MFS_HIP_TRY(launch_bgemm_nk(bw.V, bw.v32, N, N, K, C, ldc, R, -1.0, 1.0, bw.W, N, bw.W, N, st));
+      }
+      return MFS_OK;
+    };
     for (int pass = 0; pass < 2; ++pass) {
       if (pass == 1) {
         // second pass only where the first cancelled: some column kept less than eta of its norm
@@ -718,18 +744,18 @@ mfs_status block_cycle(const BlockWork& bw, const BlockProcess& pr, const KeptSp
         if (!again) break;
         if (bw.n_second) ++*bw.n_second;
       }
-      MFS_HIP_TRY(launch_bdots(bw.V, bw.v32, N, K, bw.W, N, R, N, bw.part, ns, st, gs32));
+      MFS_TRY(dots());
       if (!defl) {
         MFS_HIP_TRY(launch_breduce(bw.part, ns, K, R, hcol, ldh, pass == 1, pass == 1 ? bw.h2 : nullptr, ldg, st));
-        MFS_HIP_TRY(launch_bgemm_nk(bw.V, bw.v32, N, N, K, pass == 0 ? hcol : bw.h2, pass == 0 ? ldh : ldg, R, -1.0,
-                                    1.0, bw.W, N, bw.W, N, st, gs32));
+        if (pass == 0) MFS_TRY(update(hcol, ldh));
+        else MFS_TRY(update(bw.h2, ldg));
       } else {
         MFS_HIP_TRY(launch_breduce(bw.part, ns, K, R, bw.h2, ldg, false, nullptr, 0, st));
         // this process's rows go to its Hessenberg column (set, then accumulated); its basis follows
         // the kept blocks directly (o = k + 1)
         MFS_HIP_TRY(launch_copy2d(bw.h2 + (int64_t)o * R, ldg, (int64_t)(j + 1) * R, R, hcol, ldh, pass == 1, st));
         MFS_TRY(project_kept(bw, kp, bw.h2, ldg, st));
-        MFS_HIP_TRY(launch_bgemm_nk(bw.V, bw.v32, N, N, K, bw.h2, ldg, R, -1.0, 1.0, bw.W, N, bw.W, N, st, gs32));
+        MFS_TRY(update(bw.h2, ldg));
       }
     }
     // W = V_{o+j+1} H(j+1, j)

@@ -220,6 +220,13 @@ int bdots_splits(int64_t N, int K);
 // summed in FP32 and added into FP64), for the Gram-Schmidt passes of the mixed solve
 hipError_t launch_bdots(const void* A, bool a32, int64_t lda, int K, const c128* B, int64_t ldb, int R, int64_t N,
                         c128* part, int nsplit, hipStream_t st, bool fp32 = false);
+// FP32 forms with complex64 right operands (converted once per pass: half the bytes re-read per tile)
+hipError_t launch_bdots32_b64(const c64* A, int64_t lda, int K, const c64* B, int64_t ldb, int R, int64_t N, c128* part,
+                              int nsplit, hipStream_t st);
+hipError_t launch_bgemm32_c64(const c64* A, int64_t lda, int64_t M, int K, const c64* C, int64_t ldc, int R,
+                              double alpha, double beta, const c128* in, int64_t ldi, c128* out, int64_t ldo,
+                              hipStream_t st);
+hipError_t launch_to_c64_2d(const c128* in, int64_t ldi, int64_t rows, int cols, c64* out, int64_t ldo, hipStream_t st);
 hipError_t launch_breduce(const c128* part, int nsplit, int K, int R, c128* out, int64_t ldo, bool accumulate,
                           c128* copy, int64_t ldc, hipStream_t st);
 hipError_t launch_bgemm_nk(const void* A, bool a32, int64_t lda, int64_t M, int K, const c128* C, int64_t ldc, int R,
