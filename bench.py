@@ -75,6 +75,10 @@ PEAK_FP32_UNPACKED_TFLOPS = 78.6
 # Many right-hand sides: G_hat tile x charge block on the FP32 matrix cores (dense FP32 MFMA peak).
 FLOP_PER_PAIR_RHS_MFMA = 8
 PEAK_FP32_MFMA_TFLOPS = 157.3
+# The same contraction as FP16 products of split operands: 3 x 8 = 24 FP16 flop per (pair, right-hand
+# side), against the dense FP16 matrix-core peak.
+FLOP_PER_PAIR_RHS_SPLIT16 = 24
+PEAK_FP16_MFMA_TFLOPS = 2500.0
 
 
 # Host threads one GPU's share of the benchmark host may use.
@@ -341,6 +345,9 @@ def main() -> int:
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="profiling: first copy a buffer of this many MiB (calibrates rocprof byte counters)")
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--mc-fp32", action="store_true",
+                    help="many right-hand sides: FP32 matrix-core products instead of FP16 products of "
+                         "split operands")
     ap.add_argument("--no-block", action="store_true",
                     help="several right-hand sides: one Krylov space per column instead of block GMRES")
     ap.add_argument("--no-deflate", action="store_true",
@@ -429,6 +436,8 @@ def main() -> int:
                           [b.S64 for b in built], [b.S32 for b in built])
         if forced:
             mfs.tune_set(scene, R, mfs.MFS_MIXED, *forced)
+        if args.mc_fp32 and mfs.pair_kernel(scene, R, mfs.MFS_MIXED) == mfs.MFS_PAIR_MC_F16X3:
+            mfs.set_split_fp16(scene, False)
         return scene
 
     def step():
@@ -481,6 +490,7 @@ def main() -> int:
         tune = mfs.autotune(probe, R=R, prec=mfs.MFS_MIXED, reps=2)
         log(f"[bench] autotune ({time.perf_counter() - t0:.1f} s): {tune}")
     shape = mfs.tune_get(probe, R, mfs.MFS_MIXED)
+    pair_kind = mfs.pair_kernel(probe, R, mfs.MFS_MIXED)
     probe.close()
 
     for i in range(args.warmup):
@@ -510,14 +520,17 @@ def main() -> int:
     ms64, n64, p64 = mfs.timing_read(mfs.MFS_KERNEL_PAIR_F64)
     mfs.timing_enable(False)
 
-    on_sym = shape["symmetric"] == 1
-    on_mfma = not on_sym and sc.R >= 8 and all(sh.k % 16 == 0 for sh in sc.shapes)
-    sub_blocks = sc.dim == 3 and all(sh.k % 16 == 0 for sh in sc.shapes) and not all(sh.k % 64 == 0 for sh in sc.shapes)
+    on_sym = pair_kind in (mfs.MFS_PAIR_F32_SYM, mfs.MFS_PAIR_F32_SYM16)
+    on_mfma = pair_kind in (mfs.MFS_PAIR_MC_F32, mfs.MFS_PAIR_MC_F16X3)
+    split16 = pair_kind == mfs.MFS_PAIR_MC_F16X3
+    sub_blocks = pair_kind == mfs.MFS_PAIR_F32_SYM16
     rt = shape["rhs_per_thread"] or (1 if R == 1 else 2 if R == 2 else 4)
-    if on_sym and sub_blocks:
+    if sub_blocks:
         kernel_name = "ghat_sym16_kernel<%d> (G_hat, FP32, symmetric, 16-point sub-blocks)" % rt
     elif on_sym:
         kernel_name = "ghat_sym_kernel<%d,%d> (G_hat, FP32, symmetric)" % (sc.dim, rt)
+    elif split16:
+        kernel_name = "ghat_mfma16_kernel<%d> (G_hat, FP16 matrix cores, split operands)" % sc.dim
     elif on_mfma:
         kernel_name = "ghat_mfma_kernel<%d> (G_hat, FP32 matrix cores)" % sc.dim
     else:
@@ -529,8 +542,10 @@ def main() -> int:
     pairs_per_launch32 = p32 / max(n32, 1)   # pair evaluations times right-hand sides
     rate = pairs_per_launch32 / (avg32 * 1e-3) if n32 else 0.0  # (pair, right-hand side) per second
     if on_mfma:
-        # the contraction on the matrix cores: 8 flop per (pair, right-hand side) complex multiply-add
-        alg_pp, kern_pp, bound, peak = FLOP_PER_PAIR_RHS_MFMA, FLOP_PER_PAIR_RHS_MFMA, "mfma", PEAK_FP32_MFMA_TFLOPS
+        # the contraction on the matrix cores: 8 flop per (pair, right-hand side) complex multiply-add;
+        # with split FP16 operands the matrix cores execute 24 (three FP16 products per real product)
+        alg_pp, bound, peak = FLOP_PER_PAIR_RHS_MFMA, "mfma", PEAK_FP32_MFMA_TFLOPS
+        kern_pp = FLOP_PER_PAIR_RHS_SPLIT16 if split16 else FLOP_PER_PAIR_RHS_MFMA
     else:
         alg_pp = alg_flop_per_pair(sc.dim, R)
         kern_pp = flop_per_pair_sym(sc.dim, R) if on_sym else flop_per_pair_plain(sc.dim, R)
@@ -579,7 +594,9 @@ def main() -> int:
                      "kernel_flop_per_pair": kern_pp, "kernel_tflops": kernel_tflops,
                      **({"peak_unpacked_fp32": PEAK_FP32_UNPACKED_TFLOPS,
                          "kernel_frac_of_unpacked_peak": kernel_tflops / PEAK_FP32_UNPACKED_TFLOPS}
-                        if not on_mfma else {})},
+                        if not on_mfma else {}),
+                     **({"peak_fp16_mfma": PEAK_FP16_MFMA_TFLOPS,
+                         "kernel_frac_of_fp16_peak": kernel_tflops / PEAK_FP16_MFMA_TFLOPS} if split16 else {})},
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a row sample ...")

@@ -422,6 +422,27 @@ mfs_status mfs_autotune(mfs_scene* scene, int32_t R, mfs_prec prec, int32_t reps
 mfs_status mfs_tune_get(const mfs_scene* scene, int32_t R, mfs_prec prec, int32_t* nchunks,
                         int32_t* rhs_per_thread, int32_t* symmetric, int32_t* source);
 
+/* Which pair kernel the pair sum G_hat q runs for (R, prec) on this scene, as the launch shape
+ * stands now (mfs_tune_set and mfs_autotune may change it). */
+typedef enum {
+  MFS_PAIR_F64 = 0,         /* FP64, plain */
+  MFS_PAIR_F32 = 1,         /* FP32 vector units, body-centre phase split */
+  MFS_PAIR_F32_SYM = 2,     /* FP32 vector units, phi once per unordered pair */
+  MFS_PAIR_F32_SYM16 = 3,   /* the same on 16-point sub-blocks (3D, bodies of multiples of 16) */
+  MFS_PAIR_MC_F32 = 4,      /* matrix cores, FP32 products (R >= 8) */
+  MFS_PAIR_MC_F16X3 = 5     /* matrix cores, FP16 products of split operands (R >= 8) */
+} mfs_pair_kernel_kind;
+mfs_status mfs_pair_kernel(const mfs_scene* scene, int32_t R, mfs_prec prec, int32_t* kind);
+
+/* Matrix-core form of the FP32 pair sum with 8 or more right-hand sides (bodies of multiples of 16
+ * points).  enable = 1 (the default where the scene allows it): FP16 products of split operands,
+ * each FP32 operand carried as a high and a low FP16 part, three products per real product,
+ * accumulated in FP32 (~2^-21 relative per product; Ootomo and Yokota 2022); it needs |phi| bounded
+ * over the scene's off-body pairs (always in 2D; in 3D from the closest pair of body centres less
+ * twice the largest body radius) and MFS_ERR_ARG is returned when no bound is known.  enable = 0:
+ * FP32 products.  Host only. */
+mfs_status mfs_scene_set_split_fp16(mfs_scene* scene, int32_t enable);
+
 /* Set the scene's own shape for (R, prec): 1 <= nchunks <= 1024; rhs_per_thread 0 = by R, or 1, 2,
  * 4; symmetric 1 = the symmetric kernel where it applies (up to 32 right-hand sides), -1 = as the
  * heuristic (up to 24), 0 = never.  nchunks = 0 removes the scene's entry. */

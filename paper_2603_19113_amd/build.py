@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmfs.so")
 
-SOURCES = ["mfs_api.hip", "pair_kernels.hip", "sapply.hip", "krylov.hip", "lsq.hip", "pool.hip", "recon.hip", "tune.hip", "bkrylov.hip"]
+SOURCES = ["mfs_api.hip", "pair_kernels.hip", "sapply.hip", "krylov.hip", "lsq.hip", "pool.hip", "recon.hip", "tune.hip", "bkrylov.hip", "mc_kernels.hip"]
 
 # Packed FP32 instructions are switched off for every HIP source: some of their forms have
 # given silently wrong results on this hardware generation.

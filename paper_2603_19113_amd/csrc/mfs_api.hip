@@ -119,7 +119,8 @@ struct mfs_scene {
   // padded layout for the symmetric pair kernel (bodies whose point count is not a multiple of 64)
   Buf pad_ptr, body_of_pad, l32p, lsqp, qpad;
   // workspaces
-  Buf partial, q32, dirs, kry, vecs;
+  Buf partial, q32, dirs, kry, vecs, qsplit;
+  int phi16_shift_auto = -1;  // the scene's bound for the FP16 matrix-core kernel (-1: none)
   // near-field tables for the last set of reconstruction factors used with this scene
   std::vector<uint64_t> near_key;
   Buf near_tab;
@@ -137,6 +138,37 @@ struct mfs_recon {
 };
 
 static std::atomic<uint64_t> g_recon_ids{1};
+
+// The scale 2^sA of phi for the FP16 matrix-core kernel: the largest sA with 2^sA |phi| < 2^13 for
+// every pair of points on different bodies (at most 2^20), or -1 where no bound is known.  2D:
+// |phi| = |H0(kappa r)| / 4 < 16 for every r the FP32 kernel can resolve (the Hankel function grows
+// only logarithmically as kappa r -> 0), so sA = 9.  3D: |phi| = 1 / (4 pi r) with r at least the
+// smallest distance between two body centres less 2 rho_max (closest pair of centres by a sweep over
+// the centres sorted by their first coordinate).
+int phi16_shift_for(int dim, int64_t T, const double* centres, double rho_max) {
+  if (dim == 2) return 9;
+  if (T < 2) return 20;
+  std::vector<int64_t> idx(T);
+  for (int64_t i = 0; i < T; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return centres[a * dim] < centres[b * dim]; });
+  double best = INFINITY;
+  for (int64_t a = 0; a < T; ++a) {
+    const double* ca = centres + idx[a] * dim;
+    for (int64_t b = a + 1; b < T; ++b) {
+      const double* cb = centres + idx[b] * dim;
+      if (cb[0] - ca[0] >= best) break;
+      double d2 = 0.0;
+      for (int d = 0; d < dim; ++d) d2 += (cb[d] - ca[d]) * (cb[d] - ca[d]);
+      best = std::min(best, std::sqrt(d2));
+    }
+  }
+  const double r_lb = best - 2.0 * rho_max;
+  if (!(r_lb > 0.0)) return -1;
+  const double phi_max = 1.0 / (4.0 * M_PI * r_lb);
+  int sA = 20;
+  while (sA >= 0 && std::ldexp(phi_max, sA) >= 8192.0) --sA;
+  return sA;
+}
 
 // Scratch memory of mfs_apply_static: the pair sum's partial slices (and the padded copy of the
 // charges for the symmetric kernel) live in this fixed array instead of scene workspace, so that
@@ -255,10 +287,15 @@ mfs_status pair_f32(mfs_scene* s, const c64* q32, int R, hipStream_t st, Partial
     MFS_HIP_TRY(launch_gather_pad(s->dev, q32, R, static_cast<c64*>(s->qpad.p), st));
     qs = static_cast<c64*>(s->qpad.p);
   }
+  void* split = nullptr;
+  if (ls.sym != 1 && ghat_uses_mfma16(s->dev, R)) {
+    MFS_TRY(ensure(s->qsplit, ghat_split_bytes(s->dev, R), &s->bytes, st));
+    split = s->qsplit.p;
+  }
   {
     TimedLaunch tl(MFS_KERNEL_PAIR_F32, s->dev.offbody_pairs * R, st);
     if (ls.sym == 1) MFS_HIP_TRY(launch_ghat_f32_sym(sym_view(s->dev), qs, R, part, ls.nchunks, ls.rt, st));
-    else MFS_HIP_TRY(launch_ghat_f32(s->dev, q32, R, part, ls.nchunks, st, ls.rt));
+    else MFS_HIP_TRY(launch_ghat_f32(s->dev, q32, R, part, ls.nchunks, st, ls.rt, split));
   }
   *out = PartialF32{part, nch, padded ? s->dev.pad_ptr : nullptr, padded ? rows : 0};
   return MFS_OK;
@@ -438,13 +475,18 @@ mfs_status apply_in_buffer(mfs_scene* s, const void* q, void* y, int R, mfs_prec
     ls.nchunks = pair_chunks_for(N, N, tpt_for(MFS_FP32));
   }
   const size_t per_slice = (size_t)R * N * sizeof(c64);
-  const int fit = (int)std::min<size_t>(cap / per_slice, 1024);
+  // the FP16 matrix-core kernel's split charges sit after the partial slices when both fit (else
+  // the FP32 matrix-core kernel runs)
+  const size_t split_bytes = ghat_uses_mfma16(s->dev, R) ? (ghat_split_bytes(s->dev, R) + 255) / 256 * 256 : 0;
+  const size_t slice_room = split_bytes && cap >= split_bytes + per_slice ? (cap - split_bytes) / 256 * 256 : cap;
+  const int fit = (int)std::min<size_t>(slice_room / per_slice, 1024);
   if (fit < 1)
     return fail(MFS_ERR_ARG, "apply_static: one FP32 partial slice needs " + std::to_string(per_slice) +
                                  " bytes (R x N x 8), more than the static scratch's " + std::to_string(cap));
   const int nch = std::min(ls.nchunks, fit);
   c64* part = static_cast<c64*>(buf);
-  MFS_HIP_TRY(launch_ghat_f32(s->dev, q32, R, part, nch, st, ls.rt));
+  void* split = slice_room < cap ? static_cast<char*>(buf) + slice_room : nullptr;
+  MFS_HIP_TRY(launch_ghat_f32(s->dev, q32, R, part, nch, st, ls.rt, split));
   MFS_HIP_TRY(launch_sapply_f32(s->dev, part, nch, q32, 1.0f, static_cast<c64*>(y), R, (int)s->kmax, st));
   return MFS_OK;
 }
@@ -1133,6 +1175,7 @@ mfs_status mfs_scene_create(int32_t dim, double kappa, int64_t T, const int32_t*
     d.all_k_mult64 = d.all_k_mult64 && (k_of_shape[s2] % 64 == 0);
   }
   d.sym16 = dim == 3 && d.all_k_mult16 && !d.all_k_mult64;
+  d.phi16_shift = sc->phi16_shift_auto = phi16_shift_for(dim, T, centres, d.rho_max);
   d.Npad = N;
   d.pad_ptr = nullptr;
   d.body_of_pad = nullptr;
@@ -1172,7 +1215,7 @@ mfs_status mfs_scene_destroy(mfs_scene* s) {
   Buf* all[] = {&s->x64,     &s->x32,     &s->l32,      &s->lsq,     &s->centres,    &s->body_of,
                 &s->body_ptr, &s->shape_of, &s->k_dev,   &s->S64_tab, &s->S32_tab,    &s->rot,
                 &s->partial,  &s->q32,      &s->dirs,    &s->kry,     &s->vecs,       &s->near_tab,
-                &s->pad_ptr,  &s->body_of_pad, &s->l32p, &s->lsqp,    &s->qpad};
+                &s->pad_ptr,  &s->body_of_pad, &s->l32p, &s->lsqp,    &s->qpad,       &s->qsplit};
   for (Buf* b : all) release(*b, &s->bytes, s->last_stream);
   delete s;
   return MFS_OK;
@@ -2008,6 +2051,31 @@ mfs_status mfs_tune_get(const mfs_scene* s, int32_t R, mfs_prec prec, int32_t* n
     *rhs_per_thread = (v == kTunePairF32 || ls.sym == 1) ? (ls.rt ? ls.rt : ghat_default_rt(R)) : 0;
   if (symmetric) *symmetric = ls.sym == 1 ? 1 : 0;
   if (source) *source = src;
+  return MFS_OK;
+}
+
+mfs_status mfs_pair_kernel(const mfs_scene* s, int32_t R, mfs_prec prec, int32_t* kind) {
+  MFS_TRY(check_scene(s));
+  if (R < 1) return fail(MFS_ERR_ARG, "pair_kernel: R must be >= 1");
+  if (!kind) return fail(MFS_ERR_ARG, "pair_kernel: kind is null");
+  if (prec == MFS_FP64) {
+    *kind = MFS_PAIR_F64;
+    return MFS_OK;
+  }
+  const LaunchShape ls = shape_for(s, false, R);
+  if (ls.sym == 1) *kind = s->dev.sym16 ? MFS_PAIR_F32_SYM16 : MFS_PAIR_F32_SYM;
+  else if (ghat_uses_mfma16(s->dev, R)) *kind = MFS_PAIR_MC_F16X3;
+  else if (ghat_uses_mfma(s->dev, R)) *kind = MFS_PAIR_MC_F32;
+  else *kind = MFS_PAIR_F32;
+  return MFS_OK;
+}
+
+mfs_status mfs_scene_set_split_fp16(mfs_scene* s, int32_t enable) {
+  MFS_TRY(check_scene(s));
+  if (enable != 0 && enable != 1) return fail(MFS_ERR_ARG, "scene_set_split_fp16: enable must be 0 or 1");
+  if (enable && s->phi16_shift_auto < 0)
+    return fail(MFS_ERR_ARG, "scene_set_split_fp16: no bound on |phi| is known for this scene (bodies too close)");
+  s->dev.phi16_shift = enable ? s->phi16_shift_auto : -1;
   return MFS_OK;
 }
 

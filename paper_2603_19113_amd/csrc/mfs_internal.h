@@ -63,6 +63,8 @@ struct SceneDev {
   const float* l32p[3];           // [Npad] body-local offsets, 0 for fillers
   const float* lsqp;              // [Npad]
   double rho_max;                 // largest |x_hat - c_body| over all shapes
+  int phi16_shift;                // sA with 2^sA |phi| < 2^13 for every off-body pair (the FP16
+                                  // matrix-core kernel), or -1 where no such bound is known
   const double* rot;              // [T][dim][dim] body orientations (row-major), or null: identity
 };
 
@@ -97,8 +99,18 @@ bool sym_padded(const SceneDev& s);
 // t[r][i] = sum_c partial[c][r][pad(i)] for the padded layout.
 hipError_t launch_reduce_partials_padded(const SceneDev& s, const c64* partial, int nchunks, int R, c64* out,
                                          hipStream_t st);
+// split: device workspace of ghat_split_bytes(s, R) bytes for the FP16 matrix-core kernel (the
+// split charges), or null: then the FP32 matrix-core kernel runs where the matrix cores are used.
 hipError_t launch_ghat_f32(const SceneDev& s, const c64* q, int R, c64* partial, int nchunks,
-                           hipStream_t st, int rt = 0);
+                           hipStream_t st, int rt = 0, void* split = nullptr);
+// The FP16 matrix-core kernel (split operands) applies: many right-hand sides, bodies of multiples of
+// 16 points, and a scale 2^sA with 2^sA |phi| < 2^13 known for the scene (phi16_shift >= 0).
+bool ghat_uses_mfma16(const SceneDev& s, int R);
+size_t ghat_split_bytes(const SceneDev& s, int R);
+// The matrix-core pair sum (mc_kernels.hip): the split FP16 form where split is given and the scene
+// allows it, else the FP32 form.
+hipError_t launch_ghat_mc(const SceneDev& s, const c64* q, int R, c64* partial, int nchunks, void* split,
+                          hipStream_t st);
 hipError_t launch_ghat_f64(const SceneDev& s, const c128* q, int R, c128* partial, int nchunks,
                            hipStream_t st);
 hipError_t launch_eval_f32(const SceneDev& s, const c64* q, int R, const double* targets, int64_t M,

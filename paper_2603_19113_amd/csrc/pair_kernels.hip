@@ -17,6 +17,7 @@
 //     to the RT charges.
 #include "mfs_internal.h"
 #include "phi.h"
+#include "bodyphase.h"
 
 namespace mfs {
 namespace {
@@ -203,45 +204,6 @@ __global__ __launch_bounds__(kBlock) void pair_sum_kernel(
   }
 }
 
-// ---------------------------------------------------------------------------
-// G_hat in FP32 with the distance split at the body centres.
-//
-// For target i on body a and source j on body b, x_i - x_j = (c_a - c_b) + (l_i - l_j), with
-// body-local offsets l (|l| <= body radius) and centre difference dc.  With D = |dc| and
-// u = |dl|^2 + 2 dc.dl, the distance is r = D + delta, delta = u / (D + r).  u is evaluated as
-// A + |l_j|^2 + P . l_j with A = |l_i|^2 + 2 dc.l_i and P = -2 (l_i + dc) formed once per
-// (target, source body) and |l_j|^2 stored per point.  D and the phase
-// kappa D mod 2 pi are formed in FP64 once per (target, source body); delta, and with it the
-// phase correction, is an O(1) quantity formed in FP32 to ~1e-7 relative.  The phase kappa r is
-// therefore accurate to ~1e-6 rad instead of ~kappa r 2^-24 (1e-4 rad at kappa r = 1400).
-// Per source body the FP32 partial sums are added into FP64 accumulators, which removes the
-// O(sqrt(N) eps) growth of one long FP32 sum.
-//
-// 2D kernel, three branches on z = kappa r:
-//   z >= 12: Hankel modulus and phase expansions (DLMF 10.18.17-18, series of M^2 taken to its
-//            square root), 3 terms each: H0 = M e^{i theta},
-//            M sqrt(pi z / 2) = 1 - 1/(16 z^2) + 53/(512 z^4),
-//            theta = z - pi/4 - 1/(8 z) + 25/(384 z^3) - 1073/(5120 z^5);
-//            errors <= 2e-7 (modulus) and 4e-8 rad (phase) for z >= 12;
-//   3 <= z < 12: A&S 9.4.3 with the same accurate phase;
-//   z < 3: A&S 9.4.1 / 9.4.2.
-// 3D kernel: exp(i kappa r) / (4 pi r) with the same phase split.
-// ---------------------------------------------------------------------------
-struct BodyPhaseConsts {
-  float kappa_rev;   // kappa / 2 pi
-  float r_far;       // 12 / kappa
-  float r_mid;       // 3 / kappa
-  // far branch, amplitude (1/4) sqrt(2/(pi kappa)) r^{-1/2} (m0 + m1 r^-2 + m2 r^-4)
-  float m0, m1, m2;
-  // far branch, phase correction in revolutions: r^-1 (p0 + p1 r^-2 + p2 r^-4)
-  float p0, p1, p2;
-  // A&S branches
-  Phi2DConstsF32 as;
-  double kappa_rev64;
-  float far_D;       // centre distance beyond which every pair of two bodies has z >= 12
-  float vfar_D;      // centre distance beyond which every pair has z >= 100 (shorter expansions)
-};
-
 template <int DIM, int TPT, int RT>
 struct BPAcc {
   float lx[TPT][DIM];  // target body-local offsets
@@ -253,57 +215,6 @@ struct BPAcc {
   float D[TPT], D2[TPT], ph0[TPT];
   float sr_[TPT][RT], si_[TPT][RT];  // FP32 partial sums over the current source body
 };
-
-// FAR: 0 = any distance (branches), 1 = every pair has z >= 12, 2 = every pair has z >= 100, where
-// the z^-4 modulus term (< 1e-9 relative) and the z^-5 phase term (< 2e-11 rad) are dropped.
-template <int DIM, int FAR = 0>
-__device__ __forceinline__ void bp_phi(const BodyPhaseConsts& k, float u, float D, float D2, float ph0,
-                                       float& pr, float& pi) {
-  const float r2 = D2 + u;
-  const float rinv = __builtin_amdgcn_rsqf(r2);
-  const float r = r2 * rinv;
-  // delta = r - D = u / (D + r), accurate where r >> 1
-  const float delta = u * __builtin_amdgcn_rcpf(D + r);
-  if constexpr (DIM == 3) {
-    const float rev = __builtin_amdgcn_fractf(fmaf(delta, k.kappa_rev, ph0));
-    const float a = rinv * 0.07957747154594767f;  // 1 / (4 pi r)
-    pr = a * __builtin_amdgcn_cosf(rev);
-    pi = a * __builtin_amdgcn_sinf(rev);
-  } else {
-    if (FAR > 0 || r >= k.r_far) {
-      const float w2 = rinv * rinv;
-      const float m = FAR == 2 ? fmaf(k.m1, w2, k.m0) : fmaf(fmaf(k.m2, w2, k.m1), w2, k.m0);
-      const float th = FAR == 2 ? rinv * fmaf(k.p1, w2, k.p0) : rinv * fmaf(fmaf(k.p2, w2, k.p1), w2, k.p0);
-      const float rev = __builtin_amdgcn_fractf(fmaf(delta, k.kappa_rev, ph0) + th);
-      const float a = m * __builtin_amdgcn_sqrtf(rinv);
-      // (i/4) H0 = (i/4) M e^{i theta}: re = -A sin, im = A cos
-      pr = -a * __builtin_amdgcn_sinf(rev);
-      pi = a * __builtin_amdgcn_cosf(rev);
-    } else if (r >= k.r_mid) {
-      const float t = k.as.three_over_kappa * rinv;
-      float f0 = 0.00014476f;
-      f0 = fmaf(f0, t, -0.00072805f);
-      f0 = fmaf(f0, t, 0.00137237f);
-      f0 = fmaf(f0, t, -0.00009512f);
-      f0 = fmaf(f0, t, -0.00552740f);
-      f0 = fmaf(f0, t, -0.00000077f);
-      f0 = fmaf(f0, t, 0.79788456f);
-      float th = 0.00013558f * 0.15915494309189535f;
-      th = fmaf(th, t, -0.00029333f * 0.15915494309189535f);
-      th = fmaf(th, t, -0.00054125f * 0.15915494309189535f);
-      th = fmaf(th, t, 0.00262573f * 0.15915494309189535f);
-      th = fmaf(th, t, -0.00003954f * 0.15915494309189535f);
-      th = fmaf(th, t, -0.04166397f * 0.15915494309189535f);
-      th = th * t;  // -1/8 is already in ph0
-      const float rev = __builtin_amdgcn_fractf(fmaf(delta, k.kappa_rev, ph0) + th);
-      const float a = k.as.amp * f0 * __builtin_amdgcn_sqrtf(rinv);
-      pr = -a * __builtin_amdgcn_sinf(rev);
-      pi = a * __builtin_amdgcn_cosf(rev);
-    } else {
-      phi2d_f32(r2, k.as, pr, pi);
-    }
-  }
-}
 
 template <int DIM, int TPT, int RT, bool MASK, int FAR = 0>
 __device__ __forceinline__ void bp_source(BPAcc<DIM, TPT, RT>& a, const BodyPhaseConsts& k, int sb,
@@ -1100,16 +1011,6 @@ __global__ __launch_bounds__(64, SymWaves<RT>::value) void ghat_sym16_kernel(
   }
 }
 
-Phi2DConstsF32 make_phi2d_f32(double kappa) {
-  Phi2DConstsF32 c;
-  c.kappa = (float)kappa;
-  c.kappa_rev = (float)(kappa / (2.0 * M_PI));
-  c.three_over_kappa = (float)(3.0 / kappa);
-  c.amp = (float)(0.25 / std::sqrt(kappa));
-  c.kappa2_9 = (float)(kappa * kappa / 9.0);
-  c.log_half_kappa = (float)std::log(0.5 * kappa);
-  return c;
-}
 
 template <typename T, int DIM, int TPT, int RT, bool EXT>
 hipError_t launch_pair(const PhiEval<T, DIM>& phi, const T* s0, const T* s1, const T* s2, const int32_t* sbody,
@@ -1154,234 +1055,6 @@ int pair_chunks_for(int64_t n_sources, int64_t n_targets, int tpt) {
 
 static const double kZero3[3] = {0.0, 0.0, 0.0};
 
-// ---------------------------------------------------------------------------
-// Many right-hand sides: T = G_hat Q, Q [R][N], on the matrix cores.
-//
-// A block of 4 waves owns 64 targets and 64 right-hand sides.  Sources are taken 16 at a time:
-//   * the block stages the charge tile Q(16 sources x 64 RHS) in LDS, transposed so that the
-//     B operand of the MFMA is read without bank conflicts;
-//   * each wave evaluates phi for its 16 targets x 16 sources with the same body-centre phase
-//     split as the single-RHS kernel, directly in the A-operand layout of
-//     v_mfma_f32_16x16x4f32 (lane l holds row l%16, k = l/16), so phi never goes through LDS;
-//   * the complex product is four real MFMAs per (k-step, 16-RHS block):
-//     Tr += Gr Qr - Gi Qi, Ti += Gr Qi + Gi Qr.
-// FP32 MFMA accumulators are added into FP64 every 16 tiles (256 sources).  Requires every body
-// to hold a multiple of 16 points, so that a 16-source tile lies in one body.
-// ---------------------------------------------------------------------------
-typedef float v4f __attribute__((ext_vector_type(4)));
-constexpr int kMfmaTargets = 64;   // per block (16 per wave)
-constexpr int kMfmaRhs = 64;       // per block (4 blocks of 16)
-constexpr int kMfmaSrc = 16;       // sources per tile
-constexpr int kMfmaFlush = 16;     // tiles between FP64 flushes
-constexpr int kMfmaMinRhs = 8;     // fewer right-hand sides use the VALU kernel
-
-template <int DIM>
-__global__ __launch_bounds__(256) void ghat_mfma_kernel(
-    BodyPhaseConsts k, const float* __restrict__ l0, const float* __restrict__ l1, const float* __restrict__ l2,
-    const float* __restrict__ lsq, const double* __restrict__ cen, const int32_t* __restrict__ body_of,
-    const c64* __restrict__ q, int64_t N, int R, int64_t chunk_len, c64* __restrict__ partial) {
-  __shared__ c64 qt[2][kMfmaSrc][kMfmaRhs];  // transposed charge tiles, double-buffered
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int64_t tbase = (int64_t)blockIdx.x * kMfmaTargets + 16 * wave;
-  const int r0 = blockIdx.z * kMfmaRhs;
-  const int64_t c0 = (int64_t)blockIdx.y * chunk_len;
-  const int64_t c1 = min(N, c0 + chunk_len);
-
-  // target of this lane in the A layout
-  const int64_t tg = tbase + (lane & 15);
-  const int64_t tgc = tg < N ? tg : N - 1;
-  float lt[DIM];
-  lt[0] = l0[tgc];
-  lt[1] = l1[tgc];
-  if constexpr (DIM == 3) lt[2] = l2[tgc];
-  const int tb = tg < N ? body_of[tgc] : -1;
-  double ct[DIM];
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) ct[d] = cen[(int64_t)body_of[tgc] * DIM + d];
-
-  v4f accR[4], accI[4];
-  double sumR[4][4], sumI[4][4];
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    accR[b] = v4f{0.f, 0.f, 0.f, 0.f};
-    accI[b] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int i = 0; i < 4; ++i) sumR[b][i] = sumI[b][i] = 0.0;
-  }
-  int cur_sb = -1;
-  float A = 0.f, D = 0.f, D2 = 0.f, ph0 = 0.f, P[DIM];
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) P[d] = 0.f;
-
-  // Software pipeline over tiles of 16 sources: while the matrix cores work on tile t (charges
-  // from one LDS buffer, phi from registers), the wave loads the charges of tile t + 1, generates
-  // its phi on the VALU and stores the charges into the other buffer; one barrier per tile.
-  // Tiles are taken kMfmaFlush at a time with FP32 accumulators, then added into FP64 sums; the
-  // flush sits outside the inner loop so the accumulators stay in the matrix-core registers.
-  const int rr = threadIdx.x >> 2;        // right-hand side staged by this thread (0..63)
-  const int sg = (threadIdx.x & 3) * 4;   // its four sources in the tile: 0, 4, 8, 12
-  const int rq = r0 + rr;
-  auto load_q = [&](int64_t j0, c64* qr) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) qr[u] = rq < R ? q[(int64_t)rq * N + j0 + sg + u] : c64{0.f, 0.f};
-  };
-  auto store_q = [&](int buf, const c64* qr) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) qt[buf][sg + u][rr] = qr[u];
-  };
-  // per (target, source body) quantities for the tile starting at j0; returns whether every target
-  // of the wave is on another body and far from this one (then all pairs take the asymptotic branch)
-  auto body_setup = [&](int64_t j0) {
-    const int sb = body_of[j0];
-    if (sb != cur_sb) {
-      cur_sb = sb;
-      double dd2 = 0.0;
-      float Ai = 0.f;
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        const double dc = ct[d] - cen[(int64_t)sb * DIM + d];
-        dd2 = fma(dc, dc, dd2);
-        const float dcf = (float)dc;
-        Ai = fmaf(lt[d], lt[d] + 2.0f * dcf, Ai);
-        P[d] = -2.0f * (lt[d] + dcf);
-      }
-      const double dd = sqrt(dd2);
-      const double ph = dd * k.kappa_rev64;
-      A = Ai;
-      D = (float)dd;
-      D2 = (float)dd2;
-      ph0 = (float)(ph - floor(ph)) - (DIM == 2 ? 0.125f : 0.0f);
-    }
-    return (bool)__all(tb < 0 || (tb != sb && D >= k.far_D));
-  };
-  // phi in the A layout: k-step s, source j0 + 4 s + lane / 16
-  auto gen_phi = [&](int64_t j0, bool far_all, float* gr, float* gi) {
-    const int sb = cur_sb;
-#pragma unroll
-    for (int st = 0; st < 4; ++st) {
-      const int64_t j = j0 + 4 * st + (lane >> 4);
-      float u = A + lsq[j];
-      u = fmaf(P[0], l0[j], u);
-      u = fmaf(P[1], l1[j], u);
-      if constexpr (DIM == 3) u = fmaf(P[2], l2[j], u);
-      float pr, pi;
-      if (far_all) {
-        bp_phi<DIM, 1>(k, u, D, D2, ph0, pr, pi);
-      } else {
-        bp_phi<DIM>(k, u, D, D2, ph0, pr, pi);
-        const bool same = tb == sb;
-        pr = same ? 0.f : pr;
-        pi = same ? 0.f : pi;
-      }
-      gr[st] = pr;
-      gi[st] = pi;
-    }
-  };
-  // the 64 MFMAs of one tile (4 k-steps x 4 blocks of 16 right-hand sides x 4 real products)
-  auto mfma_tile = [&](int buf, const float* gr, const float* gi) {
-#pragma unroll
-    for (int st = 0; st < 4; ++st) {
-      const float ngi = -gi[st];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const c64 qq = qt[buf][4 * st + (lane >> 4)][16 * b + (lane & 15)];
-        accR[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr[st], qq.re, accR[b], 0, 0, 0);
-        accR[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ngi, qq.im, accR[b], 0, 0, 0);
-        accI[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr[st], qq.im, accI[b], 0, 0, 0);
-        accI[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(gi[st], qq.re, accI[b], 0, 0, 0);
-      }
-    }
-  };
-
-  if (c0 < c1) {
-    c64 qreg[4];
-    float gr[4], gi[4];
-    load_q(c0, qreg);
-    store_q(0, qreg);
-    gen_phi(c0, body_setup(c0), gr, gi);
-    __syncthreads();
-    int buf = 0;
-    for (int64_t jb = c0; jb < c1; jb += (int64_t)kMfmaSrc * kMfmaFlush) {
-      const int64_t je = min(c1, jb + (int64_t)kMfmaSrc * kMfmaFlush);
-      for (int64_t j0 = jb; j0 < je; j0 += kMfmaSrc) {
-        const int64_t jn = j0 + kMfmaSrc;
-        const bool more = jn < c1;
-        bool far_next = false;
-        if (more) {
-          load_q(jn, qreg);  // in flight during the matrix-core work below
-          far_next = body_setup(jn);
-        }
-        float gn[4], gm[4];
-        if (more && far_next) {
-          // straight-line block: the scheduler interleaves the next tile's phi with this tile's MFMAs
-          mfma_tile(buf, gr, gi);
-          gen_phi(jn, true, gn, gm);
-#pragma unroll
-          for (int i = 0; i < 56; ++i) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
-            __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // two VALU
-          }
-        } else {
-          mfma_tile(buf, gr, gi);
-          if (more) gen_phi(jn, false, gn, gm);
-        }
-        if (more) {
-          store_q(buf ^ 1, qreg);
-#pragma unroll
-          for (int st = 0; st < 4; ++st) {
-            gr[st] = gn[st];
-            gi[st] = gm[st];
-          }
-        }
-        __syncthreads();
-        buf ^= 1;
-      }
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          sumR[b][i] += (double)accR[b][i];
-          sumI[b][i] += (double)accI[b][i];
-          accR[b][i] = 0.f;
-          accI[b][i] = 0.f;
-        }
-    }
-  }
-  // output layout of the 16x16 MFMA: lane l, register i -> row 4 (l / 16) + i, column l % 16
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const int r = r0 + 16 * b + (lane & 15);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t t = tbase + 4 * (lane >> 4) + i;
-      if (r < R && t < N)
-        partial[((int64_t)blockIdx.y * R + r) * N + t] = c64{(float)sumR[b][i], (float)sumI[b][i]};
-    }
-  }
-}
-
-static BodyPhaseConsts make_bodyphase(double kappa, double rho_max) {
-  BodyPhaseConsts k{};
-  const double two_pi = 2.0 * M_PI;
-  k.kappa_rev = (float)(kappa / two_pi);
-  k.kappa_rev64 = kappa / two_pi;
-  k.r_far = (float)(12.0 / kappa);
-  k.r_mid = (float)(3.0 / kappa);
-  const double amp = 0.25 * std::sqrt(2.0 / (M_PI * kappa));  // (1/4) sqrt(2/(pi kappa))
-  const double k2 = kappa * kappa;
-  k.m0 = (float)amp;
-  k.m1 = (float)(-amp / (16.0 * k2));
-  k.m2 = (float)(amp * 53.0 / (512.0 * k2 * k2));
-  k.p0 = (float)(-1.0 / (8.0 * kappa) / two_pi);
-  k.p1 = (float)(25.0 / (384.0 * k2 * kappa) / two_pi);
-  k.p2 = (float)(-1073.0 / (5120.0 * k2 * k2 * kappa) / two_pi);
-  k.as = make_phi2d_f32(kappa);
-  // |x_i - x_j| >= D - 2 rho_max, so D >= 12/kappa + 2 rho_max (plus rounding slack) is far for all pairs
-  k.far_D = (float)((12.0 / kappa + 2.0 * rho_max) * (1.0 + 1e-5) + 1e-6);
-  k.vfar_D = (float)((100.0 / kappa + 2.0 * rho_max) * (1.0 + 1e-5) + 1e-6);
-  return k;
-}
 
 template <int DIM, int RT>
 static hipError_t launch_bodyphase(const SceneDev& s, const c64* q, int R, c64* partial, int nchunks,
@@ -1397,18 +1070,7 @@ static hipError_t launch_bodyphase(const SceneDev& s, const c64* q, int R, c64* 
   return hipGetLastError();
 }
 
-template <int DIM>
-static hipError_t launch_mfma(const SceneDev& s, const c64* q, int R, c64* partial, int nchunks, hipStream_t st) {
-  int64_t chunk_len = (s.N + nchunks - 1) / nchunks;
-  chunk_len = (chunk_len + kMfmaSrc - 1) / kMfmaSrc * kMfmaSrc;
-  dim3 grid((unsigned)((s.N + kMfmaTargets - 1) / kMfmaTargets), (unsigned)nchunks,
-            (unsigned)((R + kMfmaRhs - 1) / kMfmaRhs));
-  hipLaunchKernelGGL((ghat_mfma_kernel<DIM>), grid, dim3(256), 0, st, make_bodyphase(s.kappa, s.rho_max), s.l32[0], s.l32[1],
-                     s.l32[2], s.lsq32, s.centres, s.body_of, q, s.N, R, chunk_len, partial);
-  return hipGetLastError();
-}
 
-bool ghat_uses_mfma(const SceneDev& s, int R) { return R >= kMfmaMinRhs && s.all_k_mult16; }
 
 int ghat_default_rt(int R) { return R == 1 ? 1 : R == 2 ? 2 : 4; }
 
@@ -1498,10 +1160,9 @@ hipError_t launch_ghat_f32_sym(const SceneDev& s, const c64* q, int R, c64* part
 }
 
 hipError_t launch_ghat_f32(const SceneDev& s, const c64* q, int R, c64* partial, int nchunks, hipStream_t st,
-                           int rt) {
+                           int rt, void* split) {
   if (s.N <= 0) return hipSuccess;
-  if (ghat_uses_mfma(s, R)) return s.dim == 2 ? launch_mfma<2>(s, q, R, partial, nchunks, st)
-                                              : launch_mfma<3>(s, q, R, partial, nchunks, st);
+  if (ghat_uses_mfma(s, R)) return launch_ghat_mc(s, q, R, partial, nchunks, split, st);
   if (rt != 1 && rt != 2 && rt != 4) rt = ghat_default_rt(R);
   if (s.dim == 2) {
     if (rt == 1) return launch_bodyphase<2, 1>(s, q, R, partial, nchunks, st);

@@ -79,8 +79,13 @@ EXPORTS = ["mfs_last_error", "mfs_version", "mfs_build_S", "mfs_scene_create", "
            "mfs_apply_static", "mfs_solve", "mfs_eval_field", "mfs_timing_enable", "mfs_timing_read", "mfs_pool_query",
            "mfs_pool_set_limit", "mfs_pool_trim", "mfs_recon_create", "mfs_recon_destroy", "mfs_recon_size",
            "mfs_near_sizes", "mfs_plane_wave_colloc", "mfs_reconstruct", "mfs_eval_field_near", "mfs_autotune",
-           "mfs_tune_get", "mfs_tune_set", "mfs_tune_save", "mfs_tune_load", "mfs_tune_clear", "mfs_tune_table_size"]
+           "mfs_tune_get", "mfs_tune_set", "mfs_tune_save", "mfs_tune_load", "mfs_tune_clear", "mfs_tune_table_size",
+           "mfs_pair_kernel", "mfs_scene_set_split_fp16"]
 MFS_KERNEL_PAIR_F32, MFS_KERNEL_PAIR_F64 = 0, 1
+# mfs_pair_kernel_kind
+MFS_PAIR_F64, MFS_PAIR_F32, MFS_PAIR_F32_SYM, MFS_PAIR_F32_SYM16, MFS_PAIR_MC_F32, MFS_PAIR_MC_F16X3 = range(6)
+PAIR_KERNEL_NAMES = {MFS_PAIR_F64: "f64", MFS_PAIR_F32: "f32", MFS_PAIR_F32_SYM: "f32_sym",
+                     MFS_PAIR_F32_SYM16: "f32_sym16", MFS_PAIR_MC_F32: "mc_f32", MFS_PAIR_MC_F16X3: "mc_f16x3"}
 
 
 def load(path: str = LIB_PATH):
@@ -127,6 +132,8 @@ def load(path: str = LIB_PATH):
         "mfs_tune_load": ([ctypes.c_char_p], ctypes.c_int),
         "mfs_tune_clear": ([], ctypes.c_int),
         "mfs_tune_table_size": ([ctypes.POINTER(i64)], ctypes.c_int),
+        "mfs_pair_kernel": ([vp, i32, i32, ctypes.POINTER(i32)], ctypes.c_int),
+        "mfs_scene_set_split_fp16": ([vp, i32], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -415,6 +422,18 @@ def tune_get(scene: Scene, R: int = 1, prec: int = MFS_MIXED) -> dict:
                              ctypes.byref(src)))
     return {"nchunks": nch.value, "rhs_per_thread": rt.value, "symmetric": sym.value,
             "source": {0: "heuristic", 1: "table", 2: "scene"}[src.value]}
+
+
+def pair_kernel(scene: Scene, R: int = 1, prec: int = MFS_MIXED) -> int:
+    """mfs_pair_kernel: the MFS_PAIR_* kernel the pair sum runs for (R, prec) on this scene."""
+    kind = ctypes.c_int32()
+    _check(_lib.mfs_pair_kernel(scene.handle, int(R), int(prec), ctypes.byref(kind)))
+    return kind.value
+
+
+def set_split_fp16(scene: Scene, enable: bool):
+    """mfs_scene_set_split_fp16: FP16 split-operand (True) or FP32 (False) matrix-core products."""
+    _check(_lib.mfs_scene_set_split_fp16(scene.handle, 1 if enable else 0))
 
 
 def tune_set(scene: Scene, R: int, prec: int, nchunks: int, rhs_per_thread: int = 0, symmetric: int = -1):
