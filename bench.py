@@ -75,8 +75,8 @@ PEAK_FP32_UNPACKED_TFLOPS = 78.6
 # Many right-hand sides: G_hat tile x charge block on the FP32 matrix cores (dense FP32 MFMA peak).
 FLOP_PER_PAIR_RHS_MFMA = 8
 PEAK_FP32_MFMA_TFLOPS = 157.3
-# The same contraction as FP16 products of split operands: 3 x 8 = 24 FP16 flop per (pair, right-hand
-# side), against the dense FP16 matrix-core peak.
+# The same contraction as FP16 products of split operands (hi + lo, three products per real product):
+# 3 x 8 = 24 FP16 flop per (pair, right-hand side), against the dense FP16 matrix-core peak.
 FLOP_PER_PAIR_RHS_SPLIT16 = 24
 PEAK_FP16_MFMA_TFLOPS = 2500.0
 
@@ -93,13 +93,15 @@ def log(msg: str):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_sha256() -> str:
-    """Hash of the pair-kernel sources, recorded with every traffic measurement."""
+def kernel_source_sha256(kernel_name: str = "") -> str:
+    """Hash of the sources of a pair kernel (the matrix-core kernels' file or the vector-unit kernels'
+    file, with the headers both share), recorded with every traffic measurement."""
     import hashlib
 
     csrc = os.path.join(ROOT, "paper_2603_19113_amd", "csrc")
-    return hashlib.sha256(open(os.path.join(csrc, "pair_kernels.hip"), "rb").read() +
-                          open(os.path.join(csrc, "phi.h"), "rb").read()).hexdigest()
+    main = "mc_kernels.hip" if kernel_name.startswith("ghat_mfma") else "pair_kernels.hip"
+    return hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
+                                   for f in (main, "bodyphase.h", "phi.h"))).hexdigest()
 
 
 def stored_traffic(key: str, scene_name: str, kernel_name: str, nchunks: int, folder: str | None = None):
@@ -119,7 +121,7 @@ def stored_traffic(key: str, scene_name: str, kernel_name: str, nchunks: int, fo
         return None
     if fields.get("scene", scene_name) != scene_name:
         return None
-    if fields.get("kernel_source_sha256") != kernel_source_sha256() or "traffic_bytes_per_launch" not in fields:
+    if fields.get("kernel_source_sha256") != kernel_source_sha256(kernel_name) or "traffic_bytes_per_launch" not in fields:
         return None
     if fields.get("nchunks") != str(nchunks):
         return None
@@ -541,11 +543,14 @@ def main() -> int:
     avg32 = ms32 / max(n32, 1)
     pairs_per_launch32 = p32 / max(n32, 1)   # pair evaluations times right-hand sides
     rate = pairs_per_launch32 / (avg32 * 1e-3) if n32 else 0.0  # (pair, right-hand side) per second
-    if on_mfma:
-        # the contraction on the matrix cores: 8 flop per (pair, right-hand side) complex multiply-add;
-        # with split FP16 operands the matrix cores execute 24 (three FP16 products per real product)
-        alg_pp, bound, peak = FLOP_PER_PAIR_RHS_MFMA, "mfma", PEAK_FP32_MFMA_TFLOPS
-        kern_pp = FLOP_PER_PAIR_RHS_SPLIT16 if split16 else FLOP_PER_PAIR_RHS_MFMA
+    if split16:
+        # the contraction as FP16 products of split operands: 24 FP16 flop per (pair, right-hand side)
+        # (three products per real product of the 8-flop complex multiply-add), against the FP16
+        # matrix-core peak; the FP32-equivalent rate (8 flop) is reported beside it
+        alg_pp, kern_pp, bound, peak = FLOP_PER_PAIR_RHS_SPLIT16, FLOP_PER_PAIR_RHS_SPLIT16, "mfma", PEAK_FP16_MFMA_TFLOPS
+    elif on_mfma:
+        # the contraction on the FP32 matrix cores: 8 flop per (pair, right-hand side) complex multiply-add
+        alg_pp, kern_pp, bound, peak = FLOP_PER_PAIR_RHS_MFMA, FLOP_PER_PAIR_RHS_MFMA, "mfma", PEAK_FP32_MFMA_TFLOPS
     else:
         alg_pp = alg_flop_per_pair(sc.dim, R)
         kern_pp = flop_per_pair_sym(sc.dim, R) if on_sym else flop_per_pair_plain(sc.dim, R)
@@ -595,8 +600,9 @@ def main() -> int:
                      **({"peak_unpacked_fp32": PEAK_FP32_UNPACKED_TFLOPS,
                          "kernel_frac_of_unpacked_peak": kernel_tflops / PEAK_FP32_UNPACKED_TFLOPS}
                         if not on_mfma else {}),
-                     **({"peak_fp16_mfma": PEAK_FP16_MFMA_TFLOPS,
-                         "kernel_frac_of_fp16_peak": kernel_tflops / PEAK_FP16_MFMA_TFLOPS} if split16 else {})},
+                     **({"fp32_equivalent_tflops": FLOP_PER_PAIR_RHS_MFMA * rate / 1e12,
+                         "fp32_equivalent_frac_of_fp32_mfma_peak": FLOP_PER_PAIR_RHS_MFMA * rate / 1e12 / PEAK_FP32_MFMA_TFLOPS}
+                        if split16 else {})},
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a row sample ...")

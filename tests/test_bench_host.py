@@ -32,7 +32,7 @@ def test_traffic_record_lookup(tmp_path):
     name = "ghat_sym16_kernel<1> (G_hat, FP32, symmetric, 16-point sub-blocks)"
     rec = tmp_path / "ghat_f32_spheres1000_traffic.md"
     rec.write_text("# record\nscene: spheres1000_kappa3\nkernel: ghat_sym16_kernel<1>\nnchunks: 37\n"
-                   f"traffic_bytes_per_launch: 123456789\nkernel_source_sha256: {bench.kernel_source_sha256()}\n")
+                   f"traffic_bytes_per_launch: 123456789\nkernel_source_sha256: {bench.kernel_source_sha256(name)}\n")
     got = bench.stored_traffic("spheres1000", "spheres1000_kappa3", name, 37, folder=str(tmp_path))
     assert got == 123456789
     assert bench.stored_traffic("spheres1000", "spheres1000_kappa3", name, 38, folder=str(tmp_path)) is None
@@ -40,8 +40,16 @@ def test_traffic_record_lookup(tmp_path):
     assert bench.stored_traffic("spheres1000", "spheres1000_kappa3", "ghat_sym_kernel<3,1> (G_hat)", 37,
                                 folder=str(tmp_path)) is None
     assert bench.stored_traffic("disks16", "disks16_kappa5", name, 37, folder=str(tmp_path)) is None
-    rec.write_text(rec.read_text().replace(bench.kernel_source_sha256(), "0" * 64))  # kernel changed since
+    rec.write_text(rec.read_text().replace(bench.kernel_source_sha256(name), "0" * 64))  # kernel changed since
     assert bench.stored_traffic("spheres1000", "spheres1000_kappa3", name, 37, folder=str(tmp_path)) is None
+
+
+def test_traffic_hash_follows_the_kernel_source():
+    """The matrix-core kernels and the vector-unit kernels live in different files: a change to one
+    leaves the other's counter records valid."""
+    mc = bench.kernel_source_sha256("ghat_mfma16_kernel<2> (G_hat, FP16 matrix cores, split operands)")
+    assert mc == bench.kernel_source_sha256("ghat_mfma_kernel<2> (G_hat, FP32 matrix cores)")
+    assert mc != bench.kernel_source_sha256("ghat_sym16_kernel<1> (G_hat, FP32, symmetric, 16-point sub-blocks)")
 
 
 def test_roofline_uses_the_algorithmic_work_per_pair():
