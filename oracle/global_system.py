@@ -112,6 +112,14 @@ def dense_operator(scene, S_of_shape, xhat, ptr, body_of):
     return np.eye(N, dtype=np.complex128) + SG
 
 
+def condition_number(scene, S_of_shape, xhat, ptr, body_of):
+    """K = cond_2(I + S G_hat), the condition number of the global coefficient matrix of eq. mbody2
+    that Sec. 5.1 (Example 1) reports: largest over smallest singular value, by a dense SVD (small N
+    only)."""
+    sv = np.linalg.svd(dense_operator(scene, S_of_shape, xhat, ptr, body_of), compute_uv=False)
+    return float(sv[0] / sv[-1])
+
+
 def dense_solve(scene, S_of_shape, xhat, ptr, body_of, b):
     """qhat = (I + S G_hat)^{-1} b by LU (numpy.linalg.solve); b [R, N]."""
     Aop = dense_operator(scene, S_of_shape, xhat, ptr, body_of)

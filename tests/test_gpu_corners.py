@@ -32,6 +32,7 @@ def _mfs_far(sh):
 SHAPES = {
     "teardrop": lambda: w.teardrop2d(levels=8, base_panels=16, d_frac=0.5),
     "cshape": lambda: w.cshape2d(levels=6, base_per_edge=3, d_frac=0.5),
+    "rod": lambda: w.rod2d(levels=4),
 }
 
 

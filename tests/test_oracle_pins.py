@@ -254,3 +254,57 @@ def test_gmres_matches_dense_lu():
     # the true residual of the dense solution
     r = b[0] - gs.matvec(sc, [S], xh, ptr, bo, q)[0]
     assert np.linalg.norm(r) / np.linalg.norm(b[0]) < 1e-13
+
+
+def _one_point_scene(dim, kappa, centres):
+    """Bodies of one equivalent point each (the body centre), for closed forms of I + S G_hat."""
+    z = np.zeros((1, dim))
+    sh = w.ShapeDiscretisation(name="point", dim=dim, colloc=z, src=z, proxy=z, eqpts=z, bounding_radius=0.0,
+                               proxy_radius=0.0)
+    c = np.asarray(centres, np.float64)
+    return w.Scene(dim=dim, kappa=kappa, shapes=[sh], shape_of=np.zeros(c.shape[0], np.int32), centres=c,
+                   directions=np.array([[1.0] + [0.0] * (dim - 1)]))
+
+
+def test_condition_number_of_one_body_is_one():
+    """One body: G_hat has no off-body entries, so I + S G_hat = I and K = 1 for any S."""
+    sc = w.make_scene("disks16", T=1)
+    S = [local_s.s_given_points(s, sc.kappa) for s in sc.shapes]
+    xh, ptr, bo = gs.pack(sc)
+    assert abs(gs.condition_number(sc, S, xh, ptr, bo) - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("dim,kappa,d,s", [(2, 3.0, 1.7, 0.8 - 0.3j), (3, 2.0, 0.9, -1.1 + 0.4j),
+                                           (2, 10.0, 0.25, 2.0 + 1.0j)])
+def test_condition_number_two_point_bodies_closed_form(dim, kappa, d, s):
+    """Two one-point bodies a distance d apart with S = [s]: I + S G_hat = [[1, c], [c, 1]],
+    c = s phi(d), a normal matrix with eigenvalues 1 +- c, so K = max |1 +- c| / min |1 +- c|."""
+    sc = _one_point_scene(dim, kappa, [[0.0] * dim, [d] + [0.0] * (dim - 1)])
+    xh, ptr, bo = gs.pack(sc)
+    K = gs.condition_number(sc, [np.array([[s]])], xh, ptr, bo)
+    r = float(d)
+    phi = (0.25j * complex(mpmath.hankel1(0, kappa * r)) if dim == 2
+           else complex(mpmath.exp(1j * kappa * r)) / (4.0 * np.pi * r))
+    c = s * phi
+    a, b = abs(1 + c), abs(1 - c)
+    assert abs(K - max(a, b) / min(a, b)) < 1e-12 * max(a, b) / min(a, b)
+
+
+def test_condition_number_three_point_bodies_in_extended_precision():
+    """Three one-point bodies on a line with S = [s] (I + S G_hat is no longer normal): K against the
+    square root of the extreme eigenvalues of M^H M, with M formed entry by entry from mpmath's
+    Hankel function and the eigenvalues taken by mpmath in extended precision."""
+    kappa, s = 4.0, 0.9 + 0.2j
+    sc = _one_point_scene(2, kappa, [[0.0, 0.0], [0.8, 0.0], [1.9, 0.0]])
+    xh, ptr, bo = gs.pack(sc)
+    K = gs.condition_number(sc, [np.array([[s]])], xh, ptr, bo)
+    M = np.eye(3, dtype=complex)
+    for i in range(3):
+        for j in range(3):
+            if i != j:
+                M[i, j] = s * 0.25j * complex(mpmath.hankel1(0, kappa * abs(xh[i, 0] - xh[j, 0])))
+    # singular values from the eigenvalues of M^H M, by mpmath in extended precision
+    ev = mpmath.eigh(mpmath.matrix((M.conj().T @ M).tolist()), eigvals_only=True)
+    ev = sorted(float(mpmath.re(e)) for e in ev)
+    assert K >= 1.0
+    assert abs(K - np.sqrt(ev[-1] / ev[0])) < 1e-10 * K

@@ -14,6 +14,7 @@ from .shapes import (  # noqa: F401
     ellipse2d,
     teardrop2d,
     cshape2d,
+    rod2d,
     kite2d,
     sphere3d,
     ellipsoid3d,

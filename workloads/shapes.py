@@ -318,6 +318,63 @@ def cshape2d(bounding=0.65, base_per_edge=4, levels=8, q=16, d_frac=0.5, k=128, 
                   vertices=raw * scale))
 
 
+def _rod_pieces(a, r):
+    """The four pieces of a rod (a 2a x 2r rectangle with semicircular caps of radius r),
+    counter-clockwise: each maps s in [0, 1] to (points, inward unit normals), with its length."""
+    def bottom(s):
+        pts = np.stack([-a + 2.0 * a * s, np.full_like(s, -r)], axis=-1)
+        return pts, np.tile([0.0, 1.0], (s.size, 1))
+
+    def top(s):
+        pts = np.stack([a - 2.0 * a * s, np.full_like(s, r)], axis=-1)
+        return pts, np.tile([0.0, -1.0], (s.size, 1))
+
+    def cap(cx, th0):
+        def f(s):
+            th = th0 + np.pi * s
+            out = np.stack([np.cos(th), np.sin(th)], axis=-1)
+            return np.array([cx, 0.0])[None, :] + r * out, -out
+        return f
+
+    return [(bottom, 2.0 * a), (cap(a, -0.5 * np.pi), np.pi * r), (top, 2.0 * a), (cap(-a, 0.5 * np.pi), np.pi * r)]
+
+
+def rod2d(bounding=0.65, aspect=6.0, base_per_side=8, base_per_cap=4, levels=6, q=16, d_frac=0.5, k=128,
+          rho_eq=0.70, r_psi=0.75, p=None):
+    """A rod: a thin rectangle with semicircular caps (Sec. 5.1 Example 4), length 2 bounding and
+    thickness 2 bounding / aspect.  The curvature jumps where the caps meet the sides, so every
+    piece is split into Gauss-Legendre panels refined dyadically toward both of its ends, with q
+    collocation points and q/2 MFS sources per panel, the sources offset inward by d_frac times the
+    panel length (less than the cap radius)."""
+    r = bounding / aspect
+    a = bounding - r
+    xq, _ = np.polynomial.legendre.leggauss(q)
+    xs, _ = np.polynomial.legendre.leggauss(q // 2)
+    col, src = [], []
+    for piece, length in _rod_pieces(a, r):
+        base = base_per_side if piece.__name__ in ("bottom", "top") else base_per_cap
+        h = 1.0 / base
+        brk = [0.0] + [h / 2.0 ** l for l in range(levels, 0, -1)]
+        brk += list(np.linspace(h, 1.0 - h, base - 1))
+        brk += [1.0 - h / 2.0 ** l for l in range(1, levels + 1)] + [1.0]
+        brk = np.array(sorted(set(brk)))
+        for s0, s1 in zip(brk[:-1], brk[1:]):
+            mid, half = 0.5 * (s0 + s1), 0.5 * (s1 - s0)
+            plen = 2.0 * half * length
+            pc, _ = piece(mid + half * xq)
+            ps, nin = piece(mid + half * xs)
+            col.append(pc)
+            src.append(ps + min(d_frac * plen, 0.5 * r) * nin)
+    colloc, src = np.concatenate(col), np.concatenate(src)
+    m = colloc.shape[0]
+    return ShapeDiscretisation(
+        name="rod", dim=2, colloc=colloc, src=src, proxy=circle_points(p if p is not None else m + 1, r_psi),
+        eqpts=circle_points(k, rho_eq), bounding_radius=bounding, proxy_radius=r_psi,
+        meta=dict(kind="rod", half_length=a, radius=r, base_per_side=base_per_side, base_per_cap=base_per_cap,
+                  levels=levels, q=q, d_frac=d_frac,
+                  junctions=np.array([[-a, -r], [a, -r], [a, r], [-a, r]])))
+
+
 def torus3d(R0=0.7, a=0.3, n_u=40, n_v=20, src_frac=0.3, k=400, rho_eq=None, p=900, r_psi=None):
     """Torus ((R0 + a cos v) cos u, (R0 + a cos v) sin u, a sin v) on a tensor grid in (u, v)
     (Sec. 3.4): n_u x n_v collocation points, (n_u/2) x (n_v/2) MFS sources (n = m/4) on the
