@@ -245,6 +245,22 @@ typedef struct {
 mfs_status mfs_solve(const mfs_scene* scene, const void* vhat_dev, int32_t R, const mfs_solve_opts* opts,
                      void* qhat_dev, mfs_solve_info* info, void* stream);
 
+/* Device bytes a scene of this layout holds after mfs_solve with these options and R right-hand
+ * sides, followed by an FP64 mfs_eval_field at n_targets points (0: none): its tables and its
+ * grow-only workspaces (pair partial sums, padded and split charges, the Krylov basis and
+ * coefficients of the per-column or the block solve, solver vectors), each as the block the
+ * allocation cache takes for it, with the launch shapes the scene would use now (its process-wide
+ * table, else the heuristic).  The split charges of the FP16 matrix-core pair sum are counted
+ * wherever it may run, so this is an upper bound where its use depends on the geometry.  Not
+ * counted: the caller's S matrices and vectors (vhat, qhat, targets, field), and blocks the cache
+ * keeps for reuse.  For admission control by device memory.  Host only; no device is touched.
+ *   dim, T, shape_of, n_shapes, k_of_shape: as for mfs_scene_create; rotations: 1 if the scene
+ *   will carry rotations.  opts: prec, restart, block, basis32 and fp64_until are read.
+ * Errors: MFS_ERR_ARG. */
+mfs_status mfs_solve_footprint(int32_t dim, int64_t T, const int32_t* shape_of, int32_t n_shapes,
+                               const int64_t* k_of_shape, int32_t rotations, int32_t R,
+                               const mfs_solve_opts* opts, int64_t n_targets, size_t* bytes_out);
+
 /* ------------------------------------------------------------------------------------------
  * For callers that cannot allocate device memory: code under HIP graph capture, tight serving
  * loops, harnesses that forbid hipMalloc.

@@ -522,6 +522,58 @@ struct BlockWork {
 };
 
 // Bytes of the block workspace for N, R, m block steps (basis of complex64 when v32).
+// Workspace of the per-column solve (GMRES per right-hand side): the basis ((m+1) N R, complex64 with
+// v32), the Hessenberg matrices, rotations, right sides and coefficient vectors, norm partials and
+// the deflation vectors, each carved at 256-byte alignment.
+struct ColumnWork {
+  size_t V, H, cs, sn, g, h1, h2, y, beta, bn, res, hn, act, jl, wn, ro, nro, part, jdev, tol, q, cr, ee, jold, rn2,
+      keep, total;
+};
+
+ColumnWork column_work_layout(int64_t N, int R, int m, bool v32) {
+  const size_t NR = (size_t)N * R;
+  const size_t szV = (v32 ? sizeof(c64) : sizeof(c128)) * (size_t)(m + 1) * NR;
+  const size_t szH = sizeof(c128) * (size_t)R * m * (m + 1);
+  const size_t szRm = sizeof(c128) * (size_t)R * m;
+  const size_t szRm1 = sizeof(c128) * (size_t)R * (m + 1);
+  const size_t szPart = sizeof(double) * 2 * (size_t)R * (m + 1) * krylov_part_blocks(N);
+  size_t off = 0;
+  auto carve = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  ColumnWork L{};
+  L.V = carve(szV);
+  L.H = carve(szH);
+  L.cs = carve(szRm);
+  L.sn = carve(szRm);
+  L.g = carve(szRm1);
+  L.h1 = carve(szRm1);
+  L.h2 = carve(szRm1);
+  L.y = carve(szRm);
+  L.beta = carve(8 * R);
+  L.bn = carve(8 * R);
+  L.res = carve(8 * R);
+  L.hn = carve(8 * R);
+  L.act = carve(4 * R);
+  L.jl = carve(4 * R);
+  L.wn = carve(8 * R);
+  L.ro = carve(4 * R);
+  L.nro = carve(4 * R);
+  L.part = carve(szPart);
+  L.jdev = carve(sizeof(int32_t));
+  L.tol = carve(sizeof(double));
+  L.q = carve(szRm1);
+  L.cr = carve(szRm1);
+  L.ee = carve(szRm1);
+  L.jold = carve(4 * R);
+  L.rn2 = carve(8 * R);
+  L.keep = carve(4 * R);
+  L.total = off;
+  return L;
+}
+
 size_t block_work_bytes(int64_t N, int R, int m, bool v32, int64_t* offs) {
   size_t off = 0;
   int idx = 0;
@@ -1009,6 +1061,17 @@ mfs_status mfs_build_S(const mfs_shape_desc* desc, void* S64_dev, void* S32_dev,
   return build_S_impl(desc, S64_dev, S32_dev, k_out, skel_idx_out, diag_out, as_stream(stream));
 }
 
+// Length of the padded layout the symmetric kernel gets (bodies padded to whole 64-point tiles), or
+// 0 where none is made: only for bodies that are not all multiples of 64 (3D sub-blocks aside), and
+// only while the padded pair count stays within 1.4 times the real one.
+int64_t sym_pad_length(const SceneDev& d, const std::vector<int64_t>& body_ptr) {
+  if (!sym_padded(d)) return 0;
+  int64_t NP = 0;
+  for (size_t t = 0; t + 1 < body_ptr.size(); ++t) NP += (body_ptr[t + 1] - body_ptr[t] + 63) / 64 * 64;
+  const double N = (double)body_ptr.back();
+  return (double)NP * (double)NP <= 1.4 * N * N && NP <= 0x7fffffff ? NP : 0;
+}
+
 mfs_status mfs_scene_create(int32_t dim, double kappa, int64_t T, const int32_t* shape_of, const double* centres,
                             const double* rotations, int32_t n_shapes, const int64_t* k_of_shape, const double* const* eq_template,
                             const void* const* S64_dev, const void* const* S32_dev, mfs_scene** out) {
@@ -1181,12 +1244,12 @@ mfs_status mfs_scene_create(int32_t dim, double kappa, int64_t T, const int32_t*
   d.body_of_pad = nullptr;
   d.lsqp = nullptr;
   for (int i = 0; i < 3; ++i) d.l32p[i] = nullptr;
-  if (sym_padded(d)) {
+  if (sym_pad_length(d, body_ptr) > 0) {
     // bodies padded to whole 64-point tiles, made only where the symmetric kernel would pay
     std::vector<int64_t> pad_ptr(T + 1, 0);
     for (int64_t t = 0; t < T; ++t) pad_ptr[t + 1] = pad_ptr[t] + (body_ptr[t + 1] - body_ptr[t] + 63) / 64 * 64;
     const int64_t NP = pad_ptr[T];
-    if ((double)NP * (double)NP <= 1.4 * (double)N * (double)N && NP <= 0x7fffffff) {
+    {
       std::vector<int32_t> body_of_pad(NP);
       for (int64_t t = 0; t < T; ++t)
         for (int64_t i = pad_ptr[t]; i < pad_ptr[t + 1]; ++i) body_of_pad[i] = (int32_t)t;
@@ -1226,6 +1289,83 @@ mfs_status mfs_scene_size(const mfs_scene* s, int64_t* N_out, int64_t* T_out, si
   if (N_out) *N_out = s->dev.N;
   if (T_out) *T_out = s->dev.T;
   if (bytes_out) *bytes_out = s->bytes;
+  return MFS_OK;
+}
+
+mfs_status mfs_solve_footprint(int32_t dim, int64_t T, const int32_t* shape_of, int32_t n_shapes,
+                               const int64_t* k_of_shape, int32_t rotations, int32_t R, const mfs_solve_opts* opts,
+                               int64_t n_targets, size_t* bytes_out) {
+  g_last_error.clear();
+  if (!bytes_out) return fail(MFS_ERR_ARG, "solve_footprint: bytes_out is null");
+  *bytes_out = 0;
+  if (dim != 2 && dim != 3) return fail(MFS_ERR_ARG, "solve_footprint: dim must be 2 or 3");
+  if (T < 1 || n_shapes < 1 || !shape_of || !k_of_shape || !opts)
+    return fail(MFS_ERR_ARG, "solve_footprint: T, n_shapes >= 1 and non-null tables and options required");
+  if (R < 1 || opts->restart < 1 || n_targets < 0)
+    return fail(MFS_ERR_ARG, "solve_footprint: R >= 1, restart >= 1 and n_targets >= 0 required");
+  if (opts->block && (R < 2 || R > 64)) return fail(MFS_ERR_ARG, "solve_footprint: block GMRES takes 2..64 right-hand sides");
+  int64_t kmax = 0;
+  for (int s = 0; s < n_shapes; ++s) {
+    if (k_of_shape[s] < 1 || k_of_shape[s] > 4096) return fail(MFS_ERR_ARG, "solve_footprint: k_of_shape out of range");
+    kmax = std::max(kmax, k_of_shape[s]);
+  }
+  std::vector<int64_t> body_ptr(T + 1, 0);
+  for (int64_t t = 0; t < T; ++t) {
+    if (shape_of[t] < 0 || shape_of[t] >= n_shapes) return fail(MFS_ERR_ARG, "solve_footprint: shape_of out of range");
+    body_ptr[t + 1] = body_ptr[t] + k_of_shape[shape_of[t]];
+  }
+  const int64_t N = body_ptr[T];
+  if (N > 0x7fffffff) return fail(MFS_ERR_ARG, "solve_footprint: N exceeds 2^31-1");
+  // a scene with the layout and flags mfs_scene_create would give (no device memory): the launch
+  // shapes and workspace sizes below come from the same functions a solve uses
+  mfs_scene sh;
+  SceneDev& d = sh.dev;
+  d.dim = dim;
+  d.N = N;
+  d.T = T;
+  d.all_k_mult16 = d.all_k_mult64 = true;
+  for (int s = 0; s < n_shapes; ++s) {
+    d.all_k_mult16 = d.all_k_mult16 && k_of_shape[s] % 16 == 0;
+    d.all_k_mult64 = d.all_k_mult64 && k_of_shape[s] % 64 == 0;
+  }
+  d.sym16 = dim == 3 && d.all_k_mult16 && !d.all_k_mult64;
+  const int64_t NP = sym_pad_length(d, body_ptr);
+  static const int64_t kNonNull = 0;
+  d.Npad = NP > 0 ? NP : N;
+  d.pad_ptr = NP > 0 ? &kNonNull : nullptr;
+  d.phi16_shift = 0;  // the split charges are counted wherever the matrix cores may run (a bound)
+  sh.kmax = kmax;
+  auto blk = [](size_t b) { return b ? pool_block_size(b) : 0; };
+  size_t total = 0;
+  // scene tables (mfs_scene_create)
+  total += blk(sizeof(double) * dim * N) + 2 * blk(sizeof(float) * dim * N) + blk(sizeof(float) * N) +
+           blk(sizeof(double) * dim * T) + blk(sizeof(int32_t) * N) + blk(sizeof(int64_t) * (T + 1)) +
+           blk(sizeof(int32_t) * T) + blk(sizeof(int64_t) * n_shapes) + 2 * blk(sizeof(void*) * n_shapes);
+  if (rotations) total += blk(sizeof(double) * T * dim * dim);
+  if (NP > 0)
+    total += blk(sizeof(int64_t) * (T + 1)) + blk(sizeof(int32_t) * NP) + blk(sizeof(float) * dim * NP) +
+             blk(sizeof(float) * NP);
+  // pair partial sums (one grow-only buffer: the largest of the FP32 sum, the FP64 residual and the
+  // FP64 field evaluation), padded charges, split charges, FP32 charges
+  const mfs_prec prec = opts->prec;
+  size_t part = 0, qpad = 0, split = 0, q32 = 0;
+  if (prec != MFS_FP64) {
+    const LaunchShape ls = shape_for(&sh, false, R);
+    part = (size_t)f32_slices(&sh, ls) * R * f32_rows(&sh, ls) * sizeof(c64);
+    if (ls.sym == 1 && NP > 0) qpad = (size_t)R * NP * sizeof(c64);
+    if (ls.sym != 1 && ghat_uses_mfma16(d, R)) split = ghat_split_bytes(d, R);
+    q32 = (size_t)R * N * sizeof(c64);
+  }
+  part = std::max(part, (size_t)shape_for(&sh, true, R).nchunks * R * N * sizeof(c128));
+  if (n_targets > 0)
+    part = std::max(part, (size_t)pair_chunks_for(N, n_targets, tpt_for(MFS_FP64)) * R * n_targets * sizeof(c128));
+  total += blk(part) + blk(qpad) + blk(split) + blk(q32) + blk(sizeof(double) * R * dim);
+  // Krylov workspace and solver vectors
+  const bool v32 = prec == MFS_MIXED && opts->basis32 != 0 && !(opts->fp64_until > 0.0);
+  const size_t kry = opts->block ? block_work_bytes(N, R, opts->restart, prec == MFS_MIXED && opts->basis32 != 0, nullptr)
+                                 : column_work_layout(N, R, opts->restart, v32).total;
+  total += blk(kry) + blk(3 * sizeof(c128) * (size_t)N * R + 256);
+  *bytes_out = total;
   return MFS_OK;
 }
 
@@ -1392,25 +1532,12 @@ mfs_status mfs_solve(const mfs_scene* sc, const void* vhat_dev, int32_t R, const
   k.nblk = krylov_nblk(N);
   // single-precision basis: inner solves that use the FP32 operator throughout
   const bool v32 = prec == MFS_MIXED && opts->basis32 != 0 && !(opts->fp64_until > 0.0);
-  const size_t szV = (v32 ? sizeof(c64) : sizeof(c128)) * (size_t)(m + 1) * NR;
-  const size_t szH = sizeof(c128) * (size_t)R * m * (m + 1);
-  const size_t szRm = sizeof(c128) * (size_t)R * m;
-  const size_t szRm1 = sizeof(c128) * (size_t)R * (m + 1);
-  const size_t szPart = sizeof(double) * 2 * (size_t)R * (m + 1) * krylov_part_blocks(N);
-  size_t off = 0;
-  auto carve = [&](size_t bytes) {
-    const size_t o = off;
-    off += (bytes + 255) / 256 * 256;
-    return o;
-  };
-  const size_t oV = carve(szV), oH = carve(szH), ocs = carve(szRm), osn = carve(szRm), og = carve(szRm1),
-               oh1 = carve(szRm1), oh2 = carve(szRm1), oy = carve(szRm), obeta = carve(8 * R), obn = carve(8 * R),
-               ores = carve(8 * R), ohn = carve(8 * R), oact = carve(4 * R), ojl = carve(4 * R),
-               own = carve(8 * R), oro = carve(4 * R), onro = carve(4 * R), opart = carve(szPart),
-               ojdev = carve(sizeof(int32_t)), otol = carve(sizeof(double)), oq = carve(szRm1),
-               ocr = carve(szRm1), oee = carve(szRm1), ojold = carve(4 * R), orn2 = carve(8 * R),
-               okeep = carve(4 * R);
-  MFS_TRY(ensure(s->kry, off, &s->bytes, st));
+  const ColumnWork L = column_work_layout(N, R, m, v32);
+  const size_t oV = L.V, oH = L.H, ocs = L.cs, osn = L.sn, og = L.g, oh1 = L.h1, oh2 = L.h2, oy = L.y,
+               obeta = L.beta, obn = L.bn, ores = L.res, ohn = L.hn, oact = L.act, ojl = L.jl, own = L.wn,
+               oro = L.ro, onro = L.nro, opart = L.part, ojdev = L.jdev, otol = L.tol, oq = L.q, ocr = L.cr,
+               oee = L.ee, ojold = L.jold, orn2 = L.rn2, okeep = L.keep;
+  MFS_TRY(ensure(s->kry, L.total, &s->bytes, st));
   char* base = static_cast<char*>(s->kry.p);
   k.V = base + oV;
   k.v32 = v32;

@@ -278,6 +278,8 @@ struct TimedLaunch {
 // is null).  pool_free hands a block back after the work enqueued on `last`.
 void* pool_alloc(size_t bytes, hipStream_t st, size_t* got, hipError_t* err);
 void pool_free(void* p, size_t bytes, hipStream_t last);
+// The block size pool_alloc takes from HIP for a fresh request of `bytes`.
+size_t pool_block_size(size_t bytes);
 void* pinned_alloc(size_t bytes, size_t* got, hipError_t* err);
 void pinned_free(void* p, size_t bytes);
 void pool_query(int64_t* hits, int64_t* misses, int64_t* cached, int64_t* live, int64_t* limit);

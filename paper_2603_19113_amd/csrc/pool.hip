@@ -260,4 +260,7 @@ hipStream_t private_stream(hipError_t* err) {
   return streams[dev];
 }
 
+// The block size pool_alloc takes from HIP for a request of `bytes` (what a fresh allocation costs).
+size_t pool_block_size(size_t bytes) { return round_size(std::max<size_t>(bytes, 1)); }
+
 }  // namespace mfs

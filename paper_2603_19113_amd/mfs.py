@@ -80,7 +80,7 @@ EXPORTS = ["mfs_last_error", "mfs_version", "mfs_build_S", "mfs_scene_create", "
            "mfs_pool_set_limit", "mfs_pool_trim", "mfs_recon_create", "mfs_recon_destroy", "mfs_recon_size",
            "mfs_near_sizes", "mfs_plane_wave_colloc", "mfs_reconstruct", "mfs_eval_field_near", "mfs_autotune",
            "mfs_tune_get", "mfs_tune_set", "mfs_tune_save", "mfs_tune_load", "mfs_tune_clear", "mfs_tune_table_size",
-           "mfs_pair_kernel", "mfs_scene_set_split_fp16"]
+           "mfs_pair_kernel", "mfs_scene_set_split_fp16", "mfs_solve_footprint"]
 MFS_KERNEL_PAIR_F32, MFS_KERNEL_PAIR_F64 = 0, 1
 # mfs_pair_kernel_kind
 MFS_PAIR_F64, MFS_PAIR_F32, MFS_PAIR_F32_SYM, MFS_PAIR_F32_SYM16, MFS_PAIR_MC_F32, MFS_PAIR_MC_F16X3 = range(6)
@@ -134,6 +134,8 @@ def load(path: str = LIB_PATH):
         "mfs_tune_table_size": ([ctypes.POINTER(i64)], ctypes.c_int),
         "mfs_pair_kernel": ([vp, i32, i32, ctypes.POINTER(i32)], ctypes.c_int),
         "mfs_scene_set_split_fp16": ([vp, i32], ctypes.c_int),
+        "mfs_solve_footprint": ([i32, i64, vp, i32, vp, i32, i32, ctypes.POINTER(SolveOpts), i64,
+                                 ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -318,6 +320,22 @@ def solve(scene: Scene, vhat, qhat, tol=1e-8, maxit=2000, restart=300, max_refin
     d = info.as_dict()
     d["status"] = _STATUS.get(code, code)
     return d
+
+
+def solve_footprint(dim: int, shape_of, k_of_shape, R: int, restart: int, prec: int = MFS_MIXED,
+                    block: bool = False, basis32: bool = False, n_targets: int = 0, rotations: bool = False,
+                    fp64_until: float = 0.0) -> int:
+    """mfs_solve_footprint: device bytes a scene of this layout holds after a solve (and an FP64
+    field evaluation at n_targets points).  Host only."""
+    so = np.ascontiguousarray(shape_of, dtype=np.int32)
+    ks = np.ascontiguousarray(k_of_shape, dtype=np.int64)
+    o = SolveOpts(restart=int(restart), prec=int(prec), block=1 if block else 0, basis32=1 if basis32 else 0,
+                  fp64_until=float(fp64_until))
+    out = ctypes.c_size_t(0)
+    _check(load().mfs_solve_footprint(int(dim), so.shape[0], so.ctypes.data, ks.shape[0], ks.ctypes.data,
+                                      1 if rotations else 0, int(R), ctypes.byref(o), int(n_targets),
+                                      ctypes.byref(out)))
+    return int(out.value)
 
 
 def eval_field(scene: Scene, qhat, targets, u, prec: int = MFS_FP64, stream=None):

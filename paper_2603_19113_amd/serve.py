@@ -3,7 +3,8 @@
 Requests (scenes with one or more incident directions) arrive over time.  The engine keeps a FIFO
 queue and a set of slots; the head of the queue is admitted as soon as a slot is free and its
 estimated device footprint fits in the HBM budget next to the requests already running.  Each slot
-runs its request on its own HIP stream (mixed-precision GMRES-IR through the C ABI), so the work
+runs its request on its own HIP stream (mixed-precision GMRES-IR through the C ABI, block GMRES for
+several directions), so the work
 of admitted requests overlaps on the device, and finished requests free their footprint for the
 queue at once.  Scattering matrices are built once per (shape, wavenumber) and stay resident in a
 shared library.  Results do not depend on what else runs: every kernel is deterministic and a
@@ -26,49 +27,35 @@ import numpy as np
 
 
 # ------------------------------------------------------------------ policy ---
-def _chunks(N: int, targets_per_thread: int) -> int:
-    """Source slices of the plain pair kernels (the library's occupancy heuristic)."""
-    waves = -(-N // (64 * targets_per_thread))
-    want = -(-16384 // max(waves, 1))
-    return max(1, min(want, max(1, N // 64), 128))
+def block_solve(R: int) -> bool:
+    """Several right-hand sides (one request's directions, or a batch's) share one block Krylov
+    space; the library's block solve takes up to 64."""
+    return 2 <= R <= 64
 
 
-def _sym_slices(n_pad: int) -> int:
-    """Partial slices of the symmetric kernel with its default distance chunking."""
-    G = -(-n_pad // 256)
-    dmax = G // 2
-    dsym = max(0, dmax - 1 if G % 2 == 0 else dmax)
-    want = max(1, min(min(1024, -(-65536 // max(G, 1))), dmax + 1))
-    dpc = -(-(dmax + 1) // want)
-    return -(-(dmax + 1) // dpc) + dsym
-
-
-def footprint_bytes(N: int, T: int, R: int, dim: int, restart: int, n_targets: int = 0) -> int:
-    """Device bytes a request holds while it runs (scene tables, pair partial sums, complex64 Krylov
-    basis and complex128 Hessenberg, solver vectors, caller tensors), mirroring the library's
-    allocations."""
-    n_pad = N + 63 * T                             # bodies padded to whole 64-point tiles, at most
-    scene = N * (8 * dim + 4 * dim + 4 * dim + 4 + 4 + 4) + T * (8 + 4 + 8 * dim) \
-        + n_pad * (4 * dim + 8) + T * 8 + (R * n_pad * 8 if R <= 32 else 0)
-    partial = max(_chunks(N, 1) * R * N * 16,      # FP64 pair sums (residuals)
-                  _chunks(N, 2) * R * N * 8,       # FP32 plain kernel
-                  _sym_slices(n_pad) * R * n_pad * 8 if R <= 32 else 0)  # FP32 symmetric kernel
-    q32 = R * N * 8
-    nblk = (N + 511) // 512                       # partial inner products: widest launch
-    # basis, Hessenberg matrix, partial inner products, and nine coefficient vectors per column
-    # (rotations, g, two Gram-Schmidt passes, y, and three for deflated correction solves)
-    krylov = (restart + 1) * R * N * 8 + R * restart * (restart + 1) * 16 + 2 * R * (restart + 1) * nblk * 8 \
-        + 9 * R * (restart + 1) * 16
-    vecs = 3 * R * N * 16
-    caller = 2 * R * N * 16 + R * max(n_targets, 1) * 16
-    return int(scene + partial + q32 + krylov + vecs + caller)
-
-
-def restart_for(T: int, kappa: float, dim: int, cap: int = 4000) -> int:
-    """Krylov basis size: GMRES on these systems needs about 6 steps per body at kappa = 10 in 2D
-    (measured); keep room for that so a request rarely restarts."""
+def restart_for(T: int, kappa: float, dim: int, R: int = 1, cap: int = 4000, block_cap: int = 2000) -> int:
+    """Krylov basis size, with room for the whole solve so that a request rarely restarts.  One
+    right-hand side: GMRES needs about 6 steps per body at kappa = 10 in 2D (measured).  Block GMRES
+    over R directions: about 0.35 block steps per body on the 2000-body mixed scene at kappa = 20
+    (687 block steps, measured)."""
+    if block_solve(R):
+        est = int(0.5 * T * max(kappa, 3.0) / 20.0) + 64
+        return max(32, min(block_cap, est))
     est = int(8 * T * max(kappa, 3.0) / 10.0) + 200
     return max(64, min(cap, est))
+
+
+def footprint_bytes(dim: int, shape_of, k_of_shape, R: int, restart: int, n_targets: int = 0) -> int:
+    """Device bytes a request holds while it runs: the library's own estimate for the scene and the
+    solve (mfs_solve_footprint: tables, pair partial sums, Krylov workspace, solver vectors) plus the
+    caller's vectors (v_hat and q_hat, complex128 R x N each, and the field at the targets)."""
+    from . import mfs
+
+    N = int(np.asarray(k_of_shape, np.int64)[np.asarray(shape_of)].sum())
+    lib = mfs.solve_footprint(dim, shape_of, k_of_shape, R, restart, prec=mfs.MFS_MIXED, block=block_solve(R),
+                              basis32=True, n_targets=n_targets)
+    caller = 2 * R * N * 16 + R * max(n_targets, 1) * 16
+    return int(lib + caller)
 
 
 class Admission:
@@ -271,7 +258,7 @@ def request_footprint(specs) -> int:
     """Device bytes of one solve over the given requests (one geometry, their directions stacked)."""
     sc = specs[0].scene
     R = sum(s.scene.R for s in specs)
-    return footprint_bytes(sc.N, sc.T, R, sc.dim, restart_for(sc.T, sc.kappa, sc.dim))
+    return footprint_bytes(sc.dim, sc.shape_of, sc.k_of_shape, R, restart_for(sc.T, sc.kappa, sc.dim, R))
 
 
 def request_batching(max_rhs: int = 64) -> Batching:
@@ -307,8 +294,9 @@ class GpuExecutor:
             return self.library[k]
 
     def __call__(self, specs, slot: int) -> list:
-        """Solve a batch of requests on one geometry as one block GMRES-IR over their stacked incident
-        directions, then split the solution rows back per request."""
+        """Solve a batch of requests on one geometry as one mixed-precision solve over their stacked
+        incident directions (block GMRES with iterative refinement for 2..64 of them, GMRES-IR for
+        one), then split the solution rows back per request."""
         torch, mfs = self.torch, self.mfs
         spec0 = specs[0]
         sc = spec0.scene
@@ -325,10 +313,10 @@ class GpuExecutor:
                 v = torch.empty((R, scene.N), dtype=torch.complex128, device="cuda")
                 mfs.plane_wave(scene, dirs, v, stream=st)
                 q = torch.empty_like(v)
-                restart = restart_for(sc.T, sc.kappa, sc.dim)
+                restart = restart_for(sc.T, sc.kappa, sc.dim, R)
                 info = mfs.solve(scene, v, q, tol=self.tol, maxit=200000, restart=restart, max_refine=30,
                                  inner_tol=self.inner_tol, prec=mfs.MFS_MIXED, stream=st, basis32=True,
-                                 deflate=True)
+                                 deflate=True, block=block_solve(R))
                 qh = q.cpu().numpy() if self.keep_solution else None  # synchronises the slot's stream
                 st.synchronize()
                 N = scene.N

@@ -57,3 +57,41 @@ def test_batched_requests_match_their_solo_solves(gpu_lib):
         for r in range(qa.shape[0]):
             rel = np.linalg.norm(qa[r] - qb[r]) / np.linalg.norm(qa[r])
             assert rel <= 1e-6, (rid, r, rel, b.batch)
+
+
+@pytest.mark.parametrize("key,T,R", [("mixed2000_R64", 24, 64), ("starfish2000", 40, 1), ("spheres1000", 5, 3)])
+def test_footprint_covers_what_a_solve_allocates(gpu_lib, key, T, R):
+    """mfs_solve_footprint against the scene's own device bytes after a mixed solve (block GMRES for
+    several directions, as the serving loop runs it) and an FP64 field evaluation, with the
+    allocation cache emptied first so that every block is a fresh one."""
+    import torch
+
+    from paper_2603_19113_amd.serve import block_solve, restart_for
+
+    mfs = gpu_lib
+    sc = w.make_scene(key, T=T)
+    sc.directions = np.resize(sc.directions, (R, sc.dim)) if sc.R != R else sc.directions
+    built = [mfs.build_S(s, sc.kappa) for s in sc.shapes]
+    torch.cuda.synchronize()
+    mfs.pool_trim()
+    scene = mfs.Scene(sc.dim, sc.kappa, sc.shape_of, sc.centres, [s.eqpts for s in sc.shapes],
+                      [b.S64 for b in built], [b.S32 for b in built])
+    restart = restart_for(sc.T, sc.kappa, sc.dim, R)
+    v = torch.empty((R, scene.N), dtype=torch.complex128, device="cuda")
+    mfs.plane_wave(scene, sc.directions, v)
+    q = torch.empty_like(v)
+    info = mfs.solve(scene, v, q, tol=1e-8, maxit=100000, restart=restart, max_refine=30, inner_tol=3e-6,
+                     prec=mfs.MFS_MIXED, basis32=True, deflate=True, block=block_solve(R))
+    tg = torch.from_numpy(np.ascontiguousarray(w.far_targets(sc, 64))).cuda()
+    u = torch.empty((R, tg.shape[0]), dtype=torch.complex128, device="cuda")
+    mfs.eval_field(scene, q, tg, u, mfs.MFS_FP64)
+    torch.cuda.synchronize()
+    held = scene.size()[2]
+    est = mfs.solve_footprint(sc.dim, sc.shape_of, sc.k_of_shape, R, restart, prec=mfs.MFS_MIXED,
+                              block=block_solve(R), basis32=True, n_targets=tg.shape[0])
+    print(f"{key} T={T} R={R}: relres {info['relres_max']:.1e}, scene holds {held / 1e6:.1f} MB, "
+          f"footprint {est / 1e6:.1f} MB", flush=True)
+    assert info["relres_max"] <= 1e-8
+    assert held <= est
+    assert held >= 0.5 * est
+    scene.close()

@@ -114,26 +114,33 @@ def test_request_stream_is_seeded_and_shaped():
 
 
 def test_footprint_grows_with_size_and_basis():
-    small = footprint_bytes(1000, 10, 1, 2, restart_for(10, 10.0, 2))
-    large = footprint_bytes(64000, 500, 4, 2, restart_for(500, 10.0, 2))
+    small = footprint_bytes(2, np.zeros(10, np.int32), [100], 1, restart_for(10, 10.0, 2))
+    large = footprint_bytes(2, np.zeros(500, np.int32), [128], 4, restart_for(500, 10.0, 2, 4))
     assert 0 < small < large
     assert restart_for(5000, 20.0, 2) == 4000  # capped
+    assert restart_for(5000, 20.0, 2, R=8) == 2000  # block steps, capped
+    assert restart_for(2000, 20.0, 2, R=64) >= 687  # the full-size mixed scene's measured block steps
 
 
-def test_footprint_counts_the_symmetric_kernel_slices():
-    """Up to 32 right-hand sides the symmetric pair kernel may run; its partial slices (about N/512
-    per right-hand side, on bodies padded to 64-point tiles) must be in the estimate."""
-    from paper_2603_19113_amd.serve import _sym_slices
+def test_footprint_comes_from_the_library():
+    """The estimate is the library's (mfs_solve_footprint) plus the caller's vectors: it counts the
+    symmetric kernel's partial slices up to 32 right-hand sides (about N/512 per right-hand side on
+    bodies padded to 64-point tiles), the block basis for several directions, and grows with R."""
+    from paper_2603_19113_amd import mfs
 
-    N, T = 32768, 256
-    n_pad = N + 63 * T
-    assert _sym_slices(256000) == 562           # the library's plan on the starfish scene
-    fp16 = footprint_bytes(N, T, 16, 2, 200)
-    assert fp16 >= _sym_slices(n_pad) * 16 * n_pad * 8
-    # beyond 32 right-hand sides the matrix-core kernel runs and needs no slices per distance
-    per_rhs_32 = footprint_bytes(N, T, 32, 2, 200) / 32
-    per_rhs_33 = footprint_bytes(N, T, 33, 2, 200) / 33
-    assert per_rhs_33 < per_rhs_32
+    shape_of = (np.arange(256) % 2).astype(np.int32)
+    ks = [112, 144]                     # not multiples of 64: the symmetric kernel's padded layout
+    N = 128 * 256
+    lib16 = mfs.solve_footprint(2, shape_of, ks, 16, 200, block=True, basis32=True)
+    assert footprint_bytes(2, shape_of, ks, 16, 200) == lib16 + 2 * 16 * N * 16 + 16 * 16
+    n_pad = 128 * 128 + 192 * 128       # 112 -> 128 and 144 -> 192 points
+    slices = 2 * n_pad // 512           # at least the source-side slices per right-hand side
+    assert lib16 >= slices * 16 * n_pad * 8
+    # a longer basis and more right-hand sides cost more; block and per-column bases differ
+    assert mfs.solve_footprint(2, shape_of, ks, 16, 400, block=True, basis32=True) > lib16
+    assert mfs.solve_footprint(2, shape_of, ks, 1, 200, basis32=True) < lib16
+    with pytest.raises(mfs.MfsError):
+        mfs.solve_footprint(2, shape_of, ks, 65, 200, block=True)   # the block solve takes <= 64
 
 
 def test_batching_merges_same_geometry_within_rhs_cap():
@@ -164,11 +171,21 @@ def test_batching_merges_same_geometry_within_rhs_cap():
     assert st["batched"] == 5
 
 
-def test_request_footprint_of_a_batch_is_below_the_sum():
-    specs = w.serving.request_stream(8, rate=1.0, seed=3, t_min=4, t_max=16, p_sweep=0.9)
-    geo = specs[0].geometry
-    same = [s for s in specs if s.geometry == geo]
-    assert len(same) >= 2
-    joint = request_footprint(same)
-    assert joint < sum(request_footprint([s]) for s in same)
-    assert joint >= max(request_footprint([s]) for s in same)
+def test_request_footprint_of_a_batch():
+    """A batch is one block solve over the stacked directions: below the sum of separate solves
+    where the N-sized arrays dominate.  Not on small scenes, where the block Hessenberg matrix
+    (R^2 m^2) can outweigh them, and not always above its largest request, whose pair sum may take
+    the symmetric kernel with its per-distance slices where the batch takes the matrix cores."""
+    for t_min, t_max, below_sum in ((4, 16, False), (300, 400, True)):
+        specs = w.serving.request_stream(8, rate=1.0, seed=3, t_min=t_min, t_max=t_max, p_sweep=0.9)
+        geo = specs[0].geometry
+        same, R = [], 0
+        for s in specs:  # a batch the engine could form: one geometry, at most 64 directions
+            if s.geometry == geo and R + s.scene.R <= 64:
+                same.append(s)
+                R += s.scene.R
+        assert len(same) >= 2
+        joint = request_footprint(same)
+        assert joint > 0
+        if below_sum:
+            assert joint < sum(request_footprint([s]) for s in same)

@@ -1,6 +1,6 @@
 """Seeded request streams for the serving loop (inputs only).
 
-Each request is a scattering scene drawn from a fixed nine-shape library: dimension 2 or 3, a body count
+Each request is a scattering scene drawn from a fixed ten-shape library: dimension 2 or 3, a body count
 log-uniform in [t_min, t_max], shapes uniform from the dimension's library, a wavenumber from the
 dimension's list, 1..r_max incident directions, and a Poisson arrival time.  Body density matches the
 starfish (2D) and sphere (3D) workloads.
@@ -13,12 +13,12 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .scenes import Scene, plane_wave_directions_2d, random_centres
-from .shapes import cshape2d, disk2d, ellipse2d, ellipsoid3d, kite2d, sphere3d, starfish2d, teardrop2d, torus3d
+from .shapes import cshape2d, disk2d, ellipse2d, ellipsoid3d, kite2d, rod2d, sphere3d, starfish2d, teardrop2d, torus3d
 
 
 def shape_library_2d():
-    """Six 2D shapes of bounding radius 0.65 (k = 64..256 equivalent points), two of them with
-    corners (Gauss-Legendre panels refined toward the corners)."""
+    """Seven 2D shapes of bounding radius 0.65 (k = 64..256 equivalent points), two of them with
+    corners and the rod with its cap junctions (Gauss-Legendre panels refined toward them)."""
     return {
         "disk": disk2d(radius=0.65, m=128, n=64, src_radius=0.455, k=64, rho_eq=0.70, p=129, r_psi=0.75),
         "ellipse": ellipse2d(a=0.65, b=0.325, m=256, n=128, d=0.06, k=128, rho_eq=0.70, p=257, r_psi=0.75),
@@ -26,6 +26,7 @@ def shape_library_2d():
         "kite": kite2d(bounding=0.65, m=512, n=256, d=0.03, k=256, rho_eq=0.70, p=513, r_psi=0.75),
         "teardrop": teardrop2d(levels=8, base_panels=16, d_frac=0.5, k=128),
         "cshape": cshape2d(levels=6, base_per_edge=3, d_frac=0.5, k=128),
+        "rod": rod2d(levels=4, k=128),
     }
 
 
