@@ -182,8 +182,13 @@ def serve(args, w, torch) -> int:
     torch.cuda.synchronize()
     batching = None if args.no_batching else request_batching()
 
+    def done(t):
+        info = t.result["info"] if t.result else {}
+        log(f"[serve] request {t.rid} {'failed' if t.error else 'done'}: {t.finish - t.arrival:.2f} s "
+            f"(batch {t.batch}, relres {info.get('relres_max', float('nan')):.1e})")
+
     def run(stream, time_scale):
-        eng = Engine(ex, budget=budget, slots=args.slots, batching=batching)
+        eng = Engine(ex, budget=budget, slots=args.slots, batching=batching, on_done=done)
         t0 = time.perf_counter()
         tickets = replay(eng, stream, [request_footprint([s]) for s in stream], time_scale=time_scale)
         wall = time.perf_counter() - t0
@@ -208,7 +213,7 @@ def serve(args, w, torch) -> int:
            "capacity_per_s": capacity, "slots": args.slots, "batching": batching is not None,
            "hbm_budget_bytes": budget, "wall_s": wall, **st, "relres_max": worst, "errors": fails[:3],
            "tol": args.tol, "pool_hits": pool1["hits"] - pool0["hits"], "pool_misses": pool1["misses"] - pool0["misses"],
-           "requests": f"2D (disk, ellipse, starfish, kite, teardrop, C-shape; kappa 5/10/20) and 3D (sphere, "
+           "requests": f"2D (disk, ellipse, starfish, kite, teardrop, C-shape, rod; kappa 5/10/20) and 3D (sphere, "
                        f"ellipsoid, torus; kappa 3/5), "
                        f"{args.serve_tmin}..{args.serve_tmax} bodies log-uniform, 1..16 directions, "
                        f"{args.p_sweep:g} of requests revisit an earlier geometry"}

@@ -118,8 +118,9 @@ class Engine:
     executor(specs, slot) -> list of result dicts, one per spec, runs one batch on the slot."""
 
     def __init__(self, executor, budget: int, slots: int = 4, clock=time.monotonic, batching: Batching | None = None,
-                 start: bool = True):
+                 start: bool = True, on_done: Callable[[Ticket], None] | None = None):
         self.executor = executor
+        self.on_done = on_done  # called from the worker for every finished ticket (progress, logging)
         self.policy = Admission(budget, slots)
         self.clock = clock
         self.batching = batching
@@ -219,6 +220,8 @@ class Engine:
                 self.lock.notify_all()
             for _, t in group:
                 t.done.set()
+                if self.on_done is not None:
+                    self.on_done(t)
 
     def drain(self, timeout: float | None = None) -> bool:
         deadline = None if timeout is None else time.monotonic() + timeout
