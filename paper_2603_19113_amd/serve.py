@@ -36,12 +36,14 @@ def block_solve(R: int) -> bool:
 def restart_for(T: int, kappa: float, dim: int, R: int = 1, cap: int = 4000, block_cap: int = 2000) -> int:
     """Krylov basis size, with room for the whole solve so that a request rarely restarts.  One
     right-hand side: GMRES needs about 6 steps per body at kappa = 10 in 2D (measured).  Block GMRES
-    over R directions: about 0.35 block steps per body on the 2000-body mixed scene at kappa = 20
-    (687 block steps, measured)."""
-    if block_solve(R):
-        est = int(0.5 * T * max(kappa, 3.0) / 20.0) + 64
-        return max(32, min(block_cap, est))
+    over R directions needs fewer block steps than one column needs steps, by a factor that grows
+    with R: 17x at R = 64 on the 2000-body mixed scene (687 block steps against ~11,800); the basis
+    is sized with R^0.6 (12x at 64, 3.5x at 8), which leaves room at small R, where restarted block
+    cycles converge slowly (measured: 495 bodies, kappa 5, R = 8 stalls at 4e-7 after 30 cycles of
+    125 block steps)."""
     est = int(8 * T * max(kappa, 3.0) / 10.0) + 200
+    if block_solve(R):
+        return max(64, min(block_cap, int(est / R ** 0.6)))
     return max(64, min(cap, est))
 
 

@@ -120,6 +120,7 @@ def test_footprint_grows_with_size_and_basis():
     assert restart_for(5000, 20.0, 2) == 4000  # capped
     assert restart_for(5000, 20.0, 2, R=8) == 2000  # block steps, capped
     assert restart_for(2000, 20.0, 2, R=64) >= 687  # the full-size mixed scene's measured block steps
+    assert restart_for(495, 5.0, 2, R=8) >= 500     # 125 stalled there (30 restarted cycles at 4e-7)
 
 
 def test_footprint_comes_from_the_library():
