@@ -446,7 +446,8 @@ typedef enum {
   MFS_PAIR_F32_SYM = 2,     /* FP32 vector units, phi once per unordered pair */
   MFS_PAIR_F32_SYM16 = 3,   /* the same on 16-point sub-blocks (3D, bodies of multiples of 16) */
   MFS_PAIR_MC_F32 = 4,      /* matrix cores, FP32 products (R >= 8) */
-  MFS_PAIR_MC_F16X3 = 5     /* matrix cores, FP16 products of split operands (R >= 8) */
+  MFS_PAIR_MC_F16X3 = 5,    /* matrix cores, FP16 products of split operands (R >= 8) */
+  MFS_PAIR_MC_F64 = 6       /* FP64 on the FP64 matrix cores (R >= 8) */
 } mfs_pair_kernel_kind;
 mfs_status mfs_pair_kernel(const mfs_scene* scene, int32_t R, mfs_prec prec, int32_t* kind);
 

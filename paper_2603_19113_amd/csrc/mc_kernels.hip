@@ -543,6 +543,119 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
   }
 }
 
+// ---------------------------------------------------------------------------
+// Many right-hand sides in FP64 (the residuals of the mixed solve, the FP64 solve): the same
+// contraction on the FP64 matrix cores, phi evaluated once per pair for all 64 right-hand sides of a
+// block instead of once per 4 in the vector-unit kernel.  phi in FP64 from the absolute FP64
+// coordinates (the FP64 Hankel function of phi.h; no body-centre split is needed at this
+// precision), FP64 products and accumulation throughout.  A block of 4 waves owns 64 targets and 64
+// right-hand sides; sources come 16 at a time (four k-steps of v_mfma_f64_16x16x4f64: A and B lanes
+// as in the FP32 form, but D row 4 v + l/16, column l % 16 in register v of lane l).  Every body
+// holds a multiple of 16 points, so a tile lies in one body.
+// ---------------------------------------------------------------------------
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int kM64Src = 16;
+
+template <int DIM>
+__global__ __launch_bounds__(256) void ghat_mfma64_kernel(double kappa, const double* __restrict__ x0,
+                                                          const double* __restrict__ x1,
+                                                          const double* __restrict__ x2,
+                                                          const int32_t* __restrict__ body_of,
+                                                          const c128* __restrict__ q, int64_t N, int R,
+                                                          int64_t chunk_len, c128* __restrict__ partial) {
+  __shared__ c128 qt[2][kM64Src][kMfmaRhs];  // charge tiles, double-buffered
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t tbase = (int64_t)blockIdx.x * kMfmaTargets + 16 * wave;
+  const int r0 = blockIdx.z * kMfmaRhs;
+  const int64_t c0 = (int64_t)blockIdx.y * chunk_len;
+  const int64_t c1 = min(N, c0 + chunk_len);
+  const int64_t tg = tbase + (lane & 15);
+  const int64_t tgc = tg < N ? tg : N - 1;
+  double xt[DIM];
+  xt[0] = x0[tgc];
+  xt[1] = x1[tgc];
+  if constexpr (DIM == 3) xt[2] = x2[tgc];
+  const int tb = tg < N ? body_of[tgc] : -1;
+  v4d accR[4], accI[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) accR[b] = accI[b] = v4d{0.0, 0.0, 0.0, 0.0};
+  // staging: thread tid moves right-hand side tid / 4, sources 4 (tid % 4) .. + 3 of the tile
+  const int rr = tid >> 2, sg = (tid & 3) * 4;
+  const int rq = r0 + rr;
+  c128 qreg[4];
+  auto load_q = [&](int64_t j0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) qreg[u] = rq < R ? q[(int64_t)rq * N + j0 + sg + u] : c128{0.0, 0.0};
+  };
+  auto store_q = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) qt[buf][sg + u][rr] = qreg[u];
+  };
+  if (c0 < c1) {
+    load_q(c0);
+    store_q(0);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t j0 = c0; j0 < c1; j0 += kM64Src) {
+      const bool more = j0 + kM64Src < c1;
+      if (more) load_q(j0 + kM64Src);  // in flight during this tile's work
+      const bool same = tb == body_of[j0];
+#pragma unroll 1
+      for (int st = 0; st < 4; ++st) {  // not unrolled: one copy of the FP64 Hankel function
+        const int64_t j = j0 + 4 * st + (lane >> 4);
+        double r2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          const double dx = xt[d] - (d == 0 ? x0[j] : d == 1 ? x1[j] : x2[j]);
+          r2 = fma(dx, dx, r2);
+        }
+        double pr = 0.0, pi = 0.0;
+        if (!same && tb >= 0) {
+          if constexpr (DIM == 2) phi2d_f64(sqrt(r2), kappa, pr, pi);
+          else phi3d_f64(sqrt(r2), kappa, pr, pi);
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const c128 qq = qt[buf][4 * st + (lane >> 4)][16 * b + (lane & 15)];
+          accR[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(pr, qq.re, accR[b], 0, 0, 0);
+          accR[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-pi, qq.im, accR[b], 0, 0, 0);
+          accI[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(pr, qq.im, accI[b], 0, 0, 0);
+          accI[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(pi, qq.re, accI[b], 0, 0, 0);
+        }
+      }
+      if (more) store_q(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int r = r0 + 16 * b + (lane & 15);
+    if (r >= R) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t t = tbase + 4 * v + (lane >> 4);
+      if (t < N) partial[((int64_t)blockIdx.y * R + r) * N + t] = c128{accR[b][v], accI[b][v]};
+    }
+  }
+}
+
+template <int DIM>
+static hipError_t launch_mfma64(const SceneDev& s, const c128* q, int R, c128* partial, int nchunks,
+                                hipStream_t st) {
+  int64_t chunk_len = (s.N + nchunks - 1) / nchunks;
+  chunk_len = (chunk_len + kM64Src - 1) / kM64Src * kM64Src;
+  dim3 grid((unsigned)((s.N + kMfmaTargets - 1) / kMfmaTargets), (unsigned)nchunks,
+            (unsigned)((R + kMfmaRhs - 1) / kMfmaRhs));
+  hipLaunchKernelGGL((ghat_mfma64_kernel<DIM>), grid, dim3(256), 0, st, s.kappa, s.x64[0], s.x64[1], s.x64[2],
+                     s.body_of, q, s.N, R, chunk_len, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_ghat_mc64(const SceneDev& s, const c128* q, int R, c128* partial, int nchunks, hipStream_t st) {
+  return s.dim == 2 ? launch_mfma64<2>(s, q, R, partial, nchunks, st) : launch_mfma64<3>(s, q, R, partial, nchunks, st);
+}
+
 template <int DIM>
 static hipError_t launch_mfma(const SceneDev& s, const c64* q, int R, c64* partial, int nchunks, hipStream_t st) {
   int64_t chunk_len = (s.N + nchunks - 1) / nchunks;

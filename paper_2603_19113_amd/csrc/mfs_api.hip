@@ -2186,7 +2186,7 @@ mfs_status mfs_pair_kernel(const mfs_scene* s, int32_t R, mfs_prec prec, int32_t
   if (R < 1) return fail(MFS_ERR_ARG, "pair_kernel: R must be >= 1");
   if (!kind) return fail(MFS_ERR_ARG, "pair_kernel: kind is null");
   if (prec == MFS_FP64) {
-    *kind = MFS_PAIR_F64;
+    *kind = ghat_uses_mfma(s->dev, R) ? MFS_PAIR_MC_F64 : MFS_PAIR_F64;
     return MFS_OK;
   }
   const LaunchShape ls = shape_for(s, false, R);

@@ -111,6 +111,8 @@ size_t ghat_split_bytes(const SceneDev& s, int R);
 // allows it, else the FP32 form.
 hipError_t launch_ghat_mc(const SceneDev& s, const c64* q, int R, c64* partial, int nchunks, void* split,
                           hipStream_t st);
+// The FP64 pair sum on the FP64 matrix cores (mc_kernels.hip), where ghat_uses_mfma holds.
+hipError_t launch_ghat_mc64(const SceneDev& s, const c128* q, int R, c128* partial, int nchunks, hipStream_t st);
 hipError_t launch_ghat_f64(const SceneDev& s, const c128* q, int R, c128* partial, int nchunks,
                            hipStream_t st);
 hipError_t launch_eval_f32(const SceneDev& s, const c64* q, int R, const double* targets, int64_t M,

@@ -1175,6 +1175,8 @@ hipError_t launch_ghat_f32(const SceneDev& s, const c64* q, int R, c64* partial,
 }
 
 hipError_t launch_ghat_f64(const SceneDev& s, const c128* q, int R, c128* partial, int nchunks, hipStream_t st) {
+  if (s.N <= 0) return hipSuccess;
+  if (ghat_uses_mfma(s, R)) return launch_ghat_mc64(s, q, R, partial, nchunks, st);
   if (s.dim == 2) {
     PhiEval<double, 2> phi{s.kappa};
     return dispatch_rt<double, 2, 1, false>(phi, s.x64[0], s.x64[1], nullptr, s.body_of, s.body_ptr, q, s.N, R,

@@ -83,9 +83,11 @@ EXPORTS = ["mfs_last_error", "mfs_version", "mfs_build_S", "mfs_scene_create", "
            "mfs_pair_kernel", "mfs_scene_set_split_fp16", "mfs_solve_footprint"]
 MFS_KERNEL_PAIR_F32, MFS_KERNEL_PAIR_F64 = 0, 1
 # mfs_pair_kernel_kind
-MFS_PAIR_F64, MFS_PAIR_F32, MFS_PAIR_F32_SYM, MFS_PAIR_F32_SYM16, MFS_PAIR_MC_F32, MFS_PAIR_MC_F16X3 = range(6)
+MFS_PAIR_F64, MFS_PAIR_F32, MFS_PAIR_F32_SYM, MFS_PAIR_F32_SYM16, MFS_PAIR_MC_F32, MFS_PAIR_MC_F16X3, \
+    MFS_PAIR_MC_F64 = range(7)
 PAIR_KERNEL_NAMES = {MFS_PAIR_F64: "f64", MFS_PAIR_F32: "f32", MFS_PAIR_F32_SYM: "f32_sym",
-                     MFS_PAIR_F32_SYM16: "f32_sym16", MFS_PAIR_MC_F32: "mc_f32", MFS_PAIR_MC_F16X3: "mc_f16x3"}
+                     MFS_PAIR_F32_SYM16: "f32_sym16", MFS_PAIR_MC_F32: "mc_f32", MFS_PAIR_MC_F16X3: "mc_f16x3",
+                     MFS_PAIR_MC_F64: "mc_f64"}
 
 
 def load(path: str = LIB_PATH):

@@ -169,3 +169,22 @@ def test_split_matrix_core_operator_and_static_entry(mfs):
     print(f"  apply {e1:.2e}, apply_static {e2:.2e}, between {entrywise_err(ys.cpu().numpy(), y.cpu().numpy()):.2e}",
           flush=True)
     gsc.close()
+
+
+@pytest.mark.parametrize("case,R", [("ragged2d", 8), ("ragged2d", 70), ("spheres5", 64)])
+def test_fp64_matrix_core_matches_oracle(mfs, case, R):
+    """The FP64 pair sum with 8 or more right-hand sides runs on the FP64 matrix cores (phi once per
+    pair for 64 right-hand sides): the oracle's G_hat q to 1e-12, entry by entry."""
+    torch = _torch()
+    sc = CASES[case]()
+    print(f"FP64 matrix-core parity {case} N={sc.N} R={R}", flush=True)
+    gsc = _ghat_scene(mfs, sc)
+    assert mfs.pair_kernel(gsc, R, mfs.MFS_FP64) == mfs.MFS_PAIR_MC_F64
+    xh, ptr, bo = gs.pack(sc)
+    q = crandn(np.random.default_rng(81 + R), R, sc.N)
+    ref = gs.ghat_apply(xh, bo, sc.kappa, q)
+    t = torch.empty((R, sc.N), dtype=torch.complex128, device="cuda")
+    mfs.ghat_apply(gsc, torch.from_numpy(q).cuda(), t, mfs.MFS_FP64)
+    err = assert_entrywise(t.cpu().numpy(), ref, 1e-12, f"FP64 matrix cores {case}")
+    print(f"  entrywise error {err:.2e}", flush=True)
+    gsc.close()
