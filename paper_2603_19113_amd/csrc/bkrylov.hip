@@ -247,8 +247,26 @@ __device__ __forceinline__ void slab_load(SlabRegs& g, const TA* __restrict__ X,
   }
 }
 
+// The FP32 kernels stage in FP32: the rounding happens at the load instead of the LDS store (same
+// values), and the staging takes half the registers.
+struct SlabRegs32 {
+  float re[8], im[8];
+};
+
+template <typename TA>
+__device__ __forceinline__ void slab_load32(SlabRegs32& g, const TA* __restrict__ X, int64_t ldx, int col, bool okc,
+                                            int64_t n, int64_t nend) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    c128 v = {0.0, 0.0};
+    if (okc && n + i < nend) v = load_c(X + (int64_t)col * ldx + n + i);
+    g.re[i] = (float)v.re;
+    g.im[i] = (float)v.im;
+  }
+}
+
 template <typename TA, typename TB>
-__global__ __launch_bounds__(256) void bdots32_kernel(const TA* __restrict__ A, int64_t lda, int K,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void bdots32_kernel(const TA* __restrict__ A, int64_t lda, int K,
                                                       const TB* __restrict__ B, int64_t ldb, int R, int64_t N,
                                                       int64_t slice_len, c128* __restrict__ part) {
   __shared__ float Are[kSlab][kPadF], Aim[kSlab][kPadF], Bre[kSlab][kPadF], Bim[kSlab][kPadF];
@@ -262,23 +280,23 @@ __global__ __launch_bounds__(256) void bdots32_kernel(const TA* __restrict__ A, 
   for (int t = 0; t < 4; ++t) sumR[t] = sumI[t] = d4{0.0, 0.0, 0.0, 0.0};
   const int col = tid >> 2, nq = (tid & 3) * 8;
   const bool oka = k0 + col < K, okb = col < R;
-  SlabRegs ga, gb;
+  SlabRegs32 ga, gb;
   if (n0 < n1) {
-    slab_load(ga, A, lda, k0 + col, oka, n0 + nq, n1);
-    slab_load(gb, B, ldb, col, okb, n0 + nq, n1);
+    slab_load32(ga, A, lda, k0 + col, oka, n0 + nq, n1);
+    slab_load32(gb, B, ldb, col, okb, n0 + nq, n1);
   }
   for (int64_t nb = n0; nb < n1; nb += kSlab) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      Are[nq + i][col] = (float)ga.re[i];
-      Aim[nq + i][col] = (float)ga.im[i];
-      Bre[nq + i][col] = (float)gb.re[i];
-      Bim[nq + i][col] = (float)gb.im[i];
+      Are[nq + i][col] = ga.re[i];
+      Aim[nq + i][col] = ga.im[i];
+      Bre[nq + i][col] = gb.re[i];
+      Bim[nq + i][col] = gb.im[i];
     }
     __syncthreads();
     if (nb + kSlab < n1) {  // next slab in flight during the products
-      slab_load(ga, A, lda, k0 + col, oka, nb + kSlab + nq, n1);
-      slab_load(gb, B, ldb, col, okb, nb + kSlab + nq, n1);
+      slab_load32(ga, A, lda, k0 + col, oka, nb + kSlab + nq, n1);
+      slab_load32(gb, B, ldb, col, okb, nb + kSlab + nq, n1);
     }
     f4 accR[4], accI[4];
 #pragma unroll
@@ -287,13 +305,22 @@ __global__ __launch_bounds__(256) void bdots32_kernel(const TA* __restrict__ A, 
     for (int kk = 0; kk < kSlab; kk += 4) {
       const int r = kk + (lane >> 4);
       const float ar = Are[r][16 * w + (lane & 15)], ai = Aim[r][16 * w + (lane & 15)];
+      float br[4], bi[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const float br = Bre[r][16 * t + (lane & 15)], bi = Bim[r][16 * t + (lane & 15)];
-        accR[t] = mfma32(ar, br, accR[t]);
-        accR[t] = mfma32(ai, bi, accR[t]);
-        accI[t] = mfma32(ar, bi, accI[t]);
-        accI[t] = mfma32(-ai, br, accI[t]);
+        br[t] = Bre[r][16 * t + (lane & 15)];
+        bi[t] = Bim[r][16 * t + (lane & 15)];
+      }
+      // eight accumulators between two products into the same one: no back-to-back dependence
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        accR[t] = mfma32(ar, br[t], accR[t]);
+        accI[t] = mfma32(ar, bi[t], accI[t]);
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        accR[t] = mfma32(ai, bi[t], accR[t]);
+        accI[t] = mfma32(-ai, br[t], accI[t]);
       }
     }
 #pragma unroll
@@ -317,7 +344,7 @@ __global__ __launch_bounds__(256) void bdots32_kernel(const TA* __restrict__ A, 
 }
 
 template <typename TA, typename TC>
-__global__ __launch_bounds__(256) void bgemm32_nk_kernel(const TA* __restrict__ A, int64_t lda, int64_t M, int K,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void bgemm32_nk_kernel(const TA* __restrict__ A, int64_t lda, int64_t M, int K,
                                                          const TC* __restrict__ C, int64_t ldc, int R, double alpha,
                                                          double beta, const c128* in, int64_t ldi, c128* out,
                                                          int64_t ldo) {
@@ -331,7 +358,7 @@ __global__ __launch_bounds__(256) void bgemm32_nk_kernel(const TA* __restrict__ 
   // C slab: 32 rows k x 64 columns c, thread tid: column tid / 4, k from (tid % 4) * 8
   const int kc = tid >> 3, nq = (tid & 7) * 8;
   const int cc = tid >> 2, kq = (tid & 3) * 8;
-  SlabRegs ga, gc;
+  SlabRegs32 ga, gc;
   auto load = [&](int kb) {
     const int k = kb + kc;
 #pragma unroll
@@ -339,23 +366,23 @@ __global__ __launch_bounds__(256) void bgemm32_nk_kernel(const TA* __restrict__ 
       const int64_t n = n0 + nq + i;
       c128 a = {0.0, 0.0};
       if (k < K && n < M) a = load_c(A + (int64_t)k * lda + n);
-      ga.re[i] = a.re;
-      ga.im[i] = a.im;
+      ga.re[i] = (float)a.re;
+      ga.im[i] = (float)a.im;
       const int kk = kb + kq + i;
       c128 v = {0.0, 0.0};
       if (kk < K && cc < R) v = load_c(C + kk + (int64_t)cc * ldc);
-      gc.re[i] = v.re;
-      gc.im[i] = v.im;
+      gc.re[i] = (float)v.re;
+      gc.im[i] = (float)v.im;
     }
   };
   if (K > 0) load(0);
   for (int kb = 0; kb < K; kb += kSlab) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      Are[kc][nq + i] = (float)ga.re[i];
-      Aim[kc][nq + i] = (float)ga.im[i];
-      Cre[kq + i][cc] = (float)gc.re[i];
-      Cim[kq + i][cc] = (float)gc.im[i];
+      Are[kc][nq + i] = ga.re[i];
+      Aim[kc][nq + i] = ga.im[i];
+      Cre[kq + i][cc] = gc.re[i];
+      Cim[kq + i][cc] = gc.im[i];
     }
     __syncthreads();
     if (kb + kSlab < K) load(kb + kSlab);  // next slab in flight during the products
@@ -366,13 +393,22 @@ __global__ __launch_bounds__(256) void bgemm32_nk_kernel(const TA* __restrict__ 
     for (int kk = 0; kk < kSlab; kk += 4) {
       const int r = kk + (lane >> 4);
       const float ar = Are[r][16 * w + (lane & 15)], ai = Aim[r][16 * w + (lane & 15)];
+      float cr[4], ci[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const float cr = Cre[r][16 * t + (lane & 15)], ci = Cim[r][16 * t + (lane & 15)];
-        accR[t] = mfma32(ar, cr, accR[t]);
-        accR[t] = mfma32(-ai, ci, accR[t]);
-        accI[t] = mfma32(ar, ci, accI[t]);
-        accI[t] = mfma32(ai, cr, accI[t]);
+        cr[t] = Cre[r][16 * t + (lane & 15)];
+        ci[t] = Cim[r][16 * t + (lane & 15)];
+      }
+      // eight accumulators between two products into the same one: no back-to-back dependence
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        accR[t] = mfma32(ar, cr[t], accR[t]);
+        accI[t] = mfma32(ar, ci[t], accI[t]);
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        accR[t] = mfma32(-ai, ci[t], accR[t]);
+        accI[t] = mfma32(ai, cr[t], accI[t]);
       }
     }
 #pragma unroll
