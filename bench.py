@@ -351,6 +351,9 @@ def main() -> int:
                     help="profiling mode: replace the solve by this many mixed operator applications")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="profiling: first copy a buffer of this many MiB (calibrates rocprof byte counters)")
+    ap.add_argument("--sym-slice-budget", type=int, default=0, metavar="BYTES",
+                    help="slice budget of the symmetric pair kernel (0: the library default); 1 forces the "
+                         "form whose 8 waves share each source tile")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--mc-fp32", action="store_true",
                     help="many right-hand sides: FP32 matrix-core products instead of FP16 products of "
@@ -407,6 +410,7 @@ def main() -> int:
 
     mfs.load()
     torch.cuda.set_device(0)
+    mfs.sym_slice_budget(args.sym_slice_budget)
     if args.serve > 0:
         return serve(args, w, torch)
     sc = w.make_scene(args.workload, T=args.bodies)
@@ -527,15 +531,18 @@ def main() -> int:
     ms64, n64, p64 = mfs.timing_read(mfs.MFS_KERNEL_PAIR_F64)
     mfs.timing_enable(False)
 
-    on_sym = pair_kind in (mfs.MFS_PAIR_F32_SYM, mfs.MFS_PAIR_F32_SYM16)
+    shared = pair_kind in (mfs.MFS_PAIR_F32_SYM_SHARED, mfs.MFS_PAIR_F32_SYM16_SHARED)
+    on_sym = shared or pair_kind in (mfs.MFS_PAIR_F32_SYM, mfs.MFS_PAIR_F32_SYM16)
     on_mfma = pair_kind in (mfs.MFS_PAIR_MC_F32, mfs.MFS_PAIR_MC_F16X3)
     split16 = pair_kind == mfs.MFS_PAIR_MC_F16X3
-    sub_blocks = pair_kind == mfs.MFS_PAIR_F32_SYM16
+    sub_blocks = pair_kind in (mfs.MFS_PAIR_F32_SYM16, mfs.MFS_PAIR_F32_SYM16_SHARED)
     rt = shape["rhs_per_thread"] or (1 if R == 1 else 2 if R == 2 else 4)
     if sub_blocks:
-        kernel_name = "ghat_sym16_kernel<%d> (G_hat, FP32, symmetric, 16-point sub-blocks)" % rt
+        kernel_name = ("ghat_sym16_shared_kernel<%d,8> (G_hat, FP32, symmetric, 16-point sub-blocks, shared source tiles)"
+                       % rt if shared else "ghat_sym16_kernel<%d> (G_hat, FP32, symmetric, 16-point sub-blocks)" % rt)
     elif on_sym:
-        kernel_name = "ghat_sym_kernel<%d,%d> (G_hat, FP32, symmetric)" % (sc.dim, rt)
+        kernel_name = ("ghat_sym_shared_kernel<%d,%d,8> (G_hat, FP32, symmetric, shared source tiles)" % (sc.dim, rt)
+                       if shared else "ghat_sym_kernel<%d,%d> (G_hat, FP32, symmetric)" % (sc.dim, rt))
     elif split16:
         kernel_name = "ghat_mfma16_kernel<%d> (G_hat, FP16 matrix cores, split operands)" % sc.dim
     elif on_mfma:

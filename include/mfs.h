@@ -386,6 +386,17 @@ mfs_status mfs_pool_query(mfs_pool_stats* out);
 /* Set the cap on cached bytes (>= 0); cached blocks are released if the cache exceeds it. */
 mfs_status mfs_pool_set_limit(int64_t max_cached_bytes);
 
+/* Budget for the partial sums of the symmetric pair kernel, process-wide (runtime only).  The
+ * kernel writes its source-side sums as partial slices of N entries per right-hand side: one per
+ * group distance where each wave stores its own (the fastest form), or about 8 times fewer where
+ * the 8 waves of a block share each staged source tile and store its sums once (a barrier per
+ * tile: a few percent more time, and 4 to 8 times fewer HBM writes).  The shared form runs when
+ * the one-wave form's slices for the call's right-hand sides would exceed `bytes`; bytes <= 0
+ * restores the default, 4 GiB.  *previous (may be null) receives the budget in force before the
+ * call.  Takes effect for pair sums launched afterwards; a solve's footprint follows it, so set it
+ * before mfs_solve_footprint and the solves it sizes.  Never fails. */
+mfs_status mfs_sym_slice_budget(int64_t bytes, int64_t* previous);
+
 /* Release every cached block to the device (waits for each block's last use).  Blocks held by live
  * scenes are not affected. */
 mfs_status mfs_pool_trim(void);
@@ -447,7 +458,11 @@ typedef enum {
   MFS_PAIR_F32_SYM16 = 3,   /* the same on 16-point sub-blocks (3D, bodies of multiples of 16) */
   MFS_PAIR_MC_F32 = 4,      /* matrix cores, FP32 products (R >= 8) */
   MFS_PAIR_MC_F16X3 = 5,    /* matrix cores, FP16 products of split operands (R >= 8) */
-  MFS_PAIR_MC_F64 = 6       /* FP64 on the FP64 matrix cores (R >= 8) */
+  MFS_PAIR_MC_F64 = 6,      /* FP64 on the FP64 matrix cores (R >= 8) */
+  MFS_PAIR_F32_SYM_SHARED = 7,   /* MFS_PAIR_F32_SYM with 8 waves per block sharing each source
+                                    tile (the slices of the one-wave form would pass the budget of
+                                    mfs_sym_slice_budget) */
+  MFS_PAIR_F32_SYM16_SHARED = 8  /* the same for MFS_PAIR_F32_SYM16 */
 } mfs_pair_kernel_kind;
 mfs_status mfs_pair_kernel(const mfs_scene* scene, int32_t R, mfs_prec prec, int32_t* kind);
 

@@ -245,7 +245,10 @@ LaunchShape shape_for(const mfs_scene* s, bool f64, int R, int* source = nullptr
   if (sym_ok && e.sym != 0) {
     ls.sym = 1;
     // a slice count tuned for the other kernel does not carry over
-    if (e.sym != 1 || e.nchunks <= 0) ls.nchunks = sym_plan(sym_view(s->dev).N, 0).nchunks_d;
+    if (e.sym != 1 || e.nchunks <= 0) {
+      const int64_t NS = sym_view(s->dev).N;
+      ls.nchunks = sym_plan(NS, 0, sym_block_waves(NS, R)).nchunks_d;
+    }
   } else {
     ls.sym = 0;
     if (e.sym == 1 || e.nchunks <= 0) ls.nchunks = pair_chunks_for(s->dev.N, s->dev.N, tpt_for(f64 ? MFS_FP64 : MFS_FP32));
@@ -259,9 +262,11 @@ int64_t f32_rows(const mfs_scene* s, const LaunchShape& ls) {
   return ls.sym == 1 && sym_padded(s->dev) ? s->dev.Npad : s->dev.N;
 }
 
-// Partial-sum slices the FP32 pair sum writes with this shape.
-int f32_slices(const mfs_scene* s, const LaunchShape& ls) {
-  return ls.sym == 1 ? sym_plan(f32_rows(s, ls), ls.nchunks).slices : ls.nchunks;
+// Partial-sum slices the FP32 pair sum writes with this shape for R right-hand sides.
+int f32_slices(const mfs_scene* s, const LaunchShape& ls, int R) {
+  if (ls.sym != 1) return ls.nchunks;
+  const int64_t rows = f32_rows(s, ls);
+  return sym_plan(rows, ls.nchunks, sym_block_waves(rows, R)).slices;
 }
 
 // Where the FP32 pair sum left its partial sums: `slices` slices of R rows of NP entries, body b's
@@ -278,7 +283,7 @@ mfs_status pair_f32(mfs_scene* s, const c64* q32, int R, hipStream_t st, Partial
   const LaunchShape ls = shape_for(s, false, R);
   const bool padded = ls.sym == 1 && sym_padded(s->dev);
   const int64_t rows = f32_rows(s, ls);
-  const int nch = f32_slices(s, ls);
+  const int nch = f32_slices(s, ls, R);
   MFS_TRY(ensure(s->partial, (size_t)nch * R * rows * sizeof(c64), &s->bytes, st));
   c64* part = static_cast<c64*>(s->partial.p);
   const c64* qs = q32;
@@ -455,7 +460,7 @@ mfs_status apply_in_buffer(mfs_scene* s, const void* q, void* y, int R, mfs_prec
   if (ls.sym == 1) {
     const bool padded = sym_padded(s->dev);
     const int64_t rows = f32_rows(s, ls);
-    const int slices = f32_slices(s, ls);
+    const int slices = f32_slices(s, ls, R);
     const size_t part_bytes = ((size_t)slices * R * rows * sizeof(c64) + 255) / 256 * 256;
     const size_t need = part_bytes + (padded ? (size_t)R * rows * sizeof(c64) : 0);
     if (need <= cap) {
@@ -1351,7 +1356,7 @@ mfs_status mfs_solve_footprint(int32_t dim, int64_t T, const int32_t* shape_of, 
   size_t part = 0, qpad = 0, split = 0, q32 = 0;
   if (prec != MFS_FP64) {
     const LaunchShape ls = shape_for(&sh, false, R);
-    part = (size_t)f32_slices(&sh, ls) * R * f32_rows(&sh, ls) * sizeof(c64);
+    part = (size_t)f32_slices(&sh, ls, R) * R * f32_rows(&sh, ls) * sizeof(c64);
     if (ls.sym == 1 && NP > 0) qpad = (size_t)R * NP * sizeof(c64);
     if (ls.sym != 1 && ghat_uses_mfma16(d, R)) split = ghat_split_bytes(d, R);
     q32 = (size_t)R * N * sizeof(c64);
@@ -2031,6 +2036,12 @@ mfs_status mfs_pool_trim(void) {
   return MFS_OK;
 }
 
+mfs_status mfs_sym_slice_budget(int64_t bytes, int64_t* previous) {
+  const int64_t old = sym_slice_budget(bytes);
+  if (previous) *previous = old > 0 ? old : kSymSliceBudget;
+  return MFS_OK;
+}
+
 mfs_status mfs_autotune(mfs_scene* s, int32_t R, mfs_prec prec, int32_t reps, mfs_tune_result* out, void* stream) {
   MFS_TRY(check_scene(s));
   if (prec != MFS_FP64 && prec != MFS_FP32 && prec != MFS_MIXED)
@@ -2078,13 +2089,14 @@ mfs_status mfs_autotune(mfs_scene* s, int32_t R, mfs_prec prec, int32_t reps, mf
   };
   if (sym_ok) {
     const int64_t NS = sym_view(s->dev).N;
-    const SymPlan hp = sym_plan(NS, 0);
+    const int W = sym_block_waves(NS, R);
+    const SymPlan hp = sym_plan(NS, 0, W);
     std::vector<int> rset{ghat_default_rt(R)};
     for (int rt : {1, 2, 4})
       if (rt != rset[0] && (rt == 1 || rt / 2 < R)) rset.push_back(rt);
     for (int f : {0, -2, -1, 1, 2}) {
       const int c = f < 0 ? (hp.nchunks_d >> -f) : (hp.nchunks_d << f);
-      for (int rt : rset) add(LaunchShape{sym_plan(NS, std::max(1, std::min(c, kTuneMaxChunks))).nchunks_d, rt, 1});
+      for (int rt : rset) add(LaunchShape{sym_plan(NS, std::max(1, std::min(c, kTuneMaxChunks)), W).nchunks_d, rt, 1});
     }
   }
   plain();
@@ -2151,7 +2163,7 @@ mfs_status mfs_autotune(mfs_scene* s, int32_t R, mfs_prec prec, int32_t reps, mf
   tune_store(s->dev.dim, v, R, N, best_ls);
   // the largest candidate may have grown the partial-sum buffer well past what the winner needs
   const size_t need = f64 ? (size_t)best_ls.nchunks * R * N * part_elem
-                          : (size_t)f32_slices(s, best_ls) * R * f32_rows(s, best_ls) * part_elem;
+                          : (size_t)f32_slices(s, best_ls, R) * R * f32_rows(s, best_ls) * part_elem;
   if (s->partial.cap > 2 * need) release(s->partial, &s->bytes, st);
   res.nchunks = best_ls.nchunks;
   res.rhs_per_thread = (v == kTunePairF32 || best_ls.sym == 1) ? (best_ls.rt ? best_ls.rt : ghat_default_rt(R)) : 0;
@@ -2190,7 +2202,11 @@ mfs_status mfs_pair_kernel(const mfs_scene* s, int32_t R, mfs_prec prec, int32_t
     return MFS_OK;
   }
   const LaunchShape ls = shape_for(s, false, R);
-  if (ls.sym == 1) *kind = s->dev.sym16 ? MFS_PAIR_F32_SYM16 : MFS_PAIR_F32_SYM;
+  if (ls.sym == 1) {
+    const bool shared = sym_block_waves(f32_rows(s, ls), R) > 1;
+    *kind = s->dev.sym16 ? (shared ? MFS_PAIR_F32_SYM16_SHARED : MFS_PAIR_F32_SYM16)
+                         : (shared ? MFS_PAIR_F32_SYM_SHARED : MFS_PAIR_F32_SYM);
+  }
   else if (ghat_uses_mfma16(s->dev, R)) *kind = MFS_PAIR_MC_F16X3;
   else if (ghat_uses_mfma(s->dev, R)) *kind = MFS_PAIR_MC_F32;
   else *kind = MFS_PAIR_F32;

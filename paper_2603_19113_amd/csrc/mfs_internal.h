@@ -78,17 +78,25 @@ bool ghat_uses_mfma(const SceneDev& s, int R);
 // rt: right-hand sides per thread of the VALU kernel (1, 2 or 4; anything else picks by R);
 // ignored where the matrix-core kernel runs.
 int ghat_default_rt(int R);
-// Symmetric pair kernel (1 to kSymMaxRhs right-hand sides): groups of 256 points, G groups, distances 0..Dmax,
-// nchunks_d distance chunks of dpc each; it writes `slices` partial slices (nchunks_d target-side,
-// Dsym source-side).  nchunks_d <= 0 picks the heuristic.
+// Symmetric pair kernels (1 to kSymMaxRhs right-hand sides): groups of 256 points (G0 of them,
+// padded with empty groups to G, a multiple of the W waves of a block), distances 0..Dmax, block
+// offsets 0..HH-1 in nchunks_d chunks of dpc each; they write `slices` partial slices (nchunks_d
+// target-side, HH / W source-side).  nchunks_d <= 0 picks the heuristic.  W = 1 (each wave stores
+// its own source-side sums: the fastest) unless those slices would pass the slice budget, then
+// kSymW (the block's waves share each source tile and store its sums once: ~kSymW times fewer
+// slices and HBM writes, at a few percent more time for the barrier per tile).
 constexpr int kSymMaxRhs = 32;         // the symmetric kernel may run up to this many right-hand sides
 constexpr int kSymDefaultMaxRhs = 24;  // and does by default up to this many
+constexpr int kSymW = 8;               // waves per block where the source tiles are shared
+constexpr int64_t kSymSliceBudget = 4ll << 30;  // default slice budget (bytes)
 struct SymPlan {
   int64_t G;
-  int Dmax, Dsym, dpc, nchunks_d, slices;
+  int W, Dmax, HH, dpc, nchunks_d, slices;
   bool even;
 };
-SymPlan sym_plan(int64_t N, int nchunks_d);
+SymPlan sym_plan(int64_t N, int nchunks_d, int W);
+int sym_block_waves(int64_t NP, int R);   // W for R right-hand sides on NP points
+int64_t sym_slice_budget(int64_t bytes);  // set the budget (<= 0: the default); returns the previous
 bool ghat_sym_possible(const SceneDev& s, int R);
 hipError_t launch_ghat_f32_sym(const SceneDev& s, const c64* q, int R, c64* partial, int nchunks_d, int rt,
                                hipStream_t st);

@@ -15,6 +15,8 @@
 //     only that range is evaluated with a per-pair body-id test, the rest runs unmasked.
 //   * grid.z tiles the right-hand sides, RT per block; phi is computed once per pair and applied
 //     to the RT charges.
+#include <atomic>
+
 #include "mfs_internal.h"
 #include "phi.h"
 #include "bodyphase.h"
@@ -391,23 +393,37 @@ __global__ __launch_bounds__(kBlock) void ghat_bodyphase_kernel(
 // group g meets group h = (g + d) mod G for d = 0 .. Dmax (Dmax = floor(G/2)):
 //   * 1 <= d < G/2: symmetric, each unordered pair of groups is met once, by g;
 //   * d = 0 (the group with itself) and d = G/2 for even G: one-sided, only t of group g.
-// One wave (one block) owns a group of targets, four per lane (lane l: targets 64 m + l), and a
-// range of distances (grid.y).  For each source tile of group h it stages the tile's coordinates
-// and charges in LDS twice over (entries e and e + 64) and makes 64 steps: at step s lane l takes
-// source (l + s) mod 64 from entry l + s, so the 64 lanes see 64 different sources and after 64
-// steps every (target, source) pair of the tile has been formed once.  The source-side sums
-// travel with the sources: at step s lane l holds the running sum of source (l + s) mod 64, adds
-// its products into it and hands it on with a wave rotation (DPP wave_rol:1, lane l receives lane
-// l + 1's value), so after 64 steps lane j holds source j's sum.  Everything stays in registers and
-// in program order: deterministic, no atomics.
-// Outputs, all plain stores (fixed summation order downstream):
-//   partial[c][N]                    target-side sums of distance chunk c (c < nchunks_d)
-//   partial[nchunks_d + d - 1][N]    source-side sums of distance d, written by group h - d.
+// A wave owns a group of targets, four per lane (lane l: targets 64 m + l).  Against a source tile
+// staged in LDS twice over (entries e and e + 64) it makes 64 steps: at step s lane l takes source
+// (l + s) mod 64 from entry l + s, so the 64 lanes see 64 different sources and after 64 steps
+// every (target, source) pair of the tile has been formed once.  The source-side sums travel with
+// the sources: at step s lane l holds the running sum of source (l + s) mod 64, adds its products
+// into it and hands it on with a wave rotation (DPP wave_rol:1, lane l receives lane l + 1's
+// value), so after 64 steps lane j holds source j's sum.  Everything stays in registers and in
+// program order: deterministic, no atomics.  Two block shapes:
+//   * ghat_sym_kernel, one wave per block and a range of distances (grid.y); it stages its own
+//     source tiles and stores its source-side sums of distance d into the slice of d:
+//       partial[c][N]                    target-side sums of distance chunk c (c < nchunks_d)
+//       partial[nchunks_d + d - 1][N]    source-side sums of distance d, written by group h - d;
+//   * ghat_sym_shared_kernel, W waves per block (G padded with empty groups to a multiple of W),
+//     wave w holding target group g = W b + w, and a chunk of block offsets hh (grid.y): at offset
+//     hh every wave meets the same source group (W b + hh) mod G, wave w at distance d = hh - w
+//     (idle where d lies outside 0 .. Dmax), so each source tile is staged once for the block, and
+//     the waves' sums of it are added in wave order by one wave and stored once:
+//       partial[c][N]                    target-side sums of offset chunk c (c < nchunks_d)
+//       partial[nchunks_d + hh / W][N]   source-side sums of offset hh, written by block
+//                                        ((h - hh) mod G) / W; for a given slice and source group
+//                                        exactly one block and one offset qualify (G is a multiple
+//                                        of W, so hh = h mod W + W * slice).
+//     About W times fewer slices (HBM writes and footprint), for a barrier per tile.
+// Both store plainly; the S product adds the slices in a fixed order.
 // Body-centre phase split and the Hankel branches are those of the kernel above; the body pair of
 // a (target tile, source tile) is wave-uniform, so are the far-field tests and the same-body skip.
 // ---------------------------------------------------------------------------
 constexpr int kSymTiles = 4;                 // target tiles per wave
 constexpr int kSymGroup = 64 * kSymTiles;    // points per group
+constexpr int kSubBlock = 16;                // points per sub-block (3D kernel on 16-point sub-blocks)
+constexpr int kSubStride = 48;               // LDS floats per staged sub-block (that kernel)
 
 template <int DIM, int RT>
 struct SymLds {
@@ -549,6 +565,117 @@ struct SymWaves {
   static constexpr int value = RT == 1 ? 4 : (RT == 2 ? 3 : 2);
 };
 
+// The block's walk over source tiles: the first tile at or after (hh, ts) of source group
+// (gb + hh) mod G that holds points, skipping groups past N; false at the chunk's end hh1.  Every
+// value here is uniform over the block, so are the barriers that follow the walk.
+// First point of tile ts of source group (gb + hh) mod G: gb + hh < 2 G for every block offset of the
+// plan (gb <= G - kSymW, hh < Dmax + 2 kSymW - 1; for G = kSymW, gb = 0 and hh < 2 G), so one
+// conditional subtraction takes the place of a 64-bit remainder.
+__device__ __forceinline__ int64_t sym_tile_start(int64_t gb, int64_t G, int hh, int ts) {
+  int64_t h = gb + hh;
+  if (h >= G) h -= G;
+  return h * kSymGroup + 64 * ts;
+}
+
+__device__ __forceinline__ bool sym_seek(int64_t gb, int64_t G, int64_t N, int hh1, int& hh, int& ts) {
+  while (hh < hh1) {
+    if (ts < kSymTiles && sym_tile_start(gb, G, hh, ts) < N) return true;
+    ++hh;
+    ts = 0;
+  }
+  return false;
+}
+
+// Each wave's source-side sums of a staged tile (double-buffered with the tiles): lane l holds
+// source l's sum, as the rotation leaves it.
+template <int RT, int W>
+struct SymComb {
+  float re[2][W][RT][64], im[2][W][RT][64];
+};
+
+// One store per source of the tile: the block's waves' sums added in wave order (deterministic).
+template <int RT, int W>
+__device__ __forceinline__ void sym_combine(const SymComb<RT, W>& cb, int buf, int lane, int64_t j0, int64_t N, int R,
+                                            int r0, int slice, float scale, c64* __restrict__ partial) {
+  if (j0 + lane >= N) return;
+#pragma unroll
+  for (int rr = 0; rr < RT; ++rr) {
+    if (r0 + rr >= R) break;
+    float xr = 0.0f, xi = 0.0f;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      xr += cb.re[buf][w][rr][lane];
+      xi += cb.im[buf][w][rr][lane];
+    }
+    partial[((int64_t)slice * R + r0 + rr) * N + j0 + lane] = c64{xr * scale, xi * scale};
+  }
+}
+
+// Staging of one source tile spread over the block: 64 / W sources per wave and one value per lane
+// (value v: field v / (64 / W) of source (64 / W) * wave + v % (64 / W); the fields are the DIM
+// coordinates, |l|^2, then the real and the imaginary parts of the RT charges, in the order of the
+// staging arrays), so that the loads of the next tile stay in flight in one or two registers while
+// the wave works on the current tile (with one wave per block, each lane holds its own source's
+// fields).  Sources past N (only where tiles may be partly filled) take zero offset and charge and
+// |l|^2 = 1, so that no distance is zero.
+template <int DIM, int RT, int W>
+struct SymStage {
+  static constexpr int kSrc = 64 / W;
+  static constexpr int kFields = DIM + 1 + 2 * RT;
+  static constexpr int kVals = kSrc * kFields;
+  static constexpr int kRegs = (kVals + 63) / 64;
+  float v[kRegs];
+};
+
+template <int DIM, int RT, int W>
+__device__ __forceinline__ void sym_stage_load(SymStage<DIM, RT, W>& st, const float* __restrict__ l0,
+                                               const float* __restrict__ l1, const float* __restrict__ l2,
+                                               const float* __restrict__ lsq, const c64* __restrict__ q,
+                                               const int (&rof)[RT], int64_t N, int64_t j0, int wv, int lane) {
+  constexpr int kSrc = SymStage<DIM, RT, W>::kSrc;
+#pragma unroll
+  for (int k = 0; k < SymStage<DIM, RT, W>::kRegs; ++k) {
+    const int v = lane + 64 * k;
+    float x = 0.0f;
+    if (v < SymStage<DIM, RT, W>::kVals) {
+      const int f = v / kSrc;
+      const int64_t j = j0 + kSrc * wv + v % kSrc;
+      if (j < N) {
+        if (f < DIM) x = (f == 0 ? l0 : f == 1 ? l1 : l2)[j];
+        else if (f == DIM) x = lsq[j];
+        else {
+          const int c = f - DIM - 1, rr = c < RT ? c : c - RT;
+          int r = rof[0];
+#pragma unroll
+          for (int i = 1; i < RT; ++i) r = rr == i ? rof[i] : r;
+          x = reinterpret_cast<const float*>(q)[2 * ((int64_t)r * N + j) + (c < RT ? 0 : 1)];
+        }
+      } else if (f == DIM) {
+        x = 1.0f;
+      }
+    }
+    st.v[k] = x;
+  }
+}
+
+// Store the staged values into the staging arrays (flat view: field f at f * STRIDE), each source
+// at entry E(p) and E(p) + DUP.
+template <int STRIDE, int DUP, bool SUB16, int DIM, int RT, int W>
+__device__ __forceinline__ void sym_stage_store(const SymStage<DIM, RT, W>& st, float* __restrict__ base, int wv,
+                                                int lane) {
+  constexpr int kSrc = SymStage<DIM, RT, W>::kSrc;
+#pragma unroll
+  for (int k = 0; k < SymStage<DIM, RT, W>::kRegs; ++k) {
+    const int v = lane + 64 * k;
+    if (v < SymStage<DIM, RT, W>::kVals) {
+      const int f = v / kSrc, p = kSrc * wv + v % kSrc;
+      const int e = f * STRIDE + (SUB16 ? (p >> 4) * kSubStride + (p & 15) : p);
+      base[e] = st.v[k];
+      base[e + DUP] = st.v[k];
+    }
+  }
+}
+
 template <int DIM, int RT>
 __global__ __launch_bounds__(64, SymWaves<RT>::value) void ghat_sym_kernel(
     BodyPhaseConsts k, const float* __restrict__ l0, const float* __restrict__ l1, const float* __restrict__ l2,
@@ -672,11 +799,149 @@ __global__ __launch_bounds__(64, SymWaves<RT>::value) void ghat_sym_kernel(
             c64{(float)ar[m][rr], (float)ai[m][rr]};
 }
 
+// The symmetric pair sum with W waves per block sharing each staged source tile (see above).
+template <int DIM, int RT, int W>
+__global__ __launch_bounds__(64 * W, SymWaves<RT>::value) void ghat_sym_shared_kernel(
+    BodyPhaseConsts k, const float* __restrict__ l0, const float* __restrict__ l1, const float* __restrict__ l2,
+    const float* __restrict__ lsq, const double* __restrict__ cen, const int32_t* __restrict__ body_of,
+    const c64* __restrict__ q, int64_t N, int R, int64_t G, int Dmax, int even_G, int HH, int dpc, int nchunks_d,
+    c64* __restrict__ partial) {
+  static_assert(W > 1, "one wave per block: ghat_sym_kernel");
+  __shared__ SymLds<DIM, RT> sh[2];
+  __shared__ SymComb<RT, W> cb;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t gb = (int64_t)blockIdx.x * W;  // the block's first target group
+  const int64_t g = gb + wv;                        // this wave's
+  const int c = blockIdx.y;
+  const int r0 = blockIdx.z * RT;  // right-hand sides r0 .. r0 + RT - 1 (those >= R repeat R - 1, unstored)
+  const int hh1 = min(HH, (c + 1) * dpc);
+  const float* lsrc[3] = {l0, l1, l2};
+  int rof[RT];
+#pragma unroll
+  for (int rr = 0; rr < RT; ++rr) rof[rr] = min(r0 + rr, R - 1);
+
+  // targets of this wave: tile m covers points g*256 + 64 m + (0..63), all on one body
+  bool act[kSymTiles];
+  int tb[kSymTiles];
+  float lt[kSymTiles][DIM], qtr[kSymTiles][RT], qti[kSymTiles][RT];
+  double ar[kSymTiles][RT], ai[kSymTiles][RT];
+#pragma unroll
+  for (int m = 0; m < kSymTiles; ++m) {
+    const int64_t t0 = g * kSymGroup + 64 * m;
+    act[m] = t0 < N;
+    const int64_t t = act[m] ? t0 + lane : 0;
+    tb[m] = act[m] ? __builtin_amdgcn_readfirstlane(body_of[t0]) : -1;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) lt[m][d] = lsrc[d][t];
+#pragma unroll
+    for (int rr = 0; rr < RT; ++rr) {
+      const c64 qq = q[(int64_t)rof[rr] * N + t];
+      qtr[m][rr] = act[m] ? qq.re : 0.0f;
+      qti[m][rr] = act[m] ? qq.im : 0.0f;
+      ar[m][rr] = ai[m][rr] = 0.0;
+    }
+  }
+
+  // Walk the source tiles of block offsets c*dpc .. hh1 - 1.  At offset hh all waves meet group
+  // (gb + hh) mod G, wave w at distance hh - w.  One barrier per tile: the tile is staged into
+  // buffer t & 1 before it, the previous tile's sums are added after it (by wave (t - 1) mod W)
+  // while the waves work on this one, and the next tile's loads are in flight meanwhile.
+  int hh = c * dpc, ts = 0, t = 0, buf = 0, psl = 0;
+  int64_t pj0 = 0;
+  bool have = sym_seek(gb, G, N, hh1, hh, ts);
+  SymStage<DIM, RT, W> stg;
+  if (have) {
+    sym_stage_load(stg, l0, l1, l2, lsq, q, rof, N, sym_tile_start(gb, G, hh, ts), wv, lane);
+    sym_stage_store<128, 64, false>(stg, &sh[0].l[0][0], wv, lane);
+  }
+  while (have) {
+    const int64_t j0 = sym_tile_start(gb, G, hh, ts);
+    __syncthreads();  // tile t staged in buffer t & 1; every wave's sums of tile t - 1 in cb
+    int nhh = hh, nts = ts + 1;
+    const bool nhave = sym_seek(gb, G, N, hh1, nhh, nts);
+    if (nhave) sym_stage_load(stg, l0, l1, l2, lsq, q, rof, N, sym_tile_start(gb, G, nhh, nts), wv, lane);
+    if (t > 0 && wv == (t - 1) % W) sym_combine(cb, buf ^ 1, lane, pj0, N, R, r0, nchunks_d + psl, 1.0f, partial);
+    const int d = hh - wv;
+    const bool active = act[0] && d >= 0 && d <= Dmax;
+    const bool sym = active && d != 0 && !(even_G && d == Dmax);
+    float sr[RT], si[RT];  // lane l: source-side sums of source j0 + l (after the tile)
+#pragma unroll
+    for (int rr = 0; rr < RT; ++rr) sr[rr] = si[rr] = 0.0f;
+    if (active) {
+      const int sb = __builtin_amdgcn_readfirstlane(body_of[j0]);
+      // per target tile: body-centre split against the source body (uniform over the wave)
+      double cs[DIM];
+#pragma unroll
+      for (int dd = 0; dd < DIM; ++dd) cs[dd] = cen[(int64_t)sb * DIM + dd];
+      bool use[kSymTiles];
+      float A[kSymTiles], P[kSymTiles][DIM], D[kSymTiles], D2[kSymTiles], ph0[kSymTiles];
+      float tr[kSymTiles][RT], ti[kSymTiles][RT];
+#pragma unroll
+      for (int m = 0; m < kSymTiles; ++m) {
+        use[m] = act[m] && tb[m] != sb;
+#pragma unroll
+        for (int rr = 0; rr < RT; ++rr) tr[m][rr] = ti[m][rr] = 0.0f;
+        const int bt = use[m] ? tb[m] : sb;
+        double D2d = 0.0;
+        float Am = 0.0f;
+#pragma unroll
+        for (int dd = 0; dd < DIM; ++dd) {
+          const double dc = cen[(int64_t)bt * DIM + dd] - cs[dd];
+          D2d = fma(dc, dc, D2d);
+          const float dcf = (float)dc;
+          Am = fmaf(lt[m][dd], lt[m][dd] + 2.0f * dcf, Am);
+          P[m][dd] = -2.0f * (lt[m][dd] + dcf);
+        }
+        A[m] = Am;
+        const double Dd = sqrt(D2d);
+        const double ph = Dd * k.kappa_rev64;
+        D[m] = (float)Dd;
+        D2[m] = (float)D2d;
+        ph0[m] = (float)(ph - floor(ph)) - (DIM == 2 ? 0.125f : 0.0f);
+      }
+      if (sym) sym_tile<DIM, RT, true>(sh[buf], k, lane, use, A, P, D, D2, ph0, qtr, qti, tr, ti, sr, si);
+      else sym_tile<DIM, RT, false>(sh[buf], k, lane, use, A, P, D, D2, ph0, qtr, qti, tr, ti, sr, si);
+#pragma unroll
+      for (int m = 0; m < kSymTiles; ++m)
+#pragma unroll
+        for (int rr = 0; rr < RT; ++rr) {
+          ar[m][rr] += (double)tr[m][rr];
+          ai[m][rr] += (double)ti[m][rr];
+        }
+    }
+#pragma unroll
+    for (int rr = 0; rr < RT; ++rr) {  // zero where this wave formed no symmetric pair with the tile
+      cb.re[buf][wv][rr][lane] = sym ? sr[rr] : 0.0f;
+      cb.im[buf][wv][rr][lane] = sym ? si[rr] : 0.0f;
+    }
+    // the next tile into the other buffer (every wave is past its last read there: the barrier)
+    if (nhave) sym_stage_store<128, 64, false>(stg, &sh[buf ^ 1].l[0][0], wv, lane);
+    pj0 = j0;
+    psl = hh / W;
+    buf ^= 1;
+    ++t;
+    hh = nhh;
+    ts = nts;
+    have = nhave;
+  }
+  __syncthreads();
+  if (t > 0 && wv == (t - 1) % W) sym_combine(cb, buf ^ 1, lane, pj0, N, R, r0, nchunks_d + psl, 1.0f, partial);
+#pragma unroll
+  for (int m = 0; m < kSymTiles; ++m)
+#pragma unroll
+    for (int rr = 0; rr < RT; ++rr)
+      if (act[m] && r0 + rr < R)
+        partial[((int64_t)c * R + r0 + rr) * N + g * kSymGroup + 64 * m + lane] =
+            c64{(float)ar[m][rr], (float)ai[m][rr]};
+}
+
 // ---------------------------------------------------------------------------
 // Symmetric pair sum in 3D on bodies of 16 n points, without padding to whole tiles.
 //
-// Same group schedule, outputs and body-centre split as ghat_sym_kernel, but a 64-point tile may
-// straddle bodies: it is seen as four sub-blocks of 16 points, each on one body (every body holds a
+// Same group schedules, outputs and body-centre split as ghat_sym_kernel (one wave per block:
+// ghat_sym16_kernel) and ghat_sym_shared_kernel (W waves: ghat_sym16_shared_kernel), but a 64-point
+// tile may straddle bodies: it is seen as four sub-blocks of 16 points, each on one body (every body holds a
 // multiple of 16 points, so bodies start on sub-block boundaries).  The 64 steps against a staged
 // source tile run in four phases of 16.  Lane l = 16 G + i (row G) takes, in phase p, sub-block
 // b = (G + p) mod 4 of the source tile, and at step t of the phase source 16 b + ((i + t) mod 16):
@@ -691,14 +956,42 @@ __global__ __launch_bounds__(64, SymWaves<RT>::value) void ghat_sym_kernel(
 // Idle target lanes and idle source slots (past N) carry zero charge and stay finite.  The pairs are
 // summed as e^{i kappa r} / r and the sums scaled by 1/(4 pi) when stored.
 // ---------------------------------------------------------------------------
-constexpr int kSubBlock = 16;   // points per sub-block
-constexpr int kSubStride = 48;  // LDS floats per staged sub-block
 
 template <int RT>
 struct Sym16Lds {
   float l[3][4 * kSubStride];
   float bs[4 * kSubStride];
   float qr[RT][4 * kSubStride], qi[RT][4 * kSubStride];
+  double cs[4][3];  // centres of the four sub-blocks' bodies (zero past N), staged with the tile
+  int sbb[4];       // bodies of the four sub-blocks, -1 past N
+};
+
+// Body-centre difference of a (target lane, source sub-block) pair, target body centre minus source
+// body centre in FP64.  Where the target lane or the source sub-block is idle the pair carries zero
+// charge; its constants are those of a body with itself (difference zero), so that every distance
+// stays finite.  Two sources of the centres: the scene's table in global memory (one wave per
+// block), or LDS (the wave's own target bodies tbase .. tbase + 15 and the staged tile's sub-blocks).
+struct CentresGlobal {
+  const double* __restrict__ cen;
+  __device__ __forceinline__ void diff(int tb, int sb, int, double (&dc)[3]) const {
+    const int bt = tb >= 0 ? tb : (sb >= 0 ? sb : 0);
+    const int bs = sb >= 0 ? sb : bt;
+#pragma unroll
+    for (int dd = 0; dd < 3; ++dd) dc[dd] = cen[(int64_t)bt * 3 + dd] - cen[(int64_t)bs * 3 + dd];
+  }
+};
+
+template <int RT>
+struct CentresLds {
+  const double (*tcen)[3];
+  int tbase;
+  const Sym16Lds<RT>* sh;
+  __device__ __forceinline__ void diff(int tb, int sb, int blk, double (&dc)[3]) const {
+    const bool both = tb >= 0 && sb >= 0;
+    const int ti = both ? tb - tbase : 0;
+#pragma unroll
+    for (int dd = 0; dd < 3; ++dd) dc[dd] = both ? tcen[ti][dd] - sh->cs[blk][dd] : 0.0;
+  }
 };
 
 // lane l receives the value of lane (l & ~15) | ((l + 1) & 15): rotation by one lane inside each row
@@ -717,19 +1010,17 @@ __device__ __forceinline__ int pick4(const int (&v)[4], int b) {
   return b == 0 ? v[0] : b == 1 ? v[1] : b == 2 ? v[2] : v[3];
 }
 
-// Body-centre split of a target (body bt, local offset lt) against source body bsrc:
-// u = A + |l_s|^2 + P . l_s with A = |l_t|^2 + 2 dc . l_t, P = -2 (l_t + dc), D = |dc| and the phase
-// of kappa D in revolutions, from the FP64 centres.
-__device__ __forceinline__ void split_consts3(const BodyPhaseConsts& k, const double* __restrict__ cen, int bt,
-                                              int bsrc, const float (&lt)[3], float& A, float (&P)[3], float& D,
-                                              float& D2, float& ph0) {
+// Body-centre split of a target (local offset lt) against a source body, dc = target body centre
+// minus source body centre (FP64): u = A + |l_s|^2 + P . l_s with A = |l_t|^2 + 2 dc . l_t,
+// P = -2 (l_t + dc), D = |dc| and the phase of kappa D in revolutions.
+__device__ __forceinline__ void split_consts3(const BodyPhaseConsts& k, const double (&dc)[3], const float (&lt)[3],
+                                              float& A, float (&P)[3], float& D, float& D2, float& ph0) {
   double D2d = 0.0;
   float Am = 0.0f;
 #pragma unroll
   for (int dd = 0; dd < 3; ++dd) {
-    const double dc = cen[(int64_t)bt * 3 + dd] - cen[(int64_t)bsrc * 3 + dd];
-    D2d = fma(dc, dc, D2d);
-    const float dcf = (float)dc;
+    D2d = fma(dc[dd], dc[dd], D2d);
+    const float dcf = (float)dc[dd];
     Am = fmaf(lt[dd], lt[dd] + 2.0f * dcf, Am);
     P[dd] = -2.0f * (lt[dd] + dcf);
   }
@@ -757,18 +1048,11 @@ __device__ __forceinline__ void phi3_4pi(const BodyPhaseConsts& k, float u, floa
 }
 constexpr float kInv4Pi = 0.07957747154594767f;
 
-// The bodies a lane's constants refer to in a phase whose source sub-block lies on body sb (-1: idle
-// slots): an idle target lane takes the source body, an idle sub-block the target's body.
-__device__ __forceinline__ void phase_bodies(int tb, int sb, int& bt, int& bsrc) {
-  bt = tb >= 0 ? tb : (sb >= 0 ? sb : 0);
-  bsrc = sb >= 0 ? sb : bt;
-}
-
 // All four target tiles against the staged source tile; no pair of the meeting is on one body.
-template <int RT, bool SYM>
-__device__ __forceinline__ void sym16_steps4(const Sym16Lds<RT>& sh, const BodyPhaseConsts& k,
-                                             const double* __restrict__ cen, int lane, const int (&tb)[kSymTiles],
-                                             const int (&sbb)[4], bool pure, const float (&lt)[kSymTiles][3],
+template <int RT, bool SYM, typename CC>
+__device__ __forceinline__ void sym16_steps4(const Sym16Lds<RT>& sh, const BodyPhaseConsts& k, const CC& cc, int lane,
+                                             const int (&tb)[kSymTiles], const int (&sbb)[4], bool pure,
+                                             const float (&lt)[kSymTiles][3],
                                              const float (&qtr)[kSymTiles][RT], const float (&qti)[kSymTiles][RT],
                                              float (&tr)[kSymTiles][RT], float (&ti)[kSymTiles][RT], float (&sr)[RT],
                                              float (&si)[RT]) {
@@ -780,9 +1064,9 @@ __device__ __forceinline__ void sym16_steps4(const Sym16Lds<RT>& sh, const BodyP
       const int sb = pick4(sbb, blk);
 #pragma unroll
       for (int m = 0; m < kSymTiles; ++m) {
-        int bt, bsrc;
-        phase_bodies(tb[m], sb, bt, bsrc);
-        split_consts3(k, cen, bt, bsrc, lt[m], A[m], P[m], D[m], D2[m], ph0[m]);
+        double dc[3];
+        cc.diff(tb[m], sb, blk, dc);
+        split_consts3(k, dc, lt[m], A[m], P[m], D[m], D2[m], ph0[m]);
       }
     }
     const int e0 = blk * kSubStride + li;
@@ -838,19 +1122,19 @@ __device__ __forceinline__ void sym16_steps4(const Sym16Lds<RT>& sh, const BodyP
 // One target tile against the staged source tile, pairs on one body skipped (a lane's source body
 // is fixed within a phase, so the test is per lane and phase): the rare meetings near the diagonal.
 // Four phases bring the source-side sums back to their own lanes, so passes can follow each other.
-template <int RT, bool SYM>
-__device__ __forceinline__ void sym16_steps1(const Sym16Lds<RT>& sh, const BodyPhaseConsts& k,
-                                             const double* __restrict__ cen, int lane, int tbm, const int (&sbb)[4],
-                                             const float (&ltm)[3], const float (&qtr)[RT], const float (&qti)[RT],
+template <int RT, bool SYM, typename CC>
+__device__ __forceinline__ void sym16_steps1(const Sym16Lds<RT>& sh, const BodyPhaseConsts& k, const CC& cc, int lane,
+                                             int tbm, const int (&sbb)[4], const float (&ltm)[3],
+                                             const float (&qtr)[RT], const float (&qti)[RT],
                                              float (&tr)[RT], float (&ti)[RT], float (&sr)[RT], float (&si)[RT]) {
   const int row = lane >> 4, li = lane & 15;
   for (int p = 0; p < 4; ++p) {
     const int blk = (row + p) & 3;
     const int sb = pick4(sbb, blk);
-    int bt, bsrc;
-    phase_bodies(tbm, sb, bt, bsrc);
+    double dc[3];
+    cc.diff(tbm, sb, blk, dc);
     float A, P[3], D, D2, ph0;
-    split_consts3(k, cen, bt, bsrc, ltm, A, P, D, D2, ph0);
+    split_consts3(k, dc, ltm, A, P, D, D2, ph0);
     const bool same = tbm >= 0 && tbm == sb;
     const int e0 = blk * kSubStride + li;
     for (int t0 = 0; t0 < kSubBlock; t0 += 8) {
@@ -884,6 +1168,20 @@ __device__ __forceinline__ void sym16_steps1(const Sym16Lds<RT>& sh, const BodyP
         si[rr] = rows_shift_next(si[rr], lane);
       }
     }
+  }
+}
+
+// Bodies and body centres of a tile's four sub-blocks into its staging buffer (lanes 0..3 of the
+// calling wave): read once per tile and block, so that the waves find them in LDS.
+template <int RT>
+__device__ __forceinline__ void sym16_stage_meta(Sym16Lds<RT>& sh, const double* __restrict__ cen,
+                                                 const int32_t* __restrict__ body_of, int64_t N, int64_t j0, int lane) {
+  if (lane < 4) {
+    const int64_t j = j0 + kSubBlock * lane;
+    const int b = j < N ? body_of[j] : -1;
+    sh.sbb[lane] = b;
+#pragma unroll
+    for (int dd = 0; dd < 3; ++dd) sh.cs[lane][dd] = b >= 0 ? cen[(int64_t)b * 3 + dd] : 0.0;
   }
 }
 
@@ -972,14 +1270,14 @@ __global__ __launch_bounds__(64, SymWaves<RT>::value) void ghat_sym16_kernel(
         for (int m = 0; m < kSymTiles; ++m) tr[m][rr] = ti[m][rr] = 0.0f;
       }
       if (!any_clash) {
-        if (sym) sym16_steps4<RT, true>(sh, k, cen, lane, tb, sbb, pure, lt, qtr, qti, tr, ti, sr, si);
-        else sym16_steps4<RT, false>(sh, k, cen, lane, tb, sbb, pure, lt, qtr, qti, tr, ti, sr, si);
+        if (sym) sym16_steps4<RT, true>(sh, k, CentresGlobal{cen}, lane, tb, sbb, pure, lt, qtr, qti, tr, ti, sr, si);
+        else sym16_steps4<RT, false>(sh, k, CentresGlobal{cen}, lane, tb, sbb, pure, lt, qtr, qti, tr, ti, sr, si);
       } else {
 #pragma unroll
         for (int m = 0; m < kSymTiles; ++m) {
           if (g * kSymGroup + 64 * m >= N) continue;  // a tile with no targets
-          if (sym) sym16_steps1<RT, true>(sh, k, cen, lane, tb[m], sbb, lt[m], qtr[m], qti[m], tr[m], ti[m], sr, si);
-          else sym16_steps1<RT, false>(sh, k, cen, lane, tb[m], sbb, lt[m], qtr[m], qti[m], tr[m], ti[m], sr, si);
+          if (sym) sym16_steps1<RT, true>(sh, k, CentresGlobal{cen}, lane, tb[m], sbb, lt[m], qtr[m], qti[m], tr[m], ti[m], sr, si);
+          else sym16_steps1<RT, false>(sh, k, CentresGlobal{cen}, lane, tb[m], sbb, lt[m], qtr[m], qti[m], tr[m], ti[m], sr, si);
         }
       }
 #pragma unroll
@@ -1000,6 +1298,155 @@ __global__ __launch_bounds__(64, SymWaves<RT>::value) void ghat_sym16_kernel(
       __syncthreads();  // the tile's entries are read before the next tile is staged
     }
   }
+#pragma unroll
+  for (int m = 0; m < kSymTiles; ++m) {
+    const int64_t t = g * kSymGroup + 64 * m + lane;
+#pragma unroll
+    for (int rr = 0; rr < RT; ++rr)
+      if (t < N && r0 + rr < R)
+        partial[((int64_t)c * R + r0 + rr) * N + t] =
+            c64{(float)(ar[m][rr] * (double)kInv4Pi), (float)(ai[m][rr] * (double)kInv4Pi)};
+  }
+}
+
+// The sub-block pair sum with W waves per block sharing each staged source tile, its bodies and
+// their centres, and each wave's target-body centres in LDS (the schedule of
+// ghat_sym_shared_kernel).
+template <int RT, int W>
+__global__ __launch_bounds__(64 * W, SymWaves<RT>::value) void ghat_sym16_shared_kernel(
+    BodyPhaseConsts k, const float* __restrict__ l0, const float* __restrict__ l1, const float* __restrict__ l2,
+    const float* __restrict__ lsq, const double* __restrict__ cen, const int32_t* __restrict__ body_of,
+    const c64* __restrict__ q, int64_t N, int R, int64_t G, int Dmax, int even_G, int HH, int dpc, int nchunks_d,
+    c64* __restrict__ partial) {
+  static_assert(W > 1, "one wave per block: ghat_sym16_kernel");
+  __shared__ Sym16Lds<RT> sh[2];
+  __shared__ SymComb<RT, W> cb;
+  __shared__ double tcen[W][kSymGroup / kSubBlock][3];  // centres of each wave's target bodies
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t gb = (int64_t)blockIdx.x * W;  // the block's first target group
+  const int64_t g = gb + wv;                        // this wave's
+  const int c = blockIdx.y;
+  const int r0 = blockIdx.z * RT;  // right-hand sides r0 .. r0 + RT - 1 (those >= R repeat R - 1, unstored)
+  const int hh1 = min(HH, (c + 1) * dpc);
+  const float* lsrc[3] = {l0, l1, l2};
+  int rof[RT];
+#pragma unroll
+  for (int rr = 0; rr < RT; ++rr) rof[rr] = min(r0 + rr, R - 1);
+
+  // targets: lane l of tile m is point g*256 + 64 m + l; lanes past N are idle (tb = -1, zero charge)
+  int tb[kSymTiles];
+  float lt[kSymTiles][3], qtr[kSymTiles][RT], qti[kSymTiles][RT];
+  double ar[kSymTiles][RT], ai[kSymTiles][RT];
+#pragma unroll
+  for (int m = 0; m < kSymTiles; ++m) {
+    const int64_t t = g * kSymGroup + 64 * m + lane;
+    const bool ok = t < N;
+    const int64_t tc = ok ? t : 0;
+    tb[m] = ok ? body_of[tc] : -1;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) lt[m][d] = ok ? lsrc[d][tc] : 0.0f;
+#pragma unroll
+    for (int rr = 0; rr < RT; ++rr) {
+      const c64 qq = q[(int64_t)rof[rr] * N + tc];
+      qtr[m][rr] = ok ? qq.re : 0.0f;
+      qti[m][rr] = ok ? qq.im : 0.0f;
+      ar[m][rr] = ai[m][rr] = 0.0;
+    }
+  }
+  const bool has_targets = g * kSymGroup < N;
+  // the wave's targets lie on bodies tbase .. tlast, at most 16 of them (every body holds a
+  // multiple of 16 points and starts on a 16-point boundary)
+  const int tbase = has_targets ? body_of[g * kSymGroup] : 0;
+  if (has_targets) {
+    const int tlast = body_of[min(N, (g + 1) * kSymGroup) - 1];
+    if (lane < 3 * (tlast - tbase + 1))
+      tcen[wv][lane / 3][lane % 3] = cen[(int64_t)(tbase + lane / 3) * 3 + lane % 3];
+  }
+
+  // The tile walk and the per-tile barrier of ghat_sym_kernel.
+  // source j0 + p sits at entries (p / 16) * 48 + p % 16 and + 16 of the staging arrays
+  int hh = c * dpc, ts = 0, t = 0, buf = 0, psl = 0;
+  int64_t pj0 = 0;
+  bool have = sym_seek(gb, G, N, hh1, hh, ts);
+  SymStage<3, RT, W> stg;
+  if (have) {
+    sym_stage_load(stg, l0, l1, l2, lsq, q, rof, N, sym_tile_start(gb, G, hh, ts), wv, lane);
+    sym_stage_store<4 * kSubStride, kSubBlock, true>(stg, &sh[0].l[0][0], wv, lane);
+    if (wv == 0) sym16_stage_meta(sh[0], cen, body_of, N, sym_tile_start(gb, G, hh, ts), lane);
+  }
+  while (have) {
+    const int64_t j0 = sym_tile_start(gb, G, hh, ts);
+    __syncthreads();  // tile t staged in buffer t & 1; every wave's sums of tile t - 1 in cb
+    int nhh = hh, nts = ts + 1;
+    const bool nhave = sym_seek(gb, G, N, hh1, nhh, nts);
+    if (nhave) sym_stage_load(stg, l0, l1, l2, lsq, q, rof, N, sym_tile_start(gb, G, nhh, nts), wv, lane);
+    // wave (t - 1) mod W adds the waves' sums of the previous tile and stages the next tile's
+    // bodies and centres (every wave is past its last read of that buffer: the barrier)
+    if (wv == (t + W - 1) % W) {
+      if (t > 0) sym_combine(cb, buf ^ 1, lane, pj0, N, R, r0, nchunks_d + psl, kInv4Pi, partial);
+      if (nhave) sym16_stage_meta(sh[buf ^ 1], cen, body_of, N, sym_tile_start(gb, G, nhh, nts), lane);
+    }
+    const int d = hh - wv;
+    const bool active = has_targets && d >= 0 && d <= Dmax;
+    const bool sym = active && d != 0 && !(even_G && d == Dmax);
+    float sr[RT], si[RT];  // lane l: source-side sums of source j0 + l (after the tile)
+#pragma unroll
+    for (int rr = 0; rr < RT; ++rr) sr[rr] = si[rr] = 0.0f;
+    if (active) {
+      int sbb[4];  // body of each sub-block of the source tile, -1 past N (wave-uniform)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sbb[u] = __builtin_amdgcn_readfirstlane(sh[buf].sbb[u]);
+      // is any pair of this meeting on one body?  (then the per-tile path with the same-body test)
+      bool clash = false;
+#pragma unroll
+      for (int m = 0; m < kSymTiles; ++m)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) clash = clash || (tb[m] >= 0 && tb[m] == sbb[u]);
+      const bool any_clash = __any(clash);
+      const bool pure = sbb[0] >= 0 && sbb[1] == sbb[0] && sbb[2] == sbb[0] && sbb[3] == sbb[0];
+      float tr[kSymTiles][RT], ti[kSymTiles][RT];
+#pragma unroll
+      for (int rr = 0; rr < RT; ++rr)
+#pragma unroll
+        for (int m = 0; m < kSymTiles; ++m) tr[m][rr] = ti[m][rr] = 0.0f;
+      if (!any_clash) {
+        if (sym) sym16_steps4<RT, true>(sh[buf], k, CentresLds<RT>{tcen[wv], tbase, &sh[buf]}, lane, tb, sbb, pure, lt, qtr, qti, tr, ti, sr, si);
+        else sym16_steps4<RT, false>(sh[buf], k, CentresLds<RT>{tcen[wv], tbase, &sh[buf]}, lane, tb, sbb, pure, lt, qtr, qti, tr, ti, sr, si);
+      } else {
+#pragma unroll
+        for (int m = 0; m < kSymTiles; ++m) {
+          if (g * kSymGroup + 64 * m >= N) continue;  // a tile with no targets
+          if (sym)
+            sym16_steps1<RT, true>(sh[buf], k, CentresLds<RT>{tcen[wv], tbase, &sh[buf]}, lane, tb[m], sbb, lt[m], qtr[m], qti[m], tr[m], ti[m], sr, si);
+          else
+            sym16_steps1<RT, false>(sh[buf], k, CentresLds<RT>{tcen[wv], tbase, &sh[buf]}, lane, tb[m], sbb, lt[m], qtr[m], qti[m], tr[m], ti[m], sr, si);
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < kSymTiles; ++m)
+#pragma unroll
+        for (int rr = 0; rr < RT; ++rr) {
+          ar[m][rr] += (double)tr[m][rr];
+          ai[m][rr] += (double)ti[m][rr];
+        }
+    }
+#pragma unroll
+    for (int rr = 0; rr < RT; ++rr) {  // zero where this wave formed no symmetric pair with the tile
+      cb.re[buf][wv][rr][lane] = sym ? sr[rr] : 0.0f;
+      cb.im[buf][wv][rr][lane] = sym ? si[rr] : 0.0f;
+    }
+    if (nhave) sym_stage_store<4 * kSubStride, kSubBlock, true>(stg, &sh[buf ^ 1].l[0][0], wv, lane);
+    pj0 = j0;
+    psl = hh / W;
+    buf ^= 1;
+    ++t;
+    hh = nhh;
+    ts = nts;
+    have = nhave;
+  }
+  __syncthreads();
+  if (t > 0 && wv == (t - 1) % W) sym_combine(cb, buf ^ 1, lane, pj0, N, R, r0, nchunks_d + psl, kInv4Pi, partial);
 #pragma unroll
   for (int m = 0; m < kSymTiles; ++m) {
     const int64_t t = g * kSymGroup + 64 * m + lane;
@@ -1074,20 +1521,41 @@ static hipError_t launch_bodyphase(const SceneDev& s, const c64* q, int R, c64* 
 
 int ghat_default_rt(int R) { return R == 1 ? 1 : R == 2 ? 2 : 4; }
 
-SymPlan sym_plan(int64_t N, int nchunks_d) {
+SymPlan sym_plan(int64_t N, int nchunks_d, int W) {
   SymPlan p{};
-  p.G = (N + kSymGroup - 1) / kSymGroup;
+  p.W = W;
+  const int64_t G0 = (N + kSymGroup - 1) / kSymGroup;
+  p.G = (G0 + W - 1) / W * W;
   p.Dmax = (int)(p.G / 2);
   p.even = p.G % 2 == 0;
-  p.Dsym = p.even ? p.Dmax - 1 : p.Dmax;
-  if (p.Dsym < 0) p.Dsym = 0;
-  // heuristic: about 64k single-wave blocks (the tuner's choice on the 2000-starfish scene: 63 chunks)
+  // one wave per block: distances 0 .. Dmax; W waves: offsets 0 .. HH - 1, wave w meeting distance
+  // hh - w, so that every wave reaches Dmax
+  p.HH = W == 1 ? p.Dmax + 1 : (p.Dmax + W + W - 1) / W * W;
+  // heuristic: about 64k waves (63 chunks on the 2000-starfish scene, 42 on the 1000 spheres)
   int want = nchunks_d > 0 ? nchunks_d : (int)std::min<int64_t>(kTuneMaxChunks, (65536 + p.G - 1) / std::max<int64_t>(p.G, 1));
-  want = std::max(1, std::min(want, p.Dmax + 1));
-  p.dpc = (p.Dmax + 1 + want - 1) / want;
-  p.nchunks_d = (p.Dmax + 1 + p.dpc - 1) / p.dpc;  // no empty chunks
-  p.slices = p.nchunks_d + p.Dsym;
+  want = std::max(1, std::min(want, p.HH));
+  p.dpc = (p.HH + want - 1) / want;
+  p.nchunks_d = (p.HH + p.dpc - 1) / p.dpc;  // no empty chunks
+  // source-side slices: one per symmetric distance (1 .. Dmax, less Dmax itself for even G), or one
+  // per W block offsets
+  const int dsym = std::max(0, p.even ? p.Dmax - 1 : p.Dmax);
+  p.slices = p.nchunks_d + (W == 1 ? dsym : p.HH / W);
   return p;
+}
+
+namespace {
+std::atomic<int64_t> g_sym_slice_budget{0};  // <= 0: kSymSliceBudget
+}
+
+int64_t sym_slice_budget(int64_t bytes) {
+  return g_sym_slice_budget.exchange(bytes);
+}
+
+int sym_block_waves(int64_t NP, int R) {
+  int64_t budget = g_sym_slice_budget.load();
+  if (budget <= 0) budget = kSymSliceBudget;
+  const SymPlan p = sym_plan(NP, 0, 1);
+  return (double)p.slices * (double)NP * (double)R * sizeof(c64) <= (double)budget ? 1 : kSymW;
 }
 
 bool ghat_sym_possible(const SceneDev& s, int R) {
@@ -1101,9 +1569,9 @@ bool ghat_sym_possible(const SceneDev& s, int R) {
     if (!s.pad_ptr || (double)s.Npad * (double)s.Npad > 1.4 * (double)s.N * (double)s.N) return false;
     NP = s.Npad;
   }
-  const SymPlan p = sym_plan(NP, 0);
-  // the source-side slices grow as N^2 / 512 per right-hand side: keep them within 8 GiB
-  return (double)(p.Dsym + 1) * (double)NP * (double)R * sizeof(c64) <= 8.0 * (1ull << 30);
+  const SymPlan p = sym_plan(NP, 0, sym_block_waves(NP, R));
+  // the source-side slices grow as N^2 / (512 W) per right-hand side: keep them within 8 GiB
+  return (double)p.slices * (double)NP * (double)R * sizeof(c64) <= 8.0 * (1ull << 30);
 }
 
 bool sym_padded(const SceneDev& s) { return !s.all_k_mult64 && !s.sym16; }
@@ -1120,42 +1588,58 @@ SceneDev sym_view(const SceneDev& s) {
   return v;
 }
 
-template <int DIM, int RT>
+template <int DIM, int RT, int W>
 static void launch_sym(const SceneDev& s, const SymPlan& p, const c64* q, int R, c64* partial, hipStream_t st) {
-  const dim3 grid((unsigned)p.G, (unsigned)p.nchunks_d, (unsigned)((R + RT - 1) / RT));
-  hipLaunchKernelGGL((ghat_sym_kernel<DIM, RT>), grid, dim3(64), 0, st, make_bodyphase(s.kappa, s.rho_max), s.l32[0],
-                     s.l32[1], s.l32[2], s.lsq32, s.centres, s.body_of, q, s.N, R, p.G, p.Dmax, p.even ? 1 : 0, p.dpc,
-                     p.nchunks_d, partial);
+  const dim3 grid((unsigned)(p.G / W), (unsigned)p.nchunks_d, (unsigned)((R + RT - 1) / RT));
+  const BodyPhaseConsts k = make_bodyphase(s.kappa, s.rho_max);
+  if constexpr (W == 1)
+    hipLaunchKernelGGL((ghat_sym_kernel<DIM, RT>), grid, dim3(64), 0, st, k, s.l32[0], s.l32[1], s.l32[2], s.lsq32,
+                       s.centres, s.body_of, q, s.N, R, p.G, p.Dmax, p.even ? 1 : 0, p.dpc, p.nchunks_d, partial);
+  else
+    hipLaunchKernelGGL((ghat_sym_shared_kernel<DIM, RT, W>), grid, dim3(64 * W), 0, st, k, s.l32[0], s.l32[1],
+                       s.l32[2], s.lsq32, s.centres, s.body_of, q, s.N, R, p.G, p.Dmax, p.even ? 1 : 0, p.HH, p.dpc,
+                       p.nchunks_d, partial);
 }
 
-template <int RT>
+template <int RT, int W>
 static void launch_sym16(const SceneDev& s, const SymPlan& p, const c64* q, int R, c64* partial, hipStream_t st) {
-  const dim3 grid((unsigned)p.G, (unsigned)p.nchunks_d, (unsigned)((R + RT - 1) / RT));
-  hipLaunchKernelGGL((ghat_sym16_kernel<RT>), grid, dim3(64), 0, st, make_bodyphase(s.kappa, s.rho_max), s.l32[0],
-                     s.l32[1], s.l32[2], s.lsq32, s.centres, s.body_of, q, s.N, R, p.G, p.Dmax, p.even ? 1 : 0, p.dpc,
-                     p.nchunks_d, partial);
+  const dim3 grid((unsigned)(p.G / W), (unsigned)p.nchunks_d, (unsigned)((R + RT - 1) / RT));
+  const BodyPhaseConsts k = make_bodyphase(s.kappa, s.rho_max);
+  if constexpr (W == 1)
+    hipLaunchKernelGGL((ghat_sym16_kernel<RT>), grid, dim3(64), 0, st, k, s.l32[0], s.l32[1], s.l32[2], s.lsq32,
+                       s.centres, s.body_of, q, s.N, R, p.G, p.Dmax, p.even ? 1 : 0, p.dpc, p.nchunks_d, partial);
+  else
+    hipLaunchKernelGGL((ghat_sym16_shared_kernel<RT, W>), grid, dim3(64 * W), 0, st, k, s.l32[0], s.l32[1],
+                       s.l32[2], s.lsq32, s.centres, s.body_of, q, s.N, R, p.G, p.Dmax, p.even ? 1 : 0, p.HH, p.dpc,
+                       p.nchunks_d, partial);
+}
+
+template <int W>
+static void launch_sym_w(const SceneDev& s, const SymPlan& p, const c64* q, int R, c64* partial, int rt,
+                         hipStream_t st) {
+  if (s.sym16) {  // 3D, bodies of 16 n points: tiles may straddle bodies
+    if (rt == 1) launch_sym16<1, W>(s, p, q, R, partial, st);
+    else if (rt == 2) launch_sym16<2, W>(s, p, q, R, partial, st);
+    else launch_sym16<4, W>(s, p, q, R, partial, st);
+  } else if (s.dim == 2) {
+    if (rt == 1) launch_sym<2, 1, W>(s, p, q, R, partial, st);
+    else if (rt == 2) launch_sym<2, 2, W>(s, p, q, R, partial, st);
+    else launch_sym<2, 4, W>(s, p, q, R, partial, st);
+  } else {
+    if (rt == 1) launch_sym<3, 1, W>(s, p, q, R, partial, st);
+    else if (rt == 2) launch_sym<3, 2, W>(s, p, q, R, partial, st);
+    else launch_sym<3, 4, W>(s, p, q, R, partial, st);
+  }
 }
 
 hipError_t launch_ghat_f32_sym(const SceneDev& s, const c64* q, int R, c64* partial, int nchunks_d, int rt,
                                hipStream_t st) {
   if (s.N <= 0) return hipSuccess;
-  const SymPlan p = sym_plan(s.N, nchunks_d);
+  const int W = sym_block_waves(s.N, R);
+  const SymPlan p = sym_plan(s.N, nchunks_d, W);
   if (rt != 1 && rt != 2 && rt != 4) rt = ghat_default_rt(R);
-  if (s.sym16) {  // 3D, bodies of 16 n points: tiles may straddle bodies
-    if (rt == 1) launch_sym16<1>(s, p, q, R, partial, st);
-    else if (rt == 2) launch_sym16<2>(s, p, q, R, partial, st);
-    else launch_sym16<4>(s, p, q, R, partial, st);
-    return hipGetLastError();
-  }
-  if (s.dim == 2) {
-    if (rt == 1) launch_sym<2, 1>(s, p, q, R, partial, st);
-    else if (rt == 2) launch_sym<2, 2>(s, p, q, R, partial, st);
-    else launch_sym<2, 4>(s, p, q, R, partial, st);
-  } else {
-    if (rt == 1) launch_sym<3, 1>(s, p, q, R, partial, st);
-    else if (rt == 2) launch_sym<3, 2>(s, p, q, R, partial, st);
-    else launch_sym<3, 4>(s, p, q, R, partial, st);
-  }
+  if (W == 1) launch_sym_w<1>(s, p, q, R, partial, rt, st);
+  else launch_sym_w<kSymW>(s, p, q, R, partial, rt, st);
   return hipGetLastError();
 }
 

@@ -77,17 +77,18 @@ class TuneResult(ctypes.Structure):
 EXPORTS = ["mfs_last_error", "mfs_version", "mfs_build_S", "mfs_scene_create", "mfs_scene_destroy",
            "mfs_scene_size", "mfs_scene_points", "mfs_plane_wave", "mfs_ghat_apply", "mfs_s_apply", "mfs_apply",
            "mfs_apply_static", "mfs_solve", "mfs_eval_field", "mfs_timing_enable", "mfs_timing_read", "mfs_pool_query",
-           "mfs_pool_set_limit", "mfs_pool_trim", "mfs_recon_create", "mfs_recon_destroy", "mfs_recon_size",
+           "mfs_pool_set_limit", "mfs_pool_trim", "mfs_sym_slice_budget", "mfs_recon_create", "mfs_recon_destroy", "mfs_recon_size",
            "mfs_near_sizes", "mfs_plane_wave_colloc", "mfs_reconstruct", "mfs_eval_field_near", "mfs_autotune",
            "mfs_tune_get", "mfs_tune_set", "mfs_tune_save", "mfs_tune_load", "mfs_tune_clear", "mfs_tune_table_size",
            "mfs_pair_kernel", "mfs_scene_set_split_fp16", "mfs_solve_footprint"]
 MFS_KERNEL_PAIR_F32, MFS_KERNEL_PAIR_F64 = 0, 1
 # mfs_pair_kernel_kind
 MFS_PAIR_F64, MFS_PAIR_F32, MFS_PAIR_F32_SYM, MFS_PAIR_F32_SYM16, MFS_PAIR_MC_F32, MFS_PAIR_MC_F16X3, \
-    MFS_PAIR_MC_F64 = range(7)
+    MFS_PAIR_MC_F64, MFS_PAIR_F32_SYM_SHARED, MFS_PAIR_F32_SYM16_SHARED = range(9)
 PAIR_KERNEL_NAMES = {MFS_PAIR_F64: "f64", MFS_PAIR_F32: "f32", MFS_PAIR_F32_SYM: "f32_sym",
                      MFS_PAIR_F32_SYM16: "f32_sym16", MFS_PAIR_MC_F32: "mc_f32", MFS_PAIR_MC_F16X3: "mc_f16x3",
-                     MFS_PAIR_MC_F64: "mc_f64"}
+                     MFS_PAIR_MC_F64: "mc_f64", MFS_PAIR_F32_SYM_SHARED: "f32_sym_shared",
+                     MFS_PAIR_F32_SYM16_SHARED: "f32_sym16_shared"}
 
 
 def load(path: str = LIB_PATH):
@@ -119,6 +120,7 @@ def load(path: str = LIB_PATH):
         "mfs_timing_read": ([i32, ctypes.POINTER(f64), ctypes.POINTER(i64), ctypes.POINTER(f64)], ctypes.c_int),
         "mfs_pool_query": ([ctypes.POINTER(PoolStats)], ctypes.c_int),
         "mfs_pool_set_limit": ([i64], ctypes.c_int),
+        "mfs_sym_slice_budget": ([i64, ctypes.POINTER(i64)], ctypes.c_int),
         "mfs_pool_trim": ([], ctypes.c_int),
         "mfs_recon_create": ([ctypes.POINTER(ShapeDesc), f64, ctypes.POINTER(vp), vp], ctypes.c_int),
         "mfs_recon_destroy": ([vp], ctypes.c_int),
@@ -422,6 +424,13 @@ def pool_stats() -> dict:
 
 def pool_set_limit(max_cached_bytes: int):
     _check(load().mfs_pool_set_limit(int(max_cached_bytes)))
+
+
+def sym_slice_budget(nbytes: int) -> int:
+    """Set the symmetric kernel's slice budget (bytes; <= 0: the default) and return the previous."""
+    prev = ctypes.c_int64(0)
+    _check(load().mfs_sym_slice_budget(int(nbytes), ctypes.byref(prev)))
+    return int(prev.value)
 
 
 def pool_trim():

@@ -93,6 +93,14 @@ def test_pool_interface_without_device(lib):
     assert lib.mfs_pool_query(None) == -1
 
 
+def test_symmetric_slice_budget_without_device(lib):
+    default = 4 << 30
+    assert mfs.sym_slice_budget(12345) == default  # the default was in force
+    assert mfs.sym_slice_budget(0) == 12345
+    assert mfs.sym_slice_budget(-7) == default      # 0 restored the default; so does a negative value
+    assert lib.mfs_sym_slice_budget(0, None) == 0   # the previous value is optional
+
+
 def test_reconstruction_entry_points_reject_null_arguments(lib):
     h = ctypes.c_void_p(0)
     assert lib.mfs_recon_create(None, 1.0, ctypes.byref(h), None) == -1

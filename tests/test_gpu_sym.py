@@ -4,7 +4,8 @@ With 1 to 32 right-hand sides in FP32 and every body holding a multiple of 64 po
 evaluates phi once per unordered pair and adds it into both sums (G_hat is symmetric).  Its
 schedule (groups of 256 points meeting at cyclic distances, one-sided at distance 0 and G/2) has
 edge cases in the number of groups G: 1, 2 (both one-sided), odd and even G, a last group with
-fewer than four tiles, and every way of cutting the distances into chunks.  Each case is held to
+fewer than four tiles, and every way of cutting the distances into chunks; every test runs with one
+wave per block and with eight waves sharing each source tile.  Each case is held to
 the oracle at the FP32 budget, and near body pairs exercise the Hankel branches below z = 100.
 """
 
@@ -18,10 +19,14 @@ from tests.gpu_helpers import FP32_OPERATOR_TOL, crandn, entrywise_err, make_gpu
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture
-def mfs(gpu_lib):
+@pytest.fixture(params=["one_wave", "shared"])
+def mfs(gpu_lib, request):
+    """Both forms of the kernel: one wave per block (the default where the slices fit the budget),
+    and eight waves sharing each source tile (forced by a one-byte slice budget)."""
     gpu_lib.tune_clear()
+    gpu_lib.sym_slice_budget(1 if request.param == "shared" else 0)
     yield gpu_lib
+    gpu_lib.sym_slice_budget(0)
     gpu_lib.tune_clear()
 
 
