@@ -588,10 +588,32 @@ struct Window {
   double br, bi;  // row base + 64 (lane 63, R = 64)
 };
 
+// A double moved across lanes by one DPP pattern (two 32-bit moves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Lane `src`'s value (src wave-uniform), in every lane.
+__device__ __forceinline__ double read_lane_d(double x, int src) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_readlane((int)b, src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the wave, the same bits in every lane: pairs within quads (quad_perm [1,0,3,2], then
+// [2,3,0,1]), half rows (row_half_mirror) and rows of 16 (row_mirror) by DPP, every lane adding the
+// same two values, then the four row sums (lanes 0, 16, 32, 48) in a fixed order.
 __device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-  return x;
+  x += dpp_d<0xB1>(x);
+  x += dpp_d<0x4E>(x);
+  x += dpp_d<0x141>(x);
+  x += dpp_d<0x140>(x);
+  return (read_lane_d(x, 0) + read_lane_d(x, 16)) + (read_lane_d(x, 32) + read_lane_d(x, 48));
 }
 
 __device__ __forceinline__ void window_load(Window& wv, const c128* __restrict__ X, int64_t base, int R, int lane) {
@@ -613,19 +635,29 @@ __device__ __forceinline__ void window_store(const Window& wv, c128* __restrict_
   if (R == 64 && lane == 63) X[base + 64] = c128{wv.br, wv.bi};
 }
 
-// x <- (I - v v^H) x on the window, v = refl[0..R]
-__device__ __forceinline__ void window_reflect(Window& wv, const c128* __restrict__ v, int R, int lane) {
-  double vr = 0.0, vi = 0.0, ur = 0.0, ui = 0.0;
+// One reflector's entries as the window holds them: lane p entry p, lane 63 also entry 64 (R = 64).
+struct Refl {
+  double vr, vi, ur, ui;
+};
+
+__device__ __forceinline__ Refl refl_load(const c128* __restrict__ v, int R, int lane) {
+  Refl f{0.0, 0.0, 0.0, 0.0};
   if (lane <= R && lane < 64) {
     const c128 t = v[lane];
-    vr = t.re;
-    vi = t.im;
+    f.vr = t.re;
+    f.vi = t.im;
   }
   if (R == 64 && lane == 63) {
     const c128 t = v[64];
-    ur = t.re;
-    ui = t.im;
+    f.ur = t.re;
+    f.ui = t.im;
   }
+  return f;
+}
+
+// x <- (I - v v^H) x on the window
+__device__ __forceinline__ void window_reflect(Window& wv, const Refl& f) {
+  const double vr = f.vr, vi = f.vi, ur = f.ur, ui = f.ui;
   // s = v^H x
   double sr = vr * wv.ar + vi * wv.ai + ur * wv.br + ui * wv.bi;
   double si = vr * wv.ai - vi * wv.ar + ur * wv.bi - ui * wv.br;
@@ -637,23 +669,22 @@ __device__ __forceinline__ void window_reflect(Window& wv, const c128* __restric
   wv.bi -= ur * si + ui * sr;
 }
 
-// Slide the window down one row: row base is final (stored), rows base+1 .. base+R+1 stay or load.
-__device__ __forceinline__ void window_slide(Window& wv, c128* __restrict__ X, int64_t base, int R, int lane) {
+// Slide the window down one row: row base is final (stored), rows base+1 .. base+R stay (lane l
+// receives lane l + 1's values: DPP wave_rol:1), and row base+R+1 = (nr_in, ni_in) comes in.
+__device__ __forceinline__ void window_slide(Window& wv, c128* __restrict__ X, int64_t base, int R, int lane,
+                                             double nr_in, double ni_in) {
   if (lane == 0) X[base] = c128{wv.ar, wv.ai};
-  const int src = (lane + 1) & 63;
-  double nr = __shfl(wv.ar, src, 64), ni = __shfl(wv.ai, src, 64);
+  double nr = dpp_d<0x134>(wv.ar), ni = dpp_d<0x134>(wv.ai);
   if (R == 64) {
     if (lane == 63) {
       nr = wv.br;
       ni = wv.bi;
-      const c128 t = X[base + 65];
-      wv.br = t.re;
-      wv.bi = t.im;
+      wv.br = nr_in;
+      wv.bi = ni_in;
     }
   } else if (lane == R) {
-    const c128 t = X[base + 1 + R];
-    nr = t.re;
-    ni = t.im;
+    nr = nr_in;
+    ni = ni_in;
   } else if (lane > R) {
     nr = ni = 0.0;
   }
@@ -662,7 +693,10 @@ __device__ __forceinline__ void window_slide(Window& wv, c128* __restrict__ X, i
 }
 
 // Apply reflectors rho0 .. rho1 - 1 (reflector rho acts on rows rho .. rho + R) to column
-// blockIdx.x of X (column c at X + c ldx).  One wave per column; columns are independent.
+// blockIdx.x of X (column c at X + c ldx).  One wave per column; columns are independent.  The
+// chain from one reflector to the next is the wave's two sums and one row shift, all DPP: the next
+// reflector's entries are loaded during the current one, and the rows the slides bring in are
+// loaded 64 at a time (lane l: the row of slide 64 c + l), a chunk ahead of their use.
 __global__ __launch_bounds__(64) void bhess_apply_kernel(const c128* __restrict__ refl, int R, int64_t rho0,
                                                          int64_t rho1, c128* __restrict__ X, int64_t ldx) {
   const int lane = threadIdx.x;
@@ -670,22 +704,42 @@ __global__ __launch_bounds__(64) void bhess_apply_kernel(const c128* __restrict_
   if (rho1 <= rho0) return;
   Window wv;
   window_load(wv, x, rho0, R, lane);
+  // slide t (after reflector rho0 + t, t < rho1 - rho0 - 1) brings in row rho0 + t + off
+  const int64_t off = R == 64 ? 65 : R + 1;
+  const int64_t nslides = rho1 - rho0 - 1;
+  auto chunk = [&](int64_t c) {
+    const int64_t t = 64 * c + lane;
+    return t < nslides ? x[rho0 + t + off] : c128{0.0, 0.0};
+  };
+  c128 cur = chunk(0), nxt = chunk(1);
+  Refl f = refl_load(refl + rho0 * (R + 1), R, lane);
   for (int64_t rho = rho0; rho < rho1; ++rho) {
-    window_reflect(wv, refl + rho * (R + 1), R, lane);
-    if (rho + 1 < rho1) window_slide(wv, x, rho, R, lane);
+    const bool more = rho + 1 < rho1;
+    const Refl fn = more ? refl_load(refl + (rho + 1) * (R + 1), R, lane) : Refl{0.0, 0.0, 0.0, 0.0};
+    window_reflect(wv, f);
+    if (more) {
+      const int64_t t = rho - rho0;
+      const int l = (int)(t & 63);
+      window_slide(wv, x, rho, R, lane, read_lane_d(cur.re, l), read_lane_d(cur.im, l));
+      if (l == 63) {
+        cur = nxt;
+        nxt = chunk(t / 64 + 2);
+      }
+    }
+    f = fn;
   }
   window_store(wv, x, rho1 - 1, R, lane);
 }
 
-// Slide the window up one row: row base + R is final (stored), rows base-1 .. base+R-1 stay or load.
+// Slide the window up one row: row base + R is final (stored), rows base-1 .. base+R-1 stay (lane l
+// receives lane l - 1's values: DPP wave_ror:1) or load.
 __device__ __forceinline__ void window_slide_up(Window& wv, c128* __restrict__ X, int64_t base, int R, int lane) {
   if (R == 64) {
     if (lane == 63) X[base + 64] = c128{wv.br, wv.bi};
   } else if (lane == R) {
     X[base + R] = c128{wv.ar, wv.ai};
   }
-  const int src = (lane + 63) & 63;
-  double nr = __shfl(wv.ar, src, 64), ni = __shfl(wv.ai, src, 64);
+  double nr = dpp_d<0x13C>(wv.ar), ni = dpp_d<0x13C>(wv.ai);
   if (R == 64 && lane == 63) {
     wv.br = wv.ar;  // old row base + 63 becomes position 64
     wv.bi = wv.ai;
@@ -710,9 +764,12 @@ __global__ __launch_bounds__(64) void bhess_apply_rev_kernel(const c128* __restr
   if (rho1 <= rho0) return;
   Window wv;
   window_load(wv, x, rho1 - 1, R, lane);
+  Refl f = refl_load(refl + (rho1 - 1) * (R + 1), R, lane);
   for (int64_t rho = rho1 - 1; rho >= rho0; --rho) {
-    window_reflect(wv, refl + rho * (R + 1), R, lane);
+    const Refl fn = rho > rho0 ? refl_load(refl + (rho - 1) * (R + 1), R, lane) : Refl{0.0, 0.0, 0.0, 0.0};
+    window_reflect(wv, f);
     if (rho > rho0) window_slide_up(wv, x, rho, R, lane);
+    f = fn;
   }
   window_store(wv, x, rho0, R, lane);
 }
@@ -729,8 +786,9 @@ __global__ __launch_bounds__(64) void bhess_newqr_kernel(c128* __restrict__ refl
     Window wv;
     window_load(wv, x, jR, R, lane);
     for (int q = 0; q < c; ++q) {
-      window_reflect(wv, refl + (jR + q) * (R + 1), R, lane);
-      window_slide(wv, x, jR + q, R, lane);
+      window_reflect(wv, refl_load(refl + (jR + q) * (R + 1), R, lane));
+      const c128 tin = x[jR + q + (R == 64 ? 65 : R + 1)];  // the row the slide brings in
+      window_slide(wv, x, jR + q, R, lane, tin.re, tin.im);
     }
     // reflector from the window at base jR + c: x -> alpha e_0, alpha = -e^{i arg x0} |x|
     const double nrm2 = wave_sum(wv.ar * wv.ar + wv.ai * wv.ai + wv.br * wv.br + wv.bi * wv.bi);
