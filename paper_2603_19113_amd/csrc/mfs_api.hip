@@ -308,7 +308,7 @@ mfs_status pair_f32(mfs_scene* s, const c64* q32, int R, hipStream_t st, Partial
 
 // y = q + S G_hat q in FP64 (all operands complex128).
 mfs_status apply_f64(mfs_scene* s, const c128* q, c128* y, int R, hipStream_t st, double beta = 1.0) {
-  const int nch = shape_for(s, true, R).nchunks;
+  const int nch = ghat_f64_slices(s->dev, R, shape_for(s, true, R).nchunks);
   MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c128), &s->bytes, st));
   c128* part = static_cast<c128*>(s->partial.p);
   {
@@ -450,7 +450,7 @@ mfs_status apply_in_buffer(mfs_scene* s, const void* q, void* y, int R, mfs_prec
                                    " bytes (R x N x 16), more than the static scratch's " + std::to_string(cap));
     const int nch = std::min(shape_for(s, true, R).nchunks, fit);
     c128* part = static_cast<c128*>(buf);
-    MFS_HIP_TRY(launch_ghat_f64(s->dev, static_cast<const c128*>(q), R, part, nch, st));
+    MFS_HIP_TRY(launch_ghat_f64(s->dev, static_cast<const c128*>(q), R, part, nch, st, false));
     MFS_HIP_TRY(launch_sapply_f64(s->dev, part, nch, static_cast<const c128*>(q), 1.0, static_cast<c128*>(y), R,
                                   (int)s->kmax, st));
     return MFS_OK;
@@ -1361,7 +1361,7 @@ mfs_status mfs_solve_footprint(int32_t dim, int64_t T, const int32_t* shape_of, 
     if (ls.sym != 1 && ghat_uses_mfma16(d, R)) split = ghat_split_bytes(d, R);
     q32 = (size_t)R * N * sizeof(c64);
   }
-  part = std::max(part, (size_t)shape_for(&sh, true, R).nchunks * R * N * sizeof(c128));
+  part = std::max(part, (size_t)ghat_f64_slices(d, R, shape_for(&sh, true, R).nchunks) * R * N * sizeof(c128));
   if (n_targets > 0)
     part = std::max(part, (size_t)pair_chunks_for(N, n_targets, tpt_for(MFS_FP64)) * R * n_targets * sizeof(c128));
   total += blk(part) + blk(qpad) + blk(split) + blk(q32) + blk(sizeof(double) * R * dim);
@@ -1408,7 +1408,7 @@ mfs_status mfs_ghat_apply(const mfs_scene* sc, const void* q_dev, void* t_dev, i
   hipStream_t st = as_stream(stream);
   s->last_stream = st;
   if (prec == MFS_FP64) {
-    const int nch = shape_for(s, true, R).nchunks;
+    const int nch = ghat_f64_slices(s->dev, R, shape_for(s, true, R).nchunks);
     MFS_TRY(ensure(s->partial, (size_t)nch * R * s->dev.N * sizeof(c128), &s->bytes, st));
     c128* part = static_cast<c128*>(s->partial.p);
     {
@@ -1950,7 +1950,7 @@ mfs_status mfs_reconstruct(const mfs_scene* sc, const mfs_recon* const* recon, c
   const int64_t N = s->dev.N;
   const NearTables& t = s->near;
   // w_hat = G_hat qhat (FP64): the field of the other bodies at each body's equivalent points
-  const int nch = shape_for(s, true, R).nchunks;
+  const int nch = ghat_f64_slices(s->dev, R, shape_for(s, true, R).nchunks);
   MFS_TRY(ensure(s->partial, (size_t)nch * R * N * sizeof(c128), &s->bytes, st));
   size_t gw = 0, gv = 0;
   hipError_t e = hipSuccess;

@@ -121,8 +121,13 @@ hipError_t launch_ghat_mc(const SceneDev& s, const c64* q, int R, c64* partial, 
                           hipStream_t st);
 // The FP64 pair sum on the FP64 matrix cores (mc_kernels.hip), where ghat_uses_mfma holds.
 hipError_t launch_ghat_mc64(const SceneDev& s, const c128* q, int R, c128* partial, int nchunks, hipStream_t st);
+// FP64 pair sum: the matrix cores from 8 right-hand sides, the symmetric kernel (its own plan, four
+// waves per block sharing each source tile) for one unless allow_sym is false, else the plain kernel in nchunks slices.
+// ghat_f64_slices gives the number of partial slices it writes.
+bool ghat_f64_sym(const SceneDev& s, int R);
+int ghat_f64_slices(const SceneDev& s, int R, int nchunks);
 hipError_t launch_ghat_f64(const SceneDev& s, const c128* q, int R, c128* partial, int nchunks,
-                           hipStream_t st);
+                           hipStream_t st, bool allow_sym = true);
 hipError_t launch_eval_f32(const SceneDev& s, const c64* q, int R, const double* targets, int64_t M,
                            c64* partial, int nchunks, hipStream_t st);
 hipError_t launch_eval_f64(const SceneDev& s, const c128* q, int R, const double* targets, int64_t M,

@@ -1459,6 +1459,156 @@ __global__ __launch_bounds__(64 * W, SymWaves<RT>::value) void ghat_sym16_shared
 }
 
 
+// ---------------------------------------------------------------------------
+// FP64 symmetric pair sum in 3D, one right-hand side (the refinement residual of the mixed solve): the
+// block schedule of ghat_sym_shared_kernel (W waves, each holding one target group of 256 points,
+// sharing each staged source tile), with phi in FP64 from the absolute coordinates (no body-centre
+// split) and same-body pairs removed pair by pair, so bodies of any size work and tiles may
+// straddle them.  Idle target lanes and source slots (past N) carry body -1 and are masked too.
+// Outputs as ghat_sym_shared_kernel's, complex128.
+// ---------------------------------------------------------------------------
+template <int DIM>
+struct SymLds64 {
+  double x[DIM][128];
+  double qr[128], qi[128];
+  int b[128];
+};
+
+// lane l receives lane (l + 1) mod 64's value (DPP wave_rol:1 on both halves)
+__device__ __forceinline__ double wave_rotate_next_d(double x) {
+  const long long v = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)v, 0x134, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(v >> 32), 0x134, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int DIM, int W>
+__global__ __launch_bounds__(64 * W) void ghat_sym_f64_kernel(double kappa, const double* __restrict__ x0,
+                                                              const double* __restrict__ x1,
+                                                              const double* __restrict__ x2,
+                                                              const int32_t* __restrict__ body_of,
+                                                              const c128* __restrict__ q, int64_t N, int64_t G,
+                                                              int Dmax, int even_G, int HH, int dpc, int nchunks_d,
+                                                              c128* __restrict__ partial) {
+  __shared__ SymLds64<DIM> sh[2];
+  __shared__ double cbr[2][W][64], cbi[2][W][64];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t gb = (int64_t)blockIdx.x * W;
+  const int64_t g = gb + wv;
+  const int c = blockIdx.y;
+  const int hh1 = min(HH, (c + 1) * dpc);
+  const double* xs[3] = {x0, x1, x2};
+  PhiEval<double, DIM> phi{kappa};
+
+  int tb[kSymTiles];
+  double tx[kSymTiles][DIM], tqr[kSymTiles], tqi[kSymTiles], ar[kSymTiles], ai[kSymTiles];
+#pragma unroll
+  for (int m = 0; m < kSymTiles; ++m) {
+    const int64_t t = g * kSymGroup + 64 * m + lane;
+    const bool ok = t < N;
+    const int64_t tc = ok ? t : 0;
+    tb[m] = ok ? body_of[tc] : -1;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) tx[m][d] = xs[d][tc];
+    tqr[m] = ok ? q[tc].re : 0.0;
+    tqi[m] = ok ? q[tc].im : 0.0;
+    ar[m] = ai[m] = 0.0;
+  }
+  const bool has_targets = g * kSymGroup < N;
+
+  // one barrier per tile: tile t staged in buffer t & 1 before it; the previous tile's sums added
+  // after it by wave (t - 1) mod W
+  int hh = c * dpc, ts = 0, t = 0, buf = 0, psl = 0;
+  int64_t pj0 = 0;
+  bool have = sym_seek(gb, G, N, hh1, hh, ts);
+  while (have) {
+    const int64_t j0 = sym_tile_start(gb, G, hh, ts);
+    if (lane < 64 / W) {  // stage the tile, 64 / W sources per wave, entries e and e + 64
+      const int e = (64 / W) * wv + lane;
+      const int64_t j = j0 + e;
+      const bool ok = j < N;
+      const int64_t jc = ok ? j : 0;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) sh[buf].x[d][e] = sh[buf].x[d][e + 64] = xs[d][jc];
+      const c128 qq = q[jc];
+      sh[buf].qr[e] = sh[buf].qr[e + 64] = ok ? qq.re : 0.0;
+      sh[buf].qi[e] = sh[buf].qi[e + 64] = ok ? qq.im : 0.0;
+      sh[buf].b[e] = sh[buf].b[e + 64] = ok ? body_of[jc] : -1;
+    }
+    __syncthreads();
+    if (t > 0 && wv == (t - 1) % W && pj0 + lane < N) {
+      double xr = 0.0, xi = 0.0;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        xr += cbr[buf ^ 1][w][lane];
+        xi += cbi[buf ^ 1][w][lane];
+      }
+      partial[(int64_t)(nchunks_d + psl) * N + pj0 + lane] = c128{xr, xi};
+    }
+    const int d = hh - wv;
+    const bool active = has_targets && d >= 0 && d <= Dmax;
+    const bool sym = active && d != 0 && !(even_G && d == Dmax);
+    double sr = 0.0, si = 0.0;  // running source-side sum of the source this lane meets
+    if (active) {
+      const SymLds64<DIM>& S = sh[buf];
+      for (int s0 = 0; s0 < 64; ++s0) {
+        const int e = lane + s0;
+        double sx[DIM];
+#pragma unroll
+        for (int dd = 0; dd < DIM; ++dd) sx[dd] = S.x[dd][e];
+        const double sqr = S.qr[e], sqi = S.qi[e];
+        const int sb = S.b[e];
+#pragma unroll
+        for (int m = 0; m < kSymTiles; ++m) {
+          double r2 = 0.0;
+#pragma unroll
+          for (int dd = 0; dd < DIM; ++dd) {
+            const double dx = tx[m][dd] - sx[dd];
+            r2 = fma(dx, dx, r2);
+          }
+          double pr, pi;
+          phi(r2, pr, pi);
+          const bool ok = tb[m] >= 0 && sb >= 0 && tb[m] != sb;  // a select: drops the values of
+          pr = ok ? pr : 0.0;                                    // a point with itself too
+          pi = ok ? pi : 0.0;
+          ar[m] = fma(pr, sqr, fma(-pi, sqi, ar[m]));
+          ai[m] = fma(pr, sqi, fma(pi, sqr, ai[m]));
+          if (sym) {
+            sr = fma(pr, tqr[m], fma(-pi, tqi[m], sr));
+            si = fma(pr, tqi[m], fma(pi, tqr[m], si));
+          }
+        }
+        sr = wave_rotate_next_d(sr);
+        si = wave_rotate_next_d(si);
+      }
+    }
+    cbr[buf][wv][lane] = sym ? sr : 0.0;
+    cbi[buf][wv][lane] = sym ? si : 0.0;
+    pj0 = j0;
+    psl = hh / W;
+    buf ^= 1;
+    ++t;
+    ++ts;
+    have = sym_seek(gb, G, N, hh1, hh, ts);
+  }
+  __syncthreads();
+  if (t > 0 && wv == (t - 1) % W && pj0 + lane < N) {
+    double xr = 0.0, xi = 0.0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      xr += cbr[buf ^ 1][w][lane];
+      xi += cbi[buf ^ 1][w][lane];
+    }
+    partial[(int64_t)(nchunks_d + psl) * N + pj0 + lane] = c128{xr, xi};
+  }
+#pragma unroll
+  for (int m = 0; m < kSymTiles; ++m) {
+    const int64_t tt = g * kSymGroup + 64 * m + lane;
+    if (tt < N) partial[(int64_t)c * N + tt] = c128{ar[m], ai[m]};
+  }
+}
+
 template <typename T, int DIM, int TPT, int RT, bool EXT>
 hipError_t launch_pair(const PhiEval<T, DIM>& phi, const T* s0, const T* s1, const T* s2, const int32_t* sbody,
                        const int64_t* body_ptr, const Cplx<T>* q, int64_t N, int R, const double* targets,
@@ -1658,9 +1808,30 @@ hipError_t launch_ghat_f32(const SceneDev& s, const c64* q, int R, c64* partial,
   return launch_bodyphase<3, 4>(s, q, R, partial, nchunks, st);
 }
 
-hipError_t launch_ghat_f64(const SceneDev& s, const c128* q, int R, c128* partial, int nchunks, hipStream_t st) {
+// waves per block of the FP64 symmetric kernel: one per SIMD (its registers allow 2 or 3 per SIMD,
+// so blocks of 8 would leave one block per CU)
+constexpr int kSymW64 = 4;
+
+// 3D only: the 2D kernel's FP64 Hankel branches, four targets per lane, take every register of a
+// SIMD (one wave), so the plain kernel stays the faster there
+bool ghat_f64_sym(const SceneDev& s, int R) { return s.dim == 3 && R == 1 && s.N > 0; }
+
+int ghat_f64_slices(const SceneDev& s, int R, int nchunks) {
+  return ghat_f64_sym(s, R) ? sym_plan(s.N, 0, kSymW64).slices : nchunks;
+}
+
+hipError_t launch_ghat_f64(const SceneDev& s, const c128* q, int R, c128* partial, int nchunks, hipStream_t st,
+                           bool allow_sym) {
   if (s.N <= 0) return hipSuccess;
   if (ghat_uses_mfma(s, R)) return launch_ghat_mc64(s, q, R, partial, nchunks, st);
+  if (allow_sym && ghat_f64_sym(s, R)) {
+    const SymPlan p = sym_plan(s.N, 0, kSymW64);
+    const dim3 grid((unsigned)(p.G / kSymW64), (unsigned)p.nchunks_d, 1);
+    hipLaunchKernelGGL((ghat_sym_f64_kernel<3, kSymW64>), grid, dim3(64 * kSymW64), 0, st, s.kappa, s.x64[0],
+                       s.x64[1], s.x64[2], s.body_of, q, s.N, p.G, p.Dmax, p.even ? 1 : 0, p.HH, p.dpc, p.nchunks_d,
+                       partial);
+    return hipGetLastError();
+  }
   if (s.dim == 2) {
     PhiEval<double, 2> phi{s.kappa};
     return dispatch_rt<double, 2, 1, false>(phi, s.x64[0], s.x64[1], nullptr, s.body_of, s.body_ptr, q, s.N, R,
