@@ -256,10 +256,20 @@ struct SlabRegs32 {
 template <typename TA>
 __device__ __forceinline__ void slab_load32(SlabRegs32& g, const TA* __restrict__ X, int64_t ldx, int col, bool okc,
                                             int64_t n, int64_t nend) {
+  const TA* p = X + (int64_t)col * ldx + n;
+  if (okc && n + 8 <= nend) {  // the common case: eight loads with no per-entry test
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const c128 v = load_c(p + i);
+      g.re[i] = (float)v.re;
+      g.im[i] = (float)v.im;
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     c128 v = {0.0, 0.0};
-    if (okc && n + i < nend) v = load_c(X + (int64_t)col * ldx + n + i);
+    if (okc && n + i < nend) v = load_c(p + i);
     g.re[i] = (float)v.re;
     g.im[i] = (float)v.im;
   }
@@ -361,18 +371,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
   SlabRegs32 ga, gc;
   auto load = [&](int kb) {
     const int k = kb + kc;
+    const TA* pa = A + (int64_t)k * lda + n0 + nq;
+    if (k < K && n0 + nq + 8 <= M) {  // the common case: no per-entry test
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int64_t n = n0 + nq + i;
-      c128 a = {0.0, 0.0};
-      if (k < K && n < M) a = load_c(A + (int64_t)k * lda + n);
-      ga.re[i] = (float)a.re;
-      ga.im[i] = (float)a.im;
-      const int kk = kb + kq + i;
-      c128 v = {0.0, 0.0};
-      if (kk < K && cc < R) v = load_c(C + kk + (int64_t)cc * ldc);
-      gc.re[i] = (float)v.re;
-      gc.im[i] = (float)v.im;
+      for (int i = 0; i < 8; ++i) {
+        const c128 a = load_c(pa + i);
+        ga.re[i] = (float)a.re;
+        ga.im[i] = (float)a.im;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        c128 a = {0.0, 0.0};
+        if (k < K && n0 + nq + i < M) a = load_c(pa + i);
+        ga.re[i] = (float)a.re;
+        ga.im[i] = (float)a.im;
+      }
+    }
+    const TC* pc = C + kb + kq + (int64_t)cc * ldc;
+    if (cc < R && kb + kq + 8 <= K) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const c128 v = load_c(pc + i);
+        gc.re[i] = (float)v.re;
+        gc.im[i] = (float)v.im;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        c128 v = {0.0, 0.0};
+        if (cc < R && kb + kq + i < K) v = load_c(pc + i);
+        gc.re[i] = (float)v.re;
+        gc.im[i] = (float)v.im;
+      }
     }
   };
   if (K > 0) load(0);
