@@ -671,19 +671,12 @@ struct Refl {
   double vr, vi, ur, ui;
 };
 
+// Every lane loads (entries min(lane, R) and min(lane + 1, R): no branch around the loads, so that a
+// load issued one reflector ahead stays in flight) and keeps what the window needs.
 __device__ __forceinline__ Refl refl_load(const c128* __restrict__ v, int R, int lane) {
-  Refl f{0.0, 0.0, 0.0, 0.0};
-  if (lane <= R && lane < 64) {
-    const c128 t = v[lane];
-    f.vr = t.re;
-    f.vi = t.im;
-  }
-  if (R == 64 && lane == 63) {
-    const c128 t = v[64];
-    f.ur = t.re;
-    f.ui = t.im;
-  }
-  return f;
+  const c128 t0 = v[min(lane, R)], t1 = v[min(lane + 1, R)];
+  const bool in = lane <= R, last = R == 64 && lane == 63;
+  return Refl{in ? t0.re : 0.0, in ? t0.im : 0.0, last ? t1.re : 0.0, last ? t1.im : 0.0};
 }
 
 // x <- (I - v v^H) x on the window
@@ -735,29 +728,23 @@ __global__ __launch_bounds__(64) void bhess_apply_kernel(const c128* __restrict_
   if (rho1 <= rho0) return;
   Window wv;
   window_load(wv, x, rho0, R, lane);
-  // slide t (after reflector rho0 + t, t < rho1 - rho0 - 1) brings in row rho0 + t + off
+  // the slide after reflector rho brings in row rho + off (for rho < rho1 - 1); the next reflector
+  // and the next incoming row are loaded one step ahead, without branches (clamped indices)
   const int64_t off = R == 64 ? 65 : R + 1;
-  const int64_t nslides = rho1 - rho0 - 1;
-  auto chunk = [&](int64_t c) {
-    const int64_t t = 64 * c + lane;
-    return t < nslides ? x[rho0 + t + off] : c128{0.0, 0.0};
-  };
-  c128 cur = chunk(0), nxt = chunk(1);
+  const int64_t rlast = rho1 - 2;  // the last reflector followed by a slide
+  // the row slide rho brings in; past the last slide any row of the window (its value is unused),
+  // so that no load leaves the rows the sweep touches
+  auto row_in = [&](int64_t rho) { return rho <= rlast ? rho + off : rho0; };
   Refl f = refl_load(refl + rho0 * (R + 1), R, lane);
+  c128 rin = x[row_in(rho0)];
   for (int64_t rho = rho0; rho < rho1; ++rho) {
-    const bool more = rho + 1 < rho1;
-    const Refl fn = more ? refl_load(refl + (rho + 1) * (R + 1), R, lane) : Refl{0.0, 0.0, 0.0, 0.0};
+    const int64_t rn = min(rho + 1, rho1 - 1);
+    const Refl fn = refl_load(refl + rn * (R + 1), R, lane);
+    const c128 rin_n = x[row_in(rho + 1)];
     window_reflect(wv, f);
-    if (more) {
-      const int64_t t = rho - rho0;
-      const int l = (int)(t & 63);
-      window_slide(wv, x, rho, R, lane, read_lane_d(cur.re, l), read_lane_d(cur.im, l));
-      if (l == 63) {
-        cur = nxt;
-        nxt = chunk(t / 64 + 2);
-      }
-    }
+    if (rho + 1 < rho1) window_slide(wv, x, rho, R, lane, rin.re, rin.im);
     f = fn;
+    rin = rin_n;
   }
   window_store(wv, x, rho1 - 1, R, lane);
 }
