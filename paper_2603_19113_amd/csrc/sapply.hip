@@ -79,6 +79,131 @@ hipError_t launch_sapply(const SceneDev& s, const void* const* S_tab, const Cplx
   return hipGetLastError();
 }
 
+// With many right-hand sides the products S_tau T_tau (k x k times k x R per body) are GEMMs and run
+// on the FP32 matrix cores: the pair kernel's slices are first added in place into slice 0 (FP64
+// sums, fixed order), then block (body, 64-row tile, 64-column tile) stages 32 columns of S and 32
+// rows of T per step in LDS and four waves each form 16 rows x 64 columns of S T, a complex product
+// as four real 16x16x4 products (the FP32 product leaves D row 4 (l / 16) + v, column l % 16 in
+// register v of lane l).
+template <typename TS>
+__global__ void reduce_slices_kernel(Cplx<TS>* __restrict__ partial, int nchunks, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double re = 0.0, im = 0.0;
+#pragma unroll 8
+  for (int c = 0; c < nchunks; ++c) {
+    const Cplx<TS> v = partial[(int64_t)c * n + i];
+    re += (double)v.re;
+    im += (double)v.im;
+  }
+  partial[i] = Cplx<TS>{(TS)re, (TS)im};
+}
+
+typedef float f4s __attribute__((ext_vector_type(4)));
+constexpr int kSmTile = 64, kSmSlab = 32, kSmPad = 68;
+
+template <typename TQ>
+__global__ __launch_bounds__(256) void sapply_mfma_kernel(const int64_t* __restrict__ body_ptr,
+                                                          const int32_t* __restrict__ shape_of,
+                                                          const void* const* __restrict__ S_of_shape,
+                                                          const c64* __restrict__ t, const int64_t* __restrict__ pptr,
+                                                          int64_t NP, const Cplx<TQ>* __restrict__ q, TQ beta,
+                                                          Cplx<TQ>* __restrict__ y, int64_t N, int R) {
+  __shared__ float Sre[kSmSlab][kSmPad], Sim[kSmSlab][kSmPad], Tre[kSmSlab][kSmPad], Tim[kSmSlab][kSmPad];
+  const int64_t body = blockIdx.x;
+  const int64_t start = body_ptr[body];
+  const int k = (int)(body_ptr[body + 1] - start);
+  const int i0 = blockIdx.y * kSmTile;
+  if (i0 >= k) return;  // the whole block (uniform)
+  const int r0 = blockIdx.z * kSmTile;
+  const c64* __restrict__ S = static_cast<const c64*>(S_of_shape[shape_of[body]]);
+  const c64* __restrict__ tb = t + pptr[body];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  f4s accR[4], accI[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) accR[c] = accI[c] = f4s{0.0f, 0.0f, 0.0f, 0.0f};
+  // S tile: column j (tid / 8), rows i0 + (tid % 8) * 8 .. + 7 (contiguous: S is column-major);
+  // T tile: column r (tid / 4), rows j0 + (tid % 4) * 8 .. + 7 (contiguous in j)
+  const int sj = tid >> 3, si = (tid & 7) * 8;
+  const int tr = tid >> 2, tj = (tid & 3) * 8;
+  for (int j0 = 0; j0 < k; j0 += kSmSlab) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int i = i0 + si + e, j = j0 + sj;
+      const c64 v = (i < k && j < k) ? S[(int64_t)j * k + i] : c64{0.0f, 0.0f};
+      Sre[sj][si + e] = v.re;
+      Sim[sj][si + e] = v.im;
+      const int jj = j0 + tj + e, r = r0 + tr;
+      const c64 u = (jj < k && r < R) ? tb[(int64_t)r * NP + jj] : c64{0.0f, 0.0f};
+      Tre[tj + e][tr] = u.re;
+      Tim[tj + e][tr] = u.im;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kSmSlab; kk += 4) {
+      const int jr = kk + (lane >> 4);
+      const float ar = Sre[jr][16 * w + (lane & 15)], ai = Sim[jr][16 * w + (lane & 15)];
+      float br[4], bi[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        br[c] = Tre[jr][16 * c + (lane & 15)];
+        bi[c] = Tim[jr][16 * c + (lane & 15)];
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        accR[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br[c], accR[c], 0, 0, 0);
+        accI[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi[c], accI[c], 0, 0, 0);
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        accR[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi[c], accR[c], 0, 0, 0);
+        accI[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br[c], accI[c], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int r = r0 + 16 * c + (lane & 15);
+    if (r >= R) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + 16 * w + 4 * (lane >> 4) + v;
+      if (i >= k) continue;
+      const int64_t idx = (int64_t)r * N + start + i;
+      Cplx<TQ> out{(TQ)accR[c][v], (TQ)accI[c][v]};
+      if (beta != TQ(0)) {
+        const Cplx<TQ> qq = q[idx];
+        out.re += beta * qq.re;
+        out.im += beta * qq.im;
+      }
+      y[idx] = out;
+    }
+  }
+}
+
+// The matrix-core form from this many right-hand sides (FP32 S).
+constexpr int kSapplyMfmaMinRhs = 16;
+
+template <typename TQ>
+hipError_t launch_sapply_mc(const SceneDev& s, c64* partial, int nchunks, const Cplx<TQ>* q, TQ beta,
+                            Cplx<TQ>* y, int R, int kmax, hipStream_t st, const int64_t* pptr, int64_t NP) {
+  if (s.T == 0 || R == 0) return hipSuccess;
+  if (!pptr) {
+    pptr = s.body_ptr;
+    NP = s.N;
+  }
+  if (nchunks > 1) {  // the slices are scratch: add them into slice 0
+    const int64_t n = NP * R;
+    hipLaunchKernelGGL(reduce_slices_kernel<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, partial,
+                       nchunks, n);
+  }
+  const dim3 grid((unsigned)s.T, (unsigned)((kmax + kSmTile - 1) / kSmTile), (unsigned)((R + kSmTile - 1) / kSmTile));
+  hipLaunchKernelGGL((sapply_mfma_kernel<TQ>), grid, dim3(256), 0, st, s.body_ptr, s.shape_of, s.S32,
+                     static_cast<const c64*>(partial), pptr, NP, q, beta, y, s.N, R);
+  return hipGetLastError();
+}
+
 // Padded layout: point ip belongs to body b = body_of_pad[ip] at offset o = ip - pad_ptr[b]; it is
 // the body's point o if o < k_b, else a filler at the body centre (offset 0, charge 0).
 __global__ void pad_scene_kernel(int dim, const int64_t* __restrict__ body_ptr, const int64_t* __restrict__ pad_ptr,
@@ -178,11 +303,17 @@ hipError_t launch_sapply_f64(const SceneDev& s, const c128* partial, int nchunks
 
 hipError_t launch_sapply_f32(const SceneDev& s, const c64* partial, int nchunks, const c64* q, float beta, c64* y,
                              int R, int kmax, hipStream_t st, const int64_t* pptr, int64_t NP) {
+  // from kSapplyMfmaMinRhs right-hand sides on the matrix cores; one slice (a caller's own t,
+  // read-only) or several (scratch, reduced in place)
+  if (R >= kSapplyMfmaMinRhs)
+    return launch_sapply_mc<float>(s, const_cast<c64*>(partial), nchunks, q, beta, y, R, kmax, st, pptr, NP);
   return launch_sapply<float, float>(s, s.S32, partial, nchunks, q, beta, y, R, kmax, st, pptr, NP);
 }
 
 hipError_t launch_sapply_mixed(const SceneDev& s, const c64* partial, int nchunks, const c128* q, double beta,
                                c128* y, int R, int kmax, hipStream_t st, const int64_t* pptr, int64_t NP) {
+  if (R >= kSapplyMfmaMinRhs)
+    return launch_sapply_mc<double>(s, const_cast<c64*>(partial), nchunks, q, beta, y, R, kmax, st, pptr, NP);
   return launch_sapply<double, float>(s, s.S32, partial, nchunks, q, beta, y, R, kmax, st, pptr, NP);
 }
 
