@@ -190,3 +190,24 @@ def test_request_footprint_of_a_batch():
         assert joint > 0
         if below_sum:
             assert joint < sum(request_footprint([s]) for s in same)
+
+
+def test_footprint_follows_the_symmetric_slice_budget():
+    """The symmetric pair kernel's partial slices, as the footprint counts them: 2000 bodies of 128
+    points in 2D (the starfish layout) keep one slice per group distance (562 slices of N complex64
+    values) under the default budget, and 128 (64 offset chunks, 64 source-side) when a one-byte
+    budget asks for the shape whose 8 waves share each source tile."""
+    from paper_2603_19113_amd import mfs
+
+    shape_of = np.zeros(2000, dtype=np.int32)
+    ks = [128]
+    N = 2000 * 128
+    before = mfs.sym_slice_budget(0)
+    try:
+        one_wave = mfs.solve_footprint(2, shape_of, ks, 1, 2000, basis32=True)
+        mfs.sym_slice_budget(1)
+        shared = mfs.solve_footprint(2, shape_of, ks, 1, 2000, basis32=True)
+    finally:
+        mfs.sym_slice_budget(before if before != 4 << 30 else 0)
+    expected = (562 - 128) * N * 8
+    assert 0.98 * expected <= one_wave - shared <= 1.02 * expected, (one_wave - shared, expected)
