@@ -239,9 +239,13 @@ LaunchShape shape_for(const mfs_scene* s, bool f64, int R, int* source = nullptr
   }
   if (source) *source = src;
   LaunchShape ls = e;
-  // untuned: the symmetric kernel up to kSymDefaultMaxRhs right-hand sides (measured against the
-  // matrix-core kernel: 3.4x faster at 8, 1.7x at 16, 0.87x at 32); tuned or set: up to kSymMaxRhs
-  const bool sym_ok = v != kTunePairF64 && ghat_sym_possible(s->dev, R) && (e.sym == 1 || R <= kSymDefaultMaxRhs);
+  // untuned: the symmetric kernel up to kSymDefaultMaxRhs right-hand sides where the matrix cores
+  // take FP32 products (it was 3.4x faster at 8, 1.7x at 16, 0.87x at 32), and below 8 where they
+  // take split FP16 products (those evaluate phi once per pair for up to 64 right-hand sides: 148 ms
+  // against 173 ms for the symmetric kernel with 8 on the 2000-body mixed scene); tuned or set: up
+  // to kSymMaxRhs
+  const bool sym_default = R <= kSymDefaultMaxRhs && !ghat_uses_mfma16(s->dev, R);
+  const bool sym_ok = v != kTunePairF64 && ghat_sym_possible(s->dev, R) && (e.sym == 1 || sym_default);
   if (sym_ok && e.sym != 0) {
     ls.sym = 1;
     // a slice count tuned for the other kernel does not carry over
@@ -1359,6 +1363,16 @@ mfs_status mfs_solve_footprint(int32_t dim, int64_t T, const int32_t* shape_of, 
     part = (size_t)f32_slices(&sh, ls, R) * R * f32_rows(&sh, ls) * sizeof(c64);
     if (ls.sym == 1 && NP > 0) qpad = (size_t)R * NP * sizeof(c64);
     if (ls.sym != 1 && ghat_uses_mfma16(d, R)) split = ghat_split_bytes(d, R);
+    if (dim == 3 && ls.sym != 1 && R <= kSymDefaultMaxRhs && ghat_sym_possible(d, R)) {
+      // in 3D the split-FP16 kernel's bound on |phi| comes from the centres, which the footprint
+      // does not see: where it fails the symmetric kernel runs, so count its slices too (a bound)
+      LaunchShape lsym = ls;
+      lsym.sym = 1;
+      const int64_t NS = sym_view(d).N;
+      lsym.nchunks = sym_plan(NS, 0, sym_block_waves(NS, R)).nchunks_d;
+      part = std::max(part, (size_t)f32_slices(&sh, lsym, R) * R * f32_rows(&sh, lsym) * sizeof(c64));
+      if (NP > 0) qpad = (size_t)R * NP * sizeof(c64);
+    }
     q32 = (size_t)R * N * sizeof(c64);
   }
   part = std::max(part, (size_t)ghat_f64_slices(d, R, shape_for(&sh, true, R).nchunks) * R * N * sizeof(c128));

@@ -150,8 +150,12 @@ def test_symmetric_kernel_many_rhs(mfs, kind, T, R):
     sc = {"disks": _disks, "starfish": _starfish, "spheres": _spheres64}[kind](T)
     print(f"symmetric ghat {kind} T={T} R={R}", flush=True)
     gsc, _ = _scene(mfs, sc)
-    # untuned: symmetric up to 24 right-hand sides, the matrix cores above
-    assert mfs.tune_get(gsc, R, mfs.MFS_FP32)["symmetric"] == (1 if R <= 24 else 0)
+    # untuned: symmetric up to 24 right-hand sides, the matrix cores above, and from 8 where the
+    # matrix cores take split FP16 products
+    untuned = mfs.tune_get(gsc, R, mfs.MFS_FP32)["symmetric"]
+    mfs.tune_set(gsc, R, mfs.MFS_FP32, 4, 0, 0)
+    split16 = mfs.pair_kernel(gsc, R, mfs.MFS_FP32) == mfs.MFS_PAIR_MC_F16X3
+    assert untuned == (1 if R <= 24 and not split16 else 0)
     xh, ptr, bo = gs.pack(sc)
     q = crandn(np.random.default_rng(33), R, xh.shape[0])
     ref = gs.ghat_apply(xh, bo, sc.kappa, q)
