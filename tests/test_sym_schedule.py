@@ -199,3 +199,38 @@ def test_sub_block_phases_see_one_sub_block_per_row():
         for G in range(4):
             assert len(set(blocks[16 * G:16 * G + 16])) == 1
         assert sorted(set(blocks)) == [0, 1, 2, 3]
+
+
+# ----------------------------------------------------------------------------------------------
+# Staging of a source tile spread over the block (shared-source shapes): 64 / W sources per wave,
+# value v of lane `lane` (v = lane + 64 k, k < ceil(values / 64)) is field v // (64 / W) of source
+# (64 / W) * wave + v % (64 / W); fields are the DIM coordinates, |l|^2, then the real and the
+# imaginary parts of the RT charges, stored at field * STRIDE + E(p) and + DUP (E(p) = p for 64-point
+# tiles; (p // 16) * 48 + p % 16 for 16-point sub-blocks).
+@pytest.mark.parametrize("W", [1, 8])
+@pytest.mark.parametrize("DIM,RT,sub16", [(2, 1, False), (2, 4, False), (3, 1, False), (3, 2, False),
+                                          (3, 1, True), (3, 2, True), (3, 4, True)])
+def test_tile_staging_stores_every_value_once(W, DIM, RT, sub16):
+    src = 64 // W
+    fields = DIM + 1 + 2 * RT
+    nvals = src * fields
+    regs = cdiv(nvals, 64)
+    stride, dup = (192, 16) if sub16 else (128, 64)
+    seen = collections.Counter()
+    entries = collections.Counter()
+    for wave in range(W):
+        for lane in range(64):
+            for k in range(regs):
+                v = lane + 64 * k
+                if v >= nvals:
+                    continue
+                f, p = v // src, src * wave + v % src
+                seen[(f, p)] += 1
+                e = f * stride + ((p >> 4) * 48 + (p & 15) if sub16 else p)
+                entries[e] += 1
+                entries[e + dup] += 1
+                assert e - f * stride + dup < stride  # inside the field's array
+    assert len(seen) == fields * 64 and set(seen.values()) == {1}
+    assert set(entries.values()) == {1}  # no two values share an LDS entry
+    if W == 8 and fields <= 8:
+        assert regs == 1  # one register per lane carries the next tile during the products
