@@ -50,13 +50,21 @@ def test_operator_with_matrix_core_S_product(mfs, case, R):
     q = crandn(np.random.default_rng(60 + R), R, sc.N).astype(np.complex64).astype(np.complex128)
     ref = gs.matvec(sc, Ss, xh, ptr, bo, q)
     qd = torch.from_numpy(q.astype(np.complex64)).cuda()
-    y = torch.empty_like(qd)
-    mfs.apply(gsc, qd, y, mfs.MFS_FP32)
-    err = assert_entrywise(y.cpu().numpy(), ref, FP32_OPERATOR_TOL, f"operator {case} R={R}")
-    ys = torch.empty_like(qd)
-    mfs.apply_static(gsc, qd, ys, mfs.MFS_FP32)
-    err_s = assert_entrywise(ys.cpu().numpy(), ref, FP32_OPERATOR_TOL, f"static operator {case} R={R}")
-    print(f"  entrywise error {err:.2e}, static entry {err_s:.2e}", flush=True)
+    # the untuned kernel, then (up to 24 right-hand sides) the symmetric kernel, whose partial sums
+    # on bodies that are not whole tiles sit in the padded layout
+    for forced_sym in (False, True):
+        if forced_sym:
+            if R > 24:
+                break
+            mfs.tune_set(gsc, R, mfs.MFS_FP32, 3, 0, 1)
+        y = torch.empty_like(qd)
+        mfs.apply(gsc, qd, y, mfs.MFS_FP32)
+        err = assert_entrywise(y.cpu().numpy(), ref, FP32_OPERATOR_TOL, f"operator {case} R={R} sym={forced_sym}")
+        ys = torch.empty_like(qd)
+        mfs.apply_static(gsc, qd, ys, mfs.MFS_FP32)
+        err_s = assert_entrywise(ys.cpu().numpy(), ref, FP32_OPERATOR_TOL,
+                                 f"static operator {case} R={R} sym={forced_sym}")
+        print(f"  sym={forced_sym}: entrywise error {err:.2e}, static entry {err_s:.2e}", flush=True)
     gsc.close()
 
 
